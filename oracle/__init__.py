@@ -1,0 +1,249 @@
+"""ctypes binding of the plain CPU oracle (test infrastructure only).
+
+Only tests/, __graft_entry__.smoke() and bench.py's cpu_baseline leg may import this module.
+It never touches the HIP library; the HIP path never imports it.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+VOL = {"ec": 0, "central": 1}
+SURF = {"roe": 0, "llf": 1, "ec": 2, "central": 3}
+IC = {"uniform": 0, "tgv": 1, "vortex": 2, "density_wave": 3}
+DIAG_KEYS = ["mass_rho", "mass_rhou", "mass_rhov", "mass_rhow", "mass_rhoE", "entropy_paper",
+             "entropy", "ke", "enstrophy", "lambda_max", "rho_min", "p_min", "nonfinite", "volume"]
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+_libs = {}
+
+
+def _lib(precision="fp64"):
+    name = {"fp64": "liborc64.so", "fp80": "liborc80.so"}[precision]
+    if name not in _libs:
+        path = os.path.join(HERE, name)
+        if not os.path.exists(path):
+            from . import build as _b
+            _b.build()
+        L = ctypes.CDLL(path)
+        L.orc_create.restype = ctypes.c_void_p
+        L.orc_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int,
+                                 ctypes.c_double, ctypes.c_int, _ip, ctypes.c_double,
+                                 ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                 ctypes.c_int]
+        L.orc_destroy.argtypes = [ctypes.c_void_p]
+        L.orc_num_nodes.restype = ctypes.c_long
+        L.orc_num_nodes.argtypes = [ctypes.c_void_p]
+        L.orc_num_elements.argtypes = [ctypes.c_void_p]
+        L.orc_elem_info.argtypes = [ctypes.c_void_p, ctypes.c_int, _ip,
+                                    ctypes.POINTER(ctypes.c_long)]
+        for fn in ("orc_get_coords", "orc_set_state", "orc_get_state", "orc_residual",
+                   "orc_gradients", "orc_diagnostics"):
+            getattr(L, fn).argtypes = [ctypes.c_void_p, _dp]
+        L.orc_get_metrics.argtypes = [ctypes.c_void_p, _dp, _dp]
+        L.orc_set_ic.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp]
+        L.orc_rk3.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_int]
+        L.orc_suggest_dt.restype = ctypes.c_double
+        L.orc_suggest_dt.argtypes = [ctypes.c_void_p, ctypes.c_double]
+        L.orc_entropy_production.restype = ctypes.c_double
+        L.orc_entropy_production.argtypes = [ctypes.c_void_p, _dp]
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_gll.argtypes = [ctypes.c_int, _dp, _dp, _dp]
+        L.orc_mortar_matrices.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp]
+        L.orc_euler_flux.argtypes = [_dp, _dp, ctypes.c_double, _dp]
+        L.orc_two_point_ec.argtypes = [_dp, _dp, _dp, ctypes.c_double, _dp]
+        L.orc_two_point_central.argtypes = [_dp, _dp, _dp, ctypes.c_double, _dp]
+        L.orc_riemann.argtypes = [ctypes.c_int, _dp, _dp, _dp, ctypes.c_double, _dp]
+        L.orc_roe_waves.argtypes = [_dp, _dp, _dp, ctypes.c_double, ctypes.c_int, _dp]
+        L.orc_entropy_vars.argtypes = [_dp, ctypes.c_double, _dp]
+        L.orc_entropy.restype = ctypes.c_double
+        L.orc_entropy.argtypes = [_dp, ctypes.c_double]
+        L.orc_logmean.restype = ctypes.c_double
+        L.orc_logmean.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.orc_viscous_flux.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, _dp]
+        _libs[name] = L
+    return _libs[name]
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _f64(a, n=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if n is not None:
+        assert a.size == n, (a.size, n)
+    return a
+
+
+def set_threads(n, precision="fp64"):
+    _lib(precision).orc_set_threads(int(n))
+
+
+# ---------------------------------------------------------------------------- point functions
+def gll(N, precision="fp64"):
+    xi, w, D = np.zeros(N + 1), np.zeros(N + 1), np.zeros((N + 1) * (N + 1))
+    rc = _lib(precision).orc_gll(N, _ptr(xi), _ptr(w), _ptr(D))
+    if rc:
+        raise ValueError(f"orc_gll({N}) failed")
+    return xi, w, D.reshape(N + 1, N + 1)
+
+
+def mortar_matrices(N, M, precision="fp64"):
+    I, P = np.zeros((M + 1) * (N + 1)), np.zeros((N + 1) * (M + 1))
+    if _lib(precision).orc_mortar_matrices(N, M, _ptr(I), _ptr(P)):
+        raise ValueError(f"orc_mortar_matrices({N},{M}) failed")
+    return I.reshape(M + 1, N + 1), P.reshape(N + 1, M + 1)
+
+
+def _point(fn, *arrays, out=5, scalars=(), precision="fp64"):
+    res = np.zeros(out)
+    args = [_ptr(_f64(a)) for a in arrays] + list(scalars) + [_ptr(res)]
+    getattr(_lib(precision), fn)(*args)
+    return res
+
+
+def euler_flux(U, n, gamma=1.4, precision="fp64"):
+    return _point("orc_euler_flux", U, n, scalars=(ctypes.c_double(gamma),), precision=precision)
+
+
+def two_point_ec(UL, UR, n, gamma=1.4, precision="fp64"):
+    return _point("orc_two_point_ec", UL, UR, n, scalars=(ctypes.c_double(gamma),),
+                  precision=precision)
+
+
+def two_point_central(UL, UR, n, gamma=1.4, precision="fp64"):
+    return _point("orc_two_point_central", UL, UR, n, scalars=(ctypes.c_double(gamma),),
+                  precision=precision)
+
+
+def riemann(kind, UL, UR, S, gamma=1.4, precision="fp64"):
+    res = np.zeros(5)
+    _lib(precision).orc_riemann(SURF[kind], _ptr(_f64(UL)), _ptr(_f64(UR)), _ptr(_f64(S)),
+                                gamma, _ptr(res))
+    return res
+
+
+def roe_waves(UL, UR, nhat, gamma=1.4, absval=True, precision="fp64"):
+    res = np.zeros(5)
+    _lib(precision).orc_roe_waves(_ptr(_f64(UL)), _ptr(_f64(UR)), _ptr(_f64(nhat)), gamma,
+                                  int(absval), _ptr(res))
+    return res
+
+
+def entropy_vars(U, gamma=1.4, precision="fp64"):
+    res = np.zeros(5)
+    _lib(precision).orc_entropy_vars(_ptr(_f64(U)), gamma, _ptr(res))
+    return res
+
+
+def entropy(U, gamma=1.4, precision="fp64"):
+    return _lib(precision).orc_entropy(_ptr(_f64(U)), gamma)
+
+
+def logmean(a, b, precision="fp64"):
+    return _lib(precision).orc_logmean(a, b)
+
+
+def viscous_flux(U, grad, gamma=1.4, Pr=0.71, Re=1600.0, precision="fp64"):
+    res = np.zeros(15)
+    _lib(precision).orc_viscous_flux(_ptr(_f64(U)), _ptr(_f64(grad)), gamma, Pr, Re, _ptr(res))
+    return res.reshape(3, 5)
+
+
+# ---------------------------------------------------------------------------- solver
+class OracleSolver:
+    """Periodic-box DGSEM solver on the CPU (plain loops, fp64 or fp80)."""
+
+    def __init__(self, ex, ey=None, ez=None, lo=(0.0, 0.0, 0.0), hi=None, deform=False,
+                 amp=0.05, N=3, orders=None, gamma=1.4, Pr=0.71, Ma=0.1, Re=0.0, vol="ec",
+                 surf="roe", precision="fp64"):
+        ey = ex if ey is None else ey
+        ez = ex if ez is None else ez
+        if hi is None:
+            hi = (2 * np.pi,) * 3
+        self.L = _lib(precision)
+        self.shape = (ex, ey, ez)
+        self.gamma, self.Pr, self.Ma, self.Re = gamma, Pr, Ma, Re
+        lo = _f64(lo, 3)
+        hi = _f64(hi, 3)
+        optr = None
+        if orders is not None:
+            self._orders = np.ascontiguousarray(orders, dtype=np.int32).reshape(-1)
+            assert self._orders.size == 3 * ex * ey * ez
+            optr = self._orders.ctypes.data_as(_ip)
+        self.h = self.L.orc_create(ex, ey, ez, _ptr(lo), _ptr(hi), int(bool(deform)), amp, int(N),
+                                   optr, gamma, Pr, Ma, Re, VOL[vol], SURF[surf])
+        if not self.h:
+            raise ValueError("orc_create rejected the configuration")
+        self.nodes = self.L.orc_num_nodes(self.h)
+        self.E = self.L.orc_num_elements(self.h)
+
+    def close(self):
+        if self.h:
+            self.L.orc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def elem(self, e):
+        n3 = (ctypes.c_int * 3)()
+        off = ctypes.c_long()
+        self.L.orc_elem_info(self.h, e, n3, ctypes.byref(off))
+        return tuple(n3), off.value
+
+    def coords(self):
+        X = np.zeros(3 * self.nodes)
+        self.L.orc_get_coords(self.h, _ptr(X))
+        return X
+
+    def metrics(self):
+        Ja, J = np.zeros(9 * self.nodes), np.zeros(self.nodes)
+        self.L.orc_get_metrics(self.h, _ptr(Ja), _ptr(J))
+        return Ja, J
+
+    def set_ic(self, ic, params=None):
+        p = _f64(params if params is not None else np.zeros(9))
+        if self.L.orc_set_ic(self.h, IC[ic], _ptr(p)):
+            raise ValueError("orc_set_ic failed")
+
+    def set_state(self, U):
+        U = _f64(U, 5 * self.nodes)
+        self.L.orc_set_state(self.h, _ptr(U))
+
+    def state(self):
+        U = np.zeros(5 * self.nodes)
+        self.L.orc_get_state(self.h, _ptr(U))
+        return U
+
+    def residual(self):
+        R = np.zeros(5 * self.nodes)
+        self.L.orc_residual(self.h, _ptr(R))
+        return R
+
+    def gradients(self):
+        G = np.zeros(12 * self.nodes)
+        self.L.orc_gradients(self.h, _ptr(G))
+        return G
+
+    def rk3(self, dt, nsteps):
+        self.L.orc_rk3(self.h, float(dt), int(nsteps))
+
+    def suggest_dt(self, cfl):
+        return self.L.orc_suggest_dt(self.h, float(cfl))
+
+    def diagnostics(self):
+        out = np.zeros(14)
+        self.L.orc_diagnostics(self.h, _ptr(out))
+        return dict(zip(DIAG_KEYS, out.tolist()))
+
+    def entropy_production(self, R):
+        return self.L.orc_entropy_production(self.h, _ptr(_f64(R, 5 * self.nodes)))

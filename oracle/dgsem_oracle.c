@@ -1,0 +1,1193 @@
+/*
+ * dgsem_oracle.c -- plain CPU oracle of the DGSEM residual and low-storage RK3 (HORSES3D,
+ * arXiv 2206.09733).  TEST INFRASTRUCTURE ONLY: loaded by tests/, __graft_entry__.smoke()
+ * and bench.py's cpu_baseline leg, never by the product path.  It shares no code with the
+ * HIP library.
+ *
+ * The paper states the continuous problem and the weak form but not the discrete formulas.
+ * Each step below names the passage it follows and the reading taken where the paper is
+ * silent:
+ *   - conservation law, Euler and viscous fluxes: section "Compressible Navier-Stokes",
+ *     eqs. compressibleNScompact and viscousfluxes (row 1 of F_e read as rho*v3; rho*e read as
+ *     total energy per unit volume; H=(rho*e+p)/rho; calorically perfect gas, gamma=1.4,
+ *     R=1 so T=p/rho, constant mu=1/Re, kappa=mu*gamma/((gamma-1)Pr));
+ *   - curvilinear map, Jacobian, contravariant fluxes: section "Spatial discretisation",
+ *     eq. compressibleNScompact_transformed; metric terms in the conservative curl form
+ *     (the p-nonconforming geometry rules the paper cites for section "Spatial p-adaptation");
+ *   - weak form with numerical flux (eqs. NS2-NS4) on Gauss-Lobatto points, written in the
+ *     equivalent SBP strong form with a boundary lift (section "Energy/Entropy stable
+ *     versions": the SBP-SAT property of Gauss-Lobatto quadrature);
+ *   - split-form volume term with Chandrashekar's entropy-conserving two-point flux and the
+ *     averaged metric of the two nodes (same section, list of split forms);
+ *   - Riemann fluxes Roe, Lax-Friedrichs (local, i.e. Rusanov), central and the EC flux at
+ *     faces (box of convective fluxes in section "Spatial discretisation");
+ *   - BR1 for the viscous terms (same box), gradients of (v,T) lifted with the face average;
+ *   - mortar coupling for faces between elements of different orders (section "Spatial
+ *     p-adaptation"): interpolate both traces to the finer face grid, flux there, L2-project
+ *     back with exactly integrated matrices;
+ *   - Williamson's low-storage RK3 (section "Time advancement");
+ *   - entropy S=-rho*s, s=ln p - gamma ln rho and w=dS/du (section "Shock capturing",
+ *     eq. shock:entropy).
+ */
+#include "dgsem_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#ifdef ORC_LONG_DOUBLE
+typedef long double real;
+#define RSQRT sqrtl
+#define RLOG logl
+#define RSIN sinl
+#define RCOS cosl
+#define RFABS fabsl
+#define REXP expl
+#define RPOW powl
+#else
+typedef double real;
+#define RSQRT sqrt
+#define RLOG log
+#define RSIN sin
+#define RCOS cos
+#define RFABS fabs
+#define REXP exp
+#define RPOW pow
+#endif
+
+#define PI_L 3.141592653589793238462643383279502884L
+
+/* ------------------------------------------------------------------------------------------
+ * 1. Gauss-Lobatto tables.  Nodes: -1, +1 and the roots of L_N' (found by Newton on
+ *    L_{N+1}-L_{N-1}, which vanishes exactly at the N+1 Lobatto points); weights
+ *    2/(N(N+1) L_N(x_j)^2); derivative matrix of the Lagrange interpolant through the nodes,
+ *    D_ij = L_N(x_i)/(L_N(x_j)(x_i-x_j)) off the diagonal, D_00=-N(N+1)/4, D_NN=N(N+1)/4.
+ *    All in long double, then rounded to `real`.
+ * ---------------------------------------------------------------------------------------- */
+static void legendre(int N, long double x, long double* L, long double* dL) {
+  if (N == 0) { *L = 1.0L; *dL = 0.0L; return; }
+  long double Lm = 1.0L, Lc = x, dLm = 0.0L, dLc = 1.0L;
+  for (int k = 1; k < N; k++) {
+    long double Ln = ((2.0L * k + 1.0L) * x * Lc - k * Lm) / (k + 1.0L);
+    long double dLn = dLm + (2.0L * k + 1.0L) * Lc;
+    Lm = Lc; Lc = Ln; dLm = dLc; dLc = dLn;
+  }
+  *L = Lc; *dL = dLc;
+}
+
+typedef struct {
+  real xi[ORC_NMAX + 1];
+  real w[ORC_NMAX + 1];
+  real D[ORC_NMAX + 1][ORC_NMAX + 1];
+  long double xl[ORC_NMAX + 1];
+} gll_t;
+
+static gll_t GLL[ORC_NMAX + 1];
+static int GLL_READY = 0;
+
+static void gll_build(int N, gll_t* g) {
+  long double x[ORC_NMAX + 1];
+  x[0] = -1.0L; x[N] = 1.0L;
+  for (int j = 1; j <= N / 2 && j < N; j++) {
+    long double t = -cosl(PI_L * j / N);
+    for (int it = 0; it < 200; it++) {
+      long double a, da, b, db, c, dc;
+      legendre(N + 1, t, &a, &da);
+      legendre(N - 1, t, &b, &db);
+      legendre(N, t, &c, &dc);
+      long double q = a - b, dq = (2.0L * N + 1.0L) * c;
+      long double dt = q / dq;
+      t -= dt;
+      if (fabsl(dt) < 1e-21L) break;
+    }
+    x[j] = t;
+    x[N - j] = -t;
+  }
+  if (N % 2 == 0 && N > 0) x[N / 2] = 0.0L;
+  long double LN[ORC_NMAX + 1];
+  for (int j = 0; j <= N; j++) {
+    long double dd;
+    legendre(N, x[j], &LN[j], &dd);
+    g->xl[j] = x[j];
+    g->xi[j] = (real)x[j];
+    g->w[j] = (real)(2.0L / (N * (N + 1.0L) * LN[j] * LN[j]));
+  }
+  for (int i = 0; i <= N; i++)
+    for (int j = 0; j <= N; j++) {
+      long double d;
+      if (i != j) d = LN[i] / (LN[j] * (x[i] - x[j]));
+      else if (i == 0) d = -N * (N + 1.0L) / 4.0L;
+      else if (i == N) d = N * (N + 1.0L) / 4.0L;
+      else d = 0.0L;
+      g->D[i][j] = (real)d;
+    }
+}
+
+static void mortar_tables(void);
+
+static void gll_init(void) {
+  if (GLL_READY) return;
+  for (int N = 1; N <= ORC_NMAX; N++) gll_build(N, &GLL[N]);
+  mortar_tables();
+  GLL_READY = 1;
+}
+
+int orc_gll(int N, double* xi, double* w, double* D) {
+  if (N < 1 || N > ORC_NMAX) return -1;
+  gll_init();
+  for (int i = 0; i <= N; i++) {
+    if (xi) xi[i] = (double)GLL[N].xi[i];
+    if (w) w[i] = (double)GLL[N].w[i];
+    for (int j = 0; j <= N; j++)
+      if (D) D[i * (N + 1) + j] = (double)GLL[N].D[i][j];
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------------------------
+ * 2. Mortar operators (section "Spatial p-adaptation": mortar coupling).  Interpolation from
+ *    the Lobatto grid of order N to the one of order M (Lagrange basis evaluated at the M
+ *    nodes), and the L2 projection back, P = Mass_N^{-1} B_NM with
+ *    Mass_N[i][j] = int l^N_i l^N_j and B_NM[i][j] = int l^N_i l^M_j integrated exactly by a
+ *    Gauss-Legendre rule of G = 2*ORC_NMAX+2 points.
+ * ---------------------------------------------------------------------------------------- */
+static long double lagrange(int N, int j, long double x) {
+  long double v = 1.0L;
+  for (int r = 0; r <= N; r++)
+    if (r != j) v *= (x - GLL[N].xl[r]) / (GLL[N].xl[j] - GLL[N].xl[r]);
+  return v;
+}
+
+#define GQ (2 * ORC_NMAX + 2)
+static long double GQX[GQ], GQW[GQ];
+static int GQ_READY = 0;
+
+static void gauss_init(void) {
+  if (GQ_READY) return;
+  for (int j = 0; j < GQ; j++) {
+    long double t = -cosl(PI_L * (j + 0.75L) / (GQ + 0.5L));
+    long double L, dL;
+    for (int it = 0; it < 200; it++) {
+      legendre(GQ, t, &L, &dL);
+      long double dt = L / dL;
+      t -= dt;
+      if (fabsl(dt) < 1e-21L) break;
+    }
+    legendre(GQ, t, &L, &dL);
+    GQX[j] = t;
+    GQW[j] = 2.0L / ((1.0L - t * t) * dL * dL);
+  }
+  GQ_READY = 1;
+}
+
+/* I[p][q]: value at node p of grid M of the order-N interpolant through values at node q. */
+static void interp_matrix(int N, int M, real I[ORC_NMAX + 1][ORC_NMAX + 1]) {
+  for (int p = 0; p <= M; p++)
+    for (int q = 0; q <= N; q++) I[p][q] = (real)lagrange(N, q, GLL[M].xl[p]);
+}
+
+/* P[i][q]: order-N nodal coefficient i of the L2 projection of the order-M basis function q. */
+static void project_matrix(int N, int M, real P[ORC_NMAX + 1][ORC_NMAX + 1]) {
+  gauss_init();
+  long double A[ORC_NMAX + 1][2 * (ORC_NMAX + 1)];
+  int n = N + 1;
+  for (int i = 0; i <= N; i++) {
+    for (int j = 0; j <= N; j++) {
+      long double s = 0.0L;
+      for (int g = 0; g < GQ; g++) s += GQW[g] * lagrange(N, i, GQX[g]) * lagrange(N, j, GQX[g]);
+      A[i][j] = s;
+    }
+    for (int j = 0; j <= M; j++) {
+      long double s = 0.0L;
+      for (int g = 0; g < GQ; g++) s += GQW[g] * lagrange(N, i, GQX[g]) * lagrange(M, j, GQX[g]);
+      A[i][n + j] = s;
+    }
+  }
+  /* Gauss-Jordan elimination with partial pivoting: [Mass | B] -> [I | Mass^{-1} B] */
+  for (int c = 0; c < n; c++) {
+    int piv = c;
+    for (int r = c + 1; r < n; r++)
+      if (fabsl(A[r][c]) > fabsl(A[piv][c])) piv = r;
+    if (piv != c)
+      for (int k = 0; k < n + M + 1; k++) { long double t = A[c][k]; A[c][k] = A[piv][k]; A[piv][k] = t; }
+    long double d = A[c][c];
+    for (int k = 0; k < n + M + 1; k++) A[c][k] /= d;
+    for (int r = 0; r < n; r++) {
+      if (r == c) continue;
+      long double f = A[r][c];
+      for (int k = 0; k < n + M + 1; k++) A[r][k] -= f * A[c][k];
+    }
+  }
+  for (int i = 0; i <= N; i++)
+    for (int q = 0; q <= M; q++) P[i][q] = (real)A[i][n + q];
+}
+
+/* INTERP[N][M]: order N -> order M interpolation, PROJ[N][M]: order M -> order N projection */
+static real INTERP[ORC_NMAX + 1][ORC_NMAX + 1][ORC_NMAX + 1][ORC_NMAX + 1];
+static real PROJ[ORC_NMAX + 1][ORC_NMAX + 1][ORC_NMAX + 1][ORC_NMAX + 1];
+
+static void mortar_tables(void) {
+  for (int N = 1; N <= ORC_NMAX; N++)
+    for (int M = N; M <= ORC_NMAX; M++) {
+      interp_matrix(N, M, INTERP[N][M]);
+      project_matrix(N, M, PROJ[N][M]);
+    }
+}
+
+int orc_mortar_matrices(int N, int M, double* I, double* P) {
+  if (N < 1 || M < N || M > ORC_NMAX) return -1;
+  gll_init();
+  for (int p = 0; p <= M; p++)
+    for (int q = 0; q <= N; q++) I[p * (N + 1) + q] = (double)INTERP[N][M][p][q];
+  for (int i = 0; i <= N; i++)
+    for (int q = 0; q <= M; q++) P[i * (M + 1) + q] = (double)PROJ[N][M][i][q];
+  return 0;
+}
+
+/* ------------------------------------------------------------------------------------------
+ * 3. Solver state.
+ * ---------------------------------------------------------------------------------------- */
+struct orc_solver {
+  int ex, ey, ez, E;
+  real lo[3], hi[3], h[3];
+  int deform;
+  real amp;
+  int (*N)[3];      /* polynomial order per element and reference direction */
+  long* off;        /* first node of each element */
+  long ntot;
+  int* nbr;         /* nbr[6e + 2d + s]: element across face (d, s), s=0 at xi_d=-1, 1 at +1 */
+  real gamma, Pr, Ma, Re, mu, kappa;
+  int vol, surf, viscous;
+  real *X, *Ja, *J; /* coordinates, metric terms, Jacobian */
+  real *U, *dU, *G, *R;
+};
+
+static inline long nidx(const int n1, const int n2, int i, int j, int k) {
+  return i + (long)n1 * (j + (long)n2 * k);
+}
+
+/* index of the node of element e with reference indices (i0,i1,i2) */
+static inline long node_of(const orc_solver* s, int e, const int ii[3]) {
+  const int* N = s->N[e];
+  return nidx(N[0] + 1, N[1] + 1, ii[0], ii[1], ii[2]);
+}
+
+static inline int nn_of(const orc_solver* s, int e) {
+  return (s->N[e][0] + 1) * (s->N[e][1] + 1) * (s->N[e][2] + 1);
+}
+
+/* state of node q of element e from array A (5 fields) */
+static inline void load5(const orc_solver* s, const real* A, int e, long q, real u[5]) {
+  int nn = nn_of(s, e);
+  const real* base = A + s->off[e] * 5;
+  for (int v = 0; v < 5; v++) u[v] = base[(long)v * nn + q];
+}
+
+static inline void load_ja(const orc_solver* s, int e, long q, int d, real n[3]) {
+  int nn = nn_of(s, e);
+  const real* base = s->Ja + s->off[e] * 9;
+  for (int c = 0; c < 3; c++) n[c] = base[(long)(3 * d + c) * nn + q];
+}
+
+/* ------------------------------------------------------------------------------------------
+ * 4. Mesh: periodic box, optional sin*sin deformation evaluated on the undeformed
+ *    coordinates, nodes = map at the Lobatto points (isoparametric).
+ * ---------------------------------------------------------------------------------------- */
+static void displacement(const orc_solver* s, const real xu[3], real dx[3]) {
+  dx[0] = dx[1] = dx[2] = 0;
+  if (s->deform) {
+    dx[0] = s->amp * RSIN(xu[1]) * RSIN(xu[2]);
+    dx[1] = s->amp * RSIN(xu[2]) * RSIN(xu[0]);
+    dx[2] = s->amp * RSIN(xu[0]) * RSIN(xu[1]);
+  }
+}
+
+/* derivative of a nodal field f along reference direction d at node (i,j,k) of element e */
+static real dref(const orc_solver* s, int e, const real* f, int d, const int ii[3]) {
+  int Nd = s->N[e][d];
+  real acc = 0;
+  int jj[3] = {ii[0], ii[1], ii[2]};
+  for (int m = 0; m <= Nd; m++) {
+    jj[d] = m;
+    acc += GLL[Nd].D[ii[d]][m] * f[node_of(s, e, jj)];
+  }
+  return acc;
+}
+
+static void build_geometry(orc_solver* s) {
+#pragma omp parallel for schedule(static)
+  for (int e = 0; e < s->E; e++) {
+    int a = e % s->ex, b = (e / s->ex) % s->ey, c = e / (s->ex * s->ey);
+    int cell[3] = {a, b, c};
+    const int* N = s->N[e];
+    int nn = nn_of(s, e);
+    real* X = s->X + s->off[e] * 3;
+    /* The map is x = corner + Xl, Xl = (1+xi)/2 h + displacement.  The metric terms depend
+     * only on derivatives of x and on x up to a constant per element (a constant c added to
+     * X_l in the curl form adds c grad X_m, whose discrete curl vanishes because the
+     * tensor-product derivative matrices commute), so they are formed from Xl, whose size is
+     * the element's, not the box's. */
+    real* Xl = (real*)malloc(sizeof(real) * 3 * nn);
+    for (int k = 0; k <= N[2]; k++)
+      for (int j = 0; j <= N[1]; j++)
+        for (int i = 0; i <= N[0]; i++) {
+          int ii[3] = {i, j, k};
+          real xu[3], loc[3], dx[3];
+          for (int d = 0; d < 3; d++) {
+            loc[d] = (1 + GLL[N[d]].xi[ii[d]]) / 2 * s->h[d];
+            xu[d] = s->lo[d] + cell[d] * s->h[d] + loc[d];
+          }
+          displacement(s, xu, dx);
+          long q = node_of(s, e, ii);
+          for (int d = 0; d < 3; d++) {
+            X[(long)d * nn + q] = xu[d] + dx[d];
+            Xl[(long)d * nn + q] = loc[d] + dx[d];
+          }
+        }
+    /* dX[m][d]: derivative of coordinate m along xi_d */
+    real* dX = (real*)malloc(sizeof(real) * 9 * nn);
+    real* A = (real*)malloc(sizeof(real) * 3 * nn);
+    for (int k = 0; k <= N[2]; k++)
+      for (int j = 0; j <= N[1]; j++)
+        for (int i = 0; i <= N[0]; i++) {
+          int ii[3] = {i, j, k};
+          long q = node_of(s, e, ii);
+          for (int m = 0; m < 3; m++)
+            for (int d = 0; d < 3; d++) dX[(3 * m + d) * nn + q] = dref(s, e, Xl + (long)m * nn, d, ii);
+        }
+    real* Ja = s->Ja + s->off[e] * 9;
+    real* J = s->J + s->off[e];
+    /* curl form: Ja^i_n = -[curl_xi (X_l grad_xi X_m)]_i with (n,m,l) cyclic */
+    for (int n = 0; n < 3; n++) {
+      int m = (n + 1) % 3, l = (n + 2) % 3;
+      for (int q = 0; q < nn; q++)
+        for (int d = 0; d < 3; d++) A[d * nn + q] = Xl[(long)l * nn + q] * dX[(3 * m + d) * nn + q];
+      for (int k = 0; k <= N[2]; k++)
+        for (int j = 0; j <= N[1]; j++)
+          for (int i = 0; i <= N[0]; i++) {
+            int ii[3] = {i, j, k};
+            long q = node_of(s, e, ii);
+            /* curl components: (d1 A2 - d2 A1, d2 A0 - d0 A2, d0 A1 - d1 A0) */
+            real c0 = dref(s, e, A + 2 * nn, 1, ii) - dref(s, e, A + 1 * nn, 2, ii);
+            real c1 = dref(s, e, A + 0 * nn, 2, ii) - dref(s, e, A + 2 * nn, 0, ii);
+            real c2 = dref(s, e, A + 1 * nn, 0, ii) - dref(s, e, A + 0 * nn, 1, ii);
+            Ja[(long)(3 * 0 + n) * nn + q] = -c0;
+            Ja[(long)(3 * 1 + n) * nn + q] = -c1;
+            Ja[(long)(3 * 2 + n) * nn + q] = -c2;
+          }
+    }
+    /* J = a_1 . (a_2 x a_3), a_d = dX/dxi_d */
+    for (int q = 0; q < nn; q++) {
+      real a1[3], a2[3], a3[3];
+      for (int m = 0; m < 3; m++) {
+        a1[m] = dX[(3 * m + 0) * nn + q];
+        a2[m] = dX[(3 * m + 1) * nn + q];
+        a3[m] = dX[(3 * m + 2) * nn + q];
+      }
+      J[q] = a1[0] * (a2[1] * a3[2] - a2[2] * a3[1]) + a1[1] * (a2[2] * a3[0] - a2[0] * a3[2]) +
+             a1[2] * (a2[0] * a3[1] - a2[1] * a3[0]);
+    }
+    free(dX);
+    free(A);
+    free(Xl);
+  }
+}
+
+orc_solver* orc_create(int ex, int ey, int ez, const double* lo, const double* hi, int deform,
+                       double amp, int n_uniform, const int* orders, double gamma, double Pr,
+                       double Ma, double Re, int vol_flux, int surf_flux) {
+  if (ex < 1 || ey < 1 || ez < 1 || !lo || !hi) return NULL;
+  if (vol_flux < 0 || vol_flux > 1 || surf_flux < 0 || surf_flux > 3) return NULL;
+  gll_init();
+  orc_solver* s = (orc_solver*)calloc(1, sizeof(orc_solver));
+  s->ex = ex; s->ey = ey; s->ez = ez; s->E = ex * ey * ez;
+  for (int d = 0; d < 3; d++) { s->lo[d] = lo[d]; s->hi[d] = hi[d]; }
+  s->h[0] = (s->hi[0] - s->lo[0]) / ex;
+  s->h[1] = (s->hi[1] - s->lo[1]) / ey;
+  s->h[2] = (s->hi[2] - s->lo[2]) / ez;
+  s->deform = deform; s->amp = amp;
+  s->gamma = gamma; s->Pr = Pr; s->Ma = Ma; s->Re = Re;
+  s->viscous = Re > 0;
+  s->mu = s->viscous ? (real)1 / (real)Re : 0;
+  s->kappa = s->viscous ? s->mu * s->gamma / ((s->gamma - 1) * s->Pr) : 0;
+  s->vol = vol_flux; s->surf = surf_flux;
+  s->N = (int(*)[3])malloc(sizeof(int[3]) * s->E);
+  s->off = (long*)malloc(sizeof(long) * (s->E + 1));
+  long acc = 0;
+  for (int e = 0; e < s->E; e++) {
+    for (int d = 0; d < 3; d++) {
+      int n = orders ? orders[3 * e + d] : n_uniform;
+      if (n < 1 || n > ORC_NMAX) { orc_destroy(s); return NULL; }
+      s->N[e][d] = n;
+    }
+    s->off[e] = acc;
+    acc += nn_of(s, e);
+  }
+  s->off[s->E] = acc;
+  s->ntot = acc;
+  s->nbr = (int*)malloc(sizeof(int) * 6 * s->E);
+  for (int e = 0; e < s->E; e++) {
+    int a = e % ex, b = (e / ex) % ey, c = e / (ex * ey);
+    s->nbr[6 * e + 0] = ((a + ex - 1) % ex) + ex * (b + ey * c);
+    s->nbr[6 * e + 1] = ((a + 1) % ex) + ex * (b + ey * c);
+    s->nbr[6 * e + 2] = a + ex * (((b + ey - 1) % ey) + ey * c);
+    s->nbr[6 * e + 3] = a + ex * (((b + 1) % ey) + ey * c);
+    s->nbr[6 * e + 4] = a + ex * (b + ey * ((c + ez - 1) % ez));
+    s->nbr[6 * e + 5] = a + ex * (b + ey * ((c + 1) % ez));
+  }
+  /* viscous terms are only defined here on conforming faces */
+  if (s->viscous)
+    for (int e = 0; e < s->E; e++)
+      for (int d = 0; d < 3; d++) {
+        int r = s->nbr[6 * e + 2 * d + 1];
+        for (int t = 0; t < 3; t++)
+          if (t != d && s->N[e][t] != s->N[r][t]) { orc_destroy(s); return NULL; }
+      }
+  s->X = (real*)calloc(3 * acc, sizeof(real));
+  s->Ja = (real*)calloc(9 * acc, sizeof(real));
+  s->J = (real*)calloc(acc, sizeof(real));
+  s->U = (real*)calloc(5 * acc, sizeof(real));
+  s->dU = (real*)calloc(5 * acc, sizeof(real));
+  s->R = (real*)calloc(5 * acc, sizeof(real));
+  s->G = (real*)calloc(12 * acc, sizeof(real));
+  if (!s->X || !s->Ja || !s->J || !s->U || !s->dU || !s->R || !s->G) { orc_destroy(s); return NULL; }
+  build_geometry(s);
+  return s;
+}
+
+void orc_destroy(orc_solver* s) {
+  if (!s) return;
+  free(s->N); free(s->off); free(s->nbr);
+  free(s->X); free(s->Ja); free(s->J);
+  free(s->U); free(s->dU); free(s->G); free(s->R);
+  free(s);
+}
+
+long orc_num_nodes(const orc_solver* s) { return s ? s->ntot : -1; }
+int orc_num_elements(const orc_solver* s) { return s ? s->E : -1; }
+int orc_elem_info(const orc_solver* s, int e, int* n3, long* off) {
+  if (!s || e < 0 || e >= s->E) return -1;
+  for (int d = 0; d < 3; d++) n3[d] = s->N[e][d];
+  *off = s->off[e];
+  return 0;
+}
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
+int orc_get_coords(const orc_solver* s, double* X) {
+  for (long i = 0; i < 3 * s->ntot; i++) X[i] = (double)s->X[i];
+  return 0;
+}
+int orc_get_metrics(const orc_solver* s, double* Ja, double* J) {
+  if (Ja) for (long i = 0; i < 9 * s->ntot; i++) Ja[i] = (double)s->Ja[i];
+  if (J) for (long i = 0; i < s->ntot; i++) J[i] = (double)s->J[i];
+  return 0;
+}
+
+/* ------------------------------------------------------------------------------------------
+ * 5. Physics (section "Compressible Navier-Stokes").
+ * ---------------------------------------------------------------------------------------- */
+typedef struct { real rho, v[3], p, E; } prim_t;
+
+static inline prim_t prim(const real u[5], real gamma) {
+  prim_t w;
+  w.rho = u[0];
+  for (int c = 0; c < 3; c++) w.v[c] = u[1 + c] / u[0];
+  w.E = u[4];
+  w.p = (gamma - 1) * (u[4] - (real)0.5 * u[0] * (w.v[0] * w.v[0] + w.v[1] * w.v[1] + w.v[2] * w.v[2]));
+  return w;
+}
+
+/* Euler flux along the (not necessarily unit) vector n: F_e . n */
+static void euler_flux(const real u[5], const real n[3], real gamma, real F[5]) {
+  prim_t w = prim(u, gamma);
+  real vn = w.v[0] * n[0] + w.v[1] * n[1] + w.v[2] * n[2];
+  F[0] = w.rho * vn;
+  for (int c = 0; c < 3; c++) F[1 + c] = u[1 + c] * vn + w.p * n[c];
+  F[4] = (w.E + w.p) * vn;
+}
+
+/* logarithmic mean (a-b)/(ln a - ln b), series in u=((a-b)/(a+b))^2 near a=b */
+static real logmean(real a, real b) {
+  real f = (a - b) / (a + b);
+  real u = f * f;
+  if (u < (real)1e-4) {
+    real s = 1 + u * ((real)1 / 3 + u * ((real)1 / 5 + u * ((real)1 / 7 + u * ((real)1 / 9 +
+             u * ((real)1 / 11 + u * ((real)1 / 13))))));
+    return (a + b) / (2 * s);
+  }
+  return (a - b) / (RLOG(a) - RLOG(b));
+}
+
+/* Chandrashekar's kinetic-energy-preserving, entropy-conserving two-point flux along n */
+static void two_point_ec(const real uL[5], const real uR[5], const real n[3], real gamma, real F[5]) {
+  prim_t L = prim(uL, gamma), R = prim(uR, gamma);
+  real bL = L.rho / (2 * L.p), bR = R.rho / (2 * R.p);
+  real rho_ln = logmean(L.rho, R.rho), b_ln = logmean(bL, bR);
+  real rho_a = (L.rho + R.rho) / 2, b_a = (bL + bR) / 2;
+  real v_a[3], v2_a = 0;
+  for (int c = 0; c < 3; c++) {
+    v_a[c] = (L.v[c] + R.v[c]) / 2;
+    v2_a += (L.v[c] * L.v[c] + R.v[c] * R.v[c]) / 2;
+  }
+  real p_hat = rho_a / (2 * b_a);
+  real vn = v_a[0] * n[0] + v_a[1] * n[1] + v_a[2] * n[2];
+  F[0] = rho_ln * vn;
+  for (int c = 0; c < 3; c++) F[1 + c] = F[0] * v_a[c] + p_hat * n[c];
+  F[4] = F[0] * (1 / (2 * (gamma - 1) * b_ln) - v2_a / 2) + v_a[0] * F[1] + v_a[1] * F[2] + v_a[2] * F[3];
+}
+
+static void two_point_central(const real uL[5], const real uR[5], const real n[3], real gamma, real F[5]) {
+  real FL[5], FR[5];
+  euler_flux(uL, n, gamma, FL);
+  euler_flux(uR, n, gamma, FR);
+  for (int v = 0; v < 5; v++) F[v] = (FL[v] + FR[v]) / 2;
+}
+
+/* Roe's wave decomposition along the unit normal n: sum_k f(lambda_k) alpha_k r_k with
+ * f = |.| (absval=1) or the identity (absval=0, then the sum equals F(uR)-F(uL)). */
+static void roe_waves(const real uL[5], const real uR[5], const real n[3], real gamma, int absval, real W[5]) {
+  prim_t L = prim(uL, gamma), R = prim(uR, gamma);
+  real sL = RSQRT(L.rho), sR = RSQRT(R.rho);
+  real HL = (L.E + L.p) / L.rho, HR = (R.E + R.p) / R.rho;
+  real v[3], q2 = 0;
+  for (int c = 0; c < 3; c++) { v[c] = (sL * L.v[c] + sR * R.v[c]) / (sL + sR); q2 += v[c] * v[c]; }
+  real H = (sL * HL + sR * HR) / (sL + sR);
+  real rho = sL * sR;
+  real c2 = (gamma - 1) * (H - q2 / 2), c = RSQRT(c2);
+  real vn = v[0] * n[0] + v[1] * n[1] + v[2] * n[2];
+  real drho = R.rho - L.rho, dp = R.p - L.p, dv[3];
+  for (int k = 0; k < 3; k++) dv[k] = R.v[k] - L.v[k];
+  real dvn = dv[0] * n[0] + dv[1] * n[1] + dv[2] * n[2];
+  real a1 = (dp - rho * c * dvn) / (2 * c2);
+  real a2 = drho - dp / c2;
+  real a3 = (dp + rho * c * dvn) / (2 * c2);
+  real l1 = vn - c, l2 = vn, l3 = vn + c;
+  if (absval) { l1 = RFABS(l1); l2 = RFABS(l2); l3 = RFABS(l3); }
+  real dvt[3];
+  for (int k = 0; k < 3; k++) dvt[k] = dv[k] - dvn * n[k];
+  real vdvt = v[0] * dvt[0] + v[1] * dvt[1] + v[2] * dvt[2];
+  W[0] = l1 * a1 + l2 * a2 + l3 * a3;
+  for (int k = 0; k < 3; k++)
+    W[1 + k] = l1 * a1 * (v[k] - c * n[k]) + l2 * (a2 * v[k] + rho * dvt[k]) + l3 * a3 * (v[k] + c * n[k]);
+  W[4] = l1 * a1 * (H - vn * c) + l2 * (a2 * q2 / 2 + rho * vdvt) + l3 * a3 * (H + vn * c);
+}
+
+/* numerical flux through a face with scaled normal S (S = |S| n_hat) */
+static void riemann(int kind, const real uL[5], const real uR[5], const real S[3], real gamma, real F[5]) {
+  real a = RSQRT(S[0] * S[0] + S[1] * S[1] + S[2] * S[2]);
+  real n[3] = {S[0] / a, S[1] / a, S[2] / a};
+  real FL[5], FR[5];
+  switch (kind) {
+    case ORC_SURF_ROE: {
+      real W[5];
+      euler_flux(uL, n, gamma, FL);
+      euler_flux(uR, n, gamma, FR);
+      roe_waves(uL, uR, n, gamma, 1, W);
+      for (int v = 0; v < 5; v++) F[v] = a * ((FL[v] + FR[v]) / 2 - W[v] / 2);
+      break;
+    }
+    case ORC_SURF_LLF: {
+      prim_t L = prim(uL, gamma), R = prim(uR, gamma);
+      real vnL = L.v[0] * n[0] + L.v[1] * n[1] + L.v[2] * n[2];
+      real vnR = R.v[0] * n[0] + R.v[1] * n[1] + R.v[2] * n[2];
+      real lL = RFABS(vnL) + RSQRT(gamma * L.p / L.rho);
+      real lR = RFABS(vnR) + RSQRT(gamma * R.p / R.rho);
+      real lam = lL > lR ? lL : lR;
+      euler_flux(uL, n, gamma, FL);
+      euler_flux(uR, n, gamma, FR);
+      for (int v = 0; v < 5; v++) F[v] = a * ((FL[v] + FR[v]) / 2 - lam * (uR[v] - uL[v]) / 2);
+      break;
+    }
+    case ORC_SURF_EC: two_point_ec(uL, uR, S, gamma, F); break;
+    default: two_point_central(uL, uR, S, gamma, F); break;
+  }
+}
+
+static void volume_flux(const orc_solver* s, const real uL[5], const real uR[5], const real n[3], real F[5]) {
+  if (s->vol == ORC_VOL_EC) two_point_ec(uL, uR, n, s->gamma, F);
+  else two_point_central(uL, uR, n, s->gamma, F);
+}
+
+/* viscous flux (eq. viscousfluxes) from the state and the gradients of (v1,v2,v3,T);
+ * grad[3c+n] = d g_c / d x_n.  Fv[5n+v]: component v of the flux in physical direction n. */
+static void viscous_flux(const real u[5], const real grad[12], real gamma, real mu, real kappa, real Fv[15]) {
+  prim_t w = prim(u, gamma);
+  real divv = grad[0] + grad[4] + grad[8];
+  real tau[3][3];
+  for (int a = 0; a < 3; a++)
+    for (int b = 0; b < 3; b++)
+      tau[a][b] = mu * (grad[3 * a + b] + grad[3 * b + a]) - (a == b ? (real)2 / 3 * mu * divv : 0);
+  for (int n = 0; n < 3; n++) {
+    Fv[5 * n + 0] = 0;
+    for (int a = 0; a < 3; a++) Fv[5 * n + 1 + a] = tau[a][n];
+    Fv[5 * n + 4] = w.v[0] * tau[0][n] + w.v[1] * tau[1][n] + w.v[2] * tau[2][n] + kappa * grad[9 + n];
+  }
+}
+
+/* ------------------------------------------------------------------------------------------
+ * 6. Faces.  The face between L (its xi_d=+1 side) and R = nbr(L, +d) (its xi_d=-1 side) is
+ *    oriented along +xi_d and uses L's metric Ja^d as the scaled normal S.  Both elements
+ *    evaluate it with the same arguments, so the flux is single-valued.  Conforming faces:
+ *    pointwise.  Non-conforming faces: mortar of orders (max, max) in the two tangential
+ *    directions; traces and L's normal interpolated to it, flux there, projected back to
+ *    each side's grid.
+ * ---------------------------------------------------------------------------------------- */
+static void face_dirs(int d, int* ta, int* tb) {
+  *ta = d == 0 ? 1 : 0;
+  *tb = d == 2 ? 1 : 2;
+}
+
+/* Flux on the face (L, +d), on the whole node grid of one side (want_R = 0: L's grid,
+ * 1: R's grid).  F[v*na*nb + p + na*r], (p, r) the indices along the two tangential
+ * directions (ta < tb). */
+static void face_flux_side(const orc_solver* s, const real* U, int L, int d, int want_R, real* F) {
+  int R = s->nbr[6 * L + 2 * d + 1];
+  int ta, tb;
+  face_dirs(d, &ta, &tb);
+  const int* NL = s->N[L];
+  const int* NR = s->N[R];
+  const int* Ns = want_R ? NR : NL;
+  int na = Ns[ta] + 1, nb = Ns[tb] + 1, nf = na * nb;
+  if (NL[ta] == NR[ta] && NL[tb] == NR[tb]) {
+    for (int r = 0; r < nb; r++)
+      for (int p = 0; p < na; p++) {
+        int iL[3], iR[3];
+        iL[d] = NL[d]; iL[ta] = p; iL[tb] = r;
+        iR[d] = 0; iR[ta] = p; iR[tb] = r;
+        real uL[5], uR[5], S[3], Fp[5];
+        load5(s, U, L, node_of(s, L, iL), uL);
+        load5(s, U, R, node_of(s, R, iR), uR);
+        load_ja(s, L, node_of(s, L, iL), d, S);
+        riemann(s->surf, uL, uR, S, s->gamma, Fp);
+        for (int v = 0; v < 5; v++) F[v * nf + p + na * r] = Fp[v];
+      }
+    return;
+  }
+  int Ma = NL[ta] > NR[ta] ? NL[ta] : NR[ta];
+  int Mb = NL[tb] > NR[tb] ? NL[tb] : NR[tb];
+  int nma = Ma + 1, nmb = Mb + 1;
+  real* Fm = (real*)malloc(sizeof(real) * 5 * nma * nmb);
+  for (int rm = 0; rm < nmb; rm++)
+    for (int pm = 0; pm < nma; pm++) {
+      real uL[5] = {0, 0, 0, 0, 0}, uR[5] = {0, 0, 0, 0, 0}, S[3] = {0, 0, 0};
+      for (int r2 = 0; r2 <= NL[tb]; r2++)
+        for (int p2 = 0; p2 <= NL[ta]; p2++) {
+          int ii[3];
+          ii[d] = NL[d]; ii[ta] = p2; ii[tb] = r2;
+          real w = INTERP[NL[ta]][Ma][pm][p2] * INTERP[NL[tb]][Mb][rm][r2], u[5], n[3];
+          long q = node_of(s, L, ii);
+          load5(s, U, L, q, u);
+          load_ja(s, L, q, d, n);
+          for (int v = 0; v < 5; v++) uL[v] += w * u[v];
+          for (int c = 0; c < 3; c++) S[c] += w * n[c];
+        }
+      for (int r2 = 0; r2 <= NR[tb]; r2++)
+        for (int p2 = 0; p2 <= NR[ta]; p2++) {
+          int ii[3];
+          ii[d] = 0; ii[ta] = p2; ii[tb] = r2;
+          real w = INTERP[NR[ta]][Ma][pm][p2] * INTERP[NR[tb]][Mb][rm][r2], u[5];
+          load5(s, U, R, node_of(s, R, ii), u);
+          for (int v = 0; v < 5; v++) uR[v] += w * u[v];
+        }
+      real Fp[5];
+      riemann(s->surf, uL, uR, S, s->gamma, Fp);
+      for (int v = 0; v < 5; v++) Fm[v * nma * nmb + pm + nma * rm] = Fp[v];
+    }
+  for (int r = 0; r < nb; r++)
+    for (int p = 0; p < na; p++)
+      for (int v = 0; v < 5; v++) {
+        real acc = 0;
+        for (int rm = 0; rm < nmb; rm++)
+          for (int pm = 0; pm < nma; pm++)
+            acc += PROJ[Ns[ta]][Ma][p][pm] * PROJ[Ns[tb]][Mb][r][rm] * Fm[v * nma * nmb + pm + nma * rm];
+        F[v * nf + p + na * r] = acc;
+      }
+  free(Fm);
+}
+
+/* ------------------------------------------------------------------------------------------
+ * 7. BR1 gradients of g = (v1, v2, v3, T), T = p/rho:
+ *    J grad g = sum_d Ja^d [ D_d g + (1/w_N)(g*-g) at xi_d=+1 - (1/w_0)(g*-g) at xi_d=-1 ],
+ *    g* = average of the two traces.
+ * ---------------------------------------------------------------------------------------- */
+static inline void gvars(const real u[5], real gamma, real g[4]) {
+  prim_t w = prim(u, gamma);
+  g[0] = w.v[0]; g[1] = w.v[1]; g[2] = w.v[2];
+  g[3] = w.p / w.rho;
+}
+
+static void compute_gradients(orc_solver* s, const real* U, real* Gout) {
+#pragma omp parallel for schedule(static)
+  for (int e = 0; e < s->E; e++) {
+    const int* N = s->N[e];
+    int nn = nn_of(s, e);
+    real* G = Gout + s->off[e] * 12;
+    for (int k = 0; k <= N[2]; k++)
+      for (int j = 0; j <= N[1]; j++)
+        for (int i = 0; i <= N[0]; i++) {
+          int ii[3] = {i, j, k};
+          long q = node_of(s, e, ii);
+          real u[5], g[4];
+          load5(s, U, e, q, u);
+          gvars(u, s->gamma, g);
+          real acc[12] = {0};
+          for (int d = 0; d < 3; d++) {
+            real a[4] = {0, 0, 0, 0};
+            int jj[3] = {i, j, k};
+            for (int m = 0; m <= N[d]; m++) {
+              jj[d] = m;
+              real um[5], gm[4];
+              load5(s, U, e, node_of(s, e, jj), um);
+              gvars(um, s->gamma, gm);
+              for (int c = 0; c < 4; c++) a[c] += GLL[N[d]].D[ii[d]][m] * gm[c];
+            }
+            for (int side = 0; side < 2; side++) {
+              int at = side ? N[d] : 0;
+              if (ii[d] != at) continue;
+              int ne = s->nbr[6 * e + 2 * d + side];
+              int kk[3] = {i, j, k};
+              kk[d] = side ? 0 : s->N[ne][d];
+              real un[5], gn[4];
+              load5(s, U, ne, node_of(s, ne, kk), un);
+              gvars(un, s->gamma, gn);
+              real wgt = 1 / GLL[N[d]].w[at];
+              for (int c = 0; c < 4; c++) {
+                real jump = (g[c] + gn[c]) / 2 - g[c];
+                a[c] += side ? wgt * jump : -wgt * jump;
+              }
+            }
+            real n[3];
+            load_ja(s, e, q, d, n);
+            for (int c = 0; c < 4; c++)
+              for (int x = 0; x < 3; x++) acc[3 * c + x] += n[x] * a[c];
+          }
+          real Jq = s->J[s->off[e] + q];
+          for (int t = 0; t < 12; t++) G[(long)t * nn + q] = acc[t] / Jq;
+        }
+  }
+}
+
+/* contravariant viscous flux of node q of element e along xi_d */
+static void contra_visc(const orc_solver* s, const real* U, const real* Gall, int e, long q, int d, const real* Sopt,
+                        real Fd[5]) {
+  int nn = nn_of(s, e);
+  real u[5], gr[12], Fv[15], n[3];
+  load5(s, U, e, q, u);
+  for (int t = 0; t < 12; t++) gr[t] = Gall[s->off[e] * 12 + (long)t * nn + q];
+  viscous_flux(u, gr, s->gamma, s->mu, s->kappa, Fv);
+  if (Sopt) { n[0] = Sopt[0]; n[1] = Sopt[1]; n[2] = Sopt[2]; }
+  else load_ja(s, e, q, d, n);
+  for (int v = 0; v < 5; v++) Fd[v] = n[0] * Fv[v] + n[1] * Fv[5 + v] + n[2] * Fv[10 + v];
+}
+
+/* ------------------------------------------------------------------------------------------
+ * 8. Residual of one element:
+ *    J dU/dt = -[ sum_d sum_m 2 D_im F#(U_i,U_m; avg Ja^d)
+ *                 + (1/w_N)(F*-F~(U)) at xi_d=+1 - (1/w_0)(F*-F~(U)) at xi_d=-1 ]
+ *              + sum_d D_d F~_v^d + (1/w_N)(F~_v*-F~_v) at +1 - (1/w_0)(F~_v*-F~_v) at -1
+ * ---------------------------------------------------------------------------------------- */
+static void element_residual(const orc_solver* s, const real* U, const real* Gall, int e, real* R) {
+  const int* N = s->N[e];
+  int nn = nn_of(s, e);
+  /* numerical flux on the six faces, each on this element's face grid */
+  real* Ff[6];
+  for (int d = 0; d < 3; d++) {
+    int ta, tb;
+    face_dirs(d, &ta, &tb);
+    int nf = (N[ta] + 1) * (N[tb] + 1);
+    for (int side = 0; side < 2; side++) {
+      Ff[2 * d + side] = (real*)malloc(sizeof(real) * 5 * nf);
+      int L = side ? e : s->nbr[6 * e + 2 * d];
+      face_flux_side(s, U, L, d, side ? 0 : 1, Ff[2 * d + side]);
+    }
+  }
+  for (int k = 0; k <= N[2]; k++)
+    for (int j = 0; j <= N[1]; j++)
+      for (int i = 0; i <= N[0]; i++) {
+        int ii[3] = {i, j, k};
+        long q = node_of(s, e, ii);
+        real u[5];
+        load5(s, U, e, q, u);
+        real V[5] = {0, 0, 0, 0, 0}, Sf[5] = {0, 0, 0, 0, 0};
+        real Vv[5] = {0, 0, 0, 0, 0}, Sv[5] = {0, 0, 0, 0, 0};
+        for (int d = 0; d < 3; d++) {
+          int Nd = N[d];
+          real nq[3];
+          load_ja(s, e, q, d, nq);
+          int jj[3] = {i, j, k};
+          for (int m = 0; m <= Nd; m++) {
+            jj[d] = m;
+            long qm = node_of(s, e, jj);
+            real um[5], nm[3], navg[3], F[5];
+            load5(s, U, e, qm, um);
+            load_ja(s, e, qm, d, nm);
+            for (int c = 0; c < 3; c++) navg[c] = (nq[c] + nm[c]) / 2;
+            volume_flux(s, u, um, navg, F);
+            for (int v = 0; v < 5; v++) V[v] += 2 * GLL[Nd].D[ii[d]][m] * F[v];
+            if (s->viscous) {
+              real Fd[5];
+              contra_visc(s, U, Gall, e, qm, d, NULL, Fd);
+              for (int v = 0; v < 5; v++) Vv[v] += GLL[Nd].D[ii[d]][m] * Fd[v];
+            }
+          }
+          for (int side = 0; side < 2; side++) {
+            int at = side ? Nd : 0;
+            if (ii[d] != at) continue;
+            int ta, tb;
+            face_dirs(d, &ta, &tb);
+            int na = N[ta] + 1, nf = na * (N[tb] + 1);
+            real Fs[5], Fo[5];
+            for (int v = 0; v < 5; v++) Fs[v] = Ff[2 * d + side][v * nf + ii[ta] + na * ii[tb]];
+            euler_flux(u, nq, s->gamma, Fo);
+            real wgt = 1 / GLL[Nd].w[at];
+            for (int v = 0; v < 5; v++) Sf[v] += (side ? wgt : -wgt) * (Fs[v] - Fo[v]);
+            if (s->viscous) {
+              /* conforming only: matching node on the other element */
+              int oth = s->nbr[6 * e + 2 * d + side];
+              int kk[3] = {i, j, k};
+              kk[d] = side ? 0 : s->N[oth][d];
+              long qo = node_of(s, oth, kk);
+              int Lq_e = side ? e : oth;
+              long Lq = side ? q : qo;
+              real S[3];
+              load_ja(s, Lq_e, Lq, d, S);
+              real Fa[5], Fb[5], Fown[5];
+              contra_visc(s, U, Gall, e, q, d, S, Fa);
+              contra_visc(s, U, Gall, oth, qo, d, S, Fb);
+              contra_visc(s, U, Gall, e, q, d, NULL, Fown);
+              for (int v = 0; v < 5; v++) {
+                real fst = (Fa[v] + Fb[v]) / 2;
+                Sv[v] += (side ? wgt : -wgt) * (fst - Fown[v]);
+              }
+            }
+          }
+        }
+        real Jq = s->J[s->off[e] + q];
+        for (int v = 0; v < 5; v++) R[(long)v * nn + q] = (-V[v] - Sf[v] + Vv[v] + Sv[v]) / Jq;
+      }
+  for (int f = 0; f < 6; f++) free(Ff[f]);
+}
+
+static void residual(orc_solver* s, const real* U, real* R) {
+  if (s->viscous) compute_gradients(s, U, s->G);
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int e = 0; e < s->E; e++) element_residual(s, U, s->G, e, R + s->off[e] * 5);
+}
+
+int orc_residual(orc_solver* s, double* Rout) {
+  if (!s) return -1;
+  residual(s, s->U, s->R);
+  if (Rout) for (long i = 0; i < 5 * s->ntot; i++) Rout[i] = (double)s->R[i];
+  return 0;
+}
+
+int orc_gradients(orc_solver* s, double* Gout) {
+  if (!s) return -1;
+  compute_gradients(s, s->U, s->G);
+  for (long i = 0; i < 12 * s->ntot; i++) Gout[i] = (double)s->G[i];
+  return 0;
+}
+
+/* ------------------------------------------------------------------------------------------
+ * 9. Williamson's low-storage RK3:  dU <- A_k dU + dt R(U);  U <- U + B_k dU.
+ * ---------------------------------------------------------------------------------------- */
+int orc_rk3(orc_solver* s, double dt, int nsteps) {
+  if (!s || nsteps < 0) return -1;
+  const real A[3] = {0, (real)-5 / 9, (real)-153 / 128};
+  const real B[3] = {(real)1 / 3, (real)15 / 16, (real)8 / 15};
+  long n5 = 5 * s->ntot;
+  for (int step = 0; step < nsteps; step++)
+    for (int k = 0; k < 3; k++) {
+      residual(s, s->U, s->R);
+#pragma omp parallel for schedule(static)
+      for (long i = 0; i < n5; i++) {
+        s->dU[i] = (k == 0 ? 0 : A[k] * s->dU[i]) + (real)dt * s->R[i];
+        s->U[i] += B[k] * s->dU[i];
+      }
+    }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------------------------
+ * 10. Initial conditions, evaluated at the node coordinates.
+ *   UNIFORM (rho, v1, v2, v3, p);  TGV on [0,2pi]^3 with p0 = 1/(gamma Ma^2), rho = p/p0;
+ *   VORTEX (beta, x0, y0, u_inf, v_inf): isentropic vortex on a rho=p=1 free stream;
+ *   DENSITY_WAVE (amp, v1, v2, v3, p, k1, k2, k3, phase): rho = 1 + amp sin(k.x + phase).
+ * ---------------------------------------------------------------------------------------- */
+static void ic_point(const orc_solver* s, int ic, const double* P, const real x[3], real u[5]) {
+  real g = s->gamma;
+  real rho = 1, v[3] = {0, 0, 0}, p = 1;
+  if (ic == ORC_IC_UNIFORM) {
+    rho = P[0]; v[0] = P[1]; v[1] = P[2]; v[2] = P[3]; p = P[4];
+  } else if (ic == ORC_IC_TGV) {
+    real p0 = 1 / (g * s->Ma * s->Ma);
+    v[0] = RSIN(x[0]) * RCOS(x[1]) * RCOS(x[2]);
+    v[1] = -RCOS(x[0]) * RSIN(x[1]) * RCOS(x[2]);
+    v[2] = 0;
+    p = p0 + (RCOS(2 * x[0]) + RCOS(2 * x[1])) * (RCOS(2 * x[2]) + 2) / 16;
+    rho = p / p0;
+  } else if (ic == ORC_IC_VORTEX) {
+    real beta = P[0], dx = x[0] - P[1], dy = x[1] - P[2];
+    real r2 = dx * dx + dy * dy;
+    real pi = (real)PI_L;
+    real f = beta / (2 * pi) * REXP((1 - r2) / 2);
+    v[0] = P[3] - f * dy;
+    v[1] = P[4] + f * dx;
+    v[2] = 0;
+    real T = 1 - (g - 1) * beta * beta / (8 * g * pi * pi) * REXP(1 - r2);
+    rho = RPOW(T, 1 / (g - 1));
+    p = rho * T;
+  } else if (ic == ORC_IC_DENSITY_WAVE) {
+    rho = 1 + P[0] * RSIN(P[5] * x[0] + P[6] * x[1] + P[7] * x[2] + P[8]);
+    v[0] = P[1]; v[1] = P[2]; v[2] = P[3]; p = P[4];
+  }
+  u[0] = rho;
+  for (int c = 0; c < 3; c++) u[1 + c] = rho * v[c];
+  u[4] = p / (g - 1) + rho * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) / 2;
+}
+
+int orc_set_ic(orc_solver* s, int ic, const double* params) {
+  if (!s || ic < 0 || ic > 3) return -1;
+  if (ic != ORC_IC_TGV && !params) return -1;
+  for (int e = 0; e < s->E; e++) {
+    int nn = nn_of(s, e);
+    for (int q = 0; q < nn; q++) {
+      real x[3], u[5];
+      for (int d = 0; d < 3; d++) x[d] = s->X[s->off[e] * 3 + (long)d * nn + q];
+      ic_point(s, ic, params, x, u);
+      for (int v = 0; v < 5; v++) s->U[s->off[e] * 5 + (long)v * nn + q] = u[v];
+    }
+  }
+  memset(s->dU, 0, sizeof(real) * 5 * s->ntot);
+  return 0;
+}
+
+int orc_set_state(orc_solver* s, const double* U) {
+  if (!s || !U) return -1;
+  for (long i = 0; i < 5 * s->ntot; i++) s->U[i] = U[i];
+  memset(s->dU, 0, sizeof(real) * 5 * s->ntot);
+  return 0;
+}
+
+int orc_get_state(const orc_solver* s, double* U) {
+  if (!s || !U) return -1;
+  for (long i = 0; i < 5 * s->ntot; i++) U[i] = (double)s->U[i];
+  return 0;
+}
+
+/* time step: CFL h_min / ((N_max+1)^2 lambda_max), limited by the viscous bound
+ * 0.25 h_min^2 / ((N_max+1)^4 gamma mu / (Pr rho_min)) */
+double orc_suggest_dt(const orc_solver* s, double cfl) {
+  real hmin = s->h[0];
+  if (s->h[1] < hmin) hmin = s->h[1];
+  if (s->h[2] < hmin) hmin = s->h[2];
+  int Nmax = 1;
+  for (int e = 0; e < s->E; e++)
+    for (int d = 0; d < 3; d++)
+      if (s->N[e][d] > Nmax) Nmax = s->N[e][d];
+  real lam = 0, rmin = 1e300;
+  for (int e = 0; e < s->E; e++) {
+    int nn = nn_of(s, e);
+    for (int q = 0; q < nn; q++) {
+      real u[5];
+      load5(s, s->U, e, q, u);
+      prim_t w = prim(u, s->gamma);
+      real l = RSQRT(w.v[0] * w.v[0] + w.v[1] * w.v[1] + w.v[2] * w.v[2]) + RSQRT(s->gamma * w.p / w.rho);
+      if (l > lam) lam = l;
+      if (w.rho < rmin) rmin = w.rho;
+    }
+  }
+  real n1 = Nmax + 1;
+  real dt = (real)cfl * hmin / (n1 * n1 * lam);
+  if (s->viscous) {
+    real dtv = (real)0.25 * hmin * hmin / (n1 * n1 * n1 * n1 * s->gamma * s->mu / (s->Pr * rmin));
+    if (dtv < dt) dt = dtv;
+  }
+  return (double)dt;
+}
+
+/* ------------------------------------------------------------------------------------------
+ * 11. Diagnostics with the Lobatto quadrature w_i w_j w_k J:
+ *   out[0..4] integral of U; out[5] integral of -rho s; out[6] integral of -rho s/(gamma-1);
+ *   out[7] kinetic energy (volume mean of rho|v|^2/2); out[8] enstrophy (volume mean of
+ *   rho|curl v|^2/2, element-local derivative of v); out[9] max(|v|+c); out[10] min rho;
+ *   out[11] min p; out[12] number of non-finite state values; out[13] volume.
+ * ---------------------------------------------------------------------------------------- */
+int orc_diagnostics(const orc_solver* s, double* out) {
+  if (!s || !out) return -1;
+  real acc[9] = {0};
+  real lam = 0, rmin = 1e300, pmin = 1e300;
+  long bad = 0;
+  for (int e = 0; e < s->E; e++) {
+    const int* N = s->N[e];
+    int nn = nn_of(s, e);
+    real* vel = (real*)malloc(sizeof(real) * 3 * nn);
+    for (int q = 0; q < nn; q++) {
+      real u[5];
+      load5(s, s->U, e, q, u);
+      for (int c = 0; c < 3; c++) vel[c * nn + q] = u[1 + c] / u[0];
+    }
+    for (int k = 0; k <= N[2]; k++)
+      for (int j = 0; j <= N[1]; j++)
+        for (int i = 0; i <= N[0]; i++) {
+          int ii[3] = {i, j, k};
+          long q = node_of(s, e, ii);
+          real u[5];
+          load5(s, s->U, e, q, u);
+          for (int v = 0; v < 5; v++)
+            if (!isfinite((double)u[v])) bad++;
+          prim_t w = prim(u, s->gamma);
+          real Jq = s->J[s->off[e] + q];
+          real wq = GLL[N[0]].w[i] * GLL[N[1]].w[j] * GLL[N[2]].w[k] * Jq;
+          for (int v = 0; v < 5; v++) acc[v] += wq * u[v];
+          real sp = RLOG(w.p) - s->gamma * RLOG(w.rho);
+          acc[5] += wq * (-w.rho * sp);
+          acc[6] += wq * (-w.rho * sp / (s->gamma - 1));
+          real v2 = w.v[0] * w.v[0] + w.v[1] * w.v[1] + w.v[2] * w.v[2];
+          acc[7] += wq * w.rho * v2 / 2;
+          /* grad v: dv_c/dx_n = (1/J) sum_d Ja^d_n D_d v_c */
+          real gv[3][3] = {{0}};
+          for (int d = 0; d < 3; d++) {
+            real n[3];
+            load_ja(s, e, q, d, n);
+            for (int c = 0; c < 3; c++) {
+              real dd = dref(s, e, vel + c * nn, d, ii);
+              for (int x = 0; x < 3; x++) gv[c][x] += n[x] * dd / Jq;
+            }
+          }
+          real om[3] = {gv[2][1] - gv[1][2], gv[0][2] - gv[2][0], gv[1][0] - gv[0][1]};
+          acc[8] += wq * w.rho * (om[0] * om[0] + om[1] * om[1] + om[2] * om[2]) / 2;
+          real l = RSQRT(v2) + RSQRT(s->gamma * w.p / w.rho);
+          if (l > lam) lam = l;
+          if (w.rho < rmin) rmin = w.rho;
+          if (w.p < pmin) pmin = w.p;
+        }
+    free(vel);
+  }
+  real vol = 0;
+  for (int e = 0; e < s->E; e++) {
+    const int* N = s->N[e];
+    for (int k = 0; k <= N[2]; k++)
+      for (int j = 0; j <= N[1]; j++)
+        for (int i = 0; i <= N[0]; i++) {
+          int ii[3] = {i, j, k};
+          vol += GLL[N[0]].w[i] * GLL[N[1]].w[j] * GLL[N[2]].w[k] * s->J[s->off[e] + node_of(s, e, ii)];
+        }
+  }
+  for (int v = 0; v < 7; v++) out[v] = (double)acc[v];
+  out[7] = (double)(acc[7] / vol);
+  out[8] = (double)(acc[8] / vol);
+  out[9] = (double)lam;
+  out[10] = (double)rmin;
+  out[11] = (double)pmin;
+  out[12] = (double)bad;
+  out[13] = (double)vol;
+  return 0;
+}
+
+/* sum over nodes of w_i w_j w_k J w(U).R: the semi-discrete entropy production rate */
+double orc_entropy_production(const orc_solver* s, const double* R) {
+  real acc = 0;
+  for (int e = 0; e < s->E; e++) {
+    const int* N = s->N[e];
+    int nn = nn_of(s, e);
+    for (int k = 0; k <= N[2]; k++)
+      for (int j = 0; j <= N[1]; j++)
+        for (int i = 0; i <= N[0]; i++) {
+          int ii[3] = {i, j, k};
+          long q = node_of(s, e, ii);
+          real u[5];
+          load5(s, s->U, e, q, u);
+          prim_t w = prim(u, s->gamma);
+          real sp = RLOG(w.p) - s->gamma * RLOG(w.rho);
+          real b = w.rho / (2 * w.p);
+          real v2 = w.v[0] * w.v[0] + w.v[1] * w.v[1] + w.v[2] * w.v[2];
+          real wv[5] = {(s->gamma - sp) / (s->gamma - 1) - b * v2, 2 * b * w.v[0], 2 * b * w.v[1],
+                        2 * b * w.v[2], -2 * b};
+          real wq = GLL[N[0]].w[i] * GLL[N[1]].w[j] * GLL[N[2]].w[k] * s->J[s->off[e] + q];
+          for (int v = 0; v < 5; v++) acc += wq * wv[v] * (real)R[s->off[e] * 5 + (long)v * nn + q];
+        }
+  }
+  return (double)acc;
+}
+
+/* ------------------------------------------------------------------------------------------
+ * 12. Point functions exported for the pins.
+ * ---------------------------------------------------------------------------------------- */
+static void to_real(const double* a, real* b, int n) { for (int i = 0; i < n; i++) b[i] = a[i]; }
+static void to_dbl(const real* a, double* b, int n) { for (int i = 0; i < n; i++) b[i] = (double)a[i]; }
+
+int orc_euler_flux(const double* U, const double* n, double gamma, double* F) {
+  real u[5], nn[3], f[5];
+  to_real(U, u, 5); to_real(n, nn, 3);
+  euler_flux(u, nn, gamma, f);
+  to_dbl(f, F, 5);
+  return 0;
+}
+int orc_two_point_ec(const double* UL, const double* UR, const double* n, double gamma, double* F) {
+  real a[5], b[5], nn[3], f[5];
+  to_real(UL, a, 5); to_real(UR, b, 5); to_real(n, nn, 3);
+  two_point_ec(a, b, nn, gamma, f);
+  to_dbl(f, F, 5);
+  return 0;
+}
+int orc_two_point_central(const double* UL, const double* UR, const double* n, double gamma, double* F) {
+  real a[5], b[5], nn[3], f[5];
+  to_real(UL, a, 5); to_real(UR, b, 5); to_real(n, nn, 3);
+  two_point_central(a, b, nn, gamma, f);
+  to_dbl(f, F, 5);
+  return 0;
+}
+int orc_riemann(int kind, const double* UL, const double* UR, const double* S, double gamma, double* F) {
+  if (kind < 0 || kind > 3) return -1;
+  real a[5], b[5], nn[3], f[5];
+  to_real(UL, a, 5); to_real(UR, b, 5); to_real(S, nn, 3);
+  riemann(kind, a, b, nn, gamma, f);
+  to_dbl(f, F, 5);
+  return 0;
+}
+int orc_roe_waves(const double* UL, const double* UR, const double* nhat, double gamma, int absval, double* W) {
+  real a[5], b[5], nn[3], f[5];
+  to_real(UL, a, 5); to_real(UR, b, 5); to_real(nhat, nn, 3);
+  roe_waves(a, b, nn, gamma, absval, f);
+  to_dbl(f, W, 5);
+  return 0;
+}
+int orc_entropy_vars(const double* U, double gamma, double* wout) {
+  real u[5];
+  to_real(U, u, 5);
+  prim_t w = prim(u, gamma);
+  real sp = RLOG(w.p) - (real)gamma * RLOG(w.rho);
+  real b = w.rho / (2 * w.p);
+  real v2 = w.v[0] * w.v[0] + w.v[1] * w.v[1] + w.v[2] * w.v[2];
+  wout[0] = (double)(((real)gamma - sp) / ((real)gamma - 1) - b * v2);
+  for (int c = 0; c < 3; c++) wout[1 + c] = (double)(2 * b * w.v[c]);
+  wout[4] = (double)(-2 * b);
+  return 0;
+}
+double orc_entropy(const double* U, double gamma) {
+  real u[5];
+  to_real(U, u, 5);
+  prim_t w = prim(u, gamma);
+  real sp = RLOG(w.p) - (real)gamma * RLOG(w.rho);
+  return (double)(-w.rho * sp / ((real)gamma - 1));
+}
+double orc_logmean(double a, double b) { return (double)logmean(a, b); }
+int orc_viscous_flux(const double* U, const double* grad, double gamma, double Pr, double Re, double* Fv) {
+  real u[5], g[12], f[15];
+  to_real(U, u, 5); to_real(grad, g, 12);
+  real mu = (real)1 / (real)Re;
+  real kappa = mu * (real)gamma / (((real)gamma - 1) * (real)Pr);
+  viscous_flux(u, g, gamma, mu, kappa, f);
+  to_dbl(f, Fv, 15);
+  return 0;
+}
