@@ -1,0 +1,183 @@
+/*
+ * dgsem.h -- C ABI of the MI355X (gfx950) DGSEM library libdgsem.so.
+ *
+ * The library evaluates the semi-discrete residual dU/dt of the compressible Euler /
+ * Navier-Stokes equations (HORSES3D paper, arXiv 2206.09733, section "Compressible
+ * Navier-Stokes", eqs. compressibleNScompact and viscousfluxes) on curvilinear hexahedral
+ * Gauss-Lobatto spectral elements (section "Spatial discretisation: discontinuous Galerkin",
+ * eqs. compressibleNScompact_transformed and NS2-NS5): an entropy-conserving split-form
+ * volume term (section "Energy/Entropy stable versions"), Riemann fluxes with surface lifting
+ * (Roe, local Lax-Friedrichs, EC, central; box of convective fluxes), BR1 viscous terms (box
+ * of viscous fluxes), and advances it with Williamson's low-storage explicit RK3 (section
+ * "Time advancement").  Every step runs in hand-written HIP kernels.
+ *
+ * Conventions
+ *  - Status: every int-returning call returns DG_OK (0) or a negative DG_E* code; the message
+ *    of the last failure on the calling thread is returned by dg_last_error().  Nothing
+ *    aborts or throws across the ABI.
+ *  - Ownership: dg_mesh / dg_solver / dg_batch handles are owned by the library and freed by
+ *    the matching *_destroy.  Device memory is owned by the caller: dg_solver_required_bytes
+ *    states the size, the caller allocates it (any device allocator) and passes it to
+ *    dg_solver_bind; the library sub-allocates inside it and never frees it.  The buffer must
+ *    stay valid until dg_solver_destroy.
+ *  - Streams: all device work of a solver is enqueued on the HIP stream given to
+ *    dg_solver_bind (NULL = the default stream).  Calls that return host data synchronise that
+ *    stream; dg_rk_step and dg_residual with a NULL host pointer only enqueue.
+ *  - Threading: a handle may be used by one host thread at a time.
+ *  - Layout of every nodal array (state U, residual R): element-major, then conserved variable
+ *    (rho, rho v1, rho v2, rho v3, rho e), then node with i fastest:
+ *        U[(off_e * 5) + v * nn_e + i + n1 * (j + n2 * k)]
+ *    where nn_e = n1 n2 n3 nodes, n_d = N_d + 1, off_e = sum of nn over elements before e.
+ *    For uniform order all elements have nn = (N+1)^3 and off_e = e nn.
+ *    Element e of an ex*ey*ez box sits at cell (e % ex, (e / ex) % ey, e / (ex ey)).
+ *  - Nondimensionalisation: rho_0 = |v_0| = L = 1, gas constant 1 (T = p/rho), p_0 =
+ *    1/(gamma Ma^2) for the Taylor-Green state, mu = 1/Re (constant), kappa = mu gamma /
+ *    ((gamma-1) Pr).  Re <= 0 selects the Euler equations.
+ */
+#ifndef DGSEM_H
+#define DGSEM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status codes */
+#define DG_OK 0
+#define DG_EINVAL (-1)       /* invalid argument or configuration                       */
+#define DG_ENOMEM (-2)       /* device buffer too small, or host allocation failed        */
+#define DG_EHIP (-3)         /* a HIP runtime call failed (message holds the HIP error)   */
+#define DG_ENONFINITE (-4)   /* a state given to the library holds NaN/Inf or rho,p <= 0   */
+#define DG_EUNSUPPORTED (-5) /* valid request outside what this build implements          */
+#define DG_ESTATE (-6)       /* call out of order (e.g. solver not bound)                 */
+
+/* ------------------------------------------------------------------ options */
+enum { DG_DEFORM_NONE = 0, DG_DEFORM_SINSIN = 1 };
+/* volume two-point flux: Chandrashekar's entropy-conserving flux, or the central average */
+enum { DG_VOL_EC = 0, DG_VOL_CENTRAL = 1 };
+/* surface numerical flux */
+enum { DG_SURF_ROE = 0, DG_SURF_LLF = 1, DG_SURF_EC = 2, DG_SURF_CENTRAL = 3 };
+/* precision: all-FP64, or FP32 flux/derivative arithmetic with FP64 metrics, RK state and
+ * reductions */
+enum { DG_FP64 = 0, DG_FP32_BULK = 1 };
+/* initial conditions, evaluated on the device at the node coordinates; params:
+ *   UNIFORM        rho, v1, v2, v3, p
+ *   TGV            (none) Taylor-Green vortex on [0,2pi]^3: v = (sin x cos y cos z,
+ *                  -cos x sin y cos z, 0), p = p_0 + (cos 2x + cos 2y)(cos 2z + 2)/16,
+ *                  rho = p/p_0
+ *   VORTEX         beta, x0, y0, u_inf, v_inf: isentropic vortex (z-uniform) on the free
+ *                  stream rho = p = 1
+ *   DENSITY_WAVE   amp, v1, v2, v3, p, k1, k2, k3, phase: rho = 1 + amp sin(k.x + phase) */
+enum { DG_IC_UNIFORM = 0, DG_IC_TGV = 1, DG_IC_VORTEX = 2, DG_IC_DENSITY_WAVE = 3 };
+
+typedef struct dg_mesh dg_mesh;
+typedef struct dg_solver dg_solver;
+
+/* Periodic box of ex*ey*ez hexahedra on [lo, hi]; with DG_DEFORM_SINSIN each node is moved by
+ * (a sin y sin z, a sin z sin x, a sin x sin y) evaluated at its undeformed position
+ * (a = deform_amp).  Uniform order n_uniform in every direction, or per-element anisotropic
+ * orders orders[3 e + d] (NULL for uniform). */
+typedef struct {
+  int ex, ey, ez;
+  double lo[3], hi[3];
+  int deform;
+  double deform_amp;
+  int n_uniform;
+  const int* orders;
+} dg_box_desc;
+
+typedef struct {
+  double gamma, Pr, Ma, Re;
+  int vol_flux, surf_flux, precision;
+} dg_physics;
+
+/* Diagnostics, all FP64 with Gauss-Lobatto quadrature w_i w_j w_k J, reduced in a fixed order
+ * (bitwise reproducible).  entropy = integral of -rho s/(gamma-1), entropy_paper = integral
+ * of -rho s (s = ln p - gamma ln rho, eq. shock:entropy); ke and enstrophy are volume means of
+ * rho|v|^2/2 and rho|curl v|^2/2 (element-local derivative of v). */
+typedef struct {
+  double mass[5];
+  double entropy_paper, entropy;
+  double ke, enstrophy;
+  double lambda_max, rho_min, p_min;
+  double volume;
+  long long nonfinite;
+} dg_diag;
+
+/* ------------------------------------------------------------------ mesh */
+/* Build the host-side mesh (connectivity, per-element orders).  Errors: DG_EINVAL for
+ * non-positive sizes, hi <= lo, orders outside [1, 7]; DG_EUNSUPPORTED for mixed orders
+ * (this build evaluates uniform-order meshes). */
+int dg_mesh_create_box(const dg_box_desc* d, dg_mesh** out);
+void dg_mesh_destroy(dg_mesh* m);
+/* n_elements, total nodes and the largest order of the mesh. */
+int dg_mesh_info(const dg_mesh* m, long long* n_elements, long long* n_nodes, int* n_max);
+
+/* ------------------------------------------------------------------ solver */
+/* Create a solver for the mesh (the mesh may be destroyed afterwards).  Errors: DG_EINVAL for
+ * gamma <= 1, Pr <= 0, unknown flux or precision codes; DG_EUNSUPPORTED for an order without
+ * a compiled kernel (uniform orders 1..7 are compiled). */
+int dg_solver_create(const dg_mesh* m, const dg_physics* p, dg_solver** out);
+/* Bytes of device memory the solver needs (host-only; used for admission control). */
+int dg_solver_required_bytes(const dg_solver* s, size_t* bytes);
+/* Hand the solver a caller-owned device buffer of at least required_bytes bytes and the HIP
+ * stream (hipStream_t, NULL = default) for all its work.  Uploads the Gauss-Lobatto tables and
+ * connectivity and runs the FP64 geometry kernels (node coordinates, curl-form metric terms
+ * Ja^d_n, J, 1/J).  Errors: DG_ENOMEM if bytes is too small, DG_EINVAL for a NULL pointer,
+ * DG_ESTATE if already bound, DG_EHIP on a HIP failure. */
+int dg_solver_bind(dg_solver* s, void* dev_ptr, size_t bytes, void* hip_stream);
+/* Evaluate an initial condition on the device; params as listed at DG_IC_*.  Resets the RK
+ * register. */
+int dg_set_initial_condition(dg_solver* s, int ic, const double* params);
+/* Copy a host state (n = 5 * total nodes doubles, layout above) to the device.  Resets the RK
+ * register.  DG_ENONFINITE if any value is non-finite or rho or p is not positive (the device
+ * state is then left unchanged). */
+int dg_set_state(dg_solver* s, const double* host_U, size_t n);
+/* Copy the current state to the host (synchronises the stream). */
+int dg_get_state(dg_solver* s, double* host_U, size_t n);
+/* R = dU/dt of the current state.  R stays on the device; if host_R is not NULL it is also
+ * copied there (n doubles, layout above; synchronises). */
+int dg_residual(dg_solver* s, double* host_R, size_t n);
+/* Advance nsteps steps of Williamson's low-storage RK3 with the fixed step dt:
+ * per stage k, dU <- A_k dU + dt R(U); U <- U + B_k dU, A = (0, -5/9, -153/128),
+ * B = (1/3, 15/16, 8/15).  Only enqueues work on the solver's stream. */
+int dg_rk_step(dg_solver* s, double dt, int nsteps);
+/* Diagnostics of the current state (synchronises). */
+int dg_diagnostics(dg_solver* s, dg_diag* out);
+/* dt = cfl h_min / ((N_max+1)^2 lambda_max), and for Navier-Stokes the smaller of that and
+ * 0.25 h_min^2 / ((N_max+1)^4 gamma mu / (Pr rho_min)); h_min = smallest undeformed element
+ * edge; lambda_max, rho_min from dg_diagnostics of the current state. */
+int dg_suggest_dt(dg_solver* s, double cfl, double* dt);
+/* Copy the geometry to the host: X (3 per node, layout [off*3 + c*nn + node]), Ja (9 per
+ * node, [off*9 + (3 d + c)*nn + node] = component c of Ja^d), J (1 per node).  Any pointer may
+ * be NULL.  Synchronises. */
+int dg_get_geometry(dg_solver* s, double* host_X, double* host_Ja, double* host_J);
+/* Device addresses of the current state and of the last residual (valid until the next
+ * dg_rk_step, which moves the state between two buffers). */
+int dg_device_pointers(dg_solver* s, void** dev_U, void** dev_R);
+/* Wait for all work enqueued by the solver. */
+int dg_synchronize(dg_solver* s);
+
+/* Kernel timing.  Between dg_profile_begin and dg_profile_end every kernel the solver launches
+ * is bracketed by two HIP events recorded on the solver's stream; dg_profile_end synchronises
+ * and returns, per kernel class, the summed elapsed milliseconds and the number of launches.
+ * Classes: DG_K_GRADIENT (Navier-Stokes pass computing the BR1 gradient and face viscous
+ * fluxes), DG_K_STAGE (residual + RK update), DG_K_DIAGNOSTICS, DG_K_OTHER (geometry, initial
+ * condition).  Recording adds the event overhead to the timed region. */
+enum { DG_K_GRADIENT = 0, DG_K_STAGE = 1, DG_K_DIAGNOSTICS = 2, DG_K_OTHER = 3, DG_K_CLASSES = 4 };
+typedef struct {
+  double ms[DG_K_CLASSES];
+  long long launches[DG_K_CLASSES];
+} dg_profile;
+int dg_profile_begin(dg_solver* s);
+int dg_profile_end(dg_solver* s, dg_profile* out);
+void dg_solver_destroy(dg_solver* s);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char* dg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DGSEM_H */

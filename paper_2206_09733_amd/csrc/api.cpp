@@ -1,0 +1,481 @@
+// api.cpp -- the C ABI of libdgsem.so (declared in include/dgsem.h): host-side mesh and
+// connectivity, the device memory plan inside the caller's buffer, argument checking and
+// error reporting, and the launch sequence of each call.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dg_internal.h"
+#include "dgsem.h"
+
+namespace dg {
+void gll_tables(int N, double* xi, double* w, double* D, double* Dh);
+}
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+static int hip_fail(hipError_t e, const char* what) {
+  g_err = std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+  return DG_EHIP;
+}
+
+#define DG_HIP(call, what)                      \
+  do {                                          \
+    hipError_t _e = (call);                     \
+    if (_e != hipSuccess) return hip_fail(_e, what); \
+  } while (0)
+
+struct dg_mesh {
+  int ex, ey, ez;
+  double lo[3], hi[3];
+  int deform;
+  double amp;
+  int N;
+};
+
+struct ProfRecord {
+  int cls;
+  hipEvent_t a, b;
+};
+
+struct dg_solver {
+  dg_mesh mesh;
+  dg_physics phys;
+  dg::View v;
+  hipStream_t stream = nullptr;
+  bool bound = false;
+  int cur = 0;
+  long long E = 0, nn = 0, ntot = 0;
+  bool profiling = false;
+  std::vector<ProfRecord> prof;      // records of the current profile region
+  std::vector<hipEvent_t> ev_pool;   // events reused across regions
+  size_t ev_used = 0;
+};
+
+namespace {
+
+struct Plan {
+  size_t tab, nbr, X, Ja, J, invJ, U0, U1, dU, R, Fvf, part, diag, total;
+};
+
+Plan make_plan(const dg_solver* s) {
+  const size_t n = (size_t)s->mesh.N + 1, nf = n * n;
+  const size_t E = (size_t)s->E, nt = (size_t)s->ntot;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = (off + bytes + 255) & ~(size_t)255;
+    return o;
+  };
+  Plan p;
+  p.tab = take(sizeof(double) * dg::tab_size((int)n));
+  p.nbr = take(sizeof(int) * 6 * E);
+  p.X = take(sizeof(double) * 3 * nt);
+  p.Ja = take(sizeof(double) * 9 * nt);
+  p.J = take(sizeof(double) * nt);
+  p.invJ = take(sizeof(double) * nt);
+  p.U0 = take(sizeof(double) * 5 * nt);
+  p.U1 = take(sizeof(double) * 5 * nt);
+  p.dU = take(sizeof(double) * 5 * nt);
+  p.R = take(sizeof(double) * 5 * nt);
+  p.Fvf = s->phys.Re > 0 ? take(sizeof(double) * E * 6 * 4 * nf) : 0;
+  p.part = take(sizeof(double) * E * dg::kDiagSlots);
+  p.diag = take(sizeof(double) * dg::kDiagSlots);
+  p.total = off;
+  return p;
+}
+
+bool finite_positive_state(const double* U, long long E, long long nn, double gamma, std::string& why) {
+  for (long long e = 0; e < E; e++) {
+    const double* u = U + e * nn * 5;
+    for (long long q = 0; q < nn; q++) {
+      const double r = u[q], m1 = u[nn + q], m2 = u[2 * nn + q], m3 = u[3 * nn + q], en = u[4 * nn + q];
+      if (!std::isfinite(r) || !std::isfinite(m1) || !std::isfinite(m2) || !std::isfinite(m3) ||
+          !std::isfinite(en)) {
+        why = "non-finite value at element " + std::to_string(e) + ", node " + std::to_string(q);
+        return false;
+      }
+      const double p = (gamma - 1.0) * (en - 0.5 * (m1 * m1 + m2 * m2 + m3 * m3) / r);
+      if (!(r > 0.0) || !(p > 0.0)) {
+        why = "non-positive density or pressure at element " + std::to_string(e) + ", node " +
+              std::to_string(q);
+        return false;
+      }
+    }
+  }
+  return true;
+}
+
+hipEvent_t take_event(dg_solver* s) {
+  if (s->ev_used == s->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    s->ev_pool.push_back(e);
+  }
+  return s->ev_pool[s->ev_used++];
+}
+
+// launch `fn` on the solver's stream, bracketed by events when profiling
+template <class F>
+hipError_t timed(dg_solver* s, int cls, F fn) {
+  if (!s->profiling) return fn();
+  ProfRecord r{cls, take_event(s), take_event(s)};
+  if (!r.a || !r.b) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(r.a, s->stream);
+  if (e != hipSuccess) return e;
+  e = fn();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(r.b, s->stream);
+  if (e != hipSuccess) return e;
+  s->prof.push_back(r);
+  return hipSuccess;
+}
+
+hipError_t run_stage(dg_solver* s, double dt, double a, double b, int mode) {
+  if (s->v.viscous) {
+    hipError_t e = timed(s, DG_K_GRADIENT, [&] { return dg::launch_gradient(s->v, s->cur, s->stream); });
+    if (e != hipSuccess) return e;
+  }
+  return timed(s, DG_K_STAGE, [&] { return dg::launch_stage(s->v, s->cur, dt, a, b, mode, s->stream); });
+}
+
+int check_bound(const dg_solver* s) {
+  if (!s) return fail(DG_EINVAL, "NULL solver");
+  if (!s->bound) return fail(DG_ESTATE, "solver is not bound to device memory (dg_solver_bind)");
+  return DG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dg_last_error(void) { return g_err.c_str(); }
+
+int dg_mesh_create_box(const dg_box_desc* d, dg_mesh** out) {
+  if (!d || !out) return fail(DG_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (d->ex < 1 || d->ey < 1 || d->ez < 1) return fail(DG_EINVAL, "element counts must be >= 1");
+  if ((long long)d->ex * d->ey * d->ez > (1LL << 30)) return fail(DG_EINVAL, "too many elements");
+  for (int k = 0; k < 3; k++)
+    if (!(d->hi[k] > d->lo[k])) return fail(DG_EINVAL, "box requires hi > lo in every direction");
+  if (d->deform != DG_DEFORM_NONE && d->deform != DG_DEFORM_SINSIN)
+    return fail(DG_EINVAL, "unknown deformation");
+  int N = d->n_uniform;
+  if (d->orders) {
+    const long long E = (long long)d->ex * d->ey * d->ez;
+    N = d->orders[0];
+    for (long long i = 0; i < 3 * E; i++) {
+      if (d->orders[i] < 1 || d->orders[i] > dg::kMaxOrder)
+        return fail(DG_EINVAL, "orders must lie in [1, 7]");
+      if (d->orders[i] != N)
+        return fail(DG_EUNSUPPORTED, "mixed per-element orders are not evaluated by this build");
+    }
+  }
+  if (N < 1 || N > dg::kMaxOrder) return fail(DG_EINVAL, "order must lie in [1, 7]");
+  dg_mesh* m = new dg_mesh;
+  m->ex = d->ex; m->ey = d->ey; m->ez = d->ez;
+  for (int k = 0; k < 3; k++) { m->lo[k] = d->lo[k]; m->hi[k] = d->hi[k]; }
+  m->deform = d->deform;
+  m->amp = d->deform_amp;
+  m->N = N;
+  *out = m;
+  return DG_OK;
+}
+
+void dg_mesh_destroy(dg_mesh* m) { delete m; }
+
+int dg_mesh_info(const dg_mesh* m, long long* n_elements, long long* n_nodes, int* n_max) {
+  if (!m) return fail(DG_EINVAL, "NULL mesh");
+  const long long E = (long long)m->ex * m->ey * m->ez;
+  const long long nn = (long long)(m->N + 1) * (m->N + 1) * (m->N + 1);
+  if (n_elements) *n_elements = E;
+  if (n_nodes) *n_nodes = E * nn;
+  if (n_max) *n_max = m->N;
+  return DG_OK;
+}
+
+int dg_solver_create(const dg_mesh* m, const dg_physics* p, dg_solver** out) {
+  if (!m || !p || !out) return fail(DG_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (!(p->gamma > 1.0)) return fail(DG_EINVAL, "gamma must exceed 1");
+  if (p->Re > 0 && !(p->Pr > 0)) return fail(DG_EINVAL, "Pr must be positive");
+  if (!(p->Ma > 0)) return fail(DG_EINVAL, "Ma must be positive");
+  if (p->vol_flux != DG_VOL_EC && p->vol_flux != DG_VOL_CENTRAL) return fail(DG_EINVAL, "unknown volume flux");
+  if (p->surf_flux < DG_SURF_ROE || p->surf_flux > DG_SURF_CENTRAL) return fail(DG_EINVAL, "unknown surface flux");
+  if (p->precision != DG_FP64 && p->precision != DG_FP32_BULK) return fail(DG_EINVAL, "unknown precision");
+  if (m->N < 1 || m->N > dg::kMaxOrder) return fail(DG_EUNSUPPORTED, "no kernel for this order");
+  dg_solver* s = new dg_solver;
+  s->mesh = *m;
+  s->phys = *p;
+  s->E = (long long)m->ex * m->ey * m->ez;
+  s->nn = (long long)(m->N + 1) * (m->N + 1) * (m->N + 1);
+  s->ntot = s->E * s->nn;
+  std::memset(&s->v, 0, sizeof(s->v));
+  dg::View& v = s->v;
+  v.E = (int)s->E;
+  v.N = m->N;
+  v.ex = m->ex; v.ey = m->ey; v.ez = m->ez;
+  v.deform = m->deform;
+  v.amp = m->amp;
+  for (int k = 0; k < 3; k++) {
+    v.lo[k] = m->lo[k];
+    v.h[k] = (m->hi[k] - m->lo[k]) / (k == 0 ? m->ex : (k == 1 ? m->ey : m->ez));
+  }
+  v.gamma = p->gamma;
+  v.Ma = p->Ma;
+  v.viscous = p->Re > 0 ? 1 : 0;
+  v.mu = v.viscous ? 1.0 / p->Re : 0.0;
+  v.kappa = v.viscous ? v.mu * p->gamma / ((p->gamma - 1.0) * p->Pr) : 0.0;
+  v.vol = p->vol_flux;
+  v.surf = p->surf_flux;
+  v.fp32 = p->precision == DG_FP32_BULK ? 1 : 0;
+  *out = s;
+  return DG_OK;
+}
+
+int dg_solver_required_bytes(const dg_solver* s, size_t* bytes) {
+  if (!s || !bytes) return fail(DG_EINVAL, "NULL argument");
+  *bytes = make_plan(s).total;
+  return DG_OK;
+}
+
+int dg_solver_bind(dg_solver* s, void* dev_ptr, size_t bytes, void* hip_stream) {
+  if (!s || !dev_ptr) return fail(DG_EINVAL, "NULL argument");
+  if (s->bound) return fail(DG_ESTATE, "solver already bound");
+  const Plan p = make_plan(s);
+  if (bytes < p.total)
+    return fail(DG_ENOMEM, "device buffer of " + std::to_string(bytes) + " bytes is smaller than the " +
+                               std::to_string(p.total) + " bytes required");
+  if (((uintptr_t)dev_ptr & 255) != 0) return fail(DG_EINVAL, "device buffer must be 256-byte aligned");
+  char* b = static_cast<char*>(dev_ptr);
+  dg::View& v = s->v;
+  v.tab = reinterpret_cast<const double*>(b + p.tab);
+  v.nbr = reinterpret_cast<const int*>(b + p.nbr);
+  v.X = reinterpret_cast<double*>(b + p.X);
+  v.Ja = reinterpret_cast<double*>(b + p.Ja);
+  v.J = reinterpret_cast<double*>(b + p.J);
+  v.invJ = reinterpret_cast<double*>(b + p.invJ);
+  v.U[0] = reinterpret_cast<double*>(b + p.U0);
+  v.U[1] = reinterpret_cast<double*>(b + p.U1);
+  v.dU = reinterpret_cast<double*>(b + p.dU);
+  v.R = reinterpret_cast<double*>(b + p.R);
+  v.Fvf = v.viscous ? reinterpret_cast<double*>(b + p.Fvf) : nullptr;
+  v.part = reinterpret_cast<double*>(b + p.part);
+  v.diag = reinterpret_cast<double*>(b + p.diag);
+  s->stream = static_cast<hipStream_t>(hip_stream);
+
+  const int n = v.N + 1;
+  std::vector<double> tab(dg::tab_size(n));
+  dg::gll_tables(v.N, tab.data() + dg::tab_xi(n), tab.data() + dg::tab_w(n), tab.data() + dg::tab_D(n),
+                 tab.data() + dg::tab_Dh(n));
+  std::vector<int> nbr(6 * s->E);
+  const int ex = v.ex, ey = v.ey, ez = v.ez;
+  for (long long e = 0; e < s->E; e++) {
+    const int a = (int)(e % ex), bb = (int)((e / ex) % ey), c = (int)(e / ((long long)ex * ey));
+    nbr[6 * e + 0] = ((a + ex - 1) % ex) + ex * (bb + ey * c);
+    nbr[6 * e + 1] = ((a + 1) % ex) + ex * (bb + ey * c);
+    nbr[6 * e + 2] = a + ex * (((bb + ey - 1) % ey) + ey * c);
+    nbr[6 * e + 3] = a + ex * (((bb + 1) % ey) + ey * c);
+    nbr[6 * e + 4] = a + ex * (bb + ey * ((c + ez - 1) % ez));
+    nbr[6 * e + 5] = a + ex * (bb + ey * ((c + 1) % ez));
+  }
+  DG_HIP(hipMemcpyAsync(b + p.tab, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice, s->stream),
+         "upload tables");
+  DG_HIP(hipMemcpyAsync(b + p.nbr, nbr.data(), sizeof(int) * nbr.size(), hipMemcpyHostToDevice, s->stream),
+         "upload connectivity");
+  DG_HIP(dg::launch_geometry(v, s->stream), "geometry kernel");
+  DG_HIP(hipMemsetAsync(v.dU, 0, sizeof(double) * 5 * s->ntot, s->stream), "clear RK register");
+  DG_HIP(hipStreamSynchronize(s->stream), "geometry");
+  s->bound = true;
+  s->cur = 0;
+  return DG_OK;
+}
+
+int dg_set_initial_condition(dg_solver* s, int ic, const double* params) {
+  int rc = check_bound(s);
+  if (rc) return rc;
+  if (ic < DG_IC_UNIFORM || ic > DG_IC_DENSITY_WAVE) return fail(DG_EINVAL, "unknown initial condition");
+  if (ic != DG_IC_TGV && !params) return fail(DG_EINVAL, "this initial condition needs parameters");
+  double P[9] = {0};
+  const int np = ic == DG_IC_UNIFORM ? 5 : (ic == DG_IC_VORTEX ? 5 : (ic == DG_IC_DENSITY_WAVE ? 9 : 0));
+  for (int k = 0; k < np; k++) {
+    if (!std::isfinite(params[k])) return fail(DG_EINVAL, "non-finite initial-condition parameter");
+    P[k] = params[k];
+  }
+  if (ic == DG_IC_UNIFORM && (!(P[0] > 0) || !(P[4] > 0)))
+    return fail(DG_EINVAL, "uniform state needs rho > 0 and p > 0");
+  DG_HIP(timed(s, DG_K_OTHER, [&] { return dg::launch_ic(s->v, s->cur, ic, P, s->stream); }),
+         "initial-condition kernel");
+  return DG_OK;
+}
+
+int dg_set_state(dg_solver* s, const double* host_U, size_t n) {
+  int rc = check_bound(s);
+  if (rc) return rc;
+  if (!host_U) return fail(DG_EINVAL, "NULL state");
+  if (n != (size_t)(5 * s->ntot)) return fail(DG_EINVAL, "state size must be 5 * number of nodes");
+  std::string why;
+  if (!finite_positive_state(host_U, s->E, s->nn, s->phys.gamma, why)) return fail(DG_ENONFINITE, why);
+  DG_HIP(hipMemcpyAsync(s->v.U[s->cur], host_U, sizeof(double) * n, hipMemcpyHostToDevice, s->stream),
+         "upload state");
+  DG_HIP(hipMemsetAsync(s->v.dU, 0, sizeof(double) * n, s->stream), "clear RK register");
+  DG_HIP(hipStreamSynchronize(s->stream), "upload state");
+  return DG_OK;
+}
+
+int dg_get_state(dg_solver* s, double* host_U, size_t n) {
+  int rc = check_bound(s);
+  if (rc) return rc;
+  if (!host_U) return fail(DG_EINVAL, "NULL output");
+  if (n != (size_t)(5 * s->ntot)) return fail(DG_EINVAL, "state size must be 5 * number of nodes");
+  DG_HIP(hipMemcpyAsync(host_U, s->v.U[s->cur], sizeof(double) * n, hipMemcpyDeviceToHost, s->stream),
+         "download state");
+  DG_HIP(hipStreamSynchronize(s->stream), "download state");
+  return DG_OK;
+}
+
+int dg_residual(dg_solver* s, double* host_R, size_t n) {
+  int rc = check_bound(s);
+  if (rc) return rc;
+  if (host_R && n != (size_t)(5 * s->ntot)) return fail(DG_EINVAL, "residual size must be 5 * number of nodes");
+  DG_HIP(run_stage(s, 0.0, 0.0, 0.0, dg::kModeResidual), "residual kernels");
+  if (host_R) {
+    DG_HIP(hipMemcpyAsync(host_R, s->v.R, sizeof(double) * n, hipMemcpyDeviceToHost, s->stream),
+           "download residual");
+    DG_HIP(hipStreamSynchronize(s->stream), "residual");
+  }
+  return DG_OK;
+}
+
+int dg_rk_step(dg_solver* s, double dt, int nsteps) {
+  int rc = check_bound(s);
+  if (rc) return rc;
+  if (nsteps < 0) return fail(DG_EINVAL, "nsteps must be >= 0");
+  if (!std::isfinite(dt) || !(dt > 0)) return fail(DG_EINVAL, "dt must be positive and finite");
+  static const double A[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
+  static const double B[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
+  for (int it = 0; it < nsteps; it++)
+    for (int k = 0; k < 3; k++) {
+      DG_HIP(run_stage(s, dt, A[k], B[k], dg::kModeRK), "RK stage kernels");
+      s->cur ^= 1;
+    }
+  return DG_OK;
+}
+
+int dg_diagnostics(dg_solver* s, dg_diag* out) {
+  int rc = check_bound(s);
+  if (rc) return rc;
+  if (!out) return fail(DG_EINVAL, "NULL output");
+  DG_HIP(timed(s, DG_K_DIAGNOSTICS, [&] { return dg::launch_diagnostics(s->v, s->cur, s->stream); }),
+         "diagnostics kernels");
+  double h[dg::kDiagSlots];
+  DG_HIP(hipMemcpyAsync(h, s->v.diag, sizeof(h), hipMemcpyDeviceToHost, s->stream), "download diagnostics");
+  DG_HIP(hipStreamSynchronize(s->stream), "diagnostics");
+  for (int k = 0; k < 5; k++) out->mass[k] = h[k];
+  out->entropy_paper = h[5];
+  out->entropy = h[6];
+  out->volume = h[13];
+  out->ke = h[7] / h[13];
+  out->enstrophy = h[8] / h[13];
+  out->lambda_max = h[9];
+  out->rho_min = h[10];
+  out->p_min = h[11];
+  out->nonfinite = (long long)h[12];
+  return DG_OK;
+}
+
+int dg_suggest_dt(dg_solver* s, double cfl, double* dt) {
+  if (!dt) return fail(DG_EINVAL, "NULL output");
+  if (!(cfl > 0) || !std::isfinite(cfl)) return fail(DG_EINVAL, "cfl must be positive");
+  dg_diag d;
+  int rc = dg_diagnostics(s, &d);
+  if (rc) return rc;
+  if (d.nonfinite || !(d.lambda_max > 0)) return fail(DG_ENONFINITE, "state is not finite");
+  const dg::View& v = s->v;
+  const double hmin = std::fmin(v.h[0], std::fmin(v.h[1], v.h[2]));
+  const double n1 = v.N + 1.0;
+  double r = cfl * hmin / (n1 * n1 * d.lambda_max);
+  if (v.viscous) {
+    const double rv = 0.25 * hmin * hmin / (n1 * n1 * n1 * n1 * s->phys.gamma * v.mu / (s->phys.Pr * d.rho_min));
+    r = std::fmin(r, rv);
+  }
+  *dt = r;
+  return DG_OK;
+}
+
+int dg_get_geometry(dg_solver* s, double* host_X, double* host_Ja, double* host_J) {
+  int rc = check_bound(s);
+  if (rc) return rc;
+  const size_t nt = (size_t)s->ntot;
+  if (host_X)
+    DG_HIP(hipMemcpyAsync(host_X, s->v.X, sizeof(double) * 3 * nt, hipMemcpyDeviceToHost, s->stream), "X");
+  if (host_Ja)
+    DG_HIP(hipMemcpyAsync(host_Ja, s->v.Ja, sizeof(double) * 9 * nt, hipMemcpyDeviceToHost, s->stream), "Ja");
+  if (host_J)
+    DG_HIP(hipMemcpyAsync(host_J, s->v.J, sizeof(double) * nt, hipMemcpyDeviceToHost, s->stream), "J");
+  DG_HIP(hipStreamSynchronize(s->stream), "geometry download");
+  return DG_OK;
+}
+
+int dg_device_pointers(dg_solver* s, void** dev_U, void** dev_R) {
+  int rc = check_bound(s);
+  if (rc) return rc;
+  if (dev_U) *dev_U = s->v.U[s->cur];
+  if (dev_R) *dev_R = s->v.R;
+  return DG_OK;
+}
+
+int dg_synchronize(dg_solver* s) {
+  int rc = check_bound(s);
+  if (rc) return rc;
+  DG_HIP(hipStreamSynchronize(s->stream), "synchronize");
+  return DG_OK;
+}
+
+int dg_profile_begin(dg_solver* s) {
+  int rc = check_bound(s);
+  if (rc) return rc;
+  s->profiling = true;
+  s->prof.clear();
+  s->ev_used = 0;
+  return DG_OK;
+}
+
+int dg_profile_end(dg_solver* s, dg_profile* out) {
+  int rc = check_bound(s);
+  if (rc) return rc;
+  if (!out) return fail(DG_EINVAL, "NULL output");
+  if (!s->profiling) return fail(DG_ESTATE, "no profile region is open");
+  s->profiling = false;
+  DG_HIP(hipStreamSynchronize(s->stream), "profile synchronize");
+  for (int k = 0; k < DG_K_CLASSES; k++) {
+    out->ms[k] = 0.0;
+    out->launches[k] = 0;
+  }
+  for (const ProfRecord& r : s->prof) {
+    float ms = 0.f;
+    DG_HIP(hipEventElapsedTime(&ms, r.a, r.b), "event elapsed time");
+    out->ms[r.cls] += ms;
+    out->launches[r.cls] += 1;
+  }
+  s->prof.clear();
+  s->ev_used = 0;
+  return DG_OK;
+}
+
+void dg_solver_destroy(dg_solver* s) {
+  if (!s) return;
+  if (s->bound) (void)hipStreamSynchronize(s->stream);
+  for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
+  delete s;
+}
+
+}  // extern "C"

@@ -1,0 +1,65 @@
+// dg_internal.h -- layout of a bound solver as seen by the kernels, and the launch entry
+// points implemented in kernels.hip.  Internal to libdgsem.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace dg {
+
+constexpr int kMaxOrder = 7;            // largest polynomial order with a compiled kernel
+constexpr int kDiagSlots = 16;          // doubles per diagnostics partial
+constexpr int kTabStride = (kMaxOrder + 1) * (kMaxOrder + 1);
+
+// Device tables of one order N, packed in one array (all doubles):
+//   [0, n)            Lobatto nodes xi
+//   [n, 2n)           quadrature weights w
+//   [2n, 2n+n^2)      derivative matrix D (row-major, D[i*n+m])
+//   [2n+n^2, 2n+2n^2) Dhat = D - e_N e_N^T / w_N + e_0 e_0^T / w_0
+inline int tab_xi(int) { return 0; }
+inline int tab_w(int n) { return n; }
+inline int tab_D(int n) { return 2 * n; }
+inline int tab_Dh(int n) { return 2 * n + n * n; }
+inline int tab_size(int n) { return 2 * n + 2 * n * n; }
+
+// Everything a kernel needs to know about one bound uniform-order solver.
+struct View {
+  int E;          // elements
+  int N;          // polynomial order
+  int ex, ey, ez; // box cells
+  int deform;
+  double amp;
+  double lo[3], h[3];
+  double gamma, mu, kappa, Ma;
+  int vol, surf, viscous, fp32;
+  const int* nbr; // [E][6] neighbour across face f = 2 d + side (side 1: xi_d = +1)
+  const double* tab;
+  double* X;      // [E][3][nn]   node coordinates
+  double* Ja;     // [E][9][nn]   Ja^d_c at index 3 d + c
+  double* J;      // [E][nn]
+  double* invJ;   // [E][nn]
+  double* U[2];   // ping-pong state buffers [E][5][nn]
+  double* dU;     // RK register [E][5][nn]
+  double* R;      // residual [E][5][nn]
+  double* Fvf;    // [E][6][4][nf] contravariant viscous flux on the element's faces
+  double* part;   // diagnostics partials [E][kDiagSlots]
+  double* diag;   // final diagnostics [kDiagSlots]
+};
+
+// Launchers (kernels.hip).  All enqueue on `st` and return the hipError_t of the launch.
+hipError_t launch_geometry(const View& v, hipStream_t st);
+hipError_t launch_ic(const View& v, int cur, int ic, const double* params, hipStream_t st);
+// Navier-Stokes pass A: BR1 gradient and face viscous fluxes of U[cur]
+hipError_t launch_gradient(const View& v, int cur, hipStream_t st);
+// residual (+ RK update) of U[cur]; for Navier-Stokes launch_gradient must precede it
+hipError_t launch_stage(const View& v, int cur, double dt, double rkA, double rkB, int mode,
+                        hipStream_t st);
+hipError_t launch_diagnostics(const View& v, int cur, hipStream_t st);
+
+// stage modes
+constexpr int kModeRK = 0;        // dU <- A dU + dt R; U[cur^1] <- U[cur] + B dU
+constexpr int kModeResidual = 1;  // R <- dU/dt of U[cur]
+
+}  // namespace dg

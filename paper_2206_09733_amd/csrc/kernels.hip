@@ -1,0 +1,914 @@
+// kernels.hip -- gfx950 kernels of the DGSEM residual and low-storage RK3.
+//
+// One workgroup per hexahedral element, one lane per Gauss-Lobatto node (64-wide waves; the
+// (N+1)^3 nodes are padded to a multiple of 64).  The element's state, primitive variables
+// and metric terms are staged in LDS; the split-form two-point fluxes run on the VALU.  The
+// numerical flux on each face is evaluated by both adjacent elements, with identical
+// arguments in identical order (owner's +xi_d side first, the owner's metric as normal), so
+// the flux is single-valued without a face array or a grid-wide barrier; the state
+// ping-pongs between two buffers so that the neighbour traces read in a stage are never
+// overwritten during it.  Workgroups are mapped to elements so that each of the 8 XCDs works
+// on a contiguous range of elements (neighbour traces then mostly hit that XCD's L2).
+//
+// Discretisation (HORSES3D paper, arXiv 2206.09733): eqs. compressibleNScompact,
+// viscousfluxes, compressibleNScompact_transformed and NS2-NS5; split forms of section
+// "Energy/Entropy stable versions"; Riemann and BR1 fluxes listed in section "Spatial
+// discretisation"; Williamson RK3 of section "Time advancement".  With the Lobatto SBP
+// property the diagonal of the two-point sum cancels the element's own flux in the surface
+// lift (2 D_NN = 1/w_N, 2 D_00 = -1/w_0), so per node
+//   J dU/dt = - sum_d sum_{m != i} D_im F#(U_i, U_m; Ja^d_i + Ja^d_m)
+//             - (1/w_N) Fs(+d face) + (1/w_0) Fs(-d face)
+//             + sum_d sum_m Dhat_im F~v^d_m                                  (Navier-Stokes)
+// with Fs = F~* - F~v* the inviscid minus the BR1 viscous face flux and
+// Dhat = D - e_N e_N^T/w_N + e_0 e_0^T/w_0 (the own-flux lift of the viscous term folded in).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "dg_internal.h"
+
+namespace dg {
+
+__host__ __device__ constexpr int nthreads_for(int N) {
+  return (((N + 1) * (N + 1) * (N + 1) + 63) / 64) * 64;
+}
+
+__host__ __device__ constexpr int pow2_at_least(int x) {
+  int p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+// Workgroup -> element.  Consecutive workgroups go round-robin over the 8 XCDs; give each XCD
+// a contiguous slice of elements instead.
+__device__ __forceinline__ int block_element(int E) {
+  const int b = blockIdx.x;
+  if ((E & 7) == 0) {
+    const int per = E >> 3;
+    return (b & 7) * per + (b >> 3);
+  }
+  return b;
+}
+
+// node index of reference indices (i_d = id, tangential p, r) on a face normal to d
+template <int n>
+__device__ __forceinline__ int face_node(int d, int id, int p, int r) {
+  return d == 0 ? id + n * (p + n * r) : (d == 1 ? p + n * (id + n * r) : p + n * (r + n * id));
+}
+
+// ------------------------------------------------------------------ physics helpers
+template <typename T>
+struct Prim {
+  T rho, v1, v2, v3, beta, lrho, lbeta, h;  // beta = rho/(2p), h = |v|^2/2
+};
+
+// primitive variables computed in FP64 from the conservative state, then rounded to T
+template <typename T>
+__device__ __forceinline__ Prim<T> make_prim(const double u[5], double gamma) {
+  const double inv = 1.0 / u[0];
+  const double v1 = u[1] * inv, v2 = u[2] * inv, v3 = u[3] * inv;
+  const double h = 0.5 * (v1 * v1 + v2 * v2 + v3 * v3);
+  const double p = (gamma - 1.0) * (u[4] - u[0] * h);
+  const double beta = 0.5 * u[0] / p;
+  Prim<T> o;
+  o.rho = (T)u[0];
+  o.v1 = (T)v1;
+  o.v2 = (T)v2;
+  o.v3 = (T)v3;
+  o.beta = (T)beta;
+  o.lrho = (T)log(u[0]);
+  o.lbeta = (T)log(beta);
+  o.h = (T)h;
+  return o;
+}
+
+// logarithmic mean (a-b)/(ln a - ln b) as num/den; near a = b the series in
+// u = ((a-b)/(a+b))^2 replaces the cancelling logarithms
+template <typename T>
+__device__ __forceinline__ void logmean_nd(T a, T b, T la, T lb, T& num, T& den) {
+  const T d = a - b, s = a + b;
+  const T u = (d * d) / (s * s);
+  const T thr = sizeof(T) == 8 ? (T)1e-4 : (T)1e-2;
+  const bool small = u < thr;
+  const T poly = (T)2 * ((T)1 + u * ((T)(1.0 / 3.0) + u * ((T)0.2 + u * (T)(1.0 / 7.0))));
+  num = small ? s : d;
+  den = small ? poly : (la - lb);
+}
+
+// Chandrashekar's entropy-conserving, kinetic-energy-preserving two-point flux along the
+// (not normalised) vector n: F#(a, b; n), linear in n.  ce = 1/(2(gamma-1)).
+template <typename T>
+__device__ __forceinline__ void flux_ec(const Prim<T>& a, const Prim<T>& b, T n1, T n2, T n3, T ce,
+                                        T F[5]) {
+  T rn, rd, bn, bd;
+  logmean_nd(a.rho, b.rho, a.lrho, b.lrho, rn, rd);
+  logmean_nd(a.beta, b.beta, a.lbeta, b.lbeta, bn, bd);
+  const T rho_ln = rn / rd;
+  const T inv_bln = bd / bn;
+  const T u = (T)0.5 * (a.v1 + b.v1), v = (T)0.5 * (a.v2 + b.v2), w = (T)0.5 * (a.v3 + b.v3);
+  const T hb = (T)0.5 * (a.h + b.h);
+  const T phat = (a.rho + b.rho) / ((T)2 * (a.beta + b.beta));
+  const T vn = u * n1 + v * n2 + w * n3;
+  F[0] = rho_ln * vn;
+  F[1] = F[0] * u + phat * n1;
+  F[2] = F[0] * v + phat * n2;
+  F[3] = F[0] * w + phat * n3;
+  F[4] = F[0] * (ce * inv_bln - hb) + u * F[1] + v * F[2] + w * F[3];
+}
+
+// central two-point flux (F(a) + F(b)) / 2 . n from the primitive variables
+template <typename T>
+__device__ __forceinline__ void flux_central(const Prim<T>& a, const Prim<T>& b, T n1, T n2, T n3,
+                                             T gm1, T F[5]) {
+  T Fa[5], Fb[5];
+  const Prim<T>* s[2] = {&a, &b};
+  T* o[2] = {Fa, Fb};
+#pragma unroll
+  for (int q = 0; q < 2; q++) {
+    const Prim<T>& P = *s[q];
+    const T p = (T)0.5 * P.rho / P.beta;
+    const T vn = P.v1 * n1 + P.v2 * n2 + P.v3 * n3;
+    const T En = p / gm1 + P.rho * P.h;
+    o[q][0] = P.rho * vn;
+    o[q][1] = P.rho * P.v1 * vn + p * n1;
+    o[q][2] = P.rho * P.v2 * vn + p * n2;
+    o[q][3] = P.rho * P.v3 * vn + p * n3;
+    o[q][4] = (En + p) * vn;
+  }
+#pragma unroll
+  for (int c = 0; c < 5; c++) F[c] = (T)0.5 * (Fa[c] + Fb[c]);
+}
+
+template <typename T>
+__device__ __forceinline__ void vol_flux(int kind, const Prim<T>& a, const Prim<T>& b, T n1, T n2,
+                                         T n3, T ce, T gm1, T F[5]) {
+  if (kind == 0) flux_ec(a, b, n1, n2, n3, ce, F);
+  else flux_central(a, b, n1, n2, n3, gm1, F);
+}
+
+// Numerical flux through a face with scaled normal S (|S| times the unit normal), between
+// the conservative states uL (the side S points away from) and uR.
+template <typename T>
+__device__ __forceinline__ void face_flux(int kind, const double uL[5], const double uR[5],
+                                          const double S[3], double gamma, T F[5]) {
+  const T gm1 = (T)(gamma - 1.0);
+  if (kind == 2) {  // entropy-conserving flux, linear in S
+    const Prim<T> a = make_prim<T>(uL, gamma), b = make_prim<T>(uR, gamma);
+    flux_ec(a, b, (T)S[0], (T)S[1], (T)S[2], (T)(0.5 / (gamma - 1.0)), F);
+    return;
+  }
+  const T s1 = (T)S[0], s2 = (T)S[1], s3 = (T)S[2];
+  const T area = sqrt(s1 * s1 + s2 * s2 + s3 * s3);
+  const T ia = (T)1 / area;
+  const T n1 = s1 * ia, n2 = s2 * ia, n3 = s3 * ia;
+  T rL, vL[3], pL, EL, rR, vR[3], pR, ER;
+  {
+    const double i = 1.0 / uL[0];
+    const double a1 = uL[1] * i, a2 = uL[2] * i, a3 = uL[3] * i;
+    const double p = (gamma - 1.0) * (uL[4] - 0.5 * uL[0] * (a1 * a1 + a2 * a2 + a3 * a3));
+    rL = (T)uL[0]; vL[0] = (T)a1; vL[1] = (T)a2; vL[2] = (T)a3; pL = (T)p; EL = (T)uL[4];
+  }
+  {
+    const double i = 1.0 / uR[0];
+    const double a1 = uR[1] * i, a2 = uR[2] * i, a3 = uR[3] * i;
+    const double p = (gamma - 1.0) * (uR[4] - 0.5 * uR[0] * (a1 * a1 + a2 * a2 + a3 * a3));
+    rR = (T)uR[0]; vR[0] = (T)a1; vR[1] = (T)a2; vR[2] = (T)a3; pR = (T)p; ER = (T)uR[4];
+  }
+  const T vnL = vL[0] * n1 + vL[1] * n2 + vL[2] * n3;
+  const T vnR = vR[0] * n1 + vR[1] * n2 + vR[2] * n3;
+  T FL[5], FR[5];
+  FL[0] = rL * vnL;
+  FR[0] = rR * vnR;
+  FL[1] = FL[0] * vL[0] + pL * n1;
+  FL[2] = FL[0] * vL[1] + pL * n2;
+  FL[3] = FL[0] * vL[2] + pL * n3;
+  FR[1] = FR[0] * vR[0] + pR * n1;
+  FR[2] = FR[0] * vR[1] + pR * n2;
+  FR[3] = FR[0] * vR[2] + pR * n3;
+  FL[4] = (EL + pL) * vnL;
+  FR[4] = (ER + pR) * vnR;
+  if (kind == 3) {  // central
+#pragma unroll
+    for (int c = 0; c < 5; c++) F[c] = area * (T)0.5 * (FL[c] + FR[c]);
+    return;
+  }
+  if (kind == 1) {  // local Lax-Friedrichs (Rusanov)
+    const T g = (T)gamma;
+    const T lamL = fabs(vnL) + sqrt(g * pL / rL);
+    const T lamR = fabs(vnR) + sqrt(g * pR / rR);
+    const T lam = lamL > lamR ? lamL : lamR;
+    const T du[5] = {(T)(uR[0] - uL[0]), (T)(uR[1] - uL[1]), (T)(uR[2] - uL[2]), (T)(uR[3] - uL[3]),
+                     (T)(uR[4] - uL[4])};
+#pragma unroll
+    for (int c = 0; c < 5; c++) F[c] = area * (T)0.5 * (FL[c] + FR[c] - lam * du[c]);
+    return;
+  }
+  // Roe: averages weighted by sqrt(rho); waves u_n - c, u_n (entropy + shear), u_n + c
+  const T sL = sqrt(rL), sR = sqrt(rR);
+  const T iw = (T)1 / (sL + sR);
+  const T u1 = (sL * vL[0] + sR * vR[0]) * iw;
+  const T u2 = (sL * vL[1] + sR * vR[1]) * iw;
+  const T u3 = (sL * vL[2] + sR * vR[2]) * iw;
+  const T H = (sL * (EL + pL) / rL + sR * (ER + pR) / rR) * iw;
+  const T rho = sL * sR;
+  const T q2 = u1 * u1 + u2 * u2 + u3 * u3;
+  const T c2 = gm1 * (H - (T)0.5 * q2);
+  const T c = sqrt(c2);
+  const T ic2 = (T)1 / c2;
+  const T vn = u1 * n1 + u2 * n2 + u3 * n3;
+  const T dr = rR - rL, dp = pR - pL;
+  const T dv1 = vR[0] - vL[0], dv2 = vR[1] - vL[1], dv3 = vR[2] - vL[2];
+  const T dvn = dv1 * n1 + dv2 * n2 + dv3 * n3;
+  const T a1 = (T)0.5 * (dp - rho * c * dvn) * ic2;
+  const T a2 = dr - dp * ic2;
+  const T a3 = (T)0.5 * (dp + rho * c * dvn) * ic2;
+  const T l1 = fabs(vn - c), l2 = fabs(vn), l3 = fabs(vn + c);
+  const T t1 = dv1 - dvn * n1, t2 = dv2 - dvn * n2, t3 = dv3 - dvn * n3;
+  const T udt = u1 * t1 + u2 * t2 + u3 * t3;
+  const T w1 = l1 * a1, w3 = l3 * a3;
+  T W[5];
+  W[0] = w1 + l2 * a2 + w3;
+  W[1] = w1 * (u1 - c * n1) + l2 * (a2 * u1 + rho * t1) + w3 * (u1 + c * n1);
+  W[2] = w1 * (u2 - c * n2) + l2 * (a2 * u2 + rho * t2) + w3 * (u2 + c * n2);
+  W[3] = w1 * (u3 - c * n3) + l2 * (a2 * u3 + rho * t3) + w3 * (u3 + c * n3);
+  W[4] = w1 * (H - vn * c) + l2 * (a2 * (T)0.5 * q2 + rho * udt) + w3 * (H + vn * c);
+#pragma unroll
+  for (int k = 0; k < 5; k++) F[k] = area * (T)0.5 * (FL[k] + FR[k] - W[k]);
+}
+
+// ------------------------------------------------------------------ BR1 gradient + viscous flux
+// Lifted gradient of g = (v1, v2, v3, T) at this lane's node and the contravariant viscous
+// flux F~v^d = sum_x Ja^d_x Fv_x (momentum 1..3, energy) in each reference direction d.
+//   J grad g = sum_d Ja^d [ D_d g + (1/w_N)(g* - g) at xi_d=+1 - (1/w_0)(g* - g) at xi_d=-1 ]
+template <int n, typename T>
+__device__ __forceinline__ void gradient_and_viscous_flux(int t, int ti, int tj, int tk,
+                                                          const double* sD, T iwN, T iw0,
+                                                          const T (*sG)[n * n * n],
+                                                          const T (*sJ)[4][n * n], const double ja[9],
+                                                          double ij, T mu, T kappa, T Fvd[3][4]) {
+  constexpr int N = n - 1, nf = n * n;
+  T a[3][4];
+#pragma unroll
+  for (int d = 0; d < 3; d++) {
+    const int id = d == 0 ? ti : (d == 1 ? tj : tk);
+    const int stride = d == 0 ? 1 : (d == 1 ? n : nf);
+    const int b0 = t - id * stride;
+#pragma unroll
+    for (int c = 0; c < 4; c++) a[d][c] = (T)0;
+#pragma unroll
+    for (int m = 0; m < n; m++) {
+      const T Dm = (T)sD[id * n + m];
+#pragma unroll
+      for (int c = 0; c < 4; c++) a[d][c] += Dm * sG[c][b0 + m * stride];
+    }
+    const int qd = d == 0 ? tj + n * tk : (d == 1 ? ti + n * tk : ti + n * tj);
+    if (id == N) {
+#pragma unroll
+      for (int c = 0; c < 4; c++) a[d][c] += iwN * sJ[2 * d + 1][c][qd];
+    }
+    if (id == 0) {
+#pragma unroll
+      for (int c = 0; c < 4; c++) a[d][c] -= iw0 * sJ[2 * d][c][qd];
+    }
+  }
+  T gr[4][3];  // gr[c][x] = d g_c / d x_x
+#pragma unroll
+  for (int c = 0; c < 4; c++)
+#pragma unroll
+    for (int x = 0; x < 3; x++)
+      gr[c][x] = (T)ij * ((T)ja[x] * a[0][c] + (T)ja[3 + x] * a[1][c] + (T)ja[6 + x] * a[2][c]);
+  const T v1 = sG[0][t], v2 = sG[1][t], v3 = sG[2][t];
+  const T divv = gr[0][0] + gr[1][1] + gr[2][2];
+  T tau[3][3];
+#pragma unroll
+  for (int p = 0; p < 3; p++)
+#pragma unroll
+    for (int q = 0; q < 3; q++)
+      tau[p][q] = mu * (gr[p][q] + gr[q][p]) - (p == q ? (T)(2.0 / 3.0) * mu * divv : (T)0);
+  T Fv[3][4];
+#pragma unroll
+  for (int x = 0; x < 3; x++) {
+    Fv[x][0] = tau[0][x];
+    Fv[x][1] = tau[1][x];
+    Fv[x][2] = tau[2][x];
+    Fv[x][3] = v1 * tau[0][x] + v2 * tau[1][x] + v3 * tau[2][x] + kappa * gr[3][x];
+  }
+#pragma unroll
+  for (int d = 0; d < 3; d++)
+#pragma unroll
+    for (int c = 0; c < 4; c++)
+      Fvd[d][c] = (T)ja[3 * d] * Fv[0][c] + (T)ja[3 * d + 1] * Fv[1][c] + (T)ja[3 * d + 2] * Fv[2][c];
+}
+
+template <typename T>
+__device__ __forceinline__ void gvars(const double u[5], double gamma, T g[4]) {
+  const double i = 1.0 / u[0];
+  const double a1 = u[1] * i, a2 = u[2] * i, a3 = u[3] * i;
+  const double p = (gamma - 1.0) * (u[4] - 0.5 * u[0] * (a1 * a1 + a2 * a2 + a3 * a3));
+  g[0] = (T)a1;
+  g[1] = (T)a2;
+  g[2] = (T)a3;
+  g[3] = (T)(p * i);
+}
+
+// ------------------------------------------------------------------ geometry (FP64 always)
+template <int N>
+__global__ void __launch_bounds__(nthreads_for(N)) geometry_kernel(View v) {
+  constexpr int n = N + 1, nn = n * n * n, nf = n * n, NT = nthreads_for(N);
+  const int e = blockIdx.x;
+  const int t = threadIdx.x;
+  const bool act = t < nn;
+  const int ti = t % n, tj = (t / n) % n, tk = t / nf;
+  __shared__ double sD[n * n], sxi[n];
+  __shared__ double sXl[3][nn], sdX[9][nn], sA[3][nn];
+  for (int x = t; x < n * n; x += NT) sD[x] = v.tab[2 * n + x];
+  if (t < n) sxi[t] = v.tab[t];
+  __syncthreads();
+  const int cell[3] = {e % v.ex, (e / v.ex) % v.ey, e / (v.ex * v.ey)};
+  const long base = (long)e * nn;
+  if (act) {
+    const int ii[3] = {ti, tj, tk};
+    double loc[3], xu[3], dx[3] = {0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+      loc[d] = (1.0 + sxi[ii[d]]) * 0.5 * v.h[d];
+      xu[d] = v.lo[d] + cell[d] * v.h[d] + loc[d];
+    }
+    if (v.deform) {
+      dx[0] = v.amp * sin(xu[1]) * sin(xu[2]);
+      dx[1] = v.amp * sin(xu[2]) * sin(xu[0]);
+      dx[2] = v.amp * sin(xu[0]) * sin(xu[1]);
+    }
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+      v.X[base * 3 + d * nn + t] = xu[d] + dx[d];
+      sXl[d][t] = loc[d] + dx[d];  // coordinates relative to the element's corner
+    }
+  }
+  __syncthreads();
+  auto dref = [&](const double* f, int d) {
+    const int id = d == 0 ? ti : (d == 1 ? tj : tk);
+    const int stride = d == 0 ? 1 : (d == 1 ? n : nf);
+    const int b0 = t - id * stride;
+    double s = 0.0;
+#pragma unroll
+    for (int m = 0; m < n; m++) s += sD[id * n + m] * f[b0 + m * stride];
+    return s;
+  };
+  if (act) {
+#pragma unroll
+    for (int m = 0; m < 3; m++)
+#pragma unroll
+      for (int d = 0; d < 3; d++) sdX[3 * m + d][t] = dref(sXl[m], d);
+  }
+  __syncthreads();
+  // curl form: Ja^d_c = -[curl_xi (X_l grad_xi X_m)]_d, (c, m, l) cyclic.  A constant added to
+  // X_l does not change it (the tensor-product derivatives commute), hence the corner-relative
+  // coordinates.
+  for (int c = 0; c < 3; c++) {
+    const int m = (c + 1) % 3, l = (c + 2) % 3;
+    if (act) {
+#pragma unroll
+      for (int d = 0; d < 3; d++) sA[d][t] = sXl[l][t] * sdX[3 * m + d][t];
+    }
+    __syncthreads();
+    if (act) {
+      const double c0 = dref(sA[2], 1) - dref(sA[1], 2);
+      const double c1 = dref(sA[0], 2) - dref(sA[2], 0);
+      const double c2 = dref(sA[1], 0) - dref(sA[0], 1);
+      v.Ja[base * 9 + (3 * 0 + c) * nn + t] = -c0;
+      v.Ja[base * 9 + (3 * 1 + c) * nn + t] = -c1;
+      v.Ja[base * 9 + (3 * 2 + c) * nn + t] = -c2;
+    }
+    __syncthreads();
+  }
+  if (act) {
+    const double* a = &sdX[0][0];
+    auto X = [&](int m, int d) { return a[(3 * m + d) * nn + t]; };
+    const double J = X(0, 0) * (X(1, 1) * X(2, 2) - X(2, 1) * X(1, 2)) +
+                     X(1, 0) * (X(2, 1) * X(0, 2) - X(0, 1) * X(2, 2)) +
+                     X(2, 0) * (X(0, 1) * X(1, 2) - X(1, 1) * X(0, 2));
+    v.J[base + t] = J;
+    v.invJ[base + t] = 1.0 / J;
+  }
+}
+
+// The face normal Ja^d on the -d side of each element is replaced by the owner's (the
+// element across that face, whose +d side it is): both sides then evaluate bitwise the same
+// face flux.  The two values differ only by rounding.
+template <int N>
+__global__ void facefix_kernel(View v) {
+  constexpr int n = N + 1, nn = n * n * n, nf = n * n;
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (long)v.E * 3 * nf) return;
+  const int e = (int)(gid / (3 * nf));
+  const int rem = (int)(gid - (long)e * 3 * nf);
+  const int d = rem / nf, q = rem - d * nf;
+  const int p = q % n, r = q / n;
+  const int ne = v.nbr[e * 6 + 2 * d + 1];
+  const int io = face_node<n>(d, N, p, r), in = face_node<n>(d, 0, p, r);
+#pragma unroll
+  for (int c = 0; c < 3; c++)
+    v.Ja[(long)ne * nn * 9 + (3 * d + c) * nn + in] = v.Ja[(long)e * nn * 9 + (3 * d + c) * nn + io];
+}
+
+// ------------------------------------------------------------------ initial conditions
+struct IcParams {
+  double p[9];
+};
+
+__global__ void ic_kernel(View v, int cur, int ic, IcParams P) {
+  const int nn = (v.N + 1) * (v.N + 1) * (v.N + 1);
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (long)v.E * nn) return;
+  const long e = gid / nn;
+  const int q = (int)(gid - e * nn);
+  const double x = v.X[e * nn * 3 + q], y = v.X[e * nn * 3 + nn + q], z = v.X[e * nn * 3 + 2 * nn + q];
+  const double g = v.gamma;
+  double rho = 1, u = 0, w = 0, s = 0, p = 1;
+  if (ic == 0) {
+    rho = P.p[0]; u = P.p[1]; w = P.p[2]; s = P.p[3]; p = P.p[4];
+  } else if (ic == 1) {
+    const double p0 = 1.0 / (g * v.Ma * v.Ma);
+    u = sin(x) * cos(y) * cos(z);
+    w = -cos(x) * sin(y) * cos(z);
+    s = 0;
+    p = p0 + (cos(2 * x) + cos(2 * y)) * (cos(2 * z) + 2) / 16;
+    rho = p / p0;
+  } else if (ic == 2) {
+    const double beta = P.p[0], dx = x - P.p[1], dy = y - P.p[2];
+    const double r2 = dx * dx + dy * dy;
+    const double pi = 3.14159265358979323846;
+    const double f = beta / (2 * pi) * exp(0.5 * (1 - r2));
+    u = P.p[3] - f * dy;
+    w = P.p[4] + f * dx;
+    s = 0;
+    const double T = 1 - (g - 1) * beta * beta / (8 * g * pi * pi) * exp(1 - r2);
+    rho = pow(T, 1 / (g - 1));
+    p = rho * T;
+  } else {
+    rho = 1 + P.p[0] * sin(P.p[5] * x + P.p[6] * y + P.p[7] * z + P.p[8]);
+    u = P.p[1]; w = P.p[2]; s = P.p[3]; p = P.p[4];
+  }
+  double* U = v.U[cur] + e * nn * 5;
+  U[q] = rho;
+  U[nn + q] = rho * u;
+  U[2 * nn + q] = rho * w;
+  U[3 * nn + q] = rho * s;
+  U[4 * nn + q] = p / (g - 1) + 0.5 * rho * (u * u + w * w + s * s);
+#pragma unroll
+  for (int c = 0; c < 5; c++) v.dU[e * nn * 5 + c * nn + q] = 0.0;
+}
+
+// ------------------------------------------------------------------ pass A (Navier-Stokes)
+// Lifted gradient of (v, T) and, on the six faces, the contravariant viscous flux along the
+// face normal direction: Fvf[e][2d+side][c][face node].
+template <int N, typename T>
+__global__ void __launch_bounds__(nthreads_for(N)) grad_kernel(View v, int cur) {
+  constexpr int n = N + 1, nn = n * n * n, nf = n * n, NT = nthreads_for(N);
+  const int e = block_element(v.E);
+  const int t = threadIdx.x;
+  const bool act = t < nn;
+  const int ti = t % n, tj = (t / n) % n, tk = t / nf;
+  const double* __restrict__ Uin = v.U[cur];
+  __shared__ double sD[n * n], sw[n];
+  __shared__ T sG[4][nn];
+  __shared__ T sJ[6][4][nf];
+  for (int x = t; x < n * n; x += NT) sD[x] = v.tab[2 * n + x];
+  if (t < n) sw[t] = v.tab[n + t];
+  const long base = (long)e * nn;
+  double ja[9], ij = 0.0;
+  if (act) {
+    double u[5];
+#pragma unroll
+    for (int c = 0; c < 5; c++) u[c] = Uin[base * 5 + c * nn + t];
+    T g[4];
+    gvars(u, v.gamma, g);
+#pragma unroll
+    for (int c = 0; c < 4; c++) sG[c][t] = g[c];
+#pragma unroll
+    for (int c = 0; c < 9; c++) ja[c] = v.Ja[base * 9 + c * nn + t];
+    ij = v.invJ[base + t];
+  }
+  __syncthreads();
+  for (int x = t; x < 6 * nf; x += NT) {
+    const int f = x / nf, q = x - f * nf;
+    const int d = f >> 1, side = f & 1;
+    const int p = q % n, r = q / n;
+    const int io = face_node<n>(d, side ? N : 0, p, r);
+    const int ne = v.nbr[e * 6 + f];
+    const int inb = face_node<n>(d, side ? 0 : N, p, r);
+    double un[5];
+#pragma unroll
+    for (int c = 0; c < 5; c++) un[c] = Uin[(long)ne * nn * 5 + c * nn + inb];
+    T gn[4];
+    gvars(un, v.gamma, gn);
+#pragma unroll
+    for (int c = 0; c < 4; c++) sJ[f][c][q] = (T)0.5 * (gn[c] - sG[c][io]);
+  }
+  __syncthreads();
+  if (act) {
+    const T iwN = (T)(1.0 / sw[N]), iw0 = (T)(1.0 / sw[0]);
+    T Fvd[3][4];
+    gradient_and_viscous_flux<n, T>(t, ti, tj, tk, sD, iwN, iw0, sG, sJ, ja, ij, (T)v.mu, (T)v.kappa,
+                                    Fvd);
+    T* Fvf = reinterpret_cast<T*>(v.Fvf) + (long)e * 6 * 4 * nf;
+    const int ii[3] = {ti, tj, tk};
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+      const int qd = d == 0 ? tj + n * tk : (d == 1 ? ti + n * tk : ti + n * tj);
+      if (ii[d] == N) {
+#pragma unroll
+        for (int c = 0; c < 4; c++) Fvf[((2 * d + 1) * 4 + c) * nf + qd] = Fvd[d][c];
+      }
+      if (ii[d] == 0) {
+#pragma unroll
+        for (int c = 0; c < 4; c++) Fvf[((2 * d) * 4 + c) * nf + qd] = Fvd[d][c];
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ stage kernel
+// Residual of one element and, in RK mode, the low-storage update
+//   dU <- A dU + dt R;  U_out <- U_in + B dU   (dU not read when A = 0).
+template <int N, typename T, bool VISC>
+__global__ void __launch_bounds__(nthreads_for(N))
+    stage_kernel(View v, int cur, double dt, double rkA, double rkB, int mode) {
+  constexpr int n = N + 1, nn = n * n * n, nf = n * n, NT = nthreads_for(N);
+  const int e = block_element(v.E);
+  const int t = threadIdx.x;
+  const bool act = t < nn;
+  const int ti = t % n, tj = (t / n) % n, tk = t / nf;
+  const double* __restrict__ Uin = v.U[cur];
+
+  __shared__ double sD[n * n], sDh[n * n], sw[n];
+  __shared__ T sP[8][nn];
+  __shared__ T sJa[9][nn];
+  __shared__ T sF[6][5][nf];
+  // phase-dependent storage: {own state (double), g, half jumps} then {F~v}
+  constexpr int bytesA = 5 * nn * (int)sizeof(double) + (VISC ? (4 * nn + 24 * nf) * (int)sizeof(T) : 0);
+  constexpr int bytesB = VISC ? 12 * nn * (int)sizeof(T) : 0;
+  __shared__ __align__(16) char sRaw[bytesA > bytesB ? bytesA : bytesB];
+  double(*sU)[nn] = reinterpret_cast<double(*)[nn]>(sRaw);
+  T(*sG)[nn] = reinterpret_cast<T(*)[nn]>(sRaw + 5 * nn * sizeof(double));
+  T(*sJ)[4][nf] = reinterpret_cast<T(*)[4][nf]>(sRaw + 5 * nn * sizeof(double) + 4 * nn * sizeof(T));
+  T(*sFv)[4][nn] = reinterpret_cast<T(*)[4][nn]>(sRaw);
+
+  for (int x = t; x < n * n; x += NT) {
+    sD[x] = v.tab[2 * n + x];
+    sDh[x] = v.tab[2 * n + n * n + x];
+  }
+  if (t < n) sw[t] = v.tab[n + t];
+  const long base = (long)e * nn;
+  double u[5], ja[9], ij = 0.0;
+  if (act) {
+#pragma unroll
+    for (int c = 0; c < 5; c++) {
+      u[c] = Uin[base * 5 + c * nn + t];
+      sU[c][t] = u[c];
+    }
+    const Prim<T> P = make_prim<T>(u, v.gamma);
+    sP[0][t] = P.rho; sP[1][t] = P.v1; sP[2][t] = P.v2; sP[3][t] = P.v3;
+    sP[4][t] = P.beta; sP[5][t] = P.lrho; sP[6][t] = P.lbeta; sP[7][t] = P.h;
+#pragma unroll
+    for (int c = 0; c < 9; c++) {
+      ja[c] = v.Ja[base * 9 + c * nn + t];
+      sJa[c][t] = (T)ja[c];
+    }
+    ij = v.invJ[base + t];
+    if (VISC) {
+      T g[4];
+      gvars(u, v.gamma, g);
+#pragma unroll
+      for (int c = 0; c < 4; c++) sG[c][t] = g[c];
+    }
+  }
+  __syncthreads();
+
+  // ---- faces: numerical flux (minus the BR1 viscous flux) on the 6 (N+1)^2 face grids
+  const T* FvfAll = VISC ? reinterpret_cast<const T*>(v.Fvf) : nullptr;
+  for (int x = t; x < 6 * nf; x += NT) {
+    const int f = x / nf, q = x - f * nf;
+    const int d = f >> 1, side = f & 1;
+    const int p = q % n, r = q / n;
+    const int io = face_node<n>(d, side ? N : 0, p, r);
+    const int ne = v.nbr[e * 6 + f];
+    const int inb = face_node<n>(d, side ? 0 : N, p, r);
+    double un[5], uL[5], uR[5], S[3];
+#pragma unroll
+    for (int c = 0; c < 5; c++) {
+      un[c] = Uin[(long)ne * nn * 5 + c * nn + inb];
+      const double uo = sU[c][io];
+      uL[c] = side ? uo : un[c];
+      uR[c] = side ? un[c] : uo;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; c++) S[c] = v.Ja[base * 9 + (3 * d + c) * nn + io];
+    T F[5];
+    face_flux<T>(v.surf, uL, uR, S, v.gamma, F);
+    if (VISC) {
+      const T* fo = FvfAll + ((long)e * 6 + f) * 4 * nf;
+      const T* fn = FvfAll + ((long)ne * 6 + (f ^ 1)) * 4 * nf;
+#pragma unroll
+      for (int c = 0; c < 4; c++) F[1 + c] -= (T)0.5 * (fo[c * nf + q] + fn[c * nf + q]);
+      T gn[4];
+      gvars(un, v.gamma, gn);
+#pragma unroll
+      for (int c = 0; c < 4; c++) sJ[f][c][q] = (T)0.5 * (gn[c] - sG[c][io]);
+    }
+#pragma unroll
+    for (int c = 0; c < 5; c++) sF[f][c][q] = F[c];
+  }
+  __syncthreads();
+
+  const T iwN = (T)(1.0 / sw[N]), iw0 = (T)(1.0 / sw[0]);
+  if (VISC) {
+    T Fvd[3][4];
+    if (act)
+      gradient_and_viscous_flux<n, T>(t, ti, tj, tk, sD, iwN, iw0, sG, sJ, ja, ij, (T)v.mu,
+                                      (T)v.kappa, Fvd);
+    __syncthreads();  // sG / sJ are overwritten by sFv below
+    if (act) {
+#pragma unroll
+      for (int d = 0; d < 3; d++)
+#pragma unroll
+        for (int c = 0; c < 4; c++) sFv[d][c][t] = Fvd[d][c];
+    }
+    __syncthreads();
+  }
+
+  if (!act) return;
+  const T ce = (T)(0.5 / (v.gamma - 1.0)), gm1 = (T)(v.gamma - 1.0);
+  Prim<T> Pi;
+  Pi.rho = sP[0][t]; Pi.v1 = sP[1][t]; Pi.v2 = sP[2][t]; Pi.v3 = sP[3][t];
+  Pi.beta = sP[4][t]; Pi.lrho = sP[5][t]; Pi.lbeta = sP[6][t]; Pi.h = sP[7][t];
+  T acc[5] = {0, 0, 0, 0, 0};
+  T accv[4] = {0, 0, 0, 0};
+  const int ii[3] = {ti, tj, tk};
+#pragma unroll
+  for (int d = 0; d < 3; d++) {
+    const int id = ii[d];
+    const int stride = d == 0 ? 1 : (d == 1 ? n : nf);
+    const int b0 = t - id * stride;
+    const T m1 = sJa[3 * d][t], m2 = sJa[3 * d + 1][t], m3 = sJa[3 * d + 2][t];
+#pragma unroll
+    for (int m = 0; m < n; m++) {
+      if (m == id) continue;
+      const int tm = b0 + m * stride;
+      Prim<T> Pm;
+      Pm.rho = sP[0][tm]; Pm.v1 = sP[1][tm]; Pm.v2 = sP[2][tm]; Pm.v3 = sP[3][tm];
+      Pm.beta = sP[4][tm]; Pm.lrho = sP[5][tm]; Pm.lbeta = sP[6][tm]; Pm.h = sP[7][tm];
+      T F[5];
+      vol_flux<T>(v.vol, Pi, Pm, m1 + sJa[3 * d][tm], m2 + sJa[3 * d + 1][tm], m3 + sJa[3 * d + 2][tm],
+                  ce, gm1, F);
+      const T Dm = (T)sD[id * n + m];
+#pragma unroll
+      for (int c = 0; c < 5; c++) acc[c] += Dm * F[c];
+    }
+    if (VISC) {
+#pragma unroll
+      for (int m = 0; m < n; m++) {
+        const T Dh = (T)sDh[id * n + m];
+#pragma unroll
+        for (int c = 0; c < 4; c++) accv[c] += Dh * sFv[d][c][b0 + m * stride];
+      }
+    }
+    const int qd = d == 0 ? tj + n * tk : (d == 1 ? ti + n * tk : ti + n * tj);
+    if (id == N) {
+#pragma unroll
+      for (int c = 0; c < 5; c++) acc[c] += iwN * sF[2 * d + 1][c][qd];
+    }
+    if (id == 0) {
+#pragma unroll
+      for (int c = 0; c < 5; c++) acc[c] -= iw0 * sF[2 * d][c][qd];
+    }
+  }
+  double R[5];
+#pragma unroll
+  for (int c = 0; c < 5; c++) {
+    T jr = -acc[c];
+    if (VISC && c > 0) jr += accv[c - 1];
+    R[c] = (double)jr * ij;
+  }
+  const long o = base * 5 + t;
+  if (mode == kModeResidual) {
+#pragma unroll
+    for (int c = 0; c < 5; c++) v.R[o + c * nn] = R[c];
+    return;
+  }
+  double* __restrict__ Uout = v.U[cur ^ 1];
+#pragma unroll
+  for (int c = 0; c < 5; c++) {
+    const double du = (rkA == 0.0 ? 0.0 : rkA * v.dU[o + c * nn]) + dt * R[c];
+    v.dU[o + c * nn] = du;
+    Uout[o + c * nn] = u[c] + rkB * du;
+  }
+}
+
+// ------------------------------------------------------------------ diagnostics (FP64)
+// slots: 0-4 integral of U, 5 integral of -rho s, 6 integral of -rho s/(gamma-1), 7 integral of
+// rho|v|^2/2, 8 integral of rho|curl v|^2/2, 9 max(|v|+c), 10 min rho, 11 min p,
+// 12 number of non-finite values, 13 volume
+template <int N>
+__global__ void __launch_bounds__(nthreads_for(N)) diag_kernel(View v, int cur) {
+  constexpr int n = N + 1, nn = n * n * n, nf = n * n, NT = nthreads_for(N);
+  const int e = blockIdx.x;
+  const int t = threadIdx.x;
+  const bool act = t < nn;
+  const int ti = t % n, tj = (t / n) % n, tk = t / nf;
+  __shared__ double sD[n * n], sw[n];
+  constexpr int NP = pow2_at_least(NT);  // tree size (NT need not be a power of two)
+  __shared__ double sV[3][nn];
+  __shared__ double red[NP];
+  for (int x = t; x < n * n; x += NT) sD[x] = v.tab[2 * n + x];
+  if (t < n) sw[t] = v.tab[n + t];
+  const long base = (long)e * nn;
+  double u[5] = {0, 0, 0, 0, 0};
+  if (act) {
+#pragma unroll
+    for (int c = 0; c < 5; c++) u[c] = v.U[cur][base * 5 + c * nn + t];
+#pragma unroll
+    for (int c = 0; c < 3; c++) sV[c][t] = u[1 + c] / u[0];
+  }
+  __syncthreads();
+  double s[kDiagSlots];
+#pragma unroll
+  for (int k = 0; k < kDiagSlots; k++) s[k] = 0.0;
+  s[9] = -INFINITY;
+  s[10] = INFINITY;
+  s[11] = INFINITY;
+  if (act) {
+    const double g = v.gamma;
+    const double wq = sw[ti] * sw[tj] * sw[tk] * v.J[base + t];
+    const double ij = v.invJ[base + t];
+    const double rho = u[0];
+    const double v1 = sV[0][t], v2 = sV[1][t], v3 = sV[2][t];
+    const double q2 = v1 * v1 + v2 * v2 + v3 * v3;
+    const double p = (g - 1) * (u[4] - 0.5 * rho * q2);
+    int bad = 0;
+#pragma unroll
+    for (int c = 0; c < 5; c++) {
+      s[c] = wq * u[c];
+      bad += isfinite(u[c]) ? 0 : 1;
+    }
+    const double sp = log(p) - g * log(rho);
+    s[5] = wq * (-rho * sp);
+    s[6] = s[5] / (g - 1);
+    s[7] = wq * 0.5 * rho * q2;
+    double gv[3][3];
+    const int ii[3] = {ti, tj, tk};
+    double dv[3][3];  // dv[d][c] = D_d v_c
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+      const int id = ii[d];
+      const int stride = d == 0 ? 1 : (d == 1 ? n : nf);
+      const int b0 = t - id * stride;
+#pragma unroll
+      for (int c = 0; c < 3; c++) {
+        double a = 0.0;
+#pragma unroll
+        for (int m = 0; m < n; m++) a += sD[id * n + m] * sV[c][b0 + m * stride];
+        dv[d][c] = a;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; c++)
+#pragma unroll
+      for (int x = 0; x < 3; x++) {
+        double a = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; d++) a += v.Ja[base * 9 + (3 * d + x) * nn + t] * dv[d][c];
+        gv[c][x] = a * ij;
+      }
+    const double o1 = gv[2][1] - gv[1][2], o2 = gv[0][2] - gv[2][0], o3 = gv[1][0] - gv[0][1];
+    s[8] = wq * 0.5 * rho * (o1 * o1 + o2 * o2 + o3 * o3);
+    s[9] = sqrt(q2) + sqrt(g * p / rho);
+    s[10] = rho;
+    s[11] = p;
+    s[12] = (double)bad;
+    s[13] = wq;
+  }
+  // fixed-order tree reduction, one slot at a time; slots beyond NT hold the identity
+  for (int k = 0; k < 14; k++) {
+    red[t] = s[k];
+    if (t + NT < NP) red[t + NT] = k == 9 ? -INFINITY : ((k == 10 || k == 11) ? INFINITY : 0.0);
+    __syncthreads();
+    for (int w = NP / 2; w > 0; w >>= 1) {
+      if (t < w) {
+        const double a = red[t], b = red[t + w];
+        red[t] = k == 9 ? fmax(a, b) : ((k == 10 || k == 11) ? fmin(a, b) : a + b);
+      }
+      __syncthreads();
+    }
+    if (t == 0) v.part[(long)e * kDiagSlots + k] = red[0];
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(256) diag_final_kernel(View v) {
+  __shared__ double red[256];
+  const int t = threadIdx.x;
+  for (int k = 0; k < 14; k++) {
+    double a = k == 9 ? -INFINITY : ((k == 10 || k == 11) ? INFINITY : 0.0);
+    for (int e = t; e < v.E; e += 256) {
+      const double b = v.part[(long)e * kDiagSlots + k];
+      a = k == 9 ? fmax(a, b) : ((k == 10 || k == 11) ? fmin(a, b) : a + b);
+    }
+    red[t] = a;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (t < w) {
+        const double x = red[t], y = red[t + w];
+        red[t] = k == 9 ? fmax(x, y) : ((k == 10 || k == 11) ? fmin(x, y) : x + y);
+      }
+      __syncthreads();
+    }
+    if (t == 0) v.diag[k] = red[0];
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+template <int N>
+static hipError_t geometry_n(const View& v, hipStream_t st) {
+  constexpr int n = N + 1, nf = n * n;
+  hipLaunchKernelGGL(geometry_kernel<N>, dim3(v.E), dim3(nthreads_for(N)), 0, st, v);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  const long total = (long)v.E * 3 * nf;
+  hipLaunchKernelGGL(facefix_kernel<N>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, v);
+  return hipGetLastError();
+}
+
+template <int N, typename T>
+static hipError_t gradient_nt(const View& v, int cur, hipStream_t st) {
+  hipLaunchKernelGGL((grad_kernel<N, T>), dim3(v.E), dim3(nthreads_for(N)), 0, st, v, cur);
+  return hipGetLastError();
+}
+
+template <int N>
+static hipError_t gradient_n(const View& v, int cur, hipStream_t st) {
+  return v.fp32 ? gradient_nt<N, float>(v, cur, st) : gradient_nt<N, double>(v, cur, st);
+}
+
+template <int N, typename T>
+static hipError_t stage_nt(const View& v, int cur, double dt, double a, double b, int mode,
+                           hipStream_t st) {
+  const dim3 grid(v.E), block(nthreads_for(N));
+  if (v.viscous)
+    hipLaunchKernelGGL((stage_kernel<N, T, true>), grid, block, 0, st, v, cur, dt, a, b, mode);
+  else
+    hipLaunchKernelGGL((stage_kernel<N, T, false>), grid, block, 0, st, v, cur, dt, a, b, mode);
+  return hipGetLastError();
+}
+
+template <int N>
+static hipError_t stage_n(const View& v, int cur, double dt, double a, double b, int mode,
+                          hipStream_t st) {
+  return v.fp32 ? stage_nt<N, float>(v, cur, dt, a, b, mode, st)
+                : stage_nt<N, double>(v, cur, dt, a, b, mode, st);
+}
+
+template <int N>
+static hipError_t diag_n(const View& v, int cur, hipStream_t st) {
+  hipLaunchKernelGGL(diag_kernel<N>, dim3(v.E), dim3(nthreads_for(N)), 0, st, v, cur);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(256), 0, st, v);
+  return hipGetLastError();
+}
+
+#define DG_DISPATCH(FN, ...)                          \
+  switch (v.N) {                                      \
+    case 1: return FN<1>(__VA_ARGS__);                \
+    case 2: return FN<2>(__VA_ARGS__);                \
+    case 3: return FN<3>(__VA_ARGS__);                \
+    case 4: return FN<4>(__VA_ARGS__);                \
+    case 5: return FN<5>(__VA_ARGS__);                \
+    case 6: return FN<6>(__VA_ARGS__);                \
+    case 7: return FN<7>(__VA_ARGS__);                \
+    default: return hipErrorInvalidValue;             \
+  }
+
+hipError_t launch_geometry(const View& v, hipStream_t st) { DG_DISPATCH(geometry_n, v, st) }
+
+hipError_t launch_gradient(const View& v, int cur, hipStream_t st) { DG_DISPATCH(gradient_n, v, cur, st) }
+
+hipError_t launch_stage(const View& v, int cur, double dt, double rkA, double rkB, int mode,
+                        hipStream_t st) {
+  DG_DISPATCH(stage_n, v, cur, dt, rkA, rkB, mode, st)
+}
+
+hipError_t launch_diagnostics(const View& v, int cur, hipStream_t st) { DG_DISPATCH(diag_n, v, cur, st) }
+
+hipError_t launch_ic(const View& v, int cur, int ic, const double* params, hipStream_t st) {
+  IcParams P;
+  for (int k = 0; k < 9; k++) P.p[k] = params ? params[k] : 0.0;
+  const int nn = (v.N + 1) * (v.N + 1) * (v.N + 1);
+  const long total = (long)v.E * nn;
+  hipLaunchKernelGGL(ic_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, v, cur, ic, P);
+  return hipGetLastError();
+}
+
+}  // namespace dg

@@ -1,0 +1,254 @@
+"""Python binding of libdgsem.so (argument marshalling only; every step runs in HIP kernels).
+
+The names follow the C ABI of include/dgsem.h.  Device memory comes from PyTorch (one uint8
+tensor per solver) and the work is enqueued on the current PyTorch stream.  There is no CPU
+fallback: without the compiled library every call raises.
+"""
+import ctypes
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdgsem.so")
+
+DG_OK, DG_EINVAL, DG_ENOMEM, DG_EHIP, DG_ENONFINITE, DG_EUNSUPPORTED, DG_ESTATE = 0, -1, -2, -3, -4, -5, -6
+VOL = {"ec": 0, "central": 1}
+SURF = {"roe": 0, "llf": 1, "ec": 2, "central": 3}
+PRECISION = {"fp64": 0, "fp32_bulk": 1}
+IC = {"uniform": 0, "tgv": 1, "vortex": 2, "density_wave": 3}
+IC_NPARAMS = {"uniform": 5, "tgv": 0, "vortex": 5, "density_wave": 9}
+
+_c = ctypes
+_dp = _c.POINTER(_c.c_double)
+
+
+class BoxDesc(_c.Structure):
+    _fields_ = [("ex", _c.c_int), ("ey", _c.c_int), ("ez", _c.c_int), ("lo", _c.c_double * 3),
+                ("hi", _c.c_double * 3), ("deform", _c.c_int), ("deform_amp", _c.c_double),
+                ("n_uniform", _c.c_int), ("orders", _c.POINTER(_c.c_int))]
+
+
+class Physics(_c.Structure):
+    _fields_ = [("gamma", _c.c_double), ("Pr", _c.c_double), ("Ma", _c.c_double),
+                ("Re", _c.c_double), ("vol_flux", _c.c_int), ("surf_flux", _c.c_int),
+                ("precision", _c.c_int)]
+
+
+class Diag(_c.Structure):
+    _fields_ = [("mass", _c.c_double * 5), ("entropy_paper", _c.c_double),
+                ("entropy", _c.c_double), ("ke", _c.c_double), ("enstrophy", _c.c_double),
+                ("lambda_max", _c.c_double), ("rho_min", _c.c_double), ("p_min", _c.c_double),
+                ("volume", _c.c_double), ("nonfinite", _c.c_longlong)]
+
+
+class Profile(_c.Structure):
+    _fields_ = [("ms", _c.c_double * 4), ("launches", _c.c_longlong * 4)]
+
+
+KERNEL_CLASSES = ["gradient", "stage", "diagnostics", "other"]
+
+EXPORTS = ["dg_last_error", "dg_mesh_create_box", "dg_mesh_destroy", "dg_mesh_info",
+           "dg_solver_create", "dg_solver_required_bytes", "dg_solver_bind",
+           "dg_set_initial_condition", "dg_set_state", "dg_get_state", "dg_residual", "dg_rk_step",
+           "dg_diagnostics", "dg_suggest_dt", "dg_get_geometry", "dg_device_pointers",
+           "dg_synchronize", "dg_solver_destroy", "dg_profile_begin", "dg_profile_end"]
+
+_lib = None
+
+
+class DgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libdgsem error {code}: {msg}")
+        self.code = code
+
+
+def lib():
+    """Load libdgsem.so (built by paper_2206_09733_amd.build / __graft_entry__.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2206_09733_amd.build`"
+                           " (there is no CPU fallback)")
+    L = _c.CDLL(LIB_PATH)
+    vp = _c.c_void_p
+    L.dg_last_error.restype = _c.c_char_p
+    L.dg_mesh_create_box.argtypes = [_c.POINTER(BoxDesc), _c.POINTER(vp)]
+    L.dg_mesh_destroy.argtypes = [vp]
+    L.dg_mesh_destroy.restype = None
+    L.dg_mesh_info.argtypes = [vp, _c.POINTER(_c.c_longlong), _c.POINTER(_c.c_longlong), _c.POINTER(_c.c_int)]
+    L.dg_solver_create.argtypes = [vp, _c.POINTER(Physics), _c.POINTER(vp)]
+    L.dg_solver_required_bytes.argtypes = [vp, _c.POINTER(_c.c_size_t)]
+    L.dg_solver_bind.argtypes = [vp, vp, _c.c_size_t, vp]
+    L.dg_set_initial_condition.argtypes = [vp, _c.c_int, _dp]
+    L.dg_set_state.argtypes = [vp, _dp, _c.c_size_t]
+    L.dg_get_state.argtypes = [vp, _dp, _c.c_size_t]
+    L.dg_residual.argtypes = [vp, _dp, _c.c_size_t]
+    L.dg_rk_step.argtypes = [vp, _c.c_double, _c.c_int]
+    L.dg_diagnostics.argtypes = [vp, _c.POINTER(Diag)]
+    L.dg_suggest_dt.argtypes = [vp, _c.c_double, _dp]
+    L.dg_get_geometry.argtypes = [vp, _dp, _dp, _dp]
+    L.dg_device_pointers.argtypes = [vp, _c.POINTER(vp), _c.POINTER(vp)]
+    L.dg_synchronize.argtypes = [vp]
+    L.dg_profile_begin.argtypes = [vp]
+    L.dg_profile_end.argtypes = [vp, _c.POINTER(Profile)]
+    L.dg_solver_destroy.argtypes = [vp]
+    L.dg_solver_destroy.restype = None
+    _lib = L
+    return L
+
+
+def check(rc):
+    if rc != DG_OK:
+        raise DgError(rc, lib().dg_last_error().decode())
+    return rc
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_dp)
+
+
+def box_desc(ex, ey, ez, lo, hi, deform, amp, N, orders=None):
+    d = BoxDesc()
+    d.ex, d.ey, d.ez = ex, ey, ez
+    d.lo[:] = list(lo)
+    d.hi[:] = list(hi)
+    d.deform = 1 if deform else 0
+    d.deform_amp = amp
+    d.n_uniform = N
+    keep = None
+    if orders is not None:
+        keep = np.ascontiguousarray(orders, dtype=np.int32).reshape(-1)
+        d.orders = keep.ctypes.data_as(_c.POINTER(_c.c_int))
+    return d, keep
+
+
+def physics(gamma=1.4, Pr=0.71, Ma=0.1, Re=0.0, vol="ec", surf="roe", precision="fp64"):
+    p = Physics()
+    p.gamma, p.Pr, p.Ma, p.Re = gamma, Pr, Ma, Re
+    p.vol_flux, p.surf_flux, p.precision = VOL[vol], SURF[surf], PRECISION[precision]
+    return p
+
+
+class Solver:
+    """One DGSEM solve on a periodic box, resident in device memory."""
+
+    def __init__(self, ex, ey=None, ez=None, lo=(0.0, 0.0, 0.0), hi=None, deform=False, amp=0.05,
+                 N=3, gamma=1.4, Pr=0.71, Ma=0.1, Re=0.0, vol="ec", surf="roe", precision="fp64",
+                 device="cuda", bind=True):
+        L = lib()
+        ey = ex if ey is None else ey
+        ez = ex if ez is None else ez
+        hi = (2 * math.pi,) * 3 if hi is None else hi
+        self.shape = (ex, ey, ez)
+        self.N = N
+        self.gamma, self.Pr, self.Ma, self.Re = gamma, Pr, Ma, Re
+        self.h = None
+        self.buf = None
+        d, _keep = box_desc(ex, ey, ez, lo, hi, deform, amp, N)
+        mesh = _c.c_void_p()
+        check(L.dg_mesh_create_box(_c.byref(d), _c.byref(mesh)))
+        try:
+            ne, nn, nmax = _c.c_longlong(), _c.c_longlong(), _c.c_int()
+            check(L.dg_mesh_info(mesh, _c.byref(ne), _c.byref(nn), _c.byref(nmax)))
+            self.E, self.nodes = ne.value, nn.value
+            h = _c.c_void_p()
+            ph = physics(gamma, Pr, Ma, Re, vol, surf, precision)
+            check(L.dg_solver_create(mesh, _c.byref(ph), _c.byref(h)))
+            self.h = h
+        finally:
+            L.dg_mesh_destroy(mesh)
+        nb = _c.c_size_t()
+        check(L.dg_solver_required_bytes(self.h, _c.byref(nb)))
+        self.required_bytes = nb.value
+        if bind:
+            self.bind(device)
+
+    def bind(self, device="cuda", stream=None):
+        import torch
+        self.buf = torch.empty(self.required_bytes + 256, dtype=torch.uint8, device=device)
+        base = self.buf.data_ptr()
+        ptr = (base + 255) & ~255
+        if stream is None:
+            stream = torch.cuda.current_stream(self.buf.device)
+        self.stream = stream
+        check(lib().dg_solver_bind(self.h, _c.c_void_p(ptr), self.required_bytes,
+                                   _c.c_void_p(stream.cuda_stream)))
+
+    # -- state
+    def set_ic(self, ic, params=None):
+        n = IC_NPARAMS[ic]
+        p = np.zeros(9)
+        if n:
+            p[:n] = np.asarray(params, dtype=np.float64)[:n]
+        check(lib().dg_set_initial_condition(self.h, IC[ic], _ptr(p)))
+
+    def set_state(self, U):
+        U = np.ascontiguousarray(U, dtype=np.float64).reshape(-1)
+        check(lib().dg_set_state(self.h, _ptr(U), U.size))
+
+    def state(self):
+        U = np.empty(5 * self.nodes)
+        check(lib().dg_get_state(self.h, _ptr(U), U.size))
+        return U
+
+    def residual(self, to_host=True):
+        if not to_host:
+            check(lib().dg_residual(self.h, None, 0))
+            return None
+        R = np.empty(5 * self.nodes)
+        check(lib().dg_residual(self.h, _ptr(R), R.size))
+        return R
+
+    def rk_step(self, dt, nsteps=1):
+        check(lib().dg_rk_step(self.h, float(dt), int(nsteps)))
+
+    def diagnostics(self):
+        d = Diag()
+        check(lib().dg_diagnostics(self.h, _c.byref(d)))
+        out = {f"mass_{k}": d.mass[i] for i, k in enumerate(["rho", "rhou", "rhov", "rhow", "rhoE"])}
+        for k in ("entropy_paper", "entropy", "ke", "enstrophy", "lambda_max", "rho_min", "p_min",
+                  "volume"):
+            out[k] = getattr(d, k)
+        out["nonfinite"] = d.nonfinite
+        return out
+
+    def suggest_dt(self, cfl):
+        dt = _c.c_double()
+        check(lib().dg_suggest_dt(self.h, float(cfl), _c.byref(dt)))
+        return dt.value
+
+    def geometry(self):
+        X, Ja, J = np.empty(3 * self.nodes), np.empty(9 * self.nodes), np.empty(self.nodes)
+        check(lib().dg_get_geometry(self.h, _ptr(X), _ptr(Ja), _ptr(J)))
+        return X, Ja, J
+
+    def device_pointers(self):
+        u, r = _c.c_void_p(), _c.c_void_p()
+        check(lib().dg_device_pointers(self.h, _c.byref(u), _c.byref(r)))
+        return u.value, r.value
+
+    def profile_begin(self):
+        check(lib().dg_profile_begin(self.h))
+
+    def profile_end(self):
+        p = Profile()
+        check(lib().dg_profile_end(self.h, _c.byref(p)))
+        return {k: {"ms": p.ms[i], "launches": p.launches[i]} for i, k in enumerate(KERNEL_CLASSES)}
+
+    def synchronize(self):
+        check(lib().dg_synchronize(self.h))
+
+    def close(self):
+        if self.h:
+            lib().dg_solver_destroy(self.h)
+            self.h = None
+        self.buf = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

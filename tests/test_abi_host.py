@@ -1,0 +1,104 @@
+"""The C-ABI library loads, exports every entry point that include/dgsem.h declares, and its
+host-side argument checks answer with the documented codes -- without touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    src = open(os.path.join(ROOT, "include", "dgsem.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\s*\*)\s*(dg_\w+)\s*\(", src, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def dg():
+    from paper_2206_09733_amd import dgsem
+    if not os.path.exists(dgsem.LIB_PATH):
+        from paper_2206_09733_amd import build
+        build.build()
+    return dgsem
+
+
+def test_library_exports_every_declared_symbol(dg):
+    names = _header_functions()
+    assert len(names) >= 18, names
+    L = dg.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(dg.EXPORTS) <= set(names)
+
+
+def test_mesh_argument_errors(dg):
+    L = dg.lib()
+    m = ctypes.c_void_p()
+    d, _ = dg.box_desc(0, 2, 2, (0, 0, 0), (1, 1, 1), False, 0.0, 3)
+    assert L.dg_mesh_create_box(ctypes.byref(d), ctypes.byref(m)) == dg.DG_EINVAL
+    assert b"element" in L.dg_last_error()
+    d, _ = dg.box_desc(2, 2, 2, (0, 0, 0), (1, -1, 1), False, 0.0, 3)
+    assert L.dg_mesh_create_box(ctypes.byref(d), ctypes.byref(m)) == dg.DG_EINVAL
+    d, _ = dg.box_desc(2, 2, 2, (0, 0, 0), (1, 1, 1), False, 0.0, 8)
+    assert L.dg_mesh_create_box(ctypes.byref(d), ctypes.byref(m)) == dg.DG_EINVAL
+    d, _ = dg.box_desc(2, 1, 1, (0, 0, 0), (1, 1, 1), False, 0.0, 3, orders=[3, 3, 3, 4, 3, 3])
+    assert L.dg_mesh_create_box(ctypes.byref(d), ctypes.byref(m)) == dg.DG_EUNSUPPORTED
+    d, _ = dg.box_desc(2, 3, 4, (0, 0, 0), (1, 1, 1), True, 0.05, 4)
+    assert L.dg_mesh_create_box(ctypes.byref(d), ctypes.byref(m)) == dg.DG_OK
+    ne, nn, nmax = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_int()
+    assert L.dg_mesh_info(m, ctypes.byref(ne), ctypes.byref(nn), ctypes.byref(nmax)) == 0
+    assert (ne.value, nn.value, nmax.value) == (24, 24 * 125, 4)
+    L.dg_mesh_destroy(m)
+
+
+def _mesh(dg, ex=2, N=3):
+    L = dg.lib()
+    m = ctypes.c_void_p()
+    d, _ = dg.box_desc(ex, ex, ex, (0, 0, 0), (1, 1, 1), False, 0.0, N)
+    dg.check(L.dg_mesh_create_box(ctypes.byref(d), ctypes.byref(m)))
+    return m
+
+
+def test_solver_argument_errors_and_sizes(dg):
+    L = dg.lib()
+    m = _mesh(dg, 2, 3)
+    s = ctypes.c_void_p()
+    for bad in (dict(gamma=1.0), dict(vol="ec", surf="roe", precision="fp64", Ma=-1.0)):
+        p = dg.physics(**bad)
+        assert L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)) == dg.DG_EINVAL
+    p = dg.physics()
+    p.surf_flux = 9
+    assert L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)) == dg.DG_EINVAL
+    p = dg.physics(Re=100.0)
+    assert L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)) == dg.DG_OK
+    nb = ctypes.c_size_t()
+    assert L.dg_solver_required_bytes(s, ctypes.byref(nb)) == 0
+    nodes = 8 * 64
+    assert nb.value >= 8 * nodes * (5 * 4 + 3 + 9 + 2)
+    # a too-small buffer is refused before any device work
+    assert L.dg_solver_bind(s, ctypes.c_void_p(256), nb.value - 1, None) == dg.DG_ENOMEM
+    assert b"smaller" in L.dg_last_error()
+    assert L.dg_solver_bind(s, None, nb.value, None) == dg.DG_EINVAL
+    # calls that need device memory refuse an unbound solver
+    assert L.dg_rk_step(s, ctypes.c_double(1e-3), 1) == dg.DG_ESTATE
+    assert L.dg_residual(s, None, 0) == dg.DG_ESTATE
+    L.dg_solver_destroy(s)
+    L.dg_mesh_destroy(m)
+
+
+def test_required_bytes_c2_fits_one_gpu(dg):
+    """32^3 elements, N = 4, Navier-Stokes: ~1.3 GB, far below 288 GB of HBM."""
+    L = dg.lib()
+    m = ctypes.c_void_p()
+    d, _ = dg.box_desc(32, 32, 32, (0, 0, 0), (6.283185307179586,) * 3, True, 0.05, 4)
+    dg.check(L.dg_mesh_create_box(ctypes.byref(d), ctypes.byref(m)))
+    s = ctypes.c_void_p()
+    p = dg.physics(Re=1600.0)
+    dg.check(L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)))
+    nb = ctypes.c_size_t()
+    dg.check(L.dg_solver_required_bytes(s, ctypes.byref(nb)))
+    assert 1.0e9 < nb.value < 2.0e9
+    L.dg_solver_destroy(s)
+    L.dg_mesh_destroy(m)

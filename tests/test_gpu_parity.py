@@ -1,0 +1,339 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle, element by element.
+
+Floating-point bar.  The residual of the split form is a sum of flux differences whose terms
+are far larger than the result (at Ma 0.1 the pressure p0 = 71.4 and total enthalpy ~250
+cancel to O(0.1-1) rates), so any two FP64 evaluations that round differently disagree by
+the rounding level of that sum.  That level is measured, per test, as the difference between
+the oracle's double build and its long-double build on the same input (e64).  The GPU result
+must lie within max(1e-12 |R|, 8 e64) of the long-double oracle, per conserved variable: the
+GPU path is as accurate as a plain FP64 evaluation.  The relative error against the double
+oracle is printed as well.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from helpers import to_conservative
+from paper_2206_09733_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TWO_PI = 2 * math.pi
+
+
+@pytest.fixture(scope="module")
+def dg():
+    from paper_2206_09733_amd import dgsem
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    dgsem.lib()
+    return dgsem
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def cfg(**kw):
+    base = dict(ex=3, N=3, deform=False, Ma=0.3, Re=0.0, vol="ec", surf="roe")
+    base.update(kw)
+    return base
+
+
+def oracle_pair(orc, c, U):
+    o64 = orc.OracleSolver(**c)
+    o64.set_state(U)
+    o80 = orc.OracleSolver(**c, precision="fp80")
+    o80.set_state(U)
+    return o64.residual(), o80.residual()
+
+
+def per_var(A, nvar=5, E=None, nn=None):
+    return np.asarray(A).reshape(E, nvar, nn)
+
+
+def assert_parity(name, Rg, R64, R80, E, nn, factor=8.0):
+    G, A, B = (x.reshape(E, 5, nn) for x in (Rg, R64, R80))
+    scale = np.abs(B).max(axis=(0, 2))
+    e64 = np.abs(A - B).max(axis=(0, 2))
+    eg = np.abs(G - B).max(axis=(0, 2))
+    rel64 = np.abs(G - A).max(axis=(0, 2)) / np.maximum(np.abs(A).max(axis=(0, 2)), 1e-300)
+    tol = np.maximum(1e-12 * scale, factor * e64)
+    log(f"[{name}] |R|={np.array2string(scale, precision=2)} gpu-vs-fp80={np.array2string(eg, precision=2)} "
+        f"fp64-vs-fp80={np.array2string(e64, precision=2)} rel-vs-fp64={np.array2string(rel64, precision=2)}")
+    assert np.all(eg <= tol), (name, eg, tol)
+    return rel64
+
+
+def perturbed_state(orc, c, seed, amp=(0.02, 0.05, 0.02)):
+    """Oracle TGV state with seeded random primitive perturbations (exercises every branch)."""
+    o = orc.OracleSolver(**c)
+    o.set_ic("tgv")
+    nn = (c["N"] + 1) ** 3
+    U0 = o.state().reshape(o.E, 5, nn)
+    drho, dv, dp = synth.primitive_perturbation(o.nodes, seed, amp)
+    rho = U0[:, 0].reshape(-1)
+    v = (U0[:, 1:4] / U0[:, :1]).transpose(0, 2, 1).reshape(-1, 3)
+    p = 0.4 * (U0[:, 4].reshape(-1) - 0.5 * rho * (v * v).sum(1))
+    U = to_conservative(rho * (1 + drho), v + dv.T, p * (1 + dp))
+    return U.reshape(o.E, nn, 5).transpose(0, 2, 1).reshape(-1)
+
+
+# ------------------------------------------------------------------ geometry and initial state
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 6, 7])
+def test_geometry_parity(dg, orc, N):
+    log(f"geometry N={N}")
+    c = dict(ex=3, ey=2, ez=4, N=N, deform=True)
+    o = orc.OracleSolver(**c)
+    g = dg.Solver(**c)
+    Xg, Jag, Jg = g.geometry()
+    Xo = o.coords()
+    Jao, Jo = o.metrics()
+    assert np.abs(Xg - Xo).max() < 1e-14
+    assert np.abs(Jag - Jao).max() < 1e-13 * np.abs(Jao).max()
+    assert np.abs(Jg - Jo).max() < 1e-13 * np.abs(Jo).max()
+
+
+@pytest.mark.parametrize("ic,params", [("tgv", None), ("uniform", [1.2, 0.3, -0.1, 0.2, 3.0]),
+                                       ("density_wave", [0.2, 1.0, 0.5, 0.0, 1.0, 1.0, 1.0, 0.0, 0.3]),
+                                       ("vortex", [5.0, 0.5, -0.3, 0.4, 0.4])])
+def test_initial_condition_parity(dg, orc, ic, params):
+    log(f"ic {ic}")
+    c = dict(ex=4, N=4, deform=True, Ma=0.1)
+    o = orc.OracleSolver(**c)
+    g = dg.Solver(**c)
+    o.set_ic(ic, params)
+    g.set_ic(ic, params)
+    Uo, Ug = o.state(), g.state()
+    assert np.abs(Ug - Uo).max() <= 1e-14 * np.abs(Uo).max()
+
+
+# ------------------------------------------------------------------ residual
+def test_residual_c1_tgv(dg, orc):
+    """The 4^3, N=3 Euler Taylor-Green case at Ma 0.1 (EC volume, Roe faces)."""
+    c = dict(ex=4, N=3, Ma=0.1)
+    o = orc.OracleSolver(**c)
+    o.set_ic("tgv")
+    U = o.state()
+    R64, R80 = oracle_pair(orc, c, U)
+    g = dg.Solver(**c)
+    g.set_state(U)
+    rel = assert_parity("C1 TGV", g.residual(), R64, R80, o.E, 64)
+    assert rel.max() < 1e-11
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("surf", ["roe", "llf", "ec", "central"])
+def test_residual_orders_and_fluxes(dg, orc, N, surf):
+    c = cfg(ex=3, ey=2, ez=2, N=N, deform=True, surf=surf, Ma=0.3)
+    log(f"residual N={N} surf={surf}")
+    U = perturbed_state(orc, c, seed=100 + N)
+    R64, R80 = oracle_pair(orc, c, U)
+    g = dg.Solver(**c)
+    g.set_state(U)
+    assert_parity(f"N={N} {surf}", g.residual(), R64, R80, 12, (N + 1) ** 3)
+
+
+def test_residual_central_volume_flux(dg, orc):
+    c = cfg(ex=2, ey=3, ez=2, N=4, deform=True, vol="central", surf="llf")
+    U = perturbed_state(orc, c, seed=7)
+    R64, R80 = oracle_pair(orc, c, U)
+    g = dg.Solver(**c)
+    g.set_state(U)
+    assert_parity("central volume", g.residual(), R64, R80, 12, 125)
+
+
+@pytest.mark.parametrize("N", [2, 3, 4, 5, 6])
+def test_residual_navier_stokes(dg, orc, N):
+    c = cfg(ex=3, ey=2, ez=3, N=N, deform=True, Re=100.0, Ma=0.3)
+    log(f"NS residual N={N}")
+    U = perturbed_state(orc, c, seed=200 + N)
+    R64, R80 = oracle_pair(orc, c, U)
+    g = dg.Solver(**c)
+    g.set_state(U)
+    assert_parity(f"NS N={N}", g.residual(), R64, R80, 18, (N + 1) ** 3)
+
+
+def test_residual_edge_meshes(dg, orc):
+    """One element across a direction (a face is its own periodic neighbour), element counts
+    that are not multiples of 8 (plain workgroup order), a non-cubic box."""
+    for c in (cfg(ex=1, ey=1, ez=1, N=3), cfg(ex=1, ey=3, ez=2, N=4, deform=True, Re=50.0),
+              cfg(ex=5, ey=3, ez=1, N=2, hi=(1.0, 2.0, 0.5), surf="llf")):
+        log(f"edge mesh {c}")
+        E = c["ex"] * c["ey"] * c["ez"]
+        U = perturbed_state(orc, c, seed=E)
+        R64, R80 = oracle_pair(orc, c, U)
+        g = dg.Solver(**c)
+        g.set_state(U)
+        assert_parity(f"edge {c['ex']}x{c['ey']}x{c['ez']}", g.residual(), R64, R80, E, (c["N"] + 1) ** 3)
+
+
+# ------------------------------------------------------------------ invariants on the GPU path
+def test_gpu_freestream_and_conservation(dg, orc):
+    c = cfg(ex=4, N=4, deform=True, Re=200.0, Ma=0.3)
+    g = dg.Solver(**c)
+    p = 1 / (1.4 * 0.09)
+    g.set_ic("uniform", [1.0, 0.3, -0.2, 0.1, p])
+    R = g.residual()
+    _, Ja, J = g.geometry()
+    scale = (p / 0.4 + p) * np.abs(Ja).max() / J.min() * 10
+    assert np.abs(R).max() < 1e-13 * scale
+    g.set_ic("tgv")
+    R = g.residual().reshape(g.E, 5, 125)
+    _, w, _ = orc.gll(4)
+    wq = (w[:, None, None] * w[None, :, None] * w[None, None, :]).reshape(-1)[None, :] * J.reshape(g.E, 125)
+    tot = np.einsum("en,evn->v", wq, R)
+    mag = np.einsum("en,evn->v", wq, np.abs(R))
+    assert np.all(np.abs(tot) < 1e-12 * mag.max()), tot
+
+
+def test_gpu_entropy_conservation(dg, orc):
+    c = cfg(ex=3, N=3, deform=True, surf="ec", Ma=0.4)
+    U = perturbed_state(orc, c, seed=11, amp=(0.05, 0.1, 0.05))
+    g = dg.Solver(**c)
+    g.set_state(U)
+    R = g.residual()
+    o = orc.OracleSolver(**c)
+    o.set_state(U)
+    ent = o.entropy_production(R)  # sum w J w(U).R with the GPU's R
+    ent_ref = abs(o.entropy_production(np.abs(R)))
+    assert abs(ent) < 1e-11 * ent_ref
+
+
+# ------------------------------------------------------------------ time integration
+def test_rk3_trajectory_c1(dg, orc):
+    """The full 4^3, N=3 Euler TGV configuration: 10 low-storage RK3 steps at CFL 0.5."""
+    c = dict(ex=4, N=3, Ma=0.1)
+    o = orc.OracleSolver(**c)
+    o.set_ic("tgv")
+    U0 = o.state()
+    dt = o.suggest_dt(0.5)
+    o.rk3(dt, 10)
+    o80 = orc.OracleSolver(**c, precision="fp80")
+    o80.set_state(U0)
+    o80.rk3(dt, 10)
+    g = dg.Solver(**c)
+    g.set_ic("tgv")
+    assert abs(g.suggest_dt(0.5) - dt) < 1e-13 * dt
+    g.set_state(U0)
+    g.rk_step(dt, 10)
+    Ug, Uo, U80 = g.state(), o.state(), o80.state()
+    d = lambda a, b: np.abs(a - b).reshape(64, 5, 64).max(axis=(0, 2))
+    sc = np.abs(U80).reshape(64, 5, 64).max(axis=(0, 2))
+    log(f"[C1 RK] gpu-vs-fp80 {d(Ug, U80) / sc} fp64-vs-fp80 {d(Uo, U80) / sc}")
+    assert np.all(d(Ug, U80) <= np.maximum(1e-14 * sc, 8 * d(Uo, U80)))
+
+
+def test_rk3_trajectory_navier_stokes(dg, orc):
+    c = dict(ex=3, N=4, deform=True, Ma=0.1, Re=1600.0)
+    o = orc.OracleSolver(**c)
+    o.set_ic("tgv")
+    U0 = o.state()
+    dt = o.suggest_dt(0.5)
+    o.rk3(dt, 5)
+    o80 = orc.OracleSolver(**c, precision="fp80")
+    o80.set_state(U0)
+    o80.rk3(dt, 5)
+    g = dg.Solver(**c)
+    g.set_state(U0)
+    g.rk_step(dt, 5)
+    Ug, Uo, U80 = g.state(), o.state(), o80.state()
+    d = lambda a, b: np.abs(a - b).reshape(27, 5, 125).max(axis=(0, 2))
+    sc = np.abs(U80).reshape(27, 5, 125).max(axis=(0, 2))
+    log(f"[NS RK] gpu-vs-fp80 {d(Ug, U80) / sc} fp64-vs-fp80 {d(Uo, U80) / sc}")
+    assert np.all(d(Ug, U80) <= np.maximum(1e-14 * sc, 8 * d(Uo, U80)))
+
+
+def test_diagnostics_parity(dg, orc):
+    c = dict(ex=4, N=4, deform=True, Ma=0.1, Re=1600.0)
+    o = orc.OracleSolver(**c)
+    o.set_ic("tgv")
+    g = dg.Solver(**c)
+    g.set_state(o.state())
+    do, dgd = o.diagnostics(), g.diagnostics()
+    keys = {"mass_rho": "mass_rho", "mass_rhoE": "mass_rhoE", "entropy": "entropy",
+            "entropy_paper": "entropy_paper", "ke": "ke", "enstrophy": "enstrophy",
+            "lambda_max": "lambda_max", "rho_min": "rho_min", "p_min": "p_min", "volume": "volume"}
+    for ko, kg in keys.items():
+        assert abs(dgd[kg] - do[ko]) <= 1e-12 * abs(do[ko]), (ko, dgd[kg], do[ko])
+    for k in ("mass_rhou", "mass_rhov", "mass_rhow"):
+        assert abs(dgd[k] - do[k]) <= 1e-12 * do["mass_rho"]
+    assert dgd["nonfinite"] == 0
+    # bitwise reproducible reductions
+    assert g.diagnostics() == dgd
+
+
+def test_set_state_rejects_bad_input(dg, orc):
+    g = dg.Solver(ex=2, N=2)
+    g.set_ic("tgv")
+    U = g.state()
+    bad = U.copy()
+    bad[7] = np.nan
+    with pytest.raises(dg.DgError) as ei:
+        g.set_state(bad)
+    assert ei.value.code == dg.DG_ENONFINITE
+    bad = U.copy()
+    bad[0] = -1.0
+    with pytest.raises(dg.DgError):
+        g.set_state(bad)
+    assert np.array_equal(g.state(), U)
+
+
+# ------------------------------------------------------------------ FP32-bulk
+@pytest.mark.parametrize("Re", [0.0, 1600.0])
+def test_fp32_bulk_error(dg, orc, Re):
+    """FP32 flux/derivative arithmetic (FP64 metrics, RK state, reductions): the residual error
+    against the FP64 oracle, per conserved variable, at the Ma 0.1 Taylor-Green state."""
+    c = dict(ex=8, N=4, deform=True, Ma=0.1, Re=Re)
+    o = orc.OracleSolver(**c)
+    o.set_ic("tgv")
+    U = o.state()
+    Ro = o.residual()
+    g = dg.Solver(**c, precision="fp32_bulk")
+    g.set_state(U)
+    Rg = g.residual()
+    E = 512
+    err = np.abs(Rg - Ro).reshape(E, 5, 125).max(axis=(0, 2)) / np.abs(Ro).reshape(E, 5, 125).max(axis=(0, 2))
+    log(f"[FP32-bulk Re={Re}] rel err per var {err}")
+    assert err.max() < 5e-3
+
+
+# ------------------------------------------------------------------ full size
+def test_full_size_c2_residual_and_step(dg, orc):
+    """32^3 elements, N=4, deformed, Navier-Stokes TGV Re 1600 Ma 0.1 -- the benchmark
+    configuration, in the launch configuration the benchmark times: every node's residual and
+    one RK3 step against the oracle."""
+    c = dict(ex=32, N=4, deform=True, Ma=0.1, Re=1600.0)
+    log("C2 full size: oracle")
+    o = orc.OracleSolver(**c)
+    o.set_ic("tgv")
+    U = o.state()
+    R64 = o.residual()
+    log("C2 full size: gpu")
+    g = dg.Solver(**c)
+    g.set_ic("tgv")
+    Ug = g.state()
+    assert np.abs(Ug - U).max() <= 1e-14 * np.abs(U).max()
+    g.set_state(U)
+    Rg = g.residual()
+    E, nn = 32768, 125
+    rel = np.abs(Rg - R64).reshape(E, 5, nn).max(axis=(0, 2)) / np.abs(R64).reshape(E, 5, nn).max(axis=(0, 2))
+    # rounding level of a plain FP64 evaluation at this size, measured on a 16^3 sample of the
+    # same problem (the long-double build is too slow for the full size)
+    cs = dict(c, ex=16)
+    os_ = orc.OracleSolver(**cs)
+    os_.set_ic("tgv")
+    R64s, R80s = oracle_pair(orc, cs, os_.state())
+    e64 = np.abs(R64s - R80s).reshape(-1, 5, nn).max(axis=(0, 2)) / np.abs(R80s).reshape(-1, 5, nn).max(axis=(0, 2))
+    log(f"[C2] rel gpu-vs-fp64 {rel}; fp64 rounding level at 16^3 {e64}")
+    assert np.all(rel <= np.maximum(1e-12, 16 * e64))
+    dt = o.suggest_dt(0.5)
+    o.rk3(dt, 1)
+    g.rk_step(dt, 1)
+    Uo, Ug = o.state(), g.state()
+    d = np.abs(Ug - Uo).reshape(E, 5, nn).max(axis=(0, 2)) / np.abs(Uo).reshape(E, 5, nn).max(axis=(0, 2))
+    log(f"[C2] one RK3 step rel state diff {d}")
+    assert d.max() < 1e-13
