@@ -94,12 +94,22 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-fp32", action="store_true")
+    ap.add_argument("--copy-reference-mib", type=int, default=0,
+                    help="first run a plain device copy of this many MiB (a known-size reference "
+                         "for hardware traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the DGSEM path here is a single-GPU build "
               "(multi-GPU element sharding is a design note, not implemented)", file=sys.stderr)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
+    if args.copy_reference_mib:
+        import torch
+        src = torch.ones(args.copy_reference_mib << 17, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     r64 = run_gpu("fp64", args.steps, args.warmup)
     nodes, N = r64["nodes"], WORKLOAD["N"]

@@ -56,6 +56,18 @@ __device__ __forceinline__ int face_node(int d, int id, int p, int r) {
   return d == 0 ? id + n * (p + n * r) : (d == 1 ? p + n * (id + n * r) : p + n * (r + n * id));
 }
 
+// Reciprocal of a positive, finite, normal operand: hardware estimate refined by two Newton
+// steps (error within an ulp or two).  The IEEE division sequence also rescales operands near
+// the exponent limits, which the physical quantities here never approach.
+__device__ __forceinline__ double rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // ------------------------------------------------------------------ physics helpers
 template <typename T>
 struct Prim {
@@ -65,11 +77,11 @@ struct Prim {
 // primitive variables computed in FP64 from the conservative state, then rounded to T
 template <typename T>
 __device__ __forceinline__ Prim<T> make_prim(const double u[5], double gamma) {
-  const double inv = 1.0 / u[0];
+  const double inv = rcp(u[0]);
   const double v1 = u[1] * inv, v2 = u[2] * inv, v3 = u[3] * inv;
   const double h = 0.5 * (v1 * v1 + v2 * v2 + v3 * v3);
   const double p = (gamma - 1.0) * (u[4] - u[0] * h);
-  const double beta = 0.5 * u[0] / p;
+  const double beta = 0.5 * u[0] * rcp(p);
   Prim<T> o;
   o.rho = (T)u[0];
   o.v1 = (T)v1;
@@ -82,32 +94,35 @@ __device__ __forceinline__ Prim<T> make_prim(const double u[5], double gamma) {
   return o;
 }
 
-// logarithmic mean (a-b)/(ln a - ln b) as num/den; near a = b the series in
-// u = ((a-b)/(a+b))^2 replaces the cancelling logarithms
-template <typename T>
-__device__ __forceinline__ void logmean_nd(T a, T b, T la, T lb, T& num, T& den) {
-  const T d = a - b, s = a + b;
-  const T u = (d * d) / (s * s);
-  const T thr = sizeof(T) == 8 ? (T)1e-4 : (T)1e-2;
-  const bool small = u < thr;
-  const T poly = (T)2 * ((T)1 + u * ((T)(1.0 / 3.0) + u * ((T)0.2 + u * (T)(1.0 / 7.0))));
-  num = small ? s : d;
-  den = small ? poly : (la - lb);
-}
-
 // Chandrashekar's entropy-conserving, kinetic-energy-preserving two-point flux along the
-// (not normalised) vector n: F#(a, b; n), linear in n.  ce = 1/(2(gamma-1)).
+// (not normalised) vector n: F#(a, b; n), linear in n and symmetric in (a, b).  ce =
+// 1/(2(gamma-1)).  Logarithmic means (x_a - x_b)/(ln x_a - ln x_b) of rho and beta: near
+// x_a = x_b the cancelling logarithms are replaced by the series in
+// u = ((x_a - x_b)/(x_a + x_b))^2, (x_a + x_b)/(2(1 + u/3 + u^2/5 + u^3/7)).  The five
+// quotients of the flux share two reciprocals.
 template <typename T>
 __device__ __forceinline__ void flux_ec(const Prim<T>& a, const Prim<T>& b, T n1, T n2, T n3, T ce,
                                         T F[5]) {
-  T rn, rd, bn, bd;
-  logmean_nd(a.rho, b.rho, a.lrho, b.lrho, rn, rd);
-  logmean_nd(a.beta, b.beta, a.lbeta, b.lbeta, bn, bd);
-  const T rho_ln = rn / rd;
-  const T inv_bln = bd / bn;
+  const T thr = sizeof(T) == 8 ? (T)1e-4 : (T)1e-2;
+  const T dr = a.rho - b.rho, sr = a.rho + b.rho;
+  const T db = a.beta - b.beta, sb = a.beta + b.beta;
+  const T r1 = rcp(sr * sb);
+  const T isb = r1 * sr;                    // 1/(beta_a + beta_b)
+  const T fr = dr * (r1 * sb), fb = db * isb;
+  const T ur = fr * fr, ub = fb * fb;
+  const bool smr = ur < thr, smb = ub < thr;
+  const T numr = smr ? sr : dr;
+  const T denr = smr ? (T)2 * ((T)1 + ur * ((T)(1.0 / 3.0) + ur * ((T)0.2 + ur * (T)(1.0 / 7.0))))
+                     : (a.lrho - b.lrho);
+  const T numb = smb ? sb : db;
+  const T denb = smb ? (T)2 * ((T)1 + ub * ((T)(1.0 / 3.0) + ub * ((T)0.2 + ub * (T)(1.0 / 7.0))))
+                     : (a.lbeta - b.lbeta);
+  const T r2 = rcp(denr * numb);
+  const T rho_ln = numr * numb * r2;        // logmean(rho)
+  const T inv_bln = denb * denr * r2;       // 1 / logmean(beta)
+  const T phat = (T)0.5 * sr * isb;         // {rho} / (2 {beta})
   const T u = (T)0.5 * (a.v1 + b.v1), v = (T)0.5 * (a.v2 + b.v2), w = (T)0.5 * (a.v3 + b.v3);
   const T hb = (T)0.5 * (a.h + b.h);
-  const T phat = (a.rho + b.rho) / ((T)2 * (a.beta + b.beta));
   const T vn = u * n1 + v * n2 + w * n3;
   F[0] = rho_ln * vn;
   F[1] = F[0] * u + phat * n1;
@@ -159,20 +174,22 @@ __device__ __forceinline__ void face_flux(int kind, const double uL[5], const do
   }
   const T s1 = (T)S[0], s2 = (T)S[1], s3 = (T)S[2];
   const T area = sqrt(s1 * s1 + s2 * s2 + s3 * s3);
-  const T ia = (T)1 / area;
+  const T ia = rcp(area);
   const T n1 = s1 * ia, n2 = s2 * ia, n3 = s3 * ia;
-  T rL, vL[3], pL, EL, rR, vR[3], pR, ER;
+  T rL, vL[3], pL, EL, rR, vR[3], pR, ER, irL, irR;
   {
-    const double i = 1.0 / uL[0];
+    const double i = rcp(uL[0]);
     const double a1 = uL[1] * i, a2 = uL[2] * i, a3 = uL[3] * i;
     const double p = (gamma - 1.0) * (uL[4] - 0.5 * uL[0] * (a1 * a1 + a2 * a2 + a3 * a3));
     rL = (T)uL[0]; vL[0] = (T)a1; vL[1] = (T)a2; vL[2] = (T)a3; pL = (T)p; EL = (T)uL[4];
+    irL = (T)i;
   }
   {
-    const double i = 1.0 / uR[0];
+    const double i = rcp(uR[0]);
     const double a1 = uR[1] * i, a2 = uR[2] * i, a3 = uR[3] * i;
     const double p = (gamma - 1.0) * (uR[4] - 0.5 * uR[0] * (a1 * a1 + a2 * a2 + a3 * a3));
     rR = (T)uR[0]; vR[0] = (T)a1; vR[1] = (T)a2; vR[2] = (T)a3; pR = (T)p; ER = (T)uR[4];
+    irR = (T)i;
   }
   const T vnL = vL[0] * n1 + vL[1] * n2 + vL[2] * n3;
   const T vnR = vR[0] * n1 + vR[1] * n2 + vR[2] * n3;
@@ -194,8 +211,8 @@ __device__ __forceinline__ void face_flux(int kind, const double uL[5], const do
   }
   if (kind == 1) {  // local Lax-Friedrichs (Rusanov)
     const T g = (T)gamma;
-    const T lamL = fabs(vnL) + sqrt(g * pL / rL);
-    const T lamR = fabs(vnR) + sqrt(g * pR / rR);
+    const T lamL = fabs(vnL) + sqrt(g * pL * irL);
+    const T lamR = fabs(vnR) + sqrt(g * pR * irR);
     const T lam = lamL > lamR ? lamL : lamR;
     const T du[5] = {(T)(uR[0] - uL[0]), (T)(uR[1] - uL[1]), (T)(uR[2] - uL[2]), (T)(uR[3] - uL[3]),
                      (T)(uR[4] - uL[4])};
@@ -205,16 +222,16 @@ __device__ __forceinline__ void face_flux(int kind, const double uL[5], const do
   }
   // Roe: averages weighted by sqrt(rho); waves u_n - c, u_n (entropy + shear), u_n + c
   const T sL = sqrt(rL), sR = sqrt(rR);
-  const T iw = (T)1 / (sL + sR);
+  const T iw = rcp(sL + sR);
   const T u1 = (sL * vL[0] + sR * vR[0]) * iw;
   const T u2 = (sL * vL[1] + sR * vR[1]) * iw;
   const T u3 = (sL * vL[2] + sR * vR[2]) * iw;
-  const T H = (sL * (EL + pL) / rL + sR * (ER + pR) / rR) * iw;
+  const T H = (sL * (EL + pL) * irL + sR * (ER + pR) * irR) * iw;
   const T rho = sL * sR;
   const T q2 = u1 * u1 + u2 * u2 + u3 * u3;
   const T c2 = gm1 * (H - (T)0.5 * q2);
   const T c = sqrt(c2);
-  const T ic2 = (T)1 / c2;
+  const T ic2 = rcp(c2);
   const T vn = u1 * n1 + u2 * n2 + u3 * n3;
   const T dr = rR - rL, dp = pR - pL;
   const T dv1 = vR[0] - vL[0], dv2 = vR[1] - vL[1], dv3 = vR[2] - vL[2];
@@ -243,7 +260,7 @@ __device__ __forceinline__ void face_flux(int kind, const double uL[5], const do
 template <int n, typename T>
 __device__ __forceinline__ void gradient_and_viscous_flux(int t, int ti, int tj, int tk,
                                                           const double* sD, T iwN, T iw0,
-                                                          const T (*sG)[n * n * n],
+                                                          const T* const sG[4],
                                                           const T (*sJ)[4][n * n], const double ja[9],
                                                           double ij, T mu, T kappa, T Fvd[3][4]) {
   constexpr int N = n - 1, nf = n * n;
@@ -302,7 +319,7 @@ __device__ __forceinline__ void gradient_and_viscous_flux(int t, int ti, int tj,
 
 template <typename T>
 __device__ __forceinline__ void gvars(const double u[5], double gamma, T g[4]) {
-  const double i = 1.0 / u[0];
+  const double i = rcp(u[0]);
   const double a1 = u[1] * i, a2 = u[2] * i, a3 = u[3] * i;
   const double p = (gamma - 1.0) * (u[4] - 0.5 * u[0] * (a1 * a1 + a2 * a2 + a3 * a3));
   g[0] = (T)a1;
@@ -510,7 +527,8 @@ __global__ void __launch_bounds__(nthreads_for(N)) grad_kernel(View v, int cur) 
   if (act) {
     const T iwN = (T)(1.0 / sw[N]), iw0 = (T)(1.0 / sw[0]);
     T Fvd[3][4];
-    gradient_and_viscous_flux<n, T>(t, ti, tj, tk, sD, iwN, iw0, sG, sJ, ja, ij, (T)v.mu, (T)v.kappa,
+    const T* const gp[4] = {sG[0], sG[1], sG[2], sG[3]};
+    gradient_and_viscous_flux<n, T>(t, ti, tj, tk, sD, iwN, iw0, gp, sJ, ja, ij, (T)v.mu, (T)v.kappa,
                                     Fvd);
     T* Fvf = reinterpret_cast<T*>(v.Fvf) + (long)e * 6 * 4 * nf;
     const int ii[3] = {ti, tj, tk};
@@ -532,61 +550,78 @@ __global__ void __launch_bounds__(nthreads_for(N)) grad_kernel(View v, int cur) 
 // ------------------------------------------------------------------ stage kernel
 // Residual of one element and, in RK mode, the low-storage update
 //   dU <- A dU + dt R;  U_out <- U_in + B dU   (dU not read when A = 0).
+// LDS holds the primitive variables of the element, the metric components of the reference
+// direction being processed, the six face-flux grids, and one phase-dependent region (BR1
+// temperature and half jumps; one direction of the contravariant viscous flux; the two-point
+// fluxes of one direction).
+// occupancy target of the stage kernel: waves per SIMD the register allocation must allow
+__host__ __device__ constexpr int stage_waves_per_eu(int N) { return N <= 5 ? 3 : 2; }
+
 template <int N, typename T, bool VISC>
 __global__ void __launch_bounds__(nthreads_for(N))
+    __attribute__((amdgpu_waves_per_eu(stage_waves_per_eu(N))))
     stage_kernel(View v, int cur, double dt, double rkA, double rkB, int mode) {
   constexpr int n = N + 1, nn = n * n * n, nf = n * n, NT = nthreads_for(N);
+  constexpr int np = n * (n - 1) / 2;  // pairs (a < b) on one line of n nodes
+  constexpr int P = nf * np;           // pairs per direction
   const int e = block_element(v.E);
   const int t = threadIdx.x;
   const bool act = t < nn;
   const int ti = t % n, tj = (t / n) % n, tk = t / nf;
+  const int ii[3] = {ti, tj, tk};
   const double* __restrict__ Uin = v.U[cur];
 
   __shared__ double sD[n * n], sDh[n * n], sw[n];
-  __shared__ T sP[8][nn];
-  __shared__ T sJa[9][nn];
-  __shared__ T sF[6][5][nf];
-  // phase-dependent storage: {own state (double), g, half jumps} then {F~v}
-  constexpr int bytesA = 5 * nn * (int)sizeof(double) + (VISC ? (4 * nn + 24 * nf) * (int)sizeof(T) : 0);
-  constexpr int bytesB = VISC ? 12 * nn * (int)sizeof(T) : 0;
-  __shared__ __align__(16) char sRaw[bytesA > bytesB ? bytesA : bytesB];
-  double(*sU)[nn] = reinterpret_cast<double(*)[nn]>(sRaw);
-  T(*sG)[nn] = reinterpret_cast<T(*)[nn]>(sRaw + 5 * nn * sizeof(double));
-  T(*sJ)[4][nf] = reinterpret_cast<T(*)[4][nf]>(sRaw + 5 * nn * sizeof(double) + 4 * nn * sizeof(T));
-  T(*sFv)[4][nn] = reinterpret_cast<T(*)[4][nn]>(sRaw);
+  __shared__ T sP[7][nn];      // rho, v1, v2, v3, beta, ln rho, ln beta
+  __shared__ T sJa3[3][nn];    // Ja^d of the direction d being processed
+  __shared__ T sF[6][5][nf];   // face fluxes F~* - F~v*
+  __shared__ unsigned char sPa[np], sPb[np];
+  constexpr int bytesA = VISC ? (nn + 24 * nf) * (int)sizeof(T) : 0;
+  constexpr int bytesB = VISC ? 4 * nn * (int)sizeof(T) : 0;
+  constexpr int bytesC = 5 * P * (int)sizeof(T);
+  constexpr int bytesAB = bytesA > bytesB ? bytesA : bytesB;
+  __shared__ __align__(16) char sRaw[bytesAB > bytesC ? bytesAB : bytesC];
+  T* sT = reinterpret_cast<T*>(sRaw);                                   // temperature
+  T(*sJ)[4][nf] = reinterpret_cast<T(*)[4][nf]>(sRaw + nn * sizeof(T));  // half jumps of g
+  T(*sFv)[nn] = reinterpret_cast<T(*)[nn]>(sRaw);                      // F~v^d, 4 components
+  T(*sPair)[P] = reinterpret_cast<T(*)[P]>(sRaw);
 
   for (int x = t; x < n * n; x += NT) {
     sD[x] = v.tab[2 * n + x];
     sDh[x] = v.tab[2 * n + n * n + x];
   }
   if (t < n) sw[t] = v.tab[n + t];
+  if (t < np) {  // pair k -> (a, b), ordered by a then b
+    int a = 0, k = t;
+    while (k >= n - 1 - a) {
+      k -= n - 1 - a;
+      a++;
+    }
+    sPa[t] = (unsigned char)a;
+    sPb[t] = (unsigned char)(a + 1 + k);
+  }
   const long base = (long)e * nn;
-  double u[5], ja[9], ij = 0.0;
+  double ja[9], ij = 0.0;
   if (act) {
+    double u[5];
 #pragma unroll
-    for (int c = 0; c < 5; c++) {
-      u[c] = Uin[base * 5 + c * nn + t];
-      sU[c][t] = u[c];
-    }
-    const Prim<T> P = make_prim<T>(u, v.gamma);
-    sP[0][t] = P.rho; sP[1][t] = P.v1; sP[2][t] = P.v2; sP[3][t] = P.v3;
-    sP[4][t] = P.beta; sP[5][t] = P.lrho; sP[6][t] = P.lbeta; sP[7][t] = P.h;
+    for (int c = 0; c < 5; c++) u[c] = Uin[base * 5 + c * nn + t];
+    const Prim<T> Pr = make_prim<T>(u, v.gamma);
+    sP[0][t] = Pr.rho; sP[1][t] = Pr.v1; sP[2][t] = Pr.v2; sP[3][t] = Pr.v3;
+    sP[4][t] = Pr.beta; sP[5][t] = Pr.lrho; sP[6][t] = Pr.lbeta;
 #pragma unroll
-    for (int c = 0; c < 9; c++) {
-      ja[c] = v.Ja[base * 9 + c * nn + t];
-      sJa[c][t] = (T)ja[c];
-    }
+    for (int c = 0; c < 9; c++) ja[c] = v.Ja[base * 9 + c * nn + t];
     ij = v.invJ[base + t];
     if (VISC) {
       T g[4];
       gvars(u, v.gamma, g);
-#pragma unroll
-      for (int c = 0; c < 4; c++) sG[c][t] = g[c];
+      sT[t] = g[3];
     }
   }
   __syncthreads();
 
-  // ---- faces: numerical flux (minus the BR1 viscous flux) on the 6 (N+1)^2 face grids
+  // ---- faces: numerical flux (minus the BR1 viscous flux) on the 6 (N+1)^2 face grids.  Both
+  // elements of a face evaluate it from the same global values in the same argument order.
   const T* FvfAll = VISC ? reinterpret_cast<const T*>(v.Fvf) : nullptr;
   for (int x = t; x < 6 * nf; x += NT) {
     const int f = x / nf, q = x - f * nf;
@@ -599,7 +634,7 @@ __global__ void __launch_bounds__(nthreads_for(N))
 #pragma unroll
     for (int c = 0; c < 5; c++) {
       un[c] = Uin[(long)ne * nn * 5 + c * nn + inb];
-      const double uo = sU[c][io];
+      const double uo = Uin[base * 5 + c * nn + io];
       uL[c] = side ? uo : un[c];
       uR[c] = side ? un[c] : uo;
     }
@@ -614,8 +649,9 @@ __global__ void __launch_bounds__(nthreads_for(N))
       for (int c = 0; c < 4; c++) F[1 + c] -= (T)0.5 * (fo[c * nf + q] + fn[c * nf + q]);
       T gn[4];
       gvars(un, v.gamma, gn);
+      const T go[4] = {sP[1][io], sP[2][io], sP[3][io], sT[io]};
 #pragma unroll
-      for (int c = 0; c < 4; c++) sJ[f][c][q] = (T)0.5 * (gn[c] - sG[c][io]);
+      for (int c = 0; c < 4; c++) sJ[f][c][q] = (T)0.5 * (gn[c] - go[c]);
     }
 #pragma unroll
     for (int c = 0; c < 5; c++) sF[f][c][q] = F[c];
@@ -623,74 +659,91 @@ __global__ void __launch_bounds__(nthreads_for(N))
   __syncthreads();
 
   const T iwN = (T)(1.0 / sw[N]), iw0 = (T)(1.0 / sw[0]);
-  if (VISC) {
-    T Fvd[3][4];
-    if (act)
-      gradient_and_viscous_flux<n, T>(t, ti, tj, tk, sD, iwN, iw0, sG, sJ, ja, ij, (T)v.mu,
-                                      (T)v.kappa, Fvd);
-    __syncthreads();  // sG / sJ are overwritten by sFv below
-    if (act) {
-#pragma unroll
-      for (int d = 0; d < 3; d++)
-#pragma unroll
-        for (int c = 0; c < 4; c++) sFv[d][c][t] = Fvd[d][c];
-    }
-    __syncthreads();
-  }
-
-  if (!act) return;
-  const T ce = (T)(0.5 / (v.gamma - 1.0)), gm1 = (T)(v.gamma - 1.0);
-  Prim<T> Pi;
-  Pi.rho = sP[0][t]; Pi.v1 = sP[1][t]; Pi.v2 = sP[2][t]; Pi.v3 = sP[3][t];
-  Pi.beta = sP[4][t]; Pi.lrho = sP[5][t]; Pi.lbeta = sP[6][t]; Pi.h = sP[7][t];
   T acc[5] = {0, 0, 0, 0, 0};
-  T accv[4] = {0, 0, 0, 0};
-  const int ii[3] = {ti, tj, tk};
-#pragma unroll
-  for (int d = 0; d < 3; d++) {
-    const int id = ii[d];
-    const int stride = d == 0 ? 1 : (d == 1 ? n : nf);
-    const int b0 = t - id * stride;
-    const T m1 = sJa[3 * d][t], m2 = sJa[3 * d + 1][t], m3 = sJa[3 * d + 2][t];
-#pragma unroll
-    for (int m = 0; m < n; m++) {
-      if (m == id) continue;
-      const int tm = b0 + m * stride;
-      Prim<T> Pm;
-      Pm.rho = sP[0][tm]; Pm.v1 = sP[1][tm]; Pm.v2 = sP[2][tm]; Pm.v3 = sP[3][tm];
-      Pm.beta = sP[4][tm]; Pm.lrho = sP[5][tm]; Pm.lbeta = sP[6][tm]; Pm.h = sP[7][tm];
-      T F[5];
-      vol_flux<T>(v.vol, Pi, Pm, m1 + sJa[3 * d][tm], m2 + sJa[3 * d + 1][tm], m3 + sJa[3 * d + 2][tm],
-                  ce, gm1, F);
-      const T Dm = (T)sD[id * n + m];
-#pragma unroll
-      for (int c = 0; c < 5; c++) acc[c] += Dm * F[c];
+  if (VISC) {
+    // BR1 gradient and contravariant viscous flux of this node, then sum_m Dhat_im F~v^d_m
+    T Fvd[3][4];
+    if (act) {
+      const T* const gp[4] = {sP[1], sP[2], sP[3], sT};
+      gradient_and_viscous_flux<n, T>(t, ti, tj, tk, sD, iwN, iw0, gp, sJ, ja, ij, (T)v.mu,
+                                      (T)v.kappa, Fvd);
     }
-    if (VISC) {
 #pragma unroll
-      for (int m = 0; m < n; m++) {
-        const T Dh = (T)sDh[id * n + m];
+    for (int d = 0; d < 3; d++) {
+      __syncthreads();  // previous users of the phase region are done
+      if (act) {
 #pragma unroll
-        for (int c = 0; c < 4; c++) accv[c] += Dh * sFv[d][c][b0 + m * stride];
+        for (int c = 0; c < 4; c++) sFv[c][t] = Fvd[d][c];
+      }
+      __syncthreads();
+      if (act) {
+        const int id = ii[d];
+        const int stride = d == 0 ? 1 : (d == 1 ? n : nf);
+        const int b0 = t - id * stride;
+#pragma unroll
+        for (int m = 0; m < n; m++) {
+          const T Dh = (T)sDh[id * n + m];
+#pragma unroll
+          for (int c = 0; c < 4; c++) acc[1 + c] -= Dh * sFv[c][b0 + m * stride];
+        }
       }
     }
-    const int qd = d == 0 ? tj + n * tk : (d == 1 ? ti + n * tk : ti + n * tj);
-    if (id == N) {
+  }
+
+  // ---- volume: split-form sums; each pair of a line is evaluated once and used by both nodes
+  const T ce = (T)(0.5 / (v.gamma - 1.0)), gm1 = (T)(v.gamma - 1.0);
+  for (int d = 0; d < 3; d++) {
+    const int stride = d == 0 ? 1 : (d == 1 ? n : nf);
+    __syncthreads();  // previous users of sJa3 / the phase region are done
+    if (act) {
 #pragma unroll
-      for (int c = 0; c < 5; c++) acc[c] += iwN * sF[2 * d + 1][c][qd];
+      for (int c = 0; c < 3; c++) sJa3[c][t] = (T)ja[3 * d + c];
     }
-    if (id == 0) {
+    __syncthreads();
+    for (int s = t; s < P; s += NT) {
+      const int line = s / np, k = s - line * np;
+      const int b0 = d == 0 ? n * line : (d == 1 ? line % n + nf * (line / n) : line);
+      const int na = b0 + sPa[k] * stride, nb = b0 + sPb[k] * stride;
+      Prim<T> A, B;
+      A.rho = sP[0][na]; A.v1 = sP[1][na]; A.v2 = sP[2][na]; A.v3 = sP[3][na];
+      A.beta = sP[4][na]; A.lrho = sP[5][na]; A.lbeta = sP[6][na];
+      A.h = (T)0.5 * (A.v1 * A.v1 + A.v2 * A.v2 + A.v3 * A.v3);
+      B.rho = sP[0][nb]; B.v1 = sP[1][nb]; B.v2 = sP[2][nb]; B.v3 = sP[3][nb];
+      B.beta = sP[4][nb]; B.lrho = sP[5][nb]; B.lbeta = sP[6][nb];
+      B.h = (T)0.5 * (B.v1 * B.v1 + B.v2 * B.v2 + B.v3 * B.v3);
+      T F[5];
+      vol_flux<T>(v.vol, A, B, sJa3[0][na] + sJa3[0][nb], sJa3[1][na] + sJa3[1][nb],
+                  sJa3[2][na] + sJa3[2][nb], ce, gm1, F);
 #pragma unroll
-      for (int c = 0; c < 5; c++) acc[c] -= iw0 * sF[2 * d][c][qd];
+      for (int c = 0; c < 5; c++) sPair[c][s] = F[c];
+    }
+    __syncthreads();
+    if (act) {
+      const int id = ii[d];
+      const int line = d == 0 ? tj + n * tk : (d == 1 ? ti + n * tk : ti + n * tj);
+#pragma unroll
+      for (int m = 0; m < n; m++) {
+        if (m == id) continue;
+        const int a = m < id ? m : id, b = m < id ? id : m;
+        const int k = line * np + a * (2 * n - a - 1) / 2 + (b - a - 1);
+        const T Dm = (T)sD[id * n + m];
+#pragma unroll
+        for (int c = 0; c < 5; c++) acc[c] += Dm * sPair[c][k];
+      }
+      if (id == N) {
+#pragma unroll
+        for (int c = 0; c < 5; c++) acc[c] += iwN * sF[2 * d + 1][c][line];
+      }
+      if (id == 0) {
+#pragma unroll
+        for (int c = 0; c < 5; c++) acc[c] -= iw0 * sF[2 * d][c][line];
+      }
     }
   }
+  if (!act) return;
   double R[5];
 #pragma unroll
-  for (int c = 0; c < 5; c++) {
-    T jr = -acc[c];
-    if (VISC && c > 0) jr += accv[c - 1];
-    R[c] = (double)jr * ij;
-  }
+  for (int c = 0; c < 5; c++) R[c] = -(double)acc[c] * ij;
   const long o = base * 5 + t;
   if (mode == kModeResidual) {
 #pragma unroll
@@ -702,7 +755,7 @@ __global__ void __launch_bounds__(nthreads_for(N))
   for (int c = 0; c < 5; c++) {
     const double du = (rkA == 0.0 ? 0.0 : rkA * v.dU[o + c * nn]) + dt * R[c];
     v.dU[o + c * nn] = du;
-    Uout[o + c * nn] = u[c] + rkB * du;
+    Uout[o + c * nn] = Uin[o + c * nn] + rkB * du;
   }
 }
 
