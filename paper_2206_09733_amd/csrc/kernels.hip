@@ -68,6 +68,16 @@ __device__ __forceinline__ double rcp(double x) {
 }
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// 1/sqrt(x) of a positive, finite, normal operand: hardware estimate refined by two Newton steps
+__device__ __forceinline__ double rsq(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  double e = fma(-x * r, r, 1.0);
+  r = fma(0.5 * r, e, r);
+  e = fma(-x * r, r, 1.0);
+  return fma(0.5 * r, e, r);
+}
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
 // ------------------------------------------------------------------ physics helpers
 template <typename T>
 struct Prim {
@@ -173,8 +183,9 @@ __device__ __forceinline__ void face_flux(int kind, const double uL[5], const do
     return;
   }
   const T s1 = (T)S[0], s2 = (T)S[1], s3 = (T)S[2];
-  const T area = sqrt(s1 * s1 + s2 * s2 + s3 * s3);
-  const T ia = rcp(area);
+  const T a2s = s1 * s1 + s2 * s2 + s3 * s3;
+  const T ia = rsq(a2s);
+  const T area = a2s * ia;
   const T n1 = s1 * ia, n2 = s2 * ia, n3 = s3 * ia;
   T rL, vL[3], pL, EL, rR, vR[3], pR, ER, irL, irR;
   {
@@ -193,45 +204,45 @@ __device__ __forceinline__ void face_flux(int kind, const double uL[5], const do
   }
   const T vnL = vL[0] * n1 + vL[1] * n2 + vL[2] * n3;
   const T vnR = vR[0] * n1 + vR[1] * n2 + vR[2] * n3;
-  T FL[5], FR[5];
-  FL[0] = rL * vnL;
-  FR[0] = rR * vnR;
-  FL[1] = FL[0] * vL[0] + pL * n1;
-  FL[2] = FL[0] * vL[1] + pL * n2;
-  FL[3] = FL[0] * vL[2] + pL * n3;
-  FR[1] = FR[0] * vR[0] + pR * n1;
-  FR[2] = FR[0] * vR[1] + pR * n2;
-  FR[3] = FR[0] * vR[2] + pR * n3;
-  FL[4] = (EL + pL) * vnL;
-  FR[4] = (ER + pR) * vnR;
+  const T HL = (EL + pL) * irL, HR = (ER + pR) * irR;
+  T Fs[5];  // F(uL).n + F(uR).n
+  Fs[0] = rL * vnL + rR * vnR;
+  Fs[1] = rL * vnL * vL[0] + rR * vnR * vR[0] + (pL + pR) * n1;
+  Fs[2] = rL * vnL * vL[1] + rR * vnR * vR[1] + (pL + pR) * n2;
+  Fs[3] = rL * vnL * vL[2] + rR * vnR * vR[2] + (pL + pR) * n3;
+  Fs[4] = rL * HL * vnL + rR * HR * vnR;
   if (kind == 3) {  // central
 #pragma unroll
-    for (int c = 0; c < 5; c++) F[c] = area * (T)0.5 * (FL[c] + FR[c]);
+    for (int c = 0; c < 5; c++) F[c] = (T)0.5 * area * Fs[c];
     return;
   }
   if (kind == 1) {  // local Lax-Friedrichs (Rusanov)
     const T g = (T)gamma;
-    const T lamL = fabs(vnL) + sqrt(g * pL * irL);
-    const T lamR = fabs(vnR) + sqrt(g * pR * irR);
+    const T cL2 = g * pL * irL, cR2 = g * pR * irR;
+    const T lamL = fabs(vnL) + cL2 * rsq(cL2);
+    const T lamR = fabs(vnR) + cR2 * rsq(cR2);
     const T lam = lamL > lamR ? lamL : lamR;
     const T du[5] = {(T)(uR[0] - uL[0]), (T)(uR[1] - uL[1]), (T)(uR[2] - uL[2]), (T)(uR[3] - uL[3]),
                      (T)(uR[4] - uL[4])};
 #pragma unroll
-    for (int c = 0; c < 5; c++) F[c] = area * (T)0.5 * (FL[c] + FR[c] - lam * du[c]);
+    for (int c = 0; c < 5; c++) F[c] = (T)0.5 * area * (Fs[c] - lam * du[c]);
     return;
   }
-  // Roe: averages weighted by sqrt(rho); waves u_n - c, u_n (entropy + shear), u_n + c
-  const T sL = sqrt(rL), sR = sqrt(rR);
-  const T iw = rcp(sL + sR);
-  const T u1 = (sL * vL[0] + sR * vR[0]) * iw;
-  const T u2 = (sL * vL[1] + sR * vR[1]) * iw;
-  const T u3 = (sL * vL[2] + sR * vR[2]) * iw;
-  const T H = (sL * (EL + pL) * irL + sR * (ER + pR) * irR) * iw;
-  const T rho = sL * sR;
+  // Roe: averages weighted by sqrt(rho), in the form (qL + Q qR)/(1 + Q), Q = sqrt(rhoR/rhoL);
+  // waves u_n - c, u_n (entropy and shear), u_n + c
+  const T x = rR * irL;
+  const T Q = x * rsq(x);
+  const T iw = rcp((T)1 + Q);
+  const T u1 = (vL[0] + Q * vR[0]) * iw;
+  const T u2 = (vL[1] + Q * vR[1]) * iw;
+  const T u3 = (vL[2] + Q * vR[2]) * iw;
+  const T H = (HL + Q * HR) * iw;
+  const T rho = rL * Q;
   const T q2 = u1 * u1 + u2 * u2 + u3 * u3;
   const T c2 = gm1 * (H - (T)0.5 * q2);
-  const T c = sqrt(c2);
-  const T ic2 = rcp(c2);
+  const T rc = rsq(c2);
+  const T c = c2 * rc;
+  const T ic2 = rc * rc;
   const T vn = u1 * n1 + u2 * n2 + u3 * n3;
   const T dr = rR - rL, dp = pR - pL;
   const T dv1 = vR[0] - vL[0], dv2 = vR[1] - vL[1], dv3 = vR[2] - vL[2];
@@ -250,7 +261,7 @@ __device__ __forceinline__ void face_flux(int kind, const double uL[5], const do
   W[3] = w1 * (u3 - c * n3) + l2 * (a2 * u3 + rho * t3) + w3 * (u3 + c * n3);
   W[4] = w1 * (H - vn * c) + l2 * (a2 * (T)0.5 * q2 + rho * udt) + w3 * (H + vn * c);
 #pragma unroll
-  for (int k = 0; k < 5; k++) F[k] = area * (T)0.5 * (FL[k] + FR[k] - W[k]);
+  for (int k = 0; k < 5; k++) F[k] = (T)0.5 * area * (Fs[k] - W[k]);
 }
 
 // ------------------------------------------------------------------ BR1 gradient + viscous flux
@@ -494,7 +505,6 @@ __global__ void __launch_bounds__(nthreads_for(N)) grad_kernel(View v, int cur) 
   for (int x = t; x < n * n; x += NT) sD[x] = v.tab[2 * n + x];
   if (t < n) sw[t] = v.tab[n + t];
   const long base = (long)e * nn;
-  double ja[9], ij = 0.0;
   if (act) {
     double u[5];
 #pragma unroll
@@ -503,9 +513,6 @@ __global__ void __launch_bounds__(nthreads_for(N)) grad_kernel(View v, int cur) 
     gvars(u, v.gamma, g);
 #pragma unroll
     for (int c = 0; c < 4; c++) sG[c][t] = g[c];
-#pragma unroll
-    for (int c = 0; c < 9; c++) ja[c] = v.Ja[base * 9 + c * nn + t];
-    ij = v.invJ[base + t];
   }
   __syncthreads();
   for (int x = t; x < 6 * nf; x += NT) {
@@ -525,6 +532,10 @@ __global__ void __launch_bounds__(nthreads_for(N)) grad_kernel(View v, int cur) 
   }
   __syncthreads();
   if (act) {
+    double ja[9];
+#pragma unroll
+    for (int c = 0; c < 9; c++) ja[c] = v.Ja[base * 9 + c * nn + t];
+    const double ij = v.invJ[base + t];
     const T iwN = (T)(1.0 / sw[N]), iw0 = (T)(1.0 / sw[0]);
     T Fvd[3][4];
     const T* const gp[4] = {sG[0], sG[1], sG[2], sG[3]};
@@ -621,7 +632,8 @@ __global__ void __launch_bounds__(nthreads_for(N))
   __syncthreads();
 
   // ---- faces: numerical flux (minus the BR1 viscous flux) on the 6 (N+1)^2 face grids.  Both
-  // elements of a face evaluate it from the same global values in the same argument order.
+  // elements of a face evaluate it from the same global values in the same argument order, so
+  // it is single-valued.
   const T* FvfAll = VISC ? reinterpret_cast<const T*>(v.Fvf) : nullptr;
   for (int x = t; x < 6 * nf; x += NT) {
     const int f = x / nf, q = x - f * nf;
