@@ -147,6 +147,21 @@ hipError_t run_stage(dg_solver* s, double dt, double a, double b, int mode) {
   return timed(s, DG_K_STAGE, [&] { return dg::launch_stage(s->v, s->cur, dt, a, b, mode, s->stream); });
 }
 
+// FP32-bulk reference state: volume means of density and pressure of the state just set
+// (any constant is exact; the closer to the state, the smaller the deviations).
+int update_reference(dg_solver* s) {
+  if (!s->v.fp32) return DG_OK;
+  double h[dg::kDiagSlots];
+  DG_HIP(dg::launch_diagnostics(s->v, s->cur, s->stream), "reference-state reduction");
+  DG_HIP(hipMemcpyAsync(h, s->v.diag, sizeof(h), hipMemcpyDeviceToHost, s->stream), "reference state");
+  DG_HIP(hipStreamSynchronize(s->stream), "reference state");
+  if (!(h[13] > 0) || !(h[0] > 0) || !(h[14] > 0) || !std::isfinite(h[0]) || !std::isfinite(h[14]))
+    return fail(DG_ENONFINITE, "state has no positive finite mean density and pressure");
+  s->v.rho_r = h[0] / h[13];
+  s->v.p_r = h[14] / h[13];
+  return DG_OK;
+}
+
 int check_bound(const dg_solver* s) {
   if (!s) return fail(DG_EINVAL, "NULL solver");
   if (!s->bound) return fail(DG_ESTATE, "solver is not bound to device memory (dg_solver_bind)");
@@ -237,6 +252,8 @@ int dg_solver_create(const dg_mesh* m, const dg_physics* p, dg_solver** out) {
   v.vol = p->vol_flux;
   v.surf = p->surf_flux;
   v.fp32 = p->precision == DG_FP32_BULK ? 1 : 0;
+  v.rho_r = 1.0;
+  v.p_r = 1.0 / (p->gamma * p->Ma * p->Ma);
   *out = s;
   return DG_OK;
 }
@@ -314,7 +331,7 @@ int dg_set_initial_condition(dg_solver* s, int ic, const double* params) {
     return fail(DG_EINVAL, "uniform state needs rho > 0 and p > 0");
   DG_HIP(timed(s, DG_K_OTHER, [&] { return dg::launch_ic(s->v, s->cur, ic, P, s->stream); }),
          "initial-condition kernel");
-  return DG_OK;
+  return update_reference(s);
 }
 
 int dg_set_state(dg_solver* s, const double* host_U, size_t n) {
@@ -328,7 +345,7 @@ int dg_set_state(dg_solver* s, const double* host_U, size_t n) {
          "upload state");
   DG_HIP(hipMemsetAsync(s->v.dU, 0, sizeof(double) * n, s->stream), "clear RK register");
   DG_HIP(hipStreamSynchronize(s->stream), "upload state");
-  return DG_OK;
+  return update_reference(s);
 }
 
 int dg_get_state(dg_solver* s, double* host_U, size_t n) {

@@ -34,6 +34,7 @@ struct View {
   double lo[3], h[3];
   double gamma, mu, kappa, Ma;
   int vol, surf, viscous, fp32;
+  double rho_r, p_r;  // FP32-bulk reference state (mean density and pressure of the state set)
   const int* nbr; // [E][6] neighbour across face f = 2 d + side (side 1: xi_d = +1)
   const double* tab;
   double* X;      // [E][3][nn]   node coordinates

@@ -264,6 +264,227 @@ __device__ __forceinline__ void face_flux(int kind, const double uL[5], const do
   for (int k = 0; k < 5; k++) F[k] = (T)0.5 * area * (Fs[k] - W[k]);
 }
 
+// ------------------------------------------------------------------ FP32-bulk: deviation form
+// With FP32 arithmetic the fluxes are formed as deviations from a constant reference state
+// (rho_r, p_r), because at low Mach number p and rho e are large constants plus small
+// variations.  Both changes below are exact in exact arithmetic:
+//  - the momentum flux loses its constant part p_r n: a constant flux proportional to the metric
+//    terms has zero residual (discrete metric identities, SBP lift);
+//  - the energy flux is split as H_r F_rho + F'_E with H_r = gamma p_r/((gamma-1) rho_r); the
+//    residual is linear in the fluxes, so R_E = H_r R_rho + R'_E, recombined in FP64.
+// Per-node inputs are formed in FP64 and rounded: x = rho/rho_r - 1, y = beta/beta_r - 1,
+// lx = ln(rho/rho_r), ly = ln(beta/beta_r) (beta = rho/(2p)), so that every quantity entering
+// the FP32 arithmetic is either O(1) or a small deviation carried at full relative precision.
+struct Ref {
+  double rho, p;  // reference density and pressure
+  double c;       // p/((gamma-1) rho)  = 1/(2 (gamma-1) beta_r)
+  double por;     // p/rho
+  double H;       // c + por, reference total enthalpy at rest
+};
+
+__device__ __forceinline__ Ref make_ref(double rho_r, double p_r, double gamma) {
+  Ref r;
+  r.rho = rho_r;
+  r.p = p_r;
+  r.por = p_r / rho_r;
+  r.c = r.por / (gamma - 1.0);
+  r.H = r.c + r.por;
+  return r;
+}
+
+// primitive deviations stored in the Prim fields: rho <- x, beta <- y, lrho <- lx, lbeta <- ly
+template <typename T>
+__device__ __forceinline__ Prim<T> make_prim_dev(const double u[5], double gamma, const Ref& R) {
+  const double inv = rcp(u[0]);
+  const double v1 = u[1] * inv, v2 = u[2] * inv, v3 = u[3] * inv;
+  const double h = 0.5 * (v1 * v1 + v2 * v2 + v3 * v3);
+  const double p = (gamma - 1.0) * (u[4] - u[0] * h);
+  const double rr = u[0] / R.rho;          // rho / rho_r
+  const double bb = rr * R.p * rcp(p);     // beta / beta_r = (rho / rho_r)(p_r / p)
+  Prim<T> o;
+  o.rho = (T)(rr - 1.0);
+  o.beta = (T)(bb - 1.0);
+  o.lrho = (T)log(rr);
+  o.lbeta = (T)log(bb);
+  o.v1 = (T)v1;
+  o.v2 = (T)v2;
+  o.v3 = (T)v3;
+  o.h = (T)h;
+  return o;
+}
+
+// logarithmic mean of (1 + xa, 1 + xb) as 1 + lam, lam formed without cancellation
+// (la, lb = ln(1 + xa), ln(1 + xb))
+template <typename T>
+__device__ __forceinline__ T logmean_dev(T xa, T xb, T la, T lb) {
+  const T d = xa - xb, w = (T)2 + xa + xb;
+  const T u = d * d * rcp(w * w);
+  const T thr = sizeof(T) == 8 ? (T)1e-4 : (T)1e-2;
+  if (u < thr) {
+    const T pm1 = u * ((T)(1.0 / 3.0) + u * ((T)0.2 + u * (T)(1.0 / 7.0)));
+    return ((T)0.5 * (xa + xb) - pm1) * rcp((T)1 + pm1);
+  }
+  const T dl = la - lb;
+  return (d - dl) * rcp(dl);
+}
+
+// Chandrashekar's flux in deviation form: F[0] = F_rho, F[1..3] = F_m - p_r n,
+// F[4] = F_E - H_r F_rho
+// vn64 = {v}.n formed in FP64 (the mass flux is carried in FP64, see the stage kernel)
+template <typename T>
+__device__ __forceinline__ void flux_ec_dev(const Prim<T>& a, const Prim<T>& b, T n1, T n2, T n3,
+                                            double vn64, const Ref& R, T F[5], double& F0d) {
+  const T lr = logmean_dev(a.rho, b.rho, a.lrho, b.lrho);   // rho_ln = rho_r (1 + lr)
+  const T lb = logmean_dev(a.beta, b.beta, a.lbeta, b.lbeta);  // beta_ln = beta_r (1 + lb)
+  const T xb = (T)0.5 * (a.rho + b.rho), yb = (T)0.5 * (a.beta + b.beta);
+  const T dphat = (T)R.p * (xb - yb) * rcp((T)1 + yb);       // {rho}/(2{beta}) - p_r
+  const T u = (T)0.5 * (a.v1 + b.v1), v = (T)0.5 * (a.v2 + b.v2), w = (T)0.5 * (a.v3 + b.v3);
+  const T hb = (T)0.5 * (a.h + b.h);
+  const T vn = u * n1 + v * n2 + w * n3;
+  F0d = R.rho * (1.0 + (double)lr) * vn64;
+  F[0] = (T)F0d;
+  F[1] = F[0] * u + dphat * n1;
+  F[2] = F[0] * v + dphat * n2;
+  F[3] = F[0] * w + dphat * n3;
+  const T kin = u * u + v * v + w * w - hb;
+  F[4] = F[0] * (kin - (T)R.c * lb * rcp((T)1 + lb) - (T)R.por * lr * rcp((T)1 + lr)) + dphat * vn;
+}
+
+// central two-point flux in deviation form
+template <typename T>
+__device__ __forceinline__ void flux_central_dev(const Prim<T>& a, const Prim<T>& b, T n1, T n2, T n3,
+                                                 const double va[3], const double vb[3], const double m[3],
+                                                 const Ref& R, T F[5], double& F0d) {
+  T Fa[5], Fb[5];
+  const Prim<T>* s[2] = {&a, &b};
+  T* o[2] = {Fa, Fb};
+#pragma unroll
+  for (int q = 0; q < 2; q++) {
+    const Prim<T>& P = *s[q];
+    const T iy = rcp((T)1 + P.beta);
+    const T rho = (T)R.rho * ((T)1 + P.rho);
+    const T dp = (T)R.p * (P.rho - P.beta) * iy;        // p - p_r
+    const T dH = -(T)R.H * P.beta * iy + P.h;           // H - H_r
+    const T vn = P.v1 * n1 + P.v2 * n2 + P.v3 * n3;
+    o[q][0] = rho * vn;
+    o[q][1] = o[q][0] * P.v1 + dp * n1;
+    o[q][2] = o[q][0] * P.v2 + dp * n2;
+    o[q][3] = o[q][0] * P.v3 + dp * n3;
+    o[q][4] = o[q][0] * dH;
+  }
+#pragma unroll
+  for (int c = 0; c < 5; c++) F[c] = (T)0.5 * (Fa[c] + Fb[c]);
+  const double ra = R.rho * (1.0 + (double)a.rho), rb = R.rho * (1.0 + (double)b.rho);
+  F0d = 0.5 * (ra * (va[0] * m[0] + va[1] * m[1] + va[2] * m[2]) +
+               rb * (vb[0] * m[0] + vb[1] * m[1] + vb[2] * m[2]));
+  F[0] = (T)F0d;
+}
+
+// face numerical flux in deviation form (same fluxes as face_flux, same component meaning as
+// flux_ec_dev)
+template <typename T>
+__device__ __forceinline__ void face_flux_dev(int kind, const double uL[5], const double uR[5],
+                                              const double S[3], double gamma, const Ref& R, T F[5],
+                                              double& F0d) {
+  // FP64 parts: the central mass flux (F(uL) + F(uR))_rho . S / 2
+  const double mS = 0.5 * ((uL[1] * rcp(uL[0]) + uR[1] * rcp(uR[0])) * S[0] +
+                           (uL[2] * rcp(uL[0]) + uR[2] * rcp(uR[0])) * S[1] +
+                           (uL[3] * rcp(uL[0]) + uR[3] * rcp(uR[0])) * S[2]);
+  if (kind == 2) {
+    const Prim<T> a = make_prim_dev<T>(uL, gamma, R), b = make_prim_dev<T>(uR, gamma, R);
+    flux_ec_dev(a, b, (T)S[0], (T)S[1], (T)S[2], mS, R, F, F0d);
+    return;
+  }
+  const double cm = 0.5 * ((uL[1] + uR[1]) * S[0] + (uL[2] + uR[2]) * S[1] + (uL[3] + uR[3]) * S[2]);
+  const T gm1 = (T)(gamma - 1.0);
+  const T s1 = (T)S[0], s2 = (T)S[1], s3 = (T)S[2];
+  const T a2s = s1 * s1 + s2 * s2 + s3 * s3;
+  const T ia = rsq(a2s);
+  const T area = a2s * ia;
+  const T n1 = s1 * ia, n2 = s2 * ia, n3 = s3 * ia;
+  T rL, vL[3], dpL, dHL, irL, rR, vR[3], dpR, dHR, irR;
+  {
+    const double i = rcp(uL[0]);
+    const double a1 = uL[1] * i, a2 = uL[2] * i, a3 = uL[3] * i;
+    const double p = (gamma - 1.0) * (uL[4] - 0.5 * uL[0] * (a1 * a1 + a2 * a2 + a3 * a3));
+    rL = (T)uL[0]; vL[0] = (T)a1; vL[1] = (T)a2; vL[2] = (T)a3; irL = (T)i;
+    dpL = (T)(p - R.p);
+    dHL = (T)((uL[4] + p) * i - R.H);
+  }
+  {
+    const double i = rcp(uR[0]);
+    const double a1 = uR[1] * i, a2 = uR[2] * i, a3 = uR[3] * i;
+    const double p = (gamma - 1.0) * (uR[4] - 0.5 * uR[0] * (a1 * a1 + a2 * a2 + a3 * a3));
+    rR = (T)uR[0]; vR[0] = (T)a1; vR[1] = (T)a2; vR[2] = (T)a3; irR = (T)i;
+    dpR = (T)(p - R.p);
+    dHR = (T)((uR[4] + p) * i - R.H);
+  }
+  const T vnL = vL[0] * n1 + vL[1] * n2 + vL[2] * n3;
+  const T vnR = vR[0] * n1 + vR[1] * n2 + vR[2] * n3;
+  T Fs[5];
+  Fs[0] = rL * vnL + rR * vnR;
+  Fs[1] = rL * vnL * vL[0] + rR * vnR * vR[0] + (dpL + dpR) * n1;
+  Fs[2] = rL * vnL * vL[1] + rR * vnR * vR[1] + (dpL + dpR) * n2;
+  Fs[3] = rL * vnL * vL[2] + rR * vnR * vR[2] + (dpL + dpR) * n3;
+  Fs[4] = rL * vnL * dHL + rR * vnR * dHR;
+  if (kind == 3) {
+#pragma unroll
+    for (int c = 0; c < 5; c++) F[c] = (T)0.5 * area * Fs[c];
+    F0d = cm;
+    F[0] = (T)F0d;
+    return;
+  }
+  if (kind == 1) {
+    const T g = (T)gamma;
+    const T pL = (T)R.p + dpL, pR = (T)R.p + dpR;
+    const T cL2 = g * pL * irL, cR2 = g * pR * irR;
+    const T lamL = fabs(vnL) + cL2 * rsq(cL2);
+    const T lamR = fabs(vnR) + cR2 * rsq(cR2);
+    const T lam = lamL > lamR ? lamL : lamR;
+    const T du[5] = {(T)(uR[0] - uL[0]), (T)(uR[1] - uL[1]), (T)(uR[2] - uL[2]), (T)(uR[3] - uL[3]),
+                     (T)((uR[4] - uL[4]) - R.H * (uR[0] - uL[0]))};
+#pragma unroll
+    for (int c = 0; c < 5; c++) F[c] = (T)0.5 * area * (Fs[c] - lam * du[c]);
+    F0d = cm - 0.5 * (double)(area * lam) * (uR[0] - uL[0]);
+    F[0] = (T)F0d;
+    return;
+  }
+  const T x = rR * irL;
+  const T Q = x * rsq(x);
+  const T iw = rcp((T)1 + Q);
+  const T u1 = (vL[0] + Q * vR[0]) * iw;
+  const T u2 = (vL[1] + Q * vR[1]) * iw;
+  const T u3 = (vL[2] + Q * vR[2]) * iw;
+  const T dH = (dHL + Q * dHR) * iw;  // Roe-averaged H - H_r
+  const T rho = rL * Q;
+  const T q2 = u1 * u1 + u2 * u2 + u3 * u3;
+  const T c2 = gm1 * ((T)R.H + dH - (T)0.5 * q2);
+  const T rc = rsq(c2);
+  const T c = c2 * rc;
+  const T ic2 = rc * rc;
+  const T vn = u1 * n1 + u2 * n2 + u3 * n3;
+  const T dr = rR - rL, dp = dpR - dpL;
+  const T dv1 = vR[0] - vL[0], dv2 = vR[1] - vL[1], dv3 = vR[2] - vL[2];
+  const T dvn = dv1 * n1 + dv2 * n2 + dv3 * n3;
+  const T a1 = (T)0.5 * (dp - rho * c * dvn) * ic2;
+  const T a2 = dr - dp * ic2;
+  const T a3 = (T)0.5 * (dp + rho * c * dvn) * ic2;
+  const T l1 = fabs(vn - c), l2 = fabs(vn), l3 = fabs(vn + c);
+  const T t1 = dv1 - dvn * n1, t2 = dv2 - dvn * n2, t3 = dv3 - dvn * n3;
+  const T udt = u1 * t1 + u2 * t2 + u3 * t3;
+  const T w1 = l1 * a1, w3 = l3 * a3;
+  T W[5];
+  W[0] = w1 + l2 * a2 + w3;
+  W[1] = w1 * (u1 - c * n1) + l2 * (a2 * u1 + rho * t1) + w3 * (u1 + c * n1);
+  W[2] = w1 * (u2 - c * n2) + l2 * (a2 * u2 + rho * t2) + w3 * (u2 + c * n2);
+  W[3] = w1 * (u3 - c * n3) + l2 * (a2 * u3 + rho * t3) + w3 * (u3 + c * n3);
+  W[4] = w1 * (dH - vn * c) + l2 * (a2 * ((T)0.5 * q2 - (T)R.H) + rho * udt) + w3 * (dH + vn * c);
+#pragma unroll
+  for (int k = 0; k < 5; k++) F[k] = (T)0.5 * area * (Fs[k] - W[k]);
+  F0d = cm - 0.5 * (double)(area * W[0]);
+  F[0] = (T)F0d;
+}
+
 // ------------------------------------------------------------------ BR1 gradient + viscous flux
 // Lifted gradient of g = (v1, v2, v3, T) at this lane's node and the contravariant viscous
 // flux F~v^d = sum_x Ja^d_x Fv_x (momentum 1..3, energy) in each reference direction d.
@@ -328,15 +549,17 @@ __device__ __forceinline__ void gradient_and_viscous_flux(int t, int ti, int tj,
       Fvd[d][c] = (T)ja[3 * d] * Fv[0][c] + (T)ja[3 * d + 1] * Fv[1][c] + (T)ja[3 * d + 2] * Fv[2][c];
 }
 
+// g = (v1, v2, v3, T - T_ref): only differences and gradients of g enter BR1, so the constant
+// T_ref (0 in FP64, p_r/rho_r in FP32-bulk) changes nothing but the rounding of T
 template <typename T>
-__device__ __forceinline__ void gvars(const double u[5], double gamma, T g[4]) {
+__device__ __forceinline__ void gvars(const double u[5], double gamma, double T_ref, T g[4]) {
   const double i = rcp(u[0]);
   const double a1 = u[1] * i, a2 = u[2] * i, a3 = u[3] * i;
   const double p = (gamma - 1.0) * (u[4] - 0.5 * u[0] * (a1 * a1 + a2 * a2 + a3 * a3));
   g[0] = (T)a1;
   g[1] = (T)a2;
   g[2] = (T)a3;
-  g[3] = (T)(p * i);
+  g[3] = (T)(p * i - T_ref);
 }
 
 // ------------------------------------------------------------------ geometry (FP64 always)
@@ -502,6 +725,7 @@ __global__ void __launch_bounds__(nthreads_for(N)) grad_kernel(View v, int cur) 
   __shared__ double sD[n * n], sw[n];
   __shared__ T sG[4][nn];
   __shared__ T sJ[6][4][nf];
+  const double Tref = sizeof(T) == 4 ? v.p_r / v.rho_r : 0.0;
   for (int x = t; x < n * n; x += NT) sD[x] = v.tab[2 * n + x];
   if (t < n) sw[t] = v.tab[n + t];
   const long base = (long)e * nn;
@@ -510,7 +734,7 @@ __global__ void __launch_bounds__(nthreads_for(N)) grad_kernel(View v, int cur) 
 #pragma unroll
     for (int c = 0; c < 5; c++) u[c] = Uin[base * 5 + c * nn + t];
     T g[4];
-    gvars(u, v.gamma, g);
+    gvars(u, v.gamma, Tref, g);
 #pragma unroll
     for (int c = 0; c < 4; c++) sG[c][t] = g[c];
   }
@@ -526,7 +750,7 @@ __global__ void __launch_bounds__(nthreads_for(N)) grad_kernel(View v, int cur) 
 #pragma unroll
     for (int c = 0; c < 5; c++) un[c] = Uin[(long)ne * nn * 5 + c * nn + inb];
     T gn[4];
-    gvars(un, v.gamma, gn);
+    gvars(un, v.gamma, Tref, gn);
 #pragma unroll
     for (int c = 0; c < 4; c++) sJ[f][c][q] = (T)0.5 * (gn[c] - sG[c][io]);
   }
@@ -581,21 +805,29 @@ __global__ void __launch_bounds__(nthreads_for(N))
   const int ti = t % n, tj = (t / n) % n, tk = t / nf;
   const int ii[3] = {ti, tj, tk};
   const double* __restrict__ Uin = v.U[cur];
+  constexpr bool DEV = sizeof(T) == 4;  // FP32-bulk: deviation form
+  const Ref Rf = make_ref(v.rho_r, v.p_r, v.gamma);
+  const double Tref = DEV ? Rf.por : 0.0;
 
   __shared__ double sD[n * n], sDh[n * n], sw[n];
-  __shared__ T sP[7][nn];      // rho, v1, v2, v3, beta, ln rho, ln beta
-  __shared__ T sJa3[3][nn];    // Ja^d of the direction d being processed
-  __shared__ T sF[6][5][nf];   // face fluxes F~* - F~v*
+  __shared__ T sP[7][nn];      // rho, v1, v2, v3, beta, ln rho, ln beta (FP32-bulk: deviations)
+  __shared__ double sJa3[3][nn];  // Ja^d of the direction d being processed
+  __shared__ T sF[6][5][nf];      // face fluxes F~* - F~v*
   __shared__ unsigned char sPa[np], sPb[np];
+  // FP32-bulk keeps the mass flux in FP64: velocities, face and pair mass fluxes
+  constexpr int nnD = DEV ? nn : 1, nfD = DEV ? nf : 1;
+  __shared__ double sVd[3][nnD];
+  __shared__ double sF0d[6][nfD];
   constexpr int bytesA = VISC ? (nn + 24 * nf) * (int)sizeof(T) : 0;
   constexpr int bytesB = VISC ? 4 * nn * (int)sizeof(T) : 0;
-  constexpr int bytesC = 5 * P * (int)sizeof(T);
+  constexpr int bytesC = 5 * P * (int)sizeof(T) + (DEV ? 8 * P : 0);
   constexpr int bytesAB = bytesA > bytesB ? bytesA : bytesB;
   __shared__ __align__(16) char sRaw[bytesAB > bytesC ? bytesAB : bytesC];
   T* sT = reinterpret_cast<T*>(sRaw);                                   // temperature
   T(*sJ)[4][nf] = reinterpret_cast<T(*)[4][nf]>(sRaw + nn * sizeof(T));  // half jumps of g
   T(*sFv)[nn] = reinterpret_cast<T(*)[nn]>(sRaw);                      // F~v^d, 4 components
   T(*sPair)[P] = reinterpret_cast<T(*)[P]>(sRaw);
+  double* sM = reinterpret_cast<double*>(sRaw + 5 * P * sizeof(T));  // FP32-bulk pair mass flux
 
   for (int x = t; x < n * n; x += NT) {
     sD[x] = v.tab[2 * n + x];
@@ -617,15 +849,21 @@ __global__ void __launch_bounds__(nthreads_for(N))
     double u[5];
 #pragma unroll
     for (int c = 0; c < 5; c++) u[c] = Uin[base * 5 + c * nn + t];
-    const Prim<T> Pr = make_prim<T>(u, v.gamma);
+    const Prim<T> Pr = DEV ? make_prim_dev<T>(u, v.gamma, Rf) : make_prim<T>(u, v.gamma);
     sP[0][t] = Pr.rho; sP[1][t] = Pr.v1; sP[2][t] = Pr.v2; sP[3][t] = Pr.v3;
     sP[4][t] = Pr.beta; sP[5][t] = Pr.lrho; sP[6][t] = Pr.lbeta;
+    if (DEV) {
+      const double ir = rcp(u[0]);
+      sVd[0][t] = u[1] * ir;
+      sVd[1][t] = u[2] * ir;
+      sVd[2][t] = u[3] * ir;
+    }
 #pragma unroll
     for (int c = 0; c < 9; c++) ja[c] = v.Ja[base * 9 + c * nn + t];
     ij = v.invJ[base + t];
     if (VISC) {
       T g[4];
-      gvars(u, v.gamma, g);
+      gvars(u, v.gamma, Tref, g);
       sT[t] = g[3];
     }
   }
@@ -653,14 +891,20 @@ __global__ void __launch_bounds__(nthreads_for(N))
 #pragma unroll
     for (int c = 0; c < 3; c++) S[c] = v.Ja[base * 9 + (3 * d + c) * nn + io];
     T F[5];
-    face_flux<T>(v.surf, uL, uR, S, v.gamma, F);
+    if (DEV) {
+      double F0d;
+      face_flux_dev<T>(v.surf, uL, uR, S, v.gamma, Rf, F, F0d);
+      sF0d[f][q] = F0d;
+    } else {
+      face_flux<T>(v.surf, uL, uR, S, v.gamma, F);
+    }
     if (VISC) {
       const T* fo = FvfAll + ((long)e * 6 + f) * 4 * nf;
       const T* fn = FvfAll + ((long)ne * 6 + (f ^ 1)) * 4 * nf;
 #pragma unroll
       for (int c = 0; c < 4; c++) F[1 + c] -= (T)0.5 * (fo[c * nf + q] + fn[c * nf + q]);
       T gn[4];
-      gvars(un, v.gamma, gn);
+      gvars(un, v.gamma, Tref, gn);
       const T go[4] = {sP[1][io], sP[2][io], sP[3][io], sT[io]};
 #pragma unroll
       for (int c = 0; c < 4; c++) sJ[f][c][q] = (T)0.5 * (gn[c] - go[c]);
@@ -672,6 +916,7 @@ __global__ void __launch_bounds__(nthreads_for(N))
 
   const T iwN = (T)(1.0 / sw[N]), iw0 = (T)(1.0 / sw[0]);
   T acc[5] = {0, 0, 0, 0, 0};
+  double acc0d = 0.0;  // FP32-bulk mass accumulator
   if (VISC) {
     // BR1 gradient and contravariant viscous flux of this node, then sum_m Dhat_im F~v^d_m
     T Fvd[3][4];
@@ -709,7 +954,7 @@ __global__ void __launch_bounds__(nthreads_for(N))
     __syncthreads();  // previous users of sJa3 / the phase region are done
     if (act) {
 #pragma unroll
-      for (int c = 0; c < 3; c++) sJa3[c][t] = (T)ja[3 * d + c];
+      for (int c = 0; c < 3; c++) sJa3[c][t] = ja[3 * d + c];
     }
     __syncthreads();
     for (int s = t; s < P; s += NT) {
@@ -724,8 +969,23 @@ __global__ void __launch_bounds__(nthreads_for(N))
       B.beta = sP[4][nb]; B.lrho = sP[5][nb]; B.lbeta = sP[6][nb];
       B.h = (T)0.5 * (B.v1 * B.v1 + B.v2 * B.v2 + B.v3 * B.v3);
       T F[5];
-      vol_flux<T>(v.vol, A, B, sJa3[0][na] + sJa3[0][nb], sJa3[1][na] + sJa3[1][nb],
-                  sJa3[2][na] + sJa3[2][nb], ce, gm1, F);
+      const double md[3] = {sJa3[0][na] + sJa3[0][nb], sJa3[1][na] + sJa3[1][nb],
+                            sJa3[2][na] + sJa3[2][nb]};
+      const T m1 = (T)md[0], m2 = (T)md[1], m3 = (T)md[2];
+      if (DEV) {
+        const double va[3] = {sVd[0][na], sVd[1][na], sVd[2][na]};
+        const double vb[3] = {sVd[0][nb], sVd[1][nb], sVd[2][nb]};
+        double F0d;
+        if (v.vol == 0) {
+          const double vn64 = 0.5 * ((va[0] + vb[0]) * md[0] + (va[1] + vb[1]) * md[1] + (va[2] + vb[2]) * md[2]);
+          flux_ec_dev(A, B, m1, m2, m3, vn64, Rf, F, F0d);
+        } else {
+          flux_central_dev(A, B, m1, m2, m3, va, vb, md, Rf, F, F0d);
+        }
+        sM[s] = F0d;
+      } else {
+        vol_flux<T>(v.vol, A, B, m1, m2, m3, ce, gm1, F);
+      }
 #pragma unroll
       for (int c = 0; c < 5; c++) sPair[c][s] = F[c];
     }
@@ -741,14 +1001,17 @@ __global__ void __launch_bounds__(nthreads_for(N))
         const T Dm = (T)sD[id * n + m];
 #pragma unroll
         for (int c = 0; c < 5; c++) acc[c] += Dm * sPair[c][k];
+        if (DEV) acc0d += sD[id * n + m] * sM[k];
       }
       if (id == N) {
 #pragma unroll
         for (int c = 0; c < 5; c++) acc[c] += iwN * sF[2 * d + 1][c][line];
+        if (DEV) acc0d += sF0d[2 * d + 1][line] / sw[N];
       }
       if (id == 0) {
 #pragma unroll
         for (int c = 0; c < 5; c++) acc[c] -= iw0 * sF[2 * d][c][line];
+        if (DEV) acc0d -= sF0d[2 * d][line] / sw[0];
       }
     }
   }
@@ -756,6 +1019,10 @@ __global__ void __launch_bounds__(nthreads_for(N))
   double R[5];
 #pragma unroll
   for (int c = 0; c < 5; c++) R[c] = -(double)acc[c] * ij;
+  if (DEV) {  // FP64 mass; energy = H_r (mass) + deviation
+    R[0] = -acc0d * ij;
+    R[4] -= Rf.H * acc0d * ij;
+  }
   const long o = base * 5 + t;
   if (mode == kModeResidual) {
 #pragma unroll
@@ -774,7 +1041,7 @@ __global__ void __launch_bounds__(nthreads_for(N))
 // ------------------------------------------------------------------ diagnostics (FP64)
 // slots: 0-4 integral of U, 5 integral of -rho s, 6 integral of -rho s/(gamma-1), 7 integral of
 // rho|v|^2/2, 8 integral of rho|curl v|^2/2, 9 max(|v|+c), 10 min rho, 11 min p,
-// 12 number of non-finite values, 13 volume
+// 12 number of non-finite values, 13 volume, 14 integral of p
 template <int N>
 __global__ void __launch_bounds__(nthreads_for(N)) diag_kernel(View v, int cur) {
   constexpr int n = N + 1, nn = n * n * n, nf = n * n, NT = nthreads_for(N);
@@ -853,9 +1120,10 @@ __global__ void __launch_bounds__(nthreads_for(N)) diag_kernel(View v, int cur) 
     s[11] = p;
     s[12] = (double)bad;
     s[13] = wq;
+    s[14] = wq * p;
   }
   // fixed-order tree reduction, one slot at a time; slots beyond NT hold the identity
-  for (int k = 0; k < 14; k++) {
+  for (int k = 0; k < 15; k++) {
     red[t] = s[k];
     if (t + NT < NP) red[t + NT] = k == 9 ? -INFINITY : ((k == 10 || k == 11) ? INFINITY : 0.0);
     __syncthreads();
@@ -874,7 +1142,7 @@ __global__ void __launch_bounds__(nthreads_for(N)) diag_kernel(View v, int cur) 
 __global__ void __launch_bounds__(256) diag_final_kernel(View v) {
   __shared__ double red[256];
   const int t = threadIdx.x;
-  for (int k = 0; k < 14; k++) {
+  for (int k = 0; k < 15; k++) {
     double a = k == 9 ? -INFINITY : ((k == 10 || k == 11) ? INFINITY : 0.0);
     for (int e = t; e < v.E; e += 256) {
       const double b = v.part[(long)e * kDiagSlots + k];
