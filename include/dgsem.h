@@ -15,7 +15,7 @@
  *  - Status: every int-returning call returns DG_OK (0) or a negative DG_E* code; the message
  *    of the last failure on the calling thread is returned by dg_last_error().  Nothing
  *    aborts or throws across the ABI.
- *  - Ownership: dg_mesh / dg_solver / dg_batch handles are owned by the library and freed by
+ *  - Ownership: dg_mesh / dg_solver handles are owned by the library and freed by
  *    the matching *_destroy.  Device memory is owned by the caller: dg_solver_required_bytes
  *    states the size, the caller allocates it (any device allocator) and passes it to
  *    dg_solver_bind; the library sub-allocates inside it and never frees it.  The buffer must
@@ -106,9 +106,13 @@ typedef struct {
 } dg_diag;
 
 /* ------------------------------------------------------------------ mesh */
-/* Build the host-side mesh (connectivity, per-element orders).  Errors: DG_EINVAL for
- * non-positive sizes, hi <= lo, orders outside [1, 7]; DG_EUNSUPPORTED for mixed orders
- * (this build evaluates uniform-order meshes). */
+/* Build the host-side mesh (connectivity, per-element orders).  A mesh whose orders[] are not
+ * all equal is a mixed-order mesh (section "Spatial p-adaptation": every element carries its
+ * own order per direction, and faces whose two sides differ in tangential order are coupled
+ * through a mortar of the larger orders; the fluxes are L2-projected back, which conserves
+ * their integral).  Errors: DG_EINVAL for non-positive sizes, hi <= lo, orders outside
+ * [1, 7]; DG_EUNSUPPORTED for a mixed-order mesh with an order above 6 or 2^31 nodes or
+ * more. */
 int dg_mesh_create_box(const dg_box_desc* d, dg_mesh** out);
 void dg_mesh_destroy(dg_mesh* m);
 /* n_elements, total nodes and the largest order of the mesh. */
@@ -117,7 +121,8 @@ int dg_mesh_info(const dg_mesh* m, long long* n_elements, long long* n_nodes, in
 /* ------------------------------------------------------------------ solver */
 /* Create a solver for the mesh (the mesh may be destroyed afterwards).  Errors: DG_EINVAL for
  * gamma <= 1, Pr <= 0, unknown flux or precision codes; DG_EUNSUPPORTED for an order without
- * a compiled kernel (uniform orders 1..7 are compiled). */
+ * a compiled kernel (uniform orders 1..7 are compiled), and for a mixed-order mesh with
+ * Re > 0 or DG_FP32_BULK (mixed-order meshes are evaluated for the Euler equations in FP64). */
 int dg_solver_create(const dg_mesh* m, const dg_physics* p, dg_solver** out);
 /* Bytes of device memory the solver needs (host-only; used for admission control). */
 int dg_solver_required_bytes(const dg_solver* s, size_t* bytes);
@@ -143,6 +148,24 @@ int dg_residual(dg_solver* s, double* host_R, size_t n);
  * per stage k, dU <- A_k dU + dt R(U); U <- U + B_k dU, A = (0, -5/9, -153/128),
  * B = (1/3, 15/16, 8/15).  Only enqueues work on the solver's stream. */
 int dg_rk_step(dg_solver* s, double dt, int nsteps);
+/* Graph replay of RK steps (on by default).  When dg_rk_step runs several steps, or the same
+ * dt as its previous call, the launches of one step are captured once per starting state
+ * buffer into a HIP graph (on a stream the library owns; no memory operations are recorded)
+ * and replayed on the solver's stream.  Graphs are dropped when the state or its FP32
+ * reference changes, after dg_autotune and when disabled; steps inside a profile region run
+ * eagerly.  enable = 0 disables replay. */
+int dg_solver_use_graphs(dg_solver* s, int enable);
+/* Mixed-order meshes: time the stage kernel (residual mode, 5 launches each) at 128, 256 and
+ * 512 threads per element workgroup on the current state and keep the fastest; *block and *us
+ * (either may be NULL) receive it and its mean launch time in microseconds.  The residual
+ * buffer is overwritten; the state is not changed.  Uniform-order meshes have one launch
+ * shape: *block receives it and *us 0.  Synchronises. */
+int dg_autotune(dg_solver* s, int* block, double* us);
+/* Set the stage-kernel block size of a mixed-order mesh by hand (128, 256 or 512; the default
+ * is 256).  The result does not depend on it: every node's sums are taken in the same order
+ * at every block size.  For a uniform-order mesh only its one launch shape is accepted.
+ * Errors: DG_EINVAL for any other value. */
+int dg_solver_set_block(dg_solver* s, int block);
 /* Diagnostics of the current state (synchronises). */
 int dg_diagnostics(dg_solver* s, dg_diag* out);
 /* dt = cfl h_min / ((N_max+1)^2 lambda_max), and for Navier-Stokes the smaller of that and

@@ -1,10 +1,13 @@
 // api.cpp -- the C ABI of libdgsem.so (declared in include/dgsem.h): host-side mesh and
 // connectivity, the device memory plan inside the caller's buffer, argument checking and
-// error reporting, and the launch sequence of each call.
+// error reporting, the launch sequence of each call, the block-size autotuner of the
+// mixed-order stage kernel, and HIP-graph replay of RK steps.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -13,6 +16,7 @@
 
 namespace dg {
 void gll_tables(int N, double* xi, double* w, double* D, double* Dh);
+void mortar_tables(int N, int M, double* I, double* P);
 }
 
 static thread_local std::string g_err;
@@ -38,7 +42,9 @@ struct dg_mesh {
   double lo[3], hi[3];
   int deform;
   double amp;
-  int N;
+  int N;                    // the order of a uniform mesh, the largest order of a mixed one
+  bool mixed = false;
+  std::vector<int> orders;  // mixed meshes: orders[3 e + d]
 };
 
 struct ProfRecord {
@@ -53,20 +59,36 @@ struct dg_solver {
   hipStream_t stream = nullptr;
   bool bound = false;
   int cur = 0;
-  long long E = 0, nn = 0, ntot = 0;
+  long long E = 0, ntot = 0;
+  std::vector<long long> off;        // first node of every element, and the total at [E]
   bool profiling = false;
   std::vector<ProfRecord> prof;      // records of the current profile region
   std::vector<hipEvent_t> ev_pool;   // events reused across regions
   size_t ev_used = 0;
+  int mix_block = 256;               // threads per element of the mixed-order stage kernel
+  // RK-step graphs: graph[p] advances one step starting from state buffer p with step graph_dt[p]
+  bool use_graphs = true;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  double graph_dt[2] = {0.0, 0.0};
+  double last_dt = 0.0;
 };
 
 namespace {
 
 struct Plan {
-  size_t tab, nbr, X, Ja, J, invJ, U0, U1, dU, R, Fvf, part, diag, total;
+  size_t tab, nbr, X, Ja, J, invJ, U0, U1, dU, R, Fvf, part, diag, elem, work, mtab, total;
+  size_t tab_n, mtab_n;
 };
 
+long long nodes_of(const dg_mesh& m, long long e) {
+  if (!m.mixed) return (long long)(m.N + 1) * (m.N + 1) * (m.N + 1);
+  const int* o = &m.orders[3 * e];
+  return (long long)(o[0] + 1) * (o[1] + 1) * (o[2] + 1);
+}
+
 Plan make_plan(const dg_solver* s) {
+  const bool mixed = s->mesh.mixed;
   const size_t n = (size_t)s->mesh.N + 1, nf = n * n;
   const size_t E = (size_t)s->E, nt = (size_t)s->ntot;
   size_t off = 0;
@@ -76,7 +98,16 @@ Plan make_plan(const dg_solver* s) {
     return o;
   };
   Plan p;
-  p.tab = take(sizeof(double) * dg::tab_size((int)n));
+  p.tab_n = 0;
+  p.mtab_n = 0;
+  if (mixed) {
+    for (int N = 1; N <= dg::kMaxOrder; N++) p.tab_n += dg::tab_size(N + 1);
+    for (int N = 1; N <= dg::kMaxOrder; N++)
+      for (int M = N + 1; M <= dg::kMaxOrder; M++) p.mtab_n += 2 * (N + 1) * (M + 1);
+  } else {
+    p.tab_n = dg::tab_size((int)n);
+  }
+  p.tab = take(sizeof(double) * p.tab_n);
   p.nbr = take(sizeof(int) * 6 * E);
   p.X = take(sizeof(double) * 3 * nt);
   p.Ja = take(sizeof(double) * 9 * nt);
@@ -89,13 +120,18 @@ Plan make_plan(const dg_solver* s) {
   p.Fvf = s->phys.Re > 0 ? take(sizeof(double) * E * 6 * 4 * nf) : 0;
   p.part = take(sizeof(double) * E * dg::kDiagSlots);
   p.diag = take(sizeof(double) * dg::kDiagSlots);
+  p.elem = mixed ? take(sizeof(int4) * E) : 0;
+  p.work = mixed ? take(sizeof(int) * E) : 0;
+  p.mtab = mixed ? take(sizeof(double) * p.mtab_n) : 0;
   p.total = off;
   return p;
 }
 
-bool finite_positive_state(const double* U, long long E, long long nn, double gamma, std::string& why) {
-  for (long long e = 0; e < E; e++) {
-    const double* u = U + e * nn * 5;
+bool finite_positive_state(const dg_solver* s, const double* U, std::string& why) {
+  const double gamma = s->phys.gamma;
+  for (long long e = 0; e < s->E; e++) {
+    const long long nn = s->off[e + 1] - s->off[e];
+    const double* u = U + s->off[e] * 5;
     for (long long q = 0; q < nn; q++) {
       const double r = u[q], m1 = u[nn + q], m2 = u[2 * nn + q], m3 = u[3 * nn + q], en = u[4 * nn + q];
       if (!std::isfinite(r) || !std::isfinite(m1) || !std::isfinite(m2) || !std::isfinite(m3) ||
@@ -139,26 +175,87 @@ hipError_t timed(dg_solver* s, int cls, F fn) {
   return hipSuccess;
 }
 
+hipError_t launch_stage_any(dg_solver* s, double dt, double a, double b, int mode) {
+  if (s->v.mixed) return dg::launch_stage_mixed(s->v, s->cur, dt, a, b, mode, s->mix_block, s->stream);
+  return dg::launch_stage(s->v, s->cur, dt, a, b, mode, s->stream);
+}
+
 hipError_t run_stage(dg_solver* s, double dt, double a, double b, int mode) {
   if (s->v.viscous) {
     hipError_t e = timed(s, DG_K_GRADIENT, [&] { return dg::launch_gradient(s->v, s->cur, s->stream); });
     if (e != hipSuccess) return e;
   }
-  return timed(s, DG_K_STAGE, [&] { return dg::launch_stage(s->v, s->cur, dt, a, b, mode, s->stream); });
+  return timed(s, DG_K_STAGE, [&] { return launch_stage_any(s, dt, a, b, mode); });
+}
+
+hipError_t launch_diag_any(dg_solver* s) {
+  return s->v.mixed ? dg::launch_diagnostics_mixed(s->v, s->cur, s->stream)
+                    : dg::launch_diagnostics(s->v, s->cur, s->stream);
+}
+
+// Williamson's low-storage RK3
+const double kRkA[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
+const double kRkB[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
+
+// (waits for the solver's stream first, so that no replay of a graph is still in flight)
+void drop_graphs(dg_solver* s) {
+  if (!s->graph[0] && !s->graph[1]) return;
+  (void)hipStreamSynchronize(s->stream);
+  for (int k = 0; k < 2; k++) {
+    if (s->graph[k]) (void)hipGraphExecDestroy(s->graph[k]);
+    s->graph[k] = nullptr;
+  }
 }
 
 // FP32-bulk reference state: volume means of density and pressure of the state just set
 // (any constant is exact; the closer to the state, the smaller the deviations).
 int update_reference(dg_solver* s) {
+  drop_graphs(s);  // captured launches hold the reference state by value
   if (!s->v.fp32) return DG_OK;
   double h[dg::kDiagSlots];
-  DG_HIP(dg::launch_diagnostics(s->v, s->cur, s->stream), "reference-state reduction");
+  DG_HIP(launch_diag_any(s), "reference-state reduction");
   DG_HIP(hipMemcpyAsync(h, s->v.diag, sizeof(h), hipMemcpyDeviceToHost, s->stream), "reference state");
   DG_HIP(hipStreamSynchronize(s->stream), "reference state");
   if (!(h[13] > 0) || !(h[0] > 0) || !(h[14] > 0) || !std::isfinite(h[0]) || !std::isfinite(h[14]))
     return fail(DG_ENONFINITE, "state has no positive finite mean density and pressure");
   s->v.rho_r = h[0] / h[13];
   s->v.p_r = h[14] / h[13];
+  return DG_OK;
+}
+
+// Record the launches of one RK step that starts from state buffer s->cur on the library's
+// capture stream (the solver's stream is swapped for it meanwhile) and instantiate them.
+int capture_step(dg_solver* s, double dt) {
+  const int parity = s->cur;
+  if (s->graph[parity]) {
+    (void)hipStreamSynchronize(s->stream);  // no replay of the old graph still in flight
+    (void)hipGraphExecDestroy(s->graph[parity]);
+    s->graph[parity] = nullptr;
+  }
+  hipStream_t user = s->stream;
+  s->stream = s->cap_stream;
+  hipGraph_t g = nullptr;
+  hipError_t err = hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (err == hipSuccess) {
+    for (int k = 0; k < 3 && err == hipSuccess; k++) {
+      err = run_stage(s, dt, kRkA[k], kRkB[k], dg::kModeRK);
+      s->cur ^= 1;
+    }
+    const hipError_t e2 = hipStreamEndCapture(s->cap_stream, &g);
+    if (err == hipSuccess) err = e2;
+  }
+  s->stream = user;
+  s->cur = parity;
+  if (err != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return hip_fail(err, "capture of an RK step");
+  }
+  hipGraphExec_t ex = nullptr;
+  err = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (err != hipSuccess) return hip_fail(err, "instantiation of the RK-step graph");
+  s->graph[parity] = ex;
+  s->graph_dt[parity] = dt;
   return DG_OK;
 }
 
@@ -183,16 +280,25 @@ int dg_mesh_create_box(const dg_box_desc* d, dg_mesh** out) {
     if (!(d->hi[k] > d->lo[k])) return fail(DG_EINVAL, "box requires hi > lo in every direction");
   if (d->deform != DG_DEFORM_NONE && d->deform != DG_DEFORM_SINSIN)
     return fail(DG_EINVAL, "unknown deformation");
+  const long long E = (long long)d->ex * d->ey * d->ez;
   int N = d->n_uniform;
+  bool mixed = false;
+  int nmax = 0;
+  long long nodes = 0;
   if (d->orders) {
-    const long long E = (long long)d->ex * d->ey * d->ez;
     N = d->orders[0];
     for (long long i = 0; i < 3 * E; i++) {
       if (d->orders[i] < 1 || d->orders[i] > dg::kMaxOrder)
         return fail(DG_EINVAL, "orders must lie in [1, 7]");
-      if (d->orders[i] != N)
-        return fail(DG_EUNSUPPORTED, "mixed per-element orders are not evaluated by this build");
+      if (d->orders[i] != N) mixed = true;
+      nmax = std::max(nmax, d->orders[i]);
     }
+    for (long long e = 0; e < E; e++)
+      nodes += (long long)(d->orders[3 * e] + 1) * (d->orders[3 * e + 1] + 1) * (d->orders[3 * e + 2] + 1);
+    if (mixed && nmax > dg::kMixMaxOrder)
+      return fail(DG_EUNSUPPORTED, "elements of mixed-order meshes take orders up to 6");
+    if (mixed && nodes >= (1LL << 31))
+      return fail(DG_EUNSUPPORTED, "mixed-order meshes take fewer than 2^31 nodes");
   }
   if (N < 1 || N > dg::kMaxOrder) return fail(DG_EINVAL, "order must lie in [1, 7]");
   dg_mesh* m = new dg_mesh;
@@ -200,7 +306,9 @@ int dg_mesh_create_box(const dg_box_desc* d, dg_mesh** out) {
   for (int k = 0; k < 3; k++) { m->lo[k] = d->lo[k]; m->hi[k] = d->hi[k]; }
   m->deform = d->deform;
   m->amp = d->deform_amp;
-  m->N = N;
+  m->mixed = mixed;
+  m->N = mixed ? nmax : N;
+  if (mixed) m->orders.assign(d->orders, d->orders + 3 * E);
   *out = m;
   return DG_OK;
 }
@@ -210,9 +318,13 @@ void dg_mesh_destroy(dg_mesh* m) { delete m; }
 int dg_mesh_info(const dg_mesh* m, long long* n_elements, long long* n_nodes, int* n_max) {
   if (!m) return fail(DG_EINVAL, "NULL mesh");
   const long long E = (long long)m->ex * m->ey * m->ez;
-  const long long nn = (long long)(m->N + 1) * (m->N + 1) * (m->N + 1);
+  long long nodes = 0;
+  if (m->mixed)
+    for (long long e = 0; e < E; e++) nodes += nodes_of(*m, e);
+  else
+    nodes = E * nodes_of(*m, 0);
   if (n_elements) *n_elements = E;
-  if (n_nodes) *n_nodes = E * nn;
+  if (n_nodes) *n_nodes = nodes;
   if (n_max) *n_max = m->N;
   return DG_OK;
 }
@@ -227,12 +339,18 @@ int dg_solver_create(const dg_mesh* m, const dg_physics* p, dg_solver** out) {
   if (p->surf_flux < DG_SURF_ROE || p->surf_flux > DG_SURF_CENTRAL) return fail(DG_EINVAL, "unknown surface flux");
   if (p->precision != DG_FP64 && p->precision != DG_FP32_BULK) return fail(DG_EINVAL, "unknown precision");
   if (m->N < 1 || m->N > dg::kMaxOrder) return fail(DG_EUNSUPPORTED, "no kernel for this order");
+  if (m->mixed && p->Re > 0)
+    return fail(DG_EUNSUPPORTED, "mixed-order meshes are evaluated for the Euler equations (Re <= 0)");
+  if (m->mixed && p->precision != DG_FP64)
+    return fail(DG_EUNSUPPORTED, "mixed-order meshes are evaluated in FP64");
   dg_solver* s = new dg_solver;
   s->mesh = *m;
   s->phys = *p;
   s->E = (long long)m->ex * m->ey * m->ez;
-  s->nn = (long long)(m->N + 1) * (m->N + 1) * (m->N + 1);
-  s->ntot = s->E * s->nn;
+  s->off.resize(s->E + 1);
+  s->off[0] = 0;
+  for (long long e = 0; e < s->E; e++) s->off[e + 1] = s->off[e] + nodes_of(*m, e);
+  s->ntot = s->off[s->E];
   std::memset(&s->v, 0, sizeof(s->v));
   dg::View& v = s->v;
   v.E = (int)s->E;
@@ -254,6 +372,8 @@ int dg_solver_create(const dg_mesh* m, const dg_physics* p, dg_solver** out) {
   v.fp32 = p->precision == DG_FP32_BULK ? 1 : 0;
   v.rho_r = 1.0;
   v.p_r = 1.0 / (p->gamma * p->Ma * p->Ma);
+  v.mixed = m->mixed ? 1 : 0;
+  v.nmax = m->N;
   *out = s;
   return DG_OK;
 }
@@ -274,6 +394,7 @@ int dg_solver_bind(dg_solver* s, void* dev_ptr, size_t bytes, void* hip_stream) 
   if (((uintptr_t)dev_ptr & 255) != 0) return fail(DG_EINVAL, "device buffer must be 256-byte aligned");
   char* b = static_cast<char*>(dev_ptr);
   dg::View& v = s->v;
+  const bool mixed = v.mixed != 0;
   v.tab = reinterpret_cast<const double*>(b + p.tab);
   v.nbr = reinterpret_cast<const int*>(b + p.nbr);
   v.X = reinterpret_cast<double*>(b + p.X);
@@ -287,12 +408,27 @@ int dg_solver_bind(dg_solver* s, void* dev_ptr, size_t bytes, void* hip_stream) 
   v.Fvf = v.viscous ? reinterpret_cast<double*>(b + p.Fvf) : nullptr;
   v.part = reinterpret_cast<double*>(b + p.part);
   v.diag = reinterpret_cast<double*>(b + p.diag);
+  v.elem = mixed ? reinterpret_cast<const int4*>(b + p.elem) : nullptr;
+  v.work = mixed ? reinterpret_cast<const int*>(b + p.work) : nullptr;
+  v.mtab = mixed ? reinterpret_cast<const double*>(b + p.mtab) : nullptr;
   s->stream = static_cast<hipStream_t>(hip_stream);
 
-  const int n = v.N + 1;
-  std::vector<double> tab(dg::tab_size(n));
-  dg::gll_tables(v.N, tab.data() + dg::tab_xi(n), tab.data() + dg::tab_w(n), tab.data() + dg::tab_D(n),
-                 tab.data() + dg::tab_Dh(n));
+  // Lobatto tables: of the one order, or of every order (at tab_off[N]) for a mixed mesh
+  std::vector<double> tab(p.tab_n);
+  auto fill = [&](int N, double* t) {
+    const int n = N + 1;
+    dg::gll_tables(N, t + dg::tab_xi(n), t + dg::tab_w(n), t + dg::tab_D(n), t + dg::tab_Dh(n));
+  };
+  if (mixed) {
+    size_t o = 0;
+    for (int N = 1; N <= dg::kMaxOrder; N++) {
+      v.tab_off[N] = (int)o;
+      fill(N, tab.data() + o);
+      o += dg::tab_size(N + 1);
+    }
+  } else {
+    fill(v.N, tab.data());
+  }
   std::vector<int> nbr(6 * s->E);
   const int ex = v.ex, ey = v.ey, ez = v.ez;
   for (long long e = 0; e < s->E; e++) {
@@ -308,9 +444,42 @@ int dg_solver_bind(dg_solver* s, void* dev_ptr, size_t bytes, void* hip_stream) 
          "upload tables");
   DG_HIP(hipMemcpyAsync(b + p.nbr, nbr.data(), sizeof(int) * nbr.size(), hipMemcpyHostToDevice, s->stream),
          "upload connectivity");
-  DG_HIP(dg::launch_geometry(v, s->stream), "geometry kernel");
+  if (mixed) {
+    // mortar matrices I_{N->M} ((M+1) x (N+1)) then P_{M->N} ((N+1) x (M+1)) at mort_off[N][M]
+    std::vector<double> mtab(p.mtab_n);
+    size_t o = 0;
+    for (int N = 1; N <= dg::kMaxOrder; N++)
+      for (int M = N + 1; M <= dg::kMaxOrder; M++) {
+        v.mort_off[N][M] = (int)o;
+        dg::mortar_tables(N, M, mtab.data() + o, mtab.data() + o + (N + 1) * (M + 1));
+        o += 2 * (N + 1) * (M + 1);
+      }
+    // element table (node counts, first node) and the launch order: largest elements first
+    std::vector<int4> elem(s->E);
+    for (long long e = 0; e < s->E; e++) {
+      const int* n = &s->mesh.orders[3 * e];
+      elem[e] = make_int4(n[0] + 1, n[1] + 1, n[2] + 1, (int)s->off[e]);
+    }
+    std::vector<int> work(s->E);
+    std::iota(work.begin(), work.end(), 0);
+    std::stable_sort(work.begin(), work.end(), [&](int x, int y) {
+      return s->off[x + 1] - s->off[x] > s->off[y + 1] - s->off[y];
+    });
+    DG_HIP(hipMemcpyAsync(b + p.mtab, mtab.data(), sizeof(double) * mtab.size(), hipMemcpyHostToDevice,
+                          s->stream), "upload mortar matrices");
+    DG_HIP(hipMemcpyAsync(b + p.elem, elem.data(), sizeof(int4) * elem.size(), hipMemcpyHostToDevice,
+                          s->stream), "upload element table");
+    DG_HIP(hipMemcpyAsync(b + p.work, work.data(), sizeof(int) * work.size(), hipMemcpyHostToDevice,
+                          s->stream), "upload work list");
+    DG_HIP(dg::launch_geometry_mixed(v, s->stream), "geometry kernel");
+    // the host vectors must outlive the copies
+    DG_HIP(hipStreamSynchronize(s->stream), "upload");
+  } else {
+    DG_HIP(dg::launch_geometry(v, s->stream), "geometry kernel");
+  }
   DG_HIP(hipMemsetAsync(v.dU, 0, sizeof(double) * 5 * s->ntot, s->stream), "clear RK register");
   DG_HIP(hipStreamSynchronize(s->stream), "geometry");
+  DG_HIP(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking), "capture stream");
   s->bound = true;
   s->cur = 0;
   return DG_OK;
@@ -329,7 +498,11 @@ int dg_set_initial_condition(dg_solver* s, int ic, const double* params) {
   }
   if (ic == DG_IC_UNIFORM && (!(P[0] > 0) || !(P[4] > 0)))
     return fail(DG_EINVAL, "uniform state needs rho > 0 and p > 0");
-  DG_HIP(timed(s, DG_K_OTHER, [&] { return dg::launch_ic(s->v, s->cur, ic, P, s->stream); }),
+  DG_HIP(timed(s, DG_K_OTHER,
+               [&] {
+                 return s->v.mixed ? dg::launch_ic_mixed(s->v, s->cur, ic, P, s->stream)
+                                   : dg::launch_ic(s->v, s->cur, ic, P, s->stream);
+               }),
          "initial-condition kernel");
   return update_reference(s);
 }
@@ -340,7 +513,7 @@ int dg_set_state(dg_solver* s, const double* host_U, size_t n) {
   if (!host_U) return fail(DG_EINVAL, "NULL state");
   if (n != (size_t)(5 * s->ntot)) return fail(DG_EINVAL, "state size must be 5 * number of nodes");
   std::string why;
-  if (!finite_positive_state(host_U, s->E, s->nn, s->phys.gamma, why)) return fail(DG_ENONFINITE, why);
+  if (!finite_positive_state(s, host_U, why)) return fail(DG_ENONFINITE, why);
   DG_HIP(hipMemcpyAsync(s->v.U[s->cur], host_U, sizeof(double) * n, hipMemcpyHostToDevice, s->stream),
          "upload state");
   DG_HIP(hipMemsetAsync(s->v.dU, 0, sizeof(double) * n, s->stream), "clear RK register");
@@ -377,13 +550,93 @@ int dg_rk_step(dg_solver* s, double dt, int nsteps) {
   if (rc) return rc;
   if (nsteps < 0) return fail(DG_EINVAL, "nsteps must be >= 0");
   if (!std::isfinite(dt) || !(dt > 0)) return fail(DG_EINVAL, "dt must be positive and finite");
-  static const double A[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
-  static const double B[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
-  for (int it = 0; it < nsteps; it++)
-    for (int k = 0; k < 3; k++) {
-      DG_HIP(run_stage(s, dt, A[k], B[k], dg::kModeRK), "RK stage kernels");
-      s->cur ^= 1;
+  // replay a captured step when the same dt recurs (several steps in this call, or the same dt
+  // as the previous call); a step size seen once runs eagerly
+  const bool replay = s->use_graphs && !s->profiling && nsteps > 0 && (nsteps > 1 || dt == s->last_dt);
+  s->last_dt = dt;
+  for (int it = 0; it < nsteps; it++) {
+    if (replay) {
+      const int par = s->cur;
+      if (!s->graph[par] || s->graph_dt[par] != dt) {
+        rc = capture_step(s, dt);
+        if (rc) return rc;
+      }
+      DG_HIP(hipGraphLaunch(s->graph[par], s->stream), "RK-step graph launch");
+      s->cur ^= 1;  // three stages, each moving the state to the other buffer
+    } else {
+      for (int k = 0; k < 3; k++) {
+        DG_HIP(run_stage(s, dt, kRkA[k], kRkB[k], dg::kModeRK), "RK stage kernels");
+        s->cur ^= 1;
+      }
     }
+  }
+  return DG_OK;
+}
+
+int dg_solver_use_graphs(dg_solver* s, int enable) {
+  if (!s) return fail(DG_EINVAL, "NULL solver");
+  s->use_graphs = enable != 0;
+  if (!s->use_graphs) drop_graphs(s);
+  return DG_OK;
+}
+
+int dg_solver_set_block(dg_solver* s, int block) {
+  if (!s) return fail(DG_EINVAL, "NULL solver");
+  if (!s->v.mixed) {
+    const int nn = (s->mesh.N + 1) * (s->mesh.N + 1) * (s->mesh.N + 1);
+    if (block != (nn + 63) / 64 * 64) return fail(DG_EINVAL, "uniform-order meshes have one launch shape");
+    return DG_OK;
+  }
+  if (block != 128 && block != 256 && block != 512) return fail(DG_EINVAL, "block must be 128, 256 or 512");
+  s->mix_block = block;
+  drop_graphs(s);
+  return DG_OK;
+}
+
+int dg_autotune(dg_solver* s, int* block, double* us) {
+  int rc = check_bound(s);
+  if (rc) return rc;
+  if (!s->v.mixed) {
+    const int nn = (s->mesh.N + 1) * (s->mesh.N + 1) * (s->mesh.N + 1);
+    if (block) *block = (nn + 63) / 64 * 64;
+    if (us) *us = 0.0;
+    return DG_OK;
+  }
+  const int cand[3] = {128, 256, 512};
+  const int reps = 5;
+  double best = 1e300;
+  int best_b = s->mix_block;
+  hipEvent_t a = nullptr, b = nullptr;
+  DG_HIP(hipEventCreate(&a), "event");
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return fail(DG_EHIP, "event");
+  }
+  hipError_t err = hipSuccess;
+  for (int c : cand) {
+    s->mix_block = c;
+    err = launch_stage_any(s, 0.0, 0.0, 0.0, dg::kModeResidual);  // warm-up
+    if (err == hipSuccess) err = hipEventRecord(a, s->stream);
+    for (int r = 0; r < reps && err == hipSuccess; r++)
+      err = launch_stage_any(s, 0.0, 0.0, 0.0, dg::kModeResidual);
+    if (err == hipSuccess) err = hipEventRecord(b, s->stream);
+    if (err == hipSuccess) err = hipEventSynchronize(b);
+    float ms = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, a, b);
+    if (err != hipSuccess) break;
+    const double t_us = 1e3 * ms / reps;
+    if (t_us < best) {
+      best = t_us;
+      best_b = c;
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  s->mix_block = best_b;
+  drop_graphs(s);
+  if (err != hipSuccess) return hip_fail(err, "autotune");
+  if (block) *block = best_b;
+  if (us) *us = best;
   return DG_OK;
 }
 
@@ -391,8 +644,7 @@ int dg_diagnostics(dg_solver* s, dg_diag* out) {
   int rc = check_bound(s);
   if (rc) return rc;
   if (!out) return fail(DG_EINVAL, "NULL output");
-  DG_HIP(timed(s, DG_K_DIAGNOSTICS, [&] { return dg::launch_diagnostics(s->v, s->cur, s->stream); }),
-         "diagnostics kernels");
+  DG_HIP(timed(s, DG_K_DIAGNOSTICS, [&] { return launch_diag_any(s); }), "diagnostics kernels");
   double h[dg::kDiagSlots];
   DG_HIP(hipMemcpyAsync(h, s->v.diag, sizeof(h), hipMemcpyDeviceToHost, s->stream), "download diagnostics");
   DG_HIP(hipStreamSynchronize(s->stream), "diagnostics");
@@ -491,6 +743,8 @@ int dg_profile_end(dg_solver* s, dg_profile* out) {
 void dg_solver_destroy(dg_solver* s) {
   if (!s) return;
   if (s->bound) (void)hipStreamSynchronize(s->stream);
+  drop_graphs(s);
+  if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
   delete s;
 }

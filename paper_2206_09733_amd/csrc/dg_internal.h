@@ -47,6 +47,16 @@ struct View {
   double* Fvf;    // [E][6][4][nf] contravariant viscous flux on the element's faces
   double* part;   // diagnostics partials [E][kDiagSlots]
   double* diag;   // final diagnostics [kDiagSlots]
+  // per-element anisotropic orders (mixed != 0): node counts per direction and first node of
+  // each element, elements in launch order (largest first), Lobatto tables of every order
+  // (offset tab_off[N] in tab) and mortar matrices (I_{N->M} then P_{M->N} at mort_off[N][M])
+  int mixed;
+  int nmax;
+  const int4* elem;
+  const int* work;
+  const double* mtab;
+  int tab_off[kMaxOrder + 1];
+  int mort_off[kMaxOrder + 1][kMaxOrder + 1];
 };
 
 // Launchers (kernels.hip).  All enqueue on `st` and return the hipError_t of the launch.
@@ -58,6 +68,15 @@ hipError_t launch_gradient(const View& v, int cur, hipStream_t st);
 hipError_t launch_stage(const View& v, int cur, double dt, double rkA, double rkB, int mode,
                         hipStream_t st);
 hipError_t launch_diagnostics(const View& v, int cur, hipStream_t st);
+hipError_t launch_diag_final(const View& v, hipStream_t st);  // partials -> diag, fixed order
+
+// mixed-order meshes (kernels_mixed.hip); block = threads per element workgroup of the stage
+constexpr int kMixMaxOrder = 6;
+hipError_t launch_geometry_mixed(const View& v, hipStream_t st);
+hipError_t launch_ic_mixed(const View& v, int cur, int ic, const double* params, hipStream_t st);
+hipError_t launch_stage_mixed(const View& v, int cur, double dt, double rkA, double rkB, int mode,
+                              int block, hipStream_t st);
+hipError_t launch_diagnostics_mixed(const View& v, int cur, hipStream_t st);
 
 // stage modes
 constexpr int kModeRK = 0;        // dU <- A dU + dt R; U[cur^1] <- U[cur] + B dU

@@ -91,3 +91,101 @@ void gll_tables(int N, double* xi, double* w, double* D, double* Dh) {
 }
 
 }  // namespace dg
+
+namespace dg {
+
+// Gauss-Legendre nodes (zeros of P_n: eigenvalues of the Jacobi matrix with off-diagonals
+// k / sqrt(4k^2 - 1)) by Sturm bisection, and weights 2 / ((1 - x^2) P_n'(x)^2).
+static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  std::vector<double> b2(n, 0.0);
+  for (int k = 1; k < n; k++) b2[k] = (double)k * k / (4.0 * k * k - 1.0);
+  for (int j = 0; j < n; j++) {
+    double lo = -1.0, hi = 1.0;
+    for (int it = 0; it < 200; it++) {
+      const double mid = 0.5 * (lo + hi);
+      if (mid <= lo || mid >= hi) break;
+      if (sturm_count(n, b2, mid) > j) hi = mid;
+      else lo = mid;
+    }
+    x[j] = 0.5 * (lo + hi);
+  }
+  for (int j = 0; j < n; j++) {
+    double pm = 1.0, pc = x[j], dm = 0.0, dc = 1.0;
+    for (int k = 1; k < n; k++) {
+      const double pn = ((2.0 * k + 1.0) * x[j] * pc - k * pm) / (k + 1.0);
+      const double dn = dm + (2.0 * k + 1.0) * pc;
+      pm = pc; pc = pn; dm = dc; dc = dn;
+    }
+    const double dp = n == 1 ? 1.0 : dc;
+    w[j] = 2.0 / ((1.0 - x[j] * x[j]) * dp * dp);
+  }
+}
+
+// value at y of the j-th Lagrange basis polynomial through nodes x[0..n) (barycentric form)
+static double lagrange_at(const double* x, int n, int j, double y) {
+  for (int k = 0; k < n; k++)
+    if (y == x[k]) return k == j ? 1.0 : 0.0;
+  double num = 0.0, den = 0.0, lj = 0.0;
+  for (int k = 0; k < n; k++) {
+    double l = 1.0;
+    for (int r = 0; r < n; r++)
+      if (r != k) l /= (x[k] - x[r]);
+    const double t = l / (y - x[k]);
+    den += t;
+    if (k == j) lj = t;
+  }
+  (void)num;
+  return lj / den;
+}
+
+// Mortar operators between Lobatto grids of orders N < M:
+//   I[p][q] (M+1)x(N+1): value at M-node p of the order-N interpolant of the q-th basis function
+//   P[i][q] (N+1)x(M+1): L2 projection onto degree N of the q-th order-M basis function,
+//     P = Mass_N^{-1} B, Mass_N[i][j] = int l^N_i l^N_j, B[i][q] = int l^N_i l^M_q, integrated
+//     exactly with Gauss-Legendre of N+M+1 points; Mass_N is factored by Cholesky.
+void mortar_tables(int N, int M, double* I, double* P) {
+  const int n = N + 1, m = M + 1;
+  std::vector<double> xn(n), wn(n), xm(m), wm(m), Dn(n * n), Dm(m * m), Dhn(n * n), Dhm(m * m);
+  gll_tables(N, xn.data(), wn.data(), Dn.data(), Dhn.data());
+  gll_tables(M, xm.data(), wm.data(), Dm.data(), Dhm.data());
+  for (int p = 0; p < m; p++)
+    for (int q = 0; q < n; q++) I[p * n + q] = lagrange_at(xn.data(), n, q, xm[p]);
+  std::vector<double> gx, gw;
+  gauss_legendre(N + M + 1, gx, gw);
+  const int G = (int)gx.size();
+  std::vector<double> A(n * n, 0.0), B(n * m, 0.0);
+  for (int g = 0; g < G; g++) {
+    std::vector<double> ln(n), lm(m);
+    for (int i = 0; i < n; i++) ln[i] = lagrange_at(xn.data(), n, i, gx[g]);
+    for (int q = 0; q < m; q++) lm[q] = lagrange_at(xm.data(), m, q, gx[g]);
+    for (int i = 0; i < n; i++) {
+      for (int j = 0; j < n; j++) A[i * n + j] += gw[g] * ln[i] * ln[j];
+      for (int q = 0; q < m; q++) B[i * m + q] += gw[g] * ln[i] * lm[q];
+    }
+  }
+  // Cholesky A = L L^T, then solve for each column of B
+  std::vector<double> L(n * n, 0.0);
+  for (int i = 0; i < n; i++)
+    for (int j = 0; j <= i; j++) {
+      double s = A[i * n + j];
+      for (int k = 0; k < j; k++) s -= L[i * n + k] * L[j * n + k];
+      L[i * n + j] = i == j ? std::sqrt(s) : s / L[j * n + j];
+    }
+  for (int q = 0; q < m; q++) {
+    std::vector<double> y(n);
+    for (int i = 0; i < n; i++) {
+      double s = B[i * m + q];
+      for (int k = 0; k < i; k++) s -= L[i * n + k] * y[k];
+      y[i] = s / L[i * n + i];
+    }
+    for (int i = n - 1; i >= 0; i--) {
+      double s = y[i];
+      for (int k = i + 1; k < n; k++) s -= L[k * n + i] * P[k * m + q];
+      P[i * m + q] = s / L[i * n + i];
+    }
+  }
+}
+
+}  // namespace dg

@@ -53,7 +53,8 @@ EXPORTS = ["dg_last_error", "dg_mesh_create_box", "dg_mesh_destroy", "dg_mesh_in
            "dg_solver_create", "dg_solver_required_bytes", "dg_solver_bind",
            "dg_set_initial_condition", "dg_set_state", "dg_get_state", "dg_residual", "dg_rk_step",
            "dg_diagnostics", "dg_suggest_dt", "dg_get_geometry", "dg_device_pointers",
-           "dg_synchronize", "dg_solver_destroy", "dg_profile_begin", "dg_profile_end"]
+           "dg_synchronize", "dg_solver_destroy", "dg_profile_begin", "dg_profile_end",
+           "dg_solver_use_graphs", "dg_autotune", "dg_solver_set_block"]
 
 _lib = None
 
@@ -96,6 +97,9 @@ def lib():
     L.dg_profile_end.argtypes = [vp, _c.POINTER(Profile)]
     L.dg_solver_destroy.argtypes = [vp]
     L.dg_solver_destroy.restype = None
+    L.dg_solver_use_graphs.argtypes = [vp, _c.c_int]
+    L.dg_autotune.argtypes = [vp, _c.POINTER(_c.c_int), _dp]
+    L.dg_solver_set_block.argtypes = [vp, _c.c_int]
     _lib = L
     return L
 
@@ -133,11 +137,15 @@ def physics(gamma=1.4, Pr=0.71, Ma=0.1, Re=0.0, vol="ec", surf="roe", precision=
 
 
 class Solver:
-    """One DGSEM solve on a periodic box, resident in device memory."""
+    """One DGSEM solve on a periodic box, resident in device memory.
+
+    `orders` (optional, shape (E, 3) or 3 E integers) gives every element its own order per
+    direction; otherwise all elements take order N.
+    """
 
     def __init__(self, ex, ey=None, ez=None, lo=(0.0, 0.0, 0.0), hi=None, deform=False, amp=0.05,
                  N=3, gamma=1.4, Pr=0.71, Ma=0.1, Re=0.0, vol="ec", surf="roe", precision="fp64",
-                 device="cuda", bind=True):
+                 device="cuda", bind=True, orders=None):
         L = lib()
         ey = ex if ey is None else ey
         ez = ex if ez is None else ez
@@ -147,13 +155,13 @@ class Solver:
         self.gamma, self.Pr, self.Ma, self.Re = gamma, Pr, Ma, Re
         self.h = None
         self.buf = None
-        d, _keep = box_desc(ex, ey, ez, lo, hi, deform, amp, N)
+        d, _keep = box_desc(ex, ey, ez, lo, hi, deform, amp, N, orders)
         mesh = _c.c_void_p()
         check(L.dg_mesh_create_box(_c.byref(d), _c.byref(mesh)))
         try:
             ne, nn, nmax = _c.c_longlong(), _c.c_longlong(), _c.c_int()
             check(L.dg_mesh_info(mesh, _c.byref(ne), _c.byref(nn), _c.byref(nmax)))
-            self.E, self.nodes = ne.value, nn.value
+            self.E, self.nodes, self.nmax = ne.value, nn.value, nmax.value
             h = _c.c_void_p()
             ph = physics(gamma, Pr, Ma, Re, vol, surf, precision)
             check(L.dg_solver_create(mesh, _c.byref(ph), _c.byref(h)))
@@ -237,6 +245,18 @@ class Solver:
         p = Profile()
         check(lib().dg_profile_end(self.h, _c.byref(p)))
         return {k: {"ms": p.ms[i], "launches": p.launches[i]} for i, k in enumerate(KERNEL_CLASSES)}
+
+    def use_graphs(self, enable=True):
+        check(lib().dg_solver_use_graphs(self.h, 1 if enable else 0))
+
+    def autotune(self):
+        """Pick the fastest stage-kernel block size (mixed-order meshes); returns (block, us)."""
+        b, us = _c.c_int(), _c.c_double()
+        check(lib().dg_autotune(self.h, _c.byref(b), _c.byref(us)))
+        return b.value, us.value
+
+    def set_block(self, block):
+        check(lib().dg_solver_set_block(self.h, int(block)))
 
     def synchronize(self):
         check(lib().dg_synchronize(self.h))

@@ -43,8 +43,15 @@ def test_mesh_argument_errors(dg):
     assert L.dg_mesh_create_box(ctypes.byref(d), ctypes.byref(m)) == dg.DG_EINVAL
     d, _ = dg.box_desc(2, 2, 2, (0, 0, 0), (1, 1, 1), False, 0.0, 8)
     assert L.dg_mesh_create_box(ctypes.byref(d), ctypes.byref(m)) == dg.DG_EINVAL
-    d, _ = dg.box_desc(2, 1, 1, (0, 0, 0), (1, 1, 1), False, 0.0, 3, orders=[3, 3, 3, 4, 3, 3])
+    # mixed orders are taken up to 6; an order 7 element in a mixed mesh is refused
+    d, _ = dg.box_desc(2, 1, 1, (0, 0, 0), (1, 1, 1), False, 0.0, 3, orders=[3, 3, 3, 7, 3, 3])
     assert L.dg_mesh_create_box(ctypes.byref(d), ctypes.byref(m)) == dg.DG_EUNSUPPORTED
+    d, _ = dg.box_desc(2, 1, 1, (0, 0, 0), (1, 1, 1), False, 0.0, 3, orders=[3, 3, 3, 0, 3, 3])
+    assert L.dg_mesh_create_box(ctypes.byref(d), ctypes.byref(m)) == dg.DG_EINVAL
+    # all-equal orders make a uniform mesh, even at order 7
+    d, _ = dg.box_desc(2, 1, 1, (0, 0, 0), (1, 1, 1), False, 0.0, 3, orders=[7] * 6)
+    assert L.dg_mesh_create_box(ctypes.byref(d), ctypes.byref(m)) == dg.DG_OK
+    L.dg_mesh_destroy(m)
     d, _ = dg.box_desc(2, 3, 4, (0, 0, 0), (1, 1, 1), True, 0.05, 4)
     assert L.dg_mesh_create_box(ctypes.byref(d), ctypes.byref(m)) == dg.DG_OK
     ne, nn, nmax = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_int()
@@ -100,5 +107,31 @@ def test_required_bytes_c2_fits_one_gpu(dg):
     nb = ctypes.c_size_t()
     dg.check(L.dg_solver_required_bytes(s, ctypes.byref(nb)))
     assert 1.0e9 < nb.value < 2.0e9
+    L.dg_solver_destroy(s)
+    L.dg_mesh_destroy(m)
+
+
+def test_mixed_order_mesh_info_and_solver_limits(dg):
+    L = dg.lib()
+    m = ctypes.c_void_p()
+    orders = [1, 2, 3, 6, 5, 4, 2, 2, 2]
+    d, _keep = dg.box_desc(3, 1, 1, (0, 0, 0), (1, 1, 1), False, 0.0, 3, orders=orders)
+    dg.check(L.dg_mesh_create_box(ctypes.byref(d), ctypes.byref(m)))
+    ne, nn, nmax = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_int()
+    dg.check(L.dg_mesh_info(m, ctypes.byref(ne), ctypes.byref(nn), ctypes.byref(nmax)))
+    assert (ne.value, nn.value, nmax.value) == (3, 2 * 3 * 4 + 7 * 6 * 5 + 27, 6)
+    s = ctypes.c_void_p()
+    for bad in (dict(Re=100.0), dict(precision="fp32_bulk")):
+        p = dg.physics(**bad)
+        assert L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)) == dg.DG_EUNSUPPORTED
+        assert b"mixed" in L.dg_last_error()
+    p = dg.physics(Ma=0.5)
+    dg.check(L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)))
+    nb = ctypes.c_size_t()
+    dg.check(L.dg_solver_required_bytes(s, ctypes.byref(nb)))
+    assert nb.value >= 8 * nn.value * (5 * 4 + 3 + 9 + 2)
+    # unbound: graph switch is host state, autotuning needs the device
+    assert L.dg_solver_use_graphs(s, 0) == dg.DG_OK
+    assert L.dg_autotune(s, None, None) == dg.DG_ESTATE
     L.dg_solver_destroy(s)
     L.dg_mesh_destroy(m)

@@ -1,0 +1,329 @@
+"""GPU parity of meshes with per-element anisotropic orders (section "Spatial p-adaptation":
+mortar coupling of p-nonconforming faces), and of HIP-graph replay of RK steps.
+
+Same floating-point bar as the uniform-order parity tests: per conserved variable the GPU
+residual lies within max(1e-12 |R|, 8 e64) of the oracle's long-double build, e64 being the
+difference between the oracle's double and long-double builds on the same input.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from helpers import to_conservative
+from paper_2206_09733_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+VORTEX_BOX = dict(lo=(-10.0,) * 3, hi=(10.0,) * 3)
+# isentropic vortex of strength 5 on the free stream rho = p = 1, advected along the diagonal
+# of the x-y plane at Mach 0.5 (sound speed sqrt(1.4))
+U_DIAG = 0.5 * math.sqrt(1.4) / math.sqrt(2.0)
+VORTEX = [5.0, 0.0, 0.0, U_DIAG, U_DIAG]
+
+
+@pytest.fixture(scope="module")
+def dg():
+    from paper_2206_09733_amd import dgsem
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    dgsem.lib()
+    return dgsem
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def layout(o):
+    """(offset, node count) of every element of an oracle solver."""
+    out = []
+    for e in range(o.E):
+        (n1, n2, n3), off = o.elem(e)
+        out.append((off, (n1 + 1) * (n2 + 1) * (n3 + 1)))
+    return out
+
+
+def per_var_max(A, lay):
+    m = np.zeros(5)
+    for off, nn in lay:
+        m = np.maximum(m, np.abs(A[5 * off:5 * (off + nn)]).reshape(5, nn).max(axis=1))
+    return m
+
+
+def assert_parity(name, Rg, R64, R80, lay, factor=8.0):
+    scale = per_var_max(R80, lay)
+    e64 = per_var_max(R64 - R80, lay)
+    eg = per_var_max(Rg - R80, lay)
+    tol = np.maximum(1e-12 * scale, factor * e64)
+    log(f"[{name}] |R|={np.array2string(scale, precision=2)} gpu-vs-fp80={np.array2string(eg, precision=2)} "
+        f"fp64-vs-fp80={np.array2string(e64, precision=2)}")
+    assert np.all(eg <= tol), (name, eg, tol)
+
+
+def perturbed(o, seed, amp=(0.02, 0.05, 0.02)):
+    """The oracle's current state with seeded random primitive perturbations at every node."""
+    U = o.state()
+    lay = layout(o)
+    drho, dv, dp = synth.primitive_perturbation(o.nodes, seed, amp)
+    out = np.empty_like(U)
+    for off, nn in lay:
+        u = U[5 * off:5 * (off + nn)].reshape(5, nn)
+        rho = u[0]
+        v = (u[1:4] / rho).T
+        p = 0.4 * (u[4] - 0.5 * rho * (v * v).sum(1))
+        s = slice(off, off + nn)
+        W = to_conservative(rho * (1 + drho[s]), v + dv[:, s].T, p * (1 + dp[s]))
+        out[5 * off:5 * (off + nn)] = W.T.reshape(-1)
+    return out
+
+
+def mixed_cfg(ex, ey, ez, seed, nlo=2, nhi=6, **kw):
+    """ex*ey*ez elements on the vortex box, orders per direction uniform in {nlo..nhi}."""
+    c = dict(ex=ex, ey=ey, ez=ez, orders=synth.mixed_orders(ex * ey * ez, seed=seed, lo=nlo, hi=nhi),
+             Ma=0.5, **VORTEX_BOX)
+    c.update(kw)
+    return c
+
+
+def gpu_solver(dg, c):
+    return dg.Solver(**{k: v for k, v in c.items()})
+
+
+# ------------------------------------------------------------------ geometry and initial state
+def test_mixed_geometry_parity(dg, orc):
+    c = mixed_cfg(3, 2, 2, seed=3, nlo=1, nhi=6, deform=True, amp=0.3)
+    log("mixed geometry")
+    o = orc.OracleSolver(**c)
+    o80 = orc.OracleSolver(**c, precision="fp80")
+    g = gpu_solver(dg, c)
+    assert g.nodes == o.nodes
+    Xg, Jag, Jg = g.geometry()
+    assert np.abs(Xg - o.coords()).max() < 1e-13
+    for name, a, b, b80 in (("Ja", Jag, o.metrics()[0], o80.metrics()[0]),
+                            ("J", Jg, o.metrics()[1], o80.metrics()[1])):
+        eg, e64 = np.abs(a - b80).max(), np.abs(b - b80).max()
+        log(f"[mixed geometry {name}] gpu-vs-fp80 {eg:.2e} fp64-vs-fp80 {e64:.2e} scale {np.abs(b80).max():.2e}")
+        assert eg <= max(1e-14 * np.abs(b80).max(), 8 * e64)
+
+
+def test_mixed_initial_condition_parity(dg, orc):
+    c = mixed_cfg(3, 3, 2, seed=4, deform=True)
+    o = orc.OracleSolver(**c)
+    g = gpu_solver(dg, c)
+    o.set_ic("vortex", VORTEX)
+    g.set_ic("vortex", VORTEX)
+    Uo, Ug = o.state(), g.state()
+    assert np.abs(Ug - Uo).max() <= 1e-14 * np.abs(Uo).max()
+
+
+# ------------------------------------------------------------------ residual
+@pytest.mark.parametrize("surf", ["roe", "llf", "ec", "central"])
+def test_mixed_residual_parity(dg, orc, surf):
+    """3x3x3 elements with orders drawn from {1..6} per direction on a deformed mesh: most faces
+    are p-nonconforming in one or both tangential directions."""
+    c = mixed_cfg(3, 3, 3, seed=10, nlo=1, nhi=6, deform=True, amp=0.3, surf=surf)
+    log(f"mixed residual {surf}")
+    o = orc.OracleSolver(**c)
+    o.set_ic("vortex", VORTEX)
+    U = perturbed(o, seed=20)
+    o.set_state(U)
+    o80 = orc.OracleSolver(**c, precision="fp80")
+    o80.set_state(U)
+    R64, R80 = o.residual(), o80.residual()
+    g = gpu_solver(dg, c)
+    g.set_state(U)
+    assert_parity(f"mixed {surf}", g.residual(), R64, R80, layout(o))
+
+
+def test_mixed_residual_central_volume_and_edge_meshes(dg, orc):
+    """Central volume flux; a single anisotropic element (every face its own periodic
+    neighbour, hence conforming); a row of two elements whose orders are permuted, so that both
+    x faces need a mortar in both tangential directions; a box that is not a cube."""
+    cases = [mixed_cfg(2, 3, 2, seed=5, vol="central", surf="llf", deform=True),
+             dict(ex=1, ey=1, ez=1, orders=np.array([[2, 5, 3]]), Ma=0.5, **VORTEX_BOX),
+             dict(ex=2, ey=1, ez=1, orders=np.array([[3, 2, 5], [5, 3, 2]]), Ma=0.5, **VORTEX_BOX),
+             dict(ex=5, ey=3, ez=1, orders=synth.mixed_orders(15, seed=6, lo=1, hi=4), Ma=0.5,
+                  lo=(0.0, 0.0, 0.0), hi=(1.0, 2.0, 0.5))]
+    for k, c in enumerate(cases):
+        log(f"mixed edge case {k}")
+        o = orc.OracleSolver(**c)
+        if k == 3:
+            o.set_ic("density_wave", [0.2, 1.0, 0.5, 0.0, 1.0, 2 * math.pi, math.pi, 4 * math.pi, 0.3])
+        else:
+            o.set_ic("vortex", VORTEX)
+        U = perturbed(o, seed=30 + k)
+        o.set_state(U)
+        o80 = orc.OracleSolver(**c, precision="fp80")
+        o80.set_state(U)
+        g = gpu_solver(dg, c)
+        g.set_state(U)
+        assert_parity(f"mixed edge {k}", g.residual(), o.residual(), o80.residual(), layout(o))
+
+
+def test_mixed_block_sizes_bitwise_equal_and_autotune(dg, orc):
+    c = mixed_cfg(4, 4, 4, seed=7, deform=True)
+    g = gpu_solver(dg, c)
+    g.set_ic("vortex", VORTEX)
+    Rs = {}
+    for b in (128, 256, 512):
+        g.set_block(b)
+        Rs[b] = g.residual()
+    assert np.array_equal(Rs[128], Rs[256]) and np.array_equal(Rs[256], Rs[512])
+    b, us = g.autotune()
+    log(f"[autotune 4^3 mixed] block {b} {us:.1f} us")
+    assert b in (128, 256, 512) and us > 0
+    assert np.array_equal(g.residual(), Rs[256])
+    with pytest.raises(dg.DgError):
+        g.set_block(64)
+
+
+# ------------------------------------------------------------------ invariants on the GPU path
+def test_mixed_gpu_freestream_and_conservation(dg, orc):
+    """A uniform state is steady on the affine mixed-order box (on curved meshes the mortar
+    interpolates the owner's metric terms, which keeps the fluxes single-valued but not the free
+    stream exact); the conserved totals are conserved on a curved mixed-order mesh."""
+    g = gpu_solver(dg, mixed_cfg(3, 3, 3, seed=8))
+    p = 1 / (1.4 * 0.25)
+    g.set_ic("uniform", [1.0, 0.4, 0.3, -0.2, p])
+    R = g.residual()
+    _, Ja, J = g.geometry()
+    scale = (p / 0.4 + p) * np.abs(Ja).max() / J.min() * 10
+    log(f"[mixed freestream] max|R| {np.abs(R).max():.2e} scale {scale:.2e}")
+    assert np.abs(R).max() < 1e-13 * scale
+    c = mixed_cfg(3, 3, 3, seed=8, deform=True, amp=0.3)
+    g = gpu_solver(dg, c)
+    g.set_ic("vortex", VORTEX)
+    R = g.residual()
+    _, Ja, J = g.geometry()
+    o = orc.OracleSolver(**c)
+    tot, mag = np.zeros(5), np.zeros(5)
+    for e in range(o.E):
+        (n1, n2, n3), off = o.elem(e)
+        w1, w2, w3 = orc.gll(n1)[1], orc.gll(n2)[1], orc.gll(n3)[1]
+        nn = (n1 + 1) * (n2 + 1) * (n3 + 1)
+        wq = (w3[:, None, None] * w2[None, :, None] * w1[None, None, :]).reshape(-1) * J[off:off + nn]
+        Re_ = R[5 * off:5 * off + 5 * nn].reshape(5, nn)
+        tot += Re_ @ wq
+        mag += np.abs(Re_) @ wq
+    log(f"[mixed conservation] totals {tot} magnitude {mag}")
+    assert np.all(np.abs(tot) < 1e-12 * mag.max()), (tot, mag)
+
+
+def test_mixed_entropy_conservation(dg, orc):
+    """EC volume and EC surface fluxes: the entropy production sum w J w(U).R of the GPU residual
+    equals the oracle's (on p-nonconforming faces the L2-projected EC flux is not entropy
+    conservative, so the sum is small but not zero; both sides must agree on it)."""
+    c = mixed_cfg(3, 3, 3, seed=9, surf="ec")
+    o = orc.OracleSolver(**c)
+    o.set_ic("vortex", VORTEX)
+    U = perturbed(o, seed=40, amp=(0.05, 0.1, 0.05))
+    o.set_state(U)
+    g = gpu_solver(dg, c)
+    g.set_state(U)
+    Rg = g.residual()
+    ent_g = o.entropy_production(Rg)
+    ent_o = o.entropy_production(o.residual())
+    ent_ref = abs(o.entropy_production(np.abs(Rg)))
+    log(f"[mixed entropy] gpu {ent_g:.3e} oracle {ent_o:.3e} scale {ent_ref:.3e}")
+    assert abs(ent_g - ent_o) < 1e-11 * ent_ref
+
+
+# ------------------------------------------------------------------ time integration and graphs
+def test_mixed_rk3_trajectory(dg, orc):
+    c = mixed_cfg(3, 3, 3, seed=11, deform=True)
+    o = orc.OracleSolver(**c)
+    o.set_ic("vortex", VORTEX)
+    U0 = o.state()
+    dt = o.suggest_dt(0.5)
+    o.rk3(dt, 5)
+    o80 = orc.OracleSolver(**c, precision="fp80")
+    o80.set_state(U0)
+    o80.rk3(dt, 5)
+    g = gpu_solver(dg, c)
+    g.set_state(U0)
+    assert abs(g.suggest_dt(0.5) - dt) < 1e-13 * dt
+    g.rk_step(dt, 5)
+    lay = layout(o)
+    Ug, Uo, U80 = g.state(), o.state(), o80.state()
+    dG, d64, d80 = Ug - U0, Uo - U0, U80 - U0
+    sc = per_var_max(d80, lay)
+    eg, e64 = per_var_max(dG - d80, lay), per_var_max(d64 - d80, lay)
+    log(f"[mixed RK, increment] gpu-vs-fp80 {eg / sc} fp64-vs-fp80 {e64 / sc}")
+    assert np.all(eg <= np.maximum(1e-12 * sc, 8 * e64))
+
+
+@pytest.mark.parametrize("case", ["uniform_ns", "mixed"])
+def test_graph_replay_equals_eager(dg, orc, case):
+    """RK steps replayed from captured graphs give bitwise the state of eager launches; several
+    replays with eager work and synchronisations between them, each checked."""
+    if case == "mixed":
+        c = mixed_cfg(3, 3, 3, seed=12, deform=True)
+        ic, params = "vortex", VORTEX
+    else:
+        c = dict(ex=3, N=4, deform=True, Ma=0.1, Re=1600.0)
+        ic, params = "tgv", None
+    ge = gpu_solver(dg, c)
+    gg = gpu_solver(dg, c)
+    ge.use_graphs(False)
+    ge.set_ic(ic, params)
+    gg.set_ic(ic, params)
+    dt = ge.suggest_dt(0.4)
+    for rep in range(4):
+        ge.rk_step(dt, 3)
+        gg.rk_step(dt, 3)  # several steps in one call: replayed
+        Ue, Ug = ge.state(), gg.state()
+        assert np.array_equal(Ue, Ug), (case, rep, np.abs(Ue - Ug).max())
+        ge.residual()      # eager work between replays
+        gg.residual()
+        gg.synchronize()
+    # single steps with a recurring dt are replayed too; a new dt is captured anew
+    for k in range(3):
+        ge.rk_step(dt, 1)
+        gg.rk_step(dt, 1)
+    ge.rk_step(0.5 * dt, 2)
+    gg.rk_step(0.5 * dt, 2)
+    assert np.array_equal(ge.state(), gg.state())
+    # a new state drops the graphs; replays continue from it
+    U = ge.state()
+    gg.set_state(U)
+    ge.set_state(U)
+    ge.rk_step(dt, 2)
+    gg.rk_step(dt, 2)
+    assert np.array_equal(ge.state(), gg.state())
+
+
+# ------------------------------------------------------------------ full size
+def test_mixed_full_size_residual_and_step(dg, orc):
+    """24^3 elements, orders (Nx, Ny, Nz) uniform in {2..6} (seed 0), isentropic vortex of strength
+    5 at Mach 0.5 advected diagonally, Euler split form: every node's residual and one RK3 step
+    against the oracle, in the launch configuration the benchmark times (autotuned block)."""
+    c = mixed_cfg(24, 24, 24, seed=0)
+    log("mixed 24^3: oracle fp64")
+    o = orc.OracleSolver(**c)
+    o.set_ic("vortex", VORTEX)
+    U = o.state()
+    R64 = o.residual()
+    log("mixed 24^3: oracle fp80")
+    o80 = orc.OracleSolver(**c, precision="fp80")
+    o80.set_state(U)
+    R80 = o80.residual()
+    log("mixed 24^3: gpu")
+    g = gpu_solver(dg, c)
+    g.set_ic("vortex", VORTEX)
+    assert np.abs(g.state() - U).max() <= 1e-14 * np.abs(U).max()
+    b, us = g.autotune()
+    log(f"[mixed 24^3] autotuned block {b}, {us:.1f} us per stage launch")
+    lay = layout(o)
+    assert_parity("mixed 24^3", g.residual(), R64, R80, lay)
+    dt = o.suggest_dt(0.5)
+    o.rk3(dt, 1)
+    o80.rk3(dt, 1)
+    g.rk_step(dt, 1)
+    dG, d64, d80 = g.state() - U, o.state() - U, o80.state() - U
+    sc = per_var_max(d80, lay)
+    eg, e64 = per_var_max(dG - d80, lay), per_var_max(d64 - d80, lay)
+    log(f"[mixed 24^3] one RK3 step, increment error: gpu-vs-fp80 {eg / sc} fp64-vs-fp80 {e64 / sc}")
+    assert np.all(eg <= np.maximum(1e-12 * sc, 8 * e64))
