@@ -38,33 +38,135 @@ def algorithmic_bytes_gradient(nodes, N, fp32):
     return nodes * (8 * 5 + 8 * 10 + (4 if fp32 else 8) * 4 * 6 * n * n / n ** 3)
 
 
-def run_gpu(precision, steps, warmup):
+def timed_steps(s, dt, steps, profile=True):
+    """Run `steps` RK3 steps between two events on the solver's stream.  With profile=True the
+    library also brackets every kernel of the timed steps with HIP events on that stream."""
     import torch
-    from paper_2206_09733_amd import dgsem
-    s = dgsem.Solver(**WORKLOAD, precision=precision)
-    s.set_ic("tgv")
-    dt = s.suggest_dt(0.5)
-    s.rk_step(dt, warmup)
-    s.synchronize()
-    stream = torch.cuda.current_stream()
+    stream = s.stream
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    if profile:
+        s.profile_begin()
     t0 = time.perf_counter()
     start.record(stream)
     s.rk_step(dt, steps)
     stop.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ev_ms = start.elapsed_time(stop)
-    # the same steps again with per-kernel HIP events (recorded by the library on its stream)
-    s.profile_begin()
-    s.rk_step(dt, steps)
-    prof = s.profile_end()
+    prof = s.profile_end() if profile else None
+    return start.elapsed_time(stop), wall, prof
+
+
+def run_gpu(precision, steps, warmup):
+    from paper_2206_09733_amd import dgsem
+    s = dgsem.Solver(**WORKLOAD, precision=precision)
+    s.set_ic("tgv")
+    dt = s.suggest_dt(0.5)
+    s.rk_step(dt, warmup)
+    s.synchronize()
+    ev_ms, wall, prof = timed_steps(s, dt, steps)
     d = s.diagnostics()
     out = dict(nodes=s.nodes, E=s.E, dt=dt, wall_s=wall, event_ms=ev_ms, prof=prof,
                finite=d["nonfinite"] == 0, ke=d["ke"])
     s.close()
     return out
+
+
+MIXED = dict(ex=24, lo=(-10.0,) * 3, hi=(10.0,) * 3, Ma=0.5, vol="ec", surf="roe")
+# isentropic vortex of strength 5, free stream rho = p = 1 moving along (1, 1, 0)/sqrt 2 at Mach 0.5
+VORTEX = [5.0, 0.0, 0.0, 0.5 * math.sqrt(1.4 / 2.0), 0.5 * math.sqrt(1.4 / 2.0)]
+
+
+def run_mixed(steps, warmup):
+    """24^3 elements with orders (Nx, Ny, Nz) uniform in {2..6} (seed 0), Euler, FP64, graph
+    replay of the RK steps, block size from the autotuner."""
+    from paper_2206_09733_amd import dgsem, synth
+    orders = synth.mixed_orders(24 ** 3, seed=0)
+    s = dgsem.Solver(**MIXED, orders=orders)
+    s.set_ic("vortex", VORTEX)
+    block, tune_us = s.autotune()
+    dt = s.suggest_dt(0.5)
+    s.rk_step(dt, warmup)
+    ev_ms, _, _ = timed_steps(s, dt, steps, profile=False)
+    _, _, prof = timed_steps(s, dt, max(2, steps // 5))
+    st = prof["stage"]
+    d = s.diagnostics()
+    out = {"workload": "Euler isentropic vortex (strength 5, Mach 0.5, diagonal) on [-10,10]^3, "
+                       "24^3 hex, per-element orders (Nx,Ny,Nz) uniform in {2..6} (seed 0), EC split "
+                       "form + Roe, mortar faces, RK3 CFL 0.5, graph replay",
+           "elements": s.E, "nodes": s.nodes, "dof": 5 * s.nodes, "dtype": "f64",
+           "value": round(5 * s.nodes * 3 * steps / (ev_ms / 1e3) / 1e9, 3), "unit": "GDOF/s",
+           "ms_per_step": round(ev_ms / steps, 4), "steps": steps, "autotuned_block": block,
+           "stage_avg_us": round(st["ms"] / st["launches"] * 1e3, 2),
+           "state_finite": d["nonfinite"] == 0}
+    s.close()
+    return out
+
+
+def run_batch_vs_solo(n=32, steps=50):
+    """The first n solves of the serving stream, each run alone one after the other, and the same
+    n as one batch (all present at the start): aggregate throughput of both forms."""
+    import torch
+    from paper_2206_09733_amd import dgsem, synth
+    specs = synth.serving_requests(n, seed=0)
+    work = sum(5 * q["E"] ** 3 * (q["N"] + 1) ** 3 * 3 * steps for q in specs)
+
+    def make():
+        out = []
+        for q in specs:
+            s = dgsem.Solver(q["E"], N=q["N"], Ma=q["Ma"], Re=q["Re"])
+            s.set_ic("tgv")
+            out.append((s, s.suggest_dt(0.5)))
+        return out
+    solo = make()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s, dt in solo:
+        s.rk_step(dt, steps)
+    torch.cuda.synchronize()
+    t_solo = time.perf_counter() - t0
+    ref = [s.state() for s, _ in solo]
+    for s, _ in solo:
+        s.close()
+    members = make()
+    b = dgsem.Batch([s for s, _ in members])
+    dts = [dt for _, dt in members]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.rk_step(dts, steps)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    same = all((s.state() == r).all() for (s, _), r in zip(members, ref))
+    launches = b.launches_per_stage()
+    b.close()
+    for s, _ in members:
+        s.close()
+    return {"solves": n, "steps": steps, "solo_gdof_s": round(work / t_solo / 1e9, 3),
+            "batch_gdof_s": round(work / t_batch / 1e9, 3), "speedup": round(t_solo / t_batch, 3),
+            "launches_per_stage_batched": launches, "launches_per_stage_solo": n,
+            "results_bitwise_equal": bool(same)}
+
+
+def run_serving(n, rate, steps, budget_gib, chunk):
+    """The serving stream: n solves from synth.serving_requests (seed 0) arriving as a Poisson
+    process of the given rate (seed 0), admitted under an HBM budget, continuously batched."""
+    from paper_2206_09733_amd import serve, synth
+    reqs = serve.requests_from_specs(synth.serving_requests(n, seed=0),
+                                     synth.poisson_arrivals(n, rate, seed=0), steps=steps)
+    ex = serve.GpuExecutor(keep_state=False)
+    sch = serve.Scheduler(ex, budget_gib * 2 ** 30, max_active=64, chunk_steps=chunk)
+    t0 = time.perf_counter()
+    res = sch.run(reqs)
+    wall = time.perf_counter() - t0
+    ex.close()
+    st = serve.summarize(reqs, res, wall)
+    st.update({"requests": n, "arrival_rate_per_s": rate, "steps_per_solve": steps,
+               "hbm_budget_gib": budget_gib, "chunk_steps": chunk, "chunks": sch.chunks,
+               "peak_active": sch.peak_active, "peak_gib": round(sch.peak_bytes / 2 ** 30, 2),
+               "nonfinite_results": sum(1 for r in res if r.diagnostics and r.diagnostics["nonfinite"])})
+    for k in ("p50_s", "p99_s", "mean_s", "wall_s", "gdof_stage_per_s"):
+        st[k] = round(st[k], 4)
+    return st
 
 
 def run_cpu_baseline(budget_s=12.0, max_steps=4):
@@ -94,6 +196,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-fp32", action="store_true")
+    ap.add_argument("--skip-mixed", action="store_true")
+    ap.add_argument("--skip-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--serve-rate", type=float, default=12.0, help="Poisson arrivals per second")
+    ap.add_argument("--serve-steps", type=int, default=200)
+    ap.add_argument("--serve-budget-gib", type=float, default=32.0)
     ap.add_argument("--copy-reference-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (a known-size reference "
                          "for hardware traffic counters)")
@@ -124,7 +232,7 @@ def main():
     b_grad = algorithmic_bytes_gradient(nodes, N, False)
     achieved = b_stage / avg_stage_s / 1e9
     result = {
-        "metric": "GDOF-updates/s per RK stage",
+        "metric": "GDOF-updates/s per RK stage (plain FP64 vs batched FP32-bulk); p50/p99 solve latency",
         "value": round(value, 3),
         "unit": "GDOF/s",
         "n_gpus": 1,
@@ -157,6 +265,12 @@ def main():
         result["fp32_bulk"] = {"value": round(v32, 3), "unit": "GDOF/s",
                                "ms_per_step": round(r32["event_ms"] / args.steps, 4),
                                "speedup_vs_fp64": round(v32 / value, 3)}
+    if not args.skip_mixed:
+        result["mixed_order"] = run_mixed(max(10, args.steps // 2), args.warmup)
+    if not args.skip_serve:
+        result["batch_vs_solo"] = run_batch_vs_solo()
+        result["serving"] = run_serving(args.serve_requests, args.serve_rate, args.serve_steps,
+                                        args.serve_budget_gib, 20)
     if rank == 0 and not args.no_cpu_baseline:
         result["cpu_baseline"] = run_cpu_baseline()
     if rank == 0:

@@ -15,7 +15,7 @@
  *  - Status: every int-returning call returns DG_OK (0) or a negative DG_E* code; the message
  *    of the last failure on the calling thread is returned by dg_last_error().  Nothing
  *    aborts or throws across the ABI.
- *  - Ownership: dg_mesh / dg_solver handles are owned by the library and freed by
+ *  - Ownership: dg_mesh / dg_solver / dg_batch handles are owned by the library and freed by
  *    the matching *_destroy.  Device memory is owned by the caller: dg_solver_required_bytes
  *    states the size, the caller allocates it (any device allocator) and passes it to
  *    dg_solver_bind; the library sub-allocates inside it and never frees it.  The buffer must
@@ -73,6 +73,7 @@ enum { DG_IC_UNIFORM = 0, DG_IC_TGV = 1, DG_IC_VORTEX = 2, DG_IC_DENSITY_WAVE = 
 
 typedef struct dg_mesh dg_mesh;
 typedef struct dg_solver dg_solver;
+typedef struct dg_batch dg_batch;
 
 /* Periodic box of ex*ey*ez hexahedra on [lo, hi]; with DG_DEFORM_SINSIN each node is moved by
  * (a sin y sin z, a sin z sin x, a sin x sin y) evaluated at its undeformed position
@@ -196,6 +197,32 @@ typedef struct {
 int dg_profile_begin(dg_solver* s);
 int dg_profile_end(dg_solver* s, dg_profile* out);
 void dg_solver_destroy(dg_solver* s);
+
+/* ------------------------------------------------------------------ batches
+ * Independent solvers advanced together (ensembles, parameter sweeps, the solves admitted by a
+ * serving loop).  Members of one polynomial order and precision (and all viscous or all
+ * inviscid) are advanced by one launch per kernel and stage that covers the elements of all of
+ * them (at most 32 members per launch), so that many small solves fill the GPU together;
+ * mixed-order members are launched one by one.  Each member keeps its own state, step size and
+ * buffer parity; the result of a member is bitwise the same as when it is stepped alone.
+ *
+ * Create a batch of n bound solvers whose steps are enqueued on hip_stream (hipStream_t, NULL =
+ * default).  The members may be bound to other streams: the caller orders the batch's steps
+ * after the work the members have pending there (e.g. by synchronising those streams) and does
+ * not use a member on its own stream while batch steps are pending.  The solvers stay owned by
+ * the caller and must outlive the batch.  Errors: DG_EINVAL for NULL, n < 1 or a repeated
+ * member; DG_ESTATE for an unbound member. */
+int dg_batch_create(dg_solver* const* solvers, int n, void* hip_stream, dg_batch** out);
+/* Advance every member nsteps steps of the RK3 of dg_rk_step, member i with step dts[i] (n
+ * doubles).  Only enqueues work on the batch's stream.  Like dg_rk_step, the launches of one
+ * step are captured into a HIP graph and replayed when several steps are taken or the same
+ * dts recur (a few graphs are kept, keyed by dts and the members' buffer parities). */
+int dg_batch_rk_step(dg_batch* b, const double* dts, int nsteps);
+/* enable = 0 disables graph replay of the batch (and drops its graphs). */
+int dg_batch_use_graphs(dg_batch* b, int enable);
+/* Kernel launches per RK stage of the batch (the one-launch-per-group structure made visible). */
+int dg_batch_launches(const dg_batch* b, int* launches_per_stage);
+void dg_batch_destroy(dg_batch* b);
 
 /* Message of the last failure on the calling thread ("" if none). */
 const char* dg_last_error(void);

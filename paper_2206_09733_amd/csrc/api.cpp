@@ -72,12 +72,13 @@ struct dg_solver {
   hipGraphExec_t graph[2] = {nullptr, nullptr};
   double graph_dt[2] = {0.0, 0.0};
   double last_dt = 0.0;
+  dg::View* dev_view = nullptr;      // device copy of v (inside the caller's buffer)
 };
 
 namespace {
 
 struct Plan {
-  size_t tab, nbr, X, Ja, J, invJ, U0, U1, dU, R, Fvf, part, diag, elem, work, mtab, total;
+  size_t tab, nbr, X, Ja, J, invJ, U0, U1, dU, R, Fvf, part, diag, elem, work, mtab, self, total;
   size_t tab_n, mtab_n;
 };
 
@@ -123,6 +124,7 @@ Plan make_plan(const dg_solver* s) {
   p.elem = mixed ? take(sizeof(int4) * E) : 0;
   p.work = mixed ? take(sizeof(int) * E) : 0;
   p.mtab = mixed ? take(sizeof(double) * p.mtab_n) : 0;
+  p.self = take(sizeof(dg::View));  // device copy of the View, read by batched launches
   p.total = off;
   return p;
 }
@@ -207,6 +209,14 @@ void drop_graphs(dg_solver* s) {
   }
 }
 
+// copy the View to its device slot (synchronously: s->v is the source)
+int upload_view(dg_solver* s) {
+  DG_HIP(hipMemcpyAsync(s->dev_view, &s->v, sizeof(dg::View), hipMemcpyHostToDevice, s->stream),
+         "upload view");
+  DG_HIP(hipStreamSynchronize(s->stream), "upload view");
+  return DG_OK;
+}
+
 // FP32-bulk reference state: volume means of density and pressure of the state just set
 // (any constant is exact; the closer to the state, the smaller the deviations).
 int update_reference(dg_solver* s) {
@@ -220,7 +230,7 @@ int update_reference(dg_solver* s) {
     return fail(DG_ENONFINITE, "state has no positive finite mean density and pressure");
   s->v.rho_r = h[0] / h[13];
   s->v.p_r = h[14] / h[13];
-  return DG_OK;
+  return upload_view(s);
 }
 
 // Record the launches of one RK step that starts from state buffer s->cur on the library's
@@ -411,6 +421,7 @@ int dg_solver_bind(dg_solver* s, void* dev_ptr, size_t bytes, void* hip_stream) 
   v.elem = mixed ? reinterpret_cast<const int4*>(b + p.elem) : nullptr;
   v.work = mixed ? reinterpret_cast<const int*>(b + p.work) : nullptr;
   v.mtab = mixed ? reinterpret_cast<const double*>(b + p.mtab) : nullptr;
+  s->dev_view = reinterpret_cast<dg::View*>(b + p.self);
   s->stream = static_cast<hipStream_t>(hip_stream);
 
   // Lobatto tables: of the one order, or of every order (at tab_off[N]) for a mixed mesh
@@ -479,6 +490,8 @@ int dg_solver_bind(dg_solver* s, void* dev_ptr, size_t bytes, void* hip_stream) 
   }
   DG_HIP(hipMemsetAsync(v.dU, 0, sizeof(double) * 5 * s->ntot, s->stream), "clear RK register");
   DG_HIP(hipStreamSynchronize(s->stream), "geometry");
+  int rc = upload_view(s);
+  if (rc) return rc;
   DG_HIP(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking), "capture stream");
   s->bound = true;
   s->cur = 0;
@@ -738,6 +751,203 @@ int dg_profile_end(dg_solver* s, dg_profile* out) {
   s->prof.clear();
   s->ev_used = 0;
   return DG_OK;
+}
+
+// ------------------------------------------------------------------ batches of solvers
+struct dg_batch {
+  struct Group {  // uniform-order members of one order and precision, viscous or not
+    int N;
+    bool fp32, visc;
+    std::vector<int> idx;
+  };
+  struct Graph {
+    std::vector<int> par;       // state buffer of every member at the step start
+    std::vector<double> dts;
+    hipGraphExec_t exec;
+  };
+  std::vector<dg_solver*> m;
+  std::vector<Group> groups;    // each with at most kMaxBatch members
+  std::vector<int> mixed;       // members advanced by launches of their own
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;
+  std::vector<Graph> graphs;    // most recent last
+  std::vector<double> last_dts;
+  bool use_graphs = true;
+};
+
+namespace {
+
+constexpr size_t kBatchGraphs = 4;
+
+void batch_drop_graphs(dg_batch* b) {
+  if (b->graphs.empty()) return;
+  (void)hipStreamSynchronize(b->stream);
+  for (auto& g : b->graphs) (void)hipGraphExecDestroy(g.exec);
+  b->graphs.clear();
+}
+
+// one RK stage of every member on stream st; afterwards every member's state has moved to its
+// other buffer
+hipError_t batch_stage(dg_batch* b, const double* dts, int k, hipStream_t st) {
+  for (const auto& g : b->groups) {
+    dg::BatchArgs B;
+    std::memset(&B, 0, sizeof(B));
+    B.n = (int)g.idx.size();
+    B.start[0] = 0;
+    for (int j = 0; j < B.n; j++) {
+      dg_solver* s = b->m[g.idx[j]];
+      B.view[j] = s->dev_view;
+      B.cur[j] = s->cur;
+      B.dt[j] = dts[g.idx[j]];
+      B.start[j + 1] = B.start[j] + (int)s->E;
+    }
+    hipError_t e;
+    if (g.visc) {
+      e = dg::launch_gradient_batch(B, g.N, g.fp32, st);
+      if (e != hipSuccess) return e;
+    }
+    e = dg::launch_stage_batch(B, g.N, g.fp32, g.visc, kRkA[k], kRkB[k], dg::kModeRK, st);
+    if (e != hipSuccess) return e;
+  }
+  for (int i : b->mixed) {
+    dg_solver* s = b->m[i];
+    hipError_t e = dg::launch_stage_mixed(s->v, s->cur, dts[i], kRkA[k], kRkB[k], dg::kModeRK, s->mix_block, st);
+    if (e != hipSuccess) return e;
+  }
+  for (dg_solver* s : b->m) s->cur ^= 1;
+  return hipSuccess;
+}
+
+int batch_capture(dg_batch* b, const double* dts) {
+  const size_t n = b->m.size();
+  dg_batch::Graph G;
+  G.par.resize(n);
+  for (size_t i = 0; i < n; i++) G.par[i] = b->m[i]->cur;
+  G.dts.assign(dts, dts + n);
+  hipGraph_t g = nullptr;
+  hipError_t err = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (err == hipSuccess) {
+    for (int k = 0; k < 3 && err == hipSuccess; k++) err = batch_stage(b, dts, k, b->cap_stream);
+    const hipError_t e2 = hipStreamEndCapture(b->cap_stream, &g);
+    if (err == hipSuccess) err = e2;
+  }
+  for (size_t i = 0; i < n; i++) b->m[i]->cur = G.par[i];  // capture launched nothing
+  if (err != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return hip_fail(err, "capture of a batch RK step");
+  }
+  err = hipGraphInstantiate(&G.exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (err != hipSuccess) return hip_fail(err, "instantiation of the batch RK-step graph");
+  if (b->graphs.size() == kBatchGraphs) {
+    (void)hipStreamSynchronize(b->stream);
+    (void)hipGraphExecDestroy(b->graphs.front().exec);
+    b->graphs.erase(b->graphs.begin());
+  }
+  b->graphs.push_back(std::move(G));
+  return DG_OK;
+}
+
+}  // namespace
+
+int dg_batch_create(dg_solver* const* solvers, int n, void* hip_stream, dg_batch** out) {
+  if (!solvers || !out) return fail(DG_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (n < 1) return fail(DG_EINVAL, "a batch needs at least one solver");
+  for (int i = 0; i < n; i++) {
+    int rc = check_bound(solvers[i]);
+    if (rc) return rc;
+    for (int j = 0; j < i; j++)
+      if (solvers[j] == solvers[i]) return fail(DG_EINVAL, "a solver appears twice in the batch");
+  }
+  dg_batch* b = new dg_batch;
+  b->m.assign(solvers, solvers + n);
+  b->stream = static_cast<hipStream_t>(hip_stream);
+  for (int i = 0; i < n; i++) {
+    const dg_solver* s = solvers[i];
+    if (s->v.mixed) {
+      b->mixed.push_back(i);
+      continue;
+    }
+    const bool fp32 = s->v.fp32 != 0, visc = s->v.viscous != 0;
+    dg_batch::Group* g = nullptr;
+    for (auto& x : b->groups)
+      if (x.N == s->v.N && x.fp32 == fp32 && x.visc == visc && (int)x.idx.size() < dg::kMaxBatch) g = &x;
+    if (!g) {
+      b->groups.push_back({s->v.N, fp32, visc, {}});
+      g = &b->groups.back();
+    }
+    g->idx.push_back(i);
+  }
+  long long blocks = 0;
+  for (const auto& g : b->groups) {
+    blocks = 0;
+    for (int i : g.idx) blocks += b->m[i]->E;
+    if (blocks >= (1LL << 31)) {
+      delete b;
+      return fail(DG_EINVAL, "a batched launch would exceed 2^31 workgroups");
+    }
+  }
+  hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete b;
+    return hip_fail(e, "capture stream");
+  }
+  *out = b;
+  return DG_OK;
+}
+
+int dg_batch_rk_step(dg_batch* b, const double* dts, int nsteps) {
+  if (!b || !dts) return fail(DG_EINVAL, "NULL argument");
+  if (nsteps < 0) return fail(DG_EINVAL, "nsteps must be >= 0");
+  const size_t n = b->m.size();
+  for (size_t i = 0; i < n; i++)
+    if (!std::isfinite(dts[i]) || !(dts[i] > 0)) return fail(DG_EINVAL, "every dt must be positive and finite");
+  const bool same = b->last_dts.size() == n && std::equal(dts, dts + n, b->last_dts.begin());
+  const bool replay = b->use_graphs && nsteps > 0 && (nsteps > 1 || same);
+  b->last_dts.assign(dts, dts + n);
+  for (int it = 0; it < nsteps; it++) {
+    if (!replay) {
+      for (int k = 0; k < 3; k++) DG_HIP(batch_stage(b, dts, k, b->stream), "batch RK stage kernels");
+      continue;
+    }
+    const dg_batch::Graph* G = nullptr;
+    for (const auto& g : b->graphs) {
+      bool hit = std::equal(dts, dts + n, g.dts.begin());
+      for (size_t i = 0; hit && i < n; i++) hit = g.par[i] == b->m[i]->cur;
+      if (hit) G = &g;
+    }
+    if (!G) {
+      int rc = batch_capture(b, dts);
+      if (rc) return rc;
+      G = &b->graphs.back();
+    }
+    DG_HIP(hipGraphLaunch(G->exec, b->stream), "batch RK-step graph launch");
+    for (dg_solver* s : b->m) s->cur ^= 1;
+  }
+  return DG_OK;
+}
+
+int dg_batch_use_graphs(dg_batch* b, int enable) {
+  if (!b) return fail(DG_EINVAL, "NULL batch");
+  b->use_graphs = enable != 0;
+  if (!b->use_graphs) batch_drop_graphs(b);
+  return DG_OK;
+}
+
+int dg_batch_launches(const dg_batch* b, int* launches_per_stage) {
+  if (!b || !launches_per_stage) return fail(DG_EINVAL, "NULL argument");
+  int k = 0;
+  for (const auto& g : b->groups) k += g.visc ? 2 : 1;
+  *launches_per_stage = k + (int)b->mixed.size();
+  return DG_OK;
+}
+
+void dg_batch_destroy(dg_batch* b) {
+  if (!b) return;
+  batch_drop_graphs(b);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  delete b;
 }
 
 void dg_solver_destroy(dg_solver* s) {

@@ -33,6 +33,14 @@ __device__ __forceinline__ int block_element(int E) {
   return b;
 }
 
+// Workgroup -> (member, element) of a batched launch, XCD-aware over the whole grid.
+__device__ __forceinline__ void batch_member(const BatchArgs& B, int& m, int& e) {
+  const int b = block_element(B.start[B.n]);
+  m = 0;
+  while (m + 1 < B.n && b >= B.start[m + 1]) m++;
+  e = b - B.start[m];
+}
+
 // node index of reference indices (i_d = id, tangential p, r) on a face normal to d
 template <int n>
 __device__ __forceinline__ int face_node(int d, int id, int p, int r) {

@@ -59,6 +59,18 @@ struct View {
   int mort_off[kMaxOrder + 1][kMaxOrder + 1];
 };
 
+// Several solvers of one order and precision advanced by one launch: workgroup b of the grid
+// works on element b - start[m] of member m (start[m] <= b < start[m+1]); each member's View
+// lives in device memory (a copy inside the member's own buffer).
+constexpr int kMaxBatch = 32;
+struct BatchArgs {
+  const View* view[kMaxBatch];
+  int start[kMaxBatch + 1];
+  int cur[kMaxBatch];
+  double dt[kMaxBatch];
+  int n;
+};
+
 // Launchers (kernels.hip).  All enqueue on `st` and return the hipError_t of the launch.
 hipError_t launch_geometry(const View& v, hipStream_t st);
 hipError_t launch_ic(const View& v, int cur, int ic, const double* params, hipStream_t st);
@@ -69,6 +81,11 @@ hipError_t launch_stage(const View& v, int cur, double dt, double rkA, double rk
                         hipStream_t st);
 hipError_t launch_diagnostics(const View& v, int cur, hipStream_t st);
 hipError_t launch_diag_final(const View& v, hipStream_t st);  // partials -> diag, fixed order
+// batched Navier-Stokes gradient pass and stage of members of order N (all viscous, or all
+// inviscid for the stage), FP32-bulk or FP64
+hipError_t launch_gradient_batch(const BatchArgs& B, int N, bool fp32, hipStream_t st);
+hipError_t launch_stage_batch(const BatchArgs& B, int N, bool fp32, bool visc, double rkA, double rkB,
+                              int mode, hipStream_t st);
 
 // mixed-order meshes (kernels_mixed.hip); block = threads per element workgroup of the stage
 constexpr int kMixMaxOrder = 6;

@@ -151,9 +151,8 @@ __global__ void ic_kernel(View v, int cur, int ic, IcParams P) {
 // Lifted gradient of (v, T) and, on the six faces, the contravariant viscous flux along the
 // face normal direction: Fvf[e][2d+side][c][face node].
 template <int N, typename T>
-__global__ void __launch_bounds__(nthreads_for(N)) grad_kernel(View v, int cur) {
+__device__ __forceinline__ void grad_body(const View& v, const int e, const int cur) {
   constexpr int n = N + 1, nn = n * n * n, nf = n * n, NT = nthreads_for(N);
-  const int e = block_element(v.E);
   const int t = threadIdx.x;
   const bool act = t < nn;
   const int ti = t % n, tj = (t / n) % n, tk = t / nf;
@@ -218,6 +217,18 @@ __global__ void __launch_bounds__(nthreads_for(N)) grad_kernel(View v, int cur) 
   }
 }
 
+template <int N, typename T>
+__global__ void __launch_bounds__(nthreads_for(N)) grad_kernel(View v, int cur) {
+  grad_body<N, T>(v, block_element(v.E), cur);
+}
+
+template <int N, typename T>
+__global__ void __launch_bounds__(nthreads_for(N)) grad_batch_kernel(BatchArgs B) {
+  int m, e;
+  batch_member(B, m, e);
+  grad_body<N, T>(*B.view[m], e, B.cur[m]);
+}
+
 // ------------------------------------------------------------------ stage kernel
 // Residual of one element and, in RK mode, the low-storage update
 //   dU <- A dU + dt R;  U_out <- U_in + B dU   (dU not read when A = 0).
@@ -229,13 +240,11 @@ __global__ void __launch_bounds__(nthreads_for(N)) grad_kernel(View v, int cur) 
 __host__ __device__ constexpr int stage_waves_per_eu(int N) { return N <= 5 ? 3 : 2; }
 
 template <int N, typename T, bool VISC>
-__global__ void __launch_bounds__(nthreads_for(N))
-    __attribute__((amdgpu_waves_per_eu(stage_waves_per_eu(N))))
-    stage_kernel(View v, int cur, double dt, double rkA, double rkB, int mode) {
+__device__ __forceinline__ void stage_body(const View& v, const int e, const int cur, const double dt,
+                                           const double rkA, const double rkB, const int mode) {
   constexpr int n = N + 1, nn = n * n * n, nf = n * n, NT = nthreads_for(N);
   constexpr int np = n * (n - 1) / 2;  // pairs (a < b) on one line of n nodes
   constexpr int P = nf * np;           // pairs per direction
-  const int e = block_element(v.E);
   const int t = threadIdx.x;
   const bool act = t < nn;
   const int ti = t % n, tj = (t / n) % n, tk = t / nf;
@@ -474,6 +483,22 @@ __global__ void __launch_bounds__(nthreads_for(N))
   }
 }
 
+template <int N, typename T, bool VISC>
+__global__ void __launch_bounds__(nthreads_for(N))
+    __attribute__((amdgpu_waves_per_eu(stage_waves_per_eu(N))))
+    stage_kernel(View v, int cur, double dt, double rkA, double rkB, int mode) {
+  stage_body<N, T, VISC>(v, block_element(v.E), cur, dt, rkA, rkB, mode);
+}
+
+template <int N, typename T, bool VISC>
+__global__ void __launch_bounds__(nthreads_for(N))
+    __attribute__((amdgpu_waves_per_eu(stage_waves_per_eu(N))))
+    stage_batch_kernel(BatchArgs B, double rkA, double rkB, int mode) {
+  int m, e;
+  batch_member(B, m, e);
+  stage_body<N, T, VISC>(*B.view[m], e, B.cur[m], B.dt[m], rkA, rkB, mode);
+}
+
 // ------------------------------------------------------------------ diagnostics (FP64)
 // slots: 0-4 integral of U, 5 integral of -rho s, 6 integral of -rho s/(gamma-1), 7 integral of
 // rho|v|^2/2, 8 integral of rho|curl v|^2/2, 9 max(|v|+c), 10 min rho, 11 min p,
@@ -670,6 +695,58 @@ hipError_t launch_stage(const View& v, int cur, double dt, double rkA, double rk
 }
 
 hipError_t launch_diagnostics(const View& v, int cur, hipStream_t st) { DG_DISPATCH(diag_n, v, cur, st) }
+
+template <int N, typename T>
+static hipError_t gradient_batch_nt(const BatchArgs& B, hipStream_t st) {
+  hipLaunchKernelGGL((grad_batch_kernel<N, T>), dim3(B.start[B.n]), dim3(nthreads_for(N)), 0, st, B);
+  return hipGetLastError();
+}
+
+template <int N>
+static hipError_t gradient_batch_n(const BatchArgs& B, bool fp32, hipStream_t st) {
+  return fp32 ? gradient_batch_nt<N, float>(B, st) : gradient_batch_nt<N, double>(B, st);
+}
+
+template <int N, typename T>
+static hipError_t stage_batch_nt(const BatchArgs& B, bool visc, double a, double b, int mode,
+                                 hipStream_t st) {
+  const dim3 grid(B.start[B.n]), block(nthreads_for(N));
+  if (visc)
+    hipLaunchKernelGGL((stage_batch_kernel<N, T, true>), grid, block, 0, st, B, a, b, mode);
+  else
+    hipLaunchKernelGGL((stage_batch_kernel<N, T, false>), grid, block, 0, st, B, a, b, mode);
+  return hipGetLastError();
+}
+
+template <int N>
+static hipError_t stage_batch_n(const BatchArgs& B, bool fp32, bool visc, double a, double b, int mode,
+                                hipStream_t st) {
+  return fp32 ? stage_batch_nt<N, float>(B, visc, a, b, mode, st)
+              : stage_batch_nt<N, double>(B, visc, a, b, mode, st);
+}
+
+#define DG_DISPATCH_N(NV, FN, ...)                    \
+  switch (NV) {                                       \
+    case 1: return FN<1>(__VA_ARGS__);                \
+    case 2: return FN<2>(__VA_ARGS__);                \
+    case 3: return FN<3>(__VA_ARGS__);                \
+    case 4: return FN<4>(__VA_ARGS__);                \
+    case 5: return FN<5>(__VA_ARGS__);                \
+    case 6: return FN<6>(__VA_ARGS__);                \
+    case 7: return FN<7>(__VA_ARGS__);                \
+    default: return hipErrorInvalidValue;             \
+  }
+
+hipError_t launch_gradient_batch(const BatchArgs& B, int N, bool fp32, hipStream_t st) {
+  if (B.n < 1 || B.n > kMaxBatch) return hipErrorInvalidValue;
+  DG_DISPATCH_N(N, gradient_batch_n, B, fp32, st)
+}
+
+hipError_t launch_stage_batch(const BatchArgs& B, int N, bool fp32, bool visc, double rkA, double rkB,
+                              int mode, hipStream_t st) {
+  if (B.n < 1 || B.n > kMaxBatch) return hipErrorInvalidValue;
+  DG_DISPATCH_N(N, stage_batch_n, B, fp32, visc, rkA, rkB, mode, st)
+}
 
 hipError_t launch_diag_final(const View& v, hipStream_t st) {
   hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(256), 0, st, v);

@@ -54,7 +54,8 @@ EXPORTS = ["dg_last_error", "dg_mesh_create_box", "dg_mesh_destroy", "dg_mesh_in
            "dg_set_initial_condition", "dg_set_state", "dg_get_state", "dg_residual", "dg_rk_step",
            "dg_diagnostics", "dg_suggest_dt", "dg_get_geometry", "dg_device_pointers",
            "dg_synchronize", "dg_solver_destroy", "dg_profile_begin", "dg_profile_end",
-           "dg_solver_use_graphs", "dg_autotune", "dg_solver_set_block"]
+           "dg_solver_use_graphs", "dg_autotune", "dg_solver_set_block", "dg_batch_create",
+           "dg_batch_rk_step", "dg_batch_use_graphs", "dg_batch_launches", "dg_batch_destroy"]
 
 _lib = None
 
@@ -73,6 +74,10 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2206_09733_amd.build`"
                            " (there is no CPU fallback)")
+    # PyTorch ships its own HIP runtime under the same soname: load it first, so that the
+    # library binds to it and the process holds one runtime (torch's device pointers and
+    # streams are then valid in the library)
+    import torch  # noqa: F401
     L = _c.CDLL(LIB_PATH)
     vp = _c.c_void_p
     L.dg_last_error.restype = _c.c_char_p
@@ -100,6 +105,12 @@ def lib():
     L.dg_solver_use_graphs.argtypes = [vp, _c.c_int]
     L.dg_autotune.argtypes = [vp, _c.POINTER(_c.c_int), _dp]
     L.dg_solver_set_block.argtypes = [vp, _c.c_int]
+    L.dg_batch_create.argtypes = [_c.POINTER(vp), _c.c_int, vp, _c.POINTER(vp)]
+    L.dg_batch_rk_step.argtypes = [vp, _dp, _c.c_int]
+    L.dg_batch_use_graphs.argtypes = [vp, _c.c_int]
+    L.dg_batch_launches.argtypes = [vp, _c.POINTER(_c.c_int)]
+    L.dg_batch_destroy.argtypes = [vp]
+    L.dg_batch_destroy.restype = None
     _lib = L
     return L
 
@@ -266,6 +277,49 @@ class Solver:
             lib().dg_solver_destroy(self.h)
             self.h = None
         self.buf = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Solvers advanced together on one stream (one launch per order/precision group).
+
+    `stream` (a torch.cuda.Stream) defaults to the first member's stream.  Work the members
+    have pending on other streams must be complete (or ordered before) the batch's steps.
+    """
+
+    def __init__(self, solvers, stream=None):
+        self.h = None
+        self.solvers = list(solvers)
+        self.stream = self.solvers[0].stream if stream is None else stream
+        arr = (_c.c_void_p * len(self.solvers))(*[s.h for s in self.solvers])
+        h = _c.c_void_p()
+        check(lib().dg_batch_create(arr, len(self.solvers), _c.c_void_p(self.stream.cuda_stream),
+                                    _c.byref(h)))
+        self.h = h
+
+    def rk_step(self, dts, nsteps=1):
+        d = np.ascontiguousarray(dts, dtype=np.float64).reshape(-1)
+        if d.size != len(self.solvers):
+            raise ValueError("one dt per member")
+        check(lib().dg_batch_rk_step(self.h, _ptr(d), int(nsteps)))
+
+    def use_graphs(self, enable=True):
+        check(lib().dg_batch_use_graphs(self.h, 1 if enable else 0))
+
+    def launches_per_stage(self):
+        k = _c.c_int()
+        check(lib().dg_batch_launches(self.h, _c.byref(k)))
+        return k.value
+
+    def close(self):
+        if self.h:
+            lib().dg_batch_destroy(self.h)
+            self.h = None
 
     def __del__(self):
         try:
