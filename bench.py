@@ -38,6 +38,34 @@ def algorithmic_bytes_gradient(nodes, N, fp32):
     return nodes * (8 * 5 + 8 * 10 + (4 if fp32 else 8) * 4 * 6 * n * n / n ** 3)
 
 
+HERE = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC_PROFILE = os.path.join(HERE, "profiles", "stage_kernel_c2_ns_fp64.md")
+KERNEL_SOURCES = ["paper_2206_09733_amd/csrc/kernels.hip", "paper_2206_09733_amd/csrc/dg_device.h",
+                  "paper_2206_09733_amd/csrc/dg_internal.h"]
+
+
+def profiled_traffic(kernel="dg::stage_kernel<4, double, true>", shape="32768 x 128"):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary,
+    or None when the kernel sources changed since the counters were taken."""
+    import hashlib
+    import re
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        h = hashlib.sha256()
+        for f in KERNEL_SOURCES:
+            h.update(open(os.path.join(HERE, f), "rb").read())
+        m = re.search(r"Kernel sources \(sha256[^`]*`([0-9a-f]+)`", text)
+        if not m or m.group(1) != h.hexdigest()[:len(m.group(1))]:
+            return None
+        for line in text.splitlines():
+            cells = [c.strip() for c in line.strip().strip("|").split("|")]
+            if len(cells) == 8 and cells[0] == f"`{kernel}`" and cells[1] == shape:
+                return float(cells[7])
+    except OSError:
+        return None
+    return None
+
+
 def timed_steps(s, dt, steps, profile=True):
     """Run `steps` RK3 steps between two events on the solver's stream.  With profile=True the
     library also brackets every kernel of the timed steps with HIP events on that stream."""
@@ -250,7 +278,7 @@ def main():
                    "elements": r64["E"], "nodes": nodes, "dof": 5 * nodes, "precision": "fp64"},
         "roofline": {"bound": "hbm", "kernel": "stage_kernel<4,double,NS>",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(),
                      "avg_launch_us": round(avg_stage_s * 1e6, 2),
                      "algorithmic_bytes_per_launch": int(b_stage)},
         "kernels": {"stage": {"avg_us": round(avg_stage_s * 1e6, 2), "launches": st["launches"],
