@@ -112,7 +112,7 @@ def run_mixed(steps, warmup):
     orders = synth.mixed_orders(24 ** 3, seed=0)
     s = dgsem.Solver(**MIXED, orders=orders)
     s.set_ic("vortex", VORTEX)
-    block, tune_us = s.autotune()
+    tiles, tune_us = s.autotune()
     dt = s.suggest_dt(0.5)
     s.rk_step(dt, warmup)
     ev_ms, _, _ = timed_steps(s, dt, steps, profile=False)
@@ -124,7 +124,7 @@ def run_mixed(steps, warmup):
                        "form + Roe, mortar faces, RK3 CFL 0.5, graph replay",
            "elements": s.E, "nodes": s.nodes, "dof": 5 * s.nodes, "dtype": "f64",
            "value": round(5 * s.nodes * 3 * steps / (ev_ms / 1e3) / 1e9, 3), "unit": "GDOF/s",
-           "ms_per_step": round(ev_ms / steps, 4), "steps": steps, "autotuned_block": block,
+           "ms_per_step": round(ev_ms / steps, 4), "steps": steps, "autotuned_tiles": f"{tiles:06b}",
            "stage_avg_us": round(st["ms"] / st["launches"] * 1e3, 2),
            "state_finite": d["nonfinite"] == 0}
     s.close()

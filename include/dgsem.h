@@ -123,7 +123,7 @@ int dg_mesh_info(const dg_mesh* m, long long* n_elements, long long* n_nodes, in
 /* Create a solver for the mesh (the mesh may be destroyed afterwards).  Errors: DG_EINVAL for
  * gamma <= 1, Pr <= 0, unknown flux or precision codes; DG_EUNSUPPORTED for an order without
  * a compiled kernel (uniform orders 1..7 are compiled), and for a mixed-order mesh with
- * Re > 0 or DG_FP32_BULK (mixed-order meshes are evaluated for the Euler equations in FP64). */
+ * Re > 0 (mixed-order meshes are evaluated for the Euler equations, in FP64 or FP32-bulk). */
 int dg_solver_create(const dg_mesh* m, const dg_physics* p, dg_solver** out);
 /* Bytes of device memory the solver needs (host-only; used for admission control). */
 int dg_solver_required_bytes(const dg_solver* s, size_t* bytes);
@@ -156,17 +156,18 @@ int dg_rk_step(dg_solver* s, double dt, int nsteps);
  * reference changes, after dg_autotune and when disabled; steps inside a profile region run
  * eagerly.  enable = 0 disables replay. */
 int dg_solver_use_graphs(dg_solver* s, int enable);
-/* Mixed-order meshes: time the stage kernel (residual mode, 5 launches each) at 128, 256 and
- * 512 threads per element workgroup on the current state and keep the fastest; *block and *us
- * (either may be NULL) receive it and its mean launch time in microseconds.  The residual
- * buffer is overwritten; the state is not changed.  Uniform-order meshes have one launch
- * shape: *block receives it and *us 0.  Synchronises. */
-int dg_autotune(dg_solver* s, int* block, double* us);
-/* Set the stage-kernel block size of a mixed-order mesh by hand (128, 256 or 512; the default
- * is 256).  The result does not depend on it: every node's sums are taken in the same order
- * at every block size.  For a uniform-order mesh only its one launch shape is accepted.
- * Errors: DG_EINVAL for any other value. */
-int dg_solver_set_block(dg_solver* s, int block);
+/* Mixed-order meshes: the stage runs one launch per bucket of elements with 64 b < nodes <=
+ * 64 (b + 1), b = 0..5, one node per lane, or two nodes per lane when bit b of the tile mask is
+ * set.  dg_autotune times both shapes of every occupied bucket on the current state (residual
+ * mode, five launches each) and keeps the faster; *tiles receives the mask and *us the summed
+ * launch time of the chosen shapes in microseconds (either pointer may be NULL).  The residual
+ * buffer is overwritten; the state is not changed.  Uniform-order meshes have one launch shape:
+ * *tiles = 0, *us = 0.  Synchronises. */
+int dg_autotune(dg_solver* s, int* tiles, double* us);
+/* Set the tile mask by hand (default 0).  The result does not depend on it: every node's sums
+ * are taken in the same order with either shape.  Uniform-order meshes accept only 0.
+ * Errors: DG_EINVAL for a value outside [0, 63]. */
+int dg_solver_set_tiles(dg_solver* s, int tiles);
 /* Diagnostics of the current state (synchronises). */
 int dg_diagnostics(dg_solver* s, dg_diag* out);
 /* dt = cfl h_min / ((N_max+1)^2 lambda_max), and for Navier-Stokes the smaller of that and

@@ -65,7 +65,7 @@ struct dg_solver {
   std::vector<ProfRecord> prof;      // records of the current profile region
   std::vector<hipEvent_t> ev_pool;   // events reused across regions
   size_t ev_used = 0;
-  int mix_block = 256;               // threads per element of the mixed-order stage kernel
+  int mix_tiles = 0;                 // mixed-order stage: bit b = two nodes per lane in bucket b
   // RK-step graphs: graph[p] advances one step starting from state buffer p with step graph_dt[p]
   bool use_graphs = true;
   hipStream_t cap_stream = nullptr;
@@ -78,7 +78,7 @@ struct dg_solver {
 namespace {
 
 struct Plan {
-  size_t tab, nbr, X, Ja, J, invJ, U0, U1, dU, R, Fvf, part, diag, elem, work, mtab, self, total;
+  size_t tab, nbr, X, Ja, J, invJ, U0, U1, dU, R, Fvf, part, diag, elem, work, mtab, Fs, self, total;
   size_t tab_n, mtab_n;
 };
 
@@ -124,6 +124,7 @@ Plan make_plan(const dg_solver* s) {
   p.elem = mixed ? take(sizeof(int4) * E) : 0;
   p.work = mixed ? take(sizeof(int) * E) : 0;
   p.mtab = mixed ? take(sizeof(double) * p.mtab_n) : 0;
+  p.Fs = mixed ? take(sizeof(double) * dg::kMixFaceDoubles * E) : 0;
   p.self = take(sizeof(dg::View));  // device copy of the View, read by batched launches
   p.total = off;
   return p;
@@ -178,7 +179,7 @@ hipError_t timed(dg_solver* s, int cls, F fn) {
 }
 
 hipError_t launch_stage_any(dg_solver* s, double dt, double a, double b, int mode) {
-  if (s->v.mixed) return dg::launch_stage_mixed(s->v, s->cur, dt, a, b, mode, s->mix_block, s->stream);
+  if (s->v.mixed) return dg::launch_stage_mixed(s->v, s->cur, dt, a, b, mode, s->mix_tiles, s->stream);
   return dg::launch_stage(s->v, s->cur, dt, a, b, mode, s->stream);
 }
 
@@ -351,8 +352,6 @@ int dg_solver_create(const dg_mesh* m, const dg_physics* p, dg_solver** out) {
   if (m->N < 1 || m->N > dg::kMaxOrder) return fail(DG_EUNSUPPORTED, "no kernel for this order");
   if (m->mixed && p->Re > 0)
     return fail(DG_EUNSUPPORTED, "mixed-order meshes are evaluated for the Euler equations (Re <= 0)");
-  if (m->mixed && p->precision != DG_FP64)
-    return fail(DG_EUNSUPPORTED, "mixed-order meshes are evaluated in FP64");
   dg_solver* s = new dg_solver;
   s->mesh = *m;
   s->phys = *p;
@@ -421,6 +420,7 @@ int dg_solver_bind(dg_solver* s, void* dev_ptr, size_t bytes, void* hip_stream) 
   v.elem = mixed ? reinterpret_cast<const int4*>(b + p.elem) : nullptr;
   v.work = mixed ? reinterpret_cast<const int*>(b + p.work) : nullptr;
   v.mtab = mixed ? reinterpret_cast<const double*>(b + p.mtab) : nullptr;
+  v.Fs = mixed ? reinterpret_cast<double*>(b + p.Fs) : nullptr;
   s->dev_view = reinterpret_cast<dg::View*>(b + p.self);
   s->stream = static_cast<hipStream_t>(hip_stream);
 
@@ -476,6 +476,17 @@ int dg_solver_bind(dg_solver* s, void* dev_ptr, size_t bytes, void* hip_stream) 
     std::stable_sort(work.begin(), work.end(), [&](int x, int y) {
       return s->off[x + 1] - s->off[x] > s->off[y + 1] - s->off[y];
     });
+    // buckets of the launch: 64 b < nodes <= 64 (b + 1), contiguous in the sorted list
+    for (int bk = 0; bk < dg::kMixBuckets; bk++) {
+      v.mix_beg[bk] = 0;
+      v.mix_cnt[bk] = 0;
+    }
+    for (long long i = 0; i < s->E; i++) {
+      const long long nn = s->off[work[i] + 1] - s->off[work[i]];
+      const int bk = (int)((nn - 1) / 64);
+      if (v.mix_cnt[bk] == 0) v.mix_beg[bk] = (int)i;
+      v.mix_cnt[bk]++;
+    }
     DG_HIP(hipMemcpyAsync(b + p.mtab, mtab.data(), sizeof(double) * mtab.size(), hipMemcpyHostToDevice,
                           s->stream), "upload mortar matrices");
     DG_HIP(hipMemcpyAsync(b + p.elem, elem.data(), sizeof(int4) * elem.size(), hipMemcpyHostToDevice,
@@ -593,32 +604,27 @@ int dg_solver_use_graphs(dg_solver* s, int enable) {
   return DG_OK;
 }
 
-int dg_solver_set_block(dg_solver* s, int block) {
+int dg_solver_set_tiles(dg_solver* s, int tiles) {
   if (!s) return fail(DG_EINVAL, "NULL solver");
   if (!s->v.mixed) {
-    const int nn = (s->mesh.N + 1) * (s->mesh.N + 1) * (s->mesh.N + 1);
-    if (block != (nn + 63) / 64 * 64) return fail(DG_EINVAL, "uniform-order meshes have one launch shape");
+    if (tiles != 0) return fail(DG_EINVAL, "uniform-order meshes have one launch shape (tiles = 0)");
     return DG_OK;
   }
-  if (block != 128 && block != 256 && block != 512) return fail(DG_EINVAL, "block must be 128, 256 or 512");
-  s->mix_block = block;
+  if (tiles < 0 || tiles >= (1 << dg::kMixBuckets)) return fail(DG_EINVAL, "tiles must be a 6-bit mask");
+  s->mix_tiles = tiles;
   drop_graphs(s);
   return DG_OK;
 }
 
-int dg_autotune(dg_solver* s, int* block, double* us) {
+int dg_autotune(dg_solver* s, int* tiles, double* us) {
   int rc = check_bound(s);
   if (rc) return rc;
   if (!s->v.mixed) {
-    const int nn = (s->mesh.N + 1) * (s->mesh.N + 1) * (s->mesh.N + 1);
-    if (block) *block = (nn + 63) / 64 * 64;
+    if (tiles) *tiles = 0;
     if (us) *us = 0.0;
     return DG_OK;
   }
-  const int cand[3] = {128, 256, 512};
   const int reps = 5;
-  double best = 1e300;
-  int best_b = s->mix_block;
   hipEvent_t a = nullptr, b = nullptr;
   DG_HIP(hipEventCreate(&a), "event");
   if (hipEventCreate(&b) != hipSuccess) {
@@ -626,30 +632,36 @@ int dg_autotune(dg_solver* s, int* block, double* us) {
     return fail(DG_EHIP, "event");
   }
   hipError_t err = hipSuccess;
-  for (int c : cand) {
-    s->mix_block = c;
-    err = launch_stage_any(s, 0.0, 0.0, 0.0, dg::kModeResidual);  // warm-up
-    if (err == hipSuccess) err = hipEventRecord(a, s->stream);
-    for (int r = 0; r < reps && err == hipSuccess; r++)
-      err = launch_stage_any(s, 0.0, 0.0, 0.0, dg::kModeResidual);
-    if (err == hipSuccess) err = hipEventRecord(b, s->stream);
-    if (err == hipSuccess) err = hipEventSynchronize(b);
-    float ms = 0.f;
-    if (err == hipSuccess) err = hipEventElapsedTime(&ms, a, b);
-    if (err != hipSuccess) break;
-    const double t_us = 1e3 * ms / reps;
-    if (t_us < best) {
-      best = t_us;
-      best_b = c;
+  int best_tiles = 0;
+  double total = 0.0;
+  err = dg::launch_faces_mixed(s->v, s->cur, s->stream);  // the buckets read the face fluxes
+  for (int bk = 0; bk < dg::kMixBuckets && err == hipSuccess; bk++) {
+    if (s->v.mix_cnt[bk] == 0) continue;
+    double best = 1e300;
+    for (int npl = 1; npl <= 2 && err == hipSuccess; npl++) {
+      err = dg::launch_stage_mixed_bucket(s->v, bk, npl, s->cur, 0.0, 0.0, 0.0, dg::kModeResidual, s->stream);
+      if (err == hipSuccess) err = hipEventRecord(a, s->stream);
+      for (int r = 0; r < reps && err == hipSuccess; r++)
+        err = dg::launch_stage_mixed_bucket(s->v, bk, npl, s->cur, 0.0, 0.0, 0.0, dg::kModeResidual, s->stream);
+      if (err == hipSuccess) err = hipEventRecord(b, s->stream);
+      if (err == hipSuccess) err = hipEventSynchronize(b);
+      float ms = 0.f;
+      if (err == hipSuccess) err = hipEventElapsedTime(&ms, a, b);
+      const double t_us = 1e3 * ms / reps;
+      if (err == hipSuccess && t_us < best) {
+        best = t_us;
+        best_tiles = npl == 2 ? (best_tiles | (1 << bk)) : (best_tiles & ~(1 << bk));
+      }
     }
+    total += best;
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
-  s->mix_block = best_b;
-  drop_graphs(s);
   if (err != hipSuccess) return hip_fail(err, "autotune");
-  if (block) *block = best_b;
-  if (us) *us = best;
+  s->mix_tiles = best_tiles;
+  drop_graphs(s);
+  if (tiles) *tiles = best_tiles;
+  if (us) *us = total;
   return DG_OK;
 }
 
@@ -811,7 +823,7 @@ hipError_t batch_stage(dg_batch* b, const double* dts, int k, hipStream_t st) {
   }
   for (int i : b->mixed) {
     dg_solver* s = b->m[i];
-    hipError_t e = dg::launch_stage_mixed(s->v, s->cur, dts[i], kRkA[k], kRkB[k], dg::kModeRK, s->mix_block, st);
+    hipError_t e = dg::launch_stage_mixed(s->v, s->cur, dts[i], kRkA[k], kRkB[k], dg::kModeRK, s->mix_tiles, st);
     if (e != hipSuccess) return e;
   }
   for (dg_solver* s : b->m) s->cur ^= 1;

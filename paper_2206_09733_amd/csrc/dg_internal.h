@@ -57,6 +57,12 @@ struct View {
   const double* mtab;
   int tab_off[kMaxOrder + 1];
   int mort_off[kMaxOrder + 1][kMaxOrder + 1];
+  // work-list range [mix_beg[b], mix_beg[b] + mix_cnt[b]) of the elements with
+  // 64 b < nodes <= 64 (b + 1)
+  int mix_beg[6], mix_cnt[6];
+  // face fluxes of mixed-order meshes: [E][6 faces][6][49], rows 0-4 the numerical flux on the
+  // element's face grid, row 5 its FP64 mass component (FP32-bulk)
+  double* Fs;
 };
 
 // Several solvers of one order and precision advanced by one launch: workgroup b of the grid
@@ -87,12 +93,20 @@ hipError_t launch_gradient_batch(const BatchArgs& B, int N, bool fp32, hipStream
 hipError_t launch_stage_batch(const BatchArgs& B, int N, bool fp32, bool visc, double rkA, double rkB,
                               int mode, hipStream_t st);
 
-// mixed-order meshes (kernels_mixed.hip); block = threads per element workgroup of the stage
+// mixed-order meshes (kernels_mixed.hip).  The stage runs one launch per bucket of elements
+// (bucket b: 64 b < nodes <= 64 (b + 1)); bit b of `tiles` gives bucket b two nodes per lane
+// instead of one.
 constexpr int kMixMaxOrder = 6;
+constexpr int kMixBuckets = 6;
 hipError_t launch_geometry_mixed(const View& v, hipStream_t st);
 hipError_t launch_ic_mixed(const View& v, int cur, int ic, const double* params, hipStream_t st);
 hipError_t launch_stage_mixed(const View& v, int cur, double dt, double rkA, double rkB, int mode,
-                              int block, hipStream_t st);
+                              int tiles, hipStream_t st);
+hipError_t launch_stage_mixed_bucket(const View& v, int b, int npl, int cur, double dt, double rkA,
+                                     double rkB, int mode, hipStream_t st);
+// the face pass alone (launch_stage_mixed runs it before the buckets)
+hipError_t launch_faces_mixed(const View& v, int cur, hipStream_t st);
+constexpr int kMixFaceDoubles = 6 * 6 * 49;  // Fs doubles per element
 hipError_t launch_diagnostics_mixed(const View& v, int cur, hipStream_t st);
 
 // stage modes

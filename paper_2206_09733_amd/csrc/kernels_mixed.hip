@@ -147,212 +147,340 @@ __global__ void __launch_bounds__(512) ic_mixed_kernel(View v, int cur, int ic, 
   }
 }
 
-// ------------------------------------------------------------------ stage kernel
-// 1D interpolation / projection along the first tangential index of a face array:
-// out[c][po + no * r] = sum_p A[po][p] in[c][p + ni * r], for r < nr (A = identity if no == ni)
-__device__ __forceinline__ void apply_a(const double* A, int no, int ni, int nr, int ncomp,
-                                        const double* in, int in_stride, double* out, int out_stride) {
-  for (int x = threadIdx.x; x < ncomp * no * nr; x += blockDim.x) {
-    const int c = x / (no * nr), y = x - c * no * nr;
-    const int po = y % no, r = y / no;
-    double s;
-    if (no == ni) {
-      s = in[c * in_stride + po + ni * r];
-    } else {
-      s = 0.0;
-      for (int p = 0; p < ni; p++) s += A[po * ni + p] * in[c * in_stride + p + ni * r];
+// ------------------------------------------------------------------ stage: faces
+// One 64-lane workgroup (a single wave) per face: the face normal to d between the owner L (its
+// +xi_d side) and R = nbr(L, +d), with L's metric Ja^d as the scaled normal.  Traces are staged
+// in LDS, interpolated to the mortar of the larger tangential orders (the identity where the
+// orders agree), the numerical flux is evaluated at the mortar points, and it is L2-projected
+// onto the face grids of both elements: Fs[e][f][c][p + n_a r], f = 2 d + side of element e,
+// c = 0..4 the flux and c = 5 its FP64 mass component (FP32-bulk).  Each face is evaluated once.
+__host__ __device__ constexpr int mix_lanes(int nnmax, int npl) { return ((nnmax + npl - 1) / npl + 63) / 64 * 64; }
+
+// q / n for 0 <= q < 4096 and 1 <= n <= 64, from inv_n = 1.0f / n: (q + 1/2)/n lies at least
+// 1/(2n) away from an integer, far more than the rounding error of the FP32 product (checked
+// for every q and n in that range).
+__device__ __forceinline__ int sdiv(int q, float inv_n) { return (int)(((float)q + 0.5f) * inv_n); }
+
+__device__ __forceinline__ int stride_of(const ElemInfo& I, int d) {
+  return d == 0 ? 1 : (d == 1 ? I.n[0] : I.n[0] * I.n[1]);
+}
+
+constexpr int kFsFace = 6 * kMixNF;  // doubles per element face in Fs
+
+template <typename T>
+__global__ void __launch_bounds__(64) mixed_face_kernel(View v, int cur) {
+  constexpr bool DEV = sizeof(T) == 4;
+  constexpr int NC = DEV ? 6 : 5;
+  const int fid = block_element(3 * v.E);
+  const int e = fid / 3, d = fid - 3 * e;
+  const int t = threadIdx.x;
+  const double* __restrict__ Uin = v.U[cur];
+  const Ref Rf = make_ref(v.rho_r, v.p_r, v.gamma);
+  int ta, tb;
+  tangential(d, ta, tb);
+  const int eR = v.nbr[e * 6 + 2 * d + 1];
+  const ElemInfo L = elem_info(v, e), R = elem_info(v, eR);
+  const int naL = L.n[ta], nbL = L.n[tb], naR = R.n[ta], nbR = R.n[tb];
+  const int ma = naL > naR ? naL : naR, mb = nbL > nbR ? nbL : nbR;
+  const float ima = 1.0f / (float)ma;
+  const double* mt = v.mtab;
+  // rows 0-4 L's state, 5-7 L's Ja^d, 8-12 R's state; then the flux rows
+  __shared__ double sA[13][kMixNF], sB[13][kMixNF];
+  // the face's mortar matrices: interpolation of L and R along a and b, projection onto L's
+  // and R's grids along a and b (unused ones stay unread)
+  __shared__ double sIaL[kMixNF], sIaR[kMixNF], sIbL[kMixNF], sIbR[kMixNF];
+  __shared__ double sPaL[kMixNF], sPaR[kMixNF], sPbL[kMixNF], sPbR[kMixNF];
+  {
+    auto stage = [&](double* dst, int n, int m, bool proj) __attribute__((always_inline)) {
+      if (n < m) {
+        const double* src = mt + v.mort_off[n - 1][m - 1] + (proj ? m * n : 0);
+        for (int x = t; x < m * n; x += 64) dst[x] = src[x];
+      }
+    };
+    stage(sIaL, naL, ma, false);
+    stage(sIaR, naR, ma, false);
+    stage(sIbL, nbL, mb, false);
+    stage(sIbR, nbR, mb, false);
+    stage(sPaL, naL, ma, true);
+    stage(sPaR, naR, ma, true);
+    stage(sPbL, nbL, mb, true);
+    stage(sPbR, nbR, mb, true);
+  }
+
+  {  // stage the traces on their own grids (index p + n_a r)
+    const int nL = naL * nbL, nR = naR * nbR;
+    const float iLa = 1.0f / (float)naL, iRa = 1.0f / (float)naR;
+    const int sLa = stride_of(L, ta), sLb = stride_of(L, tb), sRa = stride_of(R, ta), sRb = stride_of(R, tb);
+    const int baseL = (L.n[d] - 1) * stride_of(L, d);
+    const long offL = L.off, offR = R.off, nnL = L.nn, nnR = R.nn;
+    for (int x = t; x < nL + nR; x += 64) {
+      if (x < nL) {
+        const int r = sdiv(x, iLa), p = x - r * naL;
+        const int q = baseL + p * sLa + r * sLb;
+#pragma unroll
+        for (int c = 0; c < 5; c++) sA[c][x] = Uin[offL * 5 + c * nnL + q];
+#pragma unroll
+        for (int c = 0; c < 3; c++) sA[5 + c][x] = v.Ja[offL * 9 + (3 * d + c) * nnL + q];
+      } else {
+        const int y = x - nL;
+        const int r = sdiv(y, iRa), p = y - r * naR;
+        const int q = p * sRa + r * sRb;
+#pragma unroll
+        for (int c = 0; c < 5; c++) sA[8 + c][y] = Uin[offR * 5 + c * nnR + q];
+      }
     }
-    out[c * out_stride + po + no * r] = s;
+  }
+  __syncthreads();
+  {  // along the first tangential direction (index pm + ma r)
+    const double* IaL = sIaL;
+    const double* IaR = sIaR;
+    const int nL1 = ma * nbL, nR1 = ma * nbR;
+    for (int x = t; x < nL1 + nR1; x += 64) {
+      const bool isL = x < nL1;
+      const int y = isL ? x : x - nL1;
+      const int r = sdiv(y, ima), pm = y - r * ma;
+      const int c0 = isL ? 0 : 8, nc = isL ? 8 : 5, nx = isL ? naL : naR;
+      const double* Ia = isL ? IaL : IaR;
+      for (int c = c0; c < c0 + nc; c++) {
+        double s;
+        if (nx == ma) {
+          s = sA[c][pm + nx * r];
+        } else {
+          s = 0.0;
+          for (int p = 0; p < nx; p++) s += Ia[pm * nx + p] * sA[c][p + nx * r];
+        }
+        sB[c][y] = s;
+      }
+    }
+  }
+  __syncthreads();
+  {  // along the second, and the numerical flux at the mortar point (rows into sA)
+    const double* IbL = sIbL;
+    const double* IbR = sIbR;
+    for (int x = t; x < ma * mb; x += 64) {
+      const int rm = sdiv(x, ima), pm = x - rm * ma;
+      double a[13];
+#pragma unroll
+      for (int c = 0; c < 13; c++) {
+        const int nbX = c < 8 ? nbL : nbR;
+        const double* Ib = c < 8 ? IbL : IbR;
+        if (nbX == mb) {
+          a[c] = sB[c][pm + ma * rm];
+        } else {
+          double s = 0.0;
+          for (int r = 0; r < nbX; r++) s += Ib[rm * nbX + r] * sB[c][pm + ma * r];
+          a[c] = s;
+        }
+      }
+      const double uL[5] = {a[0], a[1], a[2], a[3], a[4]};
+      const double S[3] = {a[5], a[6], a[7]};
+      const double uR[5] = {a[8], a[9], a[10], a[11], a[12]};
+      T F[5];
+      if (DEV) {
+        double F0d;
+        face_flux_dev<T>(v.surf, uL, uR, S, v.gamma, Rf, F, F0d);
+        sA[5][x] = F0d;
+      } else {
+        face_flux<T>(v.surf, uL, uR, S, v.gamma, F);
+      }
+#pragma unroll
+      for (int c = 0; c < 5; c++) sA[c][x] = (double)F[c];
+    }
+  }
+  __syncthreads();
+  // L2 projection onto each side's grid, first along a (rows 0-5 of sB for L, 6-11 for R),
+  // then along b into Fs
+  const ElemInfo* Side[2] = {&L, &R};
+  const int eS[2] = {e, eR}, fS[2] = {2 * d + 1, 2 * d};
+  for (int x = t; x < 2 * kMixNF; x += 64) {
+    const int side = x >= kMixNF ? 1 : 0, y = x - side * kMixNF;
+    const int na = Side[side]->n[ta];
+    if (y >= na * mb) continue;
+    const int rm = sdiv(y, 1.0f / (float)na), po = y - rm * na;
+    const double* Pa = side ? sPaR : sPaL;
+#pragma unroll
+    for (int c = 0; c < NC; c++) {
+      double s;
+      if (na == ma) {
+        s = sA[c][po + ma * rm];
+      } else {
+        s = 0.0;
+        for (int pm = 0; pm < ma; pm++) s += Pa[po * ma + pm] * sA[c][pm + ma * rm];
+      }
+      sB[6 * side + c][y] = s;
+    }
+  }
+  __syncthreads();
+  for (int x = t; x < 2 * kMixNF; x += 64) {
+    const int side = x >= kMixNF ? 1 : 0, y = x - side * kMixNF;
+    const int na = Side[side]->n[ta], nb = Side[side]->n[tb];
+    if (y >= na * nb) continue;
+    const int ro = sdiv(y, 1.0f / (float)na), po = y - ro * na;
+    const double* Pb = side ? sPbR : sPbL;
+    double* out = v.Fs + ((long)eS[side] * 6 + fS[side]) * kFsFace;
+#pragma unroll
+    for (int c = 0; c < NC; c++) {
+      double s;
+      if (nb == mb) {
+        s = sB[6 * side + c][po + na * ro];
+      } else {
+        s = 0.0;
+        for (int rm = 0; rm < mb; rm++) s += Pb[ro * mb + rm] * sB[6 * side + c][po + na * rm];
+      }
+      out[c * kMixNF + y] = s;
+    }
   }
 }
 
-// ... and along the second: out[c][p + np * ro] = sum_r B[ro][r] in[c][p + np * r]
-__device__ __forceinline__ void apply_b(const double* B, int no, int ni, int np, int ncomp,
-                                        const double* in, int in_stride, double* out, int out_stride) {
-  for (int x = threadIdx.x; x < ncomp * np * no; x += blockDim.x) {
-    const int c = x / (np * no), y = x - c * np * no;
-    const int p = y % np, ro = y / np;
-    double s;
-    if (no == ni) {
-      s = in[c * in_stride + p + np * ro];
-    } else {
-      s = 0.0;
-      for (int r = 0; r < ni; r++) s += B[ro * ni + r] * in[c * in_stride + p + np * r];
-    }
-    out[c * out_stride + p + np * ro] = s;
-  }
-}
-
-template <int BS>
-__global__ void __launch_bounds__(BS) mixed_stage_kernel(View v, int cur, double dt, double rkA,
-                                                         double rkB, int mode) {
-  constexpr int SLOTS = (kMixNN + BS - 1) / BS;
-  const int e = v.work[blockIdx.x];
+// ------------------------------------------------------------------ stage: volume and update
+// Elements are launched by bucket: bucket b holds the elements of 64 b < nn <= 64 (b + 1) nodes,
+// a contiguous range of the work list (sorted by node count).  A lane holds NPL nodes (1 or 2,
+// the autotuner's choice per bucket), so the workgroup has mix_lanes(NNMAX, NPL) lanes.
+template <int NNMAX, int NPL, typename T>
+__global__ void __launch_bounds__(mix_lanes(NNMAX, NPL))
+    mixed_stage_kernel(View v, int wbeg, int cur, double dt, double rkA, double rkB, int mode) {
+  constexpr int BS = mix_lanes(NNMAX, NPL);
+  constexpr bool DEV = sizeof(T) == 4;  // FP32-bulk: deviation form, FP64 mass flux
+  const int e = v.work[wbeg + blockIdx.x];
   const ElemInfo I = elem_info(v, e);
   const int t = threadIdx.x;
   const long off = I.off, nn = I.nn;
   const double* __restrict__ Uin = v.U[cur];
+  const double* __restrict__ Fs = v.Fs + (long)e * 6 * kFsFace;
+  const Ref Rf = make_ref(v.rho_r, v.p_r, v.gamma);
+  const int str[3] = {1, I.n[0], I.n[0] * I.n[1]};
+  const float inv0 = 1.0f / (float)I.n[0], inv01 = 1.0f / (float)str[2];
 
   __shared__ double sD[3][kMixNF], sw[3][kMixN];
-  __shared__ double sP[7][kMixNN];     // rho, v1, v2, v3, beta, ln rho, ln beta
-  __shared__ double sJ3[3][kMixNN];    // Ja^d of the direction being processed
-  __shared__ double sF[6][5][kMixNF];  // numerical flux on the element's own face grids
-  __shared__ double sL[8][kMixNF];     // mortar work: left trace (5) and owner normal (3)
-  __shared__ double sR[5][kMixNF];     //              right trace
-  __shared__ double sT[8][kMixNF];     //              tensor-product intermediate
-
+  __shared__ T sP[7][NNMAX];             // rho, v1, v2, v3, beta, ln rho, ln beta (FP32-bulk: deviations)
+  constexpr int NV = DEV ? NNMAX : 1;
+  __shared__ double sVd[3][NV];          // FP32-bulk: FP64 velocities for the mass flux
+  __shared__ double sJ3[3][NNMAX];       // Ja^d of the direction in work
   for (int d = 0; d < 3; d++) {
     const int n = I.n[d];
     for (int x = t; x < n * n; x += BS) sD[d][x] = tab_D(v, n)[x];
     if (t < n) sw[d][t] = tab_w(v, n)[t];
   }
-  for (int q = t; q < I.nn; q += BS) {
-    double u[5];
-    for (int c = 0; c < 5; c++) u[c] = Uin[off * 5 + c * nn + q];
-    const Prim<double> P = make_prim<double>(u, v.gamma);
-    sP[0][q] = P.rho; sP[1][q] = P.v1; sP[2][q] = P.v2; sP[3][q] = P.v3;
-    sP[4][q] = P.beta; sP[5][q] = P.lrho; sP[6][q] = P.lbeta;
+  int ii[NPL][3];
+#pragma unroll
+  for (int s = 0; s < NPL; s++) {
+    const int q = t + s * BS;
+    const int k = sdiv(q, inv01), rem = q - k * str[2];
+    const int j = sdiv(rem, inv0);
+    ii[s][0] = rem - j * I.n[0];
+    ii[s][1] = j;
+    ii[s][2] = k;
+    if (q < I.nn) {
+      double u[5];
+#pragma unroll
+      for (int c = 0; c < 5; c++) u[c] = Uin[off * 5 + c * nn + q];
+      const Prim<T> P = DEV ? make_prim_dev<T>(u, v.gamma, Rf) : make_prim<T>(u, v.gamma);
+      sP[0][q] = P.rho; sP[1][q] = P.v1; sP[2][q] = P.v2; sP[3][q] = P.v3;
+      sP[4][q] = P.beta; sP[5][q] = P.lrho; sP[6][q] = P.lbeta;
+      if (DEV) {
+        const double ir = rcp(u[0]);
+        sVd[0][q] = u[1] * ir;
+        sVd[1][q] = u[2] * ir;
+        sVd[2][q] = u[3] * ir;
+      }
+    }
   }
 
-  // ---- faces
-  for (int f = 0; f < 6; f++) {
-    const int d = f >> 1, side = f & 1;
+  // For each node and direction: sum over the line of D_im F#(U_i, U_m; Ja_i + Ja_m), then the
+  // surface lift of the face fluxes.  Slot s of the lane holds node t + s BS.
+  T acc0[5] = {0, 0, 0, 0, 0}, acc1[5] = {0, 0, 0, 0, 0};
+  double m0 = 0.0, m1 = 0.0;  // FP32-bulk: FP64 mass accumulators
+  const T ce = (T)(0.5 / (v.gamma - 1.0)), gm1 = (T)(v.gamma - 1.0);
+  auto node_volume = [&](const int d, const int q, const int* iq, T* acc, double& accm) __attribute__((always_inline)) {
+    const int n = I.n[d], sd = str[d];
     int ta, tb;
     tangential(d, ta, tb);
-    const int ne = v.nbr[e * 6 + f];
-    const ElemInfo In = elem_info(v, ne);
-    const ElemInfo& IL = side ? I : In;   // owner: the element whose +d face this is
-    const ElemInfo& IR = side ? In : I;
-    const int naL = IL.n[ta], nbL = IL.n[tb], naR = IR.n[ta], nbR = IR.n[tb];
-    const int na = I.n[ta], nb = I.n[tb];
-    const long offL = IL.off, offR = IR.off, nnL = IL.nn, nnR = IR.nn;
-    const int idL = IL.n[d] - 1;
-    if (naL == naR && nbL == nbR) {
-      for (int q = t; q < na * nb; q += BS) {
-        const int p = q % na, r = q / na;
-        const int iL = face_node_rt(IL.n, d, idL, p, r), iR = face_node_rt(IR.n, d, 0, p, r);
-        double uL[5], uR[5], S[3];
-        for (int c = 0; c < 5; c++) {
-          uL[c] = Uin[offL * 5 + c * nnL + iL];
-          uR[c] = Uin[offR * 5 + c * nnR + iR];
+    const int id = iq[d];
+    const int b0 = q - id * sd;
+    Prim<T> A;
+    A.rho = sP[0][q]; A.v1 = sP[1][q]; A.v2 = sP[2][q]; A.v3 = sP[3][q];
+    A.beta = sP[4][q]; A.lrho = sP[5][q]; A.lbeta = sP[6][q];
+    A.h = (T)0.5 * (A.v1 * A.v1 + A.v2 * A.v2 + A.v3 * A.v3);
+    const double ja0 = sJ3[0][q], ja1 = sJ3[1][q], ja2 = sJ3[2][q];
+    for (int m = 0; m < n; m++) {
+      if (m == id) continue;
+      const int qm = b0 + m * sd;
+      Prim<T> B;
+      B.rho = sP[0][qm]; B.v1 = sP[1][qm]; B.v2 = sP[2][qm]; B.v3 = sP[3][qm];
+      B.beta = sP[4][qm]; B.lrho = sP[5][qm]; B.lbeta = sP[6][qm];
+      B.h = (T)0.5 * (B.v1 * B.v1 + B.v2 * B.v2 + B.v3 * B.v3);
+      const double md[3] = {ja0 + sJ3[0][qm], ja1 + sJ3[1][qm], ja2 + sJ3[2][qm]};
+      T F[5];
+      double F0d = 0.0;
+      if (DEV) {
+        const double va[3] = {sVd[0][q], sVd[1][q], sVd[2][q]};
+        const double vb[3] = {sVd[0][qm], sVd[1][qm], sVd[2][qm]};
+        if (v.vol == 0) {
+          const double vn64 = 0.5 * ((va[0] + vb[0]) * md[0] + (va[1] + vb[1]) * md[1] + (va[2] + vb[2]) * md[2]);
+          flux_ec_dev(A, B, (T)md[0], (T)md[1], (T)md[2], vn64, Rf, F, F0d);
+        } else {
+          flux_central_dev(A, B, (T)md[0], (T)md[1], (T)md[2], va, vb, md, Rf, F, F0d);
         }
-        for (int c = 0; c < 3; c++) S[c] = v.Ja[offL * 9 + (3 * d + c) * nnL + iL];
-        double F[5];
-        face_flux<double>(v.surf, uL, uR, S, v.gamma, F);
-        for (int c = 0; c < 5; c++) sF[f][c][q] = F[c];
-      }
-      continue;
-    }
-    const int ma = naL > naR ? naL : naR, mb = nbL > nbR ? nbL : nbR;
-    __syncthreads();  // mortar work arrays free
-    for (int q = t; q < naL * nbL; q += BS) {
-      const int p = q % naL, r = q / naL;
-      const int iL = face_node_rt(IL.n, d, idL, p, r);
-      for (int c = 0; c < 5; c++) sL[c][q] = Uin[offL * 5 + c * nnL + iL];
-      for (int c = 0; c < 3; c++) sL[5 + c][q] = v.Ja[offL * 9 + (3 * d + c) * nnL + iL];
-    }
-    for (int q = t; q < naR * nbR; q += BS) {
-      const int p = q % naR, r = q / naR;
-      const int iR = face_node_rt(IR.n, d, 0, p, r);
-      for (int c = 0; c < 5; c++) sR[c][q] = Uin[offR * 5 + c * nnR + iR];
-    }
-    __syncthreads();
-    // interpolate to the mortar grid (ma x mb): along the first tangential index, then the second
-    const double* mt = v.mtab;
-    const double* IaL = naL < ma ? mt + v.mort_off[naL - 1][ma - 1] : nullptr;
-    const double* IbL = nbL < mb ? mt + v.mort_off[nbL - 1][mb - 1] : nullptr;
-    const double* IaR = naR < ma ? mt + v.mort_off[naR - 1][ma - 1] : nullptr;
-    const double* IbR = nbR < mb ? mt + v.mort_off[nbR - 1][mb - 1] : nullptr;
-    apply_a(IaL, ma, naL, nbL, 8, &sL[0][0], kMixNF, &sT[0][0], kMixNF);
-    __syncthreads();
-    apply_b(IbL, mb, nbL, ma, 8, &sT[0][0], kMixNF, &sL[0][0], kMixNF);
-    __syncthreads();
-    apply_a(IaR, ma, naR, nbR, 5, &sR[0][0], kMixNF, &sT[0][0], kMixNF);
-    __syncthreads();
-    apply_b(IbR, mb, nbR, ma, 5, &sT[0][0], kMixNF, &sR[0][0], kMixNF);
-    __syncthreads();
-    for (int q = t; q < ma * mb; q += BS) {
-      double uL[5], uR[5], S[3], F[5];
-      for (int c = 0; c < 5; c++) {
-        uL[c] = sL[c][q];
-        uR[c] = sR[c][q];
-      }
-      for (int c = 0; c < 3; c++) S[c] = sL[5 + c][q];
-      face_flux<double>(v.surf, uL, uR, S, v.gamma, F);
-      for (int c = 0; c < 5; c++) sL[c][q] = F[c];  // mortar flux replaces the left trace
-    }
-    __syncthreads();
-    // project onto the element's own face grid (na x nb)
-    const double* Pa = na < ma ? mt + v.mort_off[na - 1][ma - 1] + ma * na : nullptr;
-    const double* Pb = nb < mb ? mt + v.mort_off[nb - 1][mb - 1] + mb * nb : nullptr;
-    apply_a(Pa, na, ma, mb, 5, &sL[0][0], kMixNF, &sT[0][0], kMixNF);
-    __syncthreads();
-    apply_b(Pb, nb, mb, na, 5, &sT[0][0], kMixNF, &sF[f][0][0], kMixNF);
-  }
-  __syncthreads();
-
-  // ---- volume (every pair evaluated from both nodes), surface lift, update
-  double acc[SLOTS][5];
-  for (int s = 0; s < SLOTS; s++)
-    for (int c = 0; c < 5; c++) acc[s][c] = 0.0;
-  const double ce = 0.5 / (v.gamma - 1.0), gm1 = v.gamma - 1.0;
-  for (int d = 0; d < 3; d++) {
-    __syncthreads();
-    for (int q = t; q < I.nn; q += BS)
-      for (int c = 0; c < 3; c++) sJ3[c][q] = v.Ja[off * 9 + (3 * d + c) * nn + q];
-    __syncthreads();
-    const int n = I.n[d];
-    const int stride = d == 0 ? 1 : (d == 1 ? I.n[0] : I.n[0] * I.n[1]);
-#pragma unroll
-    for (int s = 0; s < SLOTS; s++) {
-      const int q = t + s * BS;
-      if (q >= I.nn) continue;
-      const int ii[3] = {q % I.n[0], (q / I.n[0]) % I.n[1], q / (I.n[0] * I.n[1])};
-      const int id = ii[d];
-      const int b0 = q - id * stride;
-      Prim<double> A;
-      A.rho = sP[0][q]; A.v1 = sP[1][q]; A.v2 = sP[2][q]; A.v3 = sP[3][q];
-      A.beta = sP[4][q]; A.lrho = sP[5][q]; A.lbeta = sP[6][q];
-      A.h = 0.5 * (A.v1 * A.v1 + A.v2 * A.v2 + A.v3 * A.v3);
-      for (int m = 0; m < n; m++) {
-        if (m == id) continue;
-        const int qm = b0 + m * stride;
-        Prim<double> B;
-        B.rho = sP[0][qm]; B.v1 = sP[1][qm]; B.v2 = sP[2][qm]; B.v3 = sP[3][qm];
-        B.beta = sP[4][qm]; B.lrho = sP[5][qm]; B.lbeta = sP[6][qm];
-        B.h = 0.5 * (B.v1 * B.v1 + B.v2 * B.v2 + B.v3 * B.v3);
-        double F[5];
-        vol_flux<double>(v.vol, A, B, sJ3[0][q] + sJ3[0][qm], sJ3[1][q] + sJ3[1][qm],
-                         sJ3[2][q] + sJ3[2][qm], ce, gm1, F);
-        const double Dm = sD[d][id * n + m];
-        for (int c = 0; c < 5; c++) acc[s][c] += Dm * F[c];
-      }
-      int ta, tb;
-      tangential(d, ta, tb);
-      const int qf = ii[ta] + I.n[ta] * ii[tb];
-      if (id == n - 1)
-        for (int c = 0; c < 5; c++) acc[s][c] += sF[2 * d + 1][c][qf] / sw[d][n - 1];
-      if (id == 0)
-        for (int c = 0; c < 5; c++) acc[s][c] -= sF[2 * d][c][qf] / sw[d][0];
-    }
-  }
-#pragma unroll
-  for (int s = 0; s < SLOTS; s++) {
-    const int q = t + s * BS;
-    if (q >= I.nn) continue;
-    const double ij = v.invJ[off + q];
-    const long o = off * 5 + q;
-    for (int c = 0; c < 5; c++) {
-      const double R = -acc[s][c] * ij;
-      if (mode == kModeResidual) {
-        v.R[o + c * nn] = R;
       } else {
-        const double du = (rkA == 0.0 ? 0.0 : rkA * v.dU[o + c * nn]) + dt * R;
+        vol_flux<T>(v.vol, A, B, (T)md[0], (T)md[1], (T)md[2], ce, gm1, F);
+      }
+      const double Dm = sD[d][id * n + m];
+#pragma unroll
+      for (int c = 0; c < 5; c++) acc[c] += (T)Dm * F[c];
+      if (DEV) accm += Dm * F0d;
+    }
+    const int qf = iq[ta] + I.n[ta] * iq[tb];
+    if (id == n - 1) {
+      const double iw = 1.0 / sw[d][n - 1];
+      const double* F = Fs + (2 * d + 1) * kFsFace;
+#pragma unroll
+      for (int c = 0; c < 5; c++) acc[c] += (T)(iw * F[c * kMixNF + qf]);
+      if (DEV) accm += iw * F[5 * kMixNF + qf];
+    }
+    if (id == 0) {
+      const double iw = 1.0 / sw[d][0];
+      const double* F = Fs + 2 * d * kFsFace;
+#pragma unroll
+      for (int c = 0; c < 5; c++) acc[c] -= (T)(iw * F[c * kMixNF + qf]);
+      if (DEV) accm -= iw * F[5 * kMixNF + qf];
+    }
+  };
+  const int q0 = t, q1 = t + BS;
+  for (int d = 0; d < 3; d++) {
+    __syncthreads();  // the previous direction's metric is no longer read
+    if (q0 < I.nn)
+#pragma unroll
+      for (int c = 0; c < 3; c++) sJ3[c][q0] = v.Ja[off * 9 + (3 * d + c) * nn + q0];
+    if (NPL == 2 && q1 < I.nn)
+#pragma unroll
+      for (int c = 0; c < 3; c++) sJ3[c][q1] = v.Ja[off * 9 + (3 * d + c) * nn + q1];
+    __syncthreads();
+    if (q0 < I.nn) node_volume(d, q0, ii[0], acc0, m0);
+    if (NPL == 2 && q1 < I.nn) node_volume(d, q1, ii[NPL - 1], acc1, m1);
+  }
+  auto node_update = [&](const int q, const T* acc, const double accm) __attribute__((always_inline)) {
+    const double ij = v.invJ[off + q];
+    double R[5];
+#pragma unroll
+    for (int c = 0; c < 5; c++) R[c] = -(double)acc[c] * ij;
+    if (DEV) {  // FP64 mass; energy = H_r (mass) + deviation
+      R[0] = -accm * ij;
+      R[4] -= Rf.H * accm * ij;
+    }
+    const long o = off * 5 + q;
+#pragma unroll
+    for (int c = 0; c < 5; c++) {
+      if (mode == kModeResidual) {
+        v.R[o + c * nn] = R[c];
+      } else {
+        const double du = (rkA == 0.0 ? 0.0 : rkA * v.dU[o + c * nn]) + dt * R[c];
         v.dU[o + c * nn] = du;
         v.U[cur ^ 1][o + c * nn] = Uin[o + c * nn] + rkB * du;
       }
     }
-  }
+  };
+  if (q0 < I.nn) node_update(q0, acc0, m0);
+  if (NPL == 2 && q1 < I.nn) node_update(q1, acc1, m1);
 }
 
 // ------------------------------------------------------------------ diagnostics (FP64)
@@ -455,20 +583,61 @@ hipError_t launch_ic_mixed(const View& v, int cur, int ic, const double* params,
   return hipGetLastError();
 }
 
-hipError_t launch_stage_mixed(const View& v, int cur, double dt, double rkA, double rkB, int mode,
-                              int block, hipStream_t st) {
-  switch (block) {
-    case 128:
-      hipLaunchKernelGGL(mixed_stage_kernel<128>, dim3(v.E), dim3(128), 0, st, v, cur, dt, rkA, rkB, mode);
-      break;
-    case 512:
-      hipLaunchKernelGGL(mixed_stage_kernel<512>, dim3(v.E), dim3(512), 0, st, v, cur, dt, rkA, rkB, mode);
-      break;
-    default:
-      hipLaunchKernelGGL(mixed_stage_kernel<256>, dim3(v.E), dim3(256), 0, st, v, cur, dt, rkA, rkB, mode);
-      break;
-  }
+template <int NNMAX, int NPL>
+static hipError_t stage_bucket(const View& v, int b, int cur, double dt, double rkA, double rkB, int mode,
+                               hipStream_t st) {
+  const dim3 grid(v.mix_cnt[b]), block(mix_lanes(NNMAX, NPL));
+  if (v.fp32)
+    hipLaunchKernelGGL((mixed_stage_kernel<NNMAX, NPL, float>), grid, block, 0, st, v, v.mix_beg[b], cur, dt,
+                       rkA, rkB, mode);
+  else
+    hipLaunchKernelGGL((mixed_stage_kernel<NNMAX, NPL, double>), grid, block, 0, st, v, v.mix_beg[b], cur, dt,
+                       rkA, rkB, mode);
   return hipGetLastError();
+}
+
+template <int NNMAX>
+static hipError_t stage_bucket_npl(const View& v, int b, int npl, int cur, double dt, double rkA, double rkB,
+                                   int mode, hipStream_t st) {
+  return npl == 2 ? stage_bucket<NNMAX, 2>(v, b, cur, dt, rkA, rkB, mode, st)
+                  : stage_bucket<NNMAX, 1>(v, b, cur, dt, rkA, rkB, mode, st);
+}
+
+hipError_t launch_faces_mixed(const View& v, int cur, hipStream_t st) {
+  if (v.fp32)
+    hipLaunchKernelGGL(mixed_face_kernel<float>, dim3(3 * v.E), dim3(64), 0, st, v, cur);
+  else
+    hipLaunchKernelGGL(mixed_face_kernel<double>, dim3(3 * v.E), dim3(64), 0, st, v, cur);
+  return hipGetLastError();
+}
+
+hipError_t launch_stage_mixed_bucket(const View& v, int b, int npl, int cur, double dt, double rkA, double rkB,
+                                     int mode, hipStream_t st) {
+  if (v.mix_cnt[b] <= 0) return hipSuccess;
+  switch (b) {
+    case 0: return stage_bucket_npl<64>(v, b, npl, cur, dt, rkA, rkB, mode, st);
+    case 1: return stage_bucket_npl<128>(v, b, npl, cur, dt, rkA, rkB, mode, st);
+    case 2: return stage_bucket_npl<192>(v, b, npl, cur, dt, rkA, rkB, mode, st);
+    case 3: return stage_bucket_npl<256>(v, b, npl, cur, dt, rkA, rkB, mode, st);
+    case 4: return stage_bucket_npl<320>(v, b, npl, cur, dt, rkA, rkB, mode, st);
+    case 5: return stage_bucket_npl<384>(v, b, npl, cur, dt, rkA, rkB, mode, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_stage_mixed(const View& v, int cur, double dt, double rkA, double rkB, int mode, int tiles,
+                              hipStream_t st) {
+  if (v.fp32)
+    hipLaunchKernelGGL(mixed_face_kernel<float>, dim3(3 * v.E), dim3(64), 0, st, v, cur);
+  else
+    hipLaunchKernelGGL(mixed_face_kernel<double>, dim3(3 * v.E), dim3(64), 0, st, v, cur);
+  const hipError_t ef = hipGetLastError();
+  if (ef != hipSuccess) return ef;
+  for (int b = kMixBuckets - 1; b >= 0; b--) {  // the work list starts with the largest elements
+    const hipError_t e = launch_stage_mixed_bucket(v, b, (tiles >> b) & 1 ? 2 : 1, cur, dt, rkA, rkB, mode, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_diagnostics_mixed(const View& v, int cur, hipStream_t st) {

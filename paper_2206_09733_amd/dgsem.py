@@ -54,7 +54,7 @@ EXPORTS = ["dg_last_error", "dg_mesh_create_box", "dg_mesh_destroy", "dg_mesh_in
            "dg_set_initial_condition", "dg_set_state", "dg_get_state", "dg_residual", "dg_rk_step",
            "dg_diagnostics", "dg_suggest_dt", "dg_get_geometry", "dg_device_pointers",
            "dg_synchronize", "dg_solver_destroy", "dg_profile_begin", "dg_profile_end",
-           "dg_solver_use_graphs", "dg_autotune", "dg_solver_set_block", "dg_batch_create",
+           "dg_solver_use_graphs", "dg_autotune", "dg_solver_set_tiles", "dg_batch_create",
            "dg_batch_rk_step", "dg_batch_use_graphs", "dg_batch_launches", "dg_batch_destroy"]
 
 _lib = None
@@ -104,7 +104,7 @@ def lib():
     L.dg_solver_destroy.restype = None
     L.dg_solver_use_graphs.argtypes = [vp, _c.c_int]
     L.dg_autotune.argtypes = [vp, _c.POINTER(_c.c_int), _dp]
-    L.dg_solver_set_block.argtypes = [vp, _c.c_int]
+    L.dg_solver_set_tiles.argtypes = [vp, _c.c_int]
     L.dg_batch_create.argtypes = [_c.POINTER(vp), _c.c_int, vp, _c.POINTER(vp)]
     L.dg_batch_rk_step.argtypes = [vp, _dp, _c.c_int]
     L.dg_batch_use_graphs.argtypes = [vp, _c.c_int]
@@ -261,13 +261,14 @@ class Solver:
         check(lib().dg_solver_use_graphs(self.h, 1 if enable else 0))
 
     def autotune(self):
-        """Pick the fastest stage-kernel block size (mixed-order meshes); returns (block, us)."""
+        """Pick the faster launch shape of every node-count bucket (mixed-order meshes); returns
+        (tile mask, summed launch time in microseconds)."""
         b, us = _c.c_int(), _c.c_double()
         check(lib().dg_autotune(self.h, _c.byref(b), _c.byref(us)))
         return b.value, us.value
 
-    def set_block(self, block):
-        check(lib().dg_solver_set_block(self.h, int(block)))
+    def set_tiles(self, tiles):
+        check(lib().dg_solver_set_tiles(self.h, int(tiles)))
 
     def synchronize(self):
         check(lib().dg_synchronize(self.h))

@@ -121,10 +121,14 @@ def test_mixed_order_mesh_info_and_solver_limits(dg):
     dg.check(L.dg_mesh_info(m, ctypes.byref(ne), ctypes.byref(nn), ctypes.byref(nmax)))
     assert (ne.value, nn.value, nmax.value) == (3, 2 * 3 * 4 + 7 * 6 * 5 + 27, 6)
     s = ctypes.c_void_p()
-    for bad in (dict(Re=100.0), dict(precision="fp32_bulk")):
-        p = dg.physics(**bad)
-        assert L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)) == dg.DG_EUNSUPPORTED
-        assert b"mixed" in L.dg_last_error()
+    p = dg.physics(Re=100.0)
+    assert L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)) == dg.DG_EUNSUPPORTED
+    assert b"mixed" in L.dg_last_error()
+    p = dg.physics(Ma=0.5, precision="fp32_bulk")
+    dg.check(L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)))
+    assert L.dg_solver_set_tiles(s, 64) == dg.DG_EINVAL
+    assert L.dg_solver_set_tiles(s, 0b100101) == dg.DG_OK
+    L.dg_solver_destroy(s)
     p = dg.physics(Ma=0.5)
     dg.check(L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)))
     nb = ctypes.c_size_t()

@@ -163,21 +163,23 @@ def test_mixed_residual_central_volume_and_edge_meshes(dg, orc):
         assert_parity(f"mixed edge {k}", g.residual(), o.residual(), o80.residual(), layout(o))
 
 
-def test_mixed_block_sizes_bitwise_equal_and_autotune(dg, orc):
+def test_mixed_tile_shapes_bitwise_equal_and_autotune(dg, orc):
+    """One or two nodes per lane, per node-count bucket: the residual is bitwise the same."""
     c = mixed_cfg(4, 4, 4, seed=7, deform=True)
     g = gpu_solver(dg, c)
     g.set_ic("vortex", VORTEX)
     Rs = {}
-    for b in (128, 256, 512):
-        g.set_block(b)
-        Rs[b] = g.residual()
-    assert np.array_equal(Rs[128], Rs[256]) and np.array_equal(Rs[256], Rs[512])
-    b, us = g.autotune()
-    log(f"[autotune 4^3 mixed] block {b} {us:.1f} us")
-    assert b in (128, 256, 512) and us > 0
-    assert np.array_equal(g.residual(), Rs[256])
+    for tiles in (0, 0b111111, 0b101010, 0b010101):
+        g.set_tiles(tiles)
+        Rs[tiles] = g.residual()
+    for tiles in Rs:
+        assert np.array_equal(Rs[tiles], Rs[0]), tiles
+    tiles, us = g.autotune()
+    log(f"[autotune 4^3 mixed] tiles {tiles:06b} {us:.1f} us")
+    assert 0 <= tiles < 64 and us > 0
+    assert np.array_equal(g.residual(), Rs[0])
     with pytest.raises(dg.DgError):
-        g.set_block(64)
+        g.set_tiles(64)
 
 
 # ------------------------------------------------------------------ invariants on the GPU path
@@ -314,10 +316,17 @@ def test_mixed_full_size_residual_and_step(dg, orc):
     g = gpu_solver(dg, c)
     g.set_ic("vortex", VORTEX)
     assert np.abs(g.state() - U).max() <= 1e-14 * np.abs(U).max()
-    b, us = g.autotune()
-    log(f"[mixed 24^3] autotuned block {b}, {us:.1f} us per stage launch")
+    tiles, us = g.autotune()
+    log(f"[mixed 24^3] autotuned tiles {tiles:06b}, {us:.1f} us per stage")
     lay = layout(o)
     assert_parity("mixed 24^3", g.residual(), R64, R80, lay)
+    g32 = dg.Solver(**c, precision="fp32_bulk")
+    g32.set_state(U)
+    g32.autotune()
+    err32 = per_var_max(g32.residual() - R64, lay) / per_var_max(R64, lay)
+    log(f"[mixed 24^3 FP32-bulk] rel err per var {err32}")
+    assert np.all(err32 < FP32_TOL), err32
+    g32.close()
     dt = o.suggest_dt(0.5)
     o.rk3(dt, 1)
     o80.rk3(dt, 1)
@@ -327,3 +336,54 @@ def test_mixed_full_size_residual_and_step(dg, orc):
     eg, e64 = per_var_max(dG - d80, lay), per_var_max(d64 - d80, lay)
     log(f"[mixed 24^3] one RK3 step, increment error: gpu-vs-fp80 {eg / sc} fp64-vs-fp80 {e64 / sc}")
     assert np.all(eg <= np.maximum(1e-12 * sc, 8 * e64))
+
+
+# ------------------------------------------------------------------ FP32-bulk on mixed orders
+# The FP32-bulk tolerance stated for the uniform path (relative L-infinity per conserved variable
+# against the FP64 oracle: density 2e-5, momentum 5e-4, energy 1e-4) holds on mixed orders too.
+FP32_TOL = np.array([2e-5, 5e-4, 5e-4, 5e-4, 1e-4])
+
+
+def test_mixed_fp32_bulk_error(dg, orc):
+    c = mixed_cfg(6, 6, 6, seed=13)
+    o = orc.OracleSolver(**c)
+    o.set_ic("vortex", VORTEX)
+    U = o.state()
+    Ro = o.residual()
+    g = dg.Solver(**c, precision="fp32_bulk")
+    g.set_state(U)
+    Rg = g.residual()
+    lay = layout(o)
+    err = per_var_max(Rg - Ro, lay) / per_var_max(Ro, lay)
+    log(f"[mixed FP32-bulk 6^3] rel err per var {err}")
+    assert np.all(err < FP32_TOL), err
+
+
+def test_mixed_fp32_bulk_trajectory_and_conservation(dg, orc):
+    """20 RK3 steps of the mixed-order vortex in FP32-bulk and FP64 on the GPU (8^3 elements of
+    edge 2.5, which resolve the vortex core): conserved totals drift only by rounding and the
+    states stay close."""
+    c = mixed_cfg(8, 8, 8, seed=14)
+    g64 = gpu_solver(dg, c)
+    g32 = dg.Solver(**c, precision="fp32_bulk")
+    g64.set_ic("vortex", VORTEX)
+    g32.set_ic("vortex", VORTEX)
+    d0 = g64.diagnostics()
+    dt = g64.suggest_dt(0.5)
+    g64.rk_step(dt, 20)
+    g32.rk_step(dt, 20)
+    d64, d32 = g64.diagnostics(), g32.diagnostics()
+    V = d0["volume"]
+    drift = {k: abs(d32[k] - d0[k]) / V for k in ("mass_rho", "mass_rhou", "mass_rhov", "mass_rhow", "mass_rhoE")}
+    log(f"[mixed FP32-bulk drift per unit volume after 20 steps] {drift}")
+    # bounds of the uniform-order FP32-bulk drift test: the deviation parts of momentum and
+    # energy are accumulated in FP32, so their totals are conserved to FP32 rounding per step
+    assert drift["mass_rho"] < 1e-13
+    assert all(drift[k] < 1e-7 for k in ("mass_rhou", "mass_rhov", "mass_rhow"))
+    assert drift["mass_rhoE"] < 1e-9 * d0["mass_rhoE"] / V
+    o = orc.OracleSolver(**c)
+    lay = layout(o)
+    U64, U32 = g64.state(), g32.state()
+    du = per_var_max(U32 - U64, lay) / per_var_max(U64, lay)
+    log(f"[mixed FP32-bulk vs FP64 state after 20 steps] rel diff per var {du}")
+    assert du.max() < 1e-5
