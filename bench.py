@@ -131,12 +131,25 @@ def run_mixed(steps, warmup):
     return out
 
 
-def run_batch_vs_solo(n=32, steps=50):
-    """The first n solves of the serving stream, each run alone one after the other, and the same
-    n as one batch (all present at the start): aggregate throughput of both forms."""
+def small_ensemble(n=64, seed=1):
+    """An ensemble of small solves (parameter sweep): E^3 boxes with E uniform in {4..8}, N in
+    {3, 4, 5}, Mach in [0.1, 0.8], half Navier-Stokes (Re in [400, 3200])."""
+    from paper_2206_09733_amd import synth
+    g = synth.rng(seed)
+    out = []
+    for i in range(n):
+        visc = bool(g.integers(0, 2))
+        out.append(dict(id=i, E=int(g.integers(4, 9)), N=int(g.integers(3, 6)), Ma=float(g.uniform(0.1, 0.8)),
+                        Re=float(g.uniform(400.0, 3200.0)) if visc else 0.0))
+    return out
+
+
+def run_batch_vs_solo(specs, steps=50):
+    """The given solves run alone one after the other, and the same solves as one batch (all
+    present at the start): aggregate throughput of both forms."""
     import torch
-    from paper_2206_09733_amd import dgsem, synth
-    specs = synth.serving_requests(n, seed=0)
+    from paper_2206_09733_amd import dgsem
+    n = len(specs)
     work = sum(5 * q["E"] ** 3 * (q["N"] + 1) ** 3 * 3 * steps for q in specs)
 
     def make():
@@ -296,7 +309,10 @@ def main():
     if not args.skip_mixed:
         result["mixed_order"] = run_mixed(max(10, args.steps // 2), args.warmup)
     if not args.skip_serve:
-        result["batch_vs_solo"] = run_batch_vs_solo()
+        from paper_2206_09733_amd import synth
+        result["batch_vs_solo"] = {
+            "serving_first_32": run_batch_vs_solo(synth.serving_requests(32, seed=0)),
+            "small_ensemble_64": run_batch_vs_solo(small_ensemble(64), steps=100)}
         result["serving"] = run_serving(args.serve_requests, args.serve_rate, args.serve_steps,
                                         args.serve_budget_gib, 20)
     if rank == 0 and not args.no_cpu_baseline:
