@@ -106,28 +106,44 @@ VORTEX = [5.0, 0.0, 0.0, 0.5 * math.sqrt(1.4 / 2.0), 0.5 * math.sqrt(1.4 / 2.0)]
 
 
 def run_mixed(steps, warmup):
-    """24^3 elements with orders (Nx, Ny, Nz) uniform in {2..6} (seed 0), Euler, FP64, graph
-    replay of the RK steps, block size from the autotuner."""
+    """24^3 elements with orders (Nx, Ny, Nz) uniform in {2..6} (seed 0), Euler, graph replay
+    of the RK steps, launch shapes from the autotuner; FP64 and FP32-bulk.  For comparison the
+    same mesh at the uniform order 6 that bounds the mixed orders (the plain form)."""
     from paper_2206_09733_amd import dgsem, synth
     orders = synth.mixed_orders(24 ** 3, seed=0)
-    s = dgsem.Solver(**MIXED, orders=orders)
-    s.set_ic("vortex", VORTEX)
-    tiles, tune_us = s.autotune()
-    dt = s.suggest_dt(0.5)
-    s.rk_step(dt, warmup)
-    ev_ms, _, _ = timed_steps(s, dt, steps, profile=False)
-    _, _, prof = timed_steps(s, dt, max(2, steps // 5))
-    st = prof["stage"]
-    d = s.diagnostics()
     out = {"workload": "Euler isentropic vortex (strength 5, Mach 0.5, diagonal) on [-10,10]^3, "
                        "24^3 hex, per-element orders (Nx,Ny,Nz) uniform in {2..6} (seed 0), EC split "
-                       "form + Roe, mortar faces, RK3 CFL 0.5, graph replay",
-           "elements": s.E, "nodes": s.nodes, "dof": 5 * s.nodes, "dtype": "f64",
-           "value": round(5 * s.nodes * 3 * steps / (ev_ms / 1e3) / 1e9, 3), "unit": "GDOF/s",
-           "ms_per_step": round(ev_ms / steps, 4), "steps": steps, "autotuned_tiles": f"{tiles:06b}",
-           "stage_avg_us": round(st["ms"] / st["launches"] * 1e3, 2),
-           "state_finite": d["nonfinite"] == 0}
-    s.close()
+                       "form + Roe, mortar faces, RK3 CFL 0.5, graph replay"}
+    for prec in ("fp64", "fp32_bulk"):
+        s = dgsem.Solver(**MIXED, orders=orders, precision=prec)
+        s.set_ic("vortex", VORTEX)
+        tiles, tune_us = s.autotune()
+        dt = s.suggest_dt(0.5)
+        s.rk_step(dt, warmup)
+        ev_ms, _, _ = timed_steps(s, dt, steps, profile=False)
+        _, _, prof = timed_steps(s, dt, max(2, steps // 5))
+        st = prof["stage"]
+        d = s.diagnostics()
+        r = {"value": round(5 * s.nodes * 3 * steps / (ev_ms / 1e3) / 1e9, 3), "unit": "GDOF/s",
+             "ms_per_step": round(ev_ms / steps, 4), "autotuned_tiles": f"{tiles:06b}",
+             "stage_avg_us": round(st["ms"] / st["launches"] * 1e3, 2), "state_finite": d["nonfinite"] == 0}
+        if prec == "fp64":
+            out.update({"elements": s.E, "nodes": s.nodes, "dof": 5 * s.nodes, "dtype": "f64", "steps": steps})
+            out.update(r)
+        else:
+            r["speedup_vs_fp64"] = round(r["value"] / out["value"], 3)
+            out["fp32_bulk"] = r
+        s.close()
+    u = dgsem.Solver(**MIXED, N=6)
+    u.set_ic("vortex", VORTEX)
+    dtu = u.suggest_dt(0.5)
+    u.rk_step(dtu, warmup)
+    ev_u, _, _ = timed_steps(u, dtu, steps, profile=False)
+    out["uniform_order6_same_mesh"] = {
+        "nodes": u.nodes, "ms_per_step": round(ev_u / steps, 4),
+        "value": round(5 * u.nodes * 3 * steps / (ev_u / 1e3) / 1e9, 3), "unit": "GDOF/s",
+        "mixed_step_speedup": round((ev_u / steps) / out["ms_per_step"], 3)}
+    u.close()
     return out
 
 
