@@ -147,6 +147,28 @@ def run_mixed(steps, warmup):
     return out
 
 
+def run_large(steps, warmup):
+    """The large comparison: 64^3 elements, N = 5 (56.6 M nodes), Navier-Stokes TGV Re 1600,
+    Ma 0.1, deformed mesh; FP64 against FP32-bulk, time per RK3 step."""
+    from paper_2206_09733_amd import dgsem
+    out = {"workload": "compressible NS Taylor-Green vortex Re1600 Ma0.1 Pr0.71, 64^3 hex deformed, "
+                       "Gauss-Lobatto N=5, EC split form + Roe + BR1, RK3 CFL 0.5"}
+    for prec in ("fp64", "fp32_bulk"):
+        s = dgsem.Solver(64, N=5, deform=True, Ma=0.1, Re=1600.0, precision=prec)
+        s.set_ic("tgv")
+        dt = s.suggest_dt(0.5)
+        s.rk_step(dt, warmup)
+        ev_ms, _, _ = timed_steps(s, dt, steps, profile=False)
+        d = s.diagnostics()
+        out[prec] = {"value": round(5 * s.nodes * 3 * steps / (ev_ms / 1e3) / 1e9, 3), "unit": "GDOF/s",
+                     "ms_per_step": round(ev_ms / steps, 3), "steps": steps, "ke": d["ke"],
+                     "enstrophy": d["enstrophy"], "state_finite": d["nonfinite"] == 0}
+        out["nodes"], out["dof"] = s.nodes, 5 * s.nodes
+        s.close()
+    out["fp32_bulk"]["speedup_vs_fp64"] = round(out["fp32_bulk"]["value"] / out["fp64"]["value"], 3)
+    return out
+
+
 def small_ensemble(n=64, seed=1):
     """An ensemble of small solves (parameter sweep): E^3 boxes with E uniform in {4..8}, N in
     {3, 4, 5}, Mach in [0.1, 0.8], half Navier-Stokes (Re in [400, 3200])."""
@@ -255,6 +277,7 @@ def main():
     ap.add_argument("--skip-fp32", action="store_true")
     ap.add_argument("--skip-mixed", action="store_true")
     ap.add_argument("--skip-serve", action="store_true")
+    ap.add_argument("--skip-large", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-rate", type=float, default=12.0, help="Poisson arrivals per second")
     ap.add_argument("--serve-steps", type=int, default=200)
@@ -324,6 +347,8 @@ def main():
                                "speedup_vs_fp64": round(v32 / value, 3)}
     if not args.skip_mixed:
         result["mixed_order"] = run_mixed(max(10, args.steps // 2), args.warmup)
+    if not args.skip_large:
+        result["large_64_n5"] = run_large(max(5, args.steps // 10), 2)
     if not args.skip_serve:
         from paper_2206_09733_amd import synth
         result["batch_vs_solo"] = {

@@ -239,9 +239,13 @@ class Solver:
         check(lib().dg_suggest_dt(self.h, float(cfl), _c.byref(dt)))
         return dt.value
 
-    def geometry(self):
-        X, Ja, J = np.empty(3 * self.nodes), np.empty(9 * self.nodes), np.empty(self.nodes)
-        check(lib().dg_get_geometry(self.h, _ptr(X), _ptr(Ja), _ptr(J)))
+    def geometry(self, want_X=True, want_Ja=True, want_J=True):
+        """(X, Ja, J) as host arrays; the ones not wanted are None (not copied)."""
+        X = np.empty(3 * self.nodes) if want_X else None
+        Ja = np.empty(9 * self.nodes) if want_Ja else None
+        J = np.empty(self.nodes) if want_J else None
+        check(lib().dg_get_geometry(self.h, _ptr(X) if want_X else None, _ptr(Ja) if want_Ja else None,
+                                    _ptr(J) if want_J else None))
         return X, Ja, J
 
     def device_pointers(self):

@@ -1,0 +1,112 @@
+"""The large comparison workload: Navier-Stokes Taylor-Green vortex, Re 1600, Ma 0.1, Pr 0.71,
+deformed mesh, Gauss-Lobatto N = 5, FP64 and FP32-bulk.
+
+- On a 16^3 subset: kinetic energy and enstrophy of the GPU path, step by step, against the
+  FP64 oracle (FP64: to rounding; FP32-bulk: within the stated tolerance).
+- At the full 64^3 size (56.6 M nodes, 283 M unknowns) the oracle is out of reach, so the run
+  is checked by properties that hold at any size: discrete conservation of the residual, FP32-bulk
+  against FP64 within the stated tolerance, and conserved totals over two RK3 steps.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from helpers import quad_weights_uniform
+
+pytestmark = pytest.mark.gpu
+
+C5 = dict(N=5, deform=True, Ma=0.1, Re=1600.0)
+# FP32-bulk tolerance stated for the residual (relative L-infinity per conserved variable
+# against FP64): density 2e-5, momentum 5e-4, energy 1e-4; 4x at full size, as for the 32^3 case
+FP32_TOL = np.array([2e-5, 5e-4, 5e-4, 5e-4, 1e-4])
+
+
+@pytest.fixture(scope="module")
+def dg():
+    from paper_2206_09733_amd import dgsem
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    dgsem.lib()
+    return dgsem
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def test_c5_subset_energy_and_enstrophy(dg, orc):
+    """16^3 subset, 10 RK3 steps at CFL 0.5: kinetic energy and enstrophy after every step."""
+    c = dict(ex=16, **C5)
+    o = orc.OracleSolver(**c)
+    o.set_ic("tgv")
+    dt = o.suggest_dt(0.5)
+    g64 = dg.Solver(**c)
+    g32 = dg.Solver(**c, precision="fp32_bulk")
+    g64.set_ic("tgv")
+    g32.set_ic("tgv")
+    ke, en = {k: [] for k in ("o", "64", "32")}, {k: [] for k in ("o", "64", "32")}
+    for step in range(10):
+        o.rk3(dt, 1)
+        g64.rk_step(dt, 1)
+        g32.rk_step(dt, 1)
+        for k, d in (("o", o.diagnostics()), ("64", g64.diagnostics()), ("32", g32.diagnostics())):
+            ke[k].append(d["ke"])
+            en[k].append(d["enstrophy"])
+    ke = {k: np.array(v) for k, v in ke.items()}
+    en = {k: np.array(v) for k, v in en.items()}
+    rel = lambda a, b: np.abs(a - b).max() / np.abs(b).max()
+    log(f"[C5 16^3] KE {ke['o'][0]:.10f} -> {ke['o'][-1]:.10f}; enstrophy {en['o'][0]:.8f} -> {en['o'][-1]:.8f}")
+    log(f"[C5 16^3] FP64 vs oracle: KE {rel(ke['64'], ke['o']):.2e} enstrophy {rel(en['64'], en['o']):.2e}; "
+        f"FP32-bulk vs oracle: KE {rel(ke['32'], ke['o']):.2e} enstrophy {rel(en['32'], en['o']):.2e}")
+    assert rel(ke["64"], ke["o"]) < 1e-12 and rel(en["64"], en["o"]) < 1e-11
+    assert rel(ke["32"], ke["o"]) < 1e-6 and rel(en["32"], en["o"]) < 1e-5
+    # viscous decay: the kinetic energy falls at every step in all three runs
+    for k in ke:
+        assert np.all(np.diff(ke[k]) < 0), k
+    g64.close()
+    g32.close()
+
+
+def test_c5_full_size_properties(dg, orc):
+    """64^3 elements: the residual conserves the totals, FP32-bulk matches FP64 within the
+    stated tolerance, and two RK3 steps keep the totals and a finite state."""
+    c = dict(ex=64, **C5)
+    E, nn = 64 ** 3, 216
+    log("C5 full size: FP64 residual")
+    g = dg.Solver(**c)
+    g.set_ic("tgv")
+    R64 = g.residual()
+    _, _, J = g.geometry(want_X=False, want_Ja=False)
+    wq = quad_weights_uniform(orc.gll(5)[1], E) * J
+    R = R64.reshape(E, 5, nn)
+    W = wq.reshape(E, nn)
+    tot = np.einsum("en,evn->v", W, R)
+    mag = np.einsum("en,evn->v", W, np.abs(R))
+    log(f"[C5 64^3] residual totals {tot} magnitudes {mag}")
+    assert np.all(np.abs(tot) < 1e-11 * mag.max())
+    del R
+    d0 = g.diagnostics()
+    dt = g.suggest_dt(0.5)
+    log("C5 full size: FP32-bulk residual")
+    g32 = dg.Solver(**c, precision="fp32_bulk")
+    g32.set_ic("tgv")
+    R32 = g32.residual()
+    err = np.abs(R32 - R64).reshape(E, 5, nn).max(axis=(0, 2)) / np.abs(R64).reshape(E, 5, nn).max(axis=(0, 2))
+    log(f"[C5 64^3] FP32-bulk vs FP64 residual, rel err per var {err}")
+    assert np.all(err < 4 * FP32_TOL), err
+    del R32, R64
+    g.rk_step(dt, 2)
+    g32.rk_step(dt, 2)
+    V = d0["volume"]
+    for name, s in (("fp64", g), ("fp32_bulk", g32)):
+        d = s.diagnostics()
+        drift = {k: abs(d[k] - d0[k]) / V for k in ("mass_rho", "mass_rhou", "mass_rhov", "mass_rhow", "mass_rhoE")}
+        log(f"[C5 64^3 {name}] drift per unit volume after 2 steps {drift}, KE {d0['ke']:.10f} -> {d['ke']:.10f}")
+        assert d["nonfinite"] == 0
+        assert drift["mass_rho"] < 1e-13 and all(drift[k] < 1e-9 for k in ("mass_rhou", "mass_rhov", "mass_rhow"))
+        assert drift["mass_rhoE"] < 1e-10 * d0["mass_rhoE"] / V
+        assert d["ke"] < d0["ke"]
+    g.close()
+    g32.close()
