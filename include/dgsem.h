@@ -157,8 +157,8 @@ int dg_rk_step(dg_solver* s, double dt, int nsteps);
  * eagerly.  enable = 0 disables replay. */
 int dg_solver_use_graphs(dg_solver* s, int enable);
 /* Mixed-order meshes: the stage runs one launch per bucket of elements with 64 b < nodes <=
- * 64 (b + 1), b = 0..5, one node per lane, or two nodes per lane when bit b of the tile mask is
- * set.  dg_autotune times both shapes of every occupied bucket on the current state (residual
+ * 64 (b + 1), b = 0..5 (a bucket of fewer than 2048 elements joins the launch of the next larger
+ * one), one node per lane, or two nodes per lane when bit b of the tile mask is set.  dg_autotune times both shapes of every occupied bucket on the current state (residual
  * mode, five launches each) and keeps the faster; *tiles receives the mask and *us the summed
  * launch time of the chosen shapes in microseconds (either pointer may be NULL).  The residual
  * buffer is overwritten; the state is not changed.  Uniform-order meshes have one launch shape:

@@ -487,6 +487,20 @@ int dg_solver_bind(dg_solver* s, void* dev_ptr, size_t bytes, void* hip_stream) 
       if (v.mix_cnt[bk] == 0) v.mix_beg[bk] = (int)i;
       v.mix_cnt[bk]++;
     }
+    // A launch of few workgroups is mostly its tail: from the largest elements down, a bucket
+    // joins the launch above it (whose workgroups are sized for larger elements) while that
+    // launch holds fewer than kMinLaunch elements.  The ranges stay contiguous in the list.
+    constexpr int kMinLaunch = 2048;
+    int top = -1;
+    for (int bk = dg::kMixBuckets - 1; bk >= 0; bk--) {
+      if (v.mix_cnt[bk] == 0) continue;
+      if (top >= 0 && v.mix_cnt[top] < kMinLaunch) {
+        v.mix_cnt[top] += v.mix_cnt[bk];
+        v.mix_cnt[bk] = 0;
+      } else {
+        top = bk;
+      }
+    }
     DG_HIP(hipMemcpyAsync(b + p.mtab, mtab.data(), sizeof(double) * mtab.size(), hipMemcpyHostToDevice,
                           s->stream), "upload mortar matrices");
     DG_HIP(hipMemcpyAsync(b + p.elem, elem.data(), sizeof(int4) * elem.size(), hipMemcpyHostToDevice,

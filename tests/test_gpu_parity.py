@@ -155,7 +155,7 @@ def test_residual_central_volume_flux(dg, orc):
     assert_parity("central volume", g.residual(), R64, R80, 12, 125)
 
 
-@pytest.mark.parametrize("N", [2, 3, 4, 5, 6])
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 6, 7])
 def test_residual_navier_stokes(dg, orc, N):
     c = cfg(ex=3, ey=2, ez=3, N=N, deform=True, Re=100.0, Ma=0.3)
     log(f"NS residual N={N}")
@@ -314,6 +314,26 @@ def test_fp32_bulk_error(dg, orc, Re):
     err = np.abs(Rg - Ro).reshape(E, 5, 125).max(axis=(0, 2)) / np.abs(Ro).reshape(E, 5, 125).max(axis=(0, 2))
     glob = np.abs(Rg - Ro).max() / np.abs(Ro).max()
     log(f"[FP32-bulk Re={Re}] rel err per var {err} global {glob:.2e}")
+    assert np.all(err < FP32_TOL), err
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 5, 6, 7])
+@pytest.mark.parametrize("surf", ["roe", "llf", "ec", "central"])
+def test_fp32_bulk_orders_and_fluxes(dg, orc, N, surf):
+    """FP32-bulk at every compiled order and surface flux (Navier-Stokes, deformed 4^3 mesh,
+    Ma 0.1 TGV): relative error per conserved variable against the FP64 oracle within the stated
+    tolerance."""
+    c = dict(ex=4, N=N, deform=True, Ma=0.1, Re=1600.0, surf=surf)
+    o = orc.OracleSolver(**c)
+    o.set_ic("tgv")
+    U = o.state()
+    Ro = o.residual()
+    g = dg.Solver(**c, precision="fp32_bulk")
+    g.set_state(U)
+    Rg = g.residual()
+    E, nn = 64, (N + 1) ** 3
+    err = np.abs(Rg - Ro).reshape(E, 5, nn).max(axis=(0, 2)) / np.abs(Ro).reshape(E, 5, nn).max(axis=(0, 2))
+    log(f"[FP32-bulk N={N} {surf}] rel err per var {err}")
     assert np.all(err < FP32_TOL), err
 
 
