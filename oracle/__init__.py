@@ -46,6 +46,7 @@ def _lib(precision="fp64"):
         L.orc_get_metrics.argtypes = [ctypes.c_void_p, _dp, _dp]
         L.orc_set_ic.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp]
         L.orc_rk3.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_int]
+        L.orc_rk.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_int]
         L.orc_suggest_dt.restype = ctypes.c_double
         L.orc_suggest_dt.argtypes = [ctypes.c_void_p, ctypes.c_double]
         L.orc_entropy_production.restype = ctypes.c_double
@@ -236,6 +237,11 @@ class OracleSolver:
 
     def rk3(self, dt, nsteps):
         self.L.orc_rk3(self.h, float(dt), int(nsteps))
+
+    def rk(self, dt, nsteps, scheme="rk3"):
+        """scheme "rk3" (Williamson) or "rk4" (Carpenter-Kennedy, five stages)."""
+        rc = self.L.orc_rk(self.h, {"rk3": 0, "rk4": 1}[scheme], float(dt), int(nsteps))
+        assert rc == 0
 
     def suggest_dt(self, cfl):
         return self.L.orc_suggest_dt(self.h, float(cfl))

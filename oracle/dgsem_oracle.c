@@ -25,7 +25,8 @@
  *   - mortar coupling for faces between elements of different orders (section "Spatial
  *     p-adaptation"): interpolate both traces to the finer face grid, flux there, L2-project
  *     back with exactly integrated matrices;
- *   - Williamson's low-storage RK3 (section "Time advancement");
+ *   - Williamson's low-storage RK3 and Carpenter-Kennedy's low-storage RK4 (section "Time
+ *     advancement");
  *   - entropy S=-rho*s, s=ln p - gamma ln rho and w=dS/du (section "Shock capturing",
  *     eq. shock:entropy).
  */
@@ -898,15 +899,37 @@ int orc_gradients(orc_solver* s, double* Gout) {
 }
 
 /* ------------------------------------------------------------------------------------------
- * 9. Williamson's low-storage RK3:  dU <- A_k dU + dt R(U);  U <- U + B_k dU.
+ * 9. Low-storage (2N) explicit Runge-Kutta schemes (section "Time advancement"): per stage k,
+ *    dU <- A_k dU + dt R(U);  U <- U + B_k dU.
+ *    scheme 0: Williamson's RK3 (the default of the paper), A = (0, -5/9, -153/128),
+ *              B = (1/3, 15/16, 8/15);
+ *    scheme 1: Carpenter and Kennedy's five-stage fourth-order scheme (the paper's RK4 option),
+ *              with their published rational coefficients.
  * ---------------------------------------------------------------------------------------- */
-int orc_rk3(orc_solver* s, double dt, int nsteps) {
-  if (!s || nsteps < 0) return -1;
-  const real A[3] = {0, (real)-5 / 9, (real)-153 / 128};
-  const real B[3] = {(real)1 / 3, (real)15 / 16, (real)8 / 15};
+int orc_rk(orc_solver* s, int scheme, double dt, int nsteps) {
+  if (!s || nsteps < 0 || scheme < 0 || scheme > 1) return -1;
+  real A[5], B[5];
+  int ns;
+  if (scheme == 0) {
+    ns = 3;
+    A[0] = 0; A[1] = (real)-5 / 9; A[2] = (real)-153 / 128;
+    B[0] = (real)1 / 3; B[1] = (real)15 / 16; B[2] = (real)8 / 15;
+  } else {
+    ns = 5;
+    A[0] = 0;
+    A[1] = -(real)567301805773.0L / (real)1357537059087.0L;
+    A[2] = -(real)2404267990393.0L / (real)2016746695238.0L;
+    A[3] = -(real)3550918686646.0L / (real)2091501179385.0L;
+    A[4] = -(real)1275806237668.0L / (real)842570457699.0L;
+    B[0] = (real)1432997174477.0L / (real)9575080441755.0L;
+    B[1] = (real)5161836677717.0L / (real)13612068292357.0L;
+    B[2] = (real)1720146321549.0L / (real)2090206949498.0L;
+    B[3] = (real)3134564353537.0L / (real)4481467310338.0L;
+    B[4] = (real)2277821191437.0L / (real)14882151754819.0L;
+  }
   long n5 = 5 * s->ntot;
   for (int step = 0; step < nsteps; step++)
-    for (int k = 0; k < 3; k++) {
+    for (int k = 0; k < ns; k++) {
       residual(s, s->U, s->R);
 #pragma omp parallel for schedule(static)
       for (long i = 0; i < n5; i++) {
@@ -916,6 +939,8 @@ int orc_rk3(orc_solver* s, double dt, int nsteps) {
     }
   return 0;
 }
+
+int orc_rk3(orc_solver* s, double dt, int nsteps) { return orc_rk(s, 0, dt, nsteps); }
 
 /* ------------------------------------------------------------------------------------------
  * 10. Initial conditions, evaluated at the node coordinates.

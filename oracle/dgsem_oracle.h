@@ -61,6 +61,7 @@ int orc_get_state(const orc_solver* s, double* U);
 int orc_residual(orc_solver* s, double* R);                   /* R = dU/dt of current state  */
 int orc_gradients(orc_solver* s, double* G);                  /* BR1 lifted grad of (v,T)    */
 int orc_rk3(orc_solver* s, double dt, int nsteps);
+int orc_rk(orc_solver* s, int scheme, double dt, int nsteps); /* 0 = Williamson RK3, 1 = CK RK4 */
 double orc_suggest_dt(const orc_solver* s, double cfl);
 int orc_diagnostics(const orc_solver* s, double* out);        /* 14 doubles, see .c          */
 double orc_entropy_production(const orc_solver* s, const double* R); /* sum wJ w(U).R      */

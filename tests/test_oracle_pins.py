@@ -525,6 +525,70 @@ def test_tgv_initial_diagnostics(orc):
     assert abs(d["lambda_max"] - (1.0 + math.sqrt(GAMMA * p0 / 1.0))) < 2e-2
 
 
+def test_rk4_order_on_the_linear_manifold(orc):
+    """Section "Time advancement", the Carpenter-Kennedy RK4 option: on the linear density-wave
+    manifold (uniform v and p, central fluxes) the one-step error against the exact solution
+    exp(dt A) rho must shrink like dt^5 (fourth order), and the scheme must differ from RK3."""
+    from scipy.linalg import expm
+    ex, N = 2, 2
+    s = orc.OracleSolver(ex, 1, 1, N=N, vol="central", surf="central", Ma=0.5)
+    nodes = s.nodes
+    n = (N + 1) ** 3
+    vel = np.array([0.7, 0.2, -0.1])
+    p = 1.3
+
+    def U_of(rho):
+        return to_conservative(rho, np.tile(vel, (nodes, 1)), np.full(nodes, p)).reshape(
+            s.E, n, 5).transpose(0, 2, 1).reshape(-1)
+
+    def rho_of(U):
+        return U.reshape(s.E, 5, n)[:, 0].reshape(-1)
+
+    eps = 1e-2
+    A = np.zeros((nodes, nodes))
+    for j in range(nodes):
+        r = np.ones(nodes)
+        r[j] += eps
+        s.set_state(U_of(r))
+        A[:, j] = rho_of(s.residual()) / eps
+    rho0 = 1 + 0.1 * synth.rng(5).uniform(-1, 1, nodes)
+    errs = {}
+    for scheme in ("rk4", "rk3"):
+        errs[scheme] = []
+        for dt in (0.08, 0.04):
+            s.set_state(U_of(rho0))
+            s.rk(dt, 1, scheme)
+            exact = 1 + expm(dt * A) @ (rho0 - 1)
+            errs[scheme].append(np.abs(rho_of(s.state()) - exact).max())
+    r4 = errs["rk4"][0] / errs["rk4"][1]
+    r3 = errs["rk3"][0] / errs["rk3"][1]
+    assert 28 < r4 < 36, errs      # local error O(dt^5)
+    assert 14 < r3 < 18, errs      # RK3: O(dt^4)
+    assert errs["rk4"][1] < errs["rk3"][1] / 10
+
+
+def test_rk4_global_order_nonlinear(orc):
+    """The RK4 option on the nonlinear Euler equations (2^3 elements, N=3, TGV at Ma 0.3, EC
+    volume flux, Roe faces): the error at a fixed end time against a run with a 16 times smaller
+    step falls by 2^4 per halving of the step (RK3: 2^3)."""
+    c = dict(ex=2, N=3, Ma=0.3)
+    o = orc.OracleSolver(**c)
+    o.set_ic("tgv")
+    U0 = o.state()
+    dt0 = o.suggest_dt(0.4)
+    T = 8 * dt0
+
+    def run(scheme, m):
+        o.set_state(U0)
+        o.rk(T / m, m, scheme)
+        return o.state()
+
+    for scheme, lo, hi in (("rk4", 13, 19), ("rk3", 6.5, 9.5)):
+        ref = run(scheme, 128)
+        e = [np.abs(run(scheme, m) - ref).max() for m in (8, 16)]
+        assert lo < e[0] / e[1] < hi, (scheme, e)
+
+
 def test_rk3_conserves_totals_c1(orc):
     """The 4^3, N=3 Euler TGV at Ma 0.1 (EC + Roe), 10 RK3 steps at CFL 0.5: mass, momentum and
     energy totals are unchanged up to round-off; entropy does not grow."""
