@@ -85,9 +85,10 @@ def timed_steps(s, dt, steps, profile=True):
     return start.elapsed_time(stop), wall, prof
 
 
-def run_gpu(precision, steps, warmup):
+def run_gpu(precision, steps, warmup, scheme="rk3"):
     from paper_2206_09733_amd import dgsem
     s = dgsem.Solver(**WORKLOAD, precision=precision)
+    s.set_scheme(scheme)
     s.set_ic("tgv")
     dt = s.suggest_dt(0.5)
     s.rk_step(dt, warmup)
@@ -345,6 +346,13 @@ def main():
         result["fp32_bulk"] = {"value": round(v32, 3), "unit": "GDOF/s",
                                "ms_per_step": round(r32["event_ms"] / args.steps, 4),
                                "speedup_vs_fp64": round(v32 / value, 3)}
+    r4 = run_gpu("fp64", max(10, args.steps // 5), args.warmup, scheme="rk4")
+    st4 = r4["prof"]["stage"]
+    result["rk4_carpenter_kennedy"] = {
+        "ms_per_step": round(r4["event_ms"] / max(10, args.steps // 5), 4),
+        "stages_per_step": 5, "stage_avg_us": round(st4["ms"] / st4["launches"] * 1e3, 2),
+        "value": round(5 * nodes * 5 * max(10, args.steps // 5) / (r4["event_ms"] / 1e3) / 1e9, 3),
+        "unit": "GDOF-updates/s per RK stage"}
     if not args.skip_mixed:
         result["mixed_order"] = run_mixed(max(10, args.steps // 2), args.warmup)
     if not args.skip_large:

@@ -145,10 +145,17 @@ int dg_get_state(dg_solver* s, double* host_U, size_t n);
 /* R = dU/dt of the current state.  R stays on the device; if host_R is not NULL it is also
  * copied there (n doubles, layout above; synchronises). */
 int dg_residual(dg_solver* s, double* host_R, size_t n);
-/* Advance nsteps steps of Williamson's low-storage RK3 with the fixed step dt:
- * per stage k, dU <- A_k dU + dt R(U); U <- U + B_k dU, A = (0, -5/9, -153/128),
- * B = (1/3, 15/16, 8/15).  Only enqueues work on the solver's stream. */
+/* Advance nsteps steps of the solver's low-storage explicit Runge-Kutta scheme (section "Time
+ * advancement") with the fixed step dt: per stage k, dU <- A_k dU + dt R(U); U <- U + B_k dU.
+ * Default: Williamson's RK3, A = (0, -5/9, -153/128), B = (1/3, 15/16, 8/15); see
+ * dg_solver_set_scheme.  Only enqueues work on the solver's stream. */
 int dg_rk_step(dg_solver* s, double dt, int nsteps);
+/* Time schemes: Williamson's three-stage RK3 (the default), or Carpenter and Kennedy's five-stage
+ * fourth-order low-storage scheme (the paper's RK4 option; their published coefficients). */
+enum { DG_RK3_WILLIAMSON = 0, DG_RK4_CARPENTER_KENNEDY = 1 };
+/* Select the scheme of dg_rk_step (and of batches the solver joins: all members of a batch must
+ * use one scheme).  Errors: DG_EINVAL for an unknown scheme. */
+int dg_solver_set_scheme(dg_solver* s, int scheme);
 /* Graph replay of RK steps (on by default).  When dg_rk_step runs several steps, or the same
  * dt as its previous call, the launches of one step are captured once per starting state
  * buffer into a HIP graph (on a stream the library owns; no memory operations are recorded)
@@ -212,7 +219,7 @@ void dg_solver_destroy(dg_solver* s);
  * after the work the members have pending there (e.g. by synchronising those streams) and does
  * not use a member on its own stream while batch steps are pending.  The solvers stay owned by
  * the caller and must outlive the batch.  Errors: DG_EINVAL for NULL, n < 1 or a repeated
- * member; DG_ESTATE for an unbound member. */
+ * member or members with different time schemes; DG_ESTATE for an unbound member. */
 int dg_batch_create(dg_solver* const* solvers, int n, void* hip_stream, dg_batch** out);
 /* Advance every member nsteps steps of the RK3 of dg_rk_step, member i with step dts[i] (n
  * doubles).  Only enqueues work on the batch's stream.  Like dg_rk_step, the launches of one

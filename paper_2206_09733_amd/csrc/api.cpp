@@ -73,6 +73,7 @@ struct dg_solver {
   double graph_dt[2] = {0.0, 0.0};
   double last_dt = 0.0;
   dg::View* dev_view = nullptr;      // device copy of v (inside the caller's buffer)
+  int scheme = DG_RK3_WILLIAMSON;    // time scheme of dg_rk_step
 };
 
 namespace {
@@ -197,8 +198,21 @@ hipError_t launch_diag_any(dg_solver* s) {
 }
 
 // Williamson's low-storage RK3
-const double kRkA[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
-const double kRkB[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
+// Low-storage (2N) Runge-Kutta schemes: per stage k, dU <- A_k dU + dt R; U <- U + B_k dU.
+struct RkScheme {
+  int stages;
+  double A[5], B[5];
+};
+// Williamson's RK3, and Carpenter and Kennedy's five-stage fourth-order scheme (their published
+// rational coefficients, evaluated in double)
+const RkScheme kRk[2] = {
+    {3, {0.0, -5.0 / 9.0, -153.0 / 128.0, 0.0, 0.0}, {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0, 0.0, 0.0}},
+    {5,
+     {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
+      -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0},
+     {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+      1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+      2277821191437.0 / 14882151754819.0}}};
 
 // (waits for the solver's stream first, so that no replay of a graph is still in flight)
 void drop_graphs(dg_solver* s) {
@@ -248,8 +262,9 @@ int capture_step(dg_solver* s, double dt) {
   hipGraph_t g = nullptr;
   hipError_t err = hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal);
   if (err == hipSuccess) {
-    for (int k = 0; k < 3 && err == hipSuccess; k++) {
-      err = run_stage(s, dt, kRkA[k], kRkB[k], dg::kModeRK);
+    const RkScheme& rk = kRk[s->scheme];
+    for (int k = 0; k < rk.stages && err == hipSuccess; k++) {
+      err = run_stage(s, dt, rk.A[k], rk.B[k], dg::kModeRK);
       s->cur ^= 1;
     }
     const hipError_t e2 = hipStreamEndCapture(s->cap_stream, &g);
@@ -602,11 +617,22 @@ int dg_rk_step(dg_solver* s, double dt, int nsteps) {
       DG_HIP(hipGraphLaunch(s->graph[par], s->stream), "RK-step graph launch");
       s->cur ^= 1;  // three stages, each moving the state to the other buffer
     } else {
-      for (int k = 0; k < 3; k++) {
-        DG_HIP(run_stage(s, dt, kRkA[k], kRkB[k], dg::kModeRK), "RK stage kernels");
+      const RkScheme& rk = kRk[s->scheme];
+      for (int k = 0; k < rk.stages; k++) {
+        DG_HIP(run_stage(s, dt, rk.A[k], rk.B[k], dg::kModeRK), "RK stage kernels");
         s->cur ^= 1;
       }
     }
+  }
+  return DG_OK;
+}
+
+int dg_solver_set_scheme(dg_solver* s, int scheme) {
+  if (!s) return fail(DG_EINVAL, "NULL solver");
+  if (scheme != DG_RK3_WILLIAMSON && scheme != DG_RK4_CARPENTER_KENNEDY) return fail(DG_EINVAL, "unknown time scheme");
+  if (scheme != s->scheme) {
+    drop_graphs(s);
+    s->scheme = scheme;
   }
   return DG_OK;
 }
@@ -799,6 +825,7 @@ struct dg_batch {
   std::vector<Graph> graphs;    // most recent last
   std::vector<double> last_dts;
   bool use_graphs = true;
+  int scheme = DG_RK3_WILLIAMSON;  // the members' common time scheme
 };
 
 namespace {
@@ -832,12 +859,14 @@ hipError_t batch_stage(dg_batch* b, const double* dts, int k, hipStream_t st) {
       e = dg::launch_gradient_batch(B, g.N, g.fp32, st);
       if (e != hipSuccess) return e;
     }
-    e = dg::launch_stage_batch(B, g.N, g.fp32, g.visc, kRkA[k], kRkB[k], dg::kModeRK, st);
+    e = dg::launch_stage_batch(B, g.N, g.fp32, g.visc, kRk[b->scheme].A[k], kRk[b->scheme].B[k], dg::kModeRK,
+                               st);
     if (e != hipSuccess) return e;
   }
   for (int i : b->mixed) {
     dg_solver* s = b->m[i];
-    hipError_t e = dg::launch_stage_mixed(s->v, s->cur, dts[i], kRkA[k], kRkB[k], dg::kModeRK, s->mix_tiles, st);
+    hipError_t e = dg::launch_stage_mixed(s->v, s->cur, dts[i], kRk[b->scheme].A[k], kRk[b->scheme].B[k],
+                                          dg::kModeRK, s->mix_tiles, st);
     if (e != hipSuccess) return e;
   }
   for (dg_solver* s : b->m) s->cur ^= 1;
@@ -853,7 +882,7 @@ int batch_capture(dg_batch* b, const double* dts) {
   hipGraph_t g = nullptr;
   hipError_t err = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
   if (err == hipSuccess) {
-    for (int k = 0; k < 3 && err == hipSuccess; k++) err = batch_stage(b, dts, k, b->cap_stream);
+    for (int k = 0; k < kRk[b->scheme].stages && err == hipSuccess; k++) err = batch_stage(b, dts, k, b->cap_stream);
     const hipError_t e2 = hipStreamEndCapture(b->cap_stream, &g);
     if (err == hipSuccess) err = e2;
   }
@@ -886,8 +915,12 @@ int dg_batch_create(dg_solver* const* solvers, int n, void* hip_stream, dg_batch
     for (int j = 0; j < i; j++)
       if (solvers[j] == solvers[i]) return fail(DG_EINVAL, "a solver appears twice in the batch");
   }
+  for (int i = 1; i < n; i++)
+    if (solvers[i]->scheme != solvers[0]->scheme)
+      return fail(DG_EINVAL, "the solvers of a batch must use one time scheme");
   dg_batch* b = new dg_batch;
   b->m.assign(solvers, solvers + n);
+  b->scheme = solvers[0]->scheme;
   b->stream = static_cast<hipStream_t>(hip_stream);
   for (int i = 0; i < n; i++) {
     const dg_solver* s = solvers[i];
@@ -934,7 +967,8 @@ int dg_batch_rk_step(dg_batch* b, const double* dts, int nsteps) {
   b->last_dts.assign(dts, dts + n);
   for (int it = 0; it < nsteps; it++) {
     if (!replay) {
-      for (int k = 0; k < 3; k++) DG_HIP(batch_stage(b, dts, k, b->stream), "batch RK stage kernels");
+      for (int k = 0; k < kRk[b->scheme].stages; k++)
+        DG_HIP(batch_stage(b, dts, k, b->stream), "batch RK stage kernels");
       continue;
     }
     const dg_batch::Graph* G = nullptr;

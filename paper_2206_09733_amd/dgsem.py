@@ -18,6 +18,7 @@ VOL = {"ec": 0, "central": 1}
 SURF = {"roe": 0, "llf": 1, "ec": 2, "central": 3}
 PRECISION = {"fp64": 0, "fp32_bulk": 1}
 IC = {"uniform": 0, "tgv": 1, "vortex": 2, "density_wave": 3}
+SCHEME = {"rk3": 0, "rk4": 1}
 IC_NPARAMS = {"uniform": 5, "tgv": 0, "vortex": 5, "density_wave": 9}
 
 _c = ctypes
@@ -55,7 +56,8 @@ EXPORTS = ["dg_last_error", "dg_mesh_create_box", "dg_mesh_destroy", "dg_mesh_in
            "dg_diagnostics", "dg_suggest_dt", "dg_get_geometry", "dg_device_pointers",
            "dg_synchronize", "dg_solver_destroy", "dg_profile_begin", "dg_profile_end",
            "dg_solver_use_graphs", "dg_autotune", "dg_solver_set_tiles", "dg_batch_create",
-           "dg_batch_rk_step", "dg_batch_use_graphs", "dg_batch_launches", "dg_batch_destroy"]
+           "dg_batch_rk_step", "dg_batch_use_graphs", "dg_batch_launches", "dg_batch_destroy",
+           "dg_solver_set_scheme"]
 
 _lib = None
 
@@ -111,6 +113,7 @@ def lib():
     L.dg_batch_launches.argtypes = [vp, _c.POINTER(_c.c_int)]
     L.dg_batch_destroy.argtypes = [vp]
     L.dg_batch_destroy.restype = None
+    L.dg_solver_set_scheme.argtypes = [vp, _c.c_int]
     _lib = L
     return L
 
@@ -263,6 +266,10 @@ class Solver:
 
     def use_graphs(self, enable=True):
         check(lib().dg_solver_use_graphs(self.h, 1 if enable else 0))
+
+    def set_scheme(self, scheme):
+        """"rk3" (Williamson, the default) or "rk4" (Carpenter-Kennedy, five stages)."""
+        check(lib().dg_solver_set_scheme(self.h, SCHEME[scheme]))
 
     def autotune(self):
         """Pick the faster launch shape of every node-count bucket (mixed-order meshes); returns

@@ -84,6 +84,8 @@ def test_solver_argument_errors_and_sizes(dg):
     assert L.dg_solver_required_bytes(s, ctypes.byref(nb)) == 0
     nodes = 8 * 64
     assert nb.value >= 8 * nodes * (5 * 4 + 3 + 9 + 2)
+    assert L.dg_solver_set_scheme(s, 2) == dg.DG_EINVAL
+    assert L.dg_solver_set_scheme(s, 1) == dg.DG_OK
     # a too-small buffer is refused before any device work
     assert L.dg_solver_bind(s, ctypes.c_void_p(256), nb.value - 1, None) == dg.DG_ENOMEM
     assert b"smaller" in L.dg_last_error()

@@ -106,3 +106,31 @@ def test_batch_argument_errors(dg):
     with pytest.raises(ValueError):
         b.rk_step([1e-3, 1e-3])
     b.close()
+
+
+def test_batch_rk4_equals_alone(dg):
+    """Members using the RK4 scheme advance in a batch exactly as alone; a batch refuses members
+    with different schemes."""
+    specs = [dict(ex=3, N=3, Ma=0.2), dict(ex=2, N=4, Ma=0.1, Re=800.0), dict(ex=2, N=5, Ma=0.3)]
+
+    def make():
+        out = []
+        for sp in specs:
+            s = dg.Solver(**sp)
+            s.set_scheme("rk4")
+            s.set_ic("tgv")
+            out.append(s)
+        return out
+    alone, batched = make(), make()
+    dts = [s.suggest_dt(0.6) for s in alone]
+    for s, dt in zip(alone, dts):
+        s.rk_step(dt, 3)
+    b = dg.Batch(batched)
+    b.rk_step(dts, 3)
+    for a, c in zip(alone, batched):
+        assert np.array_equal(a.state(), c.state())
+    b.close()
+    other = dg.Solver(ex=2, N=3)
+    with pytest.raises(dg.DgError) as ei:
+        dg.Batch([batched[0], other])
+    assert ei.value.code == dg.DG_EINVAL

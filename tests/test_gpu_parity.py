@@ -256,6 +256,45 @@ def test_rk3_trajectory_navier_stokes(dg, orc):
     assert np.all(d(Ug, U80) <= np.maximum(1e-14 * sc, 8 * d(Uo, U80)))
 
 
+@pytest.mark.parametrize("case", ["c1_euler", "navier_stokes"])
+def test_rk4_trajectory(dg, orc, case):
+    """Carpenter-Kennedy RK4 (the paper's RK4 option): GPU trajectory against the oracle's double
+    and long-double builds, with graph replay, and against eager launches bitwise."""
+    c = dict(ex=4, N=3, Ma=0.1) if case == "c1_euler" else dict(ex=3, N=4, deform=True, Ma=0.1, Re=1600.0)
+    steps = 10 if case == "c1_euler" else 5
+    o = orc.OracleSolver(**c)
+    o.set_ic("tgv")
+    U0 = o.state()
+    dt = o.suggest_dt(0.8)
+    o.rk(dt, steps, "rk4")
+    o80 = orc.OracleSolver(**c, precision="fp80")
+    o80.set_state(U0)
+    o80.rk(dt, steps, "rk4")
+    g = dg.Solver(**c)
+    g.set_scheme("rk4")
+    g.set_state(U0)
+    g.rk_step(dt, steps)
+    ge = dg.Solver(**c)
+    ge.set_scheme("rk4")
+    ge.use_graphs(False)
+    ge.set_state(U0)
+    for _ in range(steps):
+        ge.rk_step(dt, 1)
+    Ug, Uo, U80 = g.state(), o.state(), o80.state()
+    assert np.array_equal(Ug, ge.state())
+    E, nn = o.E, (c["N"] + 1) ** 3
+    d = lambda a, b: np.abs(a - b).reshape(E, 5, nn).max(axis=(0, 2))
+    dG, d64, d80 = Ug - U0, Uo - U0, U80 - U0
+    sc = np.abs(d80).reshape(E, 5, nn).max(axis=(0, 2))
+    log(f"[RK4 {case}] increment error: gpu-vs-fp80 {d(dG, d80) / sc} fp64-vs-fp80 {d(d64, d80) / sc}")
+    assert np.all(d(dG, d80) <= np.maximum(1e-12 * sc, 8 * d(d64, d80)))
+    # not the RK3 trajectory
+    g3 = dg.Solver(**c)
+    g3.set_state(U0)
+    g3.rk_step(dt, steps)
+    assert np.abs(g3.state() - Ug).max() > 1e3 * np.abs(Ug - U80).max()
+
+
 def test_diagnostics_parity(dg, orc):
     c = dict(ex=4, N=4, deform=True, Ma=0.1, Re=1600.0)
     o = orc.OracleSolver(**c)
