@@ -401,7 +401,7 @@ orc_solver* orc_create(int ex, int ey, int ez, const double* lo, const double* h
                        double amp, int n_uniform, const int* orders, double gamma, double Pr,
                        double Ma, double Re, int vol_flux, int surf_flux) {
   if (ex < 1 || ey < 1 || ez < 1 || !lo || !hi) return NULL;
-  if (vol_flux < 0 || vol_flux > 1 || surf_flux < 0 || surf_flux > 3) return NULL;
+  if (vol_flux < 0 || vol_flux > ORC_VOL_IR || surf_flux < 0 || surf_flux > ORC_SURF_IR) return NULL;
   gll_init();
   orc_solver* s = (orc_solver*)calloc(1, sizeof(orc_solver));
   s->ex = ex; s->ey = ey; s->ez = ez; s->E = ex * ey * ez;
@@ -546,6 +546,31 @@ static void two_point_ec(const real uL[5], const real uR[5], const real n[3], re
   F[4] = F[0] * (1 / (2 * (gamma - 1) * b_ln) - v2_a / 2) + v_a[0] * F[1] + v_a[1] * F[2] + v_a[2] * F[3];
 }
 
+/* Ismail and Roe's entropy-conserving two-point flux along n (one of the entropy-conserving
+ * split forms of section "Energy/Entropy stable versions"), written with the parameter vector
+ * z = sqrt(rho/p) (1, v1, v2, v3, p): with {.} the arithmetic and (.)^ln the logarithmic mean,
+ *   rho^ = {z1} (z5)^ln,  v^ = {z1 v}/{z1},  p1^ = {z5}/{z1},
+ *   p2^ = (gamma+1)/(2 gamma) (z5)^ln/(z1)^ln + (gamma-1)/(2 gamma) {z5}/{z1},
+ *   H^ = gamma p2^/((gamma-1) rho^) + |v^|^2/2;
+ *   F = (rho^ v^.n,  rho^ v^ (v^.n) + p1^ n,  rho^ H^ (v^.n)). */
+static void two_point_ir(const real uL[5], const real uR[5], const real n[3], real gamma, real F[5]) {
+  prim_t L = prim(uL, gamma), R = prim(uR, gamma);
+  real z1L = RSQRT(L.rho / L.p), z1R = RSQRT(R.rho / R.p);
+  real z5L = RSQRT(L.rho * L.p), z5R = RSQRT(R.rho * R.p);
+  real z1a = (z1L + z1R) / 2, z5a = (z5L + z5R) / 2;
+  real z1ln = logmean(z1L, z1R), z5ln = logmean(z5L, z5R);
+  real rho = z1a * z5ln;
+  real v[3];
+  for (int c = 0; c < 3; c++) v[c] = (z1L * L.v[c] + z1R * R.v[c]) / 2 / z1a;
+  real p1 = z5a / z1a;
+  real p2 = (gamma + 1) / (2 * gamma) * z5ln / z1ln + (gamma - 1) / (2 * gamma) * z5a / z1a;
+  real H = gamma * p2 / ((gamma - 1) * rho) + (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) / 2;
+  real vn = v[0] * n[0] + v[1] * n[1] + v[2] * n[2];
+  F[0] = rho * vn;
+  for (int c = 0; c < 3; c++) F[1 + c] = F[0] * v[c] + p1 * n[c];
+  F[4] = F[0] * H;
+}
+
 static void two_point_central(const real uL[5], const real uR[5], const real n[3], real gamma, real F[5]) {
   real FL[5], FR[5];
   euler_flux(uL, n, gamma, FL);
@@ -609,12 +634,28 @@ static void riemann(int kind, const real uL[5], const real uR[5], const real S[3
       break;
     }
     case ORC_SURF_EC: two_point_ec(uL, uR, S, gamma, F); break;
+    case ORC_SURF_IR: two_point_ir(uL, uR, S, gamma, F); break;
+    case ORC_SURF_ES: {
+      /* entropy-stable: Chandrashekar's flux minus local Lax-Friedrichs dissipation; the
+       * dissipation (U_R - U_L) has a non-negative inner product with the jump of the entropy
+       * variables (S is convex), so every face produces entropy of the right sign */
+      prim_t L = prim(uL, gamma), R = prim(uR, gamma);
+      real vnL = L.v[0] * n[0] + L.v[1] * n[1] + L.v[2] * n[2];
+      real vnR = R.v[0] * n[0] + R.v[1] * n[1] + R.v[2] * n[2];
+      real lL = RFABS(vnL) + RSQRT(gamma * L.p / L.rho);
+      real lR = RFABS(vnR) + RSQRT(gamma * R.p / R.rho);
+      real lam = lL > lR ? lL : lR;
+      two_point_ec(uL, uR, S, gamma, F);
+      for (int v = 0; v < 5; v++) F[v] -= a * lam * (uR[v] - uL[v]) / 2;
+      break;
+    }
     default: two_point_central(uL, uR, S, gamma, F); break;
   }
 }
 
 static void volume_flux(const orc_solver* s, const real uL[5], const real uR[5], const real n[3], real F[5]) {
   if (s->vol == ORC_VOL_EC) two_point_ec(uL, uR, n, s->gamma, F);
+  else if (s->vol == ORC_VOL_IR) two_point_ir(uL, uR, n, s->gamma, F);
   else two_point_central(uL, uR, n, s->gamma, F);
 }
 
@@ -1165,6 +1206,13 @@ int orc_two_point_ec(const double* UL, const double* UR, const double* n, double
   to_dbl(f, F, 5);
   return 0;
 }
+int orc_two_point_ir(const double* UL, const double* UR, const double* n, double gamma, double* F) {
+  real a[5], b[5], nn[3], f[5];
+  to_real(UL, a, 5); to_real(UR, b, 5); to_real(n, nn, 3);
+  two_point_ir(a, b, nn, gamma, f);
+  to_dbl(f, F, 5);
+  return 0;
+}
 int orc_two_point_central(const double* UL, const double* UR, const double* n, double gamma, double* F) {
   real a[5], b[5], nn[3], f[5];
   to_real(UL, a, 5); to_real(UR, b, 5); to_real(n, nn, 3);
@@ -1173,7 +1221,7 @@ int orc_two_point_central(const double* UL, const double* UR, const double* n, d
   return 0;
 }
 int orc_riemann(int kind, const double* UL, const double* UR, const double* S, double gamma, double* F) {
-  if (kind < 0 || kind > 3) return -1;
+  if (kind < 0 || kind > ORC_SURF_IR) return -1;
   real a[5], b[5], nn[3], f[5];
   to_real(UL, a, 5); to_real(UR, b, 5); to_real(S, nn, 3);
   riemann(kind, a, b, nn, gamma, f);

@@ -133,6 +133,44 @@ def test_ec_flux_consistency_symmetry_tadmor(orc):
         assert abs(dw @ F - dpsi) < 1e-13 * scale
 
 
+def test_ismail_roe_flux_consistency_symmetry_tadmor(orc):
+    """Ismail-Roe entropy-conserving two-point flux (an entropy-conserving split form of section
+    "Energy/Entropy stable versions"): consistency with F_e, symmetry, Tadmor's condition
+    (w_R - w_L).F# = psi_R - psi_L for the entropy of eq. shock:entropy, and it is a different
+    flux from Chandrashekar's (both are entropy conserving; they differ off the diagonal)."""
+    UL, UR, nv = _pairs()
+    differ = 0.0
+    for uL, uR, n in zip(UL, UR, nv):
+        F = orc.two_point_ir(uL, uR, n)
+        np.testing.assert_allclose(orc.two_point_ir(uL, uL, n), orc.euler_flux(uL, n),
+                                   rtol=1e-13, atol=1e-13)
+        np.testing.assert_allclose(F, orc.two_point_ir(uR, uL, n), rtol=1e-14, atol=1e-14)
+        dw = orc.entropy_vars(uR) - orc.entropy_vars(uL)
+        dpsi = uR[1:4] @ n - uL[1:4] @ n
+        scale = np.abs(dw) @ np.abs(F) + abs(uR[1:4] @ n) + abs(uL[1:4] @ n)
+        assert abs(dw @ F - dpsi) < 1e-13 * scale
+        differ = max(differ, np.abs(F - orc.two_point_ec(uL, uR, n)).max() / np.abs(F).max())
+    assert differ > 1e-3
+
+
+def test_entropy_stable_surface_flux(orc):
+    """EC flux with local Lax-Friedrichs dissipation: consistency, the dissipation term equals
+    -lambda/2 |S| (U_R - U_L), and its entropy production (w_R - w_L).(F - F_EC) is negative."""
+    UL, UR, nv = _pairs(200)
+    for uL, uR, n in zip(UL, UR, nv):
+        a = np.linalg.norm(n)
+        nh = n / a
+        F = orc.riemann("es", uL, uR, n)
+        lam = max(abs(u[1:4] @ nh / u[0]) + math.sqrt(GAMMA * 0.4 * (u[4] - 0.5 * (u[1:4] @ u[1:4]) / u[0]) / u[0])
+                  for u in (uL, uR))
+        np.testing.assert_allclose(F - orc.two_point_ec(uL, uR, n), -0.5 * lam * a * (uR - uL),
+                                   rtol=1e-11, atol=1e-12)
+        np.testing.assert_allclose(orc.riemann("es", uL, uL, n), orc.euler_flux(uL, n),
+                                   rtol=1e-13, atol=1e-13)
+        dw = orc.entropy_vars(uR) - orc.entropy_vars(uL)
+        assert dw @ (F - orc.two_point_ec(uL, uR, n)) < 0
+
+
 def test_central_flux(orc):
     UL, UR, nv = _pairs(50)
     for uL, uR, n in zip(UL, UR, nv):
@@ -296,13 +334,14 @@ def _conservation_sums(orc, s, R, N):
     return tot, mag
 
 
-@pytest.mark.parametrize("surf", ["roe", "llf", "ec"])
+@pytest.mark.parametrize("surf,vol", [("roe", "ec"), ("llf", "ec"), ("ec", "ec"), ("es", "ec"), ("ir", "ir"),
+                                      ("roe", "ir")])
 @pytest.mark.parametrize("Re", [0.0, 400.0])
-def test_conservation_of_totals(orc, surf, Re):
+def test_conservation_of_totals(orc, surf, vol, Re):
     """Periodic box, single-valued face fluxes: sum over nodes of w J dU/dt vanishes for every
     conserved variable (mass, momentum, energy)."""
     N = 3
-    s = orc.OracleSolver(3, N=N, deform=True, Ma=0.4, Re=Re, surf=surf)
+    s = orc.OracleSolver(3, N=N, deform=True, Ma=0.4, Re=Re, surf=surf, vol=vol)
     s.set_ic("tgv")
     R = s.residual()
     tot, mag = _conservation_sums(orc, s, R, N)
@@ -336,6 +375,16 @@ def test_entropy_conservation_and_dissipation(orc):
     s2.set_state(U)
     ent_roe = s2.entropy_production(s2.residual())
     assert ent_roe < -1e-6 * scale
+    # Ismail-Roe split form with Ismail-Roe faces: entropy conservative too; with the
+    # entropy-stable faces (EC + LLF dissipation) entropy decays
+    s3 = orc.OracleSolver(3, N=N, deform=True, Ma=0.4, vol="ir", surf="ir")
+    s3.set_state(U)
+    ent_ir = s3.entropy_production(s3.residual())
+    assert abs(ent_ir) < 1e-11 * scale, (ent_ir, scale)
+    s4 = orc.OracleSolver(3, N=N, deform=True, Ma=0.4, surf="es")
+    s4.set_state(U)
+    ent_es = s4.entropy_production(s4.residual())
+    assert ent_es < -1e-6 * scale
 
 
 def test_split_central_equals_strong_form_affine(orc):
