@@ -54,10 +54,14 @@ extern "C" {
 
 /* ------------------------------------------------------------------ options */
 enum { DG_DEFORM_NONE = 0, DG_DEFORM_SINSIN = 1 };
-/* volume two-point flux: Chandrashekar's entropy-conserving flux, or the central average */
-enum { DG_VOL_EC = 0, DG_VOL_CENTRAL = 1 };
-/* surface numerical flux */
-enum { DG_SURF_ROE = 0, DG_SURF_LLF = 1, DG_SURF_EC = 2, DG_SURF_CENTRAL = 3 };
+/* volume two-point flux (split forms of section "Energy/Entropy stable versions"):
+ * Chandrashekar's entropy-conserving, kinetic-energy-preserving flux; the central average;
+ * Ismail and Roe's entropy-conserving flux */
+enum { DG_VOL_EC = 0, DG_VOL_CENTRAL = 1, DG_VOL_IR = 2 };
+/* surface numerical flux: Roe, local Lax-Friedrichs, Chandrashekar's EC flux, central,
+ * entropy stable (Chandrashekar's flux minus local Lax-Friedrichs dissipation), Ismail-Roe.
+ * The Ismail-Roe and entropy-stable options are evaluated in FP64 only. */
+enum { DG_SURF_ROE = 0, DG_SURF_LLF = 1, DG_SURF_EC = 2, DG_SURF_CENTRAL = 3, DG_SURF_ES = 4, DG_SURF_IR = 5 };
 /* precision: all-FP64, or FP32 flux/derivative arithmetic with FP64 metrics, RK state and
  * reductions */
 enum { DG_FP64 = 0, DG_FP32_BULK = 1 };
@@ -122,8 +126,9 @@ int dg_mesh_info(const dg_mesh* m, long long* n_elements, long long* n_nodes, in
 /* ------------------------------------------------------------------ solver */
 /* Create a solver for the mesh (the mesh may be destroyed afterwards).  Errors: DG_EINVAL for
  * gamma <= 1, Pr <= 0, unknown flux or precision codes; DG_EUNSUPPORTED for an order without
- * a compiled kernel (uniform orders 1..7 are compiled), and for a mixed-order mesh with
- * Re > 0 (mixed-order meshes are evaluated for the Euler equations, in FP64 or FP32-bulk). */
+ * a compiled kernel (uniform orders 1..7 are compiled), for a mixed-order mesh with Re > 0
+ * (mixed-order meshes are evaluated for the Euler equations, in FP64 or FP32-bulk), and for
+ * DG_FP32_BULK with DG_VOL_IR, DG_SURF_ES or DG_SURF_IR. */
 int dg_solver_create(const dg_mesh* m, const dg_physics* p, dg_solver** out);
 /* Bytes of device memory the solver needs (host-only; used for admission control). */
 int dg_solver_required_bytes(const dg_solver* s, size_t* bytes);

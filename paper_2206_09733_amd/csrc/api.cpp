@@ -361,10 +361,12 @@ int dg_solver_create(const dg_mesh* m, const dg_physics* p, dg_solver** out) {
   if (!(p->gamma > 1.0)) return fail(DG_EINVAL, "gamma must exceed 1");
   if (p->Re > 0 && !(p->Pr > 0)) return fail(DG_EINVAL, "Pr must be positive");
   if (!(p->Ma > 0)) return fail(DG_EINVAL, "Ma must be positive");
-  if (p->vol_flux != DG_VOL_EC && p->vol_flux != DG_VOL_CENTRAL) return fail(DG_EINVAL, "unknown volume flux");
-  if (p->surf_flux < DG_SURF_ROE || p->surf_flux > DG_SURF_CENTRAL) return fail(DG_EINVAL, "unknown surface flux");
+  if (p->vol_flux < DG_VOL_EC || p->vol_flux > DG_VOL_IR) return fail(DG_EINVAL, "unknown volume flux");
+  if (p->surf_flux < DG_SURF_ROE || p->surf_flux > DG_SURF_IR) return fail(DG_EINVAL, "unknown surface flux");
   if (p->precision != DG_FP64 && p->precision != DG_FP32_BULK) return fail(DG_EINVAL, "unknown precision");
   if (m->N < 1 || m->N > dg::kMaxOrder) return fail(DG_EUNSUPPORTED, "no kernel for this order");
+  if (p->precision == DG_FP32_BULK && (p->vol_flux == DG_VOL_IR || p->surf_flux >= DG_SURF_ES))
+    return fail(DG_EUNSUPPORTED, "the Ismail-Roe and entropy-stable fluxes are evaluated in FP64");
   if (m->mixed && p->Re > 0)
     return fail(DG_EUNSUPPORTED, "mixed-order meshes are evaluated for the Euler equations (Re <= 0)");
   dg_solver* s = new dg_solver;
@@ -807,9 +809,9 @@ int dg_profile_end(dg_solver* s, dg_profile* out) {
 
 // ------------------------------------------------------------------ batches of solvers
 struct dg_batch {
-  struct Group {  // uniform-order members of one order and precision, viscous or not
+  struct Group {  // uniform-order members of one order, precision and surface-flux family, viscous or not
     int N;
-    bool fp32, visc;
+    bool fp32, visc, xs;
     std::vector<int> idx;
   };
   struct Graph {
@@ -859,8 +861,8 @@ hipError_t batch_stage(dg_batch* b, const double* dts, int k, hipStream_t st) {
       e = dg::launch_gradient_batch(B, g.N, g.fp32, st);
       if (e != hipSuccess) return e;
     }
-    e = dg::launch_stage_batch(B, g.N, g.fp32, g.visc, kRk[b->scheme].A[k], kRk[b->scheme].B[k], dg::kModeRK,
-                               st);
+    e = dg::launch_stage_batch(B, g.N, g.fp32, g.visc, g.xs, kRk[b->scheme].A[k], kRk[b->scheme].B[k],
+                               dg::kModeRK, st);
     if (e != hipSuccess) return e;
   }
   for (int i : b->mixed) {
@@ -928,12 +930,13 @@ int dg_batch_create(dg_solver* const* solvers, int n, void* hip_stream, dg_batch
       b->mixed.push_back(i);
       continue;
     }
-    const bool fp32 = s->v.fp32 != 0, visc = s->v.viscous != 0;
+    const bool fp32 = s->v.fp32 != 0, visc = s->v.viscous != 0, xs = s->v.surf >= DG_SURF_ES;
     dg_batch::Group* g = nullptr;
     for (auto& x : b->groups)
-      if (x.N == s->v.N && x.fp32 == fp32 && x.visc == visc && (int)x.idx.size() < dg::kMaxBatch) g = &x;
+      if (x.N == s->v.N && x.fp32 == fp32 && x.visc == visc && x.xs == xs && (int)x.idx.size() < dg::kMaxBatch)
+        g = &x;
     if (!g) {
-      b->groups.push_back({s->v.N, fp32, visc, {}});
+      b->groups.push_back({s->v.N, fp32, visc, xs, {}});
       g = &b->groups.back();
     }
     g->idx.push_back(i);

@@ -155,17 +155,61 @@ __device__ __forceinline__ void flux_central(const Prim<T>& a, const Prim<T>& b,
   for (int c = 0; c < 5; c++) F[c] = (T)0.5 * (Fa[c] + Fb[c]);
 }
 
+// logarithmic mean of x_a, x_b from their logarithms la, lb (series near x_a = x_b, as above)
+template <typename T>
+__device__ __forceinline__ T logmean_logs(T xa, T xb, T la, T lb) {
+  const T s = xa + xb, d = xa - xb;
+  const T f = d * rcp(s), u = f * f;
+  const T thr = sizeof(T) == 8 ? (T)1e-4 : (T)1e-2;
+  if (u < thr) return s * rcp((T)2 * ((T)1 + u * ((T)(1.0 / 3.0) + u * ((T)0.2 + u * (T)(1.0 / 7.0)))));
+  return d * rcp(la - lb);
+}
+
+// Ismail and Roe's entropy-conserving two-point flux along n, from the parameter vector
+// z = sqrt(rho/p) (1, v, p): z1 = sqrt(2 beta), z5 = rho / z1, so ln z1 = (ln 2 + ln beta)/2 and
+// ln z5 = ln rho - ln z1 come from the stored logarithms.
+//   rho^ = {z1} (z5)^ln, v^ = {z1 v}/{z1}, p1^ = {z5}/{z1},
+//   p2^ = (gamma+1)/(2 gamma) (z5)^ln/(z1)^ln + (gamma-1)/(2 gamma) p1^,
+//   H^ = gamma p2^/((gamma-1) rho^) + |v^|^2/2,  F = (rho^ v^.n, rho^ v^ v^.n + p1^ n, rho^ H^ v^.n)
+template <typename T>
+__device__ __forceinline__ void flux_ir(const Prim<T>& a, const Prim<T>& b, T n1, T n2, T n3, T gm1, T F[5]) {
+  const T g = gm1 + (T)1;
+  const T z1a = sqrt((T)2 * a.beta), z1b = sqrt((T)2 * b.beta);
+  const T iz1a = rcp(z1a), iz1b = rcp(z1b);
+  const T z5a = a.rho * iz1a, z5b = b.rho * iz1b;
+  const T hl2 = (T)0.34657359027997264;  // ln(2) / 2
+  const T l1a = hl2 + (T)0.5 * a.lbeta, l1b = hl2 + (T)0.5 * b.lbeta;
+  const T z1ln = logmean_logs(z1a, z1b, l1a, l1b);
+  const T z5ln = logmean_logs(z5a, z5b, a.lrho - l1a, b.lrho - l1b);
+  const T is1 = rcp(z1a + z1b);
+  const T rho = (T)0.5 * (z1a + z1b) * z5ln;
+  const T u = (z1a * a.v1 + z1b * b.v1) * is1, v = (z1a * a.v2 + z1b * b.v2) * is1,
+          w = (z1a * a.v3 + z1b * b.v3) * is1;
+  const T p1 = (z5a + z5b) * is1;
+  const T p2 = (g + (T)1) / ((T)2 * g) * z5ln * rcp(z1ln) + gm1 / ((T)2 * g) * p1;
+  const T H = g * p2 * rcp(gm1 * rho) + (T)0.5 * (u * u + v * v + w * w);
+  const T vn = u * n1 + v * n2 + w * n3;
+  F[0] = rho * vn;
+  F[1] = F[0] * u + p1 * n1;
+  F[2] = F[0] * v + p1 * n2;
+  F[3] = F[0] * w + p1 * n3;
+  F[4] = F[0] * H;
+}
+
+// volume two-point flux: 0 Chandrashekar, 1 central, 2 Ismail-Roe
 template <typename T>
 __device__ __forceinline__ void vol_flux(int kind, const Prim<T>& a, const Prim<T>& b, T n1, T n2,
                                          T n3, T ce, T gm1, T F[5]) {
   if (kind == 0) flux_ec(a, b, n1, n2, n3, ce, F);
+  else if (kind == 2) flux_ir(a, b, n1, n2, n3, gm1, F);
   else flux_central(a, b, n1, n2, n3, gm1, F);
 }
 
 // Numerical flux through a face with scaled normal S (|S| times the unit normal), between
-// the conservative states uL (the side S points away from) and uR.
+// the conservative states uL (the side S points away from) and uR: Roe (0), local
+// Lax-Friedrichs (1), Chandrashekar's EC flux (2), central (3).
 template <typename T>
-__device__ __forceinline__ void face_flux(int kind, const double uL[5], const double uR[5],
+__device__ __forceinline__ void face_flux_std(int kind, const double uL[5], const double uR[5],
                                           const double S[3], double gamma, T F[5]) {
   const T gm1 = (T)(gamma - 1.0);
   if (kind == 2) {  // entropy-conserving flux, linear in S
@@ -253,6 +297,48 @@ __device__ __forceinline__ void face_flux(int kind, const double uL[5], const do
   W[4] = w1 * (H - vn * c) + l2 * (a2 * (T)0.5 * q2 + rho * udt) + w3 * (H + vn * c);
 #pragma unroll
   for (int k = 0; k < 5; k++) F[k] = (T)0.5 * area * (Fs[k] - W[k]);
+}
+
+// The extended surface fluxes: entropy stable (4: Chandrashekar's flux minus local
+// Lax-Friedrichs dissipation) and Ismail-Roe (5).
+template <typename T>
+__device__ __forceinline__ void face_flux_xs(int kind, const double uL[5], const double uR[5],
+                                             const double S[3], double gamma, T F[5]) {
+  const T gm1 = (T)(gamma - 1.0);
+  const Prim<T> a = make_prim<T>(uL, gamma), b = make_prim<T>(uR, gamma);
+  if (kind == 5) {
+    flux_ir(a, b, (T)S[0], (T)S[1], (T)S[2], gm1, F);
+    return;
+  }
+  flux_ec(a, b, (T)S[0], (T)S[1], (T)S[2], (T)(0.5 / (gamma - 1.0)), F);
+  const T s1 = (T)S[0], s2 = (T)S[1], s3 = (T)S[2];
+  const T a2s = s1 * s1 + s2 * s2 + s3 * s3;
+  const T ia = rsq(a2s);
+  const T area = a2s * ia;
+  const T g = (T)gamma;
+  T lam = (T)0;
+  const double* u2[2] = {uL, uR};
+#pragma unroll
+  for (int q = 0; q < 2; q++) {
+    const double* u = u2[q];
+    const double i = rcp(u[0]);
+    const double a1 = u[1] * i, a2 = u[2] * i, a3 = u[3] * i;
+    const T p = (T)((gamma - 1.0) * (u[4] - 0.5 * u[0] * (a1 * a1 + a2 * a2 + a3 * a3)));
+    const T vn = ((T)a1 * s1 + (T)a2 * s2 + (T)a3 * s3) * ia;
+    const T c2 = g * p * (T)i;
+    const T l = fabs(vn) + c2 * rsq(c2);
+    lam = l > lam ? l : lam;
+  }
+#pragma unroll
+  for (int c = 0; c < 5; c++) F[c] -= (T)0.5 * area * lam * (T)(uR[c] - uL[c]);
+}
+
+// XS selects the family: the two are compiled apart so that the common one keeps its registers
+template <typename T, bool XS = false>
+__device__ __forceinline__ void face_flux(int kind, const double uL[5], const double uR[5],
+                                          const double S[3], double gamma, T F[5]) {
+  if constexpr (XS) face_flux_xs<T>(kind, uL, uR, S, gamma, F);
+  else face_flux_std<T>(kind, uL, uR, S, gamma, F);
 }
 
 // ------------------------------------------------------------------ FP32-bulk: deviation form

@@ -90,8 +90,8 @@ hipError_t launch_diag_final(const View& v, hipStream_t st);  // partials -> dia
 // batched Navier-Stokes gradient pass and stage of members of order N (all viscous, or all
 // inviscid for the stage), FP32-bulk or FP64
 hipError_t launch_gradient_batch(const BatchArgs& B, int N, bool fp32, hipStream_t st);
-hipError_t launch_stage_batch(const BatchArgs& B, int N, bool fp32, bool visc, double rkA, double rkB,
-                              int mode, hipStream_t st);
+hipError_t launch_stage_batch(const BatchArgs& B, int N, bool fp32, bool visc, bool xs, double rkA, double rkB,
+                              int mode, hipStream_t st);  // xs: members use the extended surface fluxes
 
 // mixed-order meshes (kernels_mixed.hip).  The stage runs one launch per bucket of elements
 // (bucket b: 64 b < nodes <= 64 (b + 1)); bit b of `tiles` gives bucket b two nodes per lane

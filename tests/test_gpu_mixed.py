@@ -120,11 +120,12 @@ def test_mixed_initial_condition_parity(dg, orc):
 
 
 # ------------------------------------------------------------------ residual
-@pytest.mark.parametrize("surf", ["roe", "llf", "ec", "central"])
+@pytest.mark.parametrize("surf", ["roe", "llf", "ec", "central", "es", "ir"])
 def test_mixed_residual_parity(dg, orc, surf):
     """3x3x3 elements with orders drawn from {1..6} per direction on a deformed mesh: most faces
     are p-nonconforming in one or both tangential directions."""
-    c = mixed_cfg(3, 3, 3, seed=10, nlo=1, nhi=6, deform=True, amp=0.3, surf=surf)
+    c = mixed_cfg(3, 3, 3, seed=10, nlo=1, nhi=6, deform=True, amp=0.3, surf=surf,
+                  vol="ir" if surf == "ir" else "ec")
     log(f"mixed residual {surf}")
     o = orc.OracleSolver(**c)
     o.set_ic("vortex", VORTEX)

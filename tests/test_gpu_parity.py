@@ -146,6 +146,40 @@ def test_residual_orders_and_fluxes(dg, orc, N, surf):
     assert_parity(f"N={N} {surf}", g.residual(), R64, R80, 12, (N + 1) ** 3)
 
 
+@pytest.mark.parametrize("N", [2, 3, 4, 5, 7])
+@pytest.mark.parametrize("vol,surf,Re", [("ir", "ir", 0.0), ("ec", "es", 0.0), ("ir", "es", 100.0),
+                                         ("ec", "ir", 100.0)])
+def test_residual_ismail_roe_and_entropy_stable(dg, orc, N, vol, surf, Re):
+    """Ismail-Roe volume/surface fluxes and the entropy-stable surface flux (FP64)."""
+    c = cfg(ex=3, ey=2, ez=2, N=N, deform=True, vol=vol, surf=surf, Re=Re, Ma=0.3)
+    log(f"residual N={N} vol={vol} surf={surf} Re={Re}")
+    U = perturbed_state(orc, c, seed=300 + N)
+    R64, R80 = oracle_pair(orc, c, U)
+    g = dg.Solver(**c)
+    g.set_state(U)
+    assert_parity(f"N={N} {vol}/{surf} Re={Re}", g.residual(), R64, R80, 12, (N + 1) ** 3)
+
+
+def test_gpu_entropy_ismail_roe_and_stable(dg, orc):
+    """On the GPU path: the Ismail-Roe split form with Ismail-Roe faces conserves entropy; with
+    the entropy-stable faces entropy decays; FP32-bulk refuses these fluxes."""
+    c = cfg(ex=3, N=3, deform=True, Ma=0.4)
+    U = perturbed_state(orc, c, seed=12, amp=(0.05, 0.1, 0.05))
+    o = orc.OracleSolver(**c)
+    o.set_state(U)
+    g = dg.Solver(**dict(c, vol="ir", surf="ir"))
+    g.set_state(U)
+    R = g.residual()
+    ref = abs(o.entropy_production(np.abs(R)))
+    assert abs(o.entropy_production(R)) < 1e-11 * ref
+    g2 = dg.Solver(**dict(c, surf="es"))
+    g2.set_state(U)
+    assert o.entropy_production(g2.residual()) < -1e-6 * ref
+    with pytest.raises(dg.DgError) as ei:
+        dg.Solver(**dict(c, surf="es"), precision="fp32_bulk", bind=False)
+    assert ei.value.code == dg.DG_EUNSUPPORTED
+
+
 def test_residual_central_volume_flux(dg, orc):
     c = cfg(ex=2, ey=3, ez=2, N=4, deform=True, vol="central", surf="llf")
     U = perturbed_state(orc, c, seed=7)
