@@ -10,8 +10,8 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
-VOL = {"ec": 0, "central": 1, "ir": 2}
-SURF = {"roe": 0, "llf": 1, "ec": 2, "central": 3, "es": 4, "ir": 5}
+VOL = {"ec": 0, "central": 1, "ir": 2, "kg": 3, "pirozzoli": 4, "ducros": 5, "morinishi": 6}
+SURF = {"roe": 0, "llf": 1, "ec": 2, "central": 3, "es": 4, "ir": 5, "es_matrix": 6, "ld_roe": 7}
 IC = {"uniform": 0, "tgv": 1, "vortex": 2, "density_wave": 3}
 DIAG_KEYS = ["mass_rho", "mass_rhou", "mass_rhov", "mass_rhow", "mass_rhoE", "entropy_paper",
              "entropy", "ke", "enstrophy", "lambda_max", "rho_min", "p_min", "nonfinite", "volume"]
@@ -58,6 +58,7 @@ def _lib(precision="fp64"):
         L.orc_two_point_ec.argtypes = [_dp, _dp, _dp, ctypes.c_double, _dp]
         L.orc_two_point_central.argtypes = [_dp, _dp, _dp, ctypes.c_double, _dp]
         L.orc_two_point_ir.argtypes = [_dp, _dp, _dp, ctypes.c_double, _dp]
+        L.orc_two_point.argtypes = [ctypes.c_int, _dp, _dp, _dp, ctypes.c_double, _dp]
         L.orc_riemann.argtypes = [ctypes.c_int, _dp, _dp, _dp, ctypes.c_double, _dp]
         L.orc_roe_waves.argtypes = [_dp, _dp, _dp, ctypes.c_double, ctypes.c_int, _dp]
         L.orc_entropy_vars.argtypes = [_dp, ctypes.c_double, _dp]
@@ -126,6 +127,14 @@ def two_point_central(UL, UR, n, gamma=1.4, precision="fp64"):
 def two_point_ir(UL, UR, n, gamma=1.4, precision="fp64"):
     return _point("orc_two_point_ir", UL, UR, n, scalars=(ctypes.c_double(gamma),),
                   precision=precision)
+
+
+def two_point(kind, UL, UR, n, gamma=1.4, precision="fp64"):
+    """Any volume two-point flux by name (see VOL)."""
+    res = np.zeros(5)
+    _lib(precision).orc_two_point(VOL[kind], _ptr(_f64(UL)), _ptr(_f64(UR)), _ptr(_f64(n)),
+                                  gamma, _ptr(res))
+    return res
 
 
 def riemann(kind, UL, UR, S, gamma=1.4, precision="fp64"):

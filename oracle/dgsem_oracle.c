@@ -19,8 +19,11 @@
  *     versions": the SBP-SAT property of Gauss-Lobatto quadrature);
  *   - split-form volume term with Chandrashekar's entropy-conserving two-point flux and the
  *     averaged metric of the two nodes (same section, list of split forms);
- *   - Riemann fluxes Roe, Lax-Friedrichs (local, i.e. Rusanov), central and the EC flux at
- *     faces (box of convective fluxes in section "Spatial discretisation");
+ *   - the other split forms of that list: Ismail-Roe's entropy-conserving flux and the
+ *     kinetic-energy-preserving fluxes of Kennedy-Gruber, Pirozzoli, Ducros and Morinishi;
+ *   - Riemann fluxes Roe (which is Roe-Pike's wave-strength evaluation), Lax-Friedrichs
+ *     (local, i.e. Rusanov), low-dissipation Roe, matrix dissipation, central and the EC flux
+ *     at faces (box of convective fluxes in section "Spatial discretisation");
  *   - BR1 for the viscous terms (same box), gradients of (v,T) lifted with the face average;
  *   - mortar coupling for faces between elements of different orders (section "Spatial
  *     p-adaptation"): interpolate both traces to the finer face grid, flux there, L2-project
@@ -401,7 +404,7 @@ orc_solver* orc_create(int ex, int ey, int ez, const double* lo, const double* h
                        double amp, int n_uniform, const int* orders, double gamma, double Pr,
                        double Ma, double Re, int vol_flux, int surf_flux) {
   if (ex < 1 || ey < 1 || ez < 1 || !lo || !hi) return NULL;
-  if (vol_flux < 0 || vol_flux > ORC_VOL_IR || surf_flux < 0 || surf_flux > ORC_SURF_IR) return NULL;
+  if (vol_flux < 0 || vol_flux > ORC_VOL_MORINISHI || surf_flux < 0 || surf_flux > ORC_SURF_LOW_DISS_ROE) return NULL;
   gll_init();
   orc_solver* s = (orc_solver*)calloc(1, sizeof(orc_solver));
   s->ex = ex; s->ey = ey; s->ez = ez; s->E = ex * ey * ez;
@@ -578,9 +581,62 @@ static void two_point_central(const real uL[5], const real uR[5], const real n[3
   for (int v = 0; v < 5; v++) F[v] = (FL[v] + FR[v]) / 2;
 }
 
+/* The kinetic-energy-preserving split forms of section "Energy/Entropy stable versions" (list
+ * of split forms), written as two-point fluxes along n from products of arithmetic means
+ * {a} = (a_L + a_R)/2; vn = v.n, e = rho*E/rho (total energy per unit mass), H = e + p/rho.
+ *   Kennedy-Gruber: F_rho = {rho}{vn},  F_m = {rho}{vn}{v} + {p} n,  F_E = {rho}{vn}{e} + {p}{vn}
+ *   Pirozzoli:      F_rho = {rho}{vn},  F_m = {rho}{vn}{v} + {p} n,  F_E = {rho}{vn}{H}
+ *   Ducros:         F_rho = {rho}{vn},  F_m = {rho v}{vn} + {p} n,   F_E = {rho e + p}{vn}
+ *   Morinishi:      F_rho = {rho vn},   F_m = {rho vn}{v} + {p} n,
+ *                   F_E = gamma/(gamma-1) {p vn} + {rho vn}({v}.{v}) - {rho vn |v|^2}/2 */
+static void two_point_kep(int kind, const real uL[5], const real uR[5], const real n[3], real gamma, real F[5]) {
+  prim_t L = prim(uL, gamma), R = prim(uR, gamma);
+  real vnL = L.v[0] * n[0] + L.v[1] * n[1] + L.v[2] * n[2];
+  real vnR = R.v[0] * n[0] + R.v[1] * n[1] + R.v[2] * n[2];
+  real rho_a = (L.rho + R.rho) / 2, vn_a = (vnL + vnR) / 2, p_a = (L.p + R.p) / 2;
+  real v_a[3];
+  for (int c = 0; c < 3; c++) v_a[c] = (L.v[c] + R.v[c]) / 2;
+  switch (kind) {
+    case ORC_VOL_KG:
+    case ORC_VOL_PIROZZOLI: {
+      F[0] = rho_a * vn_a;
+      for (int c = 0; c < 3; c++) F[1 + c] = rho_a * vn_a * v_a[c] + p_a * n[c];
+      if (kind == ORC_VOL_KG) {
+        real e_a = (L.E / L.rho + R.E / R.rho) / 2;
+        F[4] = rho_a * vn_a * e_a + p_a * vn_a;
+      } else {
+        real H_a = ((L.E + L.p) / L.rho + (R.E + R.p) / R.rho) / 2;
+        F[4] = rho_a * vn_a * H_a;
+      }
+      break;
+    }
+    case ORC_VOL_DUCROS: {
+      F[0] = rho_a * vn_a;
+      for (int c = 0; c < 3; c++) F[1 + c] = (uL[1 + c] + uR[1 + c]) / 2 * vn_a + p_a * n[c];
+      F[4] = ((L.E + L.p) + (R.E + R.p)) / 2 * vn_a;
+      break;
+    }
+    default: { /* Morinishi */
+      real m_a = (L.rho * vnL + R.rho * vnR) / 2;
+      real v2L = L.v[0] * L.v[0] + L.v[1] * L.v[1] + L.v[2] * L.v[2];
+      real v2R = R.v[0] * R.v[0] + R.v[1] * R.v[1] + R.v[2] * R.v[2];
+      F[0] = m_a;
+      for (int c = 0; c < 3; c++) F[1 + c] = m_a * v_a[c] + p_a * n[c];
+      F[4] = gamma / (gamma - 1) * (L.p * vnL + R.p * vnR) / 2 +
+             m_a * (v_a[0] * v_a[0] + v_a[1] * v_a[1] + v_a[2] * v_a[2]) -
+             (L.rho * vnL * v2L + R.rho * vnR * v2R) / 4;
+      break;
+    }
+  }
+}
+
 /* Roe's wave decomposition along the unit normal n: sum_k f(lambda_k) alpha_k r_k with
- * f = |.| (absval=1) or the identity (absval=0, then the sum equals F(uR)-F(uL)). */
-static void roe_waves(const real uL[5], const real uR[5], const real n[3], real gamma, int absval, real W[5]) {
+ * f = |.| (absval=1) or the identity (absval=0, then the sum equals F(uR)-F(uL)).  The wave
+ * strengths come from the jumps (Roe and Pike's evaluation, no Roe matrix is formed).  zv
+ * scales the velocity jump inside the strengths: 1 for Roe's flux, the Mach-number factor of
+ * the low-dissipation variant below. */
+static void roe_waves_z(const real uL[5], const real uR[5], const real n[3], real gamma, int absval, real zv,
+                        real W[5]) {
   prim_t L = prim(uL, gamma), R = prim(uR, gamma);
   real sL = RSQRT(L.rho), sR = RSQRT(R.rho);
   real HL = (L.E + L.p) / L.rho, HR = (R.E + R.p) / R.rho;
@@ -591,7 +647,7 @@ static void roe_waves(const real uL[5], const real uR[5], const real n[3], real 
   real c2 = (gamma - 1) * (H - q2 / 2), c = RSQRT(c2);
   real vn = v[0] * n[0] + v[1] * n[1] + v[2] * n[2];
   real drho = R.rho - L.rho, dp = R.p - L.p, dv[3];
-  for (int k = 0; k < 3; k++) dv[k] = R.v[k] - L.v[k];
+  for (int k = 0; k < 3; k++) dv[k] = zv * (R.v[k] - L.v[k]);
   real dvn = dv[0] * n[0] + dv[1] * n[1] + dv[2] * n[2];
   real a1 = (dp - rho * c * dvn) / (2 * c2);
   real a2 = drho - dp / c2;
@@ -605,6 +661,60 @@ static void roe_waves(const real uL[5], const real uR[5], const real n[3], real 
   for (int k = 0; k < 3; k++)
     W[1 + k] = l1 * a1 * (v[k] - c * n[k]) + l2 * (a2 * v[k] + rho * dvt[k]) + l3 * a3 * (v[k] + c * n[k]);
   W[4] = l1 * a1 * (H - vn * c) + l2 * (a2 * q2 / 2 + rho * vdvt) + l3 * a3 * (H + vn * c);
+}
+
+static void roe_waves(const real uL[5], const real uR[5], const real n[3], real gamma, int absval, real W[5]) {
+  roe_waves_z(uL, uR, n, gamma, absval, 1, W);
+}
+
+/* entropy variables w = dS/du of S = -rho s/(gamma-1), s = ln p - gamma ln rho */
+static void entropy_vars(const real u[5], real gamma, real w[5]) {
+  prim_t q = prim(u, gamma);
+  real sp = RLOG(q.p) - gamma * RLOG(q.rho);
+  real b = q.rho / (2 * q.p);
+  real v2 = q.v[0] * q.v[0] + q.v[1] * q.v[1] + q.v[2] * q.v[2];
+  w[0] = (gamma - sp) / (gamma - 1) - b * v2;
+  for (int c = 0; c < 3; c++) w[1 + c] = 2 * b * q.v[c];
+  w[4] = -2 * b;
+}
+
+/* Matrix dissipation for the entropy-stable flux along the unit normal n:
+ * D = R |Lambda| T R^T (w_R - w_L), with the eigenvectors R of the Euler flux Jacobian along n
+ * and Barth's scaling T = diag(rho/(2 gamma), rho (gamma-1)/gamma, p, p, rho/(2 gamma)), for
+ * which R T R^T = du/dw.  Reading: R, Lambda, T are taken at the averaged state
+ * rho^ = (rho)^ln, v^ = {v}, p^ = {rho}/(2{beta}) (Chandrashekar's averages), with
+ * c^2 = gamma p^/rho^ and H^ = c^2/(gamma-1) + |v^|^2/2.  The two shear waves are summed with the
+ * tangential projector I - n n^T, so no tangent basis is needed.  D . (w_R - w_L) >= 0. */
+static void matrix_dissipation(const real uL[5], const real uR[5], const real n[3], real gamma, real D[5]) {
+  prim_t L = prim(uL, gamma), R = prim(uR, gamma);
+  real bL = L.rho / (2 * L.p), bR = R.rho / (2 * R.p);
+  real rho = logmean(L.rho, R.rho);
+  real p = (L.rho + R.rho) / (2 * (bL + bR));
+  real v[3], q2 = 0;
+  for (int c = 0; c < 3; c++) { v[c] = (L.v[c] + R.v[c]) / 2; q2 += v[c] * v[c]; }
+  real c2 = gamma * p / rho, c = RSQRT(c2);
+  real H = c2 / (gamma - 1) + q2 / 2;
+  real vn = v[0] * n[0] + v[1] * n[1] + v[2] * n[2];
+  real wL[5], wR[5], dw[5];
+  entropy_vars(uL, gamma, wL);
+  entropy_vars(uR, gamma, wR);
+  for (int k = 0; k < 5; k++) dw[k] = wR[k] - wL[k];
+  real r1[5] = {1, v[0] - c * n[0], v[1] - c * n[1], v[2] - c * n[2], H - c * vn};
+  real r2[5] = {1, v[0], v[1], v[2], q2 / 2};
+  real r5[5] = {1, v[0] + c * n[0], v[1] + c * n[1], v[2] + c * n[2], H + c * vn};
+  real s1 = 0, s2 = 0, s5 = 0;
+  for (int k = 0; k < 5; k++) { s1 += r1[k] * dw[k]; s2 += r2[k] * dw[k]; s5 += r5[k] * dw[k]; }
+  s1 *= RFABS(vn - c) * rho / (2 * gamma);
+  s2 *= RFABS(vn) * rho * (gamma - 1) / gamma;
+  s5 *= RFABS(vn + c) * rho / (2 * gamma);
+  real q[3], qn = 0;
+  for (int k = 0; k < 3; k++) { q[k] = dw[1 + k] + v[k] * dw[4]; qn += q[k] * n[k]; }
+  real qt[3], vqt = 0;
+  for (int k = 0; k < 3; k++) { qt[k] = q[k] - qn * n[k]; vqt += v[k] * qt[k]; }
+  real sh = p * RFABS(vn);
+  for (int k = 0; k < 5; k++) D[k] = s1 * r1[k] + s2 * r2[k] + s5 * r5[k];
+  for (int k = 0; k < 3; k++) D[1 + k] += sh * qt[k];
+  D[4] += sh * vqt;
 }
 
 /* numerical flux through a face with scaled normal S (S = |S| n_hat) */
@@ -649,6 +759,31 @@ static void riemann(int kind, const real uL[5], const real uR[5], const real S[3
       for (int v = 0; v < 5; v++) F[v] -= a * lam * (uR[v] - uL[v]) / 2;
       break;
     }
+    case ORC_SURF_ES_MATRIX: {
+      /* entropy-stable: Chandrashekar's flux minus the matrix dissipation above */
+      real D[5];
+      two_point_ec(uL, uR, S, gamma, F);
+      matrix_dissipation(uL, uR, n, gamma, D);
+      for (int v = 0; v < 5; v++) F[v] -= a * D[v] / 2;
+      break;
+    }
+    case ORC_SURF_LOW_DISS_ROE: {
+      /* low-dissipation Roe: Roe's flux with the velocity jump in the wave strengths scaled by
+       * z = min(1, max(M_L, M_R)), M = |v|/c the local Mach numbers (reading: the
+       * low-Mach-number correction of Oswald et al., which leaves density and pressure jumps
+       * and supersonic faces as in Roe's flux) */
+      prim_t L = prim(uL, gamma), R = prim(uR, gamma);
+      real ML = RSQRT((L.v[0] * L.v[0] + L.v[1] * L.v[1] + L.v[2] * L.v[2]) * L.rho / (gamma * L.p));
+      real MR = RSQRT((R.v[0] * R.v[0] + R.v[1] * R.v[1] + R.v[2] * R.v[2]) * R.rho / (gamma * R.p));
+      real z = ML > MR ? ML : MR;
+      if (z > 1) z = 1;
+      real W[5];
+      euler_flux(uL, n, gamma, FL);
+      euler_flux(uR, n, gamma, FR);
+      roe_waves_z(uL, uR, n, gamma, 1, z, W);
+      for (int v = 0; v < 5; v++) F[v] = a * ((FL[v] + FR[v]) / 2 - W[v] / 2);
+      break;
+    }
     default: two_point_central(uL, uR, S, gamma, F); break;
   }
 }
@@ -656,7 +791,8 @@ static void riemann(int kind, const real uL[5], const real uR[5], const real S[3
 static void volume_flux(const orc_solver* s, const real uL[5], const real uR[5], const real n[3], real F[5]) {
   if (s->vol == ORC_VOL_EC) two_point_ec(uL, uR, n, s->gamma, F);
   else if (s->vol == ORC_VOL_IR) two_point_ir(uL, uR, n, s->gamma, F);
-  else two_point_central(uL, uR, n, s->gamma, F);
+  else if (s->vol == ORC_VOL_CENTRAL) two_point_central(uL, uR, n, s->gamma, F);
+  else two_point_kep(s->vol, uL, uR, n, s->gamma, F);
 }
 
 /* viscous flux (eq. viscousfluxes) from the state and the gradients of (v1,v2,v3,T);
@@ -1220,8 +1356,19 @@ int orc_two_point_central(const double* UL, const double* UR, const double* n, d
   to_dbl(f, F, 5);
   return 0;
 }
+int orc_two_point(int vol_kind, const double* UL, const double* UR, const double* n, double gamma, double* F) {
+  if (vol_kind < 0 || vol_kind > ORC_VOL_MORINISHI) return -1;
+  real a[5], b[5], nn[3], f[5];
+  to_real(UL, a, 5); to_real(UR, b, 5); to_real(n, nn, 3);
+  if (vol_kind == ORC_VOL_EC) two_point_ec(a, b, nn, gamma, f);
+  else if (vol_kind == ORC_VOL_IR) two_point_ir(a, b, nn, gamma, f);
+  else if (vol_kind == ORC_VOL_CENTRAL) two_point_central(a, b, nn, gamma, f);
+  else two_point_kep(vol_kind, a, b, nn, gamma, f);
+  to_dbl(f, F, 5);
+  return 0;
+}
 int orc_riemann(int kind, const double* UL, const double* UR, const double* S, double gamma, double* F) {
-  if (kind < 0 || kind > ORC_SURF_IR) return -1;
+  if (kind < 0 || kind > ORC_SURF_LOW_DISS_ROE) return -1;
   real a[5], b[5], nn[3], f[5];
   to_real(UL, a, 5); to_real(UR, b, 5); to_real(S, nn, 3);
   riemann(kind, a, b, nn, gamma, f);
@@ -1236,15 +1383,10 @@ int orc_roe_waves(const double* UL, const double* UR, const double* nhat, double
   return 0;
 }
 int orc_entropy_vars(const double* U, double gamma, double* wout) {
-  real u[5];
+  real u[5], w[5];
   to_real(U, u, 5);
-  prim_t w = prim(u, gamma);
-  real sp = RLOG(w.p) - (real)gamma * RLOG(w.rho);
-  real b = w.rho / (2 * w.p);
-  real v2 = w.v[0] * w.v[0] + w.v[1] * w.v[1] + w.v[2] * w.v[2];
-  wout[0] = (double)(((real)gamma - sp) / ((real)gamma - 1) - b * v2);
-  for (int c = 0; c < 3; c++) wout[1 + c] = (double)(2 * b * w.v[c]);
-  wout[4] = (double)(-2 * b);
+  entropy_vars(u, gamma, w);
+  to_dbl(w, wout, 5);
   return 0;
 }
 double orc_entropy(const double* U, double gamma) {

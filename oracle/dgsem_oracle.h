@@ -29,8 +29,10 @@ extern "C" {
 
 #define ORC_NMAX 8
 
-enum { ORC_VOL_EC = 0, ORC_VOL_CENTRAL = 1, ORC_VOL_IR = 2 };
-enum { ORC_SURF_ROE = 0, ORC_SURF_LLF = 1, ORC_SURF_EC = 2, ORC_SURF_CENTRAL = 3, ORC_SURF_ES = 4, ORC_SURF_IR = 5 };
+enum { ORC_VOL_EC = 0, ORC_VOL_CENTRAL = 1, ORC_VOL_IR = 2, ORC_VOL_KG = 3, ORC_VOL_PIROZZOLI = 4,
+       ORC_VOL_DUCROS = 5, ORC_VOL_MORINISHI = 6 };
+enum { ORC_SURF_ROE = 0, ORC_SURF_LLF = 1, ORC_SURF_EC = 2, ORC_SURF_CENTRAL = 3, ORC_SURF_ES = 4, ORC_SURF_IR = 5,
+       ORC_SURF_ES_MATRIX = 6, ORC_SURF_LOW_DISS_ROE = 7 };
 enum { ORC_IC_UNIFORM = 0, ORC_IC_TGV = 1, ORC_IC_VORTEX = 2, ORC_IC_DENSITY_WAVE = 3 };
 
 typedef struct orc_solver orc_solver;
@@ -71,6 +73,7 @@ int orc_euler_flux(const double* U, const double* n, double gamma, double* F);
 int orc_two_point_ec(const double* UL, const double* UR, const double* n, double gamma, double* F);
 int orc_two_point_ir(const double* UL, const double* UR, const double* n, double gamma, double* F);
 int orc_two_point_central(const double* UL, const double* UR, const double* n, double gamma, double* F);
+int orc_two_point(int vol_kind, const double* UL, const double* UR, const double* n, double gamma, double* F);
 int orc_riemann(int kind, const double* UL, const double* UR, const double* S, double gamma, double* F);
 int orc_roe_waves(const double* UL, const double* UR, const double* nhat, double gamma, int absval,
                   double* W);

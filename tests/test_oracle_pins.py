@@ -171,6 +171,186 @@ def test_entropy_stable_surface_flux(orc):
         assert dw @ (F - orc.two_point_ec(uL, uR, n)) < 0
 
 
+KEP = ["kg", "pirozzoli", "ducros", "morinishi"]
+
+
+def test_kep_fluxes_consistency_symmetry(orc):
+    """The kinetic-energy-preserving split forms (Kennedy-Gruber, Pirozzoli, Ducros, Morinishi;
+    section "Energy/Entropy stable versions", list of split forms): consistency with F_e,
+    symmetry, linearity in n, and every one of them a different flux off the diagonal."""
+    UL, UR, nv = _pairs(100, seed=21)
+    differ = np.zeros((len(KEP), len(KEP)))
+    for uL, uR, n in zip(UL, UR, nv):
+        F = {k: orc.two_point(k, uL, uR, n) for k in KEP}
+        for k in KEP:
+            np.testing.assert_allclose(orc.two_point(k, uL, uL, n), orc.euler_flux(uL, n),
+                                       rtol=1e-13, atol=1e-13)
+            np.testing.assert_allclose(F[k], orc.two_point(k, uR, uL, n), rtol=1e-14, atol=1e-14)
+            np.testing.assert_allclose(orc.two_point(k, uL, uR, 2.5 * n), 2.5 * F[k], rtol=1e-14,
+                                       atol=1e-14)
+        for a in range(len(KEP)):
+            for b in range(len(KEP)):
+                differ[a, b] = max(differ[a, b], np.abs(F[KEP[a]] - F[KEP[b]]).max() / np.abs(F[KEP[a]]).max())
+    assert np.all(differ + np.eye(len(KEP)) > 1e-4), differ
+
+
+def _pair_split(D, a, b, ax):
+    """2 sum_m D_im {a}{b} along axis ax, written with the product rule (row sums of D vanish):
+    (D(ab) + a Db + b Da) / 2."""
+    d = lambda f: np.moveaxis(np.tensordot(D, f, axes=([1], [ax])), 0, ax)
+    return 0.5 * (d(a * b) + a * d(b) + b * d(a))
+
+
+def _triple_split(D, a, b, c, ax):
+    """2 sum_m D_im {a}{b}{c} along axis ax:
+    (D(abc) + a D(bc) + b D(ac) + c D(ab) + ab Dc + ac Db + bc Da) / 4."""
+    d = lambda f: np.moveaxis(np.tensordot(D, f, axes=([1], [ax])), 0, ax)
+    return 0.25 * (d(a * b * c) + a * d(b * c) + b * d(a * c) + c * d(a * b) + a * b * d(c) +
+                   a * c * d(b) + b * c * d(a))
+
+
+@pytest.mark.parametrize("kind", KEP)
+def test_kep_split_forms_equal_product_rule(orc, kind):
+    """On affine elements each product-of-means flux turns the split-form volume term into the
+    classical quadratic / cubic split form of the derivative (Kennedy and Gruber's product-rule
+    expansions), e.g. 2 sum_m D_im {a}{b} = (D(ab) + a Db + b Da)/2.  The residual of the oracle
+    with central faces must equal those expansions plus the central surface lift, evaluated here
+    with numpy from D alone."""
+    N, ex = 3, 2
+    n = N + 1
+    s = orc.OracleSolver(ex, N=N, vol=kind, surf="central", Ma=0.5, hi=(2 * math.pi,) * 3)
+    s.set_ic("tgv")
+    # perturb so that density, velocity and pressure all vary
+    U0 = s.state()
+    drho, dv, dp = synth.primitive_perturbation(s.nodes, seed=4, amp=(0.1, 0.1, 0.1))
+    Un = U0.reshape(s.E, 5, n ** 3).transpose(0, 2, 1).reshape(-1, 5)
+    rho = Un[:, 0] * (1 + drho)
+    v = Un[:, 1:4] / Un[:, :1] + dv.T
+    pr = 0.4 * (Un[:, 4] - 0.5 * (Un[:, 1:4] ** 2).sum(1) / Un[:, 0]) * (1 + dp)
+    U = to_conservative(rho, v, pr).reshape(s.E, n ** 3, 5).transpose(0, 2, 1).reshape(-1)
+    s.set_state(U)
+    Ue = U.reshape(ex, ex, ex, 5, n, n, n)  # [c][b][a][v][k][j][i]
+    _, w, D = orc.gll(N)
+    h = 2 * math.pi / ex
+    ja = (h / 2) ** 2
+    Jc = (h / 2) ** 3
+    r = Ue[:, :, :, 0]
+    vel = [Ue[:, :, :, 1 + c] / r for c in range(3)]
+    E = Ue[:, :, :, 4]
+    p = 0.4 * (E - 0.5 * r * sum(x * x for x in vel))
+    e, H = E / r, (E + p) / r
+    div = np.zeros_like(Ue)
+    for d, ax in enumerate([5, 4, 3]):  # x: node axis i, y: j, z: k (axes of a per-variable field)
+        un = vel[d]
+        if kind in ("kg", "pirozzoli", "ducros"):
+            div[:, :, :, 0] += _pair_split(D, r, un, ax)
+        else:
+            div[:, :, :, 0] += (np.moveaxis(np.tensordot(D, r * un, axes=([1], [ax])), 0, ax))
+        for c in range(3):
+            if kind in ("kg", "pirozzoli"):
+                div[:, :, :, 1 + c] += _triple_split(D, r, un, vel[c], ax)
+            elif kind == "ducros":
+                div[:, :, :, 1 + c] += _pair_split(D, r * vel[c], un, ax)
+            else:
+                div[:, :, :, 1 + c] += _pair_split(D, r * un, vel[c], ax)
+        div[:, :, :, 1 + d] += np.moveaxis(np.tensordot(D, p, axes=([1], [ax])), 0, ax)
+        if kind == "kg":
+            div[:, :, :, 4] += _triple_split(D, r, un, e, ax) + _pair_split(D, p, un, ax)
+        elif kind == "pirozzoli":
+            div[:, :, :, 4] += _triple_split(D, r, un, H, ax)
+        elif kind == "ducros":
+            div[:, :, :, 4] += _pair_split(D, E + p, un, ax)
+        else:
+            dd = lambda f: np.moveaxis(np.tensordot(D, f, axes=([1], [ax])), 0, ax)
+            div[:, :, :, 4] += (GAMMA / 0.4 * dd(p * un) +
+                                sum(_triple_split(D, r * un, vel[c], vel[c], ax) for c in range(3)) -
+                                0.5 * dd(r * un * sum(x * x for x in vel)))
+    div *= ja
+    F = np.zeros((3,) + Ue.shape)
+    for d in range(3):
+        nvec = np.zeros(3)
+        nvec[d] = ja
+        Uf = np.moveaxis(Ue, 3, -1).reshape(-1, 5)
+        F[d] = np.moveaxis(np.array([orc.euler_flux(u, nvec) for u in Uf]).reshape(
+            ex, ex, ex, n, n, n, 5), -1, 3)
+    surf = np.zeros_like(div)
+    for d, (eax, nax) in enumerate([(2, 6), (1, 5), (0, 4)]):
+        Fd = F[d]
+        plus = np.take(Fd, [N], axis=nax)
+        minus = np.take(Fd, [0], axis=nax)
+        nb_minus = np.roll(minus, -1, axis=eax)
+        nb_plus = np.roll(plus, 1, axis=eax)
+        sl_p = [slice(None)] * 7
+        sl_p[nax] = slice(N, N + 1)
+        sl_m = [slice(None)] * 7
+        sl_m[nax] = slice(0, 1)
+        surf[tuple(sl_p)] += (0.5 * (plus + nb_minus) - plus) / w[N]
+        surf[tuple(sl_m)] -= (0.5 * (nb_plus + minus) - minus) / w[0]
+    R_split = -(div + surf) / Jc
+    R = s.residual().reshape(R_split.shape)
+    err = rel_per_var(R.reshape(-1), R_split.reshape(-1), s.E)
+    assert np.all(err < 1e-12), err
+
+
+def test_matrix_dissipation_surface_flux(orc):
+    """Entropy-stable flux with matrix dissipation (box of convective fluxes in section
+    "Spatial discretisation"): consistency; every face produces entropy of the right sign,
+    (w_R - w_L).(F* - F_EC) <= 0; and for nearby states its dissipation agrees with Roe's to
+    third order in the jump (both are |A| (U_R - U_L)/2 at the mean state, because R T R^T is
+    the entropy Jacobian du/dw), so the mismatch falls 8x per halving of the jump while the
+    dissipation itself falls 2x."""
+    UL, UR, nv = _pairs(200, seed=31)
+    for uL, uR, n in zip(UL, UR, nv):
+        F = orc.riemann("es_matrix", uL, uR, n)
+        np.testing.assert_allclose(orc.riemann("es_matrix", uL, uL, n), orc.euler_flux(uL, n),
+                                   rtol=1e-13, atol=1e-13)
+        dw = orc.entropy_vars(uR) - orc.entropy_vars(uL)
+        assert dw @ (F - orc.two_point_ec(uL, uR, n)) < 0
+    rng = synth.rng(5)
+    for t in range(20):
+        ub = to_conservative(rng.uniform(0.7, 1.3), rng.normal(0, 0.4, 3), rng.uniform(0.8, 1.5))
+        du = rng.normal(0, 1, 5) * np.array([0.1, 0.1, 0.1, 0.1, 0.3])
+        n = synth.unit_vectors(1, 40 + t)[0] * 1.7
+        mis, dis = [], []
+        for eps in (1e-2, 5e-3, 2.5e-3):
+            uL, uR = ub - eps * du, ub + eps * du
+            Desm = orc.riemann("es_matrix", uL, uR, n) - orc.two_point_ec(uL, uR, n)
+            Droe = orc.riemann("roe", uL, uR, n) - orc.two_point_central(uL, uR, n)
+            mis.append(np.abs(Desm - Droe).max())
+            dis.append(np.abs(Droe).max())
+        assert 1.8 < dis[0] / dis[1] < 2.2 and 1.8 < dis[1] / dis[2] < 2.2
+        assert mis[0] / mis[1] > 6.5 and mis[1] / mis[2] > 6.5, (mis, dis)
+
+
+def test_low_dissipation_roe(orc):
+    """Low-dissipation Roe flux: consistency; Roe's flux wherever one side is supersonic and for
+    jumps of density and pressure alone; for a jump of velocity alone its dissipation is Roe's
+    times z = max(M_L, M_R) < 1 (M the local Mach numbers)."""
+    UL, UR, nv = _pairs(50, seed=41)
+    for uL, uR, n in zip(UL, UR, nv):
+        np.testing.assert_allclose(orc.riemann("ld_roe", uL, uL, n), orc.euler_flux(uL, n),
+                                   rtol=1e-13, atol=1e-13)
+    n = np.array([0.6, -0.3, 1.1])
+    mach = lambda r, v, p: np.linalg.norm(v) / math.sqrt(GAMMA * p / r)
+    # supersonic left state
+    uL = to_conservative(1.0, [1.3, 0.2, 0.1], 1.0)
+    uR = to_conservative(1.1, [0.3, -0.1, 0.2], 1.3)
+    np.testing.assert_allclose(orc.riemann("ld_roe", uL, uR, n), orc.riemann("roe", uL, uR, n),
+                               rtol=1e-14, atol=1e-14)
+    # density and pressure jump, common velocity, low Mach
+    uL = to_conservative(1.0, [0.1, 0.05, 0.0], 1.0)
+    uR = to_conservative(1.2, [0.1, 0.05, 0.0], 1.4)
+    np.testing.assert_allclose(orc.riemann("ld_roe", uL, uR, n), orc.riemann("roe", uL, uR, n),
+                               rtol=1e-14, atol=1e-14)
+    # velocity jump alone
+    vL, vR = np.array([0.1, 0.05, 0.0]), np.array([0.05, 0.12, -0.04])
+    uL, uR = to_conservative(1.0, vL, 1.0), to_conservative(1.0, vR, 1.0)
+    z = max(mach(1.0, vL, 1.0), mach(1.0, vR, 1.0))
+    cen = orc.two_point_central(uL, uR, n)
+    np.testing.assert_allclose(orc.riemann("ld_roe", uL, uR, n) - cen,
+                               z * (orc.riemann("roe", uL, uR, n) - cen), rtol=1e-12, atol=1e-15)
+
+
 def test_central_flux(orc):
     UL, UR, nv = _pairs(50)
     for uL, uR, n in zip(UL, UR, nv):
@@ -214,7 +394,7 @@ def test_llf_flux(orc):
                                    rtol=1e-13, atol=1e-13)
 
 
-@pytest.mark.parametrize("kind", ["roe", "llf", "ec", "central"])
+@pytest.mark.parametrize("kind", ["roe", "llf", "ec", "central", "es", "ir", "es_matrix", "ld_roe"])
 def test_rotational_invariance(orc, kind):
     """Numerical fluxes commute with rotations: F*(T uL, T uR; T S) = T F*(uL, uR; S)."""
     UL, UR, nv = _pairs(40, seed=5)
@@ -324,6 +504,19 @@ def test_freestream_preservation(orc, surf, Re):
     assert np.abs(R).max() < 1e-13 * scale
 
 
+@pytest.mark.parametrize("vol", ["ir", "kg", "pirozzoli", "ducros", "morinishi"])
+def test_freestream_preservation_split_forms(orc, vol):
+    """Every consistent, symmetric two-point flux with the averaged metric keeps a uniform state
+    steady on the curvilinear mesh."""
+    s = orc.OracleSolver(3, N=4, deform=True, Ma=0.3, vol=vol, surf="roe")
+    p = 1 / (GAMMA * 0.09)
+    s.set_ic("uniform", [1.0, 0.3, -0.2, 0.1, p])
+    R = s.residual()
+    Ja, J = s.metrics()
+    scale = (p / 0.4 + p) * np.abs(Ja).max() / J.min() * 4 * 5 / 2
+    assert np.abs(R).max() < 1e-13 * scale
+
+
 def _conservation_sums(orc, s, R, N):
     _, w, _ = orc.gll(N)
     _, J = s.metrics()
@@ -335,7 +528,8 @@ def _conservation_sums(orc, s, R, N):
 
 
 @pytest.mark.parametrize("surf,vol", [("roe", "ec"), ("llf", "ec"), ("ec", "ec"), ("es", "ec"), ("ir", "ir"),
-                                      ("roe", "ir")])
+                                      ("roe", "ir"), ("es_matrix", "ec"), ("ld_roe", "kg"),
+                                      ("roe", "pirozzoli"), ("llf", "ducros"), ("central", "morinishi")])
 @pytest.mark.parametrize("Re", [0.0, 400.0])
 def test_conservation_of_totals(orc, surf, vol, Re):
     """Periodic box, single-valued face fluxes: sum over nodes of w J dU/dt vanishes for every
@@ -385,6 +579,10 @@ def test_entropy_conservation_and_dissipation(orc):
     s4.set_state(U)
     ent_es = s4.entropy_production(s4.residual())
     assert ent_es < -1e-6 * scale
+    s5 = orc.OracleSolver(3, N=N, deform=True, Ma=0.4, surf="es_matrix")
+    s5.set_state(U)
+    ent_esm = s5.entropy_production(s5.residual())
+    assert ent_esm < -1e-6 * scale
 
 
 def test_split_central_equals_strong_form_affine(orc):
