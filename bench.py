@@ -44,7 +44,7 @@ KERNEL_SOURCES = ["paper_2206_09733_amd/csrc/kernels.hip", "paper_2206_09733_amd
                   "paper_2206_09733_amd/csrc/dg_internal.h"]
 
 
-def profiled_traffic(kernel="dg::stage_kernel<4, double, true, false>", shape="32768 x 128"):
+def profiled_traffic(kernel="dg::stage_kernel<4, double, true, 0>", shape="32768 x 128"):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary,
     or None when the kernel sources changed since the counters were taken."""
     import hashlib

@@ -54,14 +54,22 @@ extern "C" {
 
 /* ------------------------------------------------------------------ options */
 enum { DG_DEFORM_NONE = 0, DG_DEFORM_SINSIN = 1 };
-/* volume two-point flux (split forms of section "Energy/Entropy stable versions"):
+/* volume two-point flux (the list of split forms of section "Energy/Entropy stable versions"):
  * Chandrashekar's entropy-conserving, kinetic-energy-preserving flux; the central average;
- * Ismail and Roe's entropy-conserving flux */
-enum { DG_VOL_EC = 0, DG_VOL_CENTRAL = 1, DG_VOL_IR = 2 };
-/* surface numerical flux: Roe, local Lax-Friedrichs, Chandrashekar's EC flux, central,
- * entropy stable (Chandrashekar's flux minus local Lax-Friedrichs dissipation), Ismail-Roe.
- * The Ismail-Roe and entropy-stable options are evaluated in FP64 only. */
-enum { DG_SURF_ROE = 0, DG_SURF_LLF = 1, DG_SURF_EC = 2, DG_SURF_CENTRAL = 3, DG_SURF_ES = 4, DG_SURF_IR = 5 };
+ * Ismail and Roe's entropy-conserving flux; the kinetic-energy-preserving forms of
+ * Kennedy-Gruber, Pirozzoli, Ducros and Morinishi (products of arithmetic means of the two
+ * states, e.g. Kennedy-Gruber's mass flux {rho}{v.n}) */
+enum { DG_VOL_EC = 0, DG_VOL_CENTRAL = 1, DG_VOL_IR = 2, DG_VOL_KENNEDY_GRUBER = 3, DG_VOL_PIROZZOLI = 4,
+       DG_VOL_DUCROS = 5, DG_VOL_MORINISHI = 6 };
+/* surface numerical flux (box of convective fluxes in section "Spatial discretisation"): Roe
+ * (evaluated with Roe and Pike's wave strengths), local Lax-Friedrichs (Rusanov),
+ * Chandrashekar's EC flux, central, entropy stable (Chandrashekar's flux minus local
+ * Lax-Friedrichs dissipation), Ismail-Roe, entropy stable with matrix dissipation
+ * (Chandrashekar's flux minus R|Lambda|T R^T times the jump of the entropy variables),
+ * low-dissipation Roe (the velocity jump scaled by the larger local Mach number, at most 1).
+ * Only DG_VOL_EC / DG_VOL_CENTRAL and the first four surface fluxes have an FP32-bulk form. */
+enum { DG_SURF_ROE = 0, DG_SURF_LLF = 1, DG_SURF_EC = 2, DG_SURF_CENTRAL = 3, DG_SURF_ES = 4, DG_SURF_IR = 5,
+       DG_SURF_ES_MATRIX = 6, DG_SURF_LOW_DISS_ROE = 7 };
 /* precision: all-FP64, or FP32 flux/derivative arithmetic with FP64 metrics, RK state and
  * reductions */
 enum { DG_FP64 = 0, DG_FP32_BULK = 1 };
@@ -128,7 +136,8 @@ int dg_mesh_info(const dg_mesh* m, long long* n_elements, long long* n_nodes, in
  * gamma <= 1, Pr <= 0, unknown flux or precision codes; DG_EUNSUPPORTED for an order without
  * a compiled kernel (uniform orders 1..7 are compiled), for a mixed-order mesh with Re > 0
  * (mixed-order meshes are evaluated for the Euler equations, in FP64 or FP32-bulk), and for
- * DG_FP32_BULK with DG_VOL_IR, DG_SURF_ES or DG_SURF_IR. */
+ * DG_FP32_BULK with a volume flux other than DG_VOL_EC / DG_VOL_CENTRAL or a surface flux other
+ * than DG_SURF_ROE / LLF / EC / CENTRAL. */
 int dg_solver_create(const dg_mesh* m, const dg_physics* p, dg_solver** out);
 /* Bytes of device memory the solver needs (host-only; used for admission control). */
 int dg_solver_required_bytes(const dg_solver* s, size_t* bytes);

@@ -361,12 +361,14 @@ int dg_solver_create(const dg_mesh* m, const dg_physics* p, dg_solver** out) {
   if (!(p->gamma > 1.0)) return fail(DG_EINVAL, "gamma must exceed 1");
   if (p->Re > 0 && !(p->Pr > 0)) return fail(DG_EINVAL, "Pr must be positive");
   if (!(p->Ma > 0)) return fail(DG_EINVAL, "Ma must be positive");
-  if (p->vol_flux < DG_VOL_EC || p->vol_flux > DG_VOL_IR) return fail(DG_EINVAL, "unknown volume flux");
-  if (p->surf_flux < DG_SURF_ROE || p->surf_flux > DG_SURF_IR) return fail(DG_EINVAL, "unknown surface flux");
+  if (p->vol_flux < DG_VOL_EC || p->vol_flux > DG_VOL_MORINISHI) return fail(DG_EINVAL, "unknown volume flux");
+  if (p->surf_flux < DG_SURF_ROE || p->surf_flux > DG_SURF_LOW_DISS_ROE)
+    return fail(DG_EINVAL, "unknown surface flux");
   if (p->precision != DG_FP64 && p->precision != DG_FP32_BULK) return fail(DG_EINVAL, "unknown precision");
   if (m->N < 1 || m->N > dg::kMaxOrder) return fail(DG_EUNSUPPORTED, "no kernel for this order");
-  if (p->precision == DG_FP32_BULK && (p->vol_flux == DG_VOL_IR || p->surf_flux >= DG_SURF_ES))
-    return fail(DG_EUNSUPPORTED, "the Ismail-Roe and entropy-stable fluxes are evaluated in FP64");
+  if (p->precision == DG_FP32_BULK && (p->vol_flux >= DG_VOL_IR || p->surf_flux >= DG_SURF_ES))
+    return fail(DG_EUNSUPPORTED, "FP32-bulk covers the EC and central volume fluxes and the Roe, LLF, EC and "
+                                 "central surface fluxes; the others are evaluated in FP64");
   if (m->mixed && p->Re > 0)
     return fail(DG_EUNSUPPORTED, "mixed-order meshes are evaluated for the Euler equations (Re <= 0)");
   dg_solver* s = new dg_solver;
@@ -811,7 +813,8 @@ int dg_profile_end(dg_solver* s, dg_profile* out) {
 struct dg_batch {
   struct Group {  // uniform-order members of one order, precision and surface-flux family, viscous or not
     int N;
-    bool fp32, visc, xs;
+    bool fp32, visc;
+    int fx;  // flux family
     std::vector<int> idx;
   };
   struct Graph {
@@ -861,7 +864,7 @@ hipError_t batch_stage(dg_batch* b, const double* dts, int k, hipStream_t st) {
       e = dg::launch_gradient_batch(B, g.N, g.fp32, st);
       if (e != hipSuccess) return e;
     }
-    e = dg::launch_stage_batch(B, g.N, g.fp32, g.visc, g.xs, kRk[b->scheme].A[k], kRk[b->scheme].B[k],
+    e = dg::launch_stage_batch(B, g.N, g.fp32, g.visc, g.fx, kRk[b->scheme].A[k], kRk[b->scheme].B[k],
                                dg::kModeRK, st);
     if (e != hipSuccess) return e;
   }
@@ -930,13 +933,14 @@ int dg_batch_create(dg_solver* const* solvers, int n, void* hip_stream, dg_batch
       b->mixed.push_back(i);
       continue;
     }
-    const bool fp32 = s->v.fp32 != 0, visc = s->v.viscous != 0, xs = s->v.surf >= DG_SURF_ES;
+    const bool fp32 = s->v.fp32 != 0, visc = s->v.viscous != 0;
+    const int fx = dg::flux_family(s->v.vol, s->v.surf);
     dg_batch::Group* g = nullptr;
     for (auto& x : b->groups)
-      if (x.N == s->v.N && x.fp32 == fp32 && x.visc == visc && x.xs == xs && (int)x.idx.size() < dg::kMaxBatch)
+      if (x.N == s->v.N && x.fp32 == fp32 && x.visc == visc && x.fx == fx && (int)x.idx.size() < dg::kMaxBatch)
         g = &x;
     if (!g) {
-      b->groups.push_back({s->v.N, fp32, visc, xs, {}});
+      b->groups.push_back({s->v.N, fp32, visc, fx, {}});
       g = &b->groups.back();
     }
     g->idx.push_back(i);

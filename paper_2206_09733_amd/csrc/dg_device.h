@@ -196,19 +196,63 @@ __device__ __forceinline__ void flux_ir(const Prim<T>& a, const Prim<T>& b, T n1
   F[4] = F[0] * H;
 }
 
-// volume two-point flux: 0 Chandrashekar, 1 central, 2 Ismail-Roe
+// Kinetic-energy-preserving split forms as two-point fluxes along n, from products of
+// arithmetic means {.}: vn = v.n, e = p/((gamma-1) rho) + |v|^2/2 = ce/beta + h, H = e + 1/(2 beta).
+//   3 Kennedy-Gruber  {rho}{vn},  {rho}{vn}{v} + {p}n,  {rho}{vn}{e} + {p}{vn}
+//   4 Pirozzoli       {rho}{vn},  {rho}{vn}{v} + {p}n,  {rho}{vn}{H}
+//   5 Ducros          {rho}{vn},  {rho v}{vn} + {p}n,   {rho H}{vn}
+//   6 Morinishi       m = {rho vn},  m{v} + {p}n,  gamma/(gamma-1){p vn} + m |{v}|^2 - {rho vn h}
 template <typename T>
+__device__ __forceinline__ void flux_kep(int kind, const Prim<T>& a, const Prim<T>& b, T n1, T n2,
+                                         T n3, T ce, T F[5]) {
+  const T iba = rcp(a.beta), ibb = rcp(b.beta);
+  const T pa = (T)0.5 * a.rho * iba, pb = (T)0.5 * b.rho * ibb;
+  const T vna = a.v1 * n1 + a.v2 * n2 + a.v3 * n3, vnb = b.v1 * n1 + b.v2 * n2 + b.v3 * n3;
+  const T u = (T)0.5 * (a.v1 + b.v1), v = (T)0.5 * (a.v2 + b.v2), w = (T)0.5 * (a.v3 + b.v3);
+  const T pm = (T)0.5 * (pa + pb), vn = (T)0.5 * (vna + vnb), rm = (T)0.5 * (a.rho + b.rho);
+  const T ea = ce * iba + a.h, eb = ce * ibb + b.h;
+  if (kind == 6) {
+    const T m = (T)0.5 * (a.rho * vna + b.rho * vnb);
+    F[0] = m;
+    F[1] = m * u + pm * n1;
+    F[2] = m * v + pm * n2;
+    F[3] = m * w + pm * n3;
+    F[4] = ((T)1 + (T)2 * ce) * (T)0.5 * (pa * vna + pb * vnb) + m * (u * u + v * v + w * w) -
+           (T)0.5 * (a.rho * vna * a.h + b.rho * vnb * b.h);
+    return;
+  }
+  F[0] = rm * vn;
+  if (kind == 5) {
+    F[1] = (T)0.5 * (a.rho * a.v1 + b.rho * b.v1) * vn + pm * n1;
+    F[2] = (T)0.5 * (a.rho * a.v2 + b.rho * b.v2) * vn + pm * n2;
+    F[3] = (T)0.5 * (a.rho * a.v3 + b.rho * b.v3) * vn + pm * n3;
+    F[4] = (T)0.5 * (a.rho * (ea + (T)0.5 * iba) + b.rho * (eb + (T)0.5 * ibb)) * vn;
+    return;
+  }
+  F[1] = F[0] * u + pm * n1;
+  F[2] = F[0] * v + pm * n2;
+  F[3] = F[0] * w + pm * n3;
+  if (kind == 3) F[4] = F[0] * (T)0.5 * (ea + eb) + pm * vn;
+  else F[4] = F[0] * (T)0.5 * (ea + eb + (T)0.5 * (iba + ibb));
+}
+
+// volume two-point flux: 0 Chandrashekar, 1 central, 2 Ismail-Roe; with KEP the
+// kinetic-energy-preserving forms 3..6 above instead
+template <typename T, bool KEP = false>
 __device__ __forceinline__ void vol_flux(int kind, const Prim<T>& a, const Prim<T>& b, T n1, T n2,
                                          T n3, T ce, T gm1, T F[5]) {
-  if (kind == 0) flux_ec(a, b, n1, n2, n3, ce, F);
+  if constexpr (KEP) flux_kep(kind, a, b, n1, n2, n3, ce, F);
+  else if (kind == 0) flux_ec(a, b, n1, n2, n3, ce, F);
   else if (kind == 2) flux_ir(a, b, n1, n2, n3, gm1, F);
   else flux_central(a, b, n1, n2, n3, gm1, F);
 }
 
 // Numerical flux through a face with scaled normal S (|S| times the unit normal), between
 // the conservative states uL (the side S points away from) and uR: Roe (0), local
-// Lax-Friedrichs (1), Chandrashekar's EC flux (2), central (3).
-template <typename T>
+// Lax-Friedrichs (1), Chandrashekar's EC flux (2), central (3).  LD turns Roe's flux into its
+// low-dissipation variant: the velocity jump in the wave strengths is scaled by
+// z = min(1, max(M_L, M_R)), the larger local Mach number.
+template <typename T, bool LD = false>
 __device__ __forceinline__ void face_flux_std(int kind, const double uL[5], const double uR[5],
                                           const double S[3], double gamma, T F[5]) {
   const T gm1 = (T)(gamma - 1.0);
@@ -280,7 +324,17 @@ __device__ __forceinline__ void face_flux_std(int kind, const double uL[5], cons
   const T ic2 = rc * rc;
   const T vn = u1 * n1 + u2 * n2 + u3 * n3;
   const T dr = rR - rL, dp = pR - pL;
-  const T dv1 = vR[0] - vL[0], dv2 = vR[1] - vL[1], dv3 = vR[2] - vL[2];
+  T dv1 = vR[0] - vL[0], dv2 = vR[1] - vL[1], dv3 = vR[2] - vL[2];
+  if constexpr (LD) {
+    const T g = (T)gamma;
+    const T mL = (vL[0] * vL[0] + vL[1] * vL[1] + vL[2] * vL[2]) * rL / (g * pL);
+    const T mR = (vR[0] * vR[0] + vR[1] * vR[1] + vR[2] * vR[2]) * rR / (g * pR);
+    const T m2 = mL > mR ? mL : mR;
+    const T z = m2 < (T)1 ? sqrt(m2) : (T)1;
+    dv1 *= z;
+    dv2 *= z;
+    dv3 *= z;
+  }
   const T dvn = dv1 * n1 + dv2 * n2 + dv3 * n3;
   const T a1 = (T)0.5 * (dp - rho * c * dvn) * ic2;
   const T a2 = dr - dp * ic2;
@@ -299,22 +353,76 @@ __device__ __forceinline__ void face_flux_std(int kind, const double uL[5], cons
   for (int k = 0; k < 5; k++) F[k] = (T)0.5 * area * (Fs[k] - W[k]);
 }
 
+// Matrix dissipation R |Lambda| T R^T (w_b - w_a) along the unit normal n: eigenvectors R of the
+// flux Jacobian, Barth's scaling T = diag(rho/(2 gamma), rho (gamma-1)/gamma, p, p, rho/(2 gamma))
+// (so that R T R^T = du/dw), all at the averaged state rho^ = (rho)^ln, v^ = {v},
+// p^ = {rho}/(2{beta}), c^2 = gamma p^/rho^, H^ = c^2/(gamma-1) + |v^|^2/2.  The jump of the
+// entropy variables w = ((gamma - s)/(gamma-1) - 2 beta h, 2 beta v, -2 beta) comes from the
+// stored logarithms: s = -(gamma-1) ln rho - ln 2 - ln beta.  The two shear waves are summed
+// with the tangential projector I - n n^T.
+template <typename T>
+__device__ __forceinline__ void matrix_dissipation(const Prim<T>& a, const Prim<T>& b, T n1, T n2, T n3,
+                                                   T gm1, T D[5]) {
+  const T g = gm1 + (T)1;
+  const T rho = logmean_logs(a.rho, b.rho, a.lrho, b.lrho);
+  const T p = (a.rho + b.rho) * rcp((T)2 * (a.beta + b.beta));
+  const T u = (T)0.5 * (a.v1 + b.v1), v = (T)0.5 * (a.v2 + b.v2), w = (T)0.5 * (a.v3 + b.v3);
+  const T q2 = u * u + v * v + w * w;
+  const T igm1 = rcp(gm1);
+  const T c2 = g * p * rcp(rho);
+  const T c = c2 * rsq(c2);
+  const T H = c2 * igm1 + (T)0.5 * q2;
+  const T vn = u * n1 + v * n2 + w * n3;
+  const T dw0 = (b.lrho - a.lrho) + (b.lbeta - a.lbeta) * igm1 - (T)2 * (b.beta * b.h - a.beta * a.h);
+  const T dw1 = (T)2 * (b.beta * b.v1 - a.beta * a.v1);
+  const T dw2 = (T)2 * (b.beta * b.v2 - a.beta * a.v2);
+  const T dw3 = (T)2 * (b.beta * b.v3 - a.beta * a.v3);
+  const T dw4 = (T)-2 * (b.beta - a.beta);
+  const T base = dw0 + u * dw1 + v * dw2 + w * dw3;  // r . dw without the c and energy parts
+  const T cn = c * (n1 * dw1 + n2 * dw2 + n3 * dw3);
+  const T s1 = (base - cn + (H - c * vn) * dw4) * fabs(vn - c) * rho * rcp((T)2 * g);
+  const T s2 = (base + (T)0.5 * q2 * dw4) * fabs(vn) * rho * gm1 * rcp(g);
+  const T s5 = (base + cn + (H + c * vn) * dw4) * fabs(vn + c) * rho * rcp((T)2 * g);
+  const T q1 = dw1 + u * dw4, qq2 = dw2 + v * dw4, q3 = dw3 + w * dw4;
+  const T qn = q1 * n1 + qq2 * n2 + q3 * n3;
+  const T t1 = q1 - qn * n1, t2 = qq2 - qn * n2, t3 = q3 - qn * n3;
+  const T sh = p * fabs(vn);
+  const T s15 = s1 + s5;
+  D[0] = s15 + s2;
+  D[1] = s15 * u + c * n1 * (s5 - s1) + s2 * u + sh * t1;
+  D[2] = s15 * v + c * n2 * (s5 - s1) + s2 * v + sh * t2;
+  D[3] = s15 * w + c * n3 * (s5 - s1) + s2 * w + sh * t3;
+  D[4] = s15 * H + c * vn * (s5 - s1) + s2 * (T)0.5 * q2 + sh * (u * t1 + v * t2 + w * t3);
+}
+
 // The extended surface fluxes: entropy stable (4: Chandrashekar's flux minus local
-// Lax-Friedrichs dissipation) and Ismail-Roe (5).
+// Lax-Friedrichs dissipation), Ismail-Roe (5), entropy stable with matrix dissipation (6:
+// Chandrashekar's flux minus the dissipation above), low-dissipation Roe (7).
 template <typename T>
 __device__ __forceinline__ void face_flux_xs(int kind, const double uL[5], const double uR[5],
                                              const double S[3], double gamma, T F[5]) {
+  if (kind == 7) {
+    face_flux_std<T, true>(0, uL, uR, S, gamma, F);
+    return;
+  }
   const T gm1 = (T)(gamma - 1.0);
   const Prim<T> a = make_prim<T>(uL, gamma), b = make_prim<T>(uR, gamma);
   if (kind == 5) {
     flux_ir(a, b, (T)S[0], (T)S[1], (T)S[2], gm1, F);
     return;
   }
-  flux_ec(a, b, (T)S[0], (T)S[1], (T)S[2], (T)(0.5 / (gamma - 1.0)), F);
   const T s1 = (T)S[0], s2 = (T)S[1], s3 = (T)S[2];
   const T a2s = s1 * s1 + s2 * s2 + s3 * s3;
   const T ia = rsq(a2s);
   const T area = a2s * ia;
+  flux_ec(a, b, s1, s2, s3, (T)(0.5 / (gamma - 1.0)), F);
+  if (kind == 6) {
+    T D[5];
+    matrix_dissipation(a, b, s1 * ia, s2 * ia, s3 * ia, gm1, D);
+#pragma unroll
+    for (int c = 0; c < 5; c++) F[c] -= (T)0.5 * area * D[c];
+    return;
+  }
   const T g = (T)gamma;
   T lam = (T)0;
   const double* u2[2] = {uL, uR};

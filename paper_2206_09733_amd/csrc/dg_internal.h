@@ -13,6 +13,12 @@ constexpr int kMaxOrder = 7;            // largest polynomial order with a compi
 constexpr int kDiagSlots = 16;          // doubles per diagnostics partial
 constexpr int kTabStride = (kMaxOrder + 1) * (kMaxOrder + 1);
 
+// Flux family of the stage kernels, compiled apart so that each kernel holds only the flux code
+// its solver uses and the common family (0) keeps its registers: bit 0 = a kinetic-energy-
+// preserving volume flux (codes >= 3), bit 1 = an extended surface flux (codes >= 4: entropy
+// stable, Ismail-Roe, matrix dissipation, low-dissipation Roe).  Families 1..3 run in FP64 only.
+__host__ __device__ constexpr int flux_family(int vol, int surf) { return (vol >= 3 ? 1 : 0) | (surf >= 4 ? 2 : 0); }
+
 // Device tables of one order N, packed in one array (all doubles):
 //   [0, n)            Lobatto nodes xi
 //   [n, 2n)           quadrature weights w
@@ -90,8 +96,8 @@ hipError_t launch_diag_final(const View& v, hipStream_t st);  // partials -> dia
 // batched Navier-Stokes gradient pass and stage of members of order N (all viscous, or all
 // inviscid for the stage), FP32-bulk or FP64
 hipError_t launch_gradient_batch(const BatchArgs& B, int N, bool fp32, hipStream_t st);
-hipError_t launch_stage_batch(const BatchArgs& B, int N, bool fp32, bool visc, bool xs, double rkA, double rkB,
-                              int mode, hipStream_t st);  // xs: members use the extended surface fluxes
+hipError_t launch_stage_batch(const BatchArgs& B, int N, bool fp32, bool visc, int fx, double rkA, double rkB,
+                              int mode, hipStream_t st);  // fx: the members' flux family
 
 // mixed-order meshes (kernels_mixed.hip).  The stage runs one launch per bucket of elements
 // (bucket b: 64 b < nodes <= 64 (b + 1)); bit b of `tiles` gives bucket b two nodes per lane

@@ -239,7 +239,7 @@ __global__ void __launch_bounds__(nthreads_for(N)) grad_batch_kernel(BatchArgs B
 // occupancy target of the stage kernel: waves per SIMD the register allocation must allow
 __host__ __device__ constexpr int stage_waves_per_eu(int N) { return N <= 5 ? 3 : 2; }
 
-template <int N, typename T, bool VISC, bool XS>
+template <int N, typename T, bool VISC, int FX>
 __device__ __forceinline__ void stage_body(const View& v, const int e, const int cur, const double dt,
                                            const double rkA, const double rkB, const int mode) {
   constexpr int n = N + 1, nn = n * n * n, nf = n * n, NT = nthreads_for(N);
@@ -303,9 +303,13 @@ __device__ __forceinline__ void stage_body(const View& v, const int e, const int
       sVd[1][t] = u[2] * ir;
       sVd[2][t] = u[3] * ir;
     }
+    // the extended surface fluxes need the registers during the face phase: their families load
+    // the metric terms after it
+    if constexpr ((FX & 2) == 0) {
 #pragma unroll
-    for (int c = 0; c < 9; c++) ja[c] = v.Ja[base * 9 + c * nn + t];
-    ij = v.invJ[base + t];
+      for (int c = 0; c < 9; c++) ja[c] = v.Ja[base * 9 + c * nn + t];
+      ij = v.invJ[base + t];
+    }
     if (VISC) {
       T g[4];
       gvars(u, v.gamma, Tref, g);
@@ -341,7 +345,7 @@ __device__ __forceinline__ void stage_body(const View& v, const int e, const int
       face_flux_dev<T>(v.surf, uL, uR, S, v.gamma, Rf, F, F0d);
       sF0d[f][q] = F0d;
     } else {
-      face_flux<T, XS>(v.surf, uL, uR, S, v.gamma, F);
+      face_flux<T, (FX & 2) != 0>(v.surf, uL, uR, S, v.gamma, F);
     }
     if (VISC) {
       const T* fo = FvfAll + ((long)e * 6 + f) * 4 * nf;
@@ -356,6 +360,13 @@ __device__ __forceinline__ void stage_body(const View& v, const int e, const int
     }
 #pragma unroll
     for (int c = 0; c < 5; c++) sF[f][c][q] = F[c];
+  }
+  if constexpr ((FX & 2) != 0) {
+    if (act) {
+#pragma unroll
+      for (int c = 0; c < 9; c++) ja[c] = v.Ja[base * 9 + c * nn + t];
+      ij = v.invJ[base + t];
+    }
   }
   __syncthreads();
 
@@ -429,7 +440,7 @@ __device__ __forceinline__ void stage_body(const View& v, const int e, const int
         }
         sM[s] = F0d;
       } else {
-        vol_flux<T>(v.vol, A, B, m1, m2, m3, ce, gm1, F);
+        vol_flux<T, (FX & 1) != 0>(v.vol, A, B, m1, m2, m3, ce, gm1, F);
       }
 #pragma unroll
       for (int c = 0; c < 5; c++) sPair[c][s] = F[c];
@@ -483,21 +494,21 @@ __device__ __forceinline__ void stage_body(const View& v, const int e, const int
   }
 }
 
-// XS: the extended surface fluxes (entropy stable, Ismail-Roe), compiled as separate kernels
-template <int N, typename T, bool VISC, bool XS>
+// FX: the flux family (see flux_family); each family is compiled as separate kernels
+template <int N, typename T, bool VISC, int FX>
 __global__ void __launch_bounds__(nthreads_for(N))
     __attribute__((amdgpu_waves_per_eu(stage_waves_per_eu(N))))
     stage_kernel(View v, int cur, double dt, double rkA, double rkB, int mode) {
-  stage_body<N, T, VISC, XS>(v, block_element(v.E), cur, dt, rkA, rkB, mode);
+  stage_body<N, T, VISC, FX>(v, block_element(v.E), cur, dt, rkA, rkB, mode);
 }
 
-template <int N, typename T, bool VISC, bool XS>
+template <int N, typename T, bool VISC, int FX>
 __global__ void __launch_bounds__(nthreads_for(N))
     __attribute__((amdgpu_waves_per_eu(stage_waves_per_eu(N))))
     stage_batch_kernel(BatchArgs B, double rkA, double rkB, int mode) {
   int m, e;
   batch_member(B, m, e);
-  stage_body<N, T, VISC, XS>(*B.view[m], e, B.cur[m], B.dt[m], rkA, rkB, mode);
+  stage_body<N, T, VISC, FX>(*B.view[m], e, B.cur[m], B.dt[m], rkA, rkB, mode);
 }
 
 // ------------------------------------------------------------------ diagnostics (FP64)
@@ -647,24 +658,29 @@ static hipError_t gradient_n(const View& v, int cur, hipStream_t st) {
   return v.fp32 ? gradient_nt<N, float>(v, cur, st) : gradient_nt<N, double>(v, cur, st);
 }
 
-template <int N, typename T, bool XS>
+template <int N, typename T, int FX>
 static hipError_t stage_ntx(const View& v, int cur, double dt, double a, double b, int mode,
                             hipStream_t st) {
   const dim3 grid(v.E), block(nthreads_for(N));
   if (v.viscous)
-    hipLaunchKernelGGL((stage_kernel<N, T, true, XS>), grid, block, 0, st, v, cur, dt, a, b, mode);
+    hipLaunchKernelGGL((stage_kernel<N, T, true, FX>), grid, block, 0, st, v, cur, dt, a, b, mode);
   else
-    hipLaunchKernelGGL((stage_kernel<N, T, false, XS>), grid, block, 0, st, v, cur, dt, a, b, mode);
+    hipLaunchKernelGGL((stage_kernel<N, T, false, FX>), grid, block, 0, st, v, cur, dt, a, b, mode);
   return hipGetLastError();
 }
 
 template <int N, typename T>
 static hipError_t stage_nt(const View& v, int cur, double dt, double a, double b, int mode,
                            hipStream_t st) {
-  if constexpr (sizeof(T) == 8) {  // the extended surface fluxes run in FP64 only
-    if (v.surf >= 4) return stage_ntx<N, T, true>(v, cur, dt, a, b, mode, st);
+  if constexpr (sizeof(T) == 8) {  // the extended fluxes run in FP64 only
+    switch (flux_family(v.vol, v.surf)) {
+      case 1: return stage_ntx<N, T, 1>(v, cur, dt, a, b, mode, st);
+      case 2: return stage_ntx<N, T, 2>(v, cur, dt, a, b, mode, st);
+      case 3: return stage_ntx<N, T, 3>(v, cur, dt, a, b, mode, st);
+      default: break;
+    }
   }
-  return stage_ntx<N, T, false>(v, cur, dt, a, b, mode, st);
+  return stage_ntx<N, T, 0>(v, cur, dt, a, b, mode, st);
 }
 
 template <int N>
@@ -717,23 +733,27 @@ static hipError_t gradient_batch_n(const BatchArgs& B, bool fp32, hipStream_t st
   return fp32 ? gradient_batch_nt<N, float>(B, st) : gradient_batch_nt<N, double>(B, st);
 }
 
-template <int N, typename T, bool XS>
+template <int N, typename T, int FX>
 static hipError_t stage_batch_nt(const BatchArgs& B, bool visc, double a, double b, int mode,
                                  hipStream_t st) {
   const dim3 grid(B.start[B.n]), block(nthreads_for(N));
   if (visc)
-    hipLaunchKernelGGL((stage_batch_kernel<N, T, true, XS>), grid, block, 0, st, B, a, b, mode);
+    hipLaunchKernelGGL((stage_batch_kernel<N, T, true, FX>), grid, block, 0, st, B, a, b, mode);
   else
-    hipLaunchKernelGGL((stage_batch_kernel<N, T, false, XS>), grid, block, 0, st, B, a, b, mode);
+    hipLaunchKernelGGL((stage_batch_kernel<N, T, false, FX>), grid, block, 0, st, B, a, b, mode);
   return hipGetLastError();
 }
 
 template <int N>
-static hipError_t stage_batch_n(const BatchArgs& B, bool fp32, bool visc, bool xs, double a, double b,
+static hipError_t stage_batch_n(const BatchArgs& B, bool fp32, bool visc, int fx, double a, double b,
                                 int mode, hipStream_t st) {
-  if (fp32) return stage_batch_nt<N, float, false>(B, visc, a, b, mode, st);
-  return xs ? stage_batch_nt<N, double, true>(B, visc, a, b, mode, st)
-            : stage_batch_nt<N, double, false>(B, visc, a, b, mode, st);
+  if (fp32) return stage_batch_nt<N, float, 0>(B, visc, a, b, mode, st);
+  switch (fx) {
+    case 1: return stage_batch_nt<N, double, 1>(B, visc, a, b, mode, st);
+    case 2: return stage_batch_nt<N, double, 2>(B, visc, a, b, mode, st);
+    case 3: return stage_batch_nt<N, double, 3>(B, visc, a, b, mode, st);
+    default: return stage_batch_nt<N, double, 0>(B, visc, a, b, mode, st);
+  }
 }
 
 #define DG_DISPATCH_N(NV, FN, ...)                    \
@@ -753,11 +773,11 @@ hipError_t launch_gradient_batch(const BatchArgs& B, int N, bool fp32, hipStream
   DG_DISPATCH_N(N, gradient_batch_n, B, fp32, st)
 }
 
-hipError_t launch_stage_batch(const BatchArgs& B, int N, bool fp32, bool visc, bool xs, double rkA, double rkB,
+hipError_t launch_stage_batch(const BatchArgs& B, int N, bool fp32, bool visc, int fx, double rkA, double rkB,
                               int mode, hipStream_t st) {
   if (B.n < 1 || B.n > kMaxBatch) return hipErrorInvalidValue;
-  if (fp32 && xs) return hipErrorInvalidValue;
-  DG_DISPATCH_N(N, stage_batch_n, B, fp32, visc, xs, rkA, rkB, mode, st)
+  if (fx < 0 || fx > 3 || (fp32 && fx != 0)) return hipErrorInvalidValue;
+  DG_DISPATCH_N(N, stage_batch_n, B, fp32, visc, fx, rkA, rkB, mode, st)
 }
 
 hipError_t launch_diag_final(const View& v, hipStream_t st) {

@@ -336,8 +336,9 @@ __global__ void __launch_bounds__(64) mixed_face_kernel(View v, int cur) {
 // ------------------------------------------------------------------ stage: volume and update
 // Elements are launched by bucket: bucket b holds the elements of 64 b < nn <= 64 (b + 1) nodes,
 // a contiguous range of the work list (sorted by node count).  A lane holds NPL nodes (1 or 2,
-// the autotuner's choice per bucket), so the workgroup has mix_lanes(NNMAX, NPL) lanes.
-template <int NNMAX, int NPL, typename T>
+// the autotuner's choice per bucket), so the workgroup has mix_lanes(NNMAX, NPL) lanes.  KEP
+// selects the kinetic-energy-preserving volume fluxes (compiled apart, FP64 only).
+template <int NNMAX, int NPL, typename T, bool KEP>
 __global__ void __launch_bounds__(mix_lanes(NNMAX, NPL))
     mixed_stage_kernel(View v, int wbeg, int cur, double dt, double rkA, double rkB, int mode) {
   constexpr int BS = mix_lanes(NNMAX, NPL);
@@ -423,7 +424,7 @@ __global__ void __launch_bounds__(mix_lanes(NNMAX, NPL))
           flux_central_dev(A, B, (T)md[0], (T)md[1], (T)md[2], va, vb, md, Rf, F, F0d);
         }
       } else {
-        vol_flux<T>(v.vol, A, B, (T)md[0], (T)md[1], (T)md[2], ce, gm1, F);
+        vol_flux<T, KEP>(v.vol, A, B, (T)md[0], (T)md[1], (T)md[2], ce, gm1, F);
       }
       const double Dm = sD[d][id * n + m];
 #pragma unroll
@@ -589,11 +590,14 @@ static hipError_t stage_bucket(const View& v, int b, int cur, double dt, double 
                                hipStream_t st) {
   const dim3 grid(v.mix_cnt[b]), block(mix_lanes(NNMAX, NPL));
   if (v.fp32)
-    hipLaunchKernelGGL((mixed_stage_kernel<NNMAX, NPL, float>), grid, block, 0, st, v, v.mix_beg[b], cur, dt,
-                       rkA, rkB, mode);
+    hipLaunchKernelGGL((mixed_stage_kernel<NNMAX, NPL, float, false>), grid, block, 0, st, v, v.mix_beg[b], cur,
+                       dt, rkA, rkB, mode);
+  else if (flux_family(v.vol, v.surf) & 1)
+    hipLaunchKernelGGL((mixed_stage_kernel<NNMAX, NPL, double, true>), grid, block, 0, st, v, v.mix_beg[b], cur,
+                       dt, rkA, rkB, mode);
   else
-    hipLaunchKernelGGL((mixed_stage_kernel<NNMAX, NPL, double>), grid, block, 0, st, v, v.mix_beg[b], cur, dt,
-                       rkA, rkB, mode);
+    hipLaunchKernelGGL((mixed_stage_kernel<NNMAX, NPL, double, false>), grid, block, 0, st, v, v.mix_beg[b], cur,
+                       dt, rkA, rkB, mode);
   return hipGetLastError();
 }
 

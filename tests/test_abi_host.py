@@ -75,9 +75,20 @@ def test_solver_argument_errors_and_sizes(dg):
     for bad in (dict(gamma=1.0), dict(vol="ec", surf="roe", precision="fp64", Ma=-1.0)):
         p = dg.physics(**bad)
         assert L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)) == dg.DG_EINVAL
-    p = dg.physics()
-    p.surf_flux = 9
-    assert L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)) == dg.DG_EINVAL
+    for vol, surf in ((7, 0), (0, 8), (-1, 0), (0, -1)):
+        p = dg.physics()
+        p.vol_flux, p.surf_flux = vol, surf
+        assert L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)) == dg.DG_EINVAL
+    # FP32-bulk covers the EC / central volume fluxes and the first four surface fluxes only
+    for vol, surf in (("ir", "roe"), ("kg", "roe"), ("morinishi", "llf"), ("ec", "es"),
+                      ("ec", "es_matrix"), ("central", "ld_roe")):
+        p = dg.physics(vol=vol, surf=surf, precision="fp32_bulk")
+        assert L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)) == dg.DG_EUNSUPPORTED
+    for vol in dg.VOL:
+        for surf in dg.SURF:
+            p = dg.physics(vol=vol, surf=surf)
+            assert L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)) == dg.DG_OK, (vol, surf)
+            L.dg_solver_destroy(s)
     p = dg.physics(Re=100.0)
     assert L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)) == dg.DG_OK
     nb = ctypes.c_size_t()

@@ -120,13 +120,14 @@ def test_mixed_initial_condition_parity(dg, orc):
 
 
 # ------------------------------------------------------------------ residual
-@pytest.mark.parametrize("surf", ["roe", "llf", "ec", "central", "es", "ir"])
-def test_mixed_residual_parity(dg, orc, surf):
+@pytest.mark.parametrize("surf,vol", [("roe", "ec"), ("llf", "ec"), ("ec", "ec"), ("central", "ec"), ("es", "ec"),
+                                      ("ir", "ir"), ("es_matrix", "ec"), ("ld_roe", "ec"), ("roe", "kg"),
+                                      ("llf", "pirozzoli"), ("ec", "ducros"), ("es_matrix", "morinishi")])
+def test_mixed_residual_parity(dg, orc, surf, vol):
     """3x3x3 elements with orders drawn from {1..6} per direction on a deformed mesh: most faces
     are p-nonconforming in one or both tangential directions."""
-    c = mixed_cfg(3, 3, 3, seed=10, nlo=1, nhi=6, deform=True, amp=0.3, surf=surf,
-                  vol="ir" if surf == "ir" else "ec")
-    log(f"mixed residual {surf}")
+    c = mixed_cfg(3, 3, 3, seed=10, nlo=1, nhi=6, deform=True, amp=0.3, surf=surf, vol=vol)
+    log(f"mixed residual {surf} {vol}")
     o = orc.OracleSolver(**c)
     o.set_ic("vortex", VORTEX)
     U = perturbed(o, seed=20)
@@ -136,7 +137,7 @@ def test_mixed_residual_parity(dg, orc, surf):
     R64, R80 = o.residual(), o80.residual()
     g = gpu_solver(dg, c)
     g.set_state(U)
-    assert_parity(f"mixed {surf}", g.residual(), R64, R80, layout(o))
+    assert_parity(f"mixed {surf} {vol}", g.residual(), R64, R80, layout(o))
 
 
 def test_mixed_residual_central_volume_and_edge_meshes(dg, orc):

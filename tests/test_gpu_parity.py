@@ -160,6 +160,42 @@ def test_residual_ismail_roe_and_entropy_stable(dg, orc, N, vol, surf, Re):
     assert_parity(f"N={N} {vol}/{surf} Re={Re}", g.residual(), R64, R80, 12, (N + 1) ** 3)
 
 
+@pytest.mark.parametrize("N", [2, 3, 4, 5, 7])
+@pytest.mark.parametrize("vol,surf,Re", [("kg", "roe", 0.0), ("pirozzoli", "llf", 100.0), ("ducros", "ec", 0.0),
+                                         ("morinishi", "central", 100.0), ("ec", "es_matrix", 0.0),
+                                         ("ir", "es_matrix", 100.0), ("ec", "ld_roe", 100.0),
+                                         ("pirozzoli", "es_matrix", 0.0), ("morinishi", "ld_roe", 100.0),
+                                         ("kg", "ld_roe", 0.0)])
+def test_residual_kep_and_dissipative_surface_fluxes(dg, orc, N, vol, surf, Re):
+    """Kinetic-energy-preserving volume fluxes (Kennedy-Gruber, Pirozzoli, Ducros, Morinishi),
+    the matrix-dissipation entropy-stable flux and the low-dissipation Roe flux, alone and
+    combined (FP64)."""
+    c = cfg(ex=3, ey=2, ez=2, N=N, deform=True, vol=vol, surf=surf, Re=Re, Ma=0.3)
+    log(f"residual N={N} vol={vol} surf={surf} Re={Re}")
+    U = perturbed_state(orc, c, seed=500 + N)
+    R64, R80 = oracle_pair(orc, c, U)
+    g = dg.Solver(**c)
+    g.set_state(U)
+    assert_parity(f"N={N} {vol}/{surf} Re={Re}", g.residual(), R64, R80, 12, (N + 1) ** 3)
+
+
+def test_gpu_entropy_matrix_dissipation(dg, orc):
+    """On the GPU path, entropy decays with the matrix-dissipation faces (EC volume flux), and
+    the rate lies within rounding of the oracle's."""
+    c = cfg(ex=3, N=3, deform=True, Ma=0.4, surf="es_matrix")
+    U = perturbed_state(orc, c, seed=13, amp=(0.05, 0.1, 0.05))
+    o = orc.OracleSolver(**c)
+    o.set_state(U)
+    g = dg.Solver(**c)
+    g.set_state(U)
+    R = g.residual()
+    ref = abs(o.entropy_production(np.abs(R)))
+    eg, eo = o.entropy_production(R), o.entropy_production(o.residual())
+    log(f"entropy production es_matrix GPU {eg:.6e} oracle {eo:.6e} scale {ref:.3e}")
+    assert eg < -1e-6 * ref
+    assert abs(eg - eo) < 1e-11 * ref
+
+
 def test_gpu_entropy_ismail_roe_and_stable(dg, orc):
     """On the GPU path: the Ismail-Roe split form with Ismail-Roe faces conserves entropy; with
     the entropy-stable faces entropy decays; FP32-bulk refuses these fluxes."""
