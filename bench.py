@@ -40,8 +40,8 @@ def algorithmic_bytes_gradient(nodes, N, fp32):
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TRAFFIC_PROFILE = os.path.join(HERE, "profiles", "stage_kernel_c2_ns_fp64.md")
-KERNEL_SOURCES = ["paper_2206_09733_amd/csrc/kernels.hip", "paper_2206_09733_amd/csrc/dg_device.h",
-                  "paper_2206_09733_amd/csrc/dg_internal.h"]
+KERNEL_SOURCES = ["paper_2206_09733_amd/csrc/kernels.hip", "paper_2206_09733_amd/csrc/stage_kernel.h",
+                  "paper_2206_09733_amd/csrc/dg_device.h", "paper_2206_09733_amd/csrc/dg_internal.h"]
 
 
 def profiled_traffic(kernel="dg::stage_kernel<4, double, true, 0>", shape="32768 x 128"):

@@ -98,6 +98,11 @@ hipError_t launch_diag_final(const View& v, hipStream_t st);  // partials -> dia
 hipError_t launch_gradient_batch(const BatchArgs& B, int N, bool fp32, hipStream_t st);
 hipError_t launch_stage_batch(const BatchArgs& B, int N, bool fp32, bool visc, int fx, double rkA, double rkB,
                               int mode, hipStream_t st);  // fx: the members' flux family
+// the extended flux families 1..3 (FP64), in kernels_ext.hip; called by the two launchers above
+hipError_t launch_stage_ext(const View& v, int fx, int cur, double dt, double rkA, double rkB, int mode,
+                            hipStream_t st);
+hipError_t launch_stage_batch_ext(const BatchArgs& B, int N, bool visc, int fx, double rkA, double rkB, int mode,
+                                  hipStream_t st);
 
 // mixed-order meshes (kernels_mixed.hip).  The stage runs one launch per bucket of elements
 // (bucket b: 64 b < nodes <= 64 (b + 1)); bit b of `tiles` gives bucket b two nodes per lane
