@@ -164,6 +164,17 @@ int dg_residual(dg_solver* s, double* host_R, size_t n);
  * Default: Williamson's RK3, A = (0, -5/9, -153/128), B = (1/3, 15/16, 8/15); see
  * dg_solver_set_scheme.  Only enqueues work on the solver's stream. */
 int dg_rk_step(dg_solver* s, double dt, int nsteps);
+/* Advance nsteps steps of the solver's scheme with a step size chosen before every step from the
+ * state it starts from, on the device: dt = cfl h_min/((N+1)^2 lambda_max), lambda_max the largest
+ * |v| + c over the nodes, and with viscosity at most 0.25 h_min^2 Pr rho_min/((N+1)^4 gamma mu) --
+ * dg_suggest_dt's formula, so a step equals dg_rk_step with dg_suggest_dt(cfl) of the same state,
+ * bit for bit.  A max/min reduction and a one-block kernel compute dt, and the stage kernels read
+ * it from device memory, so the steps need no host round trip (and replay one captured graph).
+ * The paper does not state how the step is chosen; the formula is this library's reading.
+ * t_advanced (may be NULL) receives the simulated time advanced.  Synchronises the stream once,
+ * at the end.  DG_EINVAL for cfl <= 0 or nsteps < 0; DG_ENONFINITE if a step started from a
+ * non-finite or non-physical state (that step and the later ones then had size 0). */
+int dg_rk_step_adaptive(dg_solver* s, double cfl, int nsteps, double* t_advanced);
 /* Time schemes: Williamson's three-stage RK3 (the default), or Carpenter and Kennedy's five-stage
  * fourth-order low-storage scheme (the paper's RK4 option; their published coefficients). */
 enum { DG_RK3_WILLIAMSON = 0, DG_RK4_CARPENTER_KENNEDY = 1 };

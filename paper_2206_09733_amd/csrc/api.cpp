@@ -72,6 +72,10 @@ struct dg_solver {
   hipGraphExec_t graph[2] = {nullptr, nullptr};
   double graph_dt[2] = {0.0, 0.0};
   double last_dt = 0.0;
+  // adaptive-step graphs: agraph[p] advances one step from buffer p with the step size chosen on
+  // the device for CFL number agraph_cfl[p]
+  hipGraphExec_t agraph[2] = {nullptr, nullptr};
+  double agraph_cfl[2] = {0.0, 0.0};
   dg::View* dev_view = nullptr;      // device copy of v (inside the caller's buffer)
   int scheme = DG_RK3_WILLIAMSON;    // time scheme of dg_rk_step
 };
@@ -79,7 +83,7 @@ struct dg_solver {
 namespace {
 
 struct Plan {
-  size_t tab, nbr, X, Ja, J, invJ, U0, U1, dU, R, Fvf, part, diag, elem, work, mtab, Fs, self, total;
+  size_t tab, nbr, X, Ja, J, invJ, U0, U1, dU, R, Fvf, part, diag, adapt, elem, work, mtab, Fs, self, total;
   size_t tab_n, mtab_n;
 };
 
@@ -122,6 +126,7 @@ Plan make_plan(const dg_solver* s) {
   p.Fvf = s->phys.Re > 0 ? take(sizeof(double) * E * 6 * 4 * nf) : 0;
   p.part = take(sizeof(double) * E * dg::kDiagSlots);
   p.diag = take(sizeof(double) * dg::kDiagSlots);
+  p.adapt = take(sizeof(double) * 8);
   p.elem = mixed ? take(sizeof(int4) * E) : 0;
   p.work = mixed ? take(sizeof(int) * E) : 0;
   p.mtab = mixed ? take(sizeof(double) * p.mtab_n) : 0;
@@ -216,11 +221,13 @@ const RkScheme kRk[2] = {
 
 // (waits for the solver's stream first, so that no replay of a graph is still in flight)
 void drop_graphs(dg_solver* s) {
-  if (!s->graph[0] && !s->graph[1]) return;
+  if (!s->graph[0] && !s->graph[1] && !s->agraph[0] && !s->agraph[1]) return;
   (void)hipStreamSynchronize(s->stream);
   for (int k = 0; k < 2; k++) {
     if (s->graph[k]) (void)hipGraphExecDestroy(s->graph[k]);
+    if (s->agraph[k]) (void)hipGraphExecDestroy(s->agraph[k]);
     s->graph[k] = nullptr;
+    s->agraph[k] = nullptr;
   }
 }
 
@@ -248,25 +255,43 @@ int update_reference(dg_solver* s) {
   return upload_view(s);
 }
 
-// Record the launches of one RK step that starts from state buffer s->cur on the library's
-// capture stream (the solver's stream is swapped for it meanwhile) and instantiate them.
-int capture_step(dg_solver* s, double dt) {
+// one RK step from buffer s->cur with step size dt (ignored by the kernels while s->v.dtp is set)
+hipError_t run_step(dg_solver* s, double dt) {
+  const RkScheme& rk = kRk[s->scheme];
+  hipError_t err = hipSuccess;
+  for (int k = 0; k < rk.stages && err == hipSuccess; k++) {
+    err = run_stage(s, dt, rk.A[k], rk.B[k], dg::kModeRK);
+    s->cur ^= 1;
+  }
+  return err;
+}
+
+// the step size of the coming step, chosen on the device from the state in buffer s->cur
+hipError_t run_step_size(dg_solver* s, double cfl) {
+  const dg::View& v = s->v;
+  const double hmin = std::fmin(v.h[0], std::fmin(v.h[1], v.h[2]));
+  return timed(s, DG_K_OTHER, [&] {
+    return dg::launch_step_size(v, s->cur, cfl, hmin, v.N + 1.0, s->phys.gamma, s->phys.Pr, s->stream);
+  });
+}
+
+// Record the launches `record` makes for one RK step that starts from state buffer s->cur on the
+// library's capture stream (the solver's stream is swapped for it meanwhile), instantiate them
+// into *slot (replacing a previous graph).
+template <class F>
+int capture_into(dg_solver* s, hipGraphExec_t* slot, F record) {
   const int parity = s->cur;
-  if (s->graph[parity]) {
+  if (*slot) {
     (void)hipStreamSynchronize(s->stream);  // no replay of the old graph still in flight
-    (void)hipGraphExecDestroy(s->graph[parity]);
-    s->graph[parity] = nullptr;
+    (void)hipGraphExecDestroy(*slot);
+    *slot = nullptr;
   }
   hipStream_t user = s->stream;
   s->stream = s->cap_stream;
   hipGraph_t g = nullptr;
   hipError_t err = hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal);
   if (err == hipSuccess) {
-    const RkScheme& rk = kRk[s->scheme];
-    for (int k = 0; k < rk.stages && err == hipSuccess; k++) {
-      err = run_stage(s, dt, rk.A[k], rk.B[k], dg::kModeRK);
-      s->cur ^= 1;
-    }
+    err = record();
     const hipError_t e2 = hipStreamEndCapture(s->cap_stream, &g);
     if (err == hipSuccess) err = e2;
   }
@@ -280,9 +305,26 @@ int capture_step(dg_solver* s, double dt) {
   err = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (err != hipSuccess) return hip_fail(err, "instantiation of the RK-step graph");
-  s->graph[parity] = ex;
-  s->graph_dt[parity] = dt;
+  *slot = ex;
   return DG_OK;
+}
+
+int capture_step(dg_solver* s, double dt) {
+  const int parity = s->cur;
+  const int rc = capture_into(s, &s->graph[parity], [&] { return run_step(s, dt); });
+  if (rc == DG_OK) s->graph_dt[parity] = dt;
+  return rc;
+}
+
+// the launches of one adaptive step: step size, then the stages (s->v.dtp is set by the caller)
+int capture_adaptive_step(dg_solver* s, double cfl) {
+  const int parity = s->cur;
+  const int rc = capture_into(s, &s->agraph[parity], [&] {
+    hipError_t e = run_step_size(s, cfl);
+    return e == hipSuccess ? run_step(s, 0.0) : e;
+  });
+  if (rc == DG_OK) s->agraph_cfl[parity] = cfl;
+  return rc;
 }
 
 int check_bound(const dg_solver* s) {
@@ -436,6 +478,8 @@ int dg_solver_bind(dg_solver* s, void* dev_ptr, size_t bytes, void* hip_stream) 
   v.Fvf = v.viscous ? reinterpret_cast<double*>(b + p.Fvf) : nullptr;
   v.part = reinterpret_cast<double*>(b + p.part);
   v.diag = reinterpret_cast<double*>(b + p.diag);
+  v.adapt = reinterpret_cast<double*>(b + p.adapt);
+  v.dtp = nullptr;
   v.elem = mixed ? reinterpret_cast<const int4*>(b + p.elem) : nullptr;
   v.work = mixed ? reinterpret_cast<const int*>(b + p.work) : nullptr;
   v.mtab = mixed ? reinterpret_cast<const double*>(b + p.mtab) : nullptr;
@@ -619,15 +663,51 @@ int dg_rk_step(dg_solver* s, double dt, int nsteps) {
         if (rc) return rc;
       }
       DG_HIP(hipGraphLaunch(s->graph[par], s->stream), "RK-step graph launch");
-      s->cur ^= 1;  // three stages, each moving the state to the other buffer
+      s->cur ^= 1;  // an odd number of stages, each moving the state to the other buffer
     } else {
-      const RkScheme& rk = kRk[s->scheme];
-      for (int k = 0; k < rk.stages; k++) {
-        DG_HIP(run_stage(s, dt, rk.A[k], rk.B[k], dg::kModeRK), "RK stage kernels");
-        s->cur ^= 1;
-      }
+      DG_HIP(run_step(s, dt), "RK stage kernels");
     }
   }
+  return DG_OK;
+}
+
+int dg_rk_step_adaptive(dg_solver* s, double cfl, int nsteps, double* t_advanced) {
+  int rc = check_bound(s);
+  if (rc) return rc;
+  if (nsteps < 0) return fail(DG_EINVAL, "nsteps must be >= 0");
+  if (!std::isfinite(cfl) || !(cfl > 0)) return fail(DG_EINVAL, "cfl must be positive and finite");
+  DG_HIP(dg::launch_adapt_reset(s->v, s->stream), "adaptive-step reset");
+  const bool replay = s->use_graphs && !s->profiling && nsteps > 1;
+  s->v.dtp = s->v.adapt;  // the stage kernels read the step size the device chose
+  hipError_t err = hipSuccess;
+  const char* what = "adaptive RK step";
+  for (int it = 0; it < nsteps && err == hipSuccess; it++) {
+    if (replay) {
+      const int par = s->cur;
+      if (!s->agraph[par] || s->agraph_cfl[par] != cfl) {
+        rc = capture_adaptive_step(s, cfl);
+        if (rc) {
+          s->v.dtp = nullptr;
+          return rc;
+        }
+      }
+      err = hipGraphLaunch(s->agraph[par], s->stream);
+      what = "adaptive-step graph launch";
+      s->cur ^= 1;  // an odd number of stages, each moving the state to the other buffer
+    } else {
+      err = run_step_size(s, cfl);
+      if (err == hipSuccess) err = run_step(s, 0.0);
+    }
+  }
+  s->v.dtp = nullptr;
+  DG_HIP(err, what);
+  double h[4];
+  DG_HIP(hipMemcpyAsync(h, s->v.adapt, sizeof(h), hipMemcpyDeviceToHost, s->stream), "adaptive-step result");
+  DG_HIP(hipStreamSynchronize(s->stream), "adaptive-step result");
+  if (t_advanced) *t_advanced = h[1];
+  if (h[2] > 0)
+    return fail(DG_ENONFINITE, "the state held non-finite or non-physical values (rho or p <= 0) at the start of a "
+                               "step; from there on the steps had size 0");
   return DG_OK;
 }
 

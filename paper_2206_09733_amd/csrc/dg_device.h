@@ -70,6 +70,15 @@ __device__ __forceinline__ double rsq(double x) {
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
 // ------------------------------------------------------------------ physics helpers
+// largest characteristic speed |v| + c of a node and its pressure (the diagnostics and the
+// adaptive step size share this, so both see the same lambda_max)
+__device__ __forceinline__ double wave_speed(const double u[5], double g, double& p) {
+  const double v1 = u[1] / u[0], v2 = u[2] / u[0], v3 = u[3] / u[0];
+  const double q2 = v1 * v1 + v2 * v2 + v3 * v3;
+  p = (g - 1) * (u[4] - 0.5 * u[0] * q2);
+  return sqrt(q2) + sqrt(g * p / u[0]);
+}
+
 template <typename T>
 struct Prim {
   T rho, v1, v2, v3, beta, lrho, lbeta, h;  // beta = rho/(2p), h = |v|^2/2

@@ -53,6 +53,11 @@ struct View {
   double* Fvf;    // [E][6][4][nf] contravariant viscous flux on the element's faces
   double* part;   // diagnostics partials [E][kDiagSlots]
   double* diag;   // final diagnostics [kDiagSlots]
+  // adaptive step size: while dtp is set the stage kernels take the step size from *dtp (written
+  // on the device by dt_kernel) instead of their dt argument; adapt[0] the step size,
+  // adapt[1] the time advanced, adapt[2] the count of non-finite or non-physical nodes seen
+  const double* dtp;
+  double* adapt;
   // per-element anisotropic orders (mixed != 0): node counts per direction and first node of
   // each element, elements in launch order (largest first), Lobatto tables of every order
   // (offset tab_off[N] in tab) and mortar matrices (I_{N->M} then P_{M->N} at mort_off[N][M])
@@ -98,6 +103,11 @@ hipError_t launch_diag_final(const View& v, hipStream_t st);  // partials -> dia
 hipError_t launch_gradient_batch(const BatchArgs& B, int N, bool fp32, hipStream_t st);
 hipError_t launch_stage_batch(const BatchArgs& B, int N, bool fp32, bool visc, int fx, double rkA, double rkB,
                               int mode, hipStream_t st);  // fx: the members' flux family
+// adaptive step size (uniform and mixed orders): clear adapt[], then per step reduce the wave
+// speeds of U[cur] and write the step size to adapt[0]
+hipError_t launch_adapt_reset(const View& v, hipStream_t st);
+hipError_t launch_step_size(const View& v, int cur, double cfl, double hmin, double n1, double gamma, double Pr,
+                            hipStream_t st);
 // the extended flux families 1..3 (FP64), in kernels_ext.hip; called by the two launchers above
 hipError_t launch_stage_ext(const View& v, int fx, int cur, double dt, double rkA, double rkB, int mode,
                             hipStream_t st);

@@ -23,6 +23,7 @@
 // Dhat = D - e_N e_N^T/w_N + e_0 e_0^T/w_0 (the own-flux lift of the viscous term folded in).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "dg_device.h"
@@ -307,7 +308,8 @@ __global__ void __launch_bounds__(nthreads_for(N)) diag_kernel(View v, int cur) 
       }
     const double o1 = gv[2][1] - gv[1][2], o2 = gv[0][2] - gv[2][0], o3 = gv[1][0] - gv[0][1];
     s[8] = wq * 0.5 * rho * (o1 * o1 + o2 * o2 + o3 * o3);
-    s[9] = sqrt(q2) + sqrt(g * p / rho);
+    double pw;
+    s[9] = wave_speed(u, g, pw);
     s[10] = rho;
     s[11] = p;
     s[12] = (double)bad;
@@ -352,6 +354,111 @@ __global__ void __launch_bounds__(256) diag_final_kernel(View v) {
     if (t == 0) v.diag[k] = red[0];
     __syncthreads();
   }
+}
+
+// ------------------------------------------------------------------ adaptive step size
+// Per block: the largest |v| + c over the nodes of its elements, the smallest density, and the
+// count of nodes that are not finite or not physical (rho <= 0, p <= 0).  One 64-lane wave per
+// element, grid-stride over the elements; uniform and mixed orders.
+__global__ void __launch_bounds__(256) lambda_kernel(View v, int cur) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int nu = (v.N + 1) * (v.N + 1) * (v.N + 1);
+  double lam = -INFINITY, rmin = INFINITY, bad = 0.0;
+  for (int e = blockIdx.x * 4 + wv; e < v.E; e += gridDim.x * 4) {
+    long off = (long)e * nu;
+    int nn = nu;
+    if (v.mixed) {
+      const int4 q = v.elem[e];
+      nn = q.x * q.y * q.z;
+      off = q.w;
+    }
+    const double* __restrict__ U = v.U[cur] + off * 5;
+    for (int i = lane; i < nn; i += 64) {
+      double u[5];
+#pragma unroll
+      for (int c = 0; c < 5; c++) u[c] = U[(long)c * nn + i];
+      double p;
+      const double l = wave_speed(u, v.gamma, p);
+      bool ok = u[0] > 0.0 && p > 0.0 && isfinite(l);
+#pragma unroll
+      for (int c = 0; c < 5; c++) ok = ok && isfinite(u[c]);
+      if (ok) {
+        lam = fmax(lam, l);
+        rmin = fmin(rmin, u[0]);
+      } else {
+        bad += 1.0;
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    lam = fmax(lam, __shfl_xor(lam, o, 64));
+    rmin = fmin(rmin, __shfl_xor(rmin, o, 64));
+    bad += __shfl_xor(bad, o, 64);
+  }
+  __shared__ double red[3][4];
+  if (lane == 0) {
+    red[0][wv] = lam;
+    red[1][wv] = rmin;
+    red[2][wv] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = red[0][0], r = red[1][0], c = red[2][0];
+    for (int w = 1; w < 4; w++) {
+      a = fmax(a, red[0][w]);
+      r = fmin(r, red[1][w]);
+      c += red[2][w];
+    }
+    v.part[3 * blockIdx.x + 0] = a;
+    v.part[3 * blockIdx.x + 1] = r;
+    v.part[3 * blockIdx.x + 2] = c;
+  }
+}
+
+// Step size from the partials: the CFL limit cfl h_min/((N+1)^2 lambda_max) and, with viscosity,
+// the cap 0.25 h_min^2/((N+1)^4 gamma mu/(Pr rho_min)) -- the host's formula, operation for
+// operation.  A state with a non-finite or non-physical node gets step size 0 and raises the count
+// in adapt[2], which the host reports.
+__global__ void __launch_bounds__(256) dt_kernel(View v, int nparts, double cfl, double hmin, double n1,
+                                                 double gamma, double Pr) {
+  __shared__ double red[3][256];
+  const int t = threadIdx.x;
+  double a = -INFINITY, r = INFINITY, c = 0.0;
+  for (int k = t; k < nparts; k += 256) {
+    a = fmax(a, v.part[3 * k]);
+    r = fmin(r, v.part[3 * k + 1]);
+    c += v.part[3 * k + 2];
+  }
+  red[0][t] = a;
+  red[1][t] = r;
+  red[2][t] = c;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+      red[0][t] = fmax(red[0][t], red[0][t + w]);
+      red[1][t] = fmin(red[1][t], red[1][t + w]);
+      red[2][t] += red[2][t + w];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double lam = red[0][0], rmin = red[1][0];
+    double bad = red[2][0];
+    double dt = cfl * hmin / (n1 * n1 * lam);
+    if (v.viscous) dt = fmin(dt, 0.25 * hmin * hmin / (n1 * n1 * n1 * n1 * gamma * v.mu / (Pr * rmin)));
+    if (bad > 0.0 || !(lam > 0.0) || !(dt > 0.0) || !isfinite(dt)) {
+      dt = 0.0;
+      bad = bad > 0.0 ? bad : 1.0;
+    }
+    v.adapt[0] = dt;
+    v.adapt[1] += dt;
+    v.adapt[2] += bad;
+  }
+}
+
+__global__ void adapt_reset_kernel(View v) {
+  if (threadIdx.x < 4) v.adapt[threadIdx.x] = 0.0;
 }
 
 // ------------------------------------------------------------------ launchers
@@ -467,6 +574,20 @@ hipError_t launch_stage_batch(const BatchArgs& B, int N, bool fp32, bool visc, i
   if (B.n < 1 || B.n > kMaxBatch) return hipErrorInvalidValue;
   if (fx < 0 || fx > 3 || (fp32 && fx != 0)) return hipErrorInvalidValue;
   DG_DISPATCH_N(N, stage_batch_n, B, fp32, visc, fx, rkA, rkB, mode, st)
+}
+
+hipError_t launch_adapt_reset(const View& v, hipStream_t st) {
+  hipLaunchKernelGGL(adapt_reset_kernel, dim3(1), dim3(64), 0, st, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_size(const View& v, int cur, double cfl, double hmin, double n1, double gamma, double Pr,
+                            hipStream_t st) {
+  // at most 3 partials per block in v.part, which holds kDiagSlots doubles per element
+  const int blocks = std::min(1024, (v.E + 3) / 4);
+  hipLaunchKernelGGL(lambda_kernel, dim3(blocks), dim3(256), 0, st, v, cur);
+  hipLaunchKernelGGL(dt_kernel, dim3(1), dim3(256), 0, st, v, blocks, cfl, hmin, n1, gamma, Pr);
+  return hipGetLastError();
 }
 
 hipError_t launch_diag_final(const View& v, hipStream_t st) {

@@ -475,7 +475,7 @@ __global__ void __launch_bounds__(mix_lanes(NNMAX, NPL))
       if (mode == kModeResidual) {
         v.R[o + c * nn] = R[c];
       } else {
-        const double du = (rkA == 0.0 ? 0.0 : rkA * v.dU[o + c * nn]) + dt * R[c];
+        const double du = (rkA == 0.0 ? 0.0 : rkA * v.dU[o + c * nn]) + (v.dtp ? *v.dtp : dt) * R[c];
         v.dU[o + c * nn] = du;
         v.U[cur ^ 1][o + c * nn] = Uin[o + c * nn] + rkB * du;
       }
@@ -550,7 +550,8 @@ __global__ void __launch_bounds__(512) diag_mixed_kernel(View v, int cur) {
       }
     const double o1 = gv[2][1] - gv[1][2], o2 = gv[0][2] - gv[2][0], o3 = gv[1][0] - gv[0][1];
     s[8] = wq * 0.5 * rho * (o1 * o1 + o2 * o2 + o3 * o3);
-    s[9] = sqrt(q2) + sqrt(g * p / rho);
+    double pw;
+    s[9] = wave_speed(u, g, pw);
     s[10] = rho;
     s[11] = p;
     s[12] = (double)bad;

@@ -269,9 +269,10 @@ __device__ __forceinline__ void stage_body(const View& v, const int e, const int
     return;
   }
   double* __restrict__ Uout = v.U[cur ^ 1];
+  const double h = v.dtp ? *v.dtp : dt;
 #pragma unroll
   for (int c = 0; c < 5; c++) {
-    const double du = (rkA == 0.0 ? 0.0 : rkA * v.dU[o + c * nn]) + dt * R[c];
+    const double du = (rkA == 0.0 ? 0.0 : rkA * v.dU[o + c * nn]) + h * R[c];
     v.dU[o + c * nn] = du;
     Uout[o + c * nn] = Uin[o + c * nn] + rkB * du;
   }

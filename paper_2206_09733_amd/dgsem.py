@@ -53,6 +53,7 @@ KERNEL_CLASSES = ["gradient", "stage", "diagnostics", "other"]
 EXPORTS = ["dg_last_error", "dg_mesh_create_box", "dg_mesh_destroy", "dg_mesh_info",
            "dg_solver_create", "dg_solver_required_bytes", "dg_solver_bind",
            "dg_set_initial_condition", "dg_set_state", "dg_get_state", "dg_residual", "dg_rk_step",
+           "dg_rk_step_adaptive",
            "dg_diagnostics", "dg_suggest_dt", "dg_get_geometry", "dg_device_pointers",
            "dg_synchronize", "dg_solver_destroy", "dg_profile_begin", "dg_profile_end",
            "dg_solver_use_graphs", "dg_autotune", "dg_solver_set_tiles", "dg_batch_create",
@@ -95,6 +96,7 @@ def lib():
     L.dg_get_state.argtypes = [vp, _dp, _c.c_size_t]
     L.dg_residual.argtypes = [vp, _dp, _c.c_size_t]
     L.dg_rk_step.argtypes = [vp, _c.c_double, _c.c_int]
+    L.dg_rk_step_adaptive.argtypes = [vp, _c.c_double, _c.c_int, _dp]
     L.dg_diagnostics.argtypes = [vp, _c.POINTER(Diag)]
     L.dg_suggest_dt.argtypes = [vp, _c.c_double, _dp]
     L.dg_get_geometry.argtypes = [vp, _dp, _dp, _dp]
@@ -226,6 +228,13 @@ class Solver:
 
     def rk_step(self, dt, nsteps=1):
         check(lib().dg_rk_step(self.h, float(dt), int(nsteps)))
+
+    def rk_step_adaptive(self, cfl, nsteps=1):
+        """nsteps steps with the step size chosen on the device before each step; returns the
+        simulated time advanced."""
+        t = _c.c_double(0.0)
+        check(lib().dg_rk_step_adaptive(self.h, float(cfl), int(nsteps), _c.byref(t)))
+        return t.value
 
     def diagnostics(self):
         d = Diag()

@@ -103,6 +103,7 @@ def test_solver_argument_errors_and_sizes(dg):
     assert L.dg_solver_bind(s, None, nb.value, None) == dg.DG_EINVAL
     # calls that need device memory refuse an unbound solver
     assert L.dg_rk_step(s, ctypes.c_double(1e-3), 1) == dg.DG_ESTATE
+    assert L.dg_rk_step_adaptive(s, ctypes.c_double(0.5), 1, None) == dg.DG_ESTATE
     assert L.dg_residual(s, None, 0) == dg.DG_ESTATE
     L.dg_solver_destroy(s)
     L.dg_mesh_destroy(m)
