@@ -12,6 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 VOL = {"ec": 0, "central": 1, "ir": 2, "kg": 3, "pirozzoli": 4, "ducros": 5, "morinishi": 6}
 SURF = {"roe": 0, "llf": 1, "ec": 2, "central": 3, "es": 4, "ir": 5, "es_matrix": 6, "ld_roe": 7}
+VISC = {"br1": 0, "br2": 1, "ip": 2}
 IC = {"uniform": 0, "tgv": 1, "vortex": 2, "density_wave": 3}
 DIAG_KEYS = ["mass_rho", "mass_rhou", "mass_rhov", "mass_rhow", "mass_rhoE", "entropy_paper",
              "entropy", "ke", "enstrophy", "lambda_max", "rho_min", "p_min", "nonfinite", "volume"]
@@ -35,6 +36,7 @@ def _lib(precision="fp64"):
                                  ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                  ctypes.c_int]
         L.orc_destroy.argtypes = [ctypes.c_void_p]
+        L.orc_set_viscous_flux.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double]
         L.orc_num_nodes.restype = ctypes.c_long
         L.orc_num_nodes.argtypes = [ctypes.c_void_p]
         L.orc_num_elements.argtypes = [ctypes.c_void_p]
@@ -177,7 +179,7 @@ class OracleSolver:
 
     def __init__(self, ex, ey=None, ez=None, lo=(0.0, 0.0, 0.0), hi=None, deform=False,
                  amp=0.05, N=3, orders=None, gamma=1.4, Pr=0.71, Ma=0.1, Re=0.0, vol="ec",
-                 surf="roe", precision="fp64"):
+                 surf="roe", precision="fp64", visc="br1", visc_eta=0.0):
         ey = ex if ey is None else ey
         ez = ex if ez is None else ez
         if hi is None:
@@ -196,6 +198,8 @@ class OracleSolver:
                                    optr, gamma, Pr, Ma, Re, VOL[vol], SURF[surf])
         if not self.h:
             raise ValueError("orc_create rejected the configuration")
+        if self.L.orc_set_viscous_flux(self.h, VISC[visc], float(visc_eta)) != 0:
+            raise ValueError("orc_set_viscous_flux rejected the configuration")
         self.nodes = self.L.orc_num_nodes(self.h)
         self.E = self.L.orc_num_elements(self.h)
 

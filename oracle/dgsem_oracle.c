@@ -25,6 +25,7 @@
  *     (local, i.e. Rusanov), low-dissipation Roe, matrix dissipation, central and the EC flux
  *     at faces (box of convective fluxes in section "Spatial discretisation");
  *   - BR1 for the viscous terms (same box), gradients of (v,T) lifted with the face average;
+ *     the same box's BR2 and symmetric interior penalty as the other face viscous fluxes;
  *   - mortar coupling for faces between elements of different orders (section "Spatial
  *     p-adaptation"): interpolate both traces to the finer face grid, flux there, L2-project
  *     back with exactly integrated matrices;
@@ -265,6 +266,8 @@ struct orc_solver {
   int* nbr;         /* nbr[6e + 2d + s]: element across face (d, s), s=0 at xi_d=-1, 1 at +1 */
   real gamma, Pr, Ma, Re, mu, kappa;
   int vol, surf, viscous;
+  int visc_flux;   /* ORC_VISC_BR1 / BR2 / IP */
+  real visc_eta;   /* BR2 lifting factor, or interior-penalty factor */
   real *X, *Ja, *J; /* coordinates, metric terms, Jacobian */
   real *U, *dU, *G, *R;
 };
@@ -418,6 +421,8 @@ orc_solver* orc_create(int ex, int ey, int ez, const double* lo, const double* h
   s->mu = s->viscous ? (real)1 / (real)Re : 0;
   s->kappa = s->viscous ? s->mu * s->gamma / ((s->gamma - 1) * s->Pr) : 0;
   s->vol = vol_flux; s->surf = surf_flux;
+  s->visc_flux = ORC_VISC_BR1;
+  s->visc_eta = 0;
   s->N = (int(*)[3])malloc(sizeof(int[3]) * s->E);
   s->off = (long*)malloc(sizeof(long) * (s->E + 1));
   long acc = 0;
@@ -795,10 +800,9 @@ static void volume_flux(const orc_solver* s, const real uL[5], const real uR[5],
   else two_point_kep(s->vol, uL, uR, n, s->gamma, F);
 }
 
-/* viscous flux (eq. viscousfluxes) from the state and the gradients of (v1,v2,v3,T);
+/* viscous flux (eq. viscousfluxes) from the velocity v and the gradients of (v1,v2,v3,T);
  * grad[3c+n] = d g_c / d x_n.  Fv[5n+v]: component v of the flux in physical direction n. */
-static void viscous_flux(const real u[5], const real grad[12], real gamma, real mu, real kappa, real Fv[15]) {
-  prim_t w = prim(u, gamma);
+static void viscous_flux_v(const real vel[3], const real grad[12], real mu, real kappa, real Fv[15]) {
   real divv = grad[0] + grad[4] + grad[8];
   real tau[3][3];
   for (int a = 0; a < 3; a++)
@@ -807,8 +811,13 @@ static void viscous_flux(const real u[5], const real grad[12], real gamma, real 
   for (int n = 0; n < 3; n++) {
     Fv[5 * n + 0] = 0;
     for (int a = 0; a < 3; a++) Fv[5 * n + 1 + a] = tau[a][n];
-    Fv[5 * n + 4] = w.v[0] * tau[0][n] + w.v[1] * tau[1][n] + w.v[2] * tau[2][n] + kappa * grad[9 + n];
+    Fv[5 * n + 4] = vel[0] * tau[0][n] + vel[1] * tau[1][n] + vel[2] * tau[2][n] + kappa * grad[9 + n];
   }
+}
+
+static void viscous_flux(const real u[5], const real grad[12], real gamma, real mu, real kappa, real Fv[15]) {
+  prim_t w = prim(u, gamma);
+  viscous_flux_v(w.v, grad, mu, kappa, Fv);
 }
 
 /* ------------------------------------------------------------------------------------------
@@ -967,6 +976,104 @@ static void contra_visc(const orc_solver* s, const real* U, const real* Gall, in
   for (int v = 0; v < 5; v++) Fd[v] = n[0] * Fv[v] + n[1] * Fv[5 + v] + n[2] * Fv[10 + v];
 }
 
+/* Gradient of g at node ii of element e from the element's own values (the broken gradient
+ * (1/J) sum_d Ja^d D_d g, no lifting); with lift_d >= 0 plus eta times the lift of the jump on
+ * the one face (lift_d, lift_side) alone -- BR2's face-local lifting. */
+static void broken_gradient(const orc_solver* s, const real* U, int e, const int ii[3], int lift_d, int lift_side,
+                            real eta, real gr[12]) {
+  const int* N = s->N[e];
+  long q = node_of(s, e, ii);
+  real u[5], g[4];
+  load5(s, U, e, q, u);
+  gvars(u, s->gamma, g);
+  for (int t = 0; t < 12; t++) gr[t] = 0;
+  for (int d = 0; d < 3; d++) {
+    real a[4] = {0, 0, 0, 0};
+    int jj[3] = {ii[0], ii[1], ii[2]};
+    for (int m = 0; m <= N[d]; m++) {
+      jj[d] = m;
+      real um[5], gm[4];
+      load5(s, U, e, node_of(s, e, jj), um);
+      gvars(um, s->gamma, gm);
+      for (int c = 0; c < 4; c++) a[c] += GLL[N[d]].D[ii[d]][m] * gm[c];
+    }
+    if (d == lift_d) {
+      int at = lift_side ? N[d] : 0;
+      int ne = s->nbr[6 * e + 2 * d + lift_side];
+      int kk[3] = {ii[0], ii[1], ii[2]};
+      kk[d] = lift_side ? 0 : s->N[ne][d];
+      real un[5], gn[4];
+      load5(s, U, ne, node_of(s, ne, kk), un);
+      gvars(un, s->gamma, gn);
+      real wgt = eta / GLL[N[d]].w[at];
+      for (int c = 0; c < 4; c++) {
+        real jump = (g[c] + gn[c]) / 2 - g[c];
+        a[c] += lift_side ? wgt * jump : -wgt * jump;
+      }
+    }
+    real n[3];
+    load_ja(s, e, q, d, n);
+    for (int c = 0; c < 4; c++)
+      for (int x = 0; x < 3; x++) gr[3 * c + x] += n[x] * a[c];
+  }
+  real Jq = s->J[s->off[e] + q];
+  for (int t = 0; t < 12; t++) gr[t] /= Jq;
+}
+
+/* Face viscous flux along the scaled normal S between the node q of element e (face (d, side))
+ * and the matching node qo of its neighbour oth, from the face gradients of the chosen scheme
+ * (box of viscous fluxes in section "Spatial discretisation"):
+ *   BR1: average of the two sides' fluxes with their fully lifted gradients;
+ *   BR2: the same with each side's broken gradient plus eta times the lift of this face's jump;
+ *   IP (symmetric interior penalty): the same with the broken gradients, plus the penalty
+ *        sigma F_v(v_mean, [g] n^) . S, [g] = g(+ side) - g(- side), n^ = S/|S|,
+ *        sigma = eta (N_d + 1)^2 / h, h = 2 min(J_e, J_oth)/|S| (the element size across the
+ *        face, exact on affine elements).
+ * The volume terms of all three use the fully lifted gradient (for the interior penalty this
+ * supplies its symmetrising term). */
+static void face_viscous_flux(const orc_solver* s, const real* U, const real* Gall, int e, const int ii[3], int d,
+                              int side, int oth, const int kk[3], const real S[3], real Fst[5]) {
+  long q = node_of(s, e, ii), qo = node_of(s, oth, kk);
+  real Fa[5], Fb[5];
+  if (s->visc_flux == ORC_VISC_BR1) {
+    contra_visc(s, U, Gall, e, q, d, S, Fa);
+    contra_visc(s, U, Gall, oth, qo, d, S, Fb);
+  } else {
+    const int br2 = s->visc_flux == ORC_VISC_BR2;
+    real ga[12], gb[12], ua[5], ub[5], Fv[15];
+    broken_gradient(s, U, e, ii, br2 ? d : -1, side, s->visc_eta, ga);
+    broken_gradient(s, U, oth, kk, br2 ? d : -1, 1 - side, s->visc_eta, gb);
+    load5(s, U, e, q, ua);
+    load5(s, U, oth, qo, ub);
+    viscous_flux(ua, ga, s->gamma, s->mu, s->kappa, Fv);
+    for (int v = 0; v < 5; v++) Fa[v] = S[0] * Fv[v] + S[1] * Fv[5 + v] + S[2] * Fv[10 + v];
+    viscous_flux(ub, gb, s->gamma, s->mu, s->kappa, Fv);
+    for (int v = 0; v < 5; v++) Fb[v] = S[0] * Fv[v] + S[1] * Fv[5 + v] + S[2] * Fv[10 + v];
+  }
+  for (int v = 0; v < 5; v++) Fst[v] = (Fa[v] + Fb[v]) / 2;
+  if (s->visc_flux == ORC_VISC_IP) {
+    real ua[5], ub[5], ga[4], gb[4];
+    load5(s, U, e, q, ua);
+    load5(s, U, oth, qo, ub);
+    gvars(ua, s->gamma, ga);
+    gvars(ub, s->gamma, gb);
+    /* the + side of the face is the element across +xi_d from the other */
+    const real* gp = side ? gb : ga;
+    const real* gm = side ? ga : gb;
+    real area = RSQRT(S[0] * S[0] + S[1] * S[1] + S[2] * S[2]);
+    real Je = s->J[s->off[e] + q], Jo = s->J[s->off[oth] + qo];
+    real h = 2 * (Je < Jo ? Je : Jo) / area;
+    real n1 = s->N[e][d] + 1;
+    real sigma = s->visc_eta * n1 * n1 / h;
+    real vm[3], gr[12], Fv[15];
+    for (int c = 0; c < 3; c++) vm[c] = (ga[c] + gb[c]) / 2;
+    for (int c = 0; c < 4; c++)
+      for (int x = 0; x < 3; x++) gr[3 * c + x] = sigma * (gp[c] - gm[c]) * S[x] / area;
+    viscous_flux_v(vm, gr, s->mu, s->kappa, Fv);
+    for (int v = 0; v < 5; v++) Fst[v] += S[0] * Fv[v] + S[1] * Fv[5 + v] + S[2] * Fv[10 + v];
+  }
+}
+
 /* ------------------------------------------------------------------------------------------
  * 8. Residual of one element:
  *    J dU/dt = -[ sum_d sum_m 2 D_im F#(U_i,U_m; avg Ja^d)
@@ -1038,14 +1145,10 @@ static void element_residual(const orc_solver* s, const real* U, const real* Gal
               long Lq = side ? q : qo;
               real S[3];
               load_ja(s, Lq_e, Lq, d, S);
-              real Fa[5], Fb[5], Fown[5];
-              contra_visc(s, U, Gall, e, q, d, S, Fa);
-              contra_visc(s, U, Gall, oth, qo, d, S, Fb);
+              real Fst[5], Fown[5];
+              face_viscous_flux(s, U, Gall, e, ii, d, side, oth, kk, S, Fst);
               contra_visc(s, U, Gall, e, q, d, NULL, Fown);
-              for (int v = 0; v < 5; v++) {
-                real fst = (Fa[v] + Fb[v]) / 2;
-                Sv[v] += (side ? wgt : -wgt) * (fst - Fown[v]);
-              }
+              for (int v = 0; v < 5; v++) Sv[v] += (side ? wgt : -wgt) * (Fst[v] - Fown[v]);
             }
           }
         }
@@ -1354,6 +1457,12 @@ int orc_two_point_central(const double* UL, const double* UR, const double* n, d
   to_real(UL, a, 5); to_real(UR, b, 5); to_real(n, nn, 3);
   two_point_central(a, b, nn, gamma, f);
   to_dbl(f, F, 5);
+  return 0;
+}
+int orc_set_viscous_flux(orc_solver* s, int kind, double eta) {
+  if (!s || kind < ORC_VISC_BR1 || kind > ORC_VISC_IP || !(eta >= 0)) return -1;
+  s->visc_flux = kind;
+  s->visc_eta = eta > 0 ? (real)eta : (kind == ORC_VISC_BR2 ? 2 : 1);
   return 0;
 }
 int orc_two_point(int vol_kind, const double* UL, const double* UR, const double* n, double gamma, double* F) {

@@ -33,6 +33,7 @@ enum { ORC_VOL_EC = 0, ORC_VOL_CENTRAL = 1, ORC_VOL_IR = 2, ORC_VOL_KG = 3, ORC_
        ORC_VOL_DUCROS = 5, ORC_VOL_MORINISHI = 6 };
 enum { ORC_SURF_ROE = 0, ORC_SURF_LLF = 1, ORC_SURF_EC = 2, ORC_SURF_CENTRAL = 3, ORC_SURF_ES = 4, ORC_SURF_IR = 5,
        ORC_SURF_ES_MATRIX = 6, ORC_SURF_LOW_DISS_ROE = 7 };
+enum { ORC_VISC_BR1 = 0, ORC_VISC_BR2 = 1, ORC_VISC_IP = 2 };
 enum { ORC_IC_UNIFORM = 0, ORC_IC_TGV = 1, ORC_IC_VORTEX = 2, ORC_IC_DENSITY_WAVE = 3 };
 
 typedef struct orc_solver orc_solver;
@@ -50,6 +51,9 @@ orc_solver* orc_create(int ex, int ey, int ez, const double* lo, const double* h
                        double amp, int n_uniform, const int* orders, double gamma, double Pr,
                        double Ma, double Re, int vol_flux, int surf_flux);
 void orc_destroy(orc_solver* s);
+/* Face viscous flux: BR1 (default), BR2 with lifting factor eta, or the symmetric interior
+ * penalty with penalty factor eta (sigma = eta (N+1)^2 / h); eta = 0 takes 2 (BR2), 1 (IP). */
+int orc_set_viscous_flux(orc_solver* s, int kind, double eta);
 long orc_num_nodes(const orc_solver* s);
 int orc_num_elements(const orc_solver* s);
 int orc_elem_info(const orc_solver* s, int e, int* n3, long* off);

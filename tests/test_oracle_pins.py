@@ -899,6 +899,94 @@ def test_fp64_build_rounding_level_c1(orc):
 
 
 # ------------------------------------------------------------------ viscous assembly
+# ------------------------------------------------------------------ BR2 and interior penalty
+@pytest.mark.parametrize("visc,eta", [("br2", 0.0), ("br2", 3.0), ("ip", 0.0), ("ip", 2.5)])
+@pytest.mark.parametrize("N", [2, 3, 4])
+def test_viscous_face_schemes_closed_form_jump(orc, visc, eta, N):
+    """Box of viscous fluxes in section "Spatial discretisation" (BR1, BR2, symmetric interior
+    penalty).  A temperature that is constant in each column of elements along x (v = 0, rho = 1)
+    has zero broken gradients and jumps only across x-faces.  The schemes then differ from BR1 only
+    in the energy equation at x-face nodes, by (1/(w J)) (F*_scheme - F*_BR1) with
+      F*_BR1 = kappa (2/h_x) (dT/(2 w_N)) |S|      (both sides' lifted gradients),
+      F*_BR2 = eta F*_BR1                           (broken gradient 0 plus eta times one lift),
+      F*_IP  = eta (N+1)^2/h_x kappa dT |S|         (penalty),
+    dT = T(+x side) - T(-x side), |S| = h_y h_z/4, J = h_x h_y h_z/8; elsewhere they agree."""
+    ex, ey, ez = 3, 2, 2
+    n = N + 1
+    Re, Pr = 100.0, 0.71
+    kappa = (1 / Re) * GAMMA / ((GAMMA - 1) * Pr)
+    col_T = [1.0, 1.3, 0.8]
+    def solver(v):
+        s = orc.OracleSolver(ex, ey, ez, N=N, Re=Re, Pr=Pr, Ma=0.3, visc=v, visc_eta=eta)
+        U = np.zeros((ez, ey, ex, 5, n, n, n))
+        for a in range(ex):
+            U[:, :, a, 0] = 1.0
+            U[:, :, a, 4] = col_T[a] / (GAMMA - 1)  # p = rho T, v = 0
+        s.set_state(U.reshape(-1))
+        return s
+    R1 = solver("br1").residual().reshape(ez, ey, ex, 5, n, n, n)
+    Rx = solver(visc).residual().reshape(ez, ey, ex, 5, n, n, n)
+    hx, hy, hz = 2 * math.pi / ex, 2 * math.pi / ey, 2 * math.pi / ez
+    area, J = hy * hz / 4, hx * hy * hz / 8
+    _, w, _ = orc.gll(N)
+    e_eta = eta if eta > 0 else (2.0 if visc == "br2" else 1.0)
+    expect = np.zeros_like(R1)
+    for a in range(ex):
+        for side in (1, 0):  # +x face of column a (a is the - side), -x face (a is the + side)
+            if side:
+                dT = col_T[(a + 1) % ex] - col_T[a]
+            else:
+                dT = col_T[a] - col_T[(a - 1) % ex]
+            f_br1 = kappa * (2 / hx) * (dT / (2 * w[N])) * area
+            f_x = e_eta * f_br1 if visc == "br2" else e_eta * n * n / hx * kappa * dT * area
+            i = N if side else 0
+            sign = 1 / w[N] if side else -1 / w[0]
+            expect[:, :, a, 4, :, :, i] += sign * (f_x - f_br1) / J
+    diff = Rx - R1
+    scale = np.abs(expect).max()
+    assert scale > 1e-3
+    assert np.abs(diff - expect).max() < 1e-11 * scale, np.abs(diff - expect).max() / scale
+
+
+@pytest.mark.parametrize("visc", ["br2", "ip"])
+def test_viscous_schemes_agree_on_continuous_states(orc, visc):
+    """For a state whose traces agree across every face (a smooth field sampled at the shared
+    face nodes) all jumps vanish, so BR2 and the interior penalty reduce to BR1 (curvilinear mesh)."""
+    c = dict(ex=3, N=4, deform=True, Ma=0.2, Re=400.0)
+    R = {}
+    for v in ("br1", visc):
+        s = orc.OracleSolver(**c, visc=v)
+        s.set_ic("tgv")
+        R[v] = s.residual()
+    err = rel_per_var(R[visc], R["br1"], 27)
+    assert np.all(err < 1e-12), err
+
+
+@pytest.mark.parametrize("visc", ["br2", "ip"])
+def test_viscous_schemes_conserve_and_keep_freestream(orc, visc):
+    """Single-valued face viscous fluxes: totals are conserved on a perturbed state; a uniform
+    state stays steady."""
+    N = 3
+    s = orc.OracleSolver(3, N=N, deform=True, Ma=0.4, Re=300.0, visc=visc)
+    s.set_ic("tgv")
+    U = s.state().reshape(s.E, 5, -1)
+    drho, dv, dp = synth.primitive_perturbation(s.nodes, seed=17, amp=(0.05, 0.1, 0.05))
+    Un = U.transpose(0, 2, 1).reshape(-1, 5)
+    rho = Un[:, 0] * (1 + drho)
+    v = Un[:, 1:4] / Un[:, :1] + dv.T
+    p = 0.4 * (Un[:, 4] - 0.5 * (Un[:, 1:4] ** 2).sum(1) / Un[:, 0]) * (1 + dp)
+    s.set_state(to_conservative(rho, v, p).reshape(s.E, -1, 5).transpose(0, 2, 1).reshape(-1))
+    R = s.residual()
+    tot, mag = _conservation_sums(orc, s, R, N)
+    assert np.all(np.abs(tot) < 1e-12 * mag.max()), (tot, mag)
+    s2 = orc.OracleSolver(3, N=4, deform=True, Ma=0.3, Re=200.0, visc=visc)
+    p0 = 1 / (GAMMA * 0.09)
+    s2.set_ic("uniform", [1.0, 0.3, -0.2, 0.1, p0])
+    Ja, J = s2.metrics()
+    scale = (p0 / 0.4 + p0) * np.abs(Ja).max() / J.min() * 4 * 5 / 2
+    assert np.abs(s2.residual()).max() < 1e-13 * scale
+
+
 def test_viscous_terms_shear_wave_and_heat_conduction(orc):
     """Eq. viscousfluxes assembled with BR1: (i) the shear flow v = (sin y, 0, 0) with uniform
     rho, p is steady for Euler and its Navier-Stokes rate is (0, -mu sin y, 0, 0, mu cos 2y);
