@@ -101,6 +101,27 @@ def run_gpu(precision, steps, warmup, scheme="rk3"):
     return out
 
 
+def run_adaptive(steps, warmup, fixed_ms):
+    """The same workload with the step size chosen on the device before every step (CFL 0.5):
+    wall time of one dg_rk_step_adaptive call of `steps` steps (it synchronises once, at the end),
+    against the fixed-step time per step."""
+    import time
+    from paper_2206_09733_amd import dgsem
+    s = dgsem.Solver(**WORKLOAD)
+    s.set_ic("tgv")
+    s.rk_step_adaptive(0.5, warmup)
+    s.synchronize()
+    t0 = time.perf_counter()
+    t_sim = s.rk_step_adaptive(0.5, steps)
+    wall = time.perf_counter() - t0
+    d = s.diagnostics()
+    s.close()
+    ms = wall * 1e3 / steps
+    return {"ms_per_step": round(ms, 4), "steps": steps, "simulated_time": t_sim,
+            "overhead_vs_fixed_pct": round(100.0 * (ms / fixed_ms - 1.0), 2),
+            "state_finite": d["nonfinite"] == 0}
+
+
 MIXED = dict(ex=24, lo=(-10.0,) * 3, hi=(10.0,) * 3, Ma=0.5, vol="ec", surf="roe")
 # isentropic vortex of strength 5, free stream rho = p = 1 moving along (1, 1, 0)/sqrt 2 at Mach 0.5
 VORTEX = [5.0, 0.0, 0.0, 0.5 * math.sqrt(1.4 / 2.0), 0.5 * math.sqrt(1.4 / 2.0)]
@@ -353,6 +374,7 @@ def main():
         "stages_per_step": 5, "stage_avg_us": round(st4["ms"] / st4["launches"] * 1e3, 2),
         "value": round(5 * nodes * 5 * max(10, args.steps // 5) / (r4["event_ms"] / 1e3) / 1e9, 3),
         "unit": "GDOF-updates/s per RK stage"}
+    result["adaptive_dt"] = run_adaptive(args.steps, args.warmup, r64["event_ms"] / args.steps)
     if not args.skip_mixed:
         result["mixed_order"] = run_mixed(max(10, args.steps // 2), args.warmup)
     if not args.skip_large:

@@ -100,9 +100,22 @@ typedef struct {
   const int* orders;
 } dg_box_desc;
 
+/* face viscous flux (box of viscous fluxes in section "Spatial discretisation"), all with the
+ * BR1-lifted gradient of (v, T) in the volume terms:
+ *   BR1  average of the two sides' viscous fluxes with their lifted gradients;
+ *   BR2  the same with each side's broken (unlifted) gradient plus visc_eta times the lift of
+ *        this face's jump alone (visc_eta = 0: 2);
+ *   IP   symmetric interior penalty: the same with the broken gradients, plus the penalty
+ *        sigma F_v(v_mean, [g] n^) . S, sigma = visc_eta (N+1)^2 / h, h = 2 min(J_-, J_+)/|S|
+ *        (visc_eta = 0: 1).
+ * The choice is this library's reading: the paper names the three fluxes, not their constants. */
+enum { DG_VISC_BR1 = 0, DG_VISC_BR2 = 1, DG_VISC_IP = 2 };
+
 typedef struct {
   double gamma, Pr, Ma, Re;
   int vol_flux, surf_flux, precision;
+  int visc_flux;    /* DG_VISC_*; used when Re > 0 */
+  double visc_eta;  /* BR2 lifting factor or interior-penalty factor; 0 = the default above */
 } dg_physics;
 
 /* Diagnostics, all FP64 with Gauss-Lobatto quadrature w_i w_j w_k J, reduced in a fixed order

@@ -407,6 +407,8 @@ int dg_solver_create(const dg_mesh* m, const dg_physics* p, dg_solver** out) {
   if (p->surf_flux < DG_SURF_ROE || p->surf_flux > DG_SURF_LOW_DISS_ROE)
     return fail(DG_EINVAL, "unknown surface flux");
   if (p->precision != DG_FP64 && p->precision != DG_FP32_BULK) return fail(DG_EINVAL, "unknown precision");
+  if (p->visc_flux < DG_VISC_BR1 || p->visc_flux > DG_VISC_IP) return fail(DG_EINVAL, "unknown viscous flux");
+  if (!(p->visc_eta >= 0) || !std::isfinite(p->visc_eta)) return fail(DG_EINVAL, "visc_eta must be >= 0");
   if (m->N < 1 || m->N > dg::kMaxOrder) return fail(DG_EUNSUPPORTED, "no kernel for this order");
   if (p->precision == DG_FP32_BULK && (p->vol_flux >= DG_VOL_IR || p->surf_flux >= DG_SURF_ES))
     return fail(DG_EUNSUPPORTED, "FP32-bulk covers the EC and central volume fluxes and the Roe, LLF, EC and "
@@ -437,6 +439,8 @@ int dg_solver_create(const dg_mesh* m, const dg_physics* p, dg_solver** out) {
   v.viscous = p->Re > 0 ? 1 : 0;
   v.mu = v.viscous ? 1.0 / p->Re : 0.0;
   v.kappa = v.viscous ? v.mu * p->gamma / ((p->gamma - 1.0) * p->Pr) : 0.0;
+  v.visc_flux = p->visc_flux;
+  v.visc_eta = p->visc_eta > 0 ? p->visc_eta : (p->visc_flux == DG_VISC_BR2 ? 2.0 : 1.0);
   v.vol = p->vol_flux;
   v.surf = p->surf_flux;
   v.fp32 = p->precision == DG_FP32_BULK ? 1 : 0;
@@ -894,7 +898,8 @@ struct dg_batch {
   struct Group {  // uniform-order members of one order, precision and surface-flux family, viscous or not
     int N;
     bool fp32, visc;
-    int fx;  // flux family
+    int fx;   // flux family
+    bool xv;  // BR2 or interior-penalty face viscous flux
     std::vector<int> idx;
   };
   struct Graph {
@@ -941,7 +946,7 @@ hipError_t batch_stage(dg_batch* b, const double* dts, int k, hipStream_t st) {
     }
     hipError_t e;
     if (g.visc) {
-      e = dg::launch_gradient_batch(B, g.N, g.fp32, st);
+      e = dg::launch_gradient_batch(B, g.N, g.fp32, g.xv, st);
       if (e != hipSuccess) return e;
     }
     e = dg::launch_stage_batch(B, g.N, g.fp32, g.visc, g.fx, kRk[b->scheme].A[k], kRk[b->scheme].B[k],
@@ -1015,12 +1020,13 @@ int dg_batch_create(dg_solver* const* solvers, int n, void* hip_stream, dg_batch
     }
     const bool fp32 = s->v.fp32 != 0, visc = s->v.viscous != 0;
     const int fx = dg::flux_family(s->v.vol, s->v.surf);
+    const bool xv = s->v.viscous && s->v.visc_flux != 0;
     dg_batch::Group* g = nullptr;
     for (auto& x : b->groups)
-      if (x.N == s->v.N && x.fp32 == fp32 && x.visc == visc && x.fx == fx && (int)x.idx.size() < dg::kMaxBatch)
+      if (x.N == s->v.N && x.fp32 == fp32 && x.visc == visc && x.fx == fx && x.xv == xv && (int)x.idx.size() < dg::kMaxBatch)
         g = &x;
     if (!g) {
-      b->groups.push_back({s->v.N, fp32, visc, fx, {}});
+      b->groups.push_back({s->v.N, fp32, visc, fx, xv, {}});
       g = &b->groups.back();
     }
     g->idx.push_back(i);

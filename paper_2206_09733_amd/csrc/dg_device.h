@@ -756,6 +756,123 @@ __device__ __forceinline__ void gvars(const double u[5], double gamma, double T_
   g[3] = (T)(p * i - T_ref);
 }
 
+// viscous flux (eq. viscousfluxes) in physical direction x from the velocity and the gradient
+// gr[c][x] of g = (v, T): momentum 1..3 and energy components
+template <typename T>
+__device__ __forceinline__ void viscous_flux_g(T v1, T v2, T v3, const T gr[4][3], T mu, T kappa, T Fv[3][4]) {
+  const T divv = gr[0][0] + gr[1][1] + gr[2][2];
+  T tau[3][3];
+#pragma unroll
+  for (int p = 0; p < 3; p++)
+#pragma unroll
+    for (int q = 0; q < 3; q++)
+      tau[p][q] = mu * (gr[p][q] + gr[q][p]) - (p == q ? (T)(2.0 / 3.0) * mu * divv : (T)0);
+#pragma unroll
+  for (int x = 0; x < 3; x++) {
+    Fv[x][0] = tau[0][x];
+    Fv[x][1] = tau[1][x];
+    Fv[x][2] = tau[2][x];
+    Fv[x][3] = v1 * tau[0][x] + v2 * tau[1][x] + v3 * tau[2][x] + kappa * gr[3][x];
+  }
+}
+
+// Face viscous fluxes of BR2 (mode 1) and the symmetric interior penalty (mode 2) at this lane's
+// node, for every face direction d the node lies on (id_d = 0 or N): Ffd[d][c], contravariant
+// along Ja^d.  BR2: broken gradient (1/J) sum_d' Ja^d' D_d' g plus eta times the lift of face d's
+// half jump alone.  Interior penalty: broken gradient, plus sigma F_v(v_mean, [g] n^) . S with
+// [g] = g(+ side) - g(- side), sigma = eta (N+1)^2 |S| / (2 min(J_-, J_+)); the neighbour's g and J
+// are read from global memory and both elements evaluate the same expression on the same values,
+// so the penalty is single-valued.
+template <int n, typename T>
+__device__ __forceinline__ void face_viscous_br2_ip(const View& v, int e, int cur, double Tref, int t, int ti,
+                                                    int tj, int tk, const double* sD, T iwN, T iw0,
+                                                    const T* const sG[4], const T (*sJ)[4][n * n],
+                                                    const double ja[9], double ij, T Ffd[3][4]) {
+  constexpr int N = n - 1, nf = n * n, nn = n * n * n;
+  const T mu = (T)v.mu, kappa = (T)v.kappa, eta = (T)v.visc_eta;
+  const bool br2 = v.visc_flux == 1;
+  const int ii[3] = {ti, tj, tk};
+  T a[3][4], lift[3][4];
+#pragma unroll
+  for (int d = 0; d < 3; d++) {
+    const int id = ii[d];
+    const int stride = d == 0 ? 1 : (d == 1 ? n : nf);
+    const int b0 = t - id * stride;
+#pragma unroll
+    for (int c = 0; c < 4; c++) a[d][c] = (T)0;
+#pragma unroll
+    for (int m = 0; m < n; m++) {
+      const T Dm = (T)sD[id * n + m];
+#pragma unroll
+      for (int c = 0; c < 4; c++) a[d][c] += Dm * sG[c][b0 + m * stride];
+    }
+    const int qd = d == 0 ? tj + n * tk : (d == 1 ? ti + n * tk : ti + n * tj);
+#pragma unroll
+    for (int c = 0; c < 4; c++)
+      lift[d][c] = id == N ? iwN * sJ[2 * d + 1][c][qd] : (id == 0 ? -iw0 * sJ[2 * d][c][qd] : (T)0);
+  }
+  const T v1 = sG[0][t], v2 = sG[1][t], v3 = sG[2][t];
+  T grb[4][3];  // broken gradient
+#pragma unroll
+  for (int c = 0; c < 4; c++)
+#pragma unroll
+    for (int x = 0; x < 3; x++)
+      grb[c][x] = (T)ij * ((T)ja[x] * a[0][c] + (T)ja[3 + x] * a[1][c] + (T)ja[6 + x] * a[2][c]);
+  T Fb[3][4];
+  if (!br2) viscous_flux_g(v1, v2, v3, grb, mu, kappa, Fb);
+#pragma unroll
+  for (int d = 0; d < 3; d++) {
+    const int id = ii[d];
+    if (id != 0 && id != N) continue;
+    const T s1 = (T)ja[3 * d], s2 = (T)ja[3 * d + 1], s3 = (T)ja[3 * d + 2];
+    T Fv[3][4];
+    if (br2) {
+      T gr[4][3];
+#pragma unroll
+      for (int c = 0; c < 4; c++)
+#pragma unroll
+        for (int x = 0; x < 3; x++) gr[c][x] = grb[c][x] + eta * (T)ij * (T)ja[3 * d + x] * lift[d][c];
+      viscous_flux_g(v1, v2, v3, gr, mu, kappa, Fv);
+    } else {
+#pragma unroll
+      for (int x = 0; x < 3; x++)
+#pragma unroll
+        for (int c = 0; c < 4; c++) Fv[x][c] = Fb[x][c];
+    }
+#pragma unroll
+    for (int c = 0; c < 4; c++) Ffd[d][c] = s1 * Fv[0][c] + s2 * Fv[1][c] + s3 * Fv[2][c];
+    if (!br2) {
+      const int side = id == N ? 1 : 0;
+      const int qd = d == 0 ? tj + n * tk : (d == 1 ? ti + n * tk : ti + n * tj);
+      const int ne = v.nbr[e * 6 + 2 * d + side];
+      const int inb = face_node<n>(d, side ? 0 : N, qd % n, qd / n);
+      double un[5];
+#pragma unroll
+      for (int c = 0; c < 5; c++) un[c] = v.U[cur][(long)ne * nn * 5 + c * nn + inb];
+      T gn[4];
+      gvars(un, v.gamma, Tref, gn);
+      const T go[4] = {v1, v2, v3, sG[3][t]};
+      const double Jo = v.J[(long)e * nn + t], Jn = v.J[(long)ne * nn + inb];
+      const T a2 = s1 * s1 + s2 * s2 + s3 * s3;
+      const T ia = rsq(a2);
+      const T sigma = eta * (T)(n * n) * (a2 * ia) / ((T)2 * (T)(Jo < Jn ? Jo : Jn));
+      T gr[4][3];
+#pragma unroll
+      for (int c = 0; c < 4; c++) {
+        const T jump = side ? gn[c] - go[c] : go[c] - gn[c];
+        gr[c][0] = sigma * jump * s1 * ia;
+        gr[c][1] = sigma * jump * s2 * ia;
+        gr[c][2] = sigma * jump * s3 * ia;
+      }
+      const T m1 = (T)0.5 * (go[0] + gn[0]), m2 = (T)0.5 * (go[1] + gn[1]), m3 = (T)0.5 * (go[2] + gn[2]);
+      T Fp[3][4];
+      viscous_flux_g(m1, m2, m3, gr, mu, kappa, Fp);
+#pragma unroll
+      for (int c = 0; c < 4; c++) Ffd[d][c] += s1 * Fp[0][c] + s2 * Fp[1][c] + s3 * Fp[2][c];
+    }
+  }
+}
+
 // ------------------------------------------------------------------ initial conditions
 struct IcParams {
   double p[9];

@@ -40,6 +40,8 @@ struct View {
   double lo[3], h[3];
   double gamma, mu, kappa, Ma;
   int vol, surf, viscous, fp32;
+  int visc_flux;    // 0 BR1, 1 BR2, 2 symmetric interior penalty (face viscous flux)
+  double visc_eta;  // BR2 lifting factor or interior-penalty factor
   double rho_r, p_r;  // FP32-bulk reference state (mean density and pressure of the state set)
   const int* nbr; // [E][6] neighbour across face f = 2 d + side (side 1: xi_d = +1)
   const double* tab;
@@ -100,7 +102,7 @@ hipError_t launch_diagnostics(const View& v, int cur, hipStream_t st);
 hipError_t launch_diag_final(const View& v, hipStream_t st);  // partials -> diag, fixed order
 // batched Navier-Stokes gradient pass and stage of members of order N (all viscous, or all
 // inviscid for the stage), FP32-bulk or FP64
-hipError_t launch_gradient_batch(const BatchArgs& B, int N, bool fp32, hipStream_t st);
+hipError_t launch_gradient_batch(const BatchArgs& B, int N, bool fp32, bool xv, hipStream_t st);  // xv: BR2/IP
 hipError_t launch_stage_batch(const BatchArgs& B, int N, bool fp32, bool visc, int fx, double rkA, double rkB,
                               int mode, hipStream_t st);  // fx: the members' flux family
 // adaptive step size (uniform and mixed orders): clear adapt[], then per step reduce the wave

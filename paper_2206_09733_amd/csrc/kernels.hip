@@ -150,9 +150,11 @@ __global__ void ic_kernel(View v, int cur, int ic, IcParams P) {
 }
 
 // ------------------------------------------------------------------ pass A (Navier-Stokes)
-// Lifted gradient of (v, T) and, on the six faces, the contravariant viscous flux along the
-// face normal direction: Fvf[e][2d+side][c][face node].
-template <int N, typename T>
+// On the six faces, the contravariant viscous flux along the face normal direction of the face
+// viscous flux scheme: Fvf[e][2d+side][c][face node] (BR1: from the lifted gradient of (v, T);
+// BR2 and interior penalty: see face_viscous_br2_ip).  The stage kernel averages the two sides.
+// XV: the BR2 / interior-penalty face fluxes (compiled apart, the BR1 kernels keep their registers)
+template <int N, typename T, bool XV>
 __device__ __forceinline__ void grad_body(const View& v, const int e, const int cur) {
   constexpr int n = N + 1, nn = n * n * n, nf = n * n, NT = nthreads_for(N);
   const int t = threadIdx.x;
@@ -200,8 +202,11 @@ __device__ __forceinline__ void grad_body(const View& v, const int e, const int 
     const T iwN = (T)(1.0 / sw[N]), iw0 = (T)(1.0 / sw[0]);
     T Fvd[3][4];
     const T* const gp[4] = {sG[0], sG[1], sG[2], sG[3]};
-    gradient_and_viscous_flux<n, T>(t, ti, tj, tk, sD, iwN, iw0, gp, sJ, ja, ij, (T)v.mu, (T)v.kappa,
-                                    Fvd);
+    if constexpr (XV)
+      face_viscous_br2_ip<n, T>(v, e, cur, Tref, t, ti, tj, tk, sD, iwN, iw0, gp, sJ, ja, ij, Fvd);
+    else  // BR1: the lifted gradient's flux
+      gradient_and_viscous_flux<n, T>(t, ti, tj, tk, sD, iwN, iw0, gp, sJ, ja, ij, (T)v.mu, (T)v.kappa,
+                                      Fvd);
     T* Fvf = reinterpret_cast<T*>(v.Fvf) + (long)e * 6 * 4 * nf;
     const int ii[3] = {ti, tj, tk};
 #pragma unroll
@@ -219,16 +224,16 @@ __device__ __forceinline__ void grad_body(const View& v, const int e, const int 
   }
 }
 
-template <int N, typename T>
+template <int N, typename T, bool XV>
 __global__ void __launch_bounds__(nthreads_for(N)) grad_kernel(View v, int cur) {
-  grad_body<N, T>(v, block_element(v.E), cur);
+  grad_body<N, T, XV>(v, block_element(v.E), cur);
 }
 
-template <int N, typename T>
+template <int N, typename T, bool XV>
 __global__ void __launch_bounds__(nthreads_for(N)) grad_batch_kernel(BatchArgs B) {
   int m, e;
   batch_member(B, m, e);
-  grad_body<N, T>(*B.view[m], e, B.cur[m]);
+  grad_body<N, T, XV>(*B.view[m], e, B.cur[m]);
 }
 
 // ------------------------------------------------------------------ diagnostics (FP64)
@@ -475,7 +480,10 @@ static hipError_t geometry_n(const View& v, hipStream_t st) {
 
 template <int N, typename T>
 static hipError_t gradient_nt(const View& v, int cur, hipStream_t st) {
-  hipLaunchKernelGGL((grad_kernel<N, T>), dim3(v.E), dim3(nthreads_for(N)), 0, st, v, cur);
+  if (v.visc_flux != 0)
+    hipLaunchKernelGGL((grad_kernel<N, T, true>), dim3(v.E), dim3(nthreads_for(N)), 0, st, v, cur);
+  else
+    hipLaunchKernelGGL((grad_kernel<N, T, false>), dim3(v.E), dim3(nthreads_for(N)), 0, st, v, cur);
   return hipGetLastError();
 }
 
@@ -534,14 +542,17 @@ hipError_t launch_stage(const View& v, int cur, double dt, double rkA, double rk
 hipError_t launch_diagnostics(const View& v, int cur, hipStream_t st) { DG_DISPATCH(diag_n, v, cur, st) }
 
 template <int N, typename T>
-static hipError_t gradient_batch_nt(const BatchArgs& B, hipStream_t st) {
-  hipLaunchKernelGGL((grad_batch_kernel<N, T>), dim3(B.start[B.n]), dim3(nthreads_for(N)), 0, st, B);
+static hipError_t gradient_batch_nt(const BatchArgs& B, bool xv, hipStream_t st) {
+  if (xv)
+    hipLaunchKernelGGL((grad_batch_kernel<N, T, true>), dim3(B.start[B.n]), dim3(nthreads_for(N)), 0, st, B);
+  else
+    hipLaunchKernelGGL((grad_batch_kernel<N, T, false>), dim3(B.start[B.n]), dim3(nthreads_for(N)), 0, st, B);
   return hipGetLastError();
 }
 
 template <int N>
-static hipError_t gradient_batch_n(const BatchArgs& B, bool fp32, hipStream_t st) {
-  return fp32 ? gradient_batch_nt<N, float>(B, st) : gradient_batch_nt<N, double>(B, st);
+static hipError_t gradient_batch_n(const BatchArgs& B, bool fp32, bool xv, hipStream_t st) {
+  return fp32 ? gradient_batch_nt<N, float>(B, xv, st) : gradient_batch_nt<N, double>(B, xv, st);
 }
 
 template <int N>
@@ -564,9 +575,9 @@ static hipError_t stage_batch_n(const BatchArgs& B, bool fp32, bool visc, int fx
     default: return hipErrorInvalidValue;             \
   }
 
-hipError_t launch_gradient_batch(const BatchArgs& B, int N, bool fp32, hipStream_t st) {
+hipError_t launch_gradient_batch(const BatchArgs& B, int N, bool fp32, bool xv, hipStream_t st) {
   if (B.n < 1 || B.n > kMaxBatch) return hipErrorInvalidValue;
-  DG_DISPATCH_N(N, gradient_batch_n, B, fp32, st)
+  DG_DISPATCH_N(N, gradient_batch_n, B, fp32, xv, st)
 }
 
 hipError_t launch_stage_batch(const BatchArgs& B, int N, bool fp32, bool visc, int fx, double rkA, double rkB,

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "libdgsem.so")
 DG_OK, DG_EINVAL, DG_ENOMEM, DG_EHIP, DG_ENONFINITE, DG_EUNSUPPORTED, DG_ESTATE = 0, -1, -2, -3, -4, -5, -6
 VOL = {"ec": 0, "central": 1, "ir": 2, "kg": 3, "pirozzoli": 4, "ducros": 5, "morinishi": 6}
 SURF = {"roe": 0, "llf": 1, "ec": 2, "central": 3, "es": 4, "ir": 5, "es_matrix": 6, "ld_roe": 7}
+VISC = {"br1": 0, "br2": 1, "ip": 2}
 PRECISION = {"fp64": 0, "fp32_bulk": 1}
 IC = {"uniform": 0, "tgv": 1, "vortex": 2, "density_wave": 3}
 SCHEME = {"rk3": 0, "rk4": 1}
@@ -34,7 +35,7 @@ class BoxDesc(_c.Structure):
 class Physics(_c.Structure):
     _fields_ = [("gamma", _c.c_double), ("Pr", _c.c_double), ("Ma", _c.c_double),
                 ("Re", _c.c_double), ("vol_flux", _c.c_int), ("surf_flux", _c.c_int),
-                ("precision", _c.c_int)]
+                ("precision", _c.c_int), ("visc_flux", _c.c_int), ("visc_eta", _c.c_double)]
 
 
 class Diag(_c.Structure):
@@ -145,10 +146,12 @@ def box_desc(ex, ey, ez, lo, hi, deform, amp, N, orders=None):
     return d, keep
 
 
-def physics(gamma=1.4, Pr=0.71, Ma=0.1, Re=0.0, vol="ec", surf="roe", precision="fp64"):
+def physics(gamma=1.4, Pr=0.71, Ma=0.1, Re=0.0, vol="ec", surf="roe", precision="fp64", visc="br1",
+            visc_eta=0.0):
     p = Physics()
     p.gamma, p.Pr, p.Ma, p.Re = gamma, Pr, Ma, Re
     p.vol_flux, p.surf_flux, p.precision = VOL[vol], SURF[surf], PRECISION[precision]
+    p.visc_flux, p.visc_eta = VISC[visc], float(visc_eta)
     return p
 
 
@@ -161,7 +164,7 @@ class Solver:
 
     def __init__(self, ex, ey=None, ez=None, lo=(0.0, 0.0, 0.0), hi=None, deform=False, amp=0.05,
                  N=3, gamma=1.4, Pr=0.71, Ma=0.1, Re=0.0, vol="ec", surf="roe", precision="fp64",
-                 device="cuda", bind=True, orders=None):
+                 device="cuda", bind=True, orders=None, visc="br1", visc_eta=0.0):
         L = lib()
         ey = ex if ey is None else ey
         ez = ex if ez is None else ez
@@ -179,7 +182,7 @@ class Solver:
             check(L.dg_mesh_info(mesh, _c.byref(ne), _c.byref(nn), _c.byref(nmax)))
             self.E, self.nodes, self.nmax = ne.value, nn.value, nmax.value
             h = _c.c_void_p()
-            ph = physics(gamma, Pr, Ma, Re, vol, surf, precision)
+            ph = physics(gamma, Pr, Ma, Re, vol, surf, precision, visc, visc_eta)
             check(L.dg_solver_create(mesh, _c.byref(ph), _c.byref(h)))
             self.h = h
         finally:

@@ -79,6 +79,10 @@ def test_solver_argument_errors_and_sizes(dg):
         p = dg.physics()
         p.vol_flux, p.surf_flux = vol, surf
         assert L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)) == dg.DG_EINVAL
+    for vf, eta in ((3, 0.0), (-1, 0.0), (1, -1.0), (2, float("nan"))):
+        p = dg.physics(Re=100.0)
+        p.visc_flux, p.visc_eta = vf, eta
+        assert L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)) == dg.DG_EINVAL
     # FP32-bulk covers the EC / central volume fluxes and the first four surface fluxes only
     for vol, surf in (("ir", "roe"), ("kg", "roe"), ("morinishi", "llf"), ("ec", "es"),
                       ("ec", "es_matrix"), ("central", "ld_roe")):

@@ -21,13 +21,14 @@ def members(dg):
     """Two uniform Euler N=3 solves of different sizes and Mach numbers (one group), two
     Navier-Stokes N=4 solves (one group), an FP32-bulk Navier-Stokes N=4 solve, N=5 Euler solves
     with LLF faces, with Ismail-Roe + entropy-stable fluxes and with Kennedy-Gruber + low-
-    dissipation Roe fluxes, an N=3 Euler solve with the Pirozzoli volume flux, and a mixed-order
-    solve."""
+    dissipation Roe fluxes, an N=3 Euler solve with the Pirozzoli volume flux, an N=4
+    Navier-Stokes solve with the interior-penalty viscous flux, and a mixed-order solve."""
     specs = [dict(ex=4, N=3, Ma=0.1), dict(ex=3, ey=2, ez=5, N=3, Ma=0.4, deform=True),
              dict(ex=3, N=4, Ma=0.1, Re=1600.0, deform=True), dict(ex=2, N=4, Ma=0.3, Re=400.0),
              dict(ex=2, N=4, Ma=0.1, Re=800.0, precision="fp32_bulk"),
              dict(ex=2, N=5, Ma=0.2, surf="llf"), dict(ex=2, N=5, Ma=0.2, surf="es", vol="ir"),
              dict(ex=2, N=5, Ma=0.2, vol="kg", surf="ld_roe"), dict(ex=2, N=3, Ma=0.3, vol="pirozzoli"),
+             dict(ex=2, N=4, Ma=0.2, Re=500.0, visc="ip"),
              dict(ex=3, orders=synth.mixed_orders(27, seed=2), Ma=0.5, lo=(-10.0,) * 3, hi=(10.0,) * 3)]
     out = []
     for sp in specs:
@@ -50,10 +51,10 @@ def test_batch_equals_alone(dg):
         s.synchronize()
     side = torch.cuda.Stream()  # a batch on a stream of its own
     b = dg.Batch(batched, stream=side)
-    # groups: N=3 Euler, N=4 NS FP64, N=4 NS FP32, N=5 Euler, and one group per extended flux
+    # groups: N=3 Euler, N=4 NS FP64, N=4 NS FP32, N=5 Euler, one group per extended flux
     # family (N=5 extended surface flux, N=5 both extensions, N=3 kinetic-energy-preserving
-    # volume flux) -> 1+2+2+1+1+1+1 launches, mixed 1
-    assert b.launches_per_stage() == 10
+    # volume flux) and N=4 NS with the interior penalty -> 1+2+2+1+1+1+1+2 launches, mixed 1
+    assert b.launches_per_stage() == 12
     b.rk_step(dts, 4)
     side.synchronize()
     for k, (a, c) in enumerate(zip(alone, batched)):

@@ -236,6 +236,56 @@ def test_residual_navier_stokes(dg, orc, N):
     assert_parity(f"NS N={N}", g.residual(), R64, R80, 18, (N + 1) ** 3)
 
 
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("visc,eta", [("br2", 0.0), ("ip", 0.0), ("br2", 4.0), ("ip", 3.0)])
+def test_residual_viscous_face_schemes(dg, orc, N, visc, eta):
+    """BR2 and symmetric interior-penalty face viscous fluxes on a perturbed state (the traces
+    jump across every face), curvilinear mesh, FP64."""
+    c = cfg(ex=3, ey=2, ez=3, N=N, deform=True, Re=100.0, Ma=0.3)
+    log(f"NS residual N={N} {visc} eta={eta}")
+    U = perturbed_state(orc, c, seed=700 + N)
+    o64 = orc.OracleSolver(**c, visc=visc, visc_eta=eta)
+    o64.set_state(U)
+    o80 = orc.OracleSolver(**c, precision="fp80", visc=visc, visc_eta=eta)
+    o80.set_state(U)
+    g = dg.Solver(**c, visc=visc, visc_eta=eta)
+    g.set_state(U)
+    assert_parity(f"NS N={N} {visc} eta={eta}", g.residual(), o64.residual(), o80.residual(), 18, (N + 1) ** 3)
+
+
+@pytest.mark.parametrize("visc", ["br2", "ip"])
+def test_viscous_face_schemes_trajectory_and_fp32(dg, orc, visc):
+    """Three RK3 steps of a perturbed Navier-Stokes state against the oracle (FP64), and the
+    FP32-bulk residual within the stated tolerance."""
+    c = cfg(ex=3, N=4, deform=True, Re=400.0, Ma=0.2)
+    U = perturbed_state(orc, c, seed=77, amp=(0.01, 0.02, 0.01))
+    o, o80 = orc.OracleSolver(**c, visc=visc), orc.OracleSolver(**c, visc=visc, precision="fp80")
+    o.set_state(U)
+    o80.set_state(U)
+    dt = o.suggest_dt(0.5)
+    o.rk3(dt, 3)
+    o80.rk3(dt, 3)
+    g = dg.Solver(**c, visc=visc)
+    g.set_state(U)
+    g.rk_step(dt, 3)
+    Ug, Uo, U80 = g.state(), o.state(), o80.state()
+    d = lambda a, b: np.abs(a - b).reshape(27, 5, 125).max(axis=(0, 2))
+    sc = np.abs(U80).reshape(27, 5, 125).max(axis=(0, 2))
+    log(f"[{visc} RK] gpu-vs-fp80 {d(Ug, U80) / sc} fp64-vs-fp80 {d(Uo, U80) / sc}")
+    assert np.all(d(Ug, U80) <= np.maximum(1e-14 * sc, 8 * d(Uo, U80)))
+    c8 = dict(ex=8, N=4, deform=True, Ma=0.1, Re=1600.0)
+    U8 = perturbed_state(orc, dict(c8, vol="ec", surf="roe"), seed=78, amp=(1e-3, 1e-3, 1e-3))
+    o8 = orc.OracleSolver(**c8, visc=visc)
+    o8.set_state(U8)
+    Ro = o8.residual()
+    g32 = dg.Solver(**c8, visc=visc, precision="fp32_bulk")
+    g32.set_state(U8)
+    Rg = g32.residual()
+    err = np.abs(Rg - Ro).reshape(512, 5, 125).max(axis=(0, 2)) / np.abs(Ro).reshape(512, 5, 125).max(axis=(0, 2))
+    log(f"[FP32-bulk {visc}] rel err per var {err}")
+    assert np.all(err < FP32_TOL), err
+
+
 def test_residual_edge_meshes(dg, orc):
     """One element across a direction (a face is its own periodic neighbour), element counts
     that are not multiples of 8 (plain workgroup order), a non-cubic box."""
