@@ -689,7 +689,9 @@ static void entropy_vars(const real u[5], real gamma, real w[5]) {
  * which R T R^T = du/dw.  Reading: R, Lambda, T are taken at the averaged state
  * rho^ = (rho)^ln, v^ = {v}, p^ = {rho}/(2{beta}) (Chandrashekar's averages), with
  * c^2 = gamma p^/rho^ and H^ = c^2/(gamma-1) + |v^|^2/2.  The two shear waves are summed with the
- * tangential projector I - n n^T, so no tangent basis is needed.  D . (w_R - w_L) >= 0. */
+ * tangential projector I - n n^T, so no tangent basis is needed.  D . (w_R - w_L) >= 0.
+ * The structure and scaling are pinned; the choice of the averaged state among consistent
+ * averages is parity unpinned (no pin distinguishes them). */
 static void matrix_dissipation(const real uL[5], const real uR[5], const real n[3], real gamma, real D[5]) {
   prim_t L = prim(uL, gamma), R = prim(uR, gamma);
   real bL = L.rho / (2 * L.p), bR = R.rho / (2 * R.p);
