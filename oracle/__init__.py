@@ -55,6 +55,10 @@ def _lib(precision="fp64"):
         L.orc_entropy_production.argtypes = [ctypes.c_void_p, _dp]
         L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_gll.argtypes = [ctypes.c_int, _dp, _dp, _dp]
+        L.orc_gl.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp]
+        L.orc_create_gauss.restype = ctypes.c_void_p
+        L.orc_create_gauss.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int,
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_int]
         L.orc_mortar_matrices.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp]
         L.orc_euler_flux.argtypes = [_dp, _dp, ctypes.c_double, _dp]
         L.orc_two_point_ec.argtypes = [_dp, _dp, _dp, ctypes.c_double, _dp]
@@ -96,6 +100,15 @@ def gll(N, precision="fp64"):
     if rc:
         raise ValueError(f"orc_gll({N}) failed")
     return xi, w, D.reshape(N + 1, N + 1)
+
+
+def gl(N, precision="fp64"):
+    """Gauss-Legendre points, weights, derivative matrix and the Lagrange basis at -1 and +1."""
+    xi, w, D, lb = np.zeros(N + 1), np.zeros(N + 1), np.zeros((N + 1) * (N + 1)), np.zeros(2 * (N + 1))
+    rc = _lib(precision).orc_gl(N, _ptr(xi), _ptr(w), _ptr(D), _ptr(lb))
+    if rc:
+        raise ValueError(f"orc_gl({N}) failed")
+    return xi, w, D.reshape(N + 1, N + 1), lb.reshape(2, N + 1)
 
 
 def mortar_matrices(N, M, precision="fp64"):
@@ -179,7 +192,7 @@ class OracleSolver:
 
     def __init__(self, ex, ey=None, ez=None, lo=(0.0, 0.0, 0.0), hi=None, deform=False,
                  amp=0.05, N=3, orders=None, gamma=1.4, Pr=0.71, Ma=0.1, Re=0.0, vol="ec",
-                 surf="roe", precision="fp64", visc="br1", visc_eta=0.0):
+                 surf="roe", precision="fp64", visc="br1", visc_eta=0.0, nodes="lobatto"):
         ey = ex if ey is None else ey
         ez = ex if ez is None else ez
         if hi is None:
@@ -194,8 +207,13 @@ class OracleSolver:
             self._orders = np.ascontiguousarray(orders, dtype=np.int32).reshape(-1)
             assert self._orders.size == 3 * ex * ey * ez
             optr = self._orders.ctypes.data_as(_ip)
-        self.h = self.L.orc_create(ex, ey, ez, _ptr(lo), _ptr(hi), int(bool(deform)), amp, int(N),
-                                   optr, gamma, Pr, Ma, Re, VOL[vol], SURF[surf])
+        if nodes == "gauss":  # undeformed, uniform order, Euler, plain weak form
+            if deform or orders is not None or Re > 0 or vol != "central":
+                raise ValueError("Gauss-Legendre nodes: undeformed uniform-order Euler boxes, central volume form")
+            self.h = self.L.orc_create_gauss(ex, ey, ez, _ptr(lo), _ptr(hi), int(N), gamma, Ma, SURF[surf])
+        else:
+            self.h = self.L.orc_create(ex, ey, ez, _ptr(lo), _ptr(hi), int(bool(deform)), amp, int(N),
+                                       optr, gamma, Pr, Ma, Re, VOL[vol], SURF[surf])
         if not self.h:
             raise ValueError("orc_create rejected the configuration")
         if self.L.orc_set_viscous_flux(self.h, VISC[visc], float(visc_eta)) != 0:

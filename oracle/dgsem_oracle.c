@@ -29,6 +29,8 @@
  *   - mortar coupling for faces between elements of different orders (section "Spatial
  *     p-adaptation"): interpolate both traces to the finer face grid, flux there, L2-project
  *     back with exactly integrated matrices;
+ *   - on Gauss-Legendre nodes (the section's other quadrature), the plain weak form with
+ *     interpolated face traces, for the Euler equations on uniform-order affine boxes;
  *   - Williamson's low-storage RK3 and Carpenter-Kennedy's low-storage RK4 (section "Time
  *     advancement");
  *   - entropy S=-rho*s, s=ln p - gamma ln rho and w=dS/du (section "Shock capturing",
@@ -88,9 +90,11 @@ typedef struct {
   real w[ORC_NMAX + 1];
   real D[ORC_NMAX + 1][ORC_NMAX + 1];
   long double xl[ORC_NMAX + 1];
+  real lb[2][ORC_NMAX + 1];  /* Lagrange basis at xi = -1 (lb[0]) and xi = +1 (lb[1]) */
 } gll_t;
 
-static gll_t GLL[ORC_NMAX + 1];
+static gll_t GLL[ORC_NMAX + 1];  /* Gauss-Lobatto */
+static gll_t GL[ORC_NMAX + 1];   /* Gauss-Legendre */
 static int GLL_READY = 0;
 
 static void gll_build(int N, gll_t* g) {
@@ -129,15 +133,71 @@ static void gll_build(int N, gll_t* g) {
       else d = 0.0L;
       g->D[i][j] = (real)d;
     }
+  for (int j = 0; j <= N; j++) {
+    g->lb[0][j] = j == 0 ? 1 : 0;
+    g->lb[1][j] = j == N ? 1 : 0;
+  }
+}
+
+/* Gauss-Legendre points of order N (the N+1 zeros of P_{N+1}, by Newton from the Chebyshev-like
+ * guesses), weights 2/((1-x^2) P'^2), derivative matrix D_ij = P'(x_i)/(P'(x_j)(x_i - x_j)),
+ * D_ii = x_i/(1 - x_i^2) (P = P_{N+1}), and the Lagrange basis at the ends as products. */
+static void gl_build(int N, gll_t* g) {
+  const int n = N + 1;
+  long double x[ORC_NMAX + 1], dP[ORC_NMAX + 1];
+  for (int j = 0; j < n; j++) {
+    long double t = -cosl(PI_L * (j + 0.75L) / (n + 0.5L));
+    long double L, dL;
+    for (int it = 0; it < 200; it++) {
+      legendre(n, t, &L, &dL);
+      long double dt = L / dL;
+      t -= dt;
+      if (fabsl(dt) < 1e-21L) break;
+    }
+    legendre(n, t, &L, &dL);
+    x[j] = t;
+    dP[j] = dL;
+  }
+  for (int j = 0; j < n; j++) {
+    g->xl[j] = x[j];
+    g->xi[j] = (real)x[j];
+    g->w[j] = (real)(2.0L / ((1.0L - x[j] * x[j]) * dP[j] * dP[j]));
+  }
+  for (int i = 0; i < n; i++)
+    for (int j = 0; j < n; j++)
+      g->D[i][j] = (real)(i != j ? dP[i] / (dP[j] * (x[i] - x[j])) : x[i] / (1.0L - x[i] * x[i]));
+  for (int j = 0; j < n; j++)
+    for (int side = 0; side < 2; side++) {
+      long double y = side ? 1.0L : -1.0L, v = 1.0L;
+      for (int r = 0; r < n; r++)
+        if (r != j) v *= (y - x[r]) / (x[j] - x[r]);
+      g->lb[side][j] = (real)v;
+    }
 }
 
 static void mortar_tables(void);
 
 static void gll_init(void) {
   if (GLL_READY) return;
-  for (int N = 1; N <= ORC_NMAX; N++) gll_build(N, &GLL[N]);
+  for (int N = 1; N <= ORC_NMAX; N++) {
+    gll_build(N, &GLL[N]);
+    gl_build(N, &GL[N]);
+  }
   mortar_tables();
   GLL_READY = 1;
+}
+
+int orc_gl(int N, double* xi, double* w, double* D, double* lb) {
+  if (N < 1 || N > ORC_NMAX) return -1;
+  gll_init();
+  for (int i = 0; i <= N; i++) {
+    if (xi) xi[i] = (double)GL[N].xi[i];
+    if (w) w[i] = (double)GL[N].w[i];
+    if (lb) { lb[i] = (double)GL[N].lb[0][i]; lb[N + 1 + i] = (double)GL[N].lb[1][i]; }
+    for (int j = 0; j <= N; j++)
+      if (D) D[i * (N + 1) + j] = (double)GL[N].D[i][j];
+  }
+  return 0;
 }
 
 int orc_gll(int N, double* xi, double* w, double* D) {
@@ -267,6 +327,8 @@ struct orc_solver {
   real gamma, Pr, Ma, Re, mu, kappa;
   int vol, surf, viscous;
   int visc_flux;   /* ORC_VISC_BR1 / BR2 / IP */
+  int gauss;       /* Gauss-Legendre nodes (weak form) instead of Gauss-Lobatto */
+  const gll_t* T;  /* the node tables of this solver: GLL or GL */
   real visc_eta;   /* BR2 lifting factor, or interior-penalty factor */
   real *X, *Ja, *J; /* coordinates, metric terms, Jacobian */
   real *U, *dU, *G, *R;
@@ -319,7 +381,7 @@ static real dref(const orc_solver* s, int e, const real* f, int d, const int ii[
   int jj[3] = {ii[0], ii[1], ii[2]};
   for (int m = 0; m <= Nd; m++) {
     jj[d] = m;
-    acc += GLL[Nd].D[ii[d]][m] * f[node_of(s, e, jj)];
+    acc += s->T[Nd].D[ii[d]][m] * f[node_of(s, e, jj)];
   }
   return acc;
 }
@@ -344,7 +406,7 @@ static void build_geometry(orc_solver* s) {
           int ii[3] = {i, j, k};
           real xu[3], loc[3], dx[3];
           for (int d = 0; d < 3; d++) {
-            loc[d] = (1 + GLL[N[d]].xi[ii[d]]) / 2 * s->h[d];
+            loc[d] = (1 + s->T[N[d]].xi[ii[d]]) / 2 * s->h[d];
             xu[d] = s->lo[d] + cell[d] * s->h[d] + loc[d];
           }
           displacement(s, xu, dx);
@@ -403,13 +465,15 @@ static void build_geometry(orc_solver* s) {
   }
 }
 
-orc_solver* orc_create(int ex, int ey, int ez, const double* lo, const double* hi, int deform,
-                       double amp, int n_uniform, const int* orders, double gamma, double Pr,
-                       double Ma, double Re, int vol_flux, int surf_flux) {
+static orc_solver* create(int ex, int ey, int ez, const double* lo, const double* hi, int deform, double amp,
+                          int n_uniform, const int* orders, double gamma, double Pr, double Ma, double Re,
+                          int vol_flux, int surf_flux, int gauss) {
   if (ex < 1 || ey < 1 || ez < 1 || !lo || !hi) return NULL;
   if (vol_flux < 0 || vol_flux > ORC_VOL_MORINISHI || surf_flux < 0 || surf_flux > ORC_SURF_LOW_DISS_ROE) return NULL;
   gll_init();
   orc_solver* s = (orc_solver*)calloc(1, sizeof(orc_solver));
+  s->gauss = gauss;
+  s->T = gauss ? GL : GLL;
   s->ex = ex; s->ey = ey; s->ez = ez; s->E = ex * ey * ez;
   for (int d = 0; d < 3; d++) { s->lo[d] = lo[d]; s->hi[d] = hi[d]; }
   s->h[0] = (s->hi[0] - s->lo[0]) / ex;
@@ -465,6 +529,17 @@ orc_solver* orc_create(int ex, int ey, int ez, const double* lo, const double* h
   if (!s->X || !s->Ja || !s->J || !s->U || !s->dU || !s->R || !s->G) { orc_destroy(s); return NULL; }
   build_geometry(s);
   return s;
+}
+
+orc_solver* orc_create(int ex, int ey, int ez, const double* lo, const double* hi, int deform,
+                       double amp, int n_uniform, const int* orders, double gamma, double Pr,
+                       double Ma, double Re, int vol_flux, int surf_flux) {
+  return create(ex, ey, ez, lo, hi, deform, amp, n_uniform, orders, gamma, Pr, Ma, Re, vol_flux, surf_flux, 0);
+}
+
+orc_solver* orc_create_gauss(int ex, int ey, int ez, const double* lo, const double* hi, int N, double gamma,
+                             double Ma, int surf_flux) {
+  return create(ex, ey, ez, lo, hi, 0, 0.0, N, NULL, gamma, 0.71, Ma, 0.0, ORC_VOL_CENTRAL, surf_flux, 1);
 }
 
 void orc_destroy(orc_solver* s) {
@@ -1160,7 +1235,85 @@ static void element_residual(const orc_solver* s, const real* U, const real* Gal
   for (int f = 0; f < 6; f++) free(Ff[f]);
 }
 
+/* ------------------------------------------------------------------------------------------
+ * 8b. Residual of one element on Gauss-Legendre nodes (section "Spatial discretisation": the
+ *     weak form NS2-NS4 with Gauss quadrature; no boundary nodes, so no split form).  With the
+ *     Lagrange basis l_i, weights w_i and the derivative matrix D on the Gauss points:
+ *       J dU_i/dt = -[ sum_d sum_m Dw_im F~^d_m
+ *                      + sum_d (l_i(+1) F*(+d face) - l_i(-1) F*(-d face)) / w_i ],
+ *     Dw_im = -D_mi w_m / w_i (the quadrature of -int F dl_i/dxi), F~^d = Ja^d . F(U) at the
+ *     nodes, F* the numerical flux between the two traces U(+-1) = sum_i l_i(+-1) U_i along the
+ *     line through the face point, with the owner's metric interpolated the same way as normal.
+ *     Uniform orders, Euler. */
+static void element_residual_gauss(const orc_solver* s, const real* U, int e, real* R) {
+  const int N = s->N[e][0], n = N + 1, nn = n * n * n;
+  const gll_t* T = &s->T[N];
+  /* numerical flux on the six faces, face point (p, r) along the two tangential directions */
+  real Ff[6][5][(ORC_NMAX + 1) * (ORC_NMAX + 1)];
+  for (int d = 0; d < 3; d++) {
+    int ta, tb;
+    face_dirs(d, &ta, &tb);
+    for (int side = 0; side < 2; side++) {
+      int L = side ? e : s->nbr[6 * e + 2 * d];
+      int Rr = s->nbr[6 * L + 2 * d + 1];
+      for (int r = 0; r < n; r++)
+        for (int p = 0; p < n; p++) {
+          real uL[5] = {0, 0, 0, 0, 0}, uR[5] = {0, 0, 0, 0, 0}, S[3] = {0, 0, 0};
+          for (int i = 0; i < n; i++) {
+            int ii[3];
+            ii[d] = i; ii[ta] = p; ii[tb] = r;
+            real a[5], b[5], ja[3];
+            long qL = node_of(s, L, ii), qR = node_of(s, Rr, ii);
+            load5(s, U, L, qL, a);
+            load5(s, U, Rr, qR, b);
+            load_ja(s, L, qL, d, ja);
+            for (int v = 0; v < 5; v++) {
+              uL[v] += T->lb[1][i] * a[v];
+              uR[v] += T->lb[0][i] * b[v];
+            }
+            for (int c = 0; c < 3; c++) S[c] += T->lb[1][i] * ja[c];
+          }
+          real F[5];
+          riemann(s->surf, uL, uR, S, s->gamma, F);
+          for (int v = 0; v < 5; v++) Ff[2 * d + side][v][p + n * r] = F[v];
+        }
+    }
+  }
+  for (int k = 0; k < n; k++)
+    for (int j = 0; j < n; j++)
+      for (int i = 0; i < n; i++) {
+        int ii[3] = {i, j, k};
+        long q = node_of(s, e, ii);
+        real V[5] = {0, 0, 0, 0, 0};
+        for (int d = 0; d < 3; d++) {
+          int ta, tb;
+          face_dirs(d, &ta, &tb);
+          int jj[3] = {i, j, k};
+          for (int m = 0; m < n; m++) {
+            jj[d] = m;
+            long qm = node_of(s, e, jj);
+            real um[5], nm[3], F[5];
+            load5(s, U, e, qm, um);
+            load_ja(s, e, qm, d, nm);
+            euler_flux(um, nm, s->gamma, F);
+            real dw = -T->D[m][ii[d]] * T->w[m] / T->w[ii[d]];
+            for (int v = 0; v < 5; v++) V[v] += dw * F[v];
+          }
+          int fq = ii[ta] + n * ii[tb];
+          for (int v = 0; v < 5; v++)
+            V[v] += (T->lb[1][ii[d]] * Ff[2 * d + 1][v][fq] - T->lb[0][ii[d]] * Ff[2 * d][v][fq]) / T->w[ii[d]];
+        }
+        real Jq = s->J[s->off[e] + q];
+        for (int v = 0; v < 5; v++) R[(long)v * nn + q] = -V[v] / Jq;
+      }
+}
+
 static void residual(orc_solver* s, const real* U, real* R) {
+  if (s->gauss) {
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int e = 0; e < s->E; e++) element_residual_gauss(s, U, e, R + s->off[e] * 5);
+    return;
+  }
   if (s->viscous) compute_gradients(s, U, s->G);
 #pragma omp parallel for schedule(dynamic, 4)
   for (int e = 0; e < s->E; e++) element_residual(s, U, s->G, e, R + s->off[e] * 5);
@@ -1354,7 +1507,7 @@ int orc_diagnostics(const orc_solver* s, double* out) {
             if (!isfinite((double)u[v])) bad++;
           prim_t w = prim(u, s->gamma);
           real Jq = s->J[s->off[e] + q];
-          real wq = GLL[N[0]].w[i] * GLL[N[1]].w[j] * GLL[N[2]].w[k] * Jq;
+          real wq = s->T[N[0]].w[i] * s->T[N[1]].w[j] * s->T[N[2]].w[k] * Jq;
           for (int v = 0; v < 5; v++) acc[v] += wq * u[v];
           real sp = RLOG(w.p) - s->gamma * RLOG(w.rho);
           acc[5] += wq * (-w.rho * sp);
@@ -1387,7 +1540,7 @@ int orc_diagnostics(const orc_solver* s, double* out) {
       for (int j = 0; j <= N[1]; j++)
         for (int i = 0; i <= N[0]; i++) {
           int ii[3] = {i, j, k};
-          vol += GLL[N[0]].w[i] * GLL[N[1]].w[j] * GLL[N[2]].w[k] * s->J[s->off[e] + node_of(s, e, ii)];
+          vol += s->T[N[0]].w[i] * s->T[N[1]].w[j] * s->T[N[2]].w[k] * s->J[s->off[e] + node_of(s, e, ii)];
         }
   }
   for (int v = 0; v < 7; v++) out[v] = (double)acc[v];
@@ -1420,7 +1573,7 @@ double orc_entropy_production(const orc_solver* s, const double* R) {
           real v2 = w.v[0] * w.v[0] + w.v[1] * w.v[1] + w.v[2] * w.v[2];
           real wv[5] = {(s->gamma - sp) / (s->gamma - 1) - b * v2, 2 * b * w.v[0], 2 * b * w.v[1],
                         2 * b * w.v[2], -2 * b};
-          real wq = GLL[N[0]].w[i] * GLL[N[1]].w[j] * GLL[N[2]].w[k] * s->J[s->off[e] + q];
+          real wq = s->T[N[0]].w[i] * s->T[N[1]].w[j] * s->T[N[2]].w[k] * s->J[s->off[e] + q];
           for (int v = 0; v < 5; v++) acc += wq * wv[v] * (real)R[s->off[e] * 5 + (long)v * nn + q];
         }
   }

@@ -40,6 +40,9 @@ typedef struct orc_solver orc_solver;
 
 /* Gauss-Lobatto nodes xi[N+1], weights w[N+1] and derivative matrix D[(N+1)*(N+1)] (row-major). */
 int orc_gll(int N, double* xi, double* w, double* D);
+/* Gauss-Legendre points xi[N+1], weights w, derivative matrix D (row-major) and the Lagrange
+ * basis at the ends, lb[0..N] at xi = -1 and lb[N+1..2N+1] at xi = +1. */
+int orc_gl(int N, double* xi, double* w, double* D, double* lb);
 
 /* Mortar operators: I[(M+1)x(N+1)] interpolates order N to order M Lobatto nodes;
  * P[(N+1)x(M+1)] is the exactly integrated L2 projection from order M back to order N. */
@@ -50,6 +53,10 @@ int orc_mortar_matrices(int N, int M, double* I, double* P);
 orc_solver* orc_create(int ex, int ey, int ez, const double* lo, const double* hi, int deform,
                        double amp, int n_uniform, const int* orders, double gamma, double Pr,
                        double Ma, double Re, int vol_flux, int surf_flux);
+/* The same box (undeformed, uniform order N) on Gauss-Legendre nodes: Euler equations, plain
+ * (non-split) weak form, face traces interpolated to the element boundaries. */
+orc_solver* orc_create_gauss(int ex, int ey, int ez, const double* lo, const double* hi, int N, double gamma,
+                             double Ma, int surf_flux);
 void orc_destroy(orc_solver* s);
 /* Face viscous flux: BR1 (default), BR2 with lifting factor eta, or the symmetric interior
  * penalty with penalty factor eta (sigma = eta (N+1)^2 / h); eta = 0 takes 2 (BR2), 1 (IP). */
