@@ -54,6 +54,12 @@ extern "C" {
 
 /* ------------------------------------------------------------------ options */
 enum { DG_DEFORM_NONE = 0, DG_DEFORM_SINSIN = 1 };
+/* quadrature / collocation points (section "Spatial discretisation" allows both): Gauss-Lobatto
+ * (every split form, the viscous terms, mixed orders, FP32-bulk), or Gauss-Legendre (more
+ * accurate; no boundary nodes, so the plain weak form with face traces interpolated to the
+ * element boundaries: Euler equations, undeformed uniform-order boxes, FP64, volume flux
+ * DG_VOL_CENTRAL, any surface flux) */
+enum { DG_NODES_LOBATTO = 0, DG_NODES_GAUSS = 1 };
 /* volume two-point flux (the list of split forms of section "Energy/Entropy stable versions"):
  * Chandrashekar's entropy-conserving, kinetic-energy-preserving flux; the central average;
  * Ismail and Roe's entropy-conserving flux; the kinetic-energy-preserving forms of
@@ -98,6 +104,7 @@ typedef struct {
   double deform_amp;
   int n_uniform;
   const int* orders;
+  int nodes;  /* DG_NODES_LOBATTO (default) or DG_NODES_GAUSS */
 } dg_box_desc;
 
 /* face viscous flux (box of viscous fluxes in section "Spatial discretisation"), all with the
@@ -266,7 +273,9 @@ int dg_batch_create(dg_solver* const* solvers, int n, void* hip_stream, dg_batch
 int dg_batch_rk_step(dg_batch* b, const double* dts, int nsteps);
 /* enable = 0 disables graph replay of the batch (and drops its graphs). */
 int dg_batch_use_graphs(dg_batch* b, int enable);
-/* Kernel launches per RK stage of the batch (the one-launch-per-group structure made visible). */
+/* Kernel launches per RK stage of the batch (the one-launch-per-group structure made visible):
+ * one per batched group (two with viscous terms), plus one for each mixed-order or
+ * Gauss-Legendre member, which runs its own launches within the batch's stages. */
 int dg_batch_launches(const dg_batch* b, int* launches_per_stage);
 void dg_batch_destroy(dg_batch* b);
 

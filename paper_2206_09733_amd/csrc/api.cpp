@@ -16,6 +16,7 @@
 
 namespace dg {
 void gll_tables(int N, double* xi, double* w, double* D, double* Dh);
+void gl_tables(int N, double* xi, double* w, double* D, double* lb);
 void mortar_tables(int N, int M, double* I, double* P);
 }
 
@@ -44,6 +45,7 @@ struct dg_mesh {
   double amp;
   int N;                    // the order of a uniform mesh, the largest order of a mixed one
   bool mixed = false;
+  bool gauss = false;       // Gauss-Legendre nodes
   std::vector<int> orders;  // mixed meshes: orders[3 e + d]
 };
 
@@ -83,7 +85,7 @@ struct dg_solver {
 namespace {
 
 struct Plan {
-  size_t tab, nbr, X, Ja, J, invJ, U0, U1, dU, R, Fvf, part, diag, adapt, elem, work, mtab, Fs, self, total;
+  size_t tab, nbr, X, Ja, J, invJ, U0, U1, dU, R, Fvf, part, diag, adapt, elem, work, mtab, Fs, Tr, self, total;
   size_t tab_n, mtab_n;
 };
 
@@ -131,6 +133,7 @@ Plan make_plan(const dg_solver* s) {
   p.work = mixed ? take(sizeof(int) * E) : 0;
   p.mtab = mixed ? take(sizeof(double) * p.mtab_n) : 0;
   p.Fs = mixed ? take(sizeof(double) * dg::kMixFaceDoubles * E) : 0;
+  p.Tr = s->mesh.gauss ? take(sizeof(double) * E * 6 * 5 * nf) : 0;
   p.self = take(sizeof(dg::View));  // device copy of the View, read by batched launches
   p.total = off;
   return p;
@@ -186,6 +189,7 @@ hipError_t timed(dg_solver* s, int cls, F fn) {
 
 hipError_t launch_stage_any(dg_solver* s, double dt, double a, double b, int mode) {
   if (s->v.mixed) return dg::launch_stage_mixed(s->v, s->cur, dt, a, b, mode, s->mix_tiles, s->stream);
+  if (s->v.gauss) return dg::launch_stage_gauss(s->v, s->cur, dt, a, b, mode, s->stream);
   return dg::launch_stage(s->v, s->cur, dt, a, b, mode, s->stream);
 }
 
@@ -348,6 +352,7 @@ int dg_mesh_create_box(const dg_box_desc* d, dg_mesh** out) {
     if (!(d->hi[k] > d->lo[k])) return fail(DG_EINVAL, "box requires hi > lo in every direction");
   if (d->deform != DG_DEFORM_NONE && d->deform != DG_DEFORM_SINSIN)
     return fail(DG_EINVAL, "unknown deformation");
+  if (d->nodes != DG_NODES_LOBATTO && d->nodes != DG_NODES_GAUSS) return fail(DG_EINVAL, "unknown node set");
   const long long E = (long long)d->ex * d->ey * d->ez;
   int N = d->n_uniform;
   bool mixed = false;
@@ -375,6 +380,11 @@ int dg_mesh_create_box(const dg_box_desc* d, dg_mesh** out) {
   m->deform = d->deform;
   m->amp = d->deform_amp;
   m->mixed = mixed;
+  m->gauss = d->nodes == DG_NODES_GAUSS;
+  if (m->gauss && (mixed || d->deform != DG_DEFORM_NONE)) {
+    delete m;
+    return fail(DG_EUNSUPPORTED, "Gauss-Legendre nodes are built for undeformed uniform-order boxes");
+  }
   m->N = mixed ? nmax : N;
   if (mixed) m->orders.assign(d->orders, d->orders + 3 * E);
   *out = m;
@@ -415,6 +425,9 @@ int dg_solver_create(const dg_mesh* m, const dg_physics* p, dg_solver** out) {
                                  "central surface fluxes; the others are evaluated in FP64");
   if (m->mixed && p->Re > 0)
     return fail(DG_EUNSUPPORTED, "mixed-order meshes are evaluated for the Euler equations (Re <= 0)");
+  if (m->gauss && (p->Re > 0 || p->precision != DG_FP64 || p->vol_flux != DG_VOL_CENTRAL))
+    return fail(DG_EUNSUPPORTED, "Gauss-Legendre nodes: Euler equations (Re <= 0), FP64, volume flux "
+                                 "DG_VOL_CENTRAL (the plain weak form)");
   dg_solver* s = new dg_solver;
   s->mesh = *m;
   s->phys = *p;
@@ -488,6 +501,8 @@ int dg_solver_bind(dg_solver* s, void* dev_ptr, size_t bytes, void* hip_stream) 
   v.work = mixed ? reinterpret_cast<const int*>(b + p.work) : nullptr;
   v.mtab = mixed ? reinterpret_cast<const double*>(b + p.mtab) : nullptr;
   v.Fs = mixed ? reinterpret_cast<double*>(b + p.Fs) : nullptr;
+  v.gauss = s->mesh.gauss ? 1 : 0;
+  v.Tr = s->mesh.gauss ? reinterpret_cast<double*>(b + p.Tr) : nullptr;
   s->dev_view = reinterpret_cast<dg::View*>(b + p.self);
   s->stream = static_cast<hipStream_t>(hip_stream);
 
@@ -495,7 +510,10 @@ int dg_solver_bind(dg_solver* s, void* dev_ptr, size_t bytes, void* hip_stream) 
   std::vector<double> tab(p.tab_n);
   auto fill = [&](int N, double* t) {
     const int n = N + 1;
-    dg::gll_tables(N, t + dg::tab_xi(n), t + dg::tab_w(n), t + dg::tab_D(n), t + dg::tab_Dh(n));
+    if (s->mesh.gauss)
+      dg::gl_tables(N, t + dg::tab_xi(n), t + dg::tab_w(n), t + dg::tab_D(n), t + dg::tab_Dh(n));
+    else
+      dg::gll_tables(N, t + dg::tab_xi(n), t + dg::tab_w(n), t + dg::tab_D(n), t + dg::tab_Dh(n));
   };
   if (mixed) {
     size_t o = 0;
@@ -909,7 +927,7 @@ struct dg_batch {
   };
   std::vector<dg_solver*> m;
   std::vector<Group> groups;    // each with at most kMaxBatch members
-  std::vector<int> mixed;       // members advanced by launches of their own
+  std::vector<int> solo;        // mixed-order and Gauss-Legendre members: launches of their own
   hipStream_t stream = nullptr;
   hipStream_t cap_stream = nullptr;
   std::vector<Graph> graphs;    // most recent last
@@ -953,10 +971,11 @@ hipError_t batch_stage(dg_batch* b, const double* dts, int k, hipStream_t st) {
                                dg::kModeRK, st);
     if (e != hipSuccess) return e;
   }
-  for (int i : b->mixed) {
+  for (int i : b->solo) {
     dg_solver* s = b->m[i];
-    hipError_t e = dg::launch_stage_mixed(s->v, s->cur, dts[i], kRk[b->scheme].A[k], kRk[b->scheme].B[k],
-                                          dg::kModeRK, s->mix_tiles, st);
+    const double A = kRk[b->scheme].A[k], Bk = kRk[b->scheme].B[k];
+    hipError_t e = s->v.mixed ? dg::launch_stage_mixed(s->v, s->cur, dts[i], A, Bk, dg::kModeRK, s->mix_tiles, st)
+                              : dg::launch_stage_gauss(s->v, s->cur, dts[i], A, Bk, dg::kModeRK, st);
     if (e != hipSuccess) return e;
   }
   for (dg_solver* s : b->m) s->cur ^= 1;
@@ -1014,8 +1033,8 @@ int dg_batch_create(dg_solver* const* solvers, int n, void* hip_stream, dg_batch
   b->stream = static_cast<hipStream_t>(hip_stream);
   for (int i = 0; i < n; i++) {
     const dg_solver* s = solvers[i];
-    if (s->v.mixed) {
-      b->mixed.push_back(i);
+    if (s->v.mixed || s->v.gauss) {  // launched one by one within the batch's stages
+      b->solo.push_back(i);
       continue;
     }
     const bool fp32 = s->v.fp32 != 0, visc = s->v.viscous != 0;
@@ -1092,7 +1111,7 @@ int dg_batch_launches(const dg_batch* b, int* launches_per_stage) {
   if (!b || !launches_per_stage) return fail(DG_EINVAL, "NULL argument");
   int k = 0;
   for (const auto& g : b->groups) k += g.visc ? 2 : 1;
-  *launches_per_stage = k + (int)b->mixed.size();
+  *launches_per_stage = k + (int)b->solo.size();
   return DG_OK;
 }
 

@@ -41,6 +41,8 @@ struct View {
   double gamma, mu, kappa, Ma;
   int vol, surf, viscous, fp32;
   int visc_flux;    // 0 BR1, 1 BR2, 2 symmetric interior penalty (face viscous flux)
+  int gauss;        // Gauss-Legendre nodes: tab's Dhat slot holds l_j(-1), l_j(+1) instead
+  double* Tr;       // Gauss-Legendre: face traces [E][6][5][nf] of the state
   double visc_eta;  // BR2 lifting factor or interior-penalty factor
   double rho_r, p_r;  // FP32-bulk reference state (mean density and pressure of the state set)
   const int* nbr; // [E][6] neighbour across face f = 2 d + side (side 1: xi_d = +1)
@@ -105,6 +107,8 @@ hipError_t launch_diag_final(const View& v, hipStream_t st);  // partials -> dia
 hipError_t launch_gradient_batch(const BatchArgs& B, int N, bool fp32, bool xv, hipStream_t st);  // xv: BR2/IP
 hipError_t launch_stage_batch(const BatchArgs& B, int N, bool fp32, bool visc, int fx, double rkA, double rkB,
                               int mode, hipStream_t st);  // fx: the members' flux family
+// Gauss-Legendre nodes: face traces of U[cur], then the weak-form residual / RK stage
+hipError_t launch_stage_gauss(const View& v, int cur, double dt, double rkA, double rkB, int mode, hipStream_t st);
 // adaptive step size (uniform and mixed orders): clear adapt[], then per step reduce the wave
 // speeds of U[cur] and write the step size to adapt[0]
 hipError_t launch_adapt_reset(const View& v, hipStream_t st);

@@ -140,6 +140,44 @@ static double lagrange_at(const double* x, int n, int j, double y) {
   return lj / den;
 }
 
+// Gauss-Legendre tables of order N (n = N + 1 points): points and weights as above, the
+// barycentric derivative matrix (rows annihilate constants), and the Lagrange basis at the ends:
+// lb[j] = l_j(-1), lb[n + j] = l_j(+1).
+void gl_tables(int N, double* xi, double* w, double* D, double* lb) {
+  const int n = N + 1;
+  std::vector<double> x, wv;
+  gauss_legendre(n, x, wv);
+  for (int j = 0; j < n / 2; j++) {  // exact symmetry about 0
+    const double a = 0.5 * (x[n - 1 - j] - x[j]);
+    x[j] = -a;
+    x[n - 1 - j] = a;
+    const double ww = 0.5 * (wv[j] + wv[n - 1 - j]);
+    wv[j] = wv[n - 1 - j] = ww;
+  }
+  if (n % 2 == 1) x[n / 2] = 0.0;
+  std::vector<double> lam(n);
+  for (int j = 0; j < n; j++) {
+    double p = 1.0;
+    for (int k = 0; k < n; k++)
+      if (k != j) p *= (x[j] - x[k]);
+    lam[j] = 1.0 / p;
+  }
+  for (int i = 0; i < n; i++) {
+    xi[i] = x[i];
+    w[i] = wv[i];
+    double diag = 0.0;
+    for (int j = 0; j < n; j++) {
+      if (j == i) continue;
+      const double d = (lam[j] / lam[i]) / (x[i] - x[j]);
+      D[i * n + j] = d;
+      diag -= d;
+    }
+    D[i * n + i] = diag;
+    lb[i] = lagrange_at(x.data(), n, i, -1.0);
+    lb[n + i] = lagrange_at(x.data(), n, i, 1.0);
+  }
+}
+
 // Mortar operators between Lobatto grids of orders N < M:
 //   I[p][q] (M+1)x(N+1): value at M-node p of the order-N interpolant of the q-th basis function
 //   P[i][q] (N+1)x(M+1): L2 projection onto degree N of the q-th order-M basis function,

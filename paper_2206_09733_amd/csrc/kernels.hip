@@ -473,6 +473,7 @@ static hipError_t geometry_n(const View& v, hipStream_t st) {
   hipLaunchKernelGGL(geometry_kernel<N>, dim3(v.E), dim3(nthreads_for(N)), 0, st, v);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
+  if (v.gauss) return hipSuccess;  // no boundary nodes: nothing to make single-valued
   const long total = (long)v.E * 3 * nf;
   hipLaunchKernelGGL(facefix_kernel<N>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, v);
   return hipGetLastError();

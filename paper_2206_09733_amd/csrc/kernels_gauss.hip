@@ -1,0 +1,194 @@
+// kernels_gauss.hip -- DGSEM on Gauss-Legendre nodes, the other quadrature that section "Spatial
+// discretisation" allows: the plain weak form (no boundary nodes, so no split form), for the
+// Euler equations on undeformed uniform-order boxes, FP64.
+//
+// Two launches per RK stage.  gauss_trace_kernel interpolates each element's state to its six
+// faces, U(+-1) = sum_i l_i(+-1) U_i along the line through every face point, into
+// Tr[E][6][5][nf].  gauss_stage_kernel then forms, per node,
+//   J dU_i/dt = -[ sum_d sum_m Dw_im F~^d_m + sum_d (l_i(+1) F*(+d) - l_i(-1) F*(-d)) / w_i ],
+// Dw_im = -D_mi w_m / w_i (the quadrature of the weak derivative), F~^d = Ja^d . F(U) at the
+// nodes, and F* the numerical flux between the element's own trace and its neighbour's, both
+// read from Tr, oriented along +xi_d with the owner's metric (the element on the -xi_d side;
+// affine elements have constant metrics) as the scaled normal, so both elements evaluate the
+// same flux from the same values.  Every node of a line receives the lift of both of the
+// line's face fluxes (l_i(+-1) != 0 for all i), unlike the Lobatto form.
+#include <hip/hip_runtime.h>
+
+#include "dg_device.h"
+
+namespace dg {
+
+// the Lobatto Dhat slot of the order's table holds l_j(-1) (n values), then l_j(+1)
+__host__ __device__ constexpr int gauss_tab_ends(int n) { return 2 * n + n * n; }
+
+template <int N>
+__global__ void __launch_bounds__(nthreads_for(N)) gauss_trace_kernel(View v, int cur) {
+  constexpr int n = N + 1, nn = n * n * n, nf = n * n, NT = nthreads_for(N);
+  const int e = block_element(v.E);
+  const int t = threadIdx.x;
+  __shared__ double sU[5][nn];
+  __shared__ double sl[2][n];
+  const double* __restrict__ U = v.U[cur] + (long)e * 5 * nn;
+  for (int x = t; x < 5 * nn; x += NT) sU[x / nn][x % nn] = U[x];
+  if (t < 2 * n) sl[t / n][t % n] = v.tab[gauss_tab_ends(n) + t];
+  __syncthreads();
+  double* __restrict__ Tr = v.Tr + (long)e * 6 * 5 * nf;
+  for (int x = t; x < 6 * nf; x += NT) {
+    const int f = x / nf, q = x - f * nf;
+    const int d = f >> 1, side = f & 1;
+    const int p = q % n, r = q / n;
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < n; i++) {
+      const int node = face_node<n>(d, i, p, r);
+      const double l = sl[side][i];
+#pragma unroll
+      for (int c = 0; c < 5; c++) acc[c] += l * sU[c][node];
+    }
+#pragma unroll
+    for (int c = 0; c < 5; c++) Tr[(f * 5 + c) * nf + q] = acc[c];
+  }
+}
+
+// Euler flux of the conservative state u along the (not normalised) vector s
+__device__ __forceinline__ void euler_flux_along(const double u[5], double gamma, double s1, double s2, double s3,
+                                                 double F[5]) {
+  const double i = 1.0 / u[0];
+  const double v1 = u[1] * i, v2 = u[2] * i, v3 = u[3] * i;
+  const double p = (gamma - 1.0) * (u[4] - 0.5 * u[0] * (v1 * v1 + v2 * v2 + v3 * v3));
+  const double vn = v1 * s1 + v2 * s2 + v3 * s3;
+  F[0] = u[0] * vn;
+  F[1] = u[1] * vn + p * s1;
+  F[2] = u[2] * vn + p * s2;
+  F[3] = u[3] * vn + p * s3;
+  F[4] = (u[4] + p) * vn;
+}
+
+// XS: the extended surface fluxes (codes >= 4), compiled apart
+template <int N, bool XS>
+__global__ void __launch_bounds__(nthreads_for(N))
+    gauss_stage_kernel(View v, int cur, double dt, double rkA, double rkB, int mode) {
+  constexpr int n = N + 1, nn = n * n * n, nf = n * n, NT = nthreads_for(N);
+  const int e = block_element(v.E);
+  const int t = threadIdx.x;
+  const bool act = t < nn;
+  const int ti = t % n, tj = (t / n) % n, tk = t / nf;
+  __shared__ double sDw[n * n], sw[n], sl[2][n];
+  __shared__ double sF[5][nn];      // contravariant flux of one direction
+  __shared__ double sFs[6][5][nf];  // numerical flux on the six faces
+  for (int x = t; x < n * n; x += NT) {
+    const int i = x / n, m = x - i * n;
+    sDw[x] = -v.tab[2 * n + m * n + i] * v.tab[n + m] / v.tab[n + i];
+  }
+  if (t < n) sw[t] = v.tab[n + t];
+  if (t < 2 * n) sl[t / n][t % n] = v.tab[gauss_tab_ends(n) + t];
+  const long base = (long)e * nn;
+  const double* __restrict__ Uin = v.U[cur];
+  double u[5], ja[9], ij = 0.0;
+  if (act) {
+#pragma unroll
+    for (int c = 0; c < 5; c++) u[c] = Uin[base * 5 + c * nn + t];
+#pragma unroll
+    for (int c = 0; c < 9; c++) ja[c] = v.Ja[base * 9 + c * nn + t];
+    ij = v.invJ[base + t];
+  }
+  // numerical fluxes on the faces, from the traces of both sides
+  for (int x = t; x < 6 * nf; x += NT) {
+    const int f = x / nf, q = x - f * nf;
+    const int d = f >> 1, side = f & 1;
+    const int ne = v.nbr[e * 6 + f];
+    const double* To = v.Tr + ((long)e * 6 + f) * 5 * nf;
+    const double* Tn = v.Tr + ((long)ne * 6 + (f ^ 1)) * 5 * nf;
+    double uL[5], uR[5], S[3];
+#pragma unroll
+    for (int c = 0; c < 5; c++) {
+      const double a = To[c * nf + q], b = Tn[c * nf + q];
+      uL[c] = side ? a : b;
+      uR[c] = side ? b : a;
+    }
+    const long owner = side ? e : ne;
+#pragma unroll
+    for (int c = 0; c < 3; c++) S[c] = v.Ja[owner * nn * 9 + (3 * d + c) * nn];
+    double F[5];
+    face_flux<double, XS>(v.surf, uL, uR, S, v.gamma, F);
+#pragma unroll
+    for (int c = 0; c < 5; c++) sFs[f][c][q] = F[c];
+  }
+  // volume: sum_m Dw_im F~^d_m along each direction's line
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  const int ii[3] = {ti, tj, tk};
+#pragma unroll
+  for (int d = 0; d < 3; d++) {
+    __syncthreads();  // sF free again (and, at d = 0, the tables staged)
+    if (act) {
+      double F[5];
+      euler_flux_along(u, v.gamma, ja[3 * d], ja[3 * d + 1], ja[3 * d + 2], F);
+#pragma unroll
+      for (int c = 0; c < 5; c++) sF[c][t] = F[c];
+    }
+    __syncthreads();
+    if (act) {
+      const int id = ii[d];
+      const int stride = d == 0 ? 1 : (d == 1 ? n : nf);
+      const int b0 = t - id * stride;
+#pragma unroll
+      for (int m = 0; m < n; m++) {
+        const double Dm = sDw[id * n + m];
+#pragma unroll
+        for (int c = 0; c < 5; c++) acc[c] += Dm * sF[c][b0 + m * stride];
+      }
+    }
+  }
+  if (!act) return;
+  // lift of the two face fluxes of each of the node's lines
+#pragma unroll
+  for (int d = 0; d < 3; d++) {
+    const int id = ii[d];
+    const int qd = d == 0 ? tj + n * tk : (d == 1 ? ti + n * tk : ti + n * tj);
+    const double lp = sl[1][id] / sw[id], lm = sl[0][id] / sw[id];
+#pragma unroll
+    for (int c = 0; c < 5; c++) acc[c] += lp * sFs[2 * d + 1][c][qd] - lm * sFs[2 * d][c][qd];
+  }
+  const long o = base * 5 + t;
+  if (mode == kModeResidual) {
+#pragma unroll
+    for (int c = 0; c < 5; c++) v.R[o + c * nn] = -acc[c] * ij;
+    return;
+  }
+  const double h = v.dtp ? *v.dtp : dt;
+  double* __restrict__ Uout = v.U[cur ^ 1];
+#pragma unroll
+  for (int c = 0; c < 5; c++) {
+    const double du = (rkA == 0.0 ? 0.0 : rkA * v.dU[o + c * nn]) + h * (-acc[c] * ij);
+    v.dU[o + c * nn] = du;
+    Uout[o + c * nn] = Uin[o + c * nn] + rkB * du;
+  }
+}
+
+template <int N>
+static hipError_t gauss_stage_n(const View& v, int cur, double dt, double a, double b, int mode, hipStream_t st) {
+  hipLaunchKernelGGL(gauss_trace_kernel<N>, dim3(v.E), dim3(nthreads_for(N)), 0, st, v, cur);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  if (v.surf >= 4)
+    hipLaunchKernelGGL((gauss_stage_kernel<N, true>), dim3(v.E), dim3(nthreads_for(N)), 0, st, v, cur, dt, a, b, mode);
+  else
+    hipLaunchKernelGGL((gauss_stage_kernel<N, false>), dim3(v.E), dim3(nthreads_for(N)), 0, st, v, cur, dt, a, b, mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_stage_gauss(const View& v, int cur, double dt, double rkA, double rkB, int mode, hipStream_t st) {
+  if (!v.gauss || !v.Tr) return hipErrorInvalidValue;
+  switch (v.N) {
+    case 1: return gauss_stage_n<1>(v, cur, dt, rkA, rkB, mode, st);
+    case 2: return gauss_stage_n<2>(v, cur, dt, rkA, rkB, mode, st);
+    case 3: return gauss_stage_n<3>(v, cur, dt, rkA, rkB, mode, st);
+    case 4: return gauss_stage_n<4>(v, cur, dt, rkA, rkB, mode, st);
+    case 5: return gauss_stage_n<5>(v, cur, dt, rkA, rkB, mode, st);
+    case 6: return gauss_stage_n<6>(v, cur, dt, rkA, rkB, mode, st);
+    case 7: return gauss_stage_n<7>(v, cur, dt, rkA, rkB, mode, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace dg

@@ -29,7 +29,7 @@ _dp = _c.POINTER(_c.c_double)
 class BoxDesc(_c.Structure):
     _fields_ = [("ex", _c.c_int), ("ey", _c.c_int), ("ez", _c.c_int), ("lo", _c.c_double * 3),
                 ("hi", _c.c_double * 3), ("deform", _c.c_int), ("deform_amp", _c.c_double),
-                ("n_uniform", _c.c_int), ("orders", _c.POINTER(_c.c_int))]
+                ("n_uniform", _c.c_int), ("orders", _c.POINTER(_c.c_int)), ("nodes", _c.c_int)]
 
 
 class Physics(_c.Structure):
@@ -131,8 +131,12 @@ def _ptr(a):
     return a.ctypes.data_as(_dp)
 
 
-def box_desc(ex, ey, ez, lo, hi, deform, amp, N, orders=None):
+NODES = {"lobatto": 0, "gauss": 1}
+
+
+def box_desc(ex, ey, ez, lo, hi, deform, amp, N, orders=None, nodes="lobatto"):
     d = BoxDesc()
+    d.nodes = NODES[nodes]
     d.ex, d.ey, d.ez = ex, ey, ez
     d.lo[:] = list(lo)
     d.hi[:] = list(hi)
@@ -164,7 +168,7 @@ class Solver:
 
     def __init__(self, ex, ey=None, ez=None, lo=(0.0, 0.0, 0.0), hi=None, deform=False, amp=0.05,
                  N=3, gamma=1.4, Pr=0.71, Ma=0.1, Re=0.0, vol="ec", surf="roe", precision="fp64",
-                 device="cuda", bind=True, orders=None, visc="br1", visc_eta=0.0):
+                 device="cuda", bind=True, orders=None, visc="br1", visc_eta=0.0, nodes="lobatto"):
         L = lib()
         ey = ex if ey is None else ey
         ez = ex if ez is None else ez
@@ -174,7 +178,7 @@ class Solver:
         self.gamma, self.Pr, self.Ma, self.Re = gamma, Pr, Ma, Re
         self.h = None
         self.buf = None
-        d, _keep = box_desc(ex, ey, ez, lo, hi, deform, amp, N, orders)
+        d, _keep = box_desc(ex, ey, ez, lo, hi, deform, amp, N, orders, nodes)
         mesh = _c.c_void_p()
         check(L.dg_mesh_create_box(_c.byref(d), _c.byref(mesh)))
         try:
