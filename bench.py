@@ -105,7 +105,6 @@ def run_adaptive(steps, warmup, fixed_ms):
     """The same workload with the step size chosen on the device before every step (CFL 0.5):
     wall time of one dg_rk_step_adaptive call of `steps` steps (it synchronises once, at the end),
     against the fixed-step time per step."""
-    import time
     from paper_2206_09733_amd import dgsem
     s = dgsem.Solver(**WORKLOAD)
     s.set_ic("tgv")
@@ -120,6 +119,30 @@ def run_adaptive(steps, warmup, fixed_ms):
     return {"ms_per_step": round(ms, 4), "steps": steps, "simulated_time": t_sim,
             "overhead_vs_fixed_pct": round(100.0 * (ms / fixed_ms - 1.0), 2),
             "state_finite": d["nonfinite"] == 0}
+
+
+def run_gauss(steps, warmup):
+    """Euler TGV on the undeformed 32^3 box at N=4 on Gauss-Legendre points (the plain weak form:
+    a face-trace kernel and the stage kernel per RK stage), against the same mesh on Lobatto
+    points with the central volume form."""
+    from paper_2206_09733_amd import dgsem
+    out = {"workload": "Euler Taylor-Green vortex Ma 0.1, 32^3 hex undeformed, N=4, Roe faces, RK3 CFL 0.5, "
+                       "plain (central) volume form"}
+    for nodes in ("gauss", "lobatto"):
+        s = dgsem.Solver(ex=32, N=4, Ma=0.1, vol="central", surf="roe", nodes=nodes)
+        s.set_ic("tgv")
+        dt = s.suggest_dt(0.5)
+        s.rk_step(dt, warmup)
+        ev_ms, _, _ = timed_steps(s, dt, steps, profile=False)
+        _, _, prof = timed_steps(s, dt, max(2, steps // 5))
+        d = s.diagnostics()
+        st = prof["stage"]
+        out[nodes] = {"value": round(5 * s.nodes * 3 * steps / (ev_ms / 1e3) / 1e9, 3), "unit": "GDOF/s",
+                      "ms_per_step": round(ev_ms / steps, 4),
+                      "stage_launch_pair_avg_us": round(st["ms"] / st["launches"] * 1e3, 2),
+                      "state_finite": d["nonfinite"] == 0}
+        s.close()
+    return out
 
 
 MIXED = dict(ex=24, lo=(-10.0,) * 3, hi=(10.0,) * 3, Ma=0.5, vol="ec", surf="roe")
@@ -375,6 +398,7 @@ def main():
         "value": round(5 * nodes * 5 * max(10, args.steps // 5) / (r4["event_ms"] / 1e3) / 1e9, 3),
         "unit": "GDOF-updates/s per RK stage"}
     result["adaptive_dt"] = run_adaptive(args.steps, args.warmup, r64["event_ms"] / args.steps)
+    result["gauss_legendre_nodes"] = run_gauss(max(10, args.steps // 2), args.warmup)
     if not args.skip_mixed:
         result["mixed_order"] = run_mixed(max(10, args.steps // 2), args.warmup)
     if not args.skip_large:
