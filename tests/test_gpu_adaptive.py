@@ -1,8 +1,9 @@
 """Adaptive step size chosen on the device (dg_rk_step_adaptive).
 
 - A step equals dg_rk_step with dg_suggest_dt of the same state, bit for bit, for uniform
-  (Euler and Navier-Stokes, RK3 and RK4) and mixed orders, with graph replay on and off, and the
-  time advanced is the sum of those step sizes.
+  orders (Euler and Navier-Stokes, RK3 and RK4, FP32-bulk, the interior-penalty viscous flux,
+  an extended flux family) and mixed orders, with graph replay on and off, and the time advanced
+  is the sum of those step sizes.
 - Against the oracle: the oracle takes its own suggested step before every step; the GPU
   trajectory lies within the parity bar of the long-double oracle's.
 - A state that blows up is reported (DG_ENONFINITE) instead of being advanced further.
@@ -37,6 +38,9 @@ CASES = {
     "euler_n3": (dict(ex=3, ey=2, ez=4, N=3, Ma=0.3, deform=True), "tgv", None),
     "ns_n4": (dict(ex=3, N=4, Ma=0.2, Re=400.0, deform=True), "tgv", None),
     "ns_n4_rk4": (dict(ex=3, N=4, Ma=0.2, Re=400.0, deform=True), "tgv", "rk4"),
+    "ns_n4_fp32_bulk": (dict(ex=3, N=4, Ma=0.2, Re=400.0, deform=True, precision="fp32_bulk"), "tgv", None),
+    "ns_n3_ip": (dict(ex=3, N=3, Ma=0.2, Re=400.0, deform=True, visc="ip"), "tgv", None),
+    "euler_n4_kep_esm": (dict(ex=3, N=4, Ma=0.3, deform=True, vol="pirozzoli", surf="es_matrix"), "tgv", None),
     "mixed": (dict(ex=3, ey=3, ez=2, orders=synth.mixed_orders(18, seed=4), Ma=0.5, lo=(-10.0,) * 3,
                    hi=(10.0,) * 3), "vortex", None),
 }
