@@ -11,7 +11,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 VOL = {"ec": 0, "central": 1, "ir": 2, "kg": 3, "pirozzoli": 4, "ducros": 5, "morinishi": 6}
-SURF = {"roe": 0, "llf": 1, "ec": 2, "central": 3, "es": 4, "ir": 5, "es_matrix": 6, "ld_roe": 7}
+SURF = {"roe": 0, "llf": 1, "ec": 2, "central": 3, "es": 4, "ir": 5, "es_matrix": 6, "ld_roe": 7,
+        "lf_global": 8}
 VISC = {"br1": 0, "br2": 1, "ip": 2}
 IC = {"uniform": 0, "tgv": 1, "vortex": 2, "density_wave": 3}
 DIAG_KEYS = ["mass_rho", "mass_rhou", "mass_rhov", "mass_rhow", "mass_rhoE", "entropy_paper",
@@ -66,6 +67,7 @@ def _lib(precision="fp64"):
         L.orc_two_point_ir.argtypes = [_dp, _dp, _dp, ctypes.c_double, _dp]
         L.orc_two_point.argtypes = [ctypes.c_int, _dp, _dp, _dp, ctypes.c_double, _dp]
         L.orc_riemann.argtypes = [ctypes.c_int, _dp, _dp, _dp, ctypes.c_double, _dp]
+        L.orc_lax_friedrichs.argtypes = [_dp, _dp, _dp, ctypes.c_double, ctypes.c_double, _dp]
         L.orc_roe_waves.argtypes = [_dp, _dp, _dp, ctypes.c_double, ctypes.c_int, _dp]
         L.orc_entropy_vars.argtypes = [_dp, ctypes.c_double, _dp]
         L.orc_entropy.restype = ctypes.c_double
@@ -156,6 +158,13 @@ def riemann(kind, UL, UR, S, gamma=1.4, precision="fp64"):
     res = np.zeros(5)
     _lib(precision).orc_riemann(SURF[kind], _ptr(_f64(UL)), _ptr(_f64(UR)), _ptr(_f64(S)),
                                 gamma, _ptr(res))
+    return res
+
+
+def lax_friedrichs(UL, UR, S, lam, gamma=1.4, precision="fp64"):
+    res = np.zeros(5)
+    _lib(precision).orc_lax_friedrichs(_ptr(_f64(UL)), _ptr(_f64(UR)), _ptr(_f64(S)), gamma, float(lam),
+                                       _ptr(res))
     return res
 
 

@@ -328,6 +328,7 @@ struct orc_solver {
   int vol, surf, viscous;
   int visc_flux;   /* ORC_VISC_BR1 / BR2 / IP */
   int gauss;       /* Gauss-Legendre nodes (weak form) instead of Gauss-Lobatto */
+  real lam_g;      /* global Lax-Friedrichs: max |v| + c of the state being evaluated */
   const gll_t* T;  /* the node tables of this solver: GLL or GL */
   real visc_eta;   /* BR2 lifting factor, or interior-penalty factor */
   real *X, *Ja, *J; /* coordinates, metric terms, Jacobian */
@@ -469,7 +470,7 @@ static orc_solver* create(int ex, int ey, int ez, const double* lo, const double
                           int n_uniform, const int* orders, double gamma, double Pr, double Ma, double Re,
                           int vol_flux, int surf_flux, int gauss) {
   if (ex < 1 || ey < 1 || ez < 1 || !lo || !hi) return NULL;
-  if (vol_flux < 0 || vol_flux > ORC_VOL_MORINISHI || surf_flux < 0 || surf_flux > ORC_SURF_LOW_DISS_ROE) return NULL;
+  if (vol_flux < 0 || vol_flux > ORC_VOL_MORINISHI || surf_flux < 0 || surf_flux > ORC_SURF_LF_GLOBAL) return NULL;
   gll_init();
   orc_solver* s = (orc_solver*)calloc(1, sizeof(orc_solver));
   s->gauss = gauss;
@@ -870,6 +871,22 @@ static void riemann(int kind, const real uL[5], const real uR[5], const real S[3
   }
 }
 
+/* Lax-Friedrichs with a given wave speed lam: {F} . S - lam |S| (U_R - U_L) / 2 */
+static void lax_friedrichs(const real uL[5], const real uR[5], const real S[3], real gamma, real lam, real F[5]) {
+  real a = RSQRT(S[0] * S[0] + S[1] * S[1] + S[2] * S[2]);
+  real FL[5], FR[5];
+  euler_flux(uL, S, gamma, FL);
+  euler_flux(uR, S, gamma, FR);
+  for (int v = 0; v < 5; v++) F[v] = (FL[v] + FR[v]) / 2 - a * lam * (uR[v] - uL[v]) / 2;
+}
+
+/* the solver's surface flux: Lax-Friedrichs (global) takes the state's largest wave speed,
+ * every other flux only the two traces */
+static void surface_flux(const orc_solver* s, const real uL[5], const real uR[5], const real S[3], real F[5]) {
+  if (s->surf == ORC_SURF_LF_GLOBAL) lax_friedrichs(uL, uR, S, s->gamma, s->lam_g, F);
+  else riemann(s->surf, uL, uR, S, s->gamma, F);
+}
+
 static void volume_flux(const orc_solver* s, const real uL[5], const real uR[5], const real n[3], real F[5]) {
   if (s->vol == ORC_VOL_EC) two_point_ec(uL, uR, n, s->gamma, F);
   else if (s->vol == ORC_VOL_IR) two_point_ir(uL, uR, n, s->gamma, F);
@@ -931,7 +948,7 @@ static void face_flux_side(const orc_solver* s, const real* U, int L, int d, int
         load5(s, U, L, node_of(s, L, iL), uL);
         load5(s, U, R, node_of(s, R, iR), uR);
         load_ja(s, L, node_of(s, L, iL), d, S);
-        riemann(s->surf, uL, uR, S, s->gamma, Fp);
+        surface_flux(s, uL, uR, S, Fp);
         for (int v = 0; v < 5; v++) F[v * nf + p + na * r] = Fp[v];
       }
     return;
@@ -963,7 +980,7 @@ static void face_flux_side(const orc_solver* s, const real* U, int L, int d, int
           for (int v = 0; v < 5; v++) uR[v] += w * u[v];
         }
       real Fp[5];
-      riemann(s->surf, uL, uR, S, s->gamma, Fp);
+      surface_flux(s, uL, uR, S, Fp);
       for (int v = 0; v < 5; v++) Fm[v * nma * nmb + pm + nma * rm] = Fp[v];
     }
   for (int r = 0; r < nb; r++)
@@ -1274,7 +1291,7 @@ static void element_residual_gauss(const orc_solver* s, const real* U, int e, re
             for (int c = 0; c < 3; c++) S[c] += T->lb[1][i] * ja[c];
           }
           real F[5];
-          riemann(s->surf, uL, uR, S, s->gamma, F);
+          surface_flux(s, uL, uR, S, F);
           for (int v = 0; v < 5; v++) Ff[2 * d + side][v][p + n * r] = F[v];
         }
     }
@@ -1309,6 +1326,21 @@ static void element_residual_gauss(const orc_solver* s, const real* U, int e, re
 }
 
 static void residual(orc_solver* s, const real* U, real* R) {
+  if (s->surf == ORC_SURF_LF_GLOBAL) {
+    /* the largest |v| + c over the nodes of the state the residual is taken of */
+    real lam = 0;
+    for (int e = 0; e < s->E; e++) {
+      int nn = nn_of(s, e);
+      for (int q = 0; q < nn; q++) {
+        real u[5];
+        load5(s, U, e, q, u);
+        prim_t w = prim(u, s->gamma);
+        real l = RSQRT(w.v[0] * w.v[0] + w.v[1] * w.v[1] + w.v[2] * w.v[2]) + RSQRT(s->gamma * w.p / w.rho);
+        if (l > lam) lam = l;
+      }
+    }
+    s->lam_g = lam;
+  }
   if (s->gauss) {
 #pragma omp parallel for schedule(dynamic, 4)
     for (int e = 0; e < s->E; e++) element_residual_gauss(s, U, e, R + s->off[e] * 5);
@@ -1628,6 +1660,13 @@ int orc_two_point(int vol_kind, const double* UL, const double* UR, const double
   else if (vol_kind == ORC_VOL_IR) two_point_ir(a, b, nn, gamma, f);
   else if (vol_kind == ORC_VOL_CENTRAL) two_point_central(a, b, nn, gamma, f);
   else two_point_kep(vol_kind, a, b, nn, gamma, f);
+  to_dbl(f, F, 5);
+  return 0;
+}
+int orc_lax_friedrichs(const double* UL, const double* UR, const double* S, double gamma, double lam, double* F) {
+  real a[5], b[5], nn[3], f[5];
+  to_real(UL, a, 5); to_real(UR, b, 5); to_real(S, nn, 3);
+  lax_friedrichs(a, b, nn, gamma, lam, f);
   to_dbl(f, F, 5);
   return 0;
 }

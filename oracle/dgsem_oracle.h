@@ -32,7 +32,7 @@ extern "C" {
 enum { ORC_VOL_EC = 0, ORC_VOL_CENTRAL = 1, ORC_VOL_IR = 2, ORC_VOL_KG = 3, ORC_VOL_PIROZZOLI = 4,
        ORC_VOL_DUCROS = 5, ORC_VOL_MORINISHI = 6 };
 enum { ORC_SURF_ROE = 0, ORC_SURF_LLF = 1, ORC_SURF_EC = 2, ORC_SURF_CENTRAL = 3, ORC_SURF_ES = 4, ORC_SURF_IR = 5,
-       ORC_SURF_ES_MATRIX = 6, ORC_SURF_LOW_DISS_ROE = 7 };
+       ORC_SURF_ES_MATRIX = 6, ORC_SURF_LOW_DISS_ROE = 7, ORC_SURF_LF_GLOBAL = 8 };
 enum { ORC_VISC_BR1 = 0, ORC_VISC_BR2 = 1, ORC_VISC_IP = 2 };
 enum { ORC_IC_UNIFORM = 0, ORC_IC_TGV = 1, ORC_IC_VORTEX = 2, ORC_IC_DENSITY_WAVE = 3 };
 
@@ -86,6 +86,8 @@ int orc_two_point_ir(const double* UL, const double* UR, const double* n, double
 int orc_two_point_central(const double* UL, const double* UR, const double* n, double gamma, double* F);
 int orc_two_point(int vol_kind, const double* UL, const double* UR, const double* n, double gamma, double* F);
 int orc_riemann(int kind, const double* UL, const double* UR, const double* S, double gamma, double* F);
+/* Lax-Friedrichs with a given (global) wave speed lam. */
+int orc_lax_friedrichs(const double* UL, const double* UR, const double* S, double gamma, double lam, double* F);
 int orc_roe_waves(const double* UL, const double* UR, const double* nhat, double gamma, int absval,
                   double* W);
 int orc_entropy_vars(const double* U, double gamma, double* w);

@@ -387,6 +387,49 @@ def test_low_dissipation_roe(orc):
                                z * (orc.riemann("roe", uL, uR, n) - cen), rtol=1e-12, atol=1e-15)
 
 
+def test_global_lax_friedrichs_residual_closed_form(orc):
+    """Lax-Friedrichs with the global wave speed (the convective-flux list names Lax-Friedrichs
+    beside Rusanov, the local one).  It is the central flux minus lambda_g |S| (U_R - U_L)/2 with
+    lambda_g = max |v| + c over the state, so on an affine mesh the residual differs from the
+    central one only at face nodes, by lambda_g |S| (U_nb - U_own) / (2 w J) per face through the
+    node; lambda_g is taken here from the state with numpy."""
+    N, ex = 3, 2
+    n = N + 1
+    c = dict(ex=ex, ey=ex, ez=ex, N=N, vol="central", Ma=0.5)
+    sc = orc.OracleSolver(**c, surf="central")
+    sc.set_ic("tgv")
+    U0 = sc.state()
+    Un = U0.reshape(sc.E, 5, -1).transpose(0, 2, 1).reshape(-1, 5)
+    drho, dv, dp = synth.primitive_perturbation(sc.nodes, seed=23, amp=(0.05, 0.1, 0.05))
+    rho = Un[:, 0] * (1 + drho)
+    v = Un[:, 1:4] / Un[:, :1] + dv.T
+    p = 0.4 * (Un[:, 4] - 0.5 * (Un[:, 1:4] ** 2).sum(1) / Un[:, 0]) * (1 + dp)
+    Uf = to_conservative(rho, v, p)
+    lam = (np.linalg.norm(v, axis=1) + np.sqrt(GAMMA * p / rho)).max()
+    U = Uf.reshape(sc.E, -1, 5).transpose(0, 2, 1).reshape(-1)
+    sc.set_state(U)
+    sl = orc.OracleSolver(**c, surf="lf_global")
+    sl.set_state(U)
+    diff = (sl.residual() - sc.residual()).reshape(ex, ex, ex, 5, n, n, n)  # [c][b][a][v][k][j][i]
+    Ue = U.reshape(ex, ex, ex, 5, n, n, n)
+    _, w, _ = orc.gll(N)
+    h = 2 * math.pi / ex
+    area, J = (h / 2) ** 2, (h / 2) ** 3
+    expect = np.zeros_like(diff)
+    for eax, nax in [(2, 6), (1, 5), (0, 4)]:
+        for side, at, nb_at, shift in ((1, N, 0, -1), (0, 0, N, 1)):
+            own = np.take(Ue, [at], axis=nax)
+            nb = np.roll(np.take(Ue, [nb_at], axis=nax), shift, axis=eax)
+            sl_ = [slice(None)] * 7
+            sl_[nax] = slice(at, at + 1)
+            expect[tuple(sl_)] += lam * area * (nb - own) / (2 * w[at] * J)
+    assert np.abs(diff - expect).max() < 1e-11 * np.abs(expect).max(), np.abs(diff - expect).max()
+    # point form: the dissipation is lambda |S| (U_R - U_L)/2 exactly
+    uL, uR, S = Uf[0], Uf[1], np.array([0.3, -0.2, 0.9])
+    np.testing.assert_allclose(orc.lax_friedrichs(uL, uR, S, 2.5) - orc.two_point_central(uL, uR, S),
+                               -0.5 * 2.5 * np.linalg.norm(S) * (uR - uL), rtol=1e-12, atol=1e-14)
+
+
 def test_central_flux(orc):
     UL, UR, nv = _pairs(50)
     for uL, uR, n in zip(UL, UR, nv):
@@ -565,7 +608,8 @@ def _conservation_sums(orc, s, R, N):
 
 @pytest.mark.parametrize("surf,vol", [("roe", "ec"), ("llf", "ec"), ("ec", "ec"), ("es", "ec"), ("ir", "ir"),
                                       ("roe", "ir"), ("es_matrix", "ec"), ("ld_roe", "kg"),
-                                      ("roe", "pirozzoli"), ("llf", "ducros"), ("central", "morinishi")])
+                                      ("roe", "pirozzoli"), ("llf", "ducros"), ("central", "morinishi"),
+                                      ("lf_global", "ec")])
 @pytest.mark.parametrize("Re", [0.0, 400.0])
 def test_conservation_of_totals(orc, surf, vol, Re):
     """Periodic box, single-valued face fluxes: sum over nodes of w J dU/dt vanishes for every
