@@ -72,10 +72,12 @@ enum { DG_VOL_EC = 0, DG_VOL_CENTRAL = 1, DG_VOL_IR = 2, DG_VOL_KENNEDY_GRUBER =
  * Chandrashekar's EC flux, central, entropy stable (Chandrashekar's flux minus local
  * Lax-Friedrichs dissipation), Ismail-Roe, entropy stable with matrix dissipation
  * (Chandrashekar's flux minus R|Lambda|T R^T times the jump of the entropy variables),
- * low-dissipation Roe (the velocity jump scaled by the larger local Mach number, at most 1).
+ * low-dissipation Roe (the velocity jump scaled by the larger local Mach number, at most 1),
+ * Lax-Friedrichs with the global wave speed (the largest |v| + c of the stage's state, reduced
+ * on the device before each stage; DG_SURF_LLF is the local form, Rusanov).
  * Only DG_VOL_EC / DG_VOL_CENTRAL and the first four surface fluxes have an FP32-bulk form. */
 enum { DG_SURF_ROE = 0, DG_SURF_LLF = 1, DG_SURF_EC = 2, DG_SURF_CENTRAL = 3, DG_SURF_ES = 4, DG_SURF_IR = 5,
-       DG_SURF_ES_MATRIX = 6, DG_SURF_LOW_DISS_ROE = 7 };
+       DG_SURF_ES_MATRIX = 6, DG_SURF_LOW_DISS_ROE = 7, DG_SURF_LF_GLOBAL = 8 };
 /* precision: all-FP64, or FP32 flux/derivative arithmetic with FP64 metrics, RK state and
  * reductions */
 enum { DG_FP64 = 0, DG_FP32_BULK = 1 };

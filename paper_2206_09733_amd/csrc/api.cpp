@@ -193,7 +193,17 @@ hipError_t launch_stage_any(dg_solver* s, double dt, double a, double b, int mod
   return dg::launch_stage(s->v, s->cur, dt, a, b, mode, s->stream);
 }
 
+// work a stage needs before its kernels: the global wave speed for Lax-Friedrichs (global)
+hipError_t pre_stage(const dg_solver* s, int cur, hipStream_t st) {
+  if (s->v.surf == DG_SURF_LF_GLOBAL) return dg::launch_lambda_max(s->v, cur, st);
+  return hipSuccess;
+}
+
 hipError_t run_stage(dg_solver* s, double dt, double a, double b, int mode) {
+  if (s->v.surf == DG_SURF_LF_GLOBAL) {
+    hipError_t e = timed(s, DG_K_OTHER, [&] { return pre_stage(s, s->cur, s->stream); });
+    if (e != hipSuccess) return e;
+  }
   if (s->v.viscous) {
     hipError_t e = timed(s, DG_K_GRADIENT, [&] { return dg::launch_gradient(s->v, s->cur, s->stream); });
     if (e != hipSuccess) return e;
@@ -414,7 +424,7 @@ int dg_solver_create(const dg_mesh* m, const dg_physics* p, dg_solver** out) {
   if (p->Re > 0 && !(p->Pr > 0)) return fail(DG_EINVAL, "Pr must be positive");
   if (!(p->Ma > 0)) return fail(DG_EINVAL, "Ma must be positive");
   if (p->vol_flux < DG_VOL_EC || p->vol_flux > DG_VOL_MORINISHI) return fail(DG_EINVAL, "unknown volume flux");
-  if (p->surf_flux < DG_SURF_ROE || p->surf_flux > DG_SURF_LOW_DISS_ROE)
+  if (p->surf_flux < DG_SURF_ROE || p->surf_flux > DG_SURF_LF_GLOBAL)
     return fail(DG_EINVAL, "unknown surface flux");
   if (p->precision != DG_FP64 && p->precision != DG_FP32_BULK) return fail(DG_EINVAL, "unknown precision");
   if (p->visc_flux < DG_VISC_BR1 || p->visc_flux > DG_VISC_IP) return fail(DG_EINVAL, "unknown viscous flux");
@@ -950,6 +960,10 @@ void batch_drop_graphs(dg_batch* b) {
 // one RK stage of every member on stream st; afterwards every member's state has moved to its
 // other buffer
 hipError_t batch_stage(dg_batch* b, const double* dts, int k, hipStream_t st) {
+  for (dg_solver* s : b->m) {
+    hipError_t e = pre_stage(s, s->cur, st);
+    if (e != hipSuccess) return e;
+  }
   for (const auto& g : b->groups) {
     dg::BatchArgs B;
     std::memset(&B, 0, sizeof(B));

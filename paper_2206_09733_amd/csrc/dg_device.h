@@ -406,10 +406,20 @@ __device__ __forceinline__ void matrix_dissipation(const Prim<T>& a, const Prim<
 
 // The extended surface fluxes: entropy stable (4: Chandrashekar's flux minus local
 // Lax-Friedrichs dissipation), Ismail-Roe (5), entropy stable with matrix dissipation (6:
-// Chandrashekar's flux minus the dissipation above), low-dissipation Roe (7).
+// Chandrashekar's flux minus the dissipation above), low-dissipation Roe (7), Lax-Friedrichs with
+// the global wave speed lam_g (8: the central flux minus lam_g |S| (U_R - U_L) / 2).
 template <typename T>
 __device__ __forceinline__ void face_flux_xs(int kind, const double uL[5], const double uR[5],
-                                             const double S[3], double gamma, T F[5]) {
+                                             const double S[3], double gamma, T F[5], double lam_g) {
+  if (kind == 8) {
+    face_flux_std<T>(3, uL, uR, S, gamma, F);
+    const T s1 = (T)S[0], s2 = (T)S[1], s3 = (T)S[2];
+    const T a2s = s1 * s1 + s2 * s2 + s3 * s3;
+    const T area = a2s * rsq(a2s);
+#pragma unroll
+    for (int c = 0; c < 5; c++) F[c] -= (T)0.5 * area * (T)lam_g * (T)(uR[c] - uL[c]);
+    return;
+  }
   if (kind == 7) {
     face_flux_std<T, true>(0, uL, uR, S, gamma, F);
     return;
@@ -453,8 +463,8 @@ __device__ __forceinline__ void face_flux_xs(int kind, const double uL[5], const
 // XS selects the family: the two are compiled apart so that the common one keeps its registers
 template <typename T, bool XS = false>
 __device__ __forceinline__ void face_flux(int kind, const double uL[5], const double uR[5],
-                                          const double S[3], double gamma, T F[5]) {
-  if constexpr (XS) face_flux_xs<T>(kind, uL, uR, S, gamma, F);
+                                          const double S[3], double gamma, T F[5], double lam_g = 0.0) {
+  if constexpr (XS) face_flux_xs<T>(kind, uL, uR, S, gamma, F, lam_g);
   else face_flux_std<T>(kind, uL, uR, S, gamma, F);
 }
 

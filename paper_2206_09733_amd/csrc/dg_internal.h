@@ -59,7 +59,8 @@ struct View {
   double* diag;   // final diagnostics [kDiagSlots]
   // adaptive step size: while dtp is set the stage kernels take the step size from *dtp (written
   // on the device by dt_kernel) instead of their dt argument; adapt[0] the step size,
-  // adapt[1] the time advanced, adapt[2] the count of non-finite or non-physical nodes seen
+  // adapt[1] the time advanced, adapt[2] the count of non-finite or non-physical nodes seen;
+  // adapt[3] the largest wave speed of the current stage's state (global Lax-Friedrichs)
   const double* dtp;
   double* adapt;
   // per-element anisotropic orders (mixed != 0): node counts per direction and first node of
@@ -112,6 +113,8 @@ hipError_t launch_stage_gauss(const View& v, int cur, double dt, double rkA, dou
 // adaptive step size (uniform and mixed orders): clear adapt[], then per step reduce the wave
 // speeds of U[cur] and write the step size to adapt[0]
 hipError_t launch_adapt_reset(const View& v, hipStream_t st);
+// global Lax-Friedrichs: the largest |v| + c of U[cur] into adapt[3], before each stage
+hipError_t launch_lambda_max(const View& v, int cur, hipStream_t st);
 hipError_t launch_step_size(const View& v, int cur, double cfl, double hmin, double n1, double gamma, double Pr,
                             hipStream_t st);
 // the extended flux families 1..3 (FP64), in kernels_ext.hip; called by the two launchers above

@@ -462,6 +462,21 @@ __global__ void __launch_bounds__(256) dt_kernel(View v, int nparts, double cfl,
   }
 }
 
+// the largest wave speed of the partials into adapt[3] (global Lax-Friedrichs)
+__global__ void __launch_bounds__(256) lambda_final_kernel(View v, int nparts) {
+  __shared__ double red[256];
+  const int t = threadIdx.x;
+  double a = 0.0;
+  for (int k = t; k < nparts; k += 256) a = fmax(a, v.part[3 * k]);
+  red[t] = a;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) red[t] = fmax(red[t], red[t + w]);
+    __syncthreads();
+  }
+  if (t == 0) v.adapt[3] = red[0];
+}
+
 __global__ void adapt_reset_kernel(View v) {
   if (threadIdx.x < 4) v.adapt[threadIdx.x] = 0.0;
 }
@@ -590,6 +605,13 @@ hipError_t launch_stage_batch(const BatchArgs& B, int N, bool fp32, bool visc, i
 
 hipError_t launch_adapt_reset(const View& v, hipStream_t st) {
   hipLaunchKernelGGL(adapt_reset_kernel, dim3(1), dim3(64), 0, st, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_lambda_max(const View& v, int cur, hipStream_t st) {
+  const int blocks = std::min(1024, (v.E + 3) / 4);
+  hipLaunchKernelGGL(lambda_kernel, dim3(blocks), dim3(256), 0, st, v, cur);
+  hipLaunchKernelGGL(lambda_final_kernel, dim3(1), dim3(256), 0, st, v, blocks);
   return hipGetLastError();
 }
 

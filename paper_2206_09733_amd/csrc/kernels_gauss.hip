@@ -110,7 +110,7 @@ __global__ void __launch_bounds__(nthreads_for(N))
 #pragma unroll
     for (int c = 0; c < 3; c++) S[c] = v.Ja[owner * nn * 9 + (3 * d + c) * nn];
     double F[5];
-    face_flux<double, XS>(v.surf, uL, uR, S, v.gamma, F);
+    face_flux<double, XS>(v.surf, uL, uR, S, v.gamma, F, XS && v.surf == 8 ? v.adapt[3] : 0.0);
 #pragma unroll
     for (int c = 0; c < 5; c++) sFs[f][c][q] = F[c];
   }

@@ -281,7 +281,7 @@ __global__ void __launch_bounds__(64) mixed_face_kernel(View v, int cur) {
         face_flux_dev<T>(v.surf, uL, uR, S, v.gamma, Rf, F, F0d);
         sA[5][x] = F0d;
       } else {
-        if (v.surf >= 4) face_flux<T, true>(v.surf, uL, uR, S, v.gamma, F);
+        if (v.surf >= 4) face_flux<T, true>(v.surf, uL, uR, S, v.gamma, F, v.surf == 8 ? v.adapt[3] : 0.0);
         else face_flux<T, false>(v.surf, uL, uR, S, v.gamma, F);
       }
 #pragma unroll

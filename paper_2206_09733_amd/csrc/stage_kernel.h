@@ -105,6 +105,7 @@ __device__ __forceinline__ void stage_body(const View& v, const int e, const int
   // elements of a face evaluate it from the same global values in the same argument order, so
   // it is single-valued.
   const T* FvfAll = VISC ? reinterpret_cast<const T*>(v.Fvf) : nullptr;
+  const double lam_g = (FX & 2) != 0 && v.surf == 8 ? v.adapt[3] : 0.0;  // global Lax-Friedrichs
   for (int x = t; x < 6 * nf; x += NT) {
     const int f = x / nf, q = x - f * nf;
     const int d = f >> 1, side = f & 1;
@@ -128,7 +129,7 @@ __device__ __forceinline__ void stage_body(const View& v, const int e, const int
       face_flux_dev<T>(v.surf, uL, uR, S, v.gamma, Rf, F, F0d);
       sF0d[f][q] = F0d;
     } else {
-      face_flux<T, (FX & 2) != 0>(v.surf, uL, uR, S, v.gamma, F);
+      face_flux<T, (FX & 2) != 0>(v.surf, uL, uR, S, v.gamma, F, lam_g);
     }
     if (VISC) {
       const T* fo = FvfAll + ((long)e * 6 + f) * 4 * nf;

@@ -15,7 +15,8 @@ LIB_PATH = os.path.join(HERE, "libdgsem.so")
 
 DG_OK, DG_EINVAL, DG_ENOMEM, DG_EHIP, DG_ENONFINITE, DG_EUNSUPPORTED, DG_ESTATE = 0, -1, -2, -3, -4, -5, -6
 VOL = {"ec": 0, "central": 1, "ir": 2, "kg": 3, "pirozzoli": 4, "ducros": 5, "morinishi": 6}
-SURF = {"roe": 0, "llf": 1, "ec": 2, "central": 3, "es": 4, "ir": 5, "es_matrix": 6, "ld_roe": 7}
+SURF = {"roe": 0, "llf": 1, "ec": 2, "central": 3, "es": 4, "ir": 5, "es_matrix": 6, "ld_roe": 7,
+        "lf_global": 8}
 VISC = {"br1": 0, "br2": 1, "ip": 2}
 PRECISION = {"fp64": 0, "fp32_bulk": 1}
 IC = {"uniform": 0, "tgv": 1, "vortex": 2, "density_wave": 3}

@@ -99,7 +99,7 @@ def test_solver_argument_errors_and_sizes(dg):
     for bad in (dict(gamma=1.0), dict(vol="ec", surf="roe", precision="fp64", Ma=-1.0)):
         p = dg.physics(**bad)
         assert L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)) == dg.DG_EINVAL
-    for vol, surf in ((7, 0), (0, 8), (-1, 0), (0, -1)):
+    for vol, surf in ((7, 0), (0, 9), (-1, 0), (0, -1)):
         p = dg.physics()
         p.vol_flux, p.surf_flux = vol, surf
         assert L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)) == dg.DG_EINVAL

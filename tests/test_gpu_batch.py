@@ -28,7 +28,7 @@ def members(dg):
              dict(ex=2, N=4, Ma=0.1, Re=800.0, precision="fp32_bulk"),
              dict(ex=2, N=5, Ma=0.2, surf="llf"), dict(ex=2, N=5, Ma=0.2, surf="es", vol="ir"),
              dict(ex=2, N=5, Ma=0.2, vol="kg", surf="ld_roe"), dict(ex=2, N=3, Ma=0.3, vol="pirozzoli"),
-             dict(ex=2, N=4, Ma=0.2, Re=500.0, visc="ip"),
+             dict(ex=2, N=4, Ma=0.2, Re=500.0, visc="ip"), dict(ex=3, N=5, Ma=0.3, surf="lf_global"),
              dict(ex=3, orders=synth.mixed_orders(27, seed=2), Ma=0.5, lo=(-10.0,) * 3, hi=(10.0,) * 3)]
     out = []
     for sp in specs:

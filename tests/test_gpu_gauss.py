@@ -64,7 +64,7 @@ def parity(name, G, A, B, E, nn, factor=8.0):
 
 
 @pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 6, 7])
-@pytest.mark.parametrize("surf", ["roe", "llf", "ec", "central", "es", "es_matrix", "ld_roe"])
+@pytest.mark.parametrize("surf", ["roe", "llf", "ec", "central", "es", "es_matrix", "ld_roe", "lf_global"])
 def test_gauss_residual_parity(dg, orc, N, surf):
     c = cfg(N=N, surf=surf)
     log(f"gauss residual N={N} {surf}")

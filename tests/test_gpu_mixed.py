@@ -122,7 +122,8 @@ def test_mixed_initial_condition_parity(dg, orc):
 # ------------------------------------------------------------------ residual
 @pytest.mark.parametrize("surf,vol", [("roe", "ec"), ("llf", "ec"), ("ec", "ec"), ("central", "ec"), ("es", "ec"),
                                       ("ir", "ir"), ("es_matrix", "ec"), ("ld_roe", "ec"), ("roe", "kg"),
-                                      ("llf", "pirozzoli"), ("ec", "ducros"), ("es_matrix", "morinishi")])
+                                      ("llf", "pirozzoli"), ("ec", "ducros"), ("es_matrix", "morinishi"),
+                                      ("lf_global", "ec")])
 def test_mixed_residual_parity(dg, orc, surf, vol):
     """3x3x3 elements with orders drawn from {1..6} per direction on a deformed mesh: most faces
     are p-nonconforming in one or both tangential directions."""

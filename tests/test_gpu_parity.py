@@ -165,7 +165,8 @@ def test_residual_ismail_roe_and_entropy_stable(dg, orc, N, vol, surf, Re):
                                          ("morinishi", "central", 100.0), ("ec", "es_matrix", 0.0),
                                          ("ir", "es_matrix", 100.0), ("ec", "ld_roe", 100.0),
                                          ("pirozzoli", "es_matrix", 0.0), ("morinishi", "ld_roe", 100.0),
-                                         ("kg", "ld_roe", 0.0)])
+                                         ("kg", "ld_roe", 0.0), ("ec", "lf_global", 0.0),
+                                         ("pirozzoli", "lf_global", 100.0)])
 def test_residual_kep_and_dissipative_surface_fluxes(dg, orc, N, vol, surf, Re):
     """Kinetic-energy-preserving volume fluxes (Kennedy-Gruber, Pirozzoli, Ducros, Morinishi),
     the matrix-dissipation entropy-stable flux and the low-dissipation Roe flux, alone and
@@ -177,6 +178,27 @@ def test_residual_kep_and_dissipative_surface_fluxes(dg, orc, N, vol, surf, Re):
     g = dg.Solver(**c)
     g.set_state(U)
     assert_parity(f"N={N} {vol}/{surf} Re={Re}", g.residual(), R64, R80, 12, (N + 1) ** 3)
+
+
+def test_global_lax_friedrichs_trajectory(dg, orc):
+    """The global wave speed is reduced on the device before every stage: three RK3 steps of a
+    perturbed state against the oracle, which takes it from each stage's state as well."""
+    c = cfg(ex=3, N=4, deform=True, Ma=0.3, surf="lf_global")
+    U = perturbed_state(orc, c, seed=91, amp=(0.02, 0.05, 0.02))
+    o, o80 = orc.OracleSolver(**c), orc.OracleSolver(**c, precision="fp80")
+    o.set_state(U)
+    o80.set_state(U)
+    dt = o.suggest_dt(0.5)
+    o.rk3(dt, 3)
+    o80.rk3(dt, 3)
+    g = dg.Solver(**c)
+    g.set_state(U)
+    g.rk_step(dt, 3)
+    Ug, Uo, U80 = g.state(), o.state(), o80.state()
+    d = lambda a, b: np.abs(a - b).reshape(27, 5, 125).max(axis=(0, 2))
+    sc = np.abs(U80).reshape(27, 5, 125).max(axis=(0, 2))
+    log(f"[lf_global RK] gpu-vs-fp80 {d(Ug, U80) / sc} fp64-vs-fp80 {d(Uo, U80) / sc}")
+    assert np.all(d(Ug, U80) <= np.maximum(1e-14 * sc, 8 * d(Uo, U80)))
 
 
 def test_gpu_entropy_matrix_dissipation(dg, orc):
