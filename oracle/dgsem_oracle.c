@@ -539,8 +539,8 @@ orc_solver* orc_create(int ex, int ey, int ez, const double* lo, const double* h
 }
 
 orc_solver* orc_create_gauss(int ex, int ey, int ez, const double* lo, const double* hi, int N, double gamma,
-                             double Ma, int surf_flux) {
-  return create(ex, ey, ez, lo, hi, 0, 0.0, N, NULL, gamma, 0.71, Ma, 0.0, ORC_VOL_CENTRAL, surf_flux, 1);
+                             double Pr, double Ma, double Re, int surf_flux) {
+  return create(ex, ey, ez, lo, hi, 0, 0.0, N, NULL, gamma, Pr, Ma, Re, ORC_VOL_CENTRAL, surf_flux, 1);
 }
 
 void orc_destroy(orc_solver* s) {
@@ -1261,8 +1261,78 @@ static void element_residual(const orc_solver* s, const real* U, const real* Gal
  *     Dw_im = -D_mi w_m / w_i (the quadrature of -int F dl_i/dxi), F~^d = Ja^d . F(U) at the
  *     nodes, F* the numerical flux between the two traces U(+-1) = sum_i l_i(+-1) U_i along the
  *     line through the face point, with the owner's metric interpolated the same way as normal.
- *     Uniform orders, Euler. */
-static void element_residual_gauss(const orc_solver* s, const real* U, int e, real* R) {
+ *     With viscosity, the BR1 viscous flux enters the same way with the opposite sign: Ja^d .
+ *     F_v(U, grad g) at the nodes, and on the faces the average of the two sides' F_v from their
+ *     traces of U and of grad g (gradients from compute_gradients_gauss).  Uniform orders. */
+/* trace on the face (d, side) of element e at face point (p, r) of a nodal field with nv
+ * components stored [c * nn + node] from base f: sum_i l_i(side) f(node i of the line) */
+static void gauss_trace(const orc_solver* s, const real* f, int nv, int e, int d, int side, int p, int r, real* out) {
+  const int N = s->N[e][0], n = N + 1, nn = n * n * n;
+  const gll_t* T = &s->T[N];
+  int ta, tb;
+  face_dirs(d, &ta, &tb);
+  for (int c = 0; c < nv; c++) out[c] = 0;
+  for (int i = 0; i < n; i++) {
+    int ii[3];
+    ii[d] = i; ii[ta] = p; ii[tb] = r;
+    long q = node_of(s, e, ii);
+    for (int c = 0; c < nv; c++) out[c] += T->lb[side][i] * f[(long)c * nn + q];
+  }
+}
+
+/* 7b. BR1 gradients of g = (v, T) on Gauss-Legendre points, weak form with the face values
+ *     g* = (g(U_L) + g(U_R)) / 2 of the interpolated traces:
+ *       J grad g = sum_d Ja^d (delta_d g),
+ *       (delta_d g)_i = -sum_m (w_m / w_i) D_mi g_m + (l_i(+1) g*(+d) - l_i(-1) g*(-d)) / w_i
+ *     (the path takes affine elements, whose metric is constant and comes out of the
+ *     derivative). */
+static void compute_gradients_gauss(orc_solver* s, const real* U, real* Gout) {
+#pragma omp parallel for schedule(static)
+  for (int e = 0; e < s->E; e++) {
+    const int N = s->N[e][0], n = N + 1, nn = n * n * n;
+    const gll_t* T = &s->T[N];
+    real* G = Gout + s->off[e] * 12;
+    for (int k = 0; k < n; k++)
+      for (int j = 0; j < n; j++)
+        for (int i = 0; i < n; i++) {
+          int ii[3] = {i, j, k};
+          long q = node_of(s, e, ii);
+          real acc[12] = {0};
+          for (int d = 0; d < 3; d++) {
+            int ta, tb;
+            face_dirs(d, &ta, &tb);
+            real a[4] = {0, 0, 0, 0};
+            int jj[3] = {i, j, k};
+            for (int m = 0; m < n; m++) {
+              jj[d] = m;
+              real um[5], gm[4];
+              load5(s, U, e, node_of(s, e, jj), um);
+              gvars(um, s->gamma, gm);
+              real dw = -T->D[m][ii[d]] * T->w[m] / T->w[ii[d]];
+              for (int c = 0; c < 4; c++) a[c] += dw * gm[c];
+            }
+            for (int side = 0; side < 2; side++) {
+              int ne = s->nbr[6 * e + 2 * d + side];
+              real uo[5], un[5], go[4], gn[4];
+              gauss_trace(s, U + s->off[e] * 5, 5, e, d, side, ii[ta], ii[tb], uo);
+              gauss_trace(s, U + s->off[ne] * 5, 5, ne, d, 1 - side, ii[ta], ii[tb], un);
+              gvars(uo, s->gamma, go);
+              gvars(un, s->gamma, gn);
+              real l = T->lb[side][ii[d]] / T->w[ii[d]];
+              for (int c = 0; c < 4; c++) a[c] += (side ? l : -l) * (go[c] + gn[c]) / 2;
+            }
+            real nv[3];
+            load_ja(s, e, q, d, nv);
+            for (int c = 0; c < 4; c++)
+              for (int x = 0; x < 3; x++) acc[3 * c + x] += nv[x] * a[c];
+          }
+          real Jq = s->J[s->off[e] + q];
+          for (int t = 0; t < 12; t++) G[(long)t * nn + q] = acc[t] / Jq;
+        }
+  }
+}
+
+static void element_residual_gauss(const orc_solver* s, const real* U, const real* Gall, int e, real* R) {
   const int N = s->N[e][0], n = N + 1, nn = n * n * n;
   const gll_t* T = &s->T[N];
   /* numerical flux on the six faces, face point (p, r) along the two tangential directions */
@@ -1292,6 +1362,16 @@ static void element_residual_gauss(const orc_solver* s, const real* U, int e, re
           }
           real F[5];
           surface_flux(s, uL, uR, S, F);
+          if (s->viscous) {
+            /* BR1: average of the two sides' viscous fluxes from their traces of U and grad g */
+            real qL[12], qR[12], Fa[15], Fb[15];
+            gauss_trace(s, Gall + s->off[L] * 12, 12, L, d, 1, p, r, qL);
+            gauss_trace(s, Gall + s->off[Rr] * 12, 12, Rr, d, 0, p, r, qR);
+            viscous_flux(uL, qL, s->gamma, s->mu, s->kappa, Fa);
+            viscous_flux(uR, qR, s->gamma, s->mu, s->kappa, Fb);
+            for (int v = 0; v < 5; v++)
+              F[v] -= (S[0] * (Fa[v] + Fb[v]) + S[1] * (Fa[5 + v] + Fb[5 + v]) + S[2] * (Fa[10 + v] + Fb[10 + v])) / 2;
+          }
           for (int v = 0; v < 5; v++) Ff[2 * d + side][v][p + n * r] = F[v];
         }
     }
@@ -1313,6 +1393,11 @@ static void element_residual_gauss(const orc_solver* s, const real* U, int e, re
             load5(s, U, e, qm, um);
             load_ja(s, e, qm, d, nm);
             euler_flux(um, nm, s->gamma, F);
+            if (s->viscous) {  /* the viscous flux enters with the opposite sign */
+              real Fd[5];
+              contra_visc(s, U, Gall, e, qm, d, NULL, Fd);
+              for (int v = 0; v < 5; v++) F[v] -= Fd[v];
+            }
             real dw = -T->D[m][ii[d]] * T->w[m] / T->w[ii[d]];
             for (int v = 0; v < 5; v++) V[v] += dw * F[v];
           }
@@ -1342,8 +1427,9 @@ static void residual(orc_solver* s, const real* U, real* R) {
     s->lam_g = lam;
   }
   if (s->gauss) {
+    if (s->viscous) compute_gradients_gauss(s, U, s->G);
 #pragma omp parallel for schedule(dynamic, 4)
-    for (int e = 0; e < s->E; e++) element_residual_gauss(s, U, e, R + s->off[e] * 5);
+    for (int e = 0; e < s->E; e++) element_residual_gauss(s, U, s->G, e, R + s->off[e] * 5);
     return;
   }
   if (s->viscous) compute_gradients(s, U, s->G);
@@ -1360,7 +1446,8 @@ int orc_residual(orc_solver* s, double* Rout) {
 
 int orc_gradients(orc_solver* s, double* Gout) {
   if (!s) return -1;
-  compute_gradients(s, s->U, s->G);
+  if (s->gauss) compute_gradients_gauss(s, s->U, s->G);
+  else compute_gradients(s, s->U, s->G);
   for (long i = 0; i < 12 * s->ntot; i++) Gout[i] = (double)s->G[i];
   return 0;
 }

@@ -819,6 +819,86 @@ def test_br1_gradient_exact_for_continuous_piecewise_linear(orc):
     assert np.abs(G - exp).max() < 1e-12
 
 
+def test_gauss_br1_gradient_exact_for_continuous_piecewise_linear(orc):
+    """BR1 in weak form on Gauss-Legendre points: for (v, T) continuous across faces and linear
+    in each element (rho = 1, so U is quadratic and its interpolated traces are exact), the
+    gradient equals the exact one at every node."""
+    ex, N = 4, 3
+    s = orc.OracleSolver(ex, N=N, Re=100.0, vol="central", nodes="gauss")
+    X = s.coords().reshape(s.E, 3, -1)
+    tri = lambda t: np.abs(t - math.pi)
+    x, y, z = X[:, 0], X[:, 1], X[:, 2]
+    v = np.stack([tri(x), 0.5 * tri(y), -0.25 * tri(z)], axis=-1)
+    T = 1.0 + 0.1 * tri(x) + 0.2 * tri(z)
+    rho = np.ones_like(x)
+    s.set_state(to_conservative(rho, v, rho * T).transpose(0, 2, 1).reshape(-1))
+    G = s.gradients().reshape(s.E, 12, -1)
+    sx = np.sign(X[:, 0] - math.pi)
+    sy = np.sign(X[:, 1] - math.pi)
+    sz = np.sign(X[:, 2] - math.pi)
+    exp = np.zeros_like(G)
+    exp[:, 0] = sx
+    exp[:, 4] = 0.5 * sy
+    exp[:, 8] = -0.25 * sz
+    exp[:, 9] = 0.1 * sx
+    exp[:, 11] = 0.2 * sz
+    assert np.abs(G - exp).max() < 1e-12
+
+
+def test_gauss_viscous_rates_conservation_freestream(orc):
+    """Navier-Stokes on Gauss-Legendre points: the shear flow v = (sin y, 0, 0) has the rate
+    (0, -mu sin y, 0, 0, mu cos 2y) and the contact T = 1 + 0.1 sin x at uniform p the rate
+    (0, 0, 0, 0, -0.1 kappa sin x), to the discretisation error (larger than on Lobatto points in
+    the shear flow: its face traces are interpolated, and p of the interpolated state differs from
+    the interpolated p at that level, which the Roe faces see; an error in the viscous terms would
+    be of order mu); on a perturbed state the totals are conserved, and a uniform state stays
+    steady."""
+    Re, Pr = 50.0, 0.71
+    mu = 1 / Re
+    kappa = mu * GAMMA / (0.4 * Pr)
+    N = 8
+    kw = dict(N=N, Re=Re, Pr=Pr, Ma=0.5, vol="central", nodes="gauss")
+    s = orc.OracleSolver(1, 6, 1, **kw)
+    X = s.coords().reshape(s.E, 3, -1)
+    y = X[:, 1]
+    nn = y.shape[1]
+    v = np.zeros((s.E, nn, 3))
+    v[:, :, 0] = np.sin(y)
+    s.set_state(to_conservative(np.ones_like(y), v, np.full_like(y, 3.0)).transpose(0, 2, 1).reshape(-1))
+    R = s.residual().reshape(s.E, 5, nn)
+    exp = np.zeros_like(R)
+    exp[:, 1] = -mu * np.sin(y)
+    exp[:, 4] = mu * np.cos(2 * y)
+    assert np.abs(R - exp).max() < 5e-5 * mu
+    s = orc.OracleSolver(6, 1, 1, **kw)
+    x = s.coords().reshape(s.E, 3, -1)[:, 0]
+    T = 1 + 0.1 * np.sin(x)
+    s.set_state(to_conservative(2.0 / T, np.zeros((s.E, nn, 3)), np.full_like(x, 2.0)).transpose(0, 2, 1).reshape(-1))
+    R = s.residual().reshape(s.E, 5, nn)
+    exp = np.zeros_like(R)
+    exp[:, 4] = -0.1 * kappa * np.sin(x)
+    assert np.abs(R - exp).max() < 2e-6 * kappa
+    N = 4
+    s = orc.OracleSolver(3, N=N, Re=300.0, Ma=0.4, vol="central", nodes="gauss")
+    s.set_ic("tgv")
+    U = s.state().reshape(s.E, 5, -1).transpose(0, 2, 1).reshape(-1, 5)
+    drho, dv, dp = synth.primitive_perturbation(s.nodes, seed=29, amp=(0.05, 0.1, 0.05))
+    rho = U[:, 0] * (1 + drho)
+    vel = U[:, 1:4] / U[:, :1] + dv.T
+    p = 0.4 * (U[:, 4] - 0.5 * (U[:, 1:4] ** 2).sum(1) / U[:, 0]) * (1 + dp)
+    s.set_state(to_conservative(rho, vel, p).reshape(s.E, -1, 5).transpose(0, 2, 1).reshape(-1))
+    R = s.residual()
+    _, w, _, _ = orc.gl(N)
+    _, J = s.metrics()
+    wq = quad_weights_uniform(w, s.E) * J
+    Rv = R.reshape(s.E, 5, -1)
+    tot = np.einsum('en,evn->v', wq.reshape(s.E, -1), Rv)
+    mag = np.einsum('en,evn->v', wq.reshape(s.E, -1), np.abs(Rv))
+    assert np.all(np.abs(tot) < 1e-12 * mag.max()), (tot, mag)
+    s.set_ic("uniform", [1.0, 0.3, -0.2, 0.1, 2.0])
+    assert np.abs(s.residual()).max() < 1e-12
+
+
 def test_br1_lift_closed_form_for_jumps(orc):
     """BR1 lift: for v1 constant in each element with jumps across x-faces, the gradient is
     (g* - g)/(h w_end) at the x-face nodes (g* the face average) and zero elsewhere."""
