@@ -845,6 +845,33 @@ def test_gauss_br1_gradient_exact_for_continuous_piecewise_linear(orc):
     assert np.abs(G - exp).max() < 1e-12
 
 
+def test_gauss_br1_gradient_closed_form_for_jumps(orc):
+    """BR1 on Gauss-Legendre points for v1 constant in each x-column of elements (c_a), rho = 1,
+    p uniform: the traces are exact, and by the generalised SBP identity the weak derivative of
+    a constant c with face values g* = (c + c_neighbour)/2 is
+      (l_i(+1) (c_next - c) - l_i(-1) (c_prev - c)) / (2 w_i),
+    so d v1/dx = (2/h_x) times that at every node, and every other gradient component is 0."""
+    ex, N = 3, 4
+    n = N + 1
+    cols = [0.3, -0.2, 0.5]
+    s = orc.OracleSolver(ex, 2, 2, N=N, Re=100.0, vol="central", nodes="gauss")
+    U = np.zeros((2, 2, ex, 5, n, n, n))
+    for a in range(ex):
+        U[:, :, a, 0] = 1.0
+        U[:, :, a, 1] = cols[a]
+        U[:, :, a, 4] = 2.0 / 0.4 + 0.5 * cols[a] ** 2
+    s.set_state(U.reshape(-1))
+    G = s.gradients().reshape(2, 2, ex, 12, n, n, n)
+    _, w, _, lb = orc.gl(N)
+    hx = 2 * math.pi / ex
+    exp = np.zeros_like(G)
+    for a in range(ex):
+        c, cn, cp = cols[a], cols[(a + 1) % ex], cols[(a - 1) % ex]
+        d = (lb[1] * (cn - c) - lb[0] * (cp - c)) / (2 * w) * (2 / hx)
+        exp[:, :, a, 0] = d[None, None, :]  # varies along i (x)
+    assert np.abs(G - exp).max() < 1e-12 * np.abs(exp).max(), np.abs(G - exp).max()
+
+
 def test_gauss_viscous_rates_conservation_freestream(orc):
     """Navier-Stokes on Gauss-Legendre points: the shear flow v = (sin y, 0, 0) has the rate
     (0, -mu sin y, 0, 0, mu cos 2y) and the contact T = 1 + 0.1 sin x at uniform p the rate
