@@ -55,10 +55,10 @@ extern "C" {
 /* ------------------------------------------------------------------ options */
 enum { DG_DEFORM_NONE = 0, DG_DEFORM_SINSIN = 1 };
 /* quadrature / collocation points (section "Spatial discretisation" allows both): Gauss-Lobatto
- * (every split form, the viscous terms, mixed orders, FP32-bulk), or Gauss-Legendre (more
+ * (every split form, every viscous flux, mixed orders, FP32-bulk), or Gauss-Legendre (more
  * accurate; no boundary nodes, so the plain weak form with face traces interpolated to the
- * element boundaries: Euler equations, undeformed uniform-order boxes, FP64, volume flux
- * DG_VOL_CENTRAL, any surface flux) */
+ * element boundaries: undeformed uniform-order boxes, FP64, volume flux DG_VOL_CENTRAL, any
+ * surface flux, BR1 viscous terms) */
 enum { DG_NODES_LOBATTO = 0, DG_NODES_GAUSS = 1 };
 /* volume two-point flux (the list of split forms of section "Energy/Entropy stable versions"):
  * Chandrashekar's entropy-conserving, kinetic-energy-preserving flux; the central average;

@@ -85,7 +85,7 @@ struct dg_solver {
 namespace {
 
 struct Plan {
-  size_t tab, nbr, X, Ja, J, invJ, U0, U1, dU, R, Fvf, part, diag, adapt, elem, work, mtab, Fs, Tr, self, total;
+  size_t tab, nbr, X, Ja, J, invJ, U0, U1, dU, R, Fvf, part, diag, adapt, elem, work, mtab, Fs, Tr, Q, self, total;
   size_t tab_n, mtab_n;
 };
 
@@ -134,6 +134,7 @@ Plan make_plan(const dg_solver* s) {
   p.mtab = mixed ? take(sizeof(double) * p.mtab_n) : 0;
   p.Fs = mixed ? take(sizeof(double) * dg::kMixFaceDoubles * E) : 0;
   p.Tr = s->mesh.gauss ? take(sizeof(double) * E * 6 * 5 * nf) : 0;
+  p.Q = s->mesh.gauss && s->phys.Re > 0 ? take(sizeof(double) * 12 * nt) : 0;
   p.self = take(sizeof(dg::View));  // device copy of the View, read by batched launches
   p.total = off;
   return p;
@@ -435,9 +436,10 @@ int dg_solver_create(const dg_mesh* m, const dg_physics* p, dg_solver** out) {
                                  "central surface fluxes; the others are evaluated in FP64");
   if (m->mixed && p->Re > 0)
     return fail(DG_EUNSUPPORTED, "mixed-order meshes are evaluated for the Euler equations (Re <= 0)");
-  if (m->gauss && (p->Re > 0 || p->precision != DG_FP64 || p->vol_flux != DG_VOL_CENTRAL))
-    return fail(DG_EUNSUPPORTED, "Gauss-Legendre nodes: Euler equations (Re <= 0), FP64, volume flux "
-                                 "DG_VOL_CENTRAL (the plain weak form)");
+  if (m->gauss && (p->precision != DG_FP64 || p->vol_flux != DG_VOL_CENTRAL ||
+                   (p->Re > 0 && p->visc_flux != DG_VISC_BR1)))
+    return fail(DG_EUNSUPPORTED, "Gauss-Legendre nodes: FP64, volume flux DG_VOL_CENTRAL (the plain weak "
+                                 "form), BR1 viscous terms");
   dg_solver* s = new dg_solver;
   s->mesh = *m;
   s->phys = *p;
@@ -513,6 +515,7 @@ int dg_solver_bind(dg_solver* s, void* dev_ptr, size_t bytes, void* hip_stream) 
   v.Fs = mixed ? reinterpret_cast<double*>(b + p.Fs) : nullptr;
   v.gauss = s->mesh.gauss ? 1 : 0;
   v.Tr = s->mesh.gauss ? reinterpret_cast<double*>(b + p.Tr) : nullptr;
+  v.Q = s->mesh.gauss && v.viscous ? reinterpret_cast<double*>(b + p.Q) : nullptr;
   s->dev_view = reinterpret_cast<dg::View*>(b + p.self);
   s->stream = static_cast<hipStream_t>(hip_stream);
 

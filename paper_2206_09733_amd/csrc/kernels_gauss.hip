@@ -1,8 +1,9 @@
 // kernels_gauss.hip -- DGSEM on Gauss-Legendre nodes, the other quadrature that section "Spatial
-// discretisation" allows: the plain weak form (no boundary nodes, so no split form), for the
-// Euler equations on undeformed uniform-order boxes, FP64.
+// discretisation" allows: the plain weak form (no boundary nodes, so no split form), with BR1
+// viscous terms for Navier-Stokes, on undeformed uniform-order boxes, FP64.
 //
-// Two launches per RK stage.  gauss_trace_kernel interpolates each element's state to its six
+// Two launches per RK stage (three with viscosity: gauss_grad_kernel between them).
+// gauss_trace_kernel interpolates each element's state to its six
 // faces, U(+-1) = sum_i l_i(+-1) U_i along the line through every face point, into
 // Tr[E][6][5][nf].  gauss_stage_kernel then forms, per node,
 //   J dU_i/dt = -[ sum_d sum_m Dw_im F~^d_m + sum_d (l_i(+1) F*(+d) - l_i(-1) F*(-d)) / w_i ],
@@ -50,6 +51,116 @@ __global__ void __launch_bounds__(nthreads_for(N)) gauss_trace_kernel(View v, in
   }
 }
 
+// BR1 on Gauss points (Navier-Stokes): the weak-form gradient of g = (v, T) with the face values
+// g* = (g(U_L) + g(U_R)) / 2 of both sides' traces,
+//   J grad g = sum_d Ja^d [ sum_m Dw_im g_m + (l_i(+1) g*(+d) - l_i(-1) g*(-d)) / w_i ]
+// (affine elements: constant metric), written to Q[E][12][nn], and on the six faces the
+// contravariant viscous flux of this side's traces, F_v(U trace, sum_i l_i grad g_i) . S with the
+// owner's metric S, into Fvf[E][6][4][nf]; the stage kernel averages the two sides.
+template <int N>
+__global__ void __launch_bounds__(nthreads_for(N)) gauss_grad_kernel(View v, int cur) {
+  constexpr int n = N + 1, nn = n * n * n, nf = n * n, NT = nthreads_for(N);
+  const int e = block_element(v.E);
+  const int t = threadIdx.x;
+  const bool act = t < nn;
+  const int ti = t % n, tj = (t / n) % n, tk = t / nf;
+  __shared__ double sDw[n * n], sw[n], sl[2][n];
+  __shared__ double sG[4][nn];
+  __shared__ double sGs[6][4][nf];  // face values g*
+  __shared__ double sQ[12][nn];
+  for (int x = t; x < n * n; x += NT) {
+    const int i = x / n, m = x - i * n;
+    sDw[x] = -v.tab[2 * n + m * n + i] * v.tab[n + m] / v.tab[n + i];
+  }
+  if (t < n) sw[t] = v.tab[n + t];
+  if (t < 2 * n) sl[t / n][t % n] = v.tab[gauss_tab_ends(n) + t];
+  const long base = (long)e * nn;
+  const double* __restrict__ Uin = v.U[cur];
+  if (act) {
+    double u[5], g[4];
+#pragma unroll
+    for (int c = 0; c < 5; c++) u[c] = Uin[base * 5 + c * nn + t];
+    gvars(u, v.gamma, 0.0, g);
+#pragma unroll
+    for (int c = 0; c < 4; c++) sG[c][t] = g[c];
+  }
+  for (int x = t; x < 6 * nf; x += NT) {
+    const int f = x / nf, q = x - f * nf;
+    const int ne = v.nbr[e * 6 + f];
+    const double* To = v.Tr + ((long)e * 6 + f) * 5 * nf;
+    const double* Tn = v.Tr + ((long)ne * 6 + (f ^ 1)) * 5 * nf;
+    double uo[5], un[5], go[4], gn[4];
+#pragma unroll
+    for (int c = 0; c < 5; c++) {
+      uo[c] = To[c * nf + q];
+      un[c] = Tn[c * nf + q];
+    }
+    gvars(uo, v.gamma, 0.0, go);
+    gvars(un, v.gamma, 0.0, gn);
+#pragma unroll
+    for (int c = 0; c < 4; c++) sGs[f][c][q] = 0.5 * (go[c] + gn[c]);
+  }
+  __syncthreads();
+  if (act) {
+    const int ii[3] = {ti, tj, tk};
+    double a[3][4];
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+      const int id = ii[d];
+      const int stride = d == 0 ? 1 : (d == 1 ? n : nf);
+      const int b0 = t - id * stride;
+      const int qd = d == 0 ? tj + n * tk : (d == 1 ? ti + n * tk : ti + n * tj);
+      const double lp = sl[1][id] / sw[id], lm = sl[0][id] / sw[id];
+#pragma unroll
+      for (int c = 0; c < 4; c++) {
+        double acc = lp * sGs[2 * d + 1][c][qd] - lm * sGs[2 * d][c][qd];
+#pragma unroll
+        for (int m = 0; m < n; m++) acc += sDw[id * n + m] * sG[c][b0 + m * stride];
+        a[d][c] = acc;
+      }
+    }
+    double ja[9];
+#pragma unroll
+    for (int c = 0; c < 9; c++) ja[c] = v.Ja[base * 9 + c * nn + t];
+    const double ij = v.invJ[base + t];
+#pragma unroll
+    for (int c = 0; c < 4; c++)
+#pragma unroll
+      for (int x = 0; x < 3; x++) {
+        const double q = ij * (ja[x] * a[0][c] + ja[3 + x] * a[1][c] + ja[6 + x] * a[2][c]);
+        sQ[3 * c + x][t] = q;
+        v.Q[(base * 12 + (3 * c + x) * nn) + t] = q;
+      }
+  }
+  __syncthreads();
+  double* __restrict__ Fvf = v.Fvf + (long)e * 6 * 4 * nf;
+  for (int x = t; x < 6 * nf; x += NT) {
+    const int f = x / nf, q = x - f * nf;
+    const int d = f >> 1, side = f & 1;
+    const int p = q % n, r = q / n;
+    double gr[4][3];
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+      double acc = 0.0;
+#pragma unroll
+      for (int i = 0; i < n; i++) acc += sl[side][i] * sQ[k][face_node<n>(d, i, p, r)];
+      gr[k / 3][k % 3] = acc;
+    }
+    const double* To = v.Tr + ((long)e * 6 + f) * 5 * nf;
+    double uo[5], go[4];
+#pragma unroll
+    for (int c = 0; c < 5; c++) uo[c] = To[c * nf + q];
+    gvars(uo, v.gamma, 0.0, go);
+    double Fv[3][4];
+    viscous_flux_g(go[0], go[1], go[2], gr, v.mu, v.kappa, Fv);
+    const long owner = side ? e : v.nbr[e * 6 + f];
+    const double s1 = v.Ja[owner * nn * 9 + (3 * d) * nn], s2 = v.Ja[owner * nn * 9 + (3 * d + 1) * nn],
+                 s3 = v.Ja[owner * nn * 9 + (3 * d + 2) * nn];
+#pragma unroll
+    for (int c = 0; c < 4; c++) Fvf[(f * 4 + c) * nf + q] = s1 * Fv[0][c] + s2 * Fv[1][c] + s3 * Fv[2][c];
+  }
+}
+
 // Euler flux of the conservative state u along the (not normalised) vector s
 __device__ __forceinline__ void euler_flux_along(const double u[5], double gamma, double s1, double s2, double s3,
                                                  double F[5]) {
@@ -64,8 +175,9 @@ __device__ __forceinline__ void euler_flux_along(const double u[5], double gamma
   F[4] = (u[4] + p) * vn;
 }
 
-// XS: the extended surface fluxes (codes >= 4), compiled apart
-template <int N, bool XS>
+// XS: the extended surface fluxes (codes >= 4), compiled apart; VISC: the BR1 viscous terms
+// (gradients and face viscous fluxes from gauss_grad_kernel), entering with the opposite sign
+template <int N, bool XS, bool VISC>
 __global__ void __launch_bounds__(nthreads_for(N))
     gauss_stage_kernel(View v, int cur, double dt, double rkA, double rkB, int mode) {
   constexpr int n = N + 1, nn = n * n * n, nf = n * n, NT = nthreads_for(N);
@@ -84,13 +196,18 @@ __global__ void __launch_bounds__(nthreads_for(N))
   if (t < 2 * n) sl[t / n][t % n] = v.tab[gauss_tab_ends(n) + t];
   const long base = (long)e * nn;
   const double* __restrict__ Uin = v.U[cur];
-  double u[5], ja[9], ij = 0.0;
+  double u[5], ja[9], ij = 0.0, gv[4] = {0.0, 0.0, 0.0, 0.0}, gr[4][3];
   if (act) {
 #pragma unroll
     for (int c = 0; c < 5; c++) u[c] = Uin[base * 5 + c * nn + t];
 #pragma unroll
     for (int c = 0; c < 9; c++) ja[c] = v.Ja[base * 9 + c * nn + t];
     ij = v.invJ[base + t];
+    if (VISC) {
+      gvars(u, v.gamma, 0.0, gv);
+#pragma unroll
+      for (int k = 0; k < 12; k++) gr[k / 3][k % 3] = v.Q[base * 12 + k * nn + t];
+    }
   }
   // numerical fluxes on the faces, from the traces of both sides
   for (int x = t; x < 6 * nf; x += NT) {
@@ -111,6 +228,12 @@ __global__ void __launch_bounds__(nthreads_for(N))
     for (int c = 0; c < 3; c++) S[c] = v.Ja[owner * nn * 9 + (3 * d + c) * nn];
     double F[5];
     face_flux<double, XS>(v.surf, uL, uR, S, v.gamma, F, XS && v.surf == 8 ? v.adapt[3] : 0.0);
+    if (VISC) {
+      const double* fo = v.Fvf + ((long)e * 6 + f) * 4 * nf;
+      const double* fn = v.Fvf + ((long)ne * 6 + (f ^ 1)) * 4 * nf;
+#pragma unroll
+      for (int c = 0; c < 4; c++) F[1 + c] -= 0.5 * (fo[c * nf + q] + fn[c * nf + q]);
+    }
 #pragma unroll
     for (int c = 0; c < 5; c++) sFs[f][c][q] = F[c];
   }
@@ -123,6 +246,12 @@ __global__ void __launch_bounds__(nthreads_for(N))
     if (act) {
       double F[5];
       euler_flux_along(u, v.gamma, ja[3 * d], ja[3 * d + 1], ja[3 * d + 2], F);
+      if (VISC) {
+        double Fv[3][4];
+        viscous_flux_g(gv[0], gv[1], gv[2], gr, v.mu, v.kappa, Fv);
+#pragma unroll
+        for (int c = 0; c < 4; c++) F[1 + c] -= ja[3 * d] * Fv[0][c] + ja[3 * d + 1] * Fv[1][c] + ja[3 * d + 2] * Fv[2][c];
+      }
 #pragma unroll
       for (int c = 0; c < 5; c++) sF[c][t] = F[c];
     }
@@ -167,13 +296,23 @@ __global__ void __launch_bounds__(nthreads_for(N))
 
 template <int N>
 static hipError_t gauss_stage_n(const View& v, int cur, double dt, double a, double b, int mode, hipStream_t st) {
-  hipLaunchKernelGGL(gauss_trace_kernel<N>, dim3(v.E), dim3(nthreads_for(N)), 0, st, v, cur);
+  const dim3 grid(v.E), block(nthreads_for(N));
+  hipLaunchKernelGGL(gauss_trace_kernel<N>, grid, block, 0, st, v, cur);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
-  if (v.surf >= 4)
-    hipLaunchKernelGGL((gauss_stage_kernel<N, true>), dim3(v.E), dim3(nthreads_for(N)), 0, st, v, cur, dt, a, b, mode);
-  else
-    hipLaunchKernelGGL((gauss_stage_kernel<N, false>), dim3(v.E), dim3(nthreads_for(N)), 0, st, v, cur, dt, a, b, mode);
+  if (v.viscous) {
+    hipLaunchKernelGGL(gauss_grad_kernel<N>, grid, block, 0, st, v, cur);
+    err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    if (v.surf >= 4)
+      hipLaunchKernelGGL((gauss_stage_kernel<N, true, true>), grid, block, 0, st, v, cur, dt, a, b, mode);
+    else
+      hipLaunchKernelGGL((gauss_stage_kernel<N, false, true>), grid, block, 0, st, v, cur, dt, a, b, mode);
+  } else if (v.surf >= 4) {
+    hipLaunchKernelGGL((gauss_stage_kernel<N, true, false>), grid, block, 0, st, v, cur, dt, a, b, mode);
+  } else {
+    hipLaunchKernelGGL((gauss_stage_kernel<N, false, false>), grid, block, 0, st, v, cur, dt, a, b, mode);
+  }
   return hipGetLastError();
 }
 

@@ -69,7 +69,7 @@ def _mesh(dg, ex=2, N=3):
 
 
 def test_gauss_legendre_limits(dg):
-    """Gauss-Legendre nodes: undeformed uniform-order boxes, Euler, FP64, central volume form."""
+    """Gauss-Legendre nodes: undeformed uniform-order boxes, FP64, central volume form, BR1."""
     L = dg.lib()
     m = ctypes.c_void_p()
     d, _ = dg.box_desc(2, 2, 2, (0, 0, 0), (1, 1, 1), True, 0.05, 3, nodes="gauss")
@@ -82,11 +82,11 @@ def test_gauss_legendre_limits(dg):
     d, _ = dg.box_desc(2, 2, 2, (0, 0, 0), (1, 1, 1), False, 0.0, 3, nodes="gauss")
     dg.check(L.dg_mesh_create_box(ctypes.byref(d), ctypes.byref(m)))
     s = ctypes.c_void_p()
-    for bad in (dict(vol="ec"), dict(vol="central", Re=100.0), dict(vol="central", precision="fp32_bulk")):
+    for bad in (dict(vol="ec"), dict(vol="central", Re=100.0, visc="br2"), dict(vol="central", precision="fp32_bulk")):
         p = dg.physics(**bad)
         assert L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)) == dg.DG_EUNSUPPORTED, bad
     for surf in dg.SURF:
-        p = dg.physics(vol="central", surf=surf)
+        p = dg.physics(vol="central", surf=surf, Re=100.0 if surf == "roe" else 0.0)
         assert L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)) == dg.DG_OK
         L.dg_solver_destroy(s)
     L.dg_mesh_destroy(m)

@@ -1,5 +1,6 @@
 """Gauss-Legendre nodes on the GPU (weak form, face traces interpolated to the element
-boundaries; Euler, undeformed uniform-order boxes, FP64) against the oracle's Gauss path.
+boundaries; Euler and BR1 Navier-Stokes, undeformed uniform-order boxes, FP64) against the
+oracle's Gauss path.
 
 - Residuals of perturbed states for orders 1..7 and every surface flux, to the parity bar
   (within 8x the FP64 oracle's distance to the long-double oracle, or 1e-12 relative).
@@ -78,6 +79,22 @@ def test_gauss_residual_parity(dg, orc, N, surf):
     g.close()
 
 
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("surf", ["roe", "ec"])
+def test_gauss_navier_stokes_residual_parity(dg, orc, N, surf):
+    """BR1 viscous terms on Gauss points: weak-form gradient, viscous flux from the traces."""
+    c = cfg(N=N, surf=surf, Re=100.0)
+    log(f"gauss NS residual N={N} {surf}")
+    U = perturbed(orc, c, seed=950 + N)
+    o64, o80 = orc.OracleSolver(**c), orc.OracleSolver(**c, precision="fp80")
+    o64.set_state(U)
+    o80.set_state(U)
+    g = dg.Solver(**c)
+    g.set_state(U)
+    parity(f"gauss NS N={N} {surf}", g.residual(), o64.residual(), o80.residual(), 18, (N + 1) ** 3)
+    g.close()
+
+
 def test_gauss_initial_condition_and_geometry(dg, orc):
     """The GPU's Gauss points (Sturm bisection) and the oracle's (Newton) give the same node
     coordinates and initial states to rounding; the metric terms of the affine box are exact."""
@@ -95,9 +112,9 @@ def test_gauss_initial_condition_and_geometry(dg, orc):
     g.close()
 
 
-@pytest.mark.parametrize("scheme", ["rk3", "rk4"])
-def test_gauss_trajectory_and_conservation(dg, orc, scheme):
-    c = cfg(ex=3, ey=3, ez=3, N=4, Ma=0.4)
+@pytest.mark.parametrize("scheme,Re", [("rk3", 0.0), ("rk4", 0.0), ("rk3", 400.0)])
+def test_gauss_trajectory_and_conservation(dg, orc, scheme, Re):
+    c = cfg(ex=3, ey=3, ez=3, N=4, Ma=0.4, Re=Re)
     U0 = perturbed(orc, c, seed=31, amp=(0.01, 0.02, 0.01))
     o, o80 = orc.OracleSolver(**c), orc.OracleSolver(**c, precision="fp80")
     for s in (o, o80):
@@ -114,7 +131,7 @@ def test_gauss_trajectory_and_conservation(dg, orc, scheme):
     Ug, Uo, U80 = g.state(), o.state(), o80.state()
     dd = lambda a, b: np.abs(a - b).reshape(27, 5, nn).max(axis=(0, 2))
     sc = np.abs(U80).reshape(27, 5, nn).max(axis=(0, 2))
-    log(f"[gauss {scheme}] gpu-vs-fp80 {dd(Ug, U80) / sc} fp64-vs-fp80 {dd(Uo, U80) / sc}")
+    log(f"[gauss {scheme} Re={Re}] gpu-vs-fp80 {dd(Ug, U80) / sc} fp64-vs-fp80 {dd(Uo, U80) / sc}")
     assert np.all(dd(Ug, U80) <= np.maximum(1e-14 * sc, 8 * dd(Uo, U80)))
     d1 = g.diagnostics()
     V = d0["volume"]
