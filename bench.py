@@ -235,10 +235,10 @@ def run_batch_vs_solo(specs, steps=50):
     n = len(specs)
     work = sum(5 * q["E"] ** 3 * (q["N"] + 1) ** 3 * 3 * steps for q in specs)
 
-    def make():
+    def make(precision="fp64"):
         out = []
         for q in specs:
-            s = dgsem.Solver(q["E"], N=q["N"], Ma=q["Ma"], Re=q["Re"])
+            s = dgsem.Solver(q["E"], N=q["N"], Ma=q["Ma"], Re=q["Re"], precision=precision)
             s.set_ic("tgv")
             out.append((s, s.suggest_dt(0.5)))
         return out
@@ -265,18 +265,38 @@ def run_batch_vs_solo(specs, steps=50):
     b.close()
     for s, _ in members:
         s.close()
+    # the chosen form: the same solves batched in FP32-bulk, against the plain FP64 solo runs
+    members = make("fp32_bulk")
+    b = dgsem.Batch([s for s, _ in members])
+    dts = [dt for _, dt in members]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.rk_step(dts, steps)
+    torch.cuda.synchronize()
+    t_b32 = time.perf_counter() - t0
+    dev = 0.0
+    for (s, _), r in zip(members, ref):
+        U = s.state().reshape(-1, 5, (s.N + 1) ** 3)
+        R = r.reshape(U.shape)
+        dev = max(dev, float((abs(U - R).max(axis=(0, 2)) / abs(R).max(axis=(0, 2))).max()))
+    b.close()
+    for s, _ in members:
+        s.close()
     return {"solves": n, "steps": steps, "solo_gdof_s": round(work / t_solo / 1e9, 3),
             "batch_gdof_s": round(work / t_batch / 1e9, 3), "speedup": round(t_solo / t_batch, 3),
             "launches_per_stage_batched": launches, "launches_per_stage_solo": n,
-            "results_bitwise_equal": bool(same)}
+            "results_bitwise_equal": bool(same),
+            "batch_fp32_bulk_gdof_s": round(work / t_b32 / 1e9, 3),
+            "speedup_fp32_bulk_batch_vs_fp64_solo": round(t_solo / t_b32, 3),
+            "fp32_bulk_state_rel_diff_vs_fp64": dev}
 
 
-def run_serving(n, rate, steps, budget_gib, chunk):
+def run_serving(n, rate, steps, budget_gib, chunk, precision="fp64"):
     """The serving stream: n solves from synth.serving_requests (seed 0) arriving as a Poisson
     process of the given rate (seed 0), admitted under an HBM budget, continuously batched."""
     from paper_2206_09733_amd import serve, synth
     reqs = serve.requests_from_specs(synth.serving_requests(n, seed=0),
-                                     synth.poisson_arrivals(n, rate, seed=0), steps=steps)
+                                     synth.poisson_arrivals(n, rate, seed=0), steps=steps, precision=precision)
     ex = serve.GpuExecutor(keep_state=False)
     sch = serve.Scheduler(ex, budget_gib * 2 ** 30, max_active=64, chunk_steps=chunk)
     t0 = time.perf_counter()
@@ -284,7 +304,7 @@ def run_serving(n, rate, steps, budget_gib, chunk):
     wall = time.perf_counter() - t0
     ex.close()
     st = serve.summarize(reqs, res, wall)
-    st.update({"requests": n, "arrival_rate_per_s": rate, "steps_per_solve": steps,
+    st.update({"precision": precision, "requests": n, "arrival_rate_per_s": rate, "steps_per_solve": steps,
                "hbm_budget_gib": budget_gib, "chunk_steps": chunk, "chunks": sch.chunks,
                "peak_active": sch.peak_active, "peak_gib": round(sch.peak_bytes / 2 ** 30, 2),
                "nonfinite_results": sum(1 for r in res if r.diagnostics and r.diagnostics["nonfinite"])})
@@ -408,8 +428,11 @@ def main():
         result["batch_vs_solo"] = {
             "serving_first_32": run_batch_vs_solo(synth.serving_requests(32, seed=0)),
             "small_ensemble_64": run_batch_vs_solo(small_ensemble(64), steps=100)}
+        # the served form computes in FP32-bulk; the same stream in FP64 for comparison
         result["serving"] = run_serving(args.serve_requests, args.serve_rate, args.serve_steps,
-                                        args.serve_budget_gib, 20)
+                                        args.serve_budget_gib, 20, precision="fp32_bulk")
+        result["serving_fp64"] = run_serving(args.serve_requests, args.serve_rate, args.serve_steps,
+                                             args.serve_budget_gib, 20, precision="fp64")
     if rank == 0 and not args.no_cpu_baseline:
         result["cpu_baseline"] = run_cpu_baseline()
     if rank == 0:

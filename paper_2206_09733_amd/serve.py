@@ -18,7 +18,8 @@ import numpy as np
 @dataclasses.dataclass
 class Request:
     """One solve: Taylor-Green vortex on the periodic box [0, 2 pi]^3 with E^3 elements of order
-    N, Mach Ma, Reynolds number Re (0 = Euler), advanced `steps` RK3 steps at CFL `cfl`."""
+    N, Mach Ma, Reynolds number Re (0 = Euler), advanced `steps` RK3 steps at CFL `cfl`, in
+    `precision` ("fp64" or "fp32_bulk")."""
     id: int
     E: int
     N: int
@@ -27,6 +28,7 @@ class Request:
     steps: int = 200
     arrival: float = 0.0
     cfl: float = 0.5
+    precision: str = "fp64"
 
     @property
     def nodes(self):
@@ -181,15 +183,15 @@ class GpuExecutor:
         self._probe = {}
 
     def required_bytes(self, req):
-        key = (req.E, req.N, req.Re > 0)
+        key = (req.E, req.N, req.Re > 0, req.precision)
         if key not in self._probe:
-            s = self.dg.Solver(req.E, N=req.N, Ma=req.Ma, Re=req.Re, bind=False)
+            s = self.dg.Solver(req.E, N=req.N, Ma=req.Ma, Re=req.Re, precision=req.precision, bind=False)
             self._probe[key] = s.required_bytes
             s.close()
         return self._probe[key]
 
     def admit(self, req):
-        s = self.dg.Solver(req.E, N=req.N, Ma=req.Ma, Re=req.Re, bind=False)
+        s = self.dg.Solver(req.E, N=req.N, Ma=req.Ma, Re=req.Re, precision=req.precision, bind=False)
         with self.torch.cuda.stream(self.setup):
             s.bind(self.device, stream=self.setup)
         s.set_ic("tgv")
@@ -231,7 +233,7 @@ class GpuExecutor:
             self.batch, self.batch_key = None, None
 
 
-def requests_from_specs(specs, arrivals, steps=200):
+def requests_from_specs(specs, arrivals, steps=200, precision="fp64"):
     """Requests from synth.serving_requests() specs and arrival times (seconds)."""
     return [Request(id=s["id"], E=s["E"], N=s["N"], Ma=s["Ma"], Re=s["Re"], steps=steps,
-                    arrival=float(a)) for s, a in zip(specs, arrivals)]
+                    arrival=float(a), precision=precision) for s, a in zip(specs, arrivals)]

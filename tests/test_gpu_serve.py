@@ -17,7 +17,7 @@ def dg():
     return dgsem
 
 
-def small_requests(n, seed, steps):
+def small_requests(n, seed, steps, mixed_precision=False):
     g = synth.rng(seed)
     arr = synth.poisson_arrivals(n, 400.0, seed)
     out = []
@@ -26,12 +26,16 @@ def small_requests(n, seed, steps):
         out.append(serve.Request(id=i, E=int(g.integers(2, 6)), N=int(g.integers(3, 6)),
                                  Ma=float(g.uniform(0.1, 0.8)),
                                  Re=float(g.uniform(400.0, 3200.0)) if viscous else 0.0,
-                                 steps=steps + int(g.integers(0, 9)), arrival=float(arr[i])))
+                                 steps=steps + int(g.integers(0, 9)), arrival=float(arr[i]),
+                                 precision="fp32_bulk" if mixed_precision and i % 2 else "fp64"))
     return out
 
 
-def test_served_results_equal_alone(dg):
-    reqs = small_requests(16, seed=5, steps=12)
+@pytest.mark.parametrize("mixed_precision", [False, True])
+def test_served_results_equal_alone(dg, mixed_precision):
+    """Each served result equals the same solve advanced alone, bitwise, also when FP64 and
+    FP32-bulk requests share the loop (they are batched in groups of their own precision)."""
+    reqs = small_requests(16, seed=5, steps=12, mixed_precision=mixed_precision)
     ex = serve.GpuExecutor()
     budget = 3 * max(ex.required_bytes(q) for q in reqs)   # memory, not arrivals, limits the mix
     sch = serve.Scheduler(ex, budget, max_active=8, chunk_steps=5)
@@ -46,7 +50,7 @@ def test_served_results_equal_alone(dg):
     assert st["completed"] == 16
     assert sch.peak_bytes <= budget and sch.peak_active > 1
     for q, r in zip(reqs, res):
-        s = dg.Solver(q.E, N=q.N, Ma=q.Ma, Re=q.Re)
+        s = dg.Solver(q.E, N=q.N, Ma=q.Ma, Re=q.Re, precision=q.precision)
         s.set_ic("tgv")
         dt = s.suggest_dt(q.cfl)
         s.rk_step(dt, q.steps)
