@@ -14,6 +14,7 @@ VOL = {"ec": 0, "central": 1, "ir": 2, "kg": 3, "pirozzoli": 4, "ducros": 5, "mo
 SURF = {"roe": 0, "llf": 1, "ec": 2, "central": 3, "es": 4, "ir": 5, "es_matrix": 6, "ld_roe": 7,
         "lf_global": 8}
 VISC = {"br1": 0, "br2": 1, "ip": 2}
+SVV_KERNEL = {"tadmor": 0, "maday": 1}
 IC = {"uniform": 0, "tgv": 1, "vortex": 2, "density_wave": 3}
 DIAG_KEYS = ["mass_rho", "mass_rhou", "mass_rhov", "mass_rhow", "mass_rhoE", "entropy_paper",
              "entropy", "ke", "enstrophy", "lambda_max", "rho_min", "p_min", "nonfinite", "volume"]
@@ -77,6 +78,11 @@ def _lib(precision="fp64"):
         L.orc_logmean.argtypes = [ctypes.c_double, ctypes.c_double]
         L.orc_viscous_flux.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_double,
                                        ctypes.c_double, _dp]
+        L.orc_set_svv.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_double]
+        L.orc_svv_residual.argtypes = [ctypes.c_void_p, _dp, _dp]
+        L.orc_svv_sensor.argtypes = [ctypes.c_void_p, _dp]
+        L.orc_svv_filter.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp]
+        L.orc_svv_flux.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]
         _libs[name] = L
     return _libs[name]
 
@@ -196,6 +202,23 @@ def viscous_flux(U, grad, gamma=1.4, Pr=0.71, Re=1600.0, precision="fp64"):
     return res.reshape(3, 5)
 
 
+def svv_filter(N, f, kernel="maday", cutoff=None, precision="fp64"):
+    """The modal SVV filter of one nodal field of an order-N element (f[k][j][i])."""
+    cutoff = N // 2 if cutoff is None else cutoff
+    out = np.zeros((N + 1) ** 3)
+    if _lib(precision).orc_svv_filter(int(N), SVV_KERNEL[kernel], int(cutoff), _ptr(_f64(f, (N + 1) ** 3)),
+                                      _ptr(out)):
+        raise ValueError("orc_svv_filter rejected the arguments")
+    return out
+
+
+def svv_flux(U, Gw, mu_a, gamma=1.4, Pr=0.71, precision="fp64"):
+    """Unfiltered artificial flux L^T D L G at one state; Gw[3c+x] = d w_c / d x_x; rows = directions."""
+    res = np.zeros(15)
+    _lib(precision).orc_svv_flux(_ptr(_f64(U, 5)), _ptr(_f64(Gw, 15)), gamma, Pr, float(mu_a), _ptr(res))
+    return res.reshape(3, 5)
+
+
 # ---------------------------------------------------------------------------- solver
 class OracleSolver:
     """Periodic-box DGSEM solver on the CPU (plain loops, fp64 or fp80)."""
@@ -301,3 +324,25 @@ class OracleSolver:
 
     def entropy_production(self, R):
         return self.L.orc_entropy_production(self.h, _ptr(_f64(R, 5 * self.nodes)))
+
+    def set_svv(self, mu_a, kernel="maday", cutoff=None, sensor=-1.0):
+        """Spectral vanishing viscosity: artificial viscosity mu_a, filter kernel and cutoff mode
+        (default N // 2 of the element orders' minimum), troubled-element sensor threshold
+        (< 0: none)."""
+        if cutoff is None:
+            cutoff = min(self.elem(e)[0][d] for e in range(self.E) for d in range(3)) // 2
+        if self.L.orc_set_svv(self.h, float(mu_a), SVV_KERNEL[kernel], int(cutoff), float(sensor)):
+            raise ValueError("orc_set_svv rejected the configuration")
+
+    def svv_residual(self):
+        """The artificial-viscosity part of the residual, and the entropy form sum <y, F* y>."""
+        R = np.zeros(5 * self.nodes)
+        form = ctypes.c_double()
+        if self.L.orc_svv_residual(self.h, _ptr(R), ctypes.byref(form)):
+            raise ValueError("SVV is not set")
+        return R, form.value
+
+    def svv_sensor(self):
+        out = np.zeros(self.E)
+        self.L.orc_svv_sensor(self.h, _ptr(out))
+        return out

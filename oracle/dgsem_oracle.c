@@ -331,6 +331,10 @@ struct orc_solver {
   real lam_g;      /* global Lax-Friedrichs: max |v| + c of the state being evaluated */
   const gll_t* T;  /* the node tables of this solver: GLL or GL */
   real visc_eta;   /* BR2 lifting factor, or interior-penalty factor */
+  int svv;         /* spectral vanishing viscosity on (section 8c) */
+  int svv_kernel, svv_cut;
+  real svv_mu, svv_kappa, svv_sensor;
+  real *Gw, *Fa;   /* entropy-variable gradients (15 per node), filtered fluxes (15 per node) */
   real *X, *Ja, *J; /* coordinates, metric terms, Jacobian */
   real *U, *dU, *G, *R;
 };
@@ -548,6 +552,7 @@ void orc_destroy(orc_solver* s) {
   free(s->N); free(s->off); free(s->nbr);
   free(s->X); free(s->Ja); free(s->J);
   free(s->U); free(s->dU); free(s->G); free(s->R);
+  free(s->Gw); free(s->Fa);
   free(s);
 }
 
@@ -1006,30 +1011,33 @@ static inline void gvars(const real u[5], real gamma, real g[4]) {
   g[3] = w.p / w.rho;
 }
 
-static void compute_gradients(orc_solver* s, const real* U, real* Gout) {
+/* BR1 gradient of nv nodal variables vars(u) (nv <= 5): Gout[off*3nv + (3c+x)*nn + node] */
+typedef void (*vars_fn)(const real u[5], real gamma, real* g);
+
+static void br1_gradient(orc_solver* s, const real* U, int nv, vars_fn vars, real* Gout) {
 #pragma omp parallel for schedule(static)
   for (int e = 0; e < s->E; e++) {
     const int* N = s->N[e];
     int nn = nn_of(s, e);
-    real* G = Gout + s->off[e] * 12;
+    real* G = Gout + s->off[e] * 3 * nv;
     for (int k = 0; k <= N[2]; k++)
       for (int j = 0; j <= N[1]; j++)
         for (int i = 0; i <= N[0]; i++) {
           int ii[3] = {i, j, k};
           long q = node_of(s, e, ii);
-          real u[5], g[4];
+          real u[5], g[5];
           load5(s, U, e, q, u);
-          gvars(u, s->gamma, g);
-          real acc[12] = {0};
+          vars(u, s->gamma, g);
+          real acc[15] = {0};
           for (int d = 0; d < 3; d++) {
-            real a[4] = {0, 0, 0, 0};
+            real a[5] = {0, 0, 0, 0, 0};
             int jj[3] = {i, j, k};
             for (int m = 0; m <= N[d]; m++) {
               jj[d] = m;
-              real um[5], gm[4];
+              real um[5], gm[5];
               load5(s, U, e, node_of(s, e, jj), um);
-              gvars(um, s->gamma, gm);
-              for (int c = 0; c < 4; c++) a[c] += GLL[N[d]].D[ii[d]][m] * gm[c];
+              vars(um, s->gamma, gm);
+              for (int c = 0; c < nv; c++) a[c] += GLL[N[d]].D[ii[d]][m] * gm[c];
             }
             for (int side = 0; side < 2; side++) {
               int at = side ? N[d] : 0;
@@ -1037,25 +1045,27 @@ static void compute_gradients(orc_solver* s, const real* U, real* Gout) {
               int ne = s->nbr[6 * e + 2 * d + side];
               int kk[3] = {i, j, k};
               kk[d] = side ? 0 : s->N[ne][d];
-              real un[5], gn[4];
+              real un[5], gn[5];
               load5(s, U, ne, node_of(s, ne, kk), un);
-              gvars(un, s->gamma, gn);
+              vars(un, s->gamma, gn);
               real wgt = 1 / GLL[N[d]].w[at];
-              for (int c = 0; c < 4; c++) {
+              for (int c = 0; c < nv; c++) {
                 real jump = (g[c] + gn[c]) / 2 - g[c];
                 a[c] += side ? wgt * jump : -wgt * jump;
               }
             }
             real n[3];
             load_ja(s, e, q, d, n);
-            for (int c = 0; c < 4; c++)
+            for (int c = 0; c < nv; c++)
               for (int x = 0; x < 3; x++) acc[3 * c + x] += n[x] * a[c];
           }
           real Jq = s->J[s->off[e] + q];
-          for (int t = 0; t < 12; t++) G[(long)t * nn + q] = acc[t] / Jq;
+          for (int t = 0; t < 3 * nv; t++) G[(long)t * nn + q] = acc[t] / Jq;
         }
   }
 }
+
+static void compute_gradients(orc_solver* s, const real* U, real* Gout) { br1_gradient(s, U, 4, gvars, Gout); }
 
 /* contravariant viscous flux of node q of element e along xi_d */
 static void contra_visc(const orc_solver* s, const real* U, const real* Gall, int e, long q, int d, const real* Sopt,
@@ -1410,6 +1420,250 @@ static void element_residual_gauss(const orc_solver* s, const real* U, const rea
       }
 }
 
+/* ------------------------------------------------------------------------------------------
+ * 8c. Spectral vanishing viscosity (section "Shock capturing").
+ *     The artificial flux F_a is the Navier-Stokes viscous flux with viscosity mu_a and
+ *     conductivity kappa_a = mu_a gamma / ((gamma-1) Pr), written as F_a = B G with G the BR1
+ *     gradient of the entropy variables w = (.., rho v/p, -rho/p) (eq. shock:fluxmatrix).
+ *     With theta = p/rho, grad v_k = theta (grad w_{k+1} + v_k grad w_5) and grad theta =
+ *     theta^2 grad w_5, so B = L^T D L with the eight rows of L
+ *       L_m G = <E_m, Z>  (m = 1..5),   Z_kj = d_j w_{k+1} + v_k d_j w_5,
+ *       L_m G = d_j w_5   (m = 6..8, j = m - 6),
+ *     E_m an orthonormal basis of the symmetric traceless 3x3 matrices, and
+ *       D = (2 mu_a theta five times, kappa_a theta^2 three times):
+ *     L^T D L G is the stress mu_a (grad v + grad v^T - 2/3 div v I) and the heat flux
+ *     kappa_a grad theta, i.e. the Navier-Stokes viscous flux.
+ *     The filtered flux (eq. shock:filteredflux): F_a^F = J^{-1/2} L^T D^{1/2} F*(sqrt(J D) L G),
+ *     the filter F* applied to each of the eight nodal fields y_m = sqrt(J D_m) L_m G of the
+ *     element in the Legendre modal space: transform, multiply mode (a,b,c) by
+ *     1 - (1 - s_a)(1 - s_b)(1 - s_c), transform back.  One-direction kernel: s_k = 0 for k <= M;
+ *     for k > M, s_k = 1 (Tadmor's step) or exp(-((k-N)/(k-M))^2) (Maday et al.).
+ *     Sensor: s_rho = sum over the nodes of w_i w_j w_k J |grad_xi rho|^2 (the element integral of
+ *     the paper by the nodal quadrature, grad_xi rho the element's own derivative); an element
+ *     with s_rho above the threshold takes the unfiltered flux L^T D L G.
+ *     Residual: as the viscous terms of section 8, J R_a = sum_d D_d F~^d
+ *     + (1/w_N)(F~* - F~) at xi_d = +1 - (1/w_0)(F~* - F~) at -1, F~^d = Ja^d . F_a^F and F~* the
+ *     average of the two sides' filtered fluxes along the owner's Ja^d.
+ * ---------------------------------------------------------------------------------------- */
+static real svv_sigma(int N, int kernel, int M, int k) {
+  if (k <= M) return 0;
+  if (kernel == ORC_SVV_TADMOR) return 1;
+  real r = (real)(k - N) / (real)(k - M);
+  return REXP(-r * r);
+}
+
+/* orthonormal basis of the symmetric traceless 3x3 matrices (Frobenius inner product) */
+static void svv_basis(real E[5][3][3]) {
+  for (int m = 0; m < 5; m++)
+    for (int a = 0; a < 3; a++)
+      for (int b = 0; b < 3; b++) E[m][a][b] = 0;
+  real r2 = 1 / RSQRT((real)2), r6 = 1 / RSQRT((real)6);
+  E[0][0][1] = E[0][1][0] = r2;
+  E[1][0][2] = E[1][2][0] = r2;
+  E[2][1][2] = E[2][2][1] = r2;
+  E[3][0][0] = r2; E[3][1][1] = -r2;
+  E[4][0][0] = r6; E[4][1][1] = r6; E[4][2][2] = -2 * r6;
+}
+
+/* rows L[8][15] (over G[3c + x], c the entropy variable, x the direction) and D[8] at one state */
+static void svv_factors(const real u[5], real gamma, real mu, real kappa, real L[8][15], real D[8]) {
+  prim_t q = prim(u, gamma);
+  real th = q.p / q.rho;
+  real E[5][3][3];
+  svv_basis(E);
+  for (int m = 0; m < 8; m++)
+    for (int t = 0; t < 15; t++) L[m][t] = 0;
+  for (int m = 0; m < 5; m++) {
+    for (int k = 0; k < 3; k++)
+      for (int j = 0; j < 3; j++) {
+        L[m][3 * (k + 1) + j] += E[m][k][j];
+        L[m][3 * 4 + j] += E[m][k][j] * q.v[k];
+      }
+    D[m] = 2 * mu * th;
+  }
+  for (int j = 0; j < 3; j++) {
+    L[5 + j][3 * 4 + j] = 1;
+    D[5 + j] = kappa * th * th;
+  }
+}
+
+/* Legendre polynomial P_a at the Lobatto node i of order N, and the discrete norm of P_a */
+static real svv_leg(int N, int a, int i) {
+  long double L, dL;
+  legendre(a, GLL[N].xl[i], &L, &dL);
+  return (real)L;
+}
+
+static real svv_norm(int N, int a) {
+  real g = 0;
+  for (int i = 0; i <= N; i++) g += GLL[N].w[i] * svv_leg(N, a, i) * svv_leg(N, a, i);
+  return g;
+}
+
+/* the modal filter of one nodal field f of an element with orders N[3] */
+static void svv_filter_field(const int N[3], int kernel, int M, const real* f, real* out) {
+  const int n0 = N[0] + 1, n1 = N[1] + 1, n2 = N[2] + 1, nn = n0 * n1 * n2;
+  real* c = (real*)malloc(sizeof(real) * nn);
+  for (int cc = 0; cc < n2; cc++)
+    for (int b = 0; b < n1; b++)
+      for (int a = 0; a < n0; a++) {
+        real acc = 0;
+        for (int k = 0; k < n2; k++)
+          for (int j = 0; j < n1; j++)
+            for (int i = 0; i < n0; i++)
+              acc += GLL[N[0]].w[i] * svv_leg(N[0], a, i) * GLL[N[1]].w[j] * svv_leg(N[1], b, j) *
+                     GLL[N[2]].w[k] * svv_leg(N[2], cc, k) * f[nidx(n0, n1, i, j, k)];
+        acc /= svv_norm(N[0], a) * svv_norm(N[1], b) * svv_norm(N[2], cc);
+        real sa = svv_sigma(N[0], kernel, M, a), sb = svv_sigma(N[1], kernel, M, b),
+             sc = svv_sigma(N[2], kernel, M, cc);
+        c[nidx(n0, n1, a, b, cc)] = acc * (1 - (1 - sa) * (1 - sb) * (1 - sc));
+      }
+  for (int k = 0; k < n2; k++)
+    for (int j = 0; j < n1; j++)
+      for (int i = 0; i < n0; i++) {
+        real acc = 0;
+        for (int cc = 0; cc < n2; cc++)
+          for (int b = 0; b < n1; b++)
+            for (int a = 0; a < n0; a++)
+              acc += svv_leg(N[0], a, i) * svv_leg(N[1], b, j) * svv_leg(N[2], cc, k) * c[nidx(n0, n1, a, b, cc)];
+        out[nidx(n0, n1, i, j, k)] = acc;
+      }
+  free(c);
+}
+
+/* the sensor s_rho of element e */
+static real svv_sensor(const orc_solver* s, const real* U, int e) {
+  const int* N = s->N[e];
+  real acc = 0;
+  for (int k = 0; k <= N[2]; k++)
+    for (int j = 0; j <= N[1]; j++)
+      for (int i = 0; i <= N[0]; i++) {
+        int ii[3] = {i, j, k};
+        long q = node_of(s, e, ii);
+        real g2 = 0;
+        for (int d = 0; d < 3; d++) {
+          real a = 0;
+          int jj[3] = {i, j, k};
+          for (int m = 0; m <= N[d]; m++) {
+            jj[d] = m;
+            a += GLL[N[d]].D[ii[d]][m] * U[s->off[e] * 5 + node_of(s, e, jj)];
+          }
+          g2 += a * a;
+        }
+        acc += GLL[N[0]].w[i] * GLL[N[1]].w[j] * GLL[N[2]].w[k] * s->J[s->off[e] + q] * g2;
+      }
+  return acc;
+}
+
+/* filtered fluxes of element e into Fa[off*15 + (5n+v)*nn + node] from the entropy-variable
+ * gradients Gw; returns sum_m <y_m, F* y_m> (nodal quadrature, the entropy form) */
+static real svv_element_flux(const orc_solver* s, const real* U, const real* Gw, int e, real* Fa) {
+  const int* N = s->N[e];
+  int nn = nn_of(s, e);
+  real* y = (real*)malloc(sizeof(real) * 8 * nn);
+  real* yf = (real*)malloc(sizeof(real) * 8 * nn);
+  real* Dn = (real*)malloc(sizeof(real) * 8 * nn);
+  real (*Ln)[8][15] = (real(*)[8][15])malloc(sizeof(real) * 8 * 15 * nn);
+  const int trouble = s->svv_sensor >= 0 && svv_sensor(s, U, e) > s->svv_sensor;
+  for (long q = 0; q < nn; q++) {
+    real u[5], G[15];
+    load5(s, U, e, q, u);
+    for (int t = 0; t < 15; t++) G[t] = Gw[s->off[e] * 15 + (long)t * nn + q];
+    svv_factors(u, s->gamma, s->svv_mu, s->svv_kappa, Ln[q], &Dn[8 * q]);
+    real Jq = s->J[s->off[e] + q];
+    for (int m = 0; m < 8; m++) {
+      real lg = 0;
+      for (int t = 0; t < 15; t++) lg += Ln[q][m][t] * G[t];
+      y[(long)m * nn + q] = RSQRT(Jq * Dn[8 * q + m]) * lg;
+    }
+  }
+  real form = 0;
+  for (int m = 0; m < 8; m++) {
+    if (trouble) for (long q = 0; q < nn; q++) yf[(long)m * nn + q] = y[(long)m * nn + q];
+    else svv_filter_field(N, s->svv_kernel, s->svv_cut, y + (long)m * nn, yf + (long)m * nn);
+  }
+  for (int k = 0; k <= N[2]; k++)
+    for (int j = 0; j <= N[1]; j++)
+      for (int i = 0; i <= N[0]; i++) {
+        int ii[3] = {i, j, k};
+        long q = node_of(s, e, ii);
+        real wq = GLL[N[0]].w[i] * GLL[N[1]].w[j] * GLL[N[2]].w[k];
+        for (int m = 0; m < 8; m++) form += wq * y[(long)m * nn + q] * yf[(long)m * nn + q];
+        real Jq = s->J[s->off[e] + q];
+        for (int x = 0; x < 3; x++)
+          for (int c = 0; c < 5; c++) {
+            real acc = 0;
+            for (int m = 0; m < 8; m++) acc += Ln[q][m][3 * c + x] * RSQRT(Dn[8 * q + m]) * yf[(long)m * nn + q];
+            Fa[s->off[e] * 15 + (long)(5 * x + c) * nn + q] = acc / RSQRT(Jq);
+          }
+      }
+  free(y); free(yf); free(Dn); free(Ln);
+  return form;
+}
+
+/* contravariant filtered flux of node q of element e along S */
+static void svv_contra(const orc_solver* s, const real* Fa, int e, long q, const real S[3], real F[5]) {
+  int nn = nn_of(s, e);
+  for (int v = 0; v < 5; v++) {
+    F[v] = 0;
+    for (int x = 0; x < 3; x++) F[v] += S[x] * Fa[s->off[e] * 15 + (long)(5 * x + v) * nn + q];
+  }
+}
+
+/* adds the artificial-viscosity residual of element e to R (R laid out as the state) */
+static void svv_element_residual(const orc_solver* s, const real* Fa, int e, real* R) {
+  const int* N = s->N[e];
+  int nn = nn_of(s, e);
+  for (int k = 0; k <= N[2]; k++)
+    for (int j = 0; j <= N[1]; j++)
+      for (int i = 0; i <= N[0]; i++) {
+        int ii[3] = {i, j, k};
+        long q = node_of(s, e, ii);
+        real Ra[5] = {0, 0, 0, 0, 0};
+        for (int d = 0; d < 3; d++) {
+          int jj[3] = {i, j, k};
+          for (int m = 0; m <= N[d]; m++) {
+            jj[d] = m;
+            long qm = node_of(s, e, jj);
+            real S[3], F[5];
+            load_ja(s, e, qm, d, S);
+            svv_contra(s, Fa, e, qm, S, F);
+            for (int v = 0; v < 5; v++) Ra[v] += GLL[N[d]].D[ii[d]][m] * F[v];
+          }
+          for (int side = 0; side < 2; side++) {
+            int at = side ? N[d] : 0;
+            if (ii[d] != at) continue;
+            int oth = s->nbr[6 * e + 2 * d + side];
+            int kk[3] = {i, j, k};
+            kk[d] = side ? 0 : s->N[oth][d];
+            long qo = node_of(s, oth, kk);
+            real S[3], own[5], Fe[5], Fo[5], nq[3];
+            if (side) load_ja(s, e, q, d, S);
+            else load_ja(s, oth, qo, d, S);
+            svv_contra(s, Fa, e, q, S, Fe);
+            svv_contra(s, Fa, oth, qo, S, Fo);
+            load_ja(s, e, q, d, nq);
+            svv_contra(s, Fa, e, q, nq, own);
+            real wgt = 1 / GLL[N[d]].w[at];
+            for (int v = 0; v < 5; v++) Ra[v] += (side ? wgt : -wgt) * ((Fe[v] + Fo[v]) / 2 - own[v]);
+          }
+        }
+        real Jq = s->J[s->off[e] + q];
+        for (int v = 0; v < 5; v++) R[(long)v * nn + q] += Ra[v] / Jq;
+      }
+}
+
+/* the artificial-viscosity residual of U added to R; returns the entropy form sum <y, F* y> */
+static real svv_residual(orc_solver* s, const real* U, real* R) {
+  br1_gradient(s, U, 5, entropy_vars, s->Gw);
+  real form = 0;
+#pragma omp parallel for schedule(dynamic, 4) reduction(+ : form)
+  for (int e = 0; e < s->E; e++) form += svv_element_flux(s, U, s->Gw, e, s->Fa);
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int e = 0; e < s->E; e++) svv_element_residual(s, s->Fa, e, R + s->off[e] * 5);
+  return form;
+}
+
 static void residual(orc_solver* s, const real* U, real* R) {
   if (s->surf == ORC_SURF_LF_GLOBAL) {
     /* the largest |v| + c over the nodes of the state the residual is taken of */
@@ -1435,6 +1689,7 @@ static void residual(orc_solver* s, const real* U, real* R) {
   if (s->viscous) compute_gradients(s, U, s->G);
 #pragma omp parallel for schedule(dynamic, 4)
   for (int e = 0; e < s->E; e++) element_residual(s, U, s->G, e, R + s->off[e] * 5);
+  if (s->svv) svv_residual(s, U, R);
 }
 
 int orc_residual(orc_solver* s, double* Rout) {
@@ -1794,5 +2049,82 @@ int orc_viscous_flux(const double* U, const double* grad, double gamma, double P
   real kappa = mu * (real)gamma / (((real)gamma - 1) * (real)Pr);
   viscous_flux(u, g, gamma, mu, kappa, f);
   to_dbl(f, Fv, 15);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------------------------
+ * 13. Spectral vanishing viscosity (section 8c) exports.
+ * ---------------------------------------------------------------------------------------- */
+int orc_set_svv(orc_solver* s, double mu_a, int kernel, int cutoff, double sensor_threshold) {
+  if (!s || s->gauss || !(mu_a >= 0) || kernel < ORC_SVV_TADMOR || kernel > ORC_SVV_MADAY) return -1;
+  if (mu_a == 0) { s->svv = 0; return 0; }
+  for (int e = 0; e < s->E; e++)
+    for (int d = 0; d < 3; d++) {
+      if (cutoff < -1 || cutoff > s->N[e][d]) return -1;
+      int r = s->nbr[6 * e + 2 * d + 1];
+      for (int t = 0; t < 3; t++)
+        if (t != d && s->N[e][t] != s->N[r][t]) return -1;  /* conforming faces only */
+    }
+  if (!s->Gw) s->Gw = (real*)calloc(15 * s->ntot, sizeof(real));
+  if (!s->Fa) s->Fa = (real*)calloc(15 * s->ntot, sizeof(real));
+  if (!s->Gw || !s->Fa) return -1;
+  s->svv = 1;
+  s->svv_mu = mu_a;
+  s->svv_kappa = s->svv_mu * s->gamma / ((s->gamma - 1) * s->Pr);
+  s->svv_kernel = kernel;
+  s->svv_cut = cutoff;
+  s->svv_sensor = sensor_threshold;
+  return 0;
+}
+
+/* the artificial-viscosity part of the residual of the current state; *form (if given) receives
+ * sum_m <y_m, F* y_m> over the elements */
+int orc_svv_residual(orc_solver* s, double* Ra, double* form) {
+  if (!s || !s->svv) return -1;
+  real* R = (real*)calloc(5 * s->ntot, sizeof(real));
+  if (!R) return -1;
+  real f = svv_residual(s, s->U, R);
+  for (long i = 0; i < 5 * s->ntot; i++) Ra[i] = (double)R[i];
+  if (form) *form = (double)f;
+  free(R);
+  return 0;
+}
+
+int orc_svv_sensor(orc_solver* s, double* sens) {
+  if (!s) return -1;
+  for (int e = 0; e < s->E; e++) sens[e] = (double)svv_sensor(s, s->U, e);
+  return 0;
+}
+
+int orc_svv_filter(int N, int kernel, int cutoff, const double* f, double* out) {
+  if (N < 1 || N > ORC_NMAX || cutoff < -1 || cutoff > N || kernel < ORC_SVV_TADMOR || kernel > ORC_SVV_MADAY)
+    return -1;
+  gll_init();
+  int n = N + 1, nn = n * n * n, Ns[3] = {N, N, N};
+  real* a = (real*)malloc(sizeof(real) * 2 * nn);
+  to_real(f, a, nn);
+  svv_filter_field(Ns, kernel, cutoff, a, a + nn);
+  to_dbl(a + nn, out, nn);
+  free(a);
+  return 0;
+}
+
+/* the unfiltered flux L^T D L G at one state, G[3c+x] = d w_c / d x_x; F[5x+v] */
+int orc_svv_flux(const double* U, const double* Gw, double gamma, double Pr, double mu_a, double* F) {
+  real u[5], G[15], L[8][15], D[8];
+  to_real(U, u, 5);
+  to_real(Gw, G, 15);
+  real mu = mu_a, kappa = mu * (real)gamma / (((real)gamma - 1) * (real)Pr);
+  svv_factors(u, gamma, mu, kappa, L, D);
+  for (int x = 0; x < 3; x++)
+    for (int c = 0; c < 5; c++) {
+      real acc = 0;
+      for (int m = 0; m < 8; m++) {
+        real lg = 0;
+        for (int t = 0; t < 15; t++) lg += L[m][t] * G[t];
+        acc += L[m][3 * c + x] * D[m] * lg;
+      }
+      F[5 * x + c] = (double)acc;
+    }
   return 0;
 }

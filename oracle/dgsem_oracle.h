@@ -34,6 +34,7 @@ enum { ORC_VOL_EC = 0, ORC_VOL_CENTRAL = 1, ORC_VOL_IR = 2, ORC_VOL_KG = 3, ORC_
 enum { ORC_SURF_ROE = 0, ORC_SURF_LLF = 1, ORC_SURF_EC = 2, ORC_SURF_CENTRAL = 3, ORC_SURF_ES = 4, ORC_SURF_IR = 5,
        ORC_SURF_ES_MATRIX = 6, ORC_SURF_LOW_DISS_ROE = 7, ORC_SURF_LF_GLOBAL = 8 };
 enum { ORC_VISC_BR1 = 0, ORC_VISC_BR2 = 1, ORC_VISC_IP = 2 };
+enum { ORC_SVV_TADMOR = 0, ORC_SVV_MADAY = 1 };
 enum { ORC_IC_UNIFORM = 0, ORC_IC_TGV = 1, ORC_IC_VORTEX = 2, ORC_IC_DENSITY_WAVE = 3 };
 
 typedef struct orc_solver orc_solver;
@@ -95,6 +96,18 @@ double orc_entropy(const double* U, double gamma);            /* -rho s/(gamma-1
 double orc_logmean(double a, double b);
 int orc_viscous_flux(const double* U, const double* grad, double gamma, double Pr, double Re,
                      double* Fv);                             /* Fv[n*5+v], 3 directions      */
+
+/* Spectral vanishing viscosity (section "Shock capturing"): the Navier-Stokes viscous flux with
+ * viscosity mu_a (conductivity from Pr) in entropy variables, half-filtered in the Legendre modal
+ * space by Tadmor's or Maday's kernel with cutoff mode M (-1..N), and unfiltered in elements whose
+ * density sensor exceeds sensor_threshold (< 0: no sensor).  Added to the residual of Lobatto
+ * solvers with conforming faces; mu_a = 0 switches it off. */
+int orc_set_svv(orc_solver* s, double mu_a, int kernel, int cutoff, double sensor_threshold);
+int orc_svv_residual(orc_solver* s, double* Ra, double* form); /* SVV part alone; entropy form */
+int orc_svv_sensor(orc_solver* s, double* sens);              /* s_rho of every element       */
+int orc_svv_filter(int N, int kernel, int cutoff, const double* f, double* out); /* one field */
+int orc_svv_flux(const double* U, const double* Gw, double gamma, double Pr, double mu_a,
+                 double* F);                                  /* unfiltered L^T D L G, F[5x+v] */
 
 #ifdef __cplusplus
 }
