@@ -120,11 +120,34 @@ typedef struct {
  * The choice is this library's reading: the paper names the three fluxes, not their constants. */
 enum { DG_VISC_BR1 = 0, DG_VISC_BR2 = 1, DG_VISC_IP = 2 };
 
+/* Spectral vanishing viscosity (section "Shock capturing"), an artificial-viscosity term added
+ * to the residual when svv_mu > 0:
+ *   F_a  the Navier-Stokes viscous flux with viscosity svv_mu and conductivity
+ *        svv_mu gamma / ((gamma-1) Pr), written in the entropy variables w as B grad w
+ *        (eq. shock:fluxmatrix), grad w the BR1 gradient;
+ *   B = L^T D L  with L grad w the symmetric traceless part of Z_kj = d_j w_{k+1} + v_k d_j w_5
+ *        (D = 2 svv_mu p/rho) and grad w_5 (D = kappa (p/rho)^2);
+ *   filtered flux J^{-1/2} L^T D^{1/2} F*(sqrt(J D) L grad w) (eq. shock:filteredflux), F* the
+ *        Legendre modal filter of each element: mode (a,b,c) times 1 - (1-s_a)(1-s_b)(1-s_c),
+ *        s_k = 0 for k <= svv_cutoff, and for k above it 1 (DG_SVV_TADMOR) or
+ *        exp(-((k-N)/(k-svv_cutoff))^2) (DG_SVV_MADAY);
+ *   sensor: an element whose s = sum_nodes w_i w_j w_k J |grad_xi rho|^2 exceeds svv_sensor
+ *        (>= 0) takes the unfiltered flux B grad w; svv_sensor < 0: no sensor;
+ *   residual: the divergence of the filtered flux with BR1 face terms (average of the two
+ *        sides' fluxes).
+ * The paper leaves the factorisation, the 3D kernel and the sensor's use to cited works: these
+ * are this library's readings.  Uniform-order Gauss-Lobatto meshes, FP64, not in batches. */
+enum { DG_SVV_TADMOR = 0, DG_SVV_MADAY = 1 };
+
 typedef struct {
   double gamma, Pr, Ma, Re;
   int vol_flux, surf_flux, precision;
   int visc_flux;    /* DG_VISC_*; used when Re > 0 */
   double visc_eta;  /* BR2 lifting factor or interior-penalty factor; 0 = the default above */
+  double svv_mu;    /* spectral vanishing viscosity: artificial viscosity, 0 = off */
+  int svv_kernel;   /* DG_SVV_TADMOR or DG_SVV_MADAY */
+  int svv_cutoff;   /* cutoff mode, -1..N (-1 with DG_SVV_TADMOR: no filtering) */
+  double svv_sensor; /* troubled-element threshold of the density sensor; < 0: none */
 } dg_physics;
 
 /* Diagnostics, all FP64 with Gauss-Lobatto quadrature w_i w_j w_k J, reduced in a fixed order
@@ -159,7 +182,9 @@ int dg_mesh_info(const dg_mesh* m, long long* n_elements, long long* n_nodes, in
  * a compiled kernel (uniform orders 1..7 are compiled), for a mixed-order mesh with Re > 0
  * (mixed-order meshes are evaluated for the Euler equations, in FP64 or FP32-bulk), and for
  * DG_FP32_BULK with a volume flux other than DG_VOL_EC / DG_VOL_CENTRAL or a surface flux other
- * than DG_SURF_ROE / LLF / EC / CENTRAL. */
+ * than DG_SURF_ROE / LLF / EC / CENTRAL.  Spectral vanishing viscosity (svv_mu > 0): DG_EINVAL
+ * for an unknown kernel, a cutoff outside [-1, N], Pr <= 0 or a NaN threshold; DG_EUNSUPPORTED
+ * on a mixed-order or Gauss-Legendre mesh or in FP32-bulk; svv_mu < 0 or non-finite: DG_EINVAL. */
 int dg_solver_create(const dg_mesh* m, const dg_physics* p, dg_solver** out);
 /* Bytes of device memory the solver needs (host-only; used for admission control). */
 int dg_solver_required_bytes(const dg_solver* s, size_t* bytes);
@@ -266,7 +291,8 @@ void dg_solver_destroy(dg_solver* s);
  * after the work the members have pending there (e.g. by synchronising those streams) and does
  * not use a member on its own stream while batch steps are pending.  The solvers stay owned by
  * the caller and must outlive the batch.  Errors: DG_EINVAL for NULL, n < 1 or a repeated
- * member or members with different time schemes; DG_ESTATE for an unbound member. */
+ * member or members with different time schemes; DG_ESTATE for an unbound member;
+ * DG_EUNSUPPORTED for a member with spectral vanishing viscosity. */
 int dg_batch_create(dg_solver* const* solvers, int n, void* hip_stream, dg_batch** out);
 /* Advance every member nsteps steps of the RK3 of dg_rk_step, member i with step dts[i] (n
  * doubles).  Only enqueues work on the batch's stream.  Like dg_rk_step, the launches of one

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "dg_internal.h"
+#include "svv.h"
 #include "dgsem.h"
 
 namespace dg {
@@ -80,12 +81,15 @@ struct dg_solver {
   double agraph_cfl[2] = {0.0, 0.0};
   dg::View* dev_view = nullptr;      // device copy of v (inside the caller's buffer)
   int scheme = DG_RK3_WILLIAMSON;    // time scheme of dg_rk_step
+  bool svv_on = false;               // spectral vanishing viscosity after every stage kernel
+  dg::SvvArgs svv{};
 };
 
 namespace {
 
 struct Plan {
-  size_t tab, nbr, X, Ja, J, invJ, U0, U1, dU, R, Fvf, part, diag, adapt, elem, work, mtab, Fs, Tr, Q, self, total;
+  size_t tab, nbr, X, Ja, J, invJ, U0, U1, dU, R, Fvf, part, diag, adapt, elem, work, mtab, Fs, Tr, Q, svvtab, Fa,
+      self, total;
   size_t tab_n, mtab_n;
 };
 
@@ -135,6 +139,8 @@ Plan make_plan(const dg_solver* s) {
   p.Fs = mixed ? take(sizeof(double) * dg::kMixFaceDoubles * E) : 0;
   p.Tr = s->mesh.gauss ? take(sizeof(double) * E * 6 * 5 * nf) : 0;
   p.Q = s->mesh.gauss && s->phys.Re > 0 ? take(sizeof(double) * 12 * nt) : 0;
+  p.svvtab = s->phys.svv_mu > 0 ? take(sizeof(double) * n * n) : 0;
+  p.Fa = s->phys.svv_mu > 0 ? take(sizeof(double) * 12 * nt) : 0;
   p.self = take(sizeof(dg::View));  // device copy of the View, read by batched launches
   p.total = off;
   return p;
@@ -209,7 +215,9 @@ hipError_t run_stage(dg_solver* s, double dt, double a, double b, int mode) {
     hipError_t e = timed(s, DG_K_GRADIENT, [&] { return dg::launch_gradient(s->v, s->cur, s->stream); });
     if (e != hipSuccess) return e;
   }
-  return timed(s, DG_K_STAGE, [&] { return launch_stage_any(s, dt, a, b, mode); });
+  hipError_t e = timed(s, DG_K_STAGE, [&] { return launch_stage_any(s, dt, a, b, mode); });
+  if (e != hipSuccess || !s->svv_on) return e;
+  return timed(s, DG_K_OTHER, [&] { return dg::launch_svv(s->v, s->cur, s->svv, dt, b, mode, s->stream); });
 }
 
 hipError_t launch_diag_any(dg_solver* s) {
@@ -440,6 +448,15 @@ int dg_solver_create(const dg_mesh* m, const dg_physics* p, dg_solver** out) {
                    (p->Re > 0 && p->visc_flux != DG_VISC_BR1)))
     return fail(DG_EUNSUPPORTED, "Gauss-Legendre nodes: FP64, volume flux DG_VOL_CENTRAL (the plain weak "
                                  "form), BR1 viscous terms");
+  if (!(p->svv_mu >= 0) || !std::isfinite(p->svv_mu)) return fail(DG_EINVAL, "svv_mu must be >= 0");
+  if (p->svv_mu > 0) {
+    if (p->svv_kernel != DG_SVV_TADMOR && p->svv_kernel != DG_SVV_MADAY) return fail(DG_EINVAL, "unknown SVV kernel");
+    if (p->svv_cutoff < -1 || p->svv_cutoff > m->N) return fail(DG_EINVAL, "SVV cutoff outside [-1, N]");
+    if (!(p->Pr > 0)) return fail(DG_EINVAL, "Pr must be positive");
+    if (std::isnan(p->svv_sensor)) return fail(DG_EINVAL, "SVV sensor threshold is NaN");
+    if (m->mixed || m->gauss || p->precision != DG_FP64)
+      return fail(DG_EUNSUPPORTED, "spectral vanishing viscosity: uniform-order Gauss-Lobatto meshes in FP64");
+  }
   dg_solver* s = new dg_solver;
   s->mesh = *m;
   s->phys = *p;
@@ -516,6 +533,14 @@ int dg_solver_bind(dg_solver* s, void* dev_ptr, size_t bytes, void* hip_stream) 
   v.gauss = s->mesh.gauss ? 1 : 0;
   v.Tr = s->mesh.gauss ? reinterpret_cast<double*>(b + p.Tr) : nullptr;
   v.Q = s->mesh.gauss && v.viscous ? reinterpret_cast<double*>(b + p.Q) : nullptr;
+  s->svv_on = s->phys.svv_mu > 0;
+  if (s->svv_on) {
+    s->svv.mu = s->phys.svv_mu;
+    s->svv.kappa = s->phys.svv_mu * s->phys.gamma / ((s->phys.gamma - 1.0) * s->phys.Pr);
+    s->svv.sensor = s->phys.svv_sensor;
+    s->svv.filt = reinterpret_cast<const double*>(b + p.svvtab);
+    s->svv.Fa = reinterpret_cast<double*>(b + p.Fa);
+  }
   s->dev_view = reinterpret_cast<dg::View*>(b + p.self);
   s->stream = static_cast<hipStream_t>(hip_stream);
 
@@ -551,6 +576,16 @@ int dg_solver_bind(dg_solver* s, void* dev_ptr, size_t bytes, void* hip_stream) 
   }
   DG_HIP(hipMemcpyAsync(b + p.tab, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice, s->stream),
          "upload tables");
+  std::vector<double> svvtab;
+  if (s->svv_on) {
+    const int n = v.N + 1;
+    svvtab.resize((size_t)n * n);
+    dg::svv_filter_table(v.N, s->phys.svv_kernel, s->phys.svv_cutoff, tab.data() + dg::tab_xi(n),
+                         tab.data() + dg::tab_w(n), svvtab.data());
+    DG_HIP(hipMemcpyAsync(b + p.svvtab, svvtab.data(), sizeof(double) * svvtab.size(), hipMemcpyHostToDevice,
+                          s->stream),
+           "upload the SVV filter");
+  }
   DG_HIP(hipMemcpyAsync(b + p.nbr, nbr.data(), sizeof(int) * nbr.size(), hipMemcpyHostToDevice, s->stream),
          "upload connectivity");
   if (mixed) {
@@ -1044,6 +1079,9 @@ int dg_batch_create(dg_solver* const* solvers, int n, void* hip_stream, dg_batch
   for (int i = 1; i < n; i++)
     if (solvers[i]->scheme != solvers[0]->scheme)
       return fail(DG_EINVAL, "the solvers of a batch must use one time scheme");
+  for (int i = 0; i < n; i++)
+    if (solvers[i]->svv_on)
+      return fail(DG_EUNSUPPORTED, "solvers with spectral vanishing viscosity advance on their own, not in a batch");
   dg_batch* b = new dg_batch;
   b->m.assign(solvers, solvers + n);
   b->scheme = solvers[0]->scheme;

@@ -1,0 +1,30 @@
+// svv.h -- spectral vanishing viscosity (section "Shock capturing"): launch interface of the two
+// kernels in kernels_svv.hip.  They run after the stage kernel of a Gauss-Lobatto, uniform-order,
+// FP64 solver and add the artificial-viscosity term to what it produced.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "dg_internal.h"
+
+namespace dg {
+
+struct SvvArgs {
+  double mu, kappa;     // artificial viscosity and conductivity mu gamma / ((gamma-1) Pr)
+  double sensor;        // density-sensor threshold; < 0: every element filtered
+  const double* filt;   // (I - Phi) of one direction, (N+1) x (N+1) row-major: Phi = V diag(s) V^-1
+  double* Fa;           // filtered physical flux [E][12][nn]: index 4 x + c, x the direction,
+                        // c = momentum 1..3, energy
+};
+
+// The term for stage input U[cur]: kernel 1 forms the filtered flux of every element; kernel 2
+// its divergence with the averaged face flux, R_a.  mode kModeResidual: R += R_a.  mode kModeRK
+// (after the stage kernel wrote dU and U[cur^1] for the same stage): dU += h R_a and
+// U[cur^1] += b h R_a, h = *v.dtp if set, else dt.
+hipError_t launch_svv(const View& v, int cur, const SvvArgs& a, double dt, double b, int mode, hipStream_t st);
+
+// Host: (I - Phi) for order N, kernel (0 Tadmor, 1 Maday) and cutoff M, from the Legendre
+// polynomials at the Lobatto nodes xi with weights w (long double, rounded once).
+void svv_filter_table(int N, int kernel, int M, const double* xi, const double* w, double* out);
+
+}  // namespace dg

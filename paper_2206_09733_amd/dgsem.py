@@ -18,6 +18,7 @@ VOL = {"ec": 0, "central": 1, "ir": 2, "kg": 3, "pirozzoli": 4, "ducros": 5, "mo
 SURF = {"roe": 0, "llf": 1, "ec": 2, "central": 3, "es": 4, "ir": 5, "es_matrix": 6, "ld_roe": 7,
         "lf_global": 8}
 VISC = {"br1": 0, "br2": 1, "ip": 2}
+SVV_KERNEL = {"tadmor": 0, "maday": 1}
 PRECISION = {"fp64": 0, "fp32_bulk": 1}
 IC = {"uniform": 0, "tgv": 1, "vortex": 2, "density_wave": 3}
 SCHEME = {"rk3": 0, "rk4": 1}
@@ -36,7 +37,9 @@ class BoxDesc(_c.Structure):
 class Physics(_c.Structure):
     _fields_ = [("gamma", _c.c_double), ("Pr", _c.c_double), ("Ma", _c.c_double),
                 ("Re", _c.c_double), ("vol_flux", _c.c_int), ("surf_flux", _c.c_int),
-                ("precision", _c.c_int), ("visc_flux", _c.c_int), ("visc_eta", _c.c_double)]
+                ("precision", _c.c_int), ("visc_flux", _c.c_int), ("visc_eta", _c.c_double),
+                ("svv_mu", _c.c_double), ("svv_kernel", _c.c_int), ("svv_cutoff", _c.c_int),
+                ("svv_sensor", _c.c_double)]
 
 
 class Diag(_c.Structure):
@@ -152,11 +155,13 @@ def box_desc(ex, ey, ez, lo, hi, deform, amp, N, orders=None, nodes="lobatto"):
 
 
 def physics(gamma=1.4, Pr=0.71, Ma=0.1, Re=0.0, vol="ec", surf="roe", precision="fp64", visc="br1",
-            visc_eta=0.0):
+            visc_eta=0.0, svv_mu=0.0, svv_kernel="maday", svv_cutoff=0, svv_sensor=-1.0):
     p = Physics()
     p.gamma, p.Pr, p.Ma, p.Re = gamma, Pr, Ma, Re
     p.vol_flux, p.surf_flux, p.precision = VOL[vol], SURF[surf], PRECISION[precision]
     p.visc_flux, p.visc_eta = VISC[visc], float(visc_eta)
+    p.svv_mu, p.svv_kernel = float(svv_mu), SVV_KERNEL[svv_kernel]
+    p.svv_cutoff, p.svv_sensor = int(svv_cutoff), float(svv_sensor)
     return p
 
 
@@ -164,12 +169,15 @@ class Solver:
     """One DGSEM solve on a periodic box, resident in device memory.
 
     `orders` (optional, shape (E, 3) or 3 E integers) gives every element its own order per
-    direction; otherwise all elements take order N.
+    direction; otherwise all elements take order N.  `svv_mu` > 0 adds spectral vanishing
+    viscosity (kernel "maday" or "tadmor", cutoff mode `svv_cutoff`, default N // 2, and the
+    troubled-element threshold `svv_sensor` of the density sensor, < 0 for none).
     """
 
     def __init__(self, ex, ey=None, ez=None, lo=(0.0, 0.0, 0.0), hi=None, deform=False, amp=0.05,
                  N=3, gamma=1.4, Pr=0.71, Ma=0.1, Re=0.0, vol="ec", surf="roe", precision="fp64",
-                 device="cuda", bind=True, orders=None, visc="br1", visc_eta=0.0, nodes="lobatto"):
+                 device="cuda", bind=True, orders=None, visc="br1", visc_eta=0.0, nodes="lobatto",
+                 svv_mu=0.0, svv_kernel="maday", svv_cutoff=None, svv_sensor=-1.0):
         L = lib()
         ey = ex if ey is None else ey
         ez = ex if ez is None else ez
@@ -187,7 +195,9 @@ class Solver:
             check(L.dg_mesh_info(mesh, _c.byref(ne), _c.byref(nn), _c.byref(nmax)))
             self.E, self.nodes, self.nmax = ne.value, nn.value, nmax.value
             h = _c.c_void_p()
-            ph = physics(gamma, Pr, Ma, Re, vol, surf, precision, visc, visc_eta)
+            cut = N // 2 if svv_cutoff is None else svv_cutoff
+            ph = physics(gamma, Pr, Ma, Re, vol, surf, precision, visc, visc_eta, svv_mu, svv_kernel, cut,
+                         svv_sensor)
             check(L.dg_solver_create(mesh, _c.byref(ph), _c.byref(h)))
             self.h = h
         finally:

@@ -181,3 +181,42 @@ def test_mixed_order_mesh_info_and_solver_limits(dg):
     assert L.dg_autotune(s, None, None) == dg.DG_ESTATE
     L.dg_solver_destroy(s)
     L.dg_mesh_destroy(m)
+
+
+def test_spectral_vanishing_viscosity_limits(dg):
+    """SVV: uniform-order Lobatto meshes in FP64; kernel, cutoff and viscosity checked; the
+    workspace grows by the filtered-flux buffer (12 doubles per node) and the filter table."""
+    L = dg.lib()
+    m, s = ctypes.c_void_p(), ctypes.c_void_p()
+    d, _ = dg.box_desc(2, 2, 2, (0, 0, 0), (1, 1, 1), True, 0.05, 3)
+    dg.check(L.dg_mesh_create_box(ctypes.byref(d), ctypes.byref(m)))
+    sizes = []
+    for svv in (0.0, 0.05):
+        p = dg.physics(svv_mu=svv, svv_cutoff=1)
+        dg.check(L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)))
+        nb = ctypes.c_size_t()
+        dg.check(L.dg_solver_required_bytes(s, ctypes.byref(nb)))
+        sizes.append(nb.value)
+        L.dg_solver_destroy(s)
+    assert sizes[1] - sizes[0] >= 12 * 8 * 8 * 64 + 16 * 8
+    for bad in (dict(svv_mu=-1.0), dict(svv_mu=float("nan")), dict(svv_mu=0.1, svv_cutoff=4),
+                dict(svv_mu=0.1, svv_cutoff=-2), dict(svv_mu=0.1, svv_sensor=float("nan")),
+                dict(svv_mu=0.1, Pr=0.0)):
+        p = dg.physics(**bad)
+        assert L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)) == dg.DG_EINVAL, bad
+    p = dg.physics(svv_mu=0.1)
+    p.svv_kernel = 2
+    assert L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)) == dg.DG_EINVAL
+    p = dg.physics(svv_mu=0.1, precision="fp32_bulk")
+    assert L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)) == dg.DG_EUNSUPPORTED
+    for kernel, cut in (("tadmor", -1), ("maday", 3), ("tadmor", 0)):
+        p = dg.physics(svv_mu=0.1, svv_kernel=kernel, svv_cutoff=cut, Re=100.0)
+        assert L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)) == dg.DG_OK
+        L.dg_solver_destroy(s)
+    L.dg_mesh_destroy(m)
+    for kw in (dict(orders=[2, 3, 3] * 8), dict(nodes="gauss")):
+        d, _k = dg.box_desc(2, 2, 2, (0, 0, 0), (1, 1, 1), False, 0.0, 3, **kw)
+        dg.check(L.dg_mesh_create_box(ctypes.byref(d), ctypes.byref(m)))
+        p = dg.physics(svv_mu=0.1, vol="central", svv_cutoff=1)
+        assert L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)) == dg.DG_EUNSUPPORTED, kw
+        L.dg_mesh_destroy(m)

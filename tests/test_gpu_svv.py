@@ -1,0 +1,224 @@
+"""Spectral vanishing viscosity on the GPU (section "Shock capturing") against the oracle.
+
+- Residuals of perturbed states on deformed meshes for orders 1..7, both kernels, Euler and
+  Navier-Stokes baselines, to the parity bar (within 8x the FP64 oracle's distance to the
+  long-double oracle, or 1e-12 relative); with the sensor on, thresholds between sensor values
+  so that some elements are troubled and some not.
+- The SVV part alone dissipates exactly the oracle's entropy form.
+- A kernel that passes no mode leaves the solver bitwise unchanged (residual and RK steps); at
+  the full 32^3 order-4 size too, where the SVV part's entropy production is also <= 0.
+- RK3 / RK4 trajectories against the oracle; graph replay and the adaptive step agree bitwise
+  with eager fixed steps; batches refuse SVV members.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2206_09733_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dg():
+    from paper_2206_09733_amd import dgsem
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    dgsem.lib()
+    return dgsem
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def perturbed(orc, c, seed, amp=(0.03, 0.05, 0.03)):
+    o = orc.OracleSolver(**c)
+    o.set_ic("tgv")
+    nn = (c["N"] + 1) ** 3
+    U0 = o.state().reshape(o.E, 5, nn).transpose(0, 2, 1).reshape(-1, 5)
+    drho, dv, dp = synth.primitive_perturbation(o.nodes, seed, amp)
+    rho = U0[:, 0] * (1 + drho)
+    v = U0[:, 1:4] / U0[:, :1] + dv.T
+    p = 0.4 * (U0[:, 4] - 0.5 * (U0[:, 1:4] ** 2).sum(1) / U0[:, 0]) * (1 + dp)
+    U = np.concatenate([rho[:, None], rho[:, None] * v, (p / 0.4 + 0.5 * rho * (v * v).sum(1))[:, None]], 1)
+    return U.reshape(o.E, nn, 5).transpose(0, 2, 1).reshape(-1)
+
+
+def parity(name, G, A, B, E, nn, factor=8.0):
+    G, A, B = (x.reshape(E, 5, nn) for x in (G, A, B))
+    scale = np.abs(B).max(axis=(0, 2))
+    e64 = np.abs(A - B).max(axis=(0, 2))
+    eg = np.abs(G - B).max(axis=(0, 2))
+    tol = np.maximum(1e-12 * scale, factor * e64)
+    log(f"[{name}] gpu-vs-fp80={np.array2string(eg, precision=2)} fp64-vs-fp80={np.array2string(e64, precision=2)}")
+    assert np.all(eg <= tol), (name, eg, tol)
+
+
+def oracles(orc, c, U, svv):
+    out = []
+    for prec in ("fp64", "fp80"):
+        o = orc.OracleSolver(**c, precision=prec)
+        o.set_state(U)
+        o.set_svv(svv["mu"], svv["kernel"], svv["cutoff"], svv.get("sensor", -1.0))
+        out.append(o)
+    return out
+
+
+def gpu_solver(dg, c, svv):
+    return dg.Solver(**c, svv_mu=svv["mu"], svv_kernel=svv["kernel"], svv_cutoff=svv["cutoff"],
+                     svv_sensor=svv.get("sensor", -1.0))
+
+
+CASES = [(N, kernel, Re) for N in range(1, 8) for kernel, Re in (("maday", 0.0), ("tadmor", 200.0))]
+
+
+@pytest.mark.parametrize("N,kernel,Re", CASES)
+def test_svv_residual_parity(dg, orc, N, kernel, Re):
+    c = dict(ex=3, ey=2, ez=3, N=N, deform=True, Ma=0.3, Re=Re)
+    svv = dict(mu=0.02, kernel=kernel, cutoff=N // 2)
+    log(f"svv residual N={N} {kernel} Re={Re}")
+    U = perturbed(orc, c, seed=1200 + N)
+    o64, o80 = oracles(orc, c, U, svv)
+    g = gpu_solver(dg, c, svv)
+    g.set_state(U)
+    parity(f"svv N={N} {kernel} Re={Re}", g.residual(), o64.residual(), o80.residual(), 18, (N + 1) ** 3)
+    g.close()
+
+
+@pytest.mark.parametrize("N", [3, 5])
+def test_svv_sensor_marks_some_elements(dg, orc, N):
+    """Threshold in the widest gap of the sorted sensor values near their median: the elements
+    above it take the unfiltered flux on both sides."""
+    c = dict(ex=3, ey=3, ez=2, N=N, deform=True, Ma=0.3)
+    U = perturbed(orc, c, seed=1300 + N, amp=(0.08, 0.05, 0.05))
+    o = orc.OracleSolver(**c)
+    o.set_state(U)
+    s = np.sort(o.svv_sensor())
+    lo, hi = len(s) // 4, 3 * len(s) // 4
+    k = lo + int(np.argmax(np.diff(s[lo:hi + 1])))
+    thr = 0.5 * (s[k] + s[k + 1])
+    log(f"sensor N={N}: threshold {thr:.6g} between {s[k]:.6g} and {s[k + 1]:.6g}, {len(s) - k - 1} troubled")
+    assert (s[k + 1] - s[k]) > 1e-6 * s[k + 1]
+    svv = dict(mu=0.03, kernel="maday", cutoff=N // 2, sensor=thr)
+    o64, o80 = oracles(orc, c, U, svv)
+    g = gpu_solver(dg, c, svv)
+    g.set_state(U)
+    parity(f"svv sensor N={N}", g.residual(), o64.residual(), o80.residual(), 18, (N + 1) ** 3)
+    g.close()
+
+
+def test_svv_part_dissipates_the_oracle_entropy_form(dg, orc):
+    c = dict(ex=3, ey=2, ez=3, N=4, deform=True, Ma=0.3, vol="ec", surf="ec")
+    U = perturbed(orc, c, seed=77)
+    svv = dict(mu=0.02, kernel="maday", cutoff=2)
+    o, _ = oracles(orc, c, U, svv)
+    _, form = o.svv_residual()
+    g, p = gpu_solver(dg, c, svv), dg.Solver(**c)
+    for s in (g, p):
+        s.set_state(U)
+    ep = o.entropy_production(g.residual() - p.residual())
+    log(f"SVV entropy production {ep:.12e}, oracle form {form:.12e}")
+    assert abs(ep + form) < 1e-9 * form
+    g.close()
+    p.close()
+
+
+@pytest.mark.parametrize("shape,N", [((3, 2, 3), 3), ((32, 32, 32), 4)])
+def test_filter_passing_nothing_leaves_the_solver_unchanged(dg, shape, N):
+    """Cutoff N: every kernel value is zero, the filtered fields are exactly zero, and so is the
+    term; the residual and two RK3 steps equal those of the plain solver bitwise."""
+    ex, ey, ez = shape
+    c = dict(ex=ex, ey=ey, ez=ez, N=N, deform=True, Ma=0.1, Re=1600.0)
+    g = dg.Solver(**c, svv_mu=0.05, svv_kernel="tadmor", svv_cutoff=N)
+    p = dg.Solver(**c)
+    for s in (g, p):
+        s.set_ic("tgv")
+    assert np.array_equal(g.residual(), p.residual())
+    dt = p.suggest_dt(0.5)
+    for s in (g, p):
+        s.rk_step(dt, 2)
+    assert np.array_equal(g.state(), p.state())
+    g.close()
+    p.close()
+
+
+def test_full_size_svv_term_dissipates_entropy(dg):
+    """32^3 elements of order 4 (the benchmark's mesh and state), Maday kernel: the SVV part of the
+    residual has non-positive entropy production sum w J w(U) . R_a and conserves momentum and
+    energy, computed on the host from the GPU's residuals and geometry."""
+    c = dict(ex=32, N=4, deform=True, Ma=0.1, Re=1600.0)
+    g = dg.Solver(**c, svv_mu=0.01, svv_kernel="maday", svv_cutoff=2)
+    p = dg.Solver(**c)
+    for s in (g, p):
+        s.set_ic("tgv")
+    Ra = (g.residual() - p.residual()).reshape(g.E, 5, 125)
+    U = g.state().reshape(g.E, 5, 125)
+    _, _, J = g.geometry(want_X=False, want_Ja=False)
+    J = J.reshape(g.E, 125)
+    w1 = np.array([0.1, 49 / 90, 32 / 45, 49 / 90, 0.1])  # Lobatto weights of order 4
+    W = np.einsum("k,j,i->kji", w1, w1, w1).reshape(-1)
+    rho, m, E = U[:, 0], U[:, 1:4], U[:, 4]
+    v = m / rho[:, None]
+    pr = 0.4 * (E - 0.5 * rho * (v * v).sum(1))
+    b = rho / pr
+    w = np.concatenate([np.zeros_like(rho)[:, None], (b[:, None] * v), -b[:, None]], 1)
+    ep = np.einsum("evn,evn,en,n->", w[:, 1:], Ra[:, 1:], J, W)
+    scale = np.einsum("evn,en,n->", np.abs(w[:, 1:] * Ra[:, 1:]), J, W)
+    tot = np.einsum("evn,en,n->v", Ra, J, W)
+    log(f"full size: SVV entropy production {ep:.6e} (scale {scale:.3e}), totals {tot}")
+    assert np.all(Ra[:, 0] == 0)
+    assert ep < 0
+    assert np.all(np.abs(tot[1:]) < 1e-12 * np.einsum("evn,en,n->v", np.abs(Ra), J, W)[1:].max())
+    g.close()
+    p.close()
+
+
+@pytest.mark.parametrize("scheme,Re", [("rk3", 0.0), ("rk4", 0.0), ("rk3", 400.0)])
+def test_svv_trajectory(dg, orc, scheme, Re):
+    c = dict(ex=3, N=4, deform=True, Ma=0.3, Re=Re)
+    svv = dict(mu=0.01, kernel="maday", cutoff=2)
+    U0 = perturbed(orc, c, seed=41, amp=(0.02, 0.03, 0.02))
+    o, o80 = oracles(orc, c, U0, svv)
+    dt = o.suggest_dt(0.4)
+    o.rk(dt, 5, scheme)
+    o80.rk(dt, 5, scheme)
+    g = gpu_solver(dg, c, svv)
+    g.set_scheme(scheme)
+    g.set_state(U0)
+    g.rk_step(dt, 5)
+    Ug, Uo, U80 = g.state(), o.state(), o80.state()
+    d = lambda a, b: np.abs(a - b).reshape(27, 5, 125).max(axis=(0, 2))
+    sc = np.abs(U80).reshape(27, 5, 125).max(axis=(0, 2))
+    log(f"[svv {scheme} Re={Re}] gpu-vs-fp80 {d(Ug, U80) / sc} fp64-vs-fp80 {d(Uo, U80) / sc}")
+    assert np.all(d(Ug, U80) <= np.maximum(1e-14 * sc, 8 * d(Uo, U80)))
+    g.close()
+
+
+def test_svv_graphs_adaptive_and_batch(dg):
+    c = dict(ex=3, ey=3, ez=2, N=4, deform=True, Ma=0.3, svv_mu=0.02, svv_kernel="maday", svv_cutoff=2,
+             svv_sensor=1e-3)
+    eager, graph, adapt = dg.Solver(**c), dg.Solver(**c), dg.Solver(**c)
+    for s in (eager, graph, adapt):
+        s.set_ic("tgv")
+    eager.use_graphs(False)
+    dts = []
+    for _ in range(4):
+        dts.append(eager.suggest_dt(0.5))
+        eager.rk_step(dts[-1], 1)
+    for d in dts:
+        graph.rk_step(d, 1)
+    assert np.array_equal(graph.state(), eager.state())
+    t = adapt.rk_step_adaptive(0.5, 4)
+    assert np.array_equal(adapt.state(), eager.state())
+    t_ref = 0.0
+    for d in dts:
+        t_ref += d
+    assert t == t_ref
+    with pytest.raises(dg.DgError) as ei:
+        dg.Batch([eager, dg.Solver(ex=2, N=3)])
+    assert ei.value.code == dg.DG_EUNSUPPORTED
+    for s in (eager, graph, adapt):
+        s.close()
