@@ -145,6 +145,38 @@ def run_gauss(steps, warmup):
     return out
 
 
+def algorithmic_bytes_svv(nodes):
+    """Unique HBM bytes of the two SVV kernels of one RK stage, FP64: the flux kernel reads U (40 B
+    per node), Ja, J, 1/J (88) and writes the filtered contravariant flux (96); the divergence
+    kernel reads the flux (96) and 1/J (8) and updates four components of dU and U_out (64 + 64)."""
+    return nodes * ((40 + 88 + 96) + (96 + 8 + 128))
+
+
+def run_svv(steps, warmup, plain_ms):
+    """The benchmark workload with spectral vanishing viscosity (Maday kernel, cutoff 2,
+    artificial viscosity 1/1600): throughput, cost against the plain step, and the two SVV
+    kernels' time per stage from the library's HIP events."""
+    from paper_2206_09733_amd import dgsem
+    s = dgsem.Solver(**WORKLOAD, svv_mu=1.0 / 1600.0, svv_kernel="maday", svv_cutoff=2)
+    s.set_ic("tgv")
+    dt = s.suggest_dt(0.5)
+    s.rk_step(dt, warmup)
+    ev_ms, _, _ = timed_steps(s, dt, steps, profile=False)
+    _, _, prof = timed_steps(s, dt, max(2, steps // 5))
+    d = s.diagnostics()
+    ot = prof["other"]
+    pair_s = ot["ms"] / ot["launches"] / 1e3
+    out = {"workload": "the benchmark workload plus SVV (Maday kernel, cutoff 2, mu_a 1/1600, no sensor)",
+           "value": round(5 * s.nodes * 3 * steps / (ev_ms / 1e3) / 1e9, 3), "unit": "GDOF/s",
+           "ms_per_step": round(ev_ms / steps, 4),
+           "overhead_vs_plain_pct": round(100.0 * (ev_ms / steps / plain_ms - 1.0), 2),
+           "svv_kernel_pair_avg_us": round(pair_s * 1e6, 2),
+           "svv_kernel_pair_GB_s": round(algorithmic_bytes_svv(s.nodes) / pair_s / 1e9, 1),
+           "state_finite": d["nonfinite"] == 0}
+    s.close()
+    return out
+
+
 MIXED = dict(ex=24, lo=(-10.0,) * 3, hi=(10.0,) * 3, Ma=0.5, vol="ec", surf="roe")
 # isentropic vortex of strength 5, free stream rho = p = 1 moving along (1, 1, 0)/sqrt 2 at Mach 0.5
 VORTEX = [5.0, 0.0, 0.0, 0.5 * math.sqrt(1.4 / 2.0), 0.5 * math.sqrt(1.4 / 2.0)]
@@ -419,6 +451,8 @@ def main():
         "unit": "GDOF-updates/s per RK stage"}
     result["adaptive_dt"] = run_adaptive(args.steps, args.warmup, r64["event_ms"] / args.steps)
     result["gauss_legendre_nodes"] = run_gauss(max(10, args.steps // 2), args.warmup)
+    result["spectral_vanishing_viscosity"] = run_svv(max(10, args.steps // 2), args.warmup,
+                                                     r64["event_ms"] / args.steps)
     if not args.skip_mixed:
         result["mixed_order"] = run_mixed(max(10, args.steps // 2), args.warmup)
     if not args.skip_large:

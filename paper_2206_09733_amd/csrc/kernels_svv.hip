@@ -193,12 +193,20 @@ __global__ void __launch_bounds__(nthreads_for(N)) svv_flux_kernel(View v, int c
   const double tau[3][3] = {{ks * y[0], ks * y[3], ks * y[4]},
                             {ks * y[3], ks * y[1], ks * y[5]},
                             {ks * y[4], ks * y[5], ks * y[2]}};
-  double* Fa = a.Fa + base * 12;
+  double F[3][4];  // physical flux along x: momentum, energy
 #pragma unroll
   for (int x = 0; x < 3; x++) {
 #pragma unroll
-    for (int k = 0; k < 3; k++) Fa[(4 * x + k) * nn + t] = tau[k][x];
-    Fa[(4 * x + 3) * nn + t] = vel[0] * tau[0][x] + vel[1] * tau[1][x] + vel[2] * tau[2][x] + kq * y[6 + x];
+    for (int k = 0; k < 3; k++) F[x][k] = tau[k][x];
+    F[x][3] = vel[0] * tau[0][x] + vel[1] * tau[1][x] + vel[2] * tau[2][x] + kq * y[6 + x];
+  }
+  double* Fa = a.Fa + base * 12;
+#pragma unroll
+  for (int d = 0; d < 3; d++) {  // Ja read again (this workgroup read it above: an L2 hit)
+    const double j0 = v.Ja[base * 9 + (3 * d) * nn + t], j1 = v.Ja[base * 9 + (3 * d + 1) * nn + t],
+                 j2 = v.Ja[base * 9 + (3 * d + 2) * nn + t];
+#pragma unroll
+    for (int c = 0; c < 4; c++) Fa[(4 * d + c) * nn + t] = j0 * F[0][c] + j1 * F[1][c] + j2 * F[2][c];
   }
 }
 
@@ -216,22 +224,13 @@ __global__ void __launch_bounds__(nthreads_for(N))
   for (int x = t; x < n * n; x += NT) sD[x] = v.tab[2 * n + x];
   if (t < n) sw[t] = v.tab[n + t];
   const long base = (long)e * nn;
-  double F[3][4];
-  if (act) {
-#pragma unroll
-    for (int x = 0; x < 3; x++)
-#pragma unroll
-      for (int c = 0; c < 4; c++) F[x][c] = a.Fa[base * 12 + (4 * x + c) * nn + t];
-  }
   double acc[4] = {0, 0, 0, 0};
 #pragma unroll
   for (int d = 0; d < 3; d++) {
-    double S[3] = {0, 0, 0}, Fd[4] = {0, 0, 0, 0};
+    double Fd[4] = {0, 0, 0, 0};
     if (act) {
 #pragma unroll
-      for (int x = 0; x < 3; x++) S[x] = v.Ja[base * 9 + (3 * d + x) * nn + t];
-#pragma unroll
-      for (int c = 0; c < 4; c++) Fd[c] = S[0] * F[0][c] + S[1] * F[1][c] + S[2] * F[2][c];
+      for (int c = 0; c < 4; c++) Fd[c] = a.Fa[base * 12 + (4 * d + c) * nn + t];
     }
     __syncthreads();  // previous direction's readers are done
     if (act) {
@@ -249,8 +248,9 @@ __global__ void __launch_bounds__(nthreads_for(N))
 #pragma unroll
       for (int c = 0; c < 4; c++) acc[c] += Dm * sF[c][b0 + m * stride];
     }
-    // faces: (F~* - F~) = S . (F_other - F_own) / 2, S the owner's Ja^d (equal to this node's
-    // after the face normals were made single-valued)
+    // faces: (F~* - F~) = S . (F_other - F_own) / 2, S the owner's Ja^d.  The face normals are
+    // single-valued (the -d side holds the owner's Ja^d), so the other side's stored
+    // contravariant flux at the matching node is S . F_other.
 #pragma unroll
     for (int side = 0; side < 2; side++) {
       if (id != (side ? N : 0)) continue;
@@ -260,10 +260,7 @@ __global__ void __launch_bounds__(nthreads_for(N))
       const double* Fo = a.Fa + (long)ne * nn * 12;
       const double wgt = side ? 0.5 / sw[N] : -0.5 / sw[0];
 #pragma unroll
-      for (int c = 0; c < 4; c++) {
-        const double fo = S[0] * Fo[c * nn + inb] + S[1] * Fo[(4 + c) * nn + inb] + S[2] * Fo[(8 + c) * nn + inb];
-        acc[c] += wgt * (fo - Fd[c]);
-      }
+      for (int c = 0; c < 4; c++) acc[c] += wgt * (Fo[(4 * d + c) * nn + inb] - Fd[c]);
     }
   }
   if (!act) return;

@@ -13,8 +13,8 @@ struct SvvArgs {
   double mu, kappa;     // artificial viscosity and conductivity mu gamma / ((gamma-1) Pr)
   double sensor;        // density-sensor threshold; < 0: every element filtered
   const double* filt;   // (I - Phi) of one direction, (N+1) x (N+1) row-major: Phi = V diag(s) V^-1
-  double* Fa;           // filtered physical flux [E][12][nn]: index 4 x + c, x the direction,
-                        // c = momentum 1..3, energy
+  double* Fa;           // filtered contravariant flux Ja^d . F [E][12][nn]: index 4 d + c, d the
+                        // reference direction, c = momentum 1..3, energy
 };
 
 // The term for stage input U[cur]: kernel 1 forms the filtered flux of every element; kernel 2
