@@ -139,6 +139,8 @@ enum { DG_VISC_BR1 = 0, DG_VISC_BR2 = 1, DG_VISC_IP = 2 };
  * are this library's readings.  Uniform-order Gauss-Lobatto meshes, FP64, not in batches. */
 enum { DG_SVV_TADMOR = 0, DG_SVV_MADAY = 1 };
 
+/* Physics of a solver.  Zero-initialise it (dg_physics p = {0}) before setting fields: every
+ * option above is off or at its default when zero. */
 typedef struct {
   double gamma, Pr, Ma, Re;
   int vol_flux, surf_flux, precision;
