@@ -49,7 +49,7 @@ extern "C" {
 #define DG_ENOMEM (-2)       /* device buffer too small, or host allocation failed        */
 #define DG_EHIP (-3)         /* a HIP runtime call failed (message holds the HIP error)   */
 #define DG_ENONFINITE (-4)   /* a state given to the library holds NaN/Inf or rho,p <= 0   */
-#define DG_EUNSUPPORTED (-5) /* valid request outside what this build implements          */
+#define DG_EUNSUPPORTED (-5) /* valid request outside what this library implements        */
 #define DG_ESTATE (-6)       /* call out of order (e.g. solver not bound)                 */
 
 /* ------------------------------------------------------------------ options */
