@@ -215,7 +215,8 @@ int dg_residual(dg_solver* s, double* host_R, size_t n);
 int dg_rk_step(dg_solver* s, double dt, int nsteps);
 /* Advance nsteps steps of the solver's scheme with a step size chosen before every step from the
  * state it starts from, on the device: dt = cfl h_min/((N+1)^2 lambda_max), lambda_max the largest
- * |v| + c over the nodes, and with viscosity at most 0.25 h_min^2 Pr rho_min/((N+1)^4 gamma mu) --
+ * |v| + c over the nodes, and with viscosity at most 0.25 h_min^2 Pr rho_min/((N+1)^4 gamma mu)
+ * (mu = 1/Re plus svv_mu) --
  * dg_suggest_dt's formula, so a step equals dg_rk_step with dg_suggest_dt(cfl) of the same state,
  * bit for bit.  A max/min reduction and a one-block kernel compute dt, and the stage kernels read
  * it from device memory, so the steps need no host round trip (and replay one captured graph).
@@ -251,9 +252,9 @@ int dg_autotune(dg_solver* s, int* tiles, double* us);
 int dg_solver_set_tiles(dg_solver* s, int tiles);
 /* Diagnostics of the current state (synchronises). */
 int dg_diagnostics(dg_solver* s, dg_diag* out);
-/* dt = cfl h_min / ((N_max+1)^2 lambda_max), and for Navier-Stokes the smaller of that and
- * 0.25 h_min^2 / ((N_max+1)^4 gamma mu / (Pr rho_min)); h_min = smallest undeformed element
- * edge; lambda_max, rho_min from dg_diagnostics of the current state. */
+/* dt = cfl h_min / ((N_max+1)^2 lambda_max), and with viscosity the smaller of that and
+ * 0.25 h_min^2 / ((N_max+1)^4 gamma mu / (Pr rho_min)), mu = 1/Re plus svv_mu; h_min = smallest
+ * undeformed element edge; lambda_max, rho_min from dg_diagnostics of the current state. */
 int dg_suggest_dt(dg_solver* s, double cfl, double* dt);
 /* Copy the geometry to the host: X (3 per node, layout [off*3 + c*nn + node]), Ja (9 per
  * node, [off*9 + (3 d + c)*nn + node] = component c of Ja^d), J (1 per node).  Any pointer may

@@ -1819,7 +1819,8 @@ int orc_get_state(const orc_solver* s, double* U) {
 }
 
 /* time step: CFL h_min / ((N_max+1)^2 lambda_max), limited by the viscous bound
- * 0.25 h_min^2 / ((N_max+1)^4 gamma mu / (Pr rho_min)) */
+ * 0.25 h_min^2 / ((N_max+1)^4 gamma mu / (Pr rho_min)), mu the physical viscosity plus the
+ * artificial one of section 8c */
 double orc_suggest_dt(const orc_solver* s, double cfl) {
   real hmin = s->h[0];
   if (s->h[1] < hmin) hmin = s->h[1];
@@ -1842,8 +1843,9 @@ double orc_suggest_dt(const orc_solver* s, double cfl) {
   }
   real n1 = Nmax + 1;
   real dt = (real)cfl * hmin / (n1 * n1 * lam);
-  if (s->viscous) {
-    real dtv = (real)0.25 * hmin * hmin / (n1 * n1 * n1 * n1 * s->gamma * s->mu / (s->Pr * rmin));
+  real mu = (s->viscous ? s->mu : 0) + (s->svv ? s->svv_mu : 0);  /* physical plus artificial */
+  if (mu > 0) {
+    real dtv = (real)0.25 * hmin * hmin / (n1 * n1 * n1 * n1 * s->gamma * mu / (s->Pr * rmin));
     if (dtv < dt) dt = dtv;
   }
   return (double)dt;

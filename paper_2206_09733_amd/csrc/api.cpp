@@ -289,12 +289,17 @@ hipError_t run_step(dg_solver* s, double dt) {
   return err;
 }
 
+// the viscosity of the step-size cap: physical plus artificial (spectral vanishing viscosity)
+double mu_eff(const dg_solver* s) {
+  return (s->v.viscous ? s->v.mu : 0.0) + (s->svv_on ? s->svv.mu : 0.0);
+}
+
 // the step size of the coming step, chosen on the device from the state in buffer s->cur
 hipError_t run_step_size(dg_solver* s, double cfl) {
   const dg::View& v = s->v;
   const double hmin = std::fmin(v.h[0], std::fmin(v.h[1], v.h[2]));
   return timed(s, DG_K_OTHER, [&] {
-    return dg::launch_step_size(v, s->cur, cfl, hmin, v.N + 1.0, s->phys.gamma, s->phys.Pr, s->stream);
+    return dg::launch_step_size(v, s->cur, cfl, hmin, v.N + 1.0, s->phys.gamma, s->phys.Pr, mu_eff(s), s->stream);
   });
 }
 
@@ -891,8 +896,9 @@ int dg_suggest_dt(dg_solver* s, double cfl, double* dt) {
   const double hmin = std::fmin(v.h[0], std::fmin(v.h[1], v.h[2]));
   const double n1 = v.N + 1.0;
   double r = cfl * hmin / (n1 * n1 * d.lambda_max);
-  if (v.viscous) {
-    const double rv = 0.25 * hmin * hmin / (n1 * n1 * n1 * n1 * s->phys.gamma * v.mu / (s->phys.Pr * d.rho_min));
+  const double mu = mu_eff(s);
+  if (mu > 0.0) {
+    const double rv = 0.25 * hmin * hmin / (n1 * n1 * n1 * n1 * s->phys.gamma * mu / (s->phys.Pr * d.rho_min));
     r = std::fmin(r, rv);
   }
   *dt = r;

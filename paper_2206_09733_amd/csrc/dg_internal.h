@@ -117,7 +117,7 @@ hipError_t launch_adapt_reset(const View& v, hipStream_t st);
 // global Lax-Friedrichs: the largest |v| + c of U[cur] into adapt[3], before each stage
 hipError_t launch_lambda_max(const View& v, int cur, hipStream_t st);
 hipError_t launch_step_size(const View& v, int cur, double cfl, double hmin, double n1, double gamma, double Pr,
-                            hipStream_t st);
+                            double mu_eff, hipStream_t st);
 // the extended flux families 1..3 (FP64), in kernels_ext.hip; called by the two launchers above
 hipError_t launch_stage_ext(const View& v, int fx, int cur, double dt, double rkA, double rkB, int mode,
                             hipStream_t st);

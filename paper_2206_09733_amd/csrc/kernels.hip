@@ -421,12 +421,12 @@ __global__ void __launch_bounds__(256) lambda_kernel(View v, int cur) {
   }
 }
 
-// Step size from the partials: the CFL limit cfl h_min/((N+1)^2 lambda_max) and, with viscosity,
-// the cap 0.25 h_min^2/((N+1)^4 gamma mu/(Pr rho_min)) -- the host's formula, operation for
-// operation.  A state with a non-finite or non-physical node gets step size 0 and raises the count
+// Step size from the partials: the CFL limit cfl h_min/((N+1)^2 lambda_max) and, when the
+// viscosity mu_eff (physical plus artificial) is positive, the cap
+// 0.25 h_min^2/((N+1)^4 gamma mu_eff/(Pr rho_min)) -- the host's formula, operation for operation.  A state with a non-finite or non-physical node gets step size 0 and raises the count
 // in adapt[2], which the host reports.
 __global__ void __launch_bounds__(256) dt_kernel(View v, int nparts, double cfl, double hmin, double n1,
-                                                 double gamma, double Pr) {
+                                                 double gamma, double Pr, double mu_eff) {
   __shared__ double red[3][256];
   const int t = threadIdx.x;
   double a = -INFINITY, r = INFINITY, c = 0.0;
@@ -451,7 +451,7 @@ __global__ void __launch_bounds__(256) dt_kernel(View v, int nparts, double cfl,
     const double lam = red[0][0], rmin = red[1][0];
     double bad = red[2][0];
     double dt = cfl * hmin / (n1 * n1 * lam);
-    if (v.viscous) dt = fmin(dt, 0.25 * hmin * hmin / (n1 * n1 * n1 * n1 * gamma * v.mu / (Pr * rmin)));
+    if (mu_eff > 0.0) dt = fmin(dt, 0.25 * hmin * hmin / (n1 * n1 * n1 * n1 * gamma * mu_eff / (Pr * rmin)));
     if (bad > 0.0 || !(lam > 0.0) || !(dt > 0.0) || !isfinite(dt)) {
       dt = 0.0;
       bad = bad > 0.0 ? bad : 1.0;
@@ -616,11 +616,11 @@ hipError_t launch_lambda_max(const View& v, int cur, hipStream_t st) {
 }
 
 hipError_t launch_step_size(const View& v, int cur, double cfl, double hmin, double n1, double gamma, double Pr,
-                            hipStream_t st) {
+                            double mu_eff, hipStream_t st) {
   // at most 3 partials per block in v.part, which holds kDiagSlots doubles per element
   const int blocks = std::min(1024, (v.E + 3) / 4);
   hipLaunchKernelGGL(lambda_kernel, dim3(blocks), dim3(256), 0, st, v, cur);
-  hipLaunchKernelGGL(dt_kernel, dim3(1), dim3(256), 0, st, v, blocks, cfl, hmin, n1, gamma, Pr);
+  hipLaunchKernelGGL(dt_kernel, dim3(1), dim3(256), 0, st, v, blocks, cfl, hmin, n1, gamma, Pr, mu_eff);
   return hipGetLastError();
 }
 

@@ -222,3 +222,29 @@ def test_svv_graphs_adaptive_and_batch(dg):
     assert ei.value.code == dg.DG_EUNSUPPORTED
     for s in (eager, graph, adapt):
         s.close()
+
+
+@pytest.mark.parametrize("Re", [0.0, 400.0])
+def test_step_size_includes_the_artificial_viscosity(dg, orc, Re):
+    """The viscous cap of the suggested step takes 1/Re plus the artificial viscosity: with a large
+    one the GPU's suggestion equals the oracle's, is smaller than without SVV, and the adaptive
+    step takes it bit for bit."""
+    c = dict(ex=3, N=4, deform=True, Ma=0.3, Re=Re)
+    svv = dict(mu=0.5, kernel="maday", cutoff=2)
+    o = orc.OracleSolver(**c)
+    o.set_ic("tgv")
+    o.set_svv(svv["mu"], svv["kernel"], svv["cutoff"])
+    g, p = gpu_solver(dg, c, svv), dg.Solver(**c)
+    for s in (g, p):
+        s.set_ic("tgv")
+    dt_o, dt_g, dt_p = o.suggest_dt(0.5), g.suggest_dt(0.5), p.suggest_dt(0.5)
+    log(f"[step size Re={Re}] oracle {dt_o:.12e} gpu {dt_g:.12e} without SVV {dt_p:.12e}")
+    assert abs(dt_g - dt_o) < 1e-13 * dt_o
+    assert dt_g < 0.5 * dt_p
+    a = gpu_solver(dg, c, svv)
+    a.set_ic("tgv")
+    assert a.rk_step_adaptive(0.5, 1) == dt_g
+    g.rk_step(dt_g, 1)
+    assert np.array_equal(a.state(), g.state())
+    for s in (g, p, a):
+        s.close()
