@@ -136,7 +136,7 @@ enum { DG_VISC_BR1 = 0, DG_VISC_BR2 = 1, DG_VISC_IP = 2 };
  *   residual: the divergence of the filtered flux with BR1 face terms (average of the two
  *        sides' fluxes).
  * The paper leaves the factorisation, the 3D kernel and the sensor's use to cited works: these
- * are this library's readings.  Uniform-order Gauss-Lobatto meshes, FP64, not in batches. */
+ * are this library's readings.  Uniform-order Gauss-Lobatto meshes, FP64. */
 enum { DG_SVV_TADMOR = 0, DG_SVV_MADAY = 1 };
 
 /* Physics of a solver.  Zero-initialise it (dg_physics p = {0}) before setting fields: every
@@ -286,7 +286,7 @@ void dg_solver_destroy(dg_solver* s);
  * serving loop).  Members of one polynomial order and precision (and all viscous or all
  * inviscid) are advanced by one launch per kernel and stage that covers the elements of all of
  * them (at most 32 members per launch), so that many small solves fill the GPU together;
- * mixed-order members are launched one by one.  Each member keeps its own state, step size and
+ * mixed-order, Gauss-Legendre and spectral-vanishing-viscosity members are launched one by one.  Each member keeps its own state, step size and
  * buffer parity; the result of a member is bitwise the same as when it is stepped alone.
  *
  * Create a batch of n bound solvers whose steps are enqueued on hip_stream (hipStream_t, NULL =
@@ -294,8 +294,7 @@ void dg_solver_destroy(dg_solver* s);
  * after the work the members have pending there (e.g. by synchronising those streams) and does
  * not use a member on its own stream while batch steps are pending.  The solvers stay owned by
  * the caller and must outlive the batch.  Errors: DG_EINVAL for NULL, n < 1 or a repeated
- * member or members with different time schemes; DG_ESTATE for an unbound member;
- * DG_EUNSUPPORTED for a member with spectral vanishing viscosity. */
+ * member or members with different time schemes; DG_ESTATE for an unbound member. */
 int dg_batch_create(dg_solver* const* solvers, int n, void* hip_stream, dg_batch** out);
 /* Advance every member nsteps steps of the RK3 of dg_rk_step, member i with step dts[i] (n
  * doubles).  Only enqueues work on the batch's stream.  Like dg_rk_step, the launches of one

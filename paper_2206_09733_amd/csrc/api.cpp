@@ -1032,8 +1032,16 @@ hipError_t batch_stage(dg_batch* b, const double* dts, int k, hipStream_t st) {
   for (int i : b->solo) {
     dg_solver* s = b->m[i];
     const double A = kRk[b->scheme].A[k], Bk = kRk[b->scheme].B[k];
-    hipError_t e = s->v.mixed ? dg::launch_stage_mixed(s->v, s->cur, dts[i], A, Bk, dg::kModeRK, s->mix_tiles, st)
-                              : dg::launch_stage_gauss(s->v, s->cur, dts[i], A, Bk, dg::kModeRK, st);
+    hipError_t e;
+    if (s->v.mixed) {
+      e = dg::launch_stage_mixed(s->v, s->cur, dts[i], A, Bk, dg::kModeRK, s->mix_tiles, st);
+    } else if (s->v.gauss) {
+      e = dg::launch_stage_gauss(s->v, s->cur, dts[i], A, Bk, dg::kModeRK, st);
+    } else {  // spectral vanishing viscosity: the solver's own stage sequence
+      e = s->v.viscous ? dg::launch_gradient(s->v, s->cur, st) : hipSuccess;
+      if (e == hipSuccess) e = dg::launch_stage(s->v, s->cur, dts[i], A, Bk, dg::kModeRK, st);
+      if (e == hipSuccess) e = dg::launch_svv(s->v, s->cur, s->svv, dts[i], Bk, dg::kModeRK, st);
+    }
     if (e != hipSuccess) return e;
   }
   for (dg_solver* s : b->m) s->cur ^= 1;
@@ -1085,16 +1093,13 @@ int dg_batch_create(dg_solver* const* solvers, int n, void* hip_stream, dg_batch
   for (int i = 1; i < n; i++)
     if (solvers[i]->scheme != solvers[0]->scheme)
       return fail(DG_EINVAL, "the solvers of a batch must use one time scheme");
-  for (int i = 0; i < n; i++)
-    if (solvers[i]->svv_on)
-      return fail(DG_EUNSUPPORTED, "solvers with spectral vanishing viscosity advance on their own, not in a batch");
   dg_batch* b = new dg_batch;
   b->m.assign(solvers, solvers + n);
   b->scheme = solvers[0]->scheme;
   b->stream = static_cast<hipStream_t>(hip_stream);
   for (int i = 0; i < n; i++) {
     const dg_solver* s = solvers[i];
-    if (s->v.mixed || s->v.gauss) {  // launched one by one within the batch's stages
+    if (s->v.mixed || s->v.gauss || s->svv_on) {  // launched one by one within the batch's stages
       b->solo.push_back(i);
       continue;
     }

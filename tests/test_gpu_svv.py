@@ -8,7 +8,7 @@
 - A kernel that passes no mode leaves the solver bitwise unchanged (residual and RK steps); at
   the full 32^3 order-4 size too, where the SVV part's entropy production is also <= 0.
 - RK3 / RK4 trajectories against the oracle; graph replay and the adaptive step agree bitwise
-  with eager fixed steps; batches refuse SVV members.
+  with eager fixed steps; a batch with an SVV member advances it as alone.
 """
 import sys
 
@@ -217,10 +217,36 @@ def test_svv_graphs_adaptive_and_batch(dg):
     for d in dts:
         t_ref += d
     assert t == t_ref
-    with pytest.raises(dg.DgError) as ei:
-        dg.Batch([eager, dg.Solver(ex=2, N=3)])
-    assert ei.value.code == dg.DG_EUNSUPPORTED
     for s in (eager, graph, adapt):
+        s.close()
+
+
+@pytest.mark.parametrize("Re", [0.0, 400.0])
+def test_batch_with_an_svv_member_equals_alone(dg, Re):
+    """A batch of an SVV solver (launched on its own within each stage) and two plain solvers
+    (one grouped launch) advances every member bitwise as alone, with and without graphs."""
+    specs = [dict(ex=3, N=4, deform=True, Ma=0.3, Re=Re, svv_mu=0.02, svv_kernel="maday", svv_cutoff=2),
+             dict(ex=3, N=4, deform=True, Ma=0.3, Re=Re), dict(ex=2, N=4, Ma=0.2, Re=Re)]
+    alone = [dg.Solver(**c) for c in specs]
+    for s in alone:
+        s.set_ic("tgv")
+    dts = [s.suggest_dt(0.4) for s in alone]
+    for s, d in zip(alone, dts):
+        s.rk_step(d, 3)
+    for graphs in (True, False):
+        mem = [dg.Solver(**c) for c in specs]
+        for s in mem:
+            s.set_ic("tgv")
+        b = dg.Batch(mem)
+        b.use_graphs(graphs)
+        assert b.launches_per_stage() == (2 if Re > 0 else 1) + 1  # the group (gradient, stage), the SVV member
+        b.rk_step(dts, 3)
+        for x, y in zip(alone, mem):
+            assert np.array_equal(x.state(), y.state())
+        b.close()
+        for s in mem:
+            s.close()
+    for s in alone:
         s.close()
 
 
