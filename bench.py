@@ -177,6 +177,33 @@ def run_svv(steps, warmup, plain_ms):
     return out
 
 
+VARIANTS = [("ec", "roe", "br1"), ("ir", "ir", "br1"), ("kg", "es_matrix", "br1"), ("pirozzoli", "ld_roe", "br1"),
+            ("ducros", "es", "br1"), ("ec", "lf_global", "br1"), ("ec", "roe", "br2"), ("ec", "roe", "ip")]
+
+
+def run_variants(steps, warmup):
+    """The benchmark workload with other volume / surface / viscous fluxes (FP64): throughput and
+    the stage and gradient kernels' time per launch from the library's HIP events."""
+    from paper_2206_09733_amd import dgsem
+    out = {}
+    for vol, surf, visc in VARIANTS:
+        s = dgsem.Solver(**{**WORKLOAD, "vol": vol, "surf": surf}, visc=visc)
+        s.set_ic("tgv")
+        dt = s.suggest_dt(0.5)
+        s.rk_step(dt, warmup)
+        ev_ms, _, prof = timed_steps(s, dt, steps)
+        d = s.diagnostics()
+        st, gr = prof["stage"], prof["gradient"]
+        out[f"{vol}+{surf}+{visc}"] = {
+            "value": round(5 * s.nodes * 3 * steps / (ev_ms / 1e3) / 1e9, 3), "unit": "GDOF/s",
+            "ms_per_step": round(ev_ms / steps, 4),
+            "stage_avg_us": round(st["ms"] / st["launches"] * 1e3, 2),
+            "gradient_avg_us": round(gr["ms"] / gr["launches"] * 1e3, 2),
+            "state_finite": d["nonfinite"] == 0}
+        s.close()
+    return out
+
+
 MIXED = dict(ex=24, lo=(-10.0,) * 3, hi=(10.0,) * 3, Ma=0.5, vol="ec", surf="roe")
 # isentropic vortex of strength 5, free stream rho = p = 1 moving along (1, 1, 0)/sqrt 2 at Mach 0.5
 VORTEX = [5.0, 0.0, 0.0, 0.5 * math.sqrt(1.4 / 2.0), 0.5 * math.sqrt(1.4 / 2.0)]
@@ -451,6 +478,7 @@ def main():
         "unit": "GDOF-updates/s per RK stage"}
     result["adaptive_dt"] = run_adaptive(args.steps, args.warmup, r64["event_ms"] / args.steps)
     result["gauss_legendre_nodes"] = run_gauss(max(10, args.steps // 2), args.warmup)
+    result["flux_variants"] = run_variants(max(10, args.steps // 5), 2)
     result["spectral_vanishing_viscosity"] = run_svv(max(10, args.steps // 2), args.warmup,
                                                      r64["event_ms"] / args.steps)
     if not args.skip_mixed:
