@@ -786,23 +786,21 @@ __device__ __forceinline__ void viscous_flux_g(T v1, T v2, T v3, const T gr[4][3
   }
 }
 
-// Face viscous fluxes of BR2 (mode 1) and the symmetric interior penalty (mode 2) at this lane's
-// node, for every face direction d the node lies on (id_d = 0 or N): Ffd[d][c], contravariant
-// along Ja^d.  BR2: broken gradient (1/J) sum_d' Ja^d' D_d' g plus eta times the lift of face d's
-// half jump alone.  Interior penalty: broken gradient, plus sigma F_v(v_mean, [g] n^) . S with
-// [g] = g(+ side) - g(- side), sigma = eta (N+1)^2 |S| / (2 min(J_-, J_+)); the neighbour's g and J
-// are read from global memory and both elements evaluate the same expression on the same values,
-// so the penalty is single-valued.
+// Face viscous fluxes of BR2 (mode 1) and the symmetric interior penalty (mode 2), in two phases.
+// The viscous flux is linear in the gradient at a fixed velocity, so each face flux is the
+// broken-gradient flux plus a face term:
+//   BR2: + F_v(v, eta (1/J) Ja^d (x) lift_d), the lift of face d's half jump alone;
+//   interior penalty: + sigma F_v(v_mean, [g] n^) . S with [g] = g(+ side) - g(- side),
+//        sigma = eta (N+1)^2 |S| / (2 min(J_-, J_+)).
+// Phase 1 (per node): the broken gradient (1/J) sum_d' Ja^d' D_d' g, its viscous flux, and the
+// contravariant component along Ja^d for every face (d, side) the node lies on, into sFb.
 template <int n, typename T>
-__device__ __forceinline__ void face_viscous_br2_ip(const View& v, int e, int cur, double Tref, int t, int ti,
-                                                    int tj, int tk, const double* sD, T iwN, T iw0,
-                                                    const T* const sG[4], const T (*sJ)[4][n * n],
-                                                    const double ja[9], double ij, T Ffd[3][4]) {
-  constexpr int N = n - 1, nf = n * n, nn = n * n * n;
-  const T mu = (T)v.mu, kappa = (T)v.kappa, eta = (T)v.visc_eta;
-  const bool br2 = v.visc_flux == 1;
+__device__ __forceinline__ void broken_face_fluxes(int t, int ti, int tj, int tk, const double* sD,
+                                                   const T* const sG[4], const double ja[9], double ij,
+                                                   T mu, T kappa, T (*sFb)[4][n * n]) {
+  constexpr int N = n - 1, nf = n * n;
   const int ii[3] = {ti, tj, tk};
-  T a[3][4], lift[3][4];
+  T a[3][4];
 #pragma unroll
   for (int d = 0; d < 3; d++) {
     const int id = ii[d];
@@ -816,71 +814,82 @@ __device__ __forceinline__ void face_viscous_br2_ip(const View& v, int e, int cu
 #pragma unroll
       for (int c = 0; c < 4; c++) a[d][c] += Dm * sG[c][b0 + m * stride];
     }
-    const int qd = d == 0 ? tj + n * tk : (d == 1 ? ti + n * tk : ti + n * tj);
-#pragma unroll
-    for (int c = 0; c < 4; c++)
-      lift[d][c] = id == N ? iwN * sJ[2 * d + 1][c][qd] : (id == 0 ? -iw0 * sJ[2 * d][c][qd] : (T)0);
   }
-  const T v1 = sG[0][t], v2 = sG[1][t], v3 = sG[2][t];
-  T grb[4][3];  // broken gradient
+  T grb[4][3];
 #pragma unroll
   for (int c = 0; c < 4; c++)
 #pragma unroll
     for (int x = 0; x < 3; x++)
       grb[c][x] = (T)ij * ((T)ja[x] * a[0][c] + (T)ja[3 + x] * a[1][c] + (T)ja[6 + x] * a[2][c]);
   T Fb[3][4];
-  if (!br2) viscous_flux_g(v1, v2, v3, grb, mu, kappa, Fb);
+  viscous_flux_g(sG[0][t], sG[1][t], sG[2][t], grb, mu, kappa, Fb);
 #pragma unroll
   for (int d = 0; d < 3; d++) {
     const int id = ii[d];
     if (id != 0 && id != N) continue;
-    const T s1 = (T)ja[3 * d], s2 = (T)ja[3 * d + 1], s3 = (T)ja[3 * d + 2];
-    T Fv[3][4];
-    if (br2) {
-      T gr[4][3];
+    const int f = 2 * d + (id == N ? 1 : 0);
+    const int qd = d == 0 ? tj + n * tk : (d == 1 ? ti + n * tk : ti + n * tj);
 #pragma unroll
-      for (int c = 0; c < 4; c++)
-#pragma unroll
-        for (int x = 0; x < 3; x++) gr[c][x] = grb[c][x] + eta * (T)ij * (T)ja[3 * d + x] * lift[d][c];
-      viscous_flux_g(v1, v2, v3, gr, mu, kappa, Fv);
-    } else {
-#pragma unroll
-      for (int x = 0; x < 3; x++)
-#pragma unroll
-        for (int c = 0; c < 4; c++) Fv[x][c] = Fb[x][c];
-    }
-#pragma unroll
-    for (int c = 0; c < 4; c++) Ffd[d][c] = s1 * Fv[0][c] + s2 * Fv[1][c] + s3 * Fv[2][c];
-    if (!br2) {
-      const int side = id == N ? 1 : 0;
-      const int qd = d == 0 ? tj + n * tk : (d == 1 ? ti + n * tk : ti + n * tj);
-      const int ne = v.nbr[e * 6 + 2 * d + side];
-      const int inb = face_node<n>(d, side ? 0 : N, qd % n, qd / n);
-      double un[5];
-#pragma unroll
-      for (int c = 0; c < 5; c++) un[c] = v.U[cur][(long)ne * nn * 5 + c * nn + inb];
-      T gn[4];
-      gvars(un, v.gamma, Tref, gn);
-      const T go[4] = {v1, v2, v3, sG[3][t]};
-      const double Jo = v.J[(long)e * nn + t], Jn = v.J[(long)ne * nn + inb];
-      const T a2 = s1 * s1 + s2 * s2 + s3 * s3;
-      const T ia = rsq(a2);
-      const T sigma = eta * (T)(n * n) * (a2 * ia) / ((T)2 * (T)(Jo < Jn ? Jo : Jn));
-      T gr[4][3];
-#pragma unroll
-      for (int c = 0; c < 4; c++) {
-        const T jump = side ? gn[c] - go[c] : go[c] - gn[c];
-        gr[c][0] = sigma * jump * s1 * ia;
-        gr[c][1] = sigma * jump * s2 * ia;
-        gr[c][2] = sigma * jump * s3 * ia;
-      }
-      const T m1 = (T)0.5 * (go[0] + gn[0]), m2 = (T)0.5 * (go[1] + gn[1]), m3 = (T)0.5 * (go[2] + gn[2]);
-      T Fp[3][4];
-      viscous_flux_g(m1, m2, m3, gr, mu, kappa, Fp);
-#pragma unroll
-      for (int c = 0; c < 4; c++) Ffd[d][c] += s1 * Fp[0][c] + s2 * Fp[1][c] + s3 * Fp[2][c];
-    }
+    for (int c = 0; c < 4; c++)
+      sFb[f][c][qd] = (T)ja[3 * d] * Fb[0][c] + (T)ja[3 * d + 1] * Fb[1][c] + (T)ja[3 * d + 2] * Fb[2][c];
   }
+}
+
+// Phase 2 (per face point q of face f = 2 d + side, own node io): the face flux of the scheme,
+// contravariant along this element's Ja^d at io (the owner's after the face normals were made
+// single-valued).  For the interior penalty the neighbour's g and J are read from global memory;
+// both elements evaluate the same expression on the same values, so the penalty is single-valued.
+template <int n, typename T>
+__device__ __forceinline__ void face_viscous_br2_ip(const View& v, int e, int cur, double Tref, int f, int q,
+                                                    int io, T iwN, T iw0, const T* const sG[4],
+                                                    const T (*sJ)[4][n * n], const T (*sFb)[4][n * n],
+                                                    T Ff[4]) {
+  constexpr int N = n - 1, nn = n * n * n;
+  const T mu = (T)v.mu, kappa = (T)v.kappa, eta = (T)v.visc_eta;
+  const int d = f >> 1, side = f & 1;
+  const long base = (long)e * nn;
+  const T s1 = (T)v.Ja[base * 9 + (3 * d) * nn + io], s2 = (T)v.Ja[base * 9 + (3 * d + 1) * nn + io],
+          s3 = (T)v.Ja[base * 9 + (3 * d + 2) * nn + io];
+  const T v1 = sG[0][io], v2 = sG[1][io], v3 = sG[2][io];
+  T gr[4][3], m1 = v1, m2 = v2, m3 = v3;
+  if (v.visc_flux == 1) {  // BR2
+    const T k = eta * (T)v.invJ[base + io];
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+      const T lift = side ? iwN * sJ[f][c][q] : -iw0 * sJ[f][c][q];
+      gr[c][0] = k * s1 * lift;
+      gr[c][1] = k * s2 * lift;
+      gr[c][2] = k * s3 * lift;
+    }
+  } else {  // interior penalty
+    const int p = q % n, r = q / n;
+    const int ne = v.nbr[e * 6 + f];
+    const int inb = face_node<n>(d, side ? 0 : N, p, r);
+    double un[5];
+#pragma unroll
+    for (int c = 0; c < 5; c++) un[c] = v.U[cur][(long)ne * nn * 5 + c * nn + inb];
+    T gn[4];
+    gvars(un, v.gamma, Tref, gn);
+    const T go[4] = {v1, v2, v3, sG[3][io]};
+    const double Jo = v.J[base + io], Jn = v.J[(long)ne * nn + inb];
+    const T a2 = s1 * s1 + s2 * s2 + s3 * s3;
+    const T ia = rsq(a2);
+    const T sigma = eta * (T)(n * n) * (a2 * ia) / ((T)2 * (T)(Jo < Jn ? Jo : Jn));
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+      const T jump = side ? gn[c] - go[c] : go[c] - gn[c];
+      gr[c][0] = sigma * jump * s1 * ia;
+      gr[c][1] = sigma * jump * s2 * ia;
+      gr[c][2] = sigma * jump * s3 * ia;
+    }
+    m1 = (T)0.5 * (go[0] + gn[0]);
+    m2 = (T)0.5 * (go[1] + gn[1]);
+    m3 = (T)0.5 * (go[2] + gn[2]);
+  }
+  T Fp[3][4];
+  viscous_flux_g(m1, m2, m3, gr, mu, kappa, Fp);
+#pragma unroll
+  for (int c = 0; c < 4; c++) Ff[c] = sFb[f][c][q] + (s1 * Fp[0][c] + s2 * Fp[1][c] + s3 * Fp[2][c]);
 }
 
 // ------------------------------------------------------------------ initial conditions

@@ -194,20 +194,34 @@ __device__ __forceinline__ void grad_body(const View& v, const int e, const int 
     for (int c = 0; c < 4; c++) sJ[f][c][q] = (T)0.5 * (gn[c] - sG[c][io]);
   }
   __syncthreads();
-  if (act) {
+  const T iwN = (T)(1.0 / sw[N]), iw0 = (T)(1.0 / sw[0]);
+  const T* const gp[4] = {sG[0], sG[1], sG[2], sG[3]};
+  T* Fvf = reinterpret_cast<T*>(v.Fvf) + (long)e * 6 * 4 * nf;
+  if constexpr (XV) {
+    // BR2 / interior penalty: broken-gradient fluxes of the face nodes, then one lane per face point
+    __shared__ T sFb[6][4][nf];
+    if (act) {
+      double ja[9];
+#pragma unroll
+      for (int c = 0; c < 9; c++) ja[c] = v.Ja[base * 9 + c * nn + t];
+      broken_face_fluxes<n, T>(t, ti, tj, tk, sD, gp, ja, v.invJ[base + t], (T)v.mu, (T)v.kappa, sFb);
+    }
+    __syncthreads();
+    for (int x = t; x < 6 * nf; x += NT) {
+      const int f = x / nf, q = x - f * nf;
+      const int io = face_node<n>(f >> 1, (f & 1) ? N : 0, q % n, q / n);
+      T Ff[4];
+      face_viscous_br2_ip<n, T>(v, e, cur, Tref, f, q, io, iwN, iw0, gp, sJ, sFb, Ff);
+#pragma unroll
+      for (int c = 0; c < 4; c++) Fvf[(f * 4 + c) * nf + q] = Ff[c];
+    }
+  } else if (act) {  // BR1: the lifted gradient's flux
     double ja[9];
 #pragma unroll
     for (int c = 0; c < 9; c++) ja[c] = v.Ja[base * 9 + c * nn + t];
     const double ij = v.invJ[base + t];
-    const T iwN = (T)(1.0 / sw[N]), iw0 = (T)(1.0 / sw[0]);
     T Fvd[3][4];
-    const T* const gp[4] = {sG[0], sG[1], sG[2], sG[3]};
-    if constexpr (XV)
-      face_viscous_br2_ip<n, T>(v, e, cur, Tref, t, ti, tj, tk, sD, iwN, iw0, gp, sJ, ja, ij, Fvd);
-    else  // BR1: the lifted gradient's flux
-      gradient_and_viscous_flux<n, T>(t, ti, tj, tk, sD, iwN, iw0, gp, sJ, ja, ij, (T)v.mu, (T)v.kappa,
-                                      Fvd);
-    T* Fvf = reinterpret_cast<T*>(v.Fvf) + (long)e * 6 * 4 * nf;
+    gradient_and_viscous_flux<n, T>(t, ti, tj, tk, sD, iwN, iw0, gp, sJ, ja, ij, (T)v.mu, (T)v.kappa, Fvd);
     const int ii[3] = {ti, tj, tk};
 #pragma unroll
     for (int d = 0; d < 3; d++) {
