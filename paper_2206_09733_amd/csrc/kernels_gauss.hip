@@ -196,20 +196,8 @@ __global__ void __launch_bounds__(nthreads_for(N))
   if (t < 2 * n) sl[t / n][t % n] = v.tab[gauss_tab_ends(n) + t];
   const long base = (long)e * nn;
   const double* __restrict__ Uin = v.U[cur];
-  double u[5], ja[9], ij = 0.0, gv[4] = {0.0, 0.0, 0.0, 0.0}, gr[4][3];
-  if (act) {
-#pragma unroll
-    for (int c = 0; c < 5; c++) u[c] = Uin[base * 5 + c * nn + t];
-#pragma unroll
-    for (int c = 0; c < 9; c++) ja[c] = v.Ja[base * 9 + c * nn + t];
-    ij = v.invJ[base + t];
-    if (VISC) {
-      gvars(u, v.gamma, 0.0, gv);
-#pragma unroll
-      for (int k = 0; k < 12; k++) gr[k / 3][k % 3] = v.Q[base * 12 + k * nn + t];
-    }
-  }
-  // numerical fluxes on the faces, from the traces of both sides
+  // numerical fluxes on the faces, from the traces of both sides (the node's own data is loaded
+  // after this phase, so that the two phases' registers do not add up)
   for (int x = t; x < 6 * nf; x += NT) {
     const int f = x / nf, q = x - f * nf;
     const int d = f >> 1, side = f & 1;
@@ -237,6 +225,21 @@ __global__ void __launch_bounds__(nthreads_for(N))
 #pragma unroll
     for (int c = 0; c < 5; c++) sFs[f][c][q] = F[c];
   }
+  double u[5], ja[9], ij = 0.0, Fv[3][4];  // Fv: physical viscous flux along x (momentum, energy)
+  if (act) {
+#pragma unroll
+    for (int c = 0; c < 5; c++) u[c] = Uin[base * 5 + c * nn + t];
+#pragma unroll
+    for (int c = 0; c < 9; c++) ja[c] = v.Ja[base * 9 + c * nn + t];
+    ij = v.invJ[base + t];
+    if (VISC) {
+      double gv[4], gr[4][3];
+      gvars(u, v.gamma, 0.0, gv);
+#pragma unroll
+      for (int k = 0; k < 12; k++) gr[k / 3][k % 3] = v.Q[base * 12 + k * nn + t];
+      viscous_flux_g(gv[0], gv[1], gv[2], gr, v.mu, v.kappa, Fv);
+    }
+  }
   // volume: sum_m Dw_im F~^d_m along each direction's line
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   const int ii[3] = {ti, tj, tk};
@@ -247,8 +250,6 @@ __global__ void __launch_bounds__(nthreads_for(N))
       double F[5];
       euler_flux_along(u, v.gamma, ja[3 * d], ja[3 * d + 1], ja[3 * d + 2], F);
       if (VISC) {
-        double Fv[3][4];
-        viscous_flux_g(gv[0], gv[1], gv[2], gr, v.mu, v.kappa, Fv);
 #pragma unroll
         for (int c = 0; c < 4; c++) F[1 + c] -= ja[3 * d] * Fv[0][c] + ja[3 * d + 1] * Fv[1][c] + ja[3 * d + 2] * Fv[2][c];
       }
