@@ -167,7 +167,9 @@ __device__ __forceinline__ int stride_of(const ElemInfo& I, int d) {
 
 constexpr int kFsFace = 6 * kMixNF;  // doubles per element face in Fs
 
-template <typename T>
+// XS: the extended surface fluxes (codes >= 4), compiled apart so that the others keep their
+// registers
+template <typename T, bool XS>
 __global__ void __launch_bounds__(64) mixed_face_kernel(View v, int cur) {
   constexpr bool DEV = sizeof(T) == 4;
   constexpr int NC = DEV ? 6 : 5;
@@ -281,8 +283,7 @@ __global__ void __launch_bounds__(64) mixed_face_kernel(View v, int cur) {
         face_flux_dev<T>(v.surf, uL, uR, S, v.gamma, Rf, F, F0d);
         sA[5][x] = F0d;
       } else {
-        if (v.surf >= 4) face_flux<T, true>(v.surf, uL, uR, S, v.gamma, F, v.surf == 8 ? v.adapt[3] : 0.0);
-        else face_flux<T, false>(v.surf, uL, uR, S, v.gamma, F);
+        face_flux<T, XS>(v.surf, uL, uR, S, v.gamma, F, XS && v.surf == 8 ? v.adapt[3] : 0.0);
       }
 #pragma unroll
       for (int c = 0; c < 5; c++) sA[c][x] = (double)F[c];
@@ -611,9 +612,11 @@ static hipError_t stage_bucket_npl(const View& v, int b, int npl, int cur, doubl
 
 hipError_t launch_faces_mixed(const View& v, int cur, hipStream_t st) {
   if (v.fp32)
-    hipLaunchKernelGGL(mixed_face_kernel<float>, dim3(3 * v.E), dim3(64), 0, st, v, cur);
+    hipLaunchKernelGGL((mixed_face_kernel<float, false>), dim3(3 * v.E), dim3(64), 0, st, v, cur);
+  else if (v.surf >= 4)
+    hipLaunchKernelGGL((mixed_face_kernel<double, true>), dim3(3 * v.E), dim3(64), 0, st, v, cur);
   else
-    hipLaunchKernelGGL(mixed_face_kernel<double>, dim3(3 * v.E), dim3(64), 0, st, v, cur);
+    hipLaunchKernelGGL((mixed_face_kernel<double, false>), dim3(3 * v.E), dim3(64), 0, st, v, cur);
   return hipGetLastError();
 }
 
@@ -633,11 +636,7 @@ hipError_t launch_stage_mixed_bucket(const View& v, int b, int npl, int cur, dou
 
 hipError_t launch_stage_mixed(const View& v, int cur, double dt, double rkA, double rkB, int mode, int tiles,
                               hipStream_t st) {
-  if (v.fp32)
-    hipLaunchKernelGGL(mixed_face_kernel<float>, dim3(3 * v.E), dim3(64), 0, st, v, cur);
-  else
-    hipLaunchKernelGGL(mixed_face_kernel<double>, dim3(3 * v.E), dim3(64), 0, st, v, cur);
-  const hipError_t ef = hipGetLastError();
+  const hipError_t ef = launch_faces_mixed(v, cur, st);
   if (ef != hipSuccess) return ef;
   for (int b = kMixBuckets - 1; b >= 0; b--) {  // the work list starts with the largest elements
     const hipError_t e = launch_stage_mixed_bucket(v, b, (tiles >> b) & 1 ? 2 : 1, cur, dt, rkA, rkB, mode, st);
