@@ -121,6 +121,24 @@ def run_adaptive(steps, warmup, fixed_ms):
             "state_finite": d["nonfinite"] == 0}
 
 
+def run_small_latency(steps=10, warmup=3):
+    """The tiny 4^3, N=3 Euler TGV case (64 elements): launch-latency bound, so reported as time
+    per RK3 step, with the step graph replayed and with eager launches."""
+    from paper_2206_09733_amd import dgsem
+    out = {"workload": "Euler Taylor-Green vortex Ma 0.1, 4^3 hex, N=3, EC + Roe, RK3 CFL 0.5"}
+    for graphs in (True, False):
+        s = dgsem.Solver(ex=4, N=3, Ma=0.1, vol="ec", surf="roe")
+        s.use_graphs(graphs)
+        s.set_ic("tgv")
+        dt = s.suggest_dt(0.5)
+        s.rk_step(dt, warmup)
+        ev_ms, wall, _ = timed_steps(s, dt, steps, profile=False)
+        out["graph_replay" if graphs else "eager_launches"] = {
+            "us_per_step_device": round(ev_ms / steps * 1e3, 2), "us_per_step_host": round(wall / steps * 1e6, 2)}
+        s.close()
+    return out
+
+
 def run_gauss(steps, warmup):
     """Euler TGV on the undeformed 32^3 box at N=4 on Gauss-Legendre points (the plain weak form:
     a face-trace kernel and the stage kernel per RK stage), against the same mesh on Lobatto
@@ -387,9 +405,17 @@ def run_cpu_baseline(budget_s=12.0, max_steps=4):
         o.rk3(dt, 1)
         t += time.perf_counter() - t0
         steps += 1
+    # one residual evaluation of the same mesh on a single thread
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    o.residual()
+    t1 = time.perf_counter() - t0
+    oracle.set_threads(threads)
     return dict(value=5 * o.nodes * 3 * steps / t / 1e9, unit="GDOF/s", cores=threads, kind="oracle",
                 sample=f"{steps} RK3 step(s) of the full 32^3 N=4 Navier-Stokes TGV mesh "
-                       f"({steps * 3} residual evaluations, {t:.1f} s)")
+                       f"({steps * 3} residual evaluations, {t:.1f} s)",
+                value_1_thread=5 * o.nodes / t1 / 1e9,
+                sample_1_thread=f"one residual evaluation of the same mesh on 1 thread ({t1:.1f} s)")
 
 
 def main():
@@ -477,6 +503,7 @@ def main():
         "value": round(5 * nodes * 5 * max(10, args.steps // 5) / (r4["event_ms"] / 1e3) / 1e9, 3),
         "unit": "GDOF-updates/s per RK stage"}
     result["adaptive_dt"] = run_adaptive(args.steps, args.warmup, r64["event_ms"] / args.steps)
+    result["small_case_latency"] = run_small_latency()
     result["gauss_legendre_nodes"] = run_gauss(max(10, args.steps // 2), args.warmup)
     result["flux_variants"] = run_variants(max(10, args.steps // 5), 2)
     result["spectral_vanishing_viscosity"] = run_svv(max(10, args.steps // 2), args.warmup,
@@ -495,6 +522,10 @@ def main():
                                         args.serve_budget_gib, 20, precision="fp32_bulk")
         result["serving_fp64"] = run_serving(args.serve_requests, args.serve_rate, args.serve_steps,
                                              args.serve_budget_gib, 20, precision="fp64")
+        # offered load at half and twice the default arrival rate (FP32-bulk, the first 64 requests)
+        result["serving_load_sweep"] = {
+            f"{f}x": run_serving(64, f * args.serve_rate, args.serve_steps, args.serve_budget_gib, 20,
+                                 precision="fp32_bulk") for f in (0.5, 2.0)}
     if rank == 0 and not args.no_cpu_baseline:
         result["cpu_baseline"] = run_cpu_baseline()
     if rank == 0:
