@@ -285,6 +285,12 @@ def run_large(steps, warmup):
         out[prec] = {"value": round(5 * s.nodes * 3 * steps / (ev_ms / 1e3) / 1e9, 3), "unit": "GDOF/s",
                      "ms_per_step": round(ev_ms / steps, 3), "steps": steps, "ke": d["ke"],
                      "enstrophy": d["enstrophy"], "state_finite": d["nonfinite"] == 0}
+        series = []  # after the timed steps, outside the timed region: (step, KE, enstrophy)
+        for k in range(5):
+            s.rk_step(dt, 1)
+            dk = s.diagnostics()
+            series.append([warmup + steps + k + 1, dk["ke"], dk["enstrophy"]])
+        out[prec]["ke_enstrophy_series"] = series
         out["nodes"], out["dof"] = s.nodes, 5 * s.nodes
         s.close()
     out["fp32_bulk"]["speedup_vs_fp64"] = round(out["fp32_bulk"]["value"] / out["fp64"]["value"], 3)
