@@ -121,9 +121,10 @@ def run_adaptive(steps, warmup, fixed_ms):
             "state_finite": d["nonfinite"] == 0}
 
 
-def run_small_latency(steps=10, warmup=3):
+def run_small_latency(steps=24, warmup=24):
     """The tiny 4^3, N=3 Euler TGV case (64 elements): launch-latency bound, so reported as time
-    per RK3 step, with the step graph replayed and with eager launches."""
+    per RK3 step, with the step graphs replayed and with eager launches (the warm-up runs as many
+    steps as the timed run, so that every graph is captured before the timing)."""
     from paper_2206_09733_amd import dgsem
     out = {"workload": "Euler Taylor-Green vortex Ma 0.1, 4^3 hex, N=3, EC + Roe, RK3 CFL 0.5"}
     for graphs in (True, False):

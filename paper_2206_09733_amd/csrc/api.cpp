@@ -74,6 +74,9 @@ struct dg_solver {
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t graph[2] = {nullptr, nullptr};
   double graph_dt[2] = {0.0, 0.0};
+  // kMultiSteps steps in one graph (fewer graph launches for small solves), same keys as graph[]
+  hipGraphExec_t mgraph[2] = {nullptr, nullptr};
+  double mgraph_dt[2] = {0.0, 0.0};
   double last_dt = 0.0;
   // adaptive-step graphs: agraph[p] advances one step from buffer p with the step size chosen on
   // the device for CFL number agraph_cfl[p]
@@ -244,13 +247,15 @@ const RkScheme kRk[2] = {
 
 // (waits for the solver's stream first, so that no replay of a graph is still in flight)
 void drop_graphs(dg_solver* s) {
-  if (!s->graph[0] && !s->graph[1] && !s->agraph[0] && !s->agraph[1]) return;
+  if (!s->graph[0] && !s->graph[1] && !s->agraph[0] && !s->agraph[1] && !s->mgraph[0] && !s->mgraph[1]) return;
   (void)hipStreamSynchronize(s->stream);
   for (int k = 0; k < 2; k++) {
     if (s->graph[k]) (void)hipGraphExecDestroy(s->graph[k]);
     if (s->agraph[k]) (void)hipGraphExecDestroy(s->agraph[k]);
+    if (s->mgraph[k]) (void)hipGraphExecDestroy(s->mgraph[k]);
     s->graph[k] = nullptr;
     s->agraph[k] = nullptr;
+    s->mgraph[k] = nullptr;
   }
 }
 
@@ -341,6 +346,19 @@ int capture_step(dg_solver* s, double dt) {
   const int parity = s->cur;
   const int rc = capture_into(s, &s->graph[parity], [&] { return run_step(s, dt); });
   if (rc == DG_OK) s->graph_dt[parity] = dt;
+  return rc;
+}
+
+// kMultiSteps consecutive steps in one graph
+constexpr int kMultiSteps = 8;
+int capture_multi_step(dg_solver* s, double dt) {
+  const int parity = s->cur;
+  const int rc = capture_into(s, &s->mgraph[parity], [&] {
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < kMultiSteps && e == hipSuccess; k++) e = run_step(s, dt);
+    return e;
+  });
+  if (rc == DG_OK) s->mgraph_dt[parity] = dt;
   return rc;
 }
 
@@ -730,17 +748,30 @@ int dg_rk_step(dg_solver* s, double dt, int nsteps) {
   // as the previous call); a step size seen once runs eagerly
   const bool replay = s->use_graphs && !s->profiling && nsteps > 0 && (nsteps > 1 || dt == s->last_dt);
   s->last_dt = dt;
-  for (int it = 0; it < nsteps; it++) {
-    if (replay) {
+  // every stage moves the state to the other buffer
+  const int flips = kRk[s->scheme].stages & 1;
+  for (int it = 0; it < nsteps;) {
+    if (replay && nsteps - it >= kMultiSteps) {  // kMultiSteps steps per graph launch
+      const int par = s->cur;
+      if (!s->mgraph[par] || s->mgraph_dt[par] != dt) {
+        rc = capture_multi_step(s, dt);
+        if (rc) return rc;
+      }
+      DG_HIP(hipGraphLaunch(s->mgraph[par], s->stream), "RK multi-step graph launch");
+      s->cur ^= (kMultiSteps * flips) & 1;
+      it += kMultiSteps;
+    } else if (replay) {
       const int par = s->cur;
       if (!s->graph[par] || s->graph_dt[par] != dt) {
         rc = capture_step(s, dt);
         if (rc) return rc;
       }
       DG_HIP(hipGraphLaunch(s->graph[par], s->stream), "RK-step graph launch");
-      s->cur ^= 1;  // an odd number of stages, each moving the state to the other buffer
+      s->cur ^= flips;
+      it++;
     } else {
       DG_HIP(run_step(s, dt), "RK stage kernels");
+      it++;
     }
   }
   return DG_OK;
