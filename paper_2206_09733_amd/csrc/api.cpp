@@ -1008,6 +1008,7 @@ struct dg_batch {
   struct Graph {
     std::vector<int> par;       // state buffer of every member at the step start
     std::vector<double> dts;
+    int steps;                  // RK steps in the graph: 1 or kMultiSteps
     hipGraphExec_t exec;
   };
   std::vector<dg_solver*> m;
@@ -1023,7 +1024,7 @@ struct dg_batch {
 
 namespace {
 
-constexpr size_t kBatchGraphs = 4;
+constexpr size_t kBatchGraphs = 8;  // one- and multi-step graphs of both parities, twice
 
 void batch_drop_graphs(dg_batch* b) {
   if (b->graphs.empty()) return;
@@ -1079,16 +1080,19 @@ hipError_t batch_stage(dg_batch* b, const double* dts, int k, hipStream_t st) {
   return hipSuccess;
 }
 
-int batch_capture(dg_batch* b, const double* dts) {
+int batch_capture(dg_batch* b, const double* dts, int steps) {
   const size_t n = b->m.size();
   dg_batch::Graph G;
   G.par.resize(n);
   for (size_t i = 0; i < n; i++) G.par[i] = b->m[i]->cur;
   G.dts.assign(dts, dts + n);
+  G.steps = steps;
   hipGraph_t g = nullptr;
   hipError_t err = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
   if (err == hipSuccess) {
-    for (int k = 0; k < kRk[b->scheme].stages && err == hipSuccess; k++) err = batch_stage(b, dts, k, b->cap_stream);
+    for (int st = 0; st < steps && err == hipSuccess; st++)
+      for (int k = 0; k < kRk[b->scheme].stages && err == hipSuccess; k++)
+        err = batch_stage(b, dts, k, b->cap_stream);
     const hipError_t e2 = hipStreamEndCapture(b->cap_stream, &g);
     if (err == hipSuccess) err = e2;
   }
@@ -1174,25 +1178,30 @@ int dg_batch_rk_step(dg_batch* b, const double* dts, int nsteps) {
   const bool same = b->last_dts.size() == n && std::equal(dts, dts + n, b->last_dts.begin());
   const bool replay = b->use_graphs && nsteps > 0 && (nsteps > 1 || same);
   b->last_dts.assign(dts, dts + n);
-  for (int it = 0; it < nsteps; it++) {
+  for (int it = 0; it < nsteps;) {
     if (!replay) {
       for (int k = 0; k < kRk[b->scheme].stages; k++)
         DG_HIP(batch_stage(b, dts, k, b->stream), "batch RK stage kernels");
+      it++;
       continue;
     }
+    // kMultiSteps steps per graph launch while that many remain, then single steps
+    const int steps = nsteps - it >= kMultiSteps ? kMultiSteps : 1;
     const dg_batch::Graph* G = nullptr;
     for (const auto& g : b->graphs) {
-      bool hit = std::equal(dts, dts + n, g.dts.begin());
+      bool hit = g.steps == steps && std::equal(dts, dts + n, g.dts.begin());
       for (size_t i = 0; hit && i < n; i++) hit = g.par[i] == b->m[i]->cur;
       if (hit) G = &g;
     }
     if (!G) {
-      int rc = batch_capture(b, dts);
+      int rc = batch_capture(b, dts, steps);
       if (rc) return rc;
       G = &b->graphs.back();
     }
     DG_HIP(hipGraphLaunch(G->exec, b->stream), "batch RK-step graph launch");
-    for (dg_solver* s : b->m) s->cur ^= 1;
+    const int flips = (steps * kRk[b->scheme].stages) & 1;  // each stage moves every state
+    for (dg_solver* s : b->m) s->cur ^= flips;
+    it += steps;
   }
   return DG_OK;
 }
