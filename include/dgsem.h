@@ -232,9 +232,10 @@ enum { DG_RK3_WILLIAMSON = 0, DG_RK4_CARPENTER_KENNEDY = 1 };
  * use one scheme).  Errors: DG_EINVAL for an unknown scheme. */
 int dg_solver_set_scheme(dg_solver* s, int scheme);
 /* Graph replay of RK steps (on by default).  When dg_rk_step runs several steps, or the same
- * dt as its previous call, the launches of one step are captured once per starting state
- * buffer into a HIP graph (on a stream the library owns; no memory operations are recorded)
- * and replayed on the solver's stream.  Graphs are dropped when the state or its FP32
+ * dt as its previous call, the launches of one step, and of 8 steps while at least 8 remain,
+ * are captured once per starting state buffer into HIP graphs (on a stream the library owns;
+ * no memory operations are recorded) and replayed on the solver's stream; the results equal
+ * those of eager launches bit for bit.  Graphs are dropped when the state or its FP32
  * reference changes, after dg_autotune and when disabled; steps inside a profile region run
  * eagerly.  enable = 0 disables replay. */
 int dg_solver_use_graphs(dg_solver* s, int enable);
@@ -296,10 +297,11 @@ void dg_solver_destroy(dg_solver* s);
  * the caller and must outlive the batch.  Errors: DG_EINVAL for NULL, n < 1 or a repeated
  * member or members with different time schemes; DG_ESTATE for an unbound member. */
 int dg_batch_create(dg_solver* const* solvers, int n, void* hip_stream, dg_batch** out);
-/* Advance every member nsteps steps of the RK3 of dg_rk_step, member i with step dts[i] (n
+/* Advance every member nsteps steps of the members' scheme, member i with step dts[i] (n
  * doubles).  Only enqueues work on the batch's stream.  Like dg_rk_step, the launches of one
- * step are captured into a HIP graph and replayed when several steps are taken or the same
- * dts recur (a few graphs are kept, keyed by dts and the members' buffer parities). */
+ * step (and of 8 steps while at least 8 remain) are captured into HIP graphs and replayed when
+ * several steps are taken or the same dts recur (a few graphs are kept, keyed by dts, the step
+ * count and the members' buffer parities). */
 int dg_batch_rk_step(dg_batch* b, const double* dts, int nsteps);
 /* enable = 0 disables graph replay of the batch (and drops its graphs). */
 int dg_batch_use_graphs(dg_batch* b, int enable);
