@@ -274,3 +274,23 @@ def test_step_size_includes_the_artificial_viscosity(dg, orc, Re):
     assert np.array_equal(a.state(), g.state())
     for s in (g, p, a):
         s.close()
+
+
+def test_filter_passing_every_mode_equals_the_unfiltered_flux(dg, orc):
+    """Tadmor's kernel with cutoff -1 passes every mode: the residual equals that of a solver whose
+    elements are all troubled (sensor threshold 0, unfiltered flux), to rounding, and both meet
+    the parity bar against the oracle."""
+    c = dict(ex=3, ey=2, ez=3, N=4, deform=True, Ma=0.3, Re=300.0)
+    U = perturbed(orc, c, seed=1400)
+    cases = [dict(mu=0.02, kernel="tadmor", cutoff=-1), dict(mu=0.02, kernel="maday", cutoff=2, sensor=0.0)]
+    R = []
+    for svv in cases:
+        o64, o80 = oracles(orc, c, U, svv)
+        g = gpu_solver(dg, c, svv)
+        g.set_state(U)
+        R.append(g.residual())
+        parity(f"svv {svv}", R[-1], o64.residual(), o80.residual(), 18, 125)
+        g.close()
+    scale = np.abs(R[1]).max()
+    log(f"identity filter vs all troubled: max|diff| / max|R| = {np.abs(R[0] - R[1]).max() / scale:.2e}")
+    assert np.abs(R[0] - R[1]).max() < 1e-13 * scale
