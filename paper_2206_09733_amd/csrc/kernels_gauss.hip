@@ -127,9 +127,7 @@ __global__ void __launch_bounds__(nthreads_for(N)) gauss_grad_kernel(View v, int
     for (int c = 0; c < 4; c++)
 #pragma unroll
       for (int x = 0; x < 3; x++) {
-        const double q = ij * (ja[x] * a[0][c] + ja[3 + x] * a[1][c] + ja[6 + x] * a[2][c]);
-        sQ[3 * c + x][t] = q;
-        v.Q[(base * 12 + (3 * c + x) * nn) + t] = q;
+        sQ[3 * c + x][t] = ij * (ja[x] * a[0][c] + ja[3 + x] * a[1][c] + ja[6 + x] * a[2][c]);
       }
   }
   __syncthreads();
@@ -188,6 +186,11 @@ __global__ void __launch_bounds__(nthreads_for(N))
   __shared__ double sDw[n * n], sw[n], sl[2][n];
   __shared__ double sF[5][nn];      // contravariant flux of one direction
   __shared__ double sFs[6][5][nf];  // numerical flux on the six faces
+  // Navier-Stokes: g = (v, T) at the nodes and the face values g* = average of the two sides'
+  // traces, for the BR1 gradient (formed here as in gauss_grad_kernel, not stored)
+  constexpr int nnV = VISC ? nn : 1, nfV = VISC ? nf : 1;
+  __shared__ double sG[4][nnV];
+  __shared__ double sGs[6][4][nfV];
   for (int x = t; x < n * n; x += NT) {
     const int i = x / n, m = x - i * n;
     sDw[x] = -v.tab[2 * n + m * n + i] * v.tab[n + m] / v.tab[n + i];
@@ -214,6 +217,13 @@ __global__ void __launch_bounds__(nthreads_for(N))
     const long owner = side ? e : ne;
 #pragma unroll
     for (int c = 0; c < 3; c++) S[c] = v.Ja[owner * nn * 9 + (3 * d + c) * nn];
+    if (VISC) {
+      double go[4], gn[4];
+      gvars(side ? uL : uR, v.gamma, 0.0, go);
+      gvars(side ? uR : uL, v.gamma, 0.0, gn);
+#pragma unroll
+      for (int c = 0; c < 4; c++) sGs[f][c][q] = 0.5 * (go[c] + gn[c]);
+    }
     double F[5];
     face_flux<double, XS>(v.surf, uL, uR, S, v.gamma, F, XS && v.surf == 8 ? v.adapt[3] : 0.0);
     if (VISC) {
@@ -226,6 +236,7 @@ __global__ void __launch_bounds__(nthreads_for(N))
     for (int c = 0; c < 5; c++) sFs[f][c][q] = F[c];
   }
   double u[5], ja[9], ij = 0.0, Fv[3][4];  // Fv: physical viscous flux along x (momentum, energy)
+  double gv[4] = {0.0, 0.0, 0.0, 0.0};
   if (act) {
 #pragma unroll
     for (int c = 0; c < 5; c++) u[c] = Uin[base * 5 + c * nn + t];
@@ -233,10 +244,36 @@ __global__ void __launch_bounds__(nthreads_for(N))
     for (int c = 0; c < 9; c++) ja[c] = v.Ja[base * 9 + c * nn + t];
     ij = v.invJ[base + t];
     if (VISC) {
-      double gv[4], gr[4][3];
       gvars(u, v.gamma, 0.0, gv);
 #pragma unroll
-      for (int k = 0; k < 12; k++) gr[k / 3][k % 3] = v.Q[base * 12 + k * nn + t];
+      for (int c = 0; c < 4; c++) sG[c][t] = gv[c];
+    }
+  }
+  if (VISC) {
+    __syncthreads();  // g and g* of the element staged
+    if (act) {  // BR1 gradient (weak form) and the viscous flux of this node
+      const int ii[3] = {ti, tj, tk};
+      double a[3][4];
+#pragma unroll
+      for (int d = 0; d < 3; d++) {
+        const int id = ii[d];
+        const int stride = d == 0 ? 1 : (d == 1 ? n : nf);
+        const int b0 = t - id * stride;
+        const int qd = d == 0 ? tj + n * tk : (d == 1 ? ti + n * tk : ti + n * tj);
+        const double lp = sl[1][id] / sw[id], lm = sl[0][id] / sw[id];
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+          double acc = lp * sGs[2 * d + 1][c][qd] - lm * sGs[2 * d][c][qd];
+#pragma unroll
+          for (int m = 0; m < n; m++) acc += sDw[id * n + m] * sG[c][b0 + m * stride];
+          a[d][c] = acc;
+        }
+      }
+      double gr[4][3];
+#pragma unroll
+      for (int c = 0; c < 4; c++)
+#pragma unroll
+        for (int x = 0; x < 3; x++) gr[c][x] = ij * (ja[x] * a[0][c] + ja[3 + x] * a[1][c] + ja[6 + x] * a[2][c]);
       viscous_flux_g(gv[0], gv[1], gv[2], gr, v.mu, v.kappa, Fv);
     }
   }
