@@ -91,7 +91,7 @@ struct dg_solver {
 namespace {
 
 struct Plan {
-  size_t tab, nbr, X, Ja, J, invJ, U0, U1, dU, R, Fvf, part, diag, adapt, elem, work, mtab, Fs, Tr, Q, svvtab, Fa,
+  size_t tab, nbr, X, Ja, J, invJ, U0, U1, dU, R, Fvf, part, diag, adapt, elem, work, mtab, Fs, Tr, svvtab, Fa,
       self, total;
   size_t tab_n, mtab_n;
 };
@@ -141,7 +141,6 @@ Plan make_plan(const dg_solver* s) {
   p.mtab = mixed ? take(sizeof(double) * p.mtab_n) : 0;
   p.Fs = mixed ? take(sizeof(double) * dg::kMixFaceDoubles * E) : 0;
   p.Tr = s->mesh.gauss ? take(sizeof(double) * E * 6 * 5 * nf) : 0;
-  p.Q = 0;  // the Gauss-Legendre stage kernel forms the BR1 gradient itself
   p.svvtab = s->phys.svv_mu > 0 ? take(sizeof(double) * n * n) : 0;
   p.Fa = s->phys.svv_mu > 0 ? take(sizeof(double) * 12 * nt) : 0;
   p.self = take(sizeof(dg::View));  // device copy of the View, read by batched launches
@@ -555,7 +554,6 @@ int dg_solver_bind(dg_solver* s, void* dev_ptr, size_t bytes, void* hip_stream) 
   v.Fs = mixed ? reinterpret_cast<double*>(b + p.Fs) : nullptr;
   v.gauss = s->mesh.gauss ? 1 : 0;
   v.Tr = s->mesh.gauss ? reinterpret_cast<double*>(b + p.Tr) : nullptr;
-  v.Q = nullptr;
   s->svv_on = s->phys.svv_mu > 0;
   if (s->svv_on) {
     s->svv.mu = s->phys.svv_mu;

@@ -43,7 +43,6 @@ struct View {
   int visc_flux;    // 0 BR1, 1 BR2, 2 symmetric interior penalty (face viscous flux)
   int gauss;        // Gauss-Legendre nodes: tab's Dhat slot holds l_j(-1), l_j(+1) instead
   double* Tr;       // Gauss-Legendre: face traces [E][6][5][nf] of the state
-  double* Q;        // Gauss-Legendre Navier-Stokes: BR1 gradients of (v, T) [E][12][nn]
   double visc_eta;  // BR2 lifting factor or interior-penalty factor
   double rho_r, p_r;  // FP32-bulk reference state (mean density and pressure of the state set)
   const int* nbr; // [E][6] neighbour across face f = 2 d + side (side 1: xi_d = +1)
