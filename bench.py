@@ -446,8 +446,9 @@ def main():
                          "for hardware traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the DGSEM path here is a single-GPU build "
-              "(multi-GPU element sharding is a design note, not implemented)", file=sys.stderr)
+        print("bench.py measures one GPU: the library runs the DGSEM path on a single GPU (sharding "
+              "the elements over several GPUs is described in the design notes, not implemented)",
+              file=sys.stderr)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
     if args.copy_reference_mib:
