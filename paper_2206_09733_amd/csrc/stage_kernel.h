@@ -45,17 +45,25 @@ __device__ __forceinline__ void stage_body(const View& v, const int e, const int
   // FP32-bulk keeps the mass flux in FP64: velocities, face and pair mass fluxes
   constexpr int nnD = DEV ? nn : 1, nfD = DEV ? nf : 1;
   __shared__ double sVd[3][nnD];
-  __shared__ double sF0d[6][nfD];
-  constexpr int bytesA = VISC ? (nn + 24 * nf) * (int)sizeof(T) : 0;
+  // One region holds each phase's arrays in turn:
+  //   A (face phase, until the gradient and the mass-flux lift are taken): temperature, half
+  //     jumps of g and (FP32-bulk) the FP64 face mass fluxes;
+  //   B (viscous volume phase): one direction of the contravariant viscous flux;
+  //   C (volume phase): the two-point fluxes of one direction (and their FP64 mass fluxes).
+  constexpr int a16 = 16;
+  constexpr int offJ = VISC ? ((nn * (int)sizeof(T) + a16 - 1) / a16) * a16 : 0;
+  constexpr int offF0 = VISC ? ((offJ + 24 * nf * (int)sizeof(T) + a16 - 1) / a16) * a16 : 0;
+  constexpr int bytesA = offF0 + (DEV ? 6 * nf * 8 : 0);
   constexpr int bytesB = VISC ? 4 * nn * (int)sizeof(T) : 0;
-  constexpr int bytesC = 5 * P * (int)sizeof(T) + (DEV ? 8 * P : 0);
+  constexpr int bytesC = ((5 * P * (int)sizeof(T) + a16 - 1) / a16) * a16 + (DEV ? 8 * P : 0);
   constexpr int bytesAB = bytesA > bytesB ? bytesA : bytesB;
   __shared__ __align__(16) char sRaw[bytesAB > bytesC ? bytesAB : bytesC];
-  T* sT = reinterpret_cast<T*>(sRaw);                                   // temperature
-  T(*sJ)[4][nf] = reinterpret_cast<T(*)[4][nf]>(sRaw + nn * sizeof(T));  // half jumps of g
-  T(*sFv)[nn] = reinterpret_cast<T(*)[nn]>(sRaw);                      // F~v^d, 4 components
+  T* sT = reinterpret_cast<T*>(sRaw);                                // temperature
+  T(*sJ)[4][nf] = reinterpret_cast<T(*)[4][nf]>(sRaw + offJ);        // half jumps of g
+  double(*sF0d)[nfD] = reinterpret_cast<double(*)[nfD]>(sRaw + offF0);  // FP32-bulk face mass flux
+  T(*sFv)[nn] = reinterpret_cast<T(*)[nn]>(sRaw);                    // F~v^d, 4 components
   T(*sPair)[P] = reinterpret_cast<T(*)[P]>(sRaw);
-  double* sM = reinterpret_cast<double*>(sRaw + 5 * P * sizeof(T));  // FP32-bulk pair mass flux
+  double* sM = reinterpret_cast<double*>(sRaw + ((5 * P * (int)sizeof(T) + a16 - 1) / a16) * a16);  // pair mass flux
 
   for (int x = t; x < n * n; x += NT) {
     sD[x] = v.tab[2 * n + x];
@@ -158,6 +166,18 @@ __device__ __forceinline__ void stage_body(const View& v, const int e, const int
   const T iwN = (T)(1.0 / sw[N]), iw0 = (T)(1.0 / sw[0]);
   T acc[5] = {0, 0, 0, 0, 0};
   double acc0d = 0.0;  // FP32-bulk mass accumulator
+  // FP32-bulk: lift of the FP64 face mass fluxes, taken before their region is reused (in FP64
+  // the order of the sum does not matter; the FP32 lifts stay beside each direction's volume
+  // sum, which they largely cancel)
+  if (DEV && act) {
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+      const int id = ii[d];
+      const int line = d == 0 ? tj + n * tk : (d == 1 ? ti + n * tk : ti + n * tj);
+      if (id == N) acc0d += sF0d[2 * d + 1][line] / sw[N];
+      if (id == 0) acc0d -= sF0d[2 * d][line] / sw[0];
+    }
+  }
   if (VISC) {
     // BR1 gradient and contravariant viscous flux of this node, then sum_m Dhat_im F~v^d_m
     T Fvd[3][4];
@@ -247,12 +267,10 @@ __device__ __forceinline__ void stage_body(const View& v, const int e, const int
       if (id == N) {
 #pragma unroll
         for (int c = 0; c < 5; c++) acc[c] += iwN * sF[2 * d + 1][c][line];
-        if (DEV) acc0d += sF0d[2 * d + 1][line] / sw[N];
       }
       if (id == 0) {
 #pragma unroll
         for (int c = 0; c < 5; c++) acc[c] -= iw0 * sF[2 * d][c][line];
-        if (DEV) acc0d -= sF0d[2 * d][line] / sw[0];
       }
     }
   }
