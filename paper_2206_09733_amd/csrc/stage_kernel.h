@@ -19,8 +19,12 @@ namespace dg {
 // direction being processed, the six face-flux grids, and one phase-dependent region (BR1
 // temperature and half jumps; one direction of the contravariant viscous flux; the two-point
 // fluxes of one direction).
-// occupancy target of the stage kernel: waves per SIMD the register allocation must allow
-__host__ __device__ constexpr int stage_waves_per_eu(int N) { return N <= 5 ? 3 : 2; }
+// occupancy target of the stage kernel: waves per SIMD the register allocation must allow (the
+// FP32-bulk kernels fit 4 at orders 1, 2, 4, 5 with at most 2 spilled registers, measured faster
+// than 3 for Euler and NS alike; at order 3 they would spill 8-10 and keep 3)
+__host__ __device__ constexpr int stage_waves_per_eu(int N, bool fp32) {
+  return N <= 5 ? (fp32 && N != 3 ? 4 : 3) : 2;
+}
 
 template <int N, typename T, bool VISC, int FX>
 __device__ __forceinline__ void stage_body(const View& v, const int e, const int cur, const double dt,
@@ -301,14 +305,14 @@ __device__ __forceinline__ void stage_body(const View& v, const int e, const int
 // FX: the flux family (see flux_family); each family is compiled as separate kernels
 template <int N, typename T, bool VISC, int FX>
 __global__ void __launch_bounds__(nthreads_for(N))
-    __attribute__((amdgpu_waves_per_eu(stage_waves_per_eu(N))))
+    __attribute__((amdgpu_waves_per_eu(stage_waves_per_eu(N, sizeof(T) == 4))))
     stage_kernel(View v, int cur, double dt, double rkA, double rkB, int mode) {
   stage_body<N, T, VISC, FX>(v, block_element(v.E), cur, dt, rkA, rkB, mode);
 }
 
 template <int N, typename T, bool VISC, int FX>
 __global__ void __launch_bounds__(nthreads_for(N))
-    __attribute__((amdgpu_waves_per_eu(stage_waves_per_eu(N))))
+    __attribute__((amdgpu_waves_per_eu(stage_waves_per_eu(N, sizeof(T) == 4))))
     stage_batch_kernel(BatchArgs B, double rkA, double rkB, int mode) {
   int m, e;
   batch_member(B, m, e);
