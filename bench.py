@@ -86,6 +86,10 @@ def timed_steps(s, dt, steps, profile=True):
 
 
 def run_gpu(precision, steps, warmup, scheme="rk3"):
+    """The workload on the product path: `steps` steps of one dg_rk_step call (graph replay),
+    timed with events on the solver's stream.  A second, profiled pass of steps/5 steps (at
+    least 2), in which the library brackets every kernel with HIP events and launches eagerly,
+    gives the per-kernel averages."""
     from paper_2206_09733_amd import dgsem
     s = dgsem.Solver(**WORKLOAD, precision=precision)
     s.set_scheme(scheme)
@@ -93,12 +97,42 @@ def run_gpu(precision, steps, warmup, scheme="rk3"):
     dt = s.suggest_dt(0.5)
     s.rk_step(dt, warmup)
     s.synchronize()
-    ev_ms, wall, prof = timed_steps(s, dt, steps)
+    ev_ms, wall, _ = timed_steps(s, dt, steps, profile=False)
+    _, _, prof = timed_steps(s, dt, max(2, steps // 5), profile=True)
     d = s.diagnostics()
     out = dict(nodes=s.nodes, E=s.E, dt=dt, wall_s=wall, event_ms=ev_ms, prof=prof,
                finite=d["nonfinite"] == 0, ke=d["ke"])
     s.close()
     return out
+
+
+def precision_error(steps=20):
+    """FP32-bulk against the FP64 path (itself checked against the oracle by the GPU tests) on
+    the benchmark workload: per conserved variable, the relative L-inf difference
+    max|a - b| / max|b| of the residual of the Taylor-Green state and of the state after `steps`
+    RK3 steps, and the change of the conserved totals (volume integrals) over those steps."""
+    import numpy as np
+    from paper_2206_09733_amd import dgsem
+    keys = ["mass_rho", "mass_rhou", "mass_rhov", "mass_rhow", "mass_rhoE"]
+    res, st, drift = {}, {}, {}
+    for prec in ("fp64", "fp32_bulk"):
+        s = dgsem.Solver(**WORKLOAD, precision=prec)
+        s.set_ic("tgv")
+        dt = s.suggest_dt(0.5)
+        d0 = s.diagnostics()
+        res[prec] = s.residual().reshape(s.E, 5, -1)
+        s.rk_step(dt, steps)
+        st[prec] = s.state().reshape(s.E, 5, -1)
+        d1 = s.diagnostics()
+        drift[prec] = [d1[k] - d0[k] for k in keys]
+        s.close()
+
+    def rel(a, b):
+        return [float(np.abs(a[:, c] - b[:, c]).max() / np.abs(b[:, c]).max()) for c in range(5)]
+    return {"variables": ["rho", "rho v1", "rho v2", "rho v3", "rho e"],
+            "residual_rel_linf": rel(res["fp32_bulk"], res["fp64"]),
+            "state_rel_linf_after_steps": rel(st["fp32_bulk"], st["fp64"]), "steps": steps,
+            "conserved_total_change": drift}
 
 
 def run_adaptive(steps, warmup, fixed_ms):
@@ -427,11 +461,17 @@ def run_cpu_baseline(budget_s=12.0, max_steps=4):
                 sample_1_thread=f"one residual evaluation of the same mesh on 1 thread ({t1:.1f} s)")
 
 
+LEGS = ["fp32", "rk4", "adaptive", "small", "gauss", "variants", "svv", "mixed", "large", "batch", "serve", "cpu"]
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--legs", default=",".join(LEGS),
+                    help="comma-separated parts to run after the headline (default: all of "
+                         + ",".join(LEGS) + "; 'none' for the headline alone)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-fp32", action="store_true")
     ap.add_argument("--skip-mixed", action="store_true")
@@ -450,6 +490,16 @@ def main():
               "the elements over several GPUs is described in the design notes, not implemented)",
               file=sys.stderr)
         sys.exit(2)
+    legs = set() if args.legs == "none" else set(x for x in args.legs.split(",") if x)
+    unknown = legs - set(LEGS)
+    if unknown:
+        ap.error(f"unknown legs {sorted(unknown)}")
+    for flag, leg in ((args.no_cpu_baseline, "cpu"), (args.skip_fp32, "fp32"), (args.skip_mixed, "mixed"),
+                      (args.skip_large, "large")):
+        if flag:
+            legs.discard(leg)
+    if args.skip_serve:
+        legs -= {"batch", "serve"}
     rank = int(os.environ.get("RANK", "0"))
     if args.copy_reference_mib:
         import torch
@@ -471,6 +521,7 @@ def main():
     b_stage = algorithmic_bytes_stage(nodes, N, True, False, 2.0 / 3.0)
     b_grad = algorithmic_bytes_gradient(nodes, N, False)
     achieved = b_stage / avg_stage_s / 1e9
+    stage_s = t / (3 * args.steps)
     result = {
         "metric": "GDOF-updates/s per RK stage (plain FP64 vs batched FP32-bulk); p50/p99 solve latency",
         "value": round(value, 3),
@@ -487,46 +538,63 @@ def main():
         "config": {"workload": "compressible NS Taylor-Green vortex Re1600 Ma0.1 Pr0.71, 32^3 hex "
                                "deformed (x+=0.05 sin y sin z, cyclic), Gauss-Lobatto N=4, EC split "
                                "form + Roe + BR1, low-storage RK3, CFL 0.5",
-                   "elements": r64["E"], "nodes": nodes, "dof": 5 * nodes, "precision": "fp64"},
+                   "elements": r64["E"], "nodes": nodes, "dof": 5 * nodes, "precision": "fp64",
+                   "timing": "one dg_rk_step call of all timed steps (graph replay), HIP events on the "
+                             "solver's stream"},
         "roofline": {"bound": "hbm", "kernel": "stage_kernel<4,double,NS>",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(),
                      "avg_launch_us": round(avg_stage_s * 1e6, 2),
+                     "avg_launch_from": f"library HIP events around each launch, a separate pass of "
+                                        f"{st['launches'] // 3} steps",
                      "algorithmic_bytes_per_launch": int(b_stage)},
+        "whole_stage": {"us_per_stage": round(stage_s * 1e6, 2),
+                        "algorithmic_bytes": int(b_stage + b_grad),
+                        "GB_s": round((b_stage + b_grad) / stage_s / 1e9, 1),
+                        "frac_hbm_peak": round((b_stage + b_grad) / stage_s / 1e9 / HBM_PEAK_GBS, 4)},
         "kernels": {"stage": {"avg_us": round(avg_stage_s * 1e6, 2), "launches": st["launches"],
                               "GB_s": round(achieved, 1)},
                     "gradient": {"avg_us": round(avg_grad_s * 1e6, 2), "launches": gr["launches"],
                                  "GB_s": round(b_grad / avg_grad_s / 1e9, 1)}},
         "state_finite": r64["finite"],
     }
-    if not args.skip_fp32:
+    if "fp32" in legs:
         r32 = run_gpu("fp32_bulk", args.steps, args.warmup)
         v32 = 5 * nodes * 3 * args.steps / (r32["event_ms"] / 1e3) / 1e9
         result["fp32_bulk"] = {"value": round(v32, 3), "unit": "GDOF/s",
                                "ms_per_step": round(r32["event_ms"] / args.steps, 4),
-                               "speedup_vs_fp64": round(v32 / value, 3)}
-    r4 = run_gpu("fp64", max(10, args.steps // 5), args.warmup, scheme="rk4")
-    st4 = r4["prof"]["stage"]
-    result["rk4_carpenter_kennedy"] = {
-        "ms_per_step": round(r4["event_ms"] / max(10, args.steps // 5), 4),
-        "stages_per_step": 5, "stage_avg_us": round(st4["ms"] / st4["launches"] * 1e3, 2),
-        "value": round(5 * nodes * 5 * max(10, args.steps // 5) / (r4["event_ms"] / 1e3) / 1e9, 3),
-        "unit": "GDOF-updates/s per RK stage"}
-    result["adaptive_dt"] = run_adaptive(args.steps, args.warmup, r64["event_ms"] / args.steps)
-    result["small_case_latency"] = run_small_latency()
-    result["gauss_legendre_nodes"] = run_gauss(max(10, args.steps // 2), args.warmup)
-    result["flux_variants"] = run_variants(max(10, args.steps // 5), 2)
-    result["spectral_vanishing_viscosity"] = run_svv(max(10, args.steps // 2), args.warmup,
-                                                     r64["event_ms"] / args.steps)
-    if not args.skip_mixed:
+                               "speedup_vs_fp64": round(v32 / value, 3),
+                               "error_vs_fp64": precision_error()}
+    if "rk4" in legs:
+        k4 = max(10, args.steps // 5)
+        r4 = run_gpu("fp64", k4, args.warmup, scheme="rk4")
+        st4 = r4["prof"]["stage"]
+        result["rk4_carpenter_kennedy"] = {
+            "ms_per_step": round(r4["event_ms"] / k4, 4),
+            "stages_per_step": 5, "stage_avg_us": round(st4["ms"] / st4["launches"] * 1e3, 2),
+            "value": round(5 * nodes * 5 * k4 / (r4["event_ms"] / 1e3) / 1e9, 3),
+            "unit": "GDOF-updates/s per RK stage"}
+    if "adaptive" in legs:
+        result["adaptive_dt"] = run_adaptive(args.steps, args.warmup, r64["event_ms"] / args.steps)
+    if "small" in legs:
+        result["small_case_latency"] = run_small_latency()
+    if "gauss" in legs:
+        result["gauss_legendre_nodes"] = run_gauss(max(10, args.steps // 2), args.warmup)
+    if "variants" in legs:
+        result["flux_variants"] = run_variants(max(10, args.steps // 5), 2)
+    if "svv" in legs:
+        result["spectral_vanishing_viscosity"] = run_svv(max(10, args.steps // 2), args.warmup,
+                                                         r64["event_ms"] / args.steps)
+    if "mixed" in legs:
         result["mixed_order"] = run_mixed(max(10, args.steps // 2), args.warmup)
-    if not args.skip_large:
+    if "large" in legs:
         result["large_64_n5"] = run_large(max(5, args.steps // 10), 2)
-    if not args.skip_serve:
+    if "batch" in legs:
         from paper_2206_09733_amd import synth
         result["batch_vs_solo"] = {
             "serving_first_32": run_batch_vs_solo(synth.serving_requests(32, seed=0)),
             "small_ensemble_64": run_batch_vs_solo(small_ensemble(64), steps=100)}
+    if "serve" in legs:
         # the served form computes in FP32-bulk; the same stream in FP64 for comparison
         result["serving"] = run_serving(args.serve_requests, args.serve_rate, args.serve_steps,
                                         args.serve_budget_gib, 20, precision="fp32_bulk")
@@ -536,7 +604,7 @@ def main():
         result["serving_load_sweep"] = {
             f"{f}x": run_serving(64, f * args.serve_rate, args.serve_steps, args.serve_budget_gib, 20,
                                  precision="fp32_bulk") for f in (0.5, 2.0)}
-    if rank == 0 and not args.no_cpu_baseline:
+    if rank == 0 and "cpu" in legs:
         result["cpu_baseline"] = run_cpu_baseline()
     if rank == 0:
         print(json.dumps(result), flush=True)

@@ -204,7 +204,7 @@ int dg_set_initial_condition(dg_solver* s, int ic, const double* params);
  * state is then left unchanged). */
 int dg_set_state(dg_solver* s, const double* host_U, size_t n);
 /* Copy the current state to the host (synchronises the stream). */
-int dg_get_state(dg_solver* s, double* host_U, size_t n);
+int dg_get_state(const dg_solver* s, double* host_U, size_t n);
 /* R = dU/dt of the current state.  R stays on the device; if host_R is not NULL it is also
  * copied there (n doubles, layout above; synchronises). */
 int dg_residual(dg_solver* s, double* host_R, size_t n);

@@ -7,6 +7,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
+#include <new>
+#include <stdexcept>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -21,16 +24,43 @@ void gl_tables(int N, double* xi, double* w, double* D, double* lb);
 void mortar_tables(int N, int M, double* I, double* P);
 }
 
+// Message of the last failure on this thread.  g_err_fixed, when set, takes precedence: it is a
+// static message used where building the string itself could fail (no host memory).
 static thread_local std::string g_err;
+static thread_local const char* g_err_fixed = nullptr;
 
-static int fail(int code, const std::string& msg) {
-  g_err = msg;
+static int fail_fixed(int code, const char* msg) noexcept {
+  g_err_fixed = msg;
+  return code;
+}
+
+static int fail(int code, const std::string& msg) noexcept {
+  try {
+    g_err = msg;
+    g_err_fixed = nullptr;
+  } catch (...) {
+    g_err_fixed = "host memory ran out while the error message was formed";
+  }
   return code;
 }
 
 static int hip_fail(hipError_t e, const char* what) {
-  g_err = std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
-  return DG_EHIP;
+  return fail(DG_EHIP, std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")");
+}
+
+// Every entry point is a function-try-block whose handler returns this, so that no exception
+// crosses the C ABI: a failed host allocation becomes DG_ENOMEM, anything else DG_EINVAL.
+// Called only from inside a catch handler (the bare throw rethrows the exception in flight).
+static int abi_exception() noexcept {
+  try {
+    throw;
+  } catch (const std::bad_alloc&) {
+    return fail_fixed(DG_ENOMEM, "host memory allocation failed");
+  } catch (const std::exception& e) {
+    return fail(DG_EINVAL, std::string("internal error: ") + e.what());
+  } catch (...) {
+    return fail_fixed(DG_EINVAL, "internal error");
+  }
 }
 
 #define DG_HIP(call, what)                      \
@@ -382,9 +412,9 @@ int check_bound(const dg_solver* s) {
 
 extern "C" {
 
-const char* dg_last_error(void) { return g_err.c_str(); }
+const char* dg_last_error(void) { return g_err_fixed ? g_err_fixed : g_err.c_str(); }
 
-int dg_mesh_create_box(const dg_box_desc* d, dg_mesh** out) {
+int dg_mesh_create_box(const dg_box_desc* d, dg_mesh** out) try {
   if (!d || !out) return fail(DG_EINVAL, "NULL argument");
   *out = nullptr;
   if (d->ex < 1 || d->ey < 1 || d->ez < 1) return fail(DG_EINVAL, "element counts must be >= 1");
@@ -415,26 +445,26 @@ int dg_mesh_create_box(const dg_box_desc* d, dg_mesh** out) {
       return fail(DG_EUNSUPPORTED, "mixed-order meshes take fewer than 2^31 nodes");
   }
   if (N < 1 || N > dg::kMaxOrder) return fail(DG_EINVAL, "order must lie in [1, 7]");
-  dg_mesh* m = new dg_mesh;
+  std::unique_ptr<dg_mesh> m(new dg_mesh);
   m->ex = d->ex; m->ey = d->ey; m->ez = d->ez;
   for (int k = 0; k < 3; k++) { m->lo[k] = d->lo[k]; m->hi[k] = d->hi[k]; }
   m->deform = d->deform;
   m->amp = d->deform_amp;
   m->mixed = mixed;
   m->gauss = d->nodes == DG_NODES_GAUSS;
-  if (m->gauss && (mixed || d->deform != DG_DEFORM_NONE)) {
-    delete m;
+  if (m->gauss && (mixed || d->deform != DG_DEFORM_NONE))
     return fail(DG_EUNSUPPORTED, "Gauss-Legendre nodes are built for undeformed uniform-order boxes");
-  }
   m->N = mixed ? nmax : N;
   if (mixed) m->orders.assign(d->orders, d->orders + 3 * E);
-  *out = m;
+  *out = m.release();
   return DG_OK;
+} catch (...) {
+  return abi_exception();
 }
 
-void dg_mesh_destroy(dg_mesh* m) { delete m; }
+void dg_mesh_destroy(dg_mesh* m) try { delete m; } catch (...) {}
 
-int dg_mesh_info(const dg_mesh* m, long long* n_elements, long long* n_nodes, int* n_max) {
+int dg_mesh_info(const dg_mesh* m, long long* n_elements, long long* n_nodes, int* n_max) try {
   if (!m) return fail(DG_EINVAL, "NULL mesh");
   const long long E = (long long)m->ex * m->ey * m->ez;
   long long nodes = 0;
@@ -446,9 +476,11 @@ int dg_mesh_info(const dg_mesh* m, long long* n_elements, long long* n_nodes, in
   if (n_nodes) *n_nodes = nodes;
   if (n_max) *n_max = m->N;
   return DG_OK;
+} catch (...) {
+  return abi_exception();
 }
 
-int dg_solver_create(const dg_mesh* m, const dg_physics* p, dg_solver** out) {
+int dg_solver_create(const dg_mesh* m, const dg_physics* p, dg_solver** out) try {
   if (!m || !p || !out) return fail(DG_EINVAL, "NULL argument");
   *out = nullptr;
   if (!(p->gamma > 1.0)) return fail(DG_EINVAL, "gamma must exceed 1");
@@ -479,7 +511,7 @@ int dg_solver_create(const dg_mesh* m, const dg_physics* p, dg_solver** out) {
     if (m->mixed || m->gauss || p->precision != DG_FP64)
       return fail(DG_EUNSUPPORTED, "spectral vanishing viscosity: uniform-order Gauss-Lobatto meshes in FP64");
   }
-  dg_solver* s = new dg_solver;
+  std::unique_ptr<dg_solver> s(new dg_solver);
   s->mesh = *m;
   s->phys = *p;
   s->E = (long long)m->ex * m->ey * m->ez;
@@ -512,17 +544,21 @@ int dg_solver_create(const dg_mesh* m, const dg_physics* p, dg_solver** out) {
   v.p_r = 1.0 / (p->gamma * p->Ma * p->Ma);
   v.mixed = m->mixed ? 1 : 0;
   v.nmax = m->N;
-  *out = s;
+  *out = s.release();
   return DG_OK;
+} catch (...) {
+  return abi_exception();
 }
 
-int dg_solver_required_bytes(const dg_solver* s, size_t* bytes) {
+int dg_solver_required_bytes(const dg_solver* s, size_t* bytes) try {
   if (!s || !bytes) return fail(DG_EINVAL, "NULL argument");
   *bytes = make_plan(s).total;
   return DG_OK;
+} catch (...) {
+  return abi_exception();
 }
 
-int dg_solver_bind(dg_solver* s, void* dev_ptr, size_t bytes, void* hip_stream) {
+int dg_solver_bind(dg_solver* s, void* dev_ptr, size_t bytes, void* hip_stream) try {
   if (!s || !dev_ptr) return fail(DG_EINVAL, "NULL argument");
   if (s->bound) return fail(DG_ESTATE, "solver already bound");
   const Plan p = make_plan(s);
@@ -675,9 +711,11 @@ int dg_solver_bind(dg_solver* s, void* dev_ptr, size_t bytes, void* hip_stream) 
   s->bound = true;
   s->cur = 0;
   return DG_OK;
+} catch (...) {
+  return abi_exception();
 }
 
-int dg_set_initial_condition(dg_solver* s, int ic, const double* params) {
+int dg_set_initial_condition(dg_solver* s, int ic, const double* params) try {
   int rc = check_bound(s);
   if (rc) return rc;
   if (ic < DG_IC_UNIFORM || ic > DG_IC_DENSITY_WAVE) return fail(DG_EINVAL, "unknown initial condition");
@@ -697,9 +735,11 @@ int dg_set_initial_condition(dg_solver* s, int ic, const double* params) {
                }),
          "initial-condition kernel");
   return update_reference(s);
+} catch (...) {
+  return abi_exception();
 }
 
-int dg_set_state(dg_solver* s, const double* host_U, size_t n) {
+int dg_set_state(dg_solver* s, const double* host_U, size_t n) try {
   int rc = check_bound(s);
   if (rc) return rc;
   if (!host_U) return fail(DG_EINVAL, "NULL state");
@@ -711,9 +751,11 @@ int dg_set_state(dg_solver* s, const double* host_U, size_t n) {
   DG_HIP(hipMemsetAsync(s->v.dU, 0, sizeof(double) * n, s->stream), "clear RK register");
   DG_HIP(hipStreamSynchronize(s->stream), "upload state");
   return update_reference(s);
+} catch (...) {
+  return abi_exception();
 }
 
-int dg_get_state(dg_solver* s, double* host_U, size_t n) {
+int dg_get_state(const dg_solver* s, double* host_U, size_t n) try {
   int rc = check_bound(s);
   if (rc) return rc;
   if (!host_U) return fail(DG_EINVAL, "NULL output");
@@ -722,9 +764,11 @@ int dg_get_state(dg_solver* s, double* host_U, size_t n) {
          "download state");
   DG_HIP(hipStreamSynchronize(s->stream), "download state");
   return DG_OK;
+} catch (...) {
+  return abi_exception();
 }
 
-int dg_residual(dg_solver* s, double* host_R, size_t n) {
+int dg_residual(dg_solver* s, double* host_R, size_t n) try {
   int rc = check_bound(s);
   if (rc) return rc;
   if (host_R && n != (size_t)(5 * s->ntot)) return fail(DG_EINVAL, "residual size must be 5 * number of nodes");
@@ -735,9 +779,11 @@ int dg_residual(dg_solver* s, double* host_R, size_t n) {
     DG_HIP(hipStreamSynchronize(s->stream), "residual");
   }
   return DG_OK;
+} catch (...) {
+  return abi_exception();
 }
 
-int dg_rk_step(dg_solver* s, double dt, int nsteps) {
+int dg_rk_step(dg_solver* s, double dt, int nsteps) try {
   int rc = check_bound(s);
   if (rc) return rc;
   if (nsteps < 0) return fail(DG_EINVAL, "nsteps must be >= 0");
@@ -773,9 +819,11 @@ int dg_rk_step(dg_solver* s, double dt, int nsteps) {
     }
   }
   return DG_OK;
+} catch (...) {
+  return abi_exception();
 }
 
-int dg_rk_step_adaptive(dg_solver* s, double cfl, int nsteps, double* t_advanced) {
+int dg_rk_step_adaptive(dg_solver* s, double cfl, int nsteps, double* t_advanced) try {
   int rc = check_bound(s);
   if (rc) return rc;
   if (nsteps < 0) return fail(DG_EINVAL, "nsteps must be >= 0");
@@ -813,9 +861,11 @@ int dg_rk_step_adaptive(dg_solver* s, double cfl, int nsteps, double* t_advanced
     return fail(DG_ENONFINITE, "the state held non-finite or non-physical values (rho or p <= 0) at the start of a "
                                "step; from there on the steps had size 0");
   return DG_OK;
+} catch (...) {
+  return abi_exception();
 }
 
-int dg_solver_set_scheme(dg_solver* s, int scheme) {
+int dg_solver_set_scheme(dg_solver* s, int scheme) try {
   if (!s) return fail(DG_EINVAL, "NULL solver");
   if (scheme != DG_RK3_WILLIAMSON && scheme != DG_RK4_CARPENTER_KENNEDY) return fail(DG_EINVAL, "unknown time scheme");
   if (scheme != s->scheme) {
@@ -823,16 +873,20 @@ int dg_solver_set_scheme(dg_solver* s, int scheme) {
     s->scheme = scheme;
   }
   return DG_OK;
+} catch (...) {
+  return abi_exception();
 }
 
-int dg_solver_use_graphs(dg_solver* s, int enable) {
+int dg_solver_use_graphs(dg_solver* s, int enable) try {
   if (!s) return fail(DG_EINVAL, "NULL solver");
   s->use_graphs = enable != 0;
   if (!s->use_graphs) drop_graphs(s);
   return DG_OK;
+} catch (...) {
+  return abi_exception();
 }
 
-int dg_solver_set_tiles(dg_solver* s, int tiles) {
+int dg_solver_set_tiles(dg_solver* s, int tiles) try {
   if (!s) return fail(DG_EINVAL, "NULL solver");
   if (!s->v.mixed) {
     if (tiles != 0) return fail(DG_EINVAL, "uniform-order meshes have one launch shape (tiles = 0)");
@@ -842,9 +896,11 @@ int dg_solver_set_tiles(dg_solver* s, int tiles) {
   s->mix_tiles = tiles;
   drop_graphs(s);
   return DG_OK;
+} catch (...) {
+  return abi_exception();
 }
 
-int dg_autotune(dg_solver* s, int* tiles, double* us) {
+int dg_autotune(dg_solver* s, int* tiles, double* us) try {
   int rc = check_bound(s);
   if (rc) return rc;
   if (!s->v.mixed) {
@@ -891,9 +947,11 @@ int dg_autotune(dg_solver* s, int* tiles, double* us) {
   if (tiles) *tiles = best_tiles;
   if (us) *us = total;
   return DG_OK;
+} catch (...) {
+  return abi_exception();
 }
 
-int dg_diagnostics(dg_solver* s, dg_diag* out) {
+int dg_diagnostics(dg_solver* s, dg_diag* out) try {
   int rc = check_bound(s);
   if (rc) return rc;
   if (!out) return fail(DG_EINVAL, "NULL output");
@@ -912,9 +970,11 @@ int dg_diagnostics(dg_solver* s, dg_diag* out) {
   out->p_min = h[11];
   out->nonfinite = (long long)h[12];
   return DG_OK;
+} catch (...) {
+  return abi_exception();
 }
 
-int dg_suggest_dt(dg_solver* s, double cfl, double* dt) {
+int dg_suggest_dt(dg_solver* s, double cfl, double* dt) try {
   if (!dt) return fail(DG_EINVAL, "NULL output");
   if (!(cfl > 0) || !std::isfinite(cfl)) return fail(DG_EINVAL, "cfl must be positive");
   dg_diag d;
@@ -932,9 +992,11 @@ int dg_suggest_dt(dg_solver* s, double cfl, double* dt) {
   }
   *dt = r;
   return DG_OK;
+} catch (...) {
+  return abi_exception();
 }
 
-int dg_get_geometry(dg_solver* s, double* host_X, double* host_Ja, double* host_J) {
+int dg_get_geometry(dg_solver* s, double* host_X, double* host_Ja, double* host_J) try {
   int rc = check_bound(s);
   if (rc) return rc;
   const size_t nt = (size_t)s->ntot;
@@ -946,33 +1008,41 @@ int dg_get_geometry(dg_solver* s, double* host_X, double* host_Ja, double* host_
     DG_HIP(hipMemcpyAsync(host_J, s->v.J, sizeof(double) * nt, hipMemcpyDeviceToHost, s->stream), "J");
   DG_HIP(hipStreamSynchronize(s->stream), "geometry download");
   return DG_OK;
+} catch (...) {
+  return abi_exception();
 }
 
-int dg_device_pointers(dg_solver* s, void** dev_U, void** dev_R) {
+int dg_device_pointers(dg_solver* s, void** dev_U, void** dev_R) try {
   int rc = check_bound(s);
   if (rc) return rc;
   if (dev_U) *dev_U = s->v.U[s->cur];
   if (dev_R) *dev_R = s->v.R;
   return DG_OK;
+} catch (...) {
+  return abi_exception();
 }
 
-int dg_synchronize(dg_solver* s) {
+int dg_synchronize(dg_solver* s) try {
   int rc = check_bound(s);
   if (rc) return rc;
   DG_HIP(hipStreamSynchronize(s->stream), "synchronize");
   return DG_OK;
+} catch (...) {
+  return abi_exception();
 }
 
-int dg_profile_begin(dg_solver* s) {
+int dg_profile_begin(dg_solver* s) try {
   int rc = check_bound(s);
   if (rc) return rc;
   s->profiling = true;
   s->prof.clear();
   s->ev_used = 0;
   return DG_OK;
+} catch (...) {
+  return abi_exception();
 }
 
-int dg_profile_end(dg_solver* s, dg_profile* out) {
+int dg_profile_end(dg_solver* s, dg_profile* out) try {
   int rc = check_bound(s);
   if (rc) return rc;
   if (!out) return fail(DG_EINVAL, "NULL output");
@@ -992,6 +1062,8 @@ int dg_profile_end(dg_solver* s, dg_profile* out) {
   s->prof.clear();
   s->ev_used = 0;
   return DG_OK;
+} catch (...) {
+  return abi_exception();
 }
 
 // ------------------------------------------------------------------ batches of solvers
@@ -1113,7 +1185,7 @@ int batch_capture(dg_batch* b, const double* dts, int steps) {
 
 }  // namespace
 
-int dg_batch_create(dg_solver* const* solvers, int n, void* hip_stream, dg_batch** out) {
+int dg_batch_create(dg_solver* const* solvers, int n, void* hip_stream, dg_batch** out) try {
   if (!solvers || !out) return fail(DG_EINVAL, "NULL argument");
   *out = nullptr;
   if (n < 1) return fail(DG_EINVAL, "a batch needs at least one solver");
@@ -1126,7 +1198,7 @@ int dg_batch_create(dg_solver* const* solvers, int n, void* hip_stream, dg_batch
   for (int i = 1; i < n; i++)
     if (solvers[i]->scheme != solvers[0]->scheme)
       return fail(DG_EINVAL, "the solvers of a batch must use one time scheme");
-  dg_batch* b = new dg_batch;
+  std::unique_ptr<dg_batch> b(new dg_batch);
   b->m.assign(solvers, solvers + n);
   b->scheme = solvers[0]->scheme;
   b->stream = static_cast<hipStream_t>(hip_stream);
@@ -1153,21 +1225,17 @@ int dg_batch_create(dg_solver* const* solvers, int n, void* hip_stream, dg_batch
   for (const auto& g : b->groups) {
     blocks = 0;
     for (int i : g.idx) blocks += b->m[i]->E;
-    if (blocks >= (1LL << 31)) {
-      delete b;
-      return fail(DG_EINVAL, "a batched launch would exceed 2^31 workgroups");
-    }
+    if (blocks >= (1LL << 31)) return fail(DG_EINVAL, "a batched launch would exceed 2^31 workgroups");
   }
   hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
-  if (e != hipSuccess) {
-    delete b;
-    return hip_fail(e, "capture stream");
-  }
-  *out = b;
+  if (e != hipSuccess) return hip_fail(e, "capture stream");
+  *out = b.release();
   return DG_OK;
+} catch (...) {
+  return abi_exception();
 }
 
-int dg_batch_rk_step(dg_batch* b, const double* dts, int nsteps) {
+int dg_batch_rk_step(dg_batch* b, const double* dts, int nsteps) try {
   if (!b || !dts) return fail(DG_EINVAL, "NULL argument");
   if (nsteps < 0) return fail(DG_EINVAL, "nsteps must be >= 0");
   const size_t n = b->m.size();
@@ -1202,37 +1270,45 @@ int dg_batch_rk_step(dg_batch* b, const double* dts, int nsteps) {
     it += steps;
   }
   return DG_OK;
+} catch (...) {
+  return abi_exception();
 }
 
-int dg_batch_use_graphs(dg_batch* b, int enable) {
+int dg_batch_use_graphs(dg_batch* b, int enable) try {
   if (!b) return fail(DG_EINVAL, "NULL batch");
   b->use_graphs = enable != 0;
   if (!b->use_graphs) batch_drop_graphs(b);
   return DG_OK;
+} catch (...) {
+  return abi_exception();
 }
 
-int dg_batch_launches(const dg_batch* b, int* launches_per_stage) {
+int dg_batch_launches(const dg_batch* b, int* launches_per_stage) try {
   if (!b || !launches_per_stage) return fail(DG_EINVAL, "NULL argument");
   int k = 0;
   for (const auto& g : b->groups) k += g.visc ? 2 : 1;
   *launches_per_stage = k + (int)b->solo.size();
   return DG_OK;
+} catch (...) {
+  return abi_exception();
 }
 
-void dg_batch_destroy(dg_batch* b) {
+void dg_batch_destroy(dg_batch* b) try {
   if (!b) return;
   batch_drop_graphs(b);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   delete b;
+} catch (...) {
 }
 
-void dg_solver_destroy(dg_solver* s) {
+void dg_solver_destroy(dg_solver* s) try {
   if (!s) return;
   if (s->bound) (void)hipStreamSynchronize(s->stream);
   drop_graphs(s);
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
   delete s;
+} catch (...) {
 }
 
 }  // extern "C"
