@@ -18,8 +18,9 @@ import numpy as np
 @dataclasses.dataclass
 class Request:
     """One solve: Taylor-Green vortex on the periodic box [0, 2 pi]^3 with E^3 elements of order
-    N, Mach Ma, Reynolds number Re (0 = Euler), advanced `steps` RK3 steps at CFL `cfl`, in
-    `precision` ("fp64" or "fp32_bulk")."""
+    N, Mach Ma, Reynolds number Re (0 = Euler), advanced `steps` RK3 steps in `precision`
+    ("fp64" or "fp32_bulk"), with the fixed step `dt`, or (dt = 0) the step that CFL number
+    `cfl` gives for the initial state."""
     id: int
     E: int
     N: int
@@ -29,6 +30,7 @@ class Request:
     arrival: float = 0.0
     cfl: float = 0.5
     precision: str = "fp64"
+    dt: float = 0.0
 
     @property
     def nodes(self):
@@ -195,7 +197,7 @@ class GpuExecutor:
         with self.torch.cuda.stream(self.setup):
             s.bind(self.device, stream=self.setup)
         s.set_ic("tgv")
-        dt = s.suggest_dt(req.cfl)  # synchronises the side stream only
+        dt = req.dt if req.dt > 0 else s.suggest_dt(req.cfl)  # synchronises the side stream only
         return s, dt
 
     def launch(self, jobs, k):

@@ -23,3 +23,36 @@ def quad_weights_uniform(w, E):
     n = len(w)
     wk = (w[:, None, None] * w[None, :, None] * w[None, None, :]).reshape(-1)
     return np.tile(wk, E)
+
+
+# FP64 parity gate.  Two FP64 evaluations of the split-form residual that round differently
+# disagree at the rounding level of its cancelling sums, so the bar is set by the oracle's own
+# FP64 error e64 (its double build against its long-double build on the same input): the GPU
+# must lie within max(floor |ref|, GATE e64) of the long-double result, per conserved variable.
+# GATE = 2: the GPU may round at most twice as badly as the plain FP64 oracle.
+GATE = 2.0
+
+
+def parity_log(name, **fields):
+    """Append one JSON record of a parity comparison to $PARITY_LOG (when set)."""
+    import json
+    import os
+    path = os.environ.get("PARITY_LOG")
+    if not path:
+        return
+    rec = {"case": name}
+    for k, v in fields.items():
+        rec[k] = np.asarray(v).tolist() if isinstance(v, np.ndarray) else v
+    with open(path, "a") as f:
+        f.write(json.dumps(rec) + "\n")
+
+
+def gate_ok(name, eg, e64, scale, floor=1e-12):
+    """True when every variable's GPU error eg lies within max(floor scale, GATE e64); logs the
+    errors relative to the scale and the ratio eg / e64."""
+    eg, e64, scale = (np.asarray(x, dtype=np.float64) for x in (eg, e64, scale))
+    tol = np.maximum(floor * scale, GATE * e64)
+    ratio = eg / np.maximum(e64, 1e-300)
+    parity_log(name, gpu_rel=eg / np.maximum(scale, 1e-300), fp64_rel=e64 / np.maximum(scale, 1e-300),
+               ratio=ratio, ok=bool(np.all(eg <= tol)))
+    return bool(np.all(eg <= tol))

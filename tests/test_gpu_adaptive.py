@@ -11,6 +11,8 @@
 import sys
 
 import numpy as np
+
+from helpers import GATE, gate_ok
 import pytest
 
 from paper_2206_09733_amd import synth
@@ -90,7 +92,7 @@ def test_adaptive_equals_suggested_fixed_steps(dg, case):
 
 def test_adaptive_against_oracle(dg, orc):
     """The oracle takes its own suggested step before each of 5 steps (FP64 and long double);
-    the GPU's adaptive trajectory lies within 8x the FP64 oracle's distance to the long-double
+    the GPU's adaptive trajectory lies within GATE (2) times the FP64 oracle's distance to the long-double
     one, as every fixed-step trajectory does."""
     c = dict(ex=3, N=4, deform=True, Ma=0.1, Re=1600.0)
     o, o80 = orc.OracleSolver(**c), orc.OracleSolver(**c, precision="fp80")
@@ -107,7 +109,7 @@ def test_adaptive_against_oracle(dg, orc):
     d = lambda a, b: np.abs(a - b).reshape(27, 5, 125).max(axis=(0, 2))
     sc = np.abs(U80).reshape(27, 5, 125).max(axis=(0, 2))
     log(f"[adaptive NS] gpu-vs-fp80 {d(Ug, U80) / sc} fp64-vs-fp80 {d(Uo, U80) / sc}")
-    assert np.all(d(Ug, U80) <= np.maximum(1e-14 * sc, 8 * d(Uo, U80)))
+    assert gate_ok("test_adaptive_against_oracle", d(Ug, U80), d(Uo, U80), sc, 1e-14), "parity gate"
 
 
 def test_adaptive_reports_blow_up_and_bad_arguments(dg):

@@ -140,3 +140,64 @@ def test_batch_rk4_equals_alone(dg):
     with pytest.raises(dg.DgError) as ei:
         dg.Batch([batched[0], other])
     assert ei.value.code == dg.DG_EINVAL
+
+
+def test_batch_members_match_oracle(dg, orc):
+    """One member of every launch group of a batch (uniform orders 3-5, Euler and Navier-Stokes,
+    the extended flux families, the interior penalty, FP32-bulk, a mixed-order member) against
+    the oracle run alone from the same state with the same step: FP64 members within the parity
+    gate (GPU vs long-double oracle within max(1e-12 |U|, GATE e64) per variable), the FP32-bulk
+    member's increment within the stated FP32-bulk tolerance of the FP64 oracle."""
+    import torch
+    from helpers import gate_ok
+    fp32_tol = np.array([2e-5, 5e-4, 5e-4, 5e-4, 1e-4])
+    specs = [dict(ex=3, ey=2, ez=5, N=3, Ma=0.4, deform=True),
+             dict(ex=3, N=4, Ma=0.1, Re=1600.0, deform=True),
+             dict(ex=2, N=4, Ma=0.1, Re=800.0, precision="fp32_bulk"),
+             dict(ex=2, N=5, Ma=0.2, surf="llf"), dict(ex=2, N=5, Ma=0.2, surf="es", vol="ir"),
+             dict(ex=2, N=3, Ma=0.3, vol="pirozzoli"),
+             dict(ex=2, N=4, Ma=0.2, Re=500.0, visc="ip"),
+             dict(ex=3, orders=synth.mixed_orders(27, seed=2), Ma=0.5, lo=(-10.0,) * 3, hi=(10.0,) * 3)]
+    steps = 4
+    gpu, ref = [], []
+    for sp in specs:
+        oc = {k: v for k, v in sp.items() if k != "precision"}
+        o = orc.OracleSolver(**oc)
+        if "orders" in sp:
+            o.set_ic("vortex", [5.0, 0.0, 0.0, 0.4, 0.4])
+        else:
+            o.set_ic("tgv")
+        U0 = o.state()
+        dt = o.suggest_dt(0.4)
+        s = dg.Solver(**sp)
+        s.set_state(U0)
+        gpu.append(s)
+        ref.append((oc, U0, dt, o))
+    b = dg.Batch(gpu, stream=torch.cuda.Stream())
+    b.rk_step([r[2] for r in ref], steps)
+    b.stream.synchronize()
+    for sp, s, (oc, U0, dt, o64) in zip(specs, gpu, ref):
+        o64.rk3(dt, steps)
+        Ug, Uo = s.state(), o64.state()
+        lay = [(o64.elem(e)[1], int(np.prod([n + 1 for n in o64.elem(e)[0]]))) for e in range(o64.E)]
+
+        def pv(A):
+            m = np.zeros(5)
+            for off, nn in lay:
+                m = np.maximum(m, np.abs(A[5 * off:5 * (off + nn)]).reshape(5, nn).max(axis=1))
+            return m
+        name = ",".join(f"{k}={v}" for k, v in sp.items() if k != "orders")
+        if sp.get("precision") == "fp32_bulk":
+            err = pv(Ug - Uo) / pv(Uo - U0)
+            print(f"[batch member {name}] increment rel err vs fp64 oracle {err}", flush=True)
+            assert np.all(err < fp32_tol), err
+        else:
+            o80 = orc.OracleSolver(**oc, precision="fp80")
+            o80.set_state(U0)
+            o80.rk3(dt, steps)
+            U80 = o80.state()
+            sc = pv(U80)
+            print(f"[batch member {name}] gpu-vs-fp80 {pv(Ug - U80) / sc} fp64-vs-fp80 {pv(Uo - U80) / sc}",
+                  flush=True)
+            assert gate_ok(f"batch member {name}", pv(Ug - U80), pv(Uo - U80), sc, 1e-14), "parity gate"
+    b.close()

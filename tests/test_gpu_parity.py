@@ -5,8 +5,9 @@ are far larger than the result (at Ma 0.1 the pressure p0 = 71.4 and total entha
 cancel to O(0.1-1) rates), so any two FP64 evaluations that round differently disagree by
 the rounding level of that sum.  That level is measured, per test, as the difference between
 the oracle's double build and its long-double build on the same input (e64).  The GPU result
-must lie within max(1e-12 |R|, 8 e64) of the long-double oracle, per conserved variable: the
-GPU path is as accurate as a plain FP64 evaluation.  The relative error against the double
+must lie within max(1e-12 |R|, GATE e64) of the long-double oracle, per conserved variable,
+with GATE = 2 (tests/helpers.py): the GPU path rounds at most twice as badly as a plain FP64
+evaluation.  The relative error against the double
 oracle is printed as well.
 """
 import math
@@ -15,7 +16,7 @@ import sys
 import numpy as np
 import pytest
 
-from helpers import to_conservative
+from helpers import to_conservative, GATE, gate_ok, parity_log
 from paper_2206_09733_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -55,16 +56,19 @@ def per_var(A, nvar=5, E=None, nn=None):
     return np.asarray(A).reshape(E, nvar, nn)
 
 
-def assert_parity(name, Rg, R64, R80, E, nn, factor=8.0):
+def assert_parity(name, Rg, R64, R80, E, nn, factor=GATE):
     G, A, B = (x.reshape(E, 5, nn) for x in (Rg, R64, R80))
     scale = np.abs(B).max(axis=(0, 2))
     e64 = np.abs(A - B).max(axis=(0, 2))
     eg = np.abs(G - B).max(axis=(0, 2))
     rel64 = np.abs(G - A).max(axis=(0, 2)) / np.maximum(np.abs(A).max(axis=(0, 2)), 1e-300)
     tol = np.maximum(1e-12 * scale, factor * e64)
+    glob = np.abs(G - B).max() / np.abs(B).max()
     log(f"[{name}] |R|={np.array2string(scale, precision=2)} gpu-vs-fp80={np.array2string(eg, precision=2)} "
-        f"fp64-vs-fp80={np.array2string(e64, precision=2)} rel-vs-fp64={np.array2string(rel64, precision=2)}")
-    assert np.all(eg <= tol), (name, eg, tol)
+        f"fp64-vs-fp80={np.array2string(e64, precision=2)} rel-vs-fp64={np.array2string(rel64, precision=2)} "
+        f"global rel vs fp80 {glob:.2e}")
+    parity_log(name + " global", gpu_global_rel=float(glob), fp64_global_rel=float(np.abs(A - B).max() / np.abs(B).max()))
+    assert gate_ok(name, eg, e64, scale) and np.all(eg <= tol), (name, eg, tol)
     return rel64
 
 
@@ -86,7 +90,7 @@ def perturbed_state(orc, c, seed, amp=(0.02, 0.05, 0.02)):
 @pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 6, 7])
 def test_geometry_parity(dg, orc, N):
     """FP64 geometry kernel: node coordinates, curl-form metric terms and Jacobian against the
-    oracle's long-double build, within 8x the double build's own rounding (the metric terms are
+    oracle's long-double build, within GATE = 2 times the double build's own rounding (the metric terms are
     sums of O(N^2) products, so their rounding grows with N)."""
     log(f"geometry N={N}")
     c = dict(ex=3, ey=2, ez=4, N=N, deform=True)
@@ -100,7 +104,7 @@ def test_geometry_parity(dg, orc, N):
                             ("J", Jg, o.metrics()[1], o80.metrics()[1])):
         eg, e64 = np.abs(a - b80).max(), np.abs(b - b80).max()
         log(f"[geometry N={N} {name}] gpu-vs-fp80 {eg:.2e} fp64-vs-fp80 {e64:.2e} scale {np.abs(b80).max():.2e}")
-        assert eg <= max(1e-14 * np.abs(b80).max(), 8 * e64)
+        assert gate_ok("test_geometry_parity", eg, e64, np.abs(b80).max(), 1e-14), "parity gate"
 
 
 @pytest.mark.parametrize("ic,params", [("tgv", None), ("uniform", [1.2, 0.3, -0.1, 0.2, 3.0]),
@@ -198,7 +202,7 @@ def test_global_lax_friedrichs_trajectory(dg, orc):
     d = lambda a, b: np.abs(a - b).reshape(27, 5, 125).max(axis=(0, 2))
     sc = np.abs(U80).reshape(27, 5, 125).max(axis=(0, 2))
     log(f"[lf_global RK] gpu-vs-fp80 {d(Ug, U80) / sc} fp64-vs-fp80 {d(Uo, U80) / sc}")
-    assert np.all(d(Ug, U80) <= np.maximum(1e-14 * sc, 8 * d(Uo, U80)))
+    assert gate_ok("test_global_lax_friedrichs_trajectory", d(Ug, U80), d(Uo, U80), sc, 1e-14), "parity gate"
 
 
 def test_gpu_entropy_matrix_dissipation(dg, orc):
@@ -294,7 +298,7 @@ def test_viscous_face_schemes_trajectory_and_fp32(dg, orc, visc):
     d = lambda a, b: np.abs(a - b).reshape(27, 5, 125).max(axis=(0, 2))
     sc = np.abs(U80).reshape(27, 5, 125).max(axis=(0, 2))
     log(f"[{visc} RK] gpu-vs-fp80 {d(Ug, U80) / sc} fp64-vs-fp80 {d(Uo, U80) / sc}")
-    assert np.all(d(Ug, U80) <= np.maximum(1e-14 * sc, 8 * d(Uo, U80)))
+    assert gate_ok("test_viscous_face_schemes_trajectory_and_fp32", d(Ug, U80), d(Uo, U80), sc, 1e-14), "parity gate"
     c8 = dict(ex=8, N=4, deform=True, Ma=0.1, Re=1600.0)
     U8 = perturbed_state(orc, dict(c8, vol="ec", surf="roe"), seed=78, amp=(1e-3, 1e-3, 1e-3))
     o8 = orc.OracleSolver(**c8, visc=visc)
@@ -375,7 +379,7 @@ def test_rk3_trajectory_c1(dg, orc):
     d = lambda a, b: np.abs(a - b).reshape(64, 5, 64).max(axis=(0, 2))
     sc = np.abs(U80).reshape(64, 5, 64).max(axis=(0, 2))
     log(f"[C1 RK] gpu-vs-fp80 {d(Ug, U80) / sc} fp64-vs-fp80 {d(Uo, U80) / sc}")
-    assert np.all(d(Ug, U80) <= np.maximum(1e-14 * sc, 8 * d(Uo, U80)))
+    assert gate_ok("test_rk3_trajectory_c1", d(Ug, U80), d(Uo, U80), sc, 1e-14), "parity gate"
 
 
 def test_rk3_trajectory_navier_stokes(dg, orc):
@@ -395,7 +399,7 @@ def test_rk3_trajectory_navier_stokes(dg, orc):
     d = lambda a, b: np.abs(a - b).reshape(27, 5, 125).max(axis=(0, 2))
     sc = np.abs(U80).reshape(27, 5, 125).max(axis=(0, 2))
     log(f"[NS RK] gpu-vs-fp80 {d(Ug, U80) / sc} fp64-vs-fp80 {d(Uo, U80) / sc}")
-    assert np.all(d(Ug, U80) <= np.maximum(1e-14 * sc, 8 * d(Uo, U80)))
+    assert gate_ok("test_rk3_trajectory_navier_stokes", d(Ug, U80), d(Uo, U80), sc, 1e-14), "parity gate"
 
 
 @pytest.mark.parametrize("case", ["c1_euler", "navier_stokes"])
@@ -429,7 +433,7 @@ def test_rk4_trajectory(dg, orc, case):
     dG, d64, d80 = Ug - U0, Uo - U0, U80 - U0
     sc = np.abs(d80).reshape(E, 5, nn).max(axis=(0, 2))
     log(f"[RK4 {case}] increment error: gpu-vs-fp80 {d(dG, d80) / sc} fp64-vs-fp80 {d(d64, d80) / sc}")
-    assert np.all(d(dG, d80) <= np.maximum(1e-12 * sc, 8 * d(d64, d80)))
+    assert gate_ok("test_rk4_trajectory", d(dG, d80), d(d64, d80), sc, 1e-12), "parity gate"
     # not the RK3 trajectory
     g3 = dg.Solver(**c)
     g3.set_state(U0)
@@ -624,4 +628,4 @@ def test_full_size_c2_residual_and_step(dg, orc):
     eg = np.abs(dG - d80).reshape(E, 5, nn).max(axis=(0, 2))
     e64 = np.abs(d64 - d80).reshape(E, 5, nn).max(axis=(0, 2))
     log(f"[C2] one RK3 step, increment error: gpu-vs-fp80 {eg / sc} fp64-vs-fp80 {e64 / sc}")
-    assert np.all(eg <= np.maximum(1e-12 * sc, 8 * e64))
+    assert gate_ok("test_full_size_c2_residual_and_step", eg, e64, sc, 1e-12), "parity gate"

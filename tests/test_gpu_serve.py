@@ -58,3 +58,76 @@ def test_served_results_equal_alone(dg, mixed_precision):
         assert r.diagnostics["nonfinite"] == 0
         assert np.array_equal(U, r.state), (q, np.abs(U - r.state).max())
         s.close()
+
+
+# FP32-bulk served results: the stated tolerance of the FP32-bulk path (relative L-inf per
+# conserved variable against the FP64 oracle), applied to the increment of the served state
+FP32_TOL = np.array([2e-5, 5e-4, 5e-4, 5e-4, 1e-4])
+
+
+def test_served_results_match_oracle(dg, orc):
+    """Served solves of each kind -- Euler and Navier-Stokes, orders 3, 4 and 5, Mach numbers up
+    to 0.8, FP64 and FP32-bulk -- against the oracle run alone with the same step.  The
+    comparison is on the increment U_k - U_0 of each side's own Taylor-Green state, so that the
+    two evaluations of the analytic initial state do not enter: FP64 requests within the parity
+    gate (max(1e-12 |dU|, GATE e64) per variable, e64 the FP64 oracle's own error against its
+    long-double build), FP32-bulk requests within the stated FP32-bulk tolerance of the FP64
+    oracle.  Other requests share the loop, so each anchored solve is served in a mix."""
+    import time
+    from helpers import gate_ok
+    kinds = [dict(E=3, N=3, Ma=0.3, Re=0.0, precision="fp64"),
+             dict(E=2, N=5, Ma=0.8, Re=400.0, precision="fp64"),
+             dict(E=2, N=4, Ma=0.8, Re=0.0, precision="fp64"),
+             dict(E=3, N=4, Ma=0.1, Re=1600.0, precision="fp64"),
+             dict(E=2, N=5, Ma=0.5, Re=0.0, precision="fp32_bulk"),
+             dict(E=3, N=3, Ma=0.1, Re=3200.0, precision="fp32_bulk"),
+             dict(E=2, N=4, Ma=0.8, Re=800.0, precision="fp32_bulk")]
+    steps = 12
+    reqs, dts = [], []
+    for i, k in enumerate(kinds):
+        o = orc.OracleSolver(k["E"], N=k["N"], Ma=k["Ma"], Re=k["Re"])
+        o.set_ic("tgv")
+        dts.append(o.suggest_dt(0.5))
+        reqs.append(serve.Request(id=i, E=k["E"], N=k["N"], Ma=k["Ma"], Re=k["Re"], steps=steps + i % 3,
+                                  arrival=0.002 * i, precision=k["precision"], dt=dts[-1]))
+    # fillers that share the loop (not anchored)
+    for j, q in enumerate(small_requests(6, seed=11, steps=8)):
+        q.id, q.arrival = len(kinds) + j, 0.001 * j
+        reqs.append(q)
+    ex = serve.GpuExecutor()
+    budget = 4 * max(ex.required_bytes(q) for q in reqs)
+    sch = serve.Scheduler(ex, budget, max_active=6, chunk_steps=4)
+    t0 = time.perf_counter()
+    res = sch.run(reqs)
+    wall = time.perf_counter() - t0
+    ex.close()
+    assert serve.summarize(reqs, res, wall)["completed"] == len(reqs)
+    assert sch.peak_active > 1
+    for i, k in enumerate(kinds):
+        q, r = reqs[i], res[i]
+        c = dict(ex=k["E"], N=k["N"], Ma=k["Ma"], Re=k["Re"])
+        s0 = dg.Solver(**c, precision=k["precision"])
+        s0.set_ic("tgv")
+        Ug0 = s0.state()
+        s0.close()
+        o64 = orc.OracleSolver(**c)
+        o64.set_ic("tgv")
+        Uo0 = o64.state()
+        o64.rk3(dts[i], q.steps)
+        E, nn = k["E"] ** 3, (k["N"] + 1) ** 3
+        d = lambda a, b: np.abs(a - b).reshape(E, 5, nn).max(axis=(0, 2))
+        dG, d64 = r.state - Ug0, o64.state() - Uo0
+        if k["precision"] == "fp64":
+            o80 = orc.OracleSolver(**c, precision="fp80")
+            o80.set_state(Uo0)
+            o80.rk3(dts[i], q.steps)
+            d80 = o80.state() - Uo0
+            sc = np.abs(d80).reshape(E, 5, nn).max(axis=(0, 2))
+            print(f"[served {k}] increment gpu-vs-fp80 {d(dG, d80) / sc} fp64-vs-fp80 {d(d64, d80) / sc}",
+                  flush=True)
+            assert gate_ok(f"served {k}", d(dG, d80), d(d64, d80), sc, 1e-12), "parity gate"
+        else:
+            sc = np.abs(d64).reshape(E, 5, nn).max(axis=(0, 2))
+            err = d(dG, d64) / sc
+            print(f"[served {k}] increment rel err vs fp64 oracle {err}", flush=True)
+            assert np.all(err < FP32_TOL), err
