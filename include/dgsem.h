@@ -253,6 +253,16 @@ int dg_autotune(dg_solver* s, int* tiles, double* us);
 int dg_solver_set_tiles(dg_solver* s, int tiles);
 /* Diagnostics of the current state (synchronises). */
 int dg_diagnostics(dg_solver* s, dg_diag* out);
+/* For callers that cannot allocate (code under HIP graph capture, tight serving loops): the
+ * diagnostics of dg_diagnostics, written as a dg_diag record to the device memory dev_out
+ * (112 bytes, caller-owned, 8-byte aligned, on the solver's device), enqueued on the solver's stream
+ * without synchronising; the values equal dg_diagnostics's bit for bit.  The per-element partial
+ * sums live in a static device array of the library (4.2 MB per device, held until the process
+ * ends), so the call allocates no memory of any kind.  That array limits the mesh to 32768
+ * elements: larger meshes get DG_EUNSUPPORTED.  Calls on one device share the array: calls whose
+ * work overlaps on one device (e.g. on two streams) race and must be ordered by the caller.
+ * Errors: DG_EINVAL for a NULL output, DG_ESTATE for an unbound solver, DG_EHIP on a HIP failure. */
+int dg_diagnostics_noalloc(dg_solver* s, dg_diag* dev_out);
 /* dt = cfl h_min / ((N_max+1)^2 lambda_max), and with viscosity the smaller of that and
  * 0.25 h_min^2 / ((N_max+1)^4 gamma mu / (Pr rho_min)), mu = 1/Re plus svv_mu; h_min = smallest
  * undeformed element edge; lambda_max, rho_min from dg_diagnostics of the current state. */

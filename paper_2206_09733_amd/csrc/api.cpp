@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <numeric>
@@ -91,6 +92,7 @@ struct dg_solver {
   dg::View v;
   hipStream_t stream = nullptr;
   bool bound = false;
+  int device = 0;                    // HIP device of the bound buffer
   int cur = 0;
   long long E = 0, ntot = 0;
   std::vector<long long> off;        // first node of every element, and the total at [E]
@@ -256,6 +258,61 @@ hipError_t launch_diag_any(dg_solver* s) {
   return s->v.mixed ? dg::launch_diagnostics_mixed(s->v, s->cur, s->stream)
                     : dg::launch_diagnostics(s->v, s->cur, s->stream);
 }
+
+}  // namespace
+
+// ------------------------------------------------------------------ diagnostics without allocation
+// dg_diagnostics_noalloc keeps its per-element partial sums and the reduced slots in this array,
+// not in the caller's buffer: a diagnostics call then needs no device memory beyond the bound
+// solver's state and geometry and the caller's 112-byte output.  Each device holds its own copy
+// for the life of the process; every call on a device shares it (calls that overlap on one device
+// race).  In host code the name is only a stand-in: kernels get the address that
+// hipGetSymbolAddress returns for the current device.
+constexpr long long kNoAllocMaxElements = 32768;
+static __device__ __align__(256) double scratch[(kNoAllocMaxElements + 1) * dg::kDiagSlots];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of `scratch` on the current device `dev` (looked up once per device)
+hipError_t scratch_on(int dev, double** out) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+// the reduced slots (see diag_kernel) as a dg_diag record in device memory
+__global__ void diag_record_kernel(const double* h, dg_diag* out) {
+  if (threadIdx.x != 0) return;
+  for (int k = 0; k < 5; k++) out->mass[k] = h[k];
+  out->entropy_paper = h[5];
+  out->entropy = h[6];
+  out->volume = h[13];
+  out->ke = h[7] / h[13];
+  out->enstrophy = h[8] / h[13];
+  out->lambda_max = h[9];
+  out->rho_min = h[10];
+  out->p_min = h[11];
+  out->nonfinite = (long long)h[12];
+}
+
+// restores the calling thread's current device on scope exit
+struct DeviceGuard {
+  int prev = -1;
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
 
 // Williamson's low-storage RK3
 // Low-storage (2N) Runge-Kutta schemes: per stage k, dU <- A_k dU + dt R; U <- U + B_k dU.
@@ -708,6 +765,13 @@ int dg_solver_bind(dg_solver* s, void* dev_ptr, size_t bytes, void* hip_stream) 
   int rc = upload_view(s);
   if (rc) return rc;
   DG_HIP(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking), "capture stream");
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, dev_ptr) == hipSuccess && attr.device >= 0) {
+    s->device = attr.device;
+  } else {
+    (void)hipGetLastError();
+    DG_HIP(hipGetDevice(&s->device), "current device");
+  }
   s->bound = true;
   s->cur = 0;
   return DG_OK;
@@ -969,6 +1033,35 @@ int dg_diagnostics(dg_solver* s, dg_diag* out) try {
   out->rho_min = h[10];
   out->p_min = h[11];
   out->nonfinite = (long long)h[12];
+  return DG_OK;
+} catch (...) {
+  return abi_exception();
+}
+
+int dg_diagnostics_noalloc(dg_solver* s, dg_diag* dev_out) try {
+  int rc = check_bound(s);
+  if (rc) return rc;
+  if (!dev_out) return fail(DG_EINVAL, "NULL output");
+  if (s->E > kNoAllocMaxElements)
+    return fail(DG_EUNSUPPORTED, "dg_diagnostics_noalloc takes meshes of at most " +
+                                     std::to_string(kNoAllocMaxElements) + " elements (its static scratch "
+                                     "holds that many partial sums); use dg_diagnostics");
+  DeviceGuard guard;
+  int dev = 0;
+  DG_HIP(hipGetDevice(&dev), "current device");
+  if (dev != s->device) {
+    guard.prev = dev;
+    DG_HIP(hipSetDevice(s->device), "select the solver's device");
+  }
+  double* ptr = nullptr;
+  DG_HIP(scratch_on(s->device, &ptr), "address of the static diagnostics scratch");
+  dg::View v = s->v;  // the solver's view with the partial sums and the slots in the scratch
+  v.part = ptr;
+  v.diag = ptr + kNoAllocMaxElements * dg::kDiagSlots;
+  DG_HIP(v.mixed ? dg::launch_diagnostics_mixed(v, s->cur, s->stream) : dg::launch_diagnostics(v, s->cur, s->stream),
+         "diagnostics kernels");
+  hipLaunchKernelGGL(diag_record_kernel, dim3(1), dim3(64), 0, s->stream, v.diag, dev_out);
+  DG_HIP(hipGetLastError(), "diagnostics record kernel");
   return DG_OK;
 } catch (...) {
   return abi_exception();

@@ -63,7 +63,7 @@ EXPORTS = ["dg_last_error", "dg_mesh_create_box", "dg_mesh_destroy", "dg_mesh_in
            "dg_synchronize", "dg_solver_destroy", "dg_profile_begin", "dg_profile_end",
            "dg_solver_use_graphs", "dg_autotune", "dg_solver_set_tiles", "dg_batch_create",
            "dg_batch_rk_step", "dg_batch_use_graphs", "dg_batch_launches", "dg_batch_destroy",
-           "dg_solver_set_scheme"]
+           "dg_solver_set_scheme", "dg_diagnostics_noalloc"]
 
 _lib = None
 
@@ -103,6 +103,7 @@ def lib():
     L.dg_rk_step.argtypes = [vp, _c.c_double, _c.c_int]
     L.dg_rk_step_adaptive.argtypes = [vp, _c.c_double, _c.c_int, _dp]
     L.dg_diagnostics.argtypes = [vp, _c.POINTER(Diag)]
+    L.dg_diagnostics_noalloc.argtypes = [vp, vp]
     L.dg_suggest_dt.argtypes = [vp, _c.c_double, _dp]
     L.dg_get_geometry.argtypes = [vp, _dp, _dp, _dp]
     L.dg_device_pointers.argtypes = [vp, _c.POINTER(vp), _c.POINTER(vp)]
@@ -257,6 +258,23 @@ class Solver:
     def diagnostics(self):
         d = Diag()
         check(lib().dg_diagnostics(self.h, _c.byref(d)))
+        out = {f"mass_{k}": d.mass[i] for i, k in enumerate(["rho", "rhou", "rhov", "rhow", "rhoE"])}
+        for k in ("entropy_paper", "entropy", "ke", "enstrophy", "lambda_max", "rho_min", "p_min",
+                  "volume"):
+            out[k] = getattr(d, k)
+        out["nonfinite"] = d.nonfinite
+        return out
+
+    def diagnostics_noalloc(self, dev_out):
+        """Enqueue the diagnostics into the device memory at address dev_out (a dg_diag record;
+        e.g. the data_ptr of a 112-byte uint8 tensor); no allocation, no synchronisation."""
+        check(lib().dg_diagnostics_noalloc(self.h, _c.c_void_p(dev_out)))
+
+    @staticmethod
+    def diag_record(raw):
+        """The dg_diag record in the bytes `raw` (112 bytes, as written by diagnostics_noalloc) as
+        the dict of diagnostics()."""
+        d = Diag.from_buffer_copy(bytes(raw))
         out = {f"mass_{k}": d.mass[i] for i, k in enumerate(["rho", "rhou", "rhov", "rhow", "rhoE"])}
         for k in ("entropy_paper", "entropy", "ke", "enstrophy", "lambda_max", "rho_min", "p_min",
                   "volume"):
