@@ -26,6 +26,14 @@ __host__ __device__ constexpr int stage_waves_per_eu(int N, bool fp32) {
   return N <= 5 ? (fp32 && N != 3 ? 4 : 3) : 2;
 }
 
+// global operands of one face point of the stage kernel's face phase: the neighbour's and the
+// element's traces, the face's scaled normal, and the sum of the two sides' face viscous fluxes
+template <typename T>
+struct FaceIn {
+  double un[5], uo[5], S[3];
+  T fv[4];
+};
+
 template <int N, typename T, bool VISC, int FX>
 __device__ __forceinline__ void stage_body(const View& v, const int e, const int cur, const double dt,
                                            const double rkA, const double rkB, const int mode) {
@@ -69,11 +77,10 @@ __device__ __forceinline__ void stage_body(const View& v, const int e, const int
   T(*sPair)[P] = reinterpret_cast<T(*)[P]>(sRaw);
   double* sM = reinterpret_cast<double*>(sRaw + ((5 * P * (int)sizeof(T) + a16 - 1) / a16) * a16);  // pair mass flux
 
-  for (int x = t; x < n * n; x += NT) {
-    sD[x] = v.tab[2 * n + x];
-    sDh[x] = v.tab[2 * n + n * n + x];
-  }
-  if (t < n) sw[t] = v.tab[n + t];
+  // tables (every lane loads, the first n^2 store: no wait of their own before the other loads)
+  static_assert(n * n <= NT, "one table entry per lane");
+  const int tt = t < n * n ? t : 0;
+  const double tD = v.tab[2 * n + tt], tDh = v.tab[2 * n + n * n + tt], tw = v.tab[n + (t < n ? t : 0)];
   if (t < np) {  // pair k -> (a, b), ordered by a then b
     int a = 0, k = t;
     while (k >= n - 1 - a) {
@@ -84,6 +91,43 @@ __device__ __forceinline__ void stage_body(const View& v, const int e, const int
     sPb[t] = (unsigned char)(a + 1 + k);
   }
   const long base = (long)e * nn;
+  // The six neighbours (uniform over the workgroup: scalar loads), and the global operands of
+  // this lane's first face point, issued before the node's own state so that the two memory
+  // round trips overlap.
+  int nb[6];
+#pragma unroll
+  for (int f = 0; f < 6; f++) nb[f] = v.nbr[e * 6 + f];
+  const T* FvfAll = VISC ? reinterpret_cast<const T*>(v.Fvf) : nullptr;
+  auto face_load = [&](int x, FaceIn<T>& I) {
+    const int f = x / nf, q = x - f * nf;
+    const int d = f >> 1, side = f & 1;
+    const int p = q % n, r = q / n;
+    const int io = face_node<n>(d, side ? N : 0, p, r);
+    const int inb = face_node<n>(d, side ? 0 : N, p, r);
+    int ne = nb[0];
+#pragma unroll
+    for (int k = 1; k < 6; k++) ne = f == k ? nb[k] : ne;
+#pragma unroll
+    for (int c = 0; c < 5; c++) {
+      I.un[c] = Uin[(long)ne * nn * 5 + c * nn + inb];
+      I.uo[c] = Uin[base * 5 + c * nn + io];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; c++) I.S[c] = v.Ja[base * 9 + (3 * d + c) * nn + io];
+    if (VISC) {
+      const T* fo = FvfAll + ((long)e * 6 + f) * 4 * nf;
+      const T* fn = FvfAll + ((long)ne * 6 + (f ^ 1)) * 4 * nf;
+#pragma unroll
+      for (int c = 0; c < 4; c++) I.fv[c] = fo[c * nf + q] + fn[c * nf + q];
+    }
+  };
+  FaceIn<T> face0;
+  if (t < 6 * nf) face_load(t, face0);
+  if (t < n * n) {
+    sD[t] = tD;
+    sDh[t] = tDh;
+  }
+  if (t < n) sw[t] = tw;
   double ja[9], ij = 0.0;
   if (act) {
     double u[5];
@@ -117,54 +161,59 @@ __device__ __forceinline__ void stage_body(const View& v, const int e, const int
   // ---- faces: numerical flux (minus the BR1 viscous flux) on the 6 (N+1)^2 face grids.  Both
   // elements of a face evaluate it from the same global values in the same argument order, so
   // it is single-valued.
-  const T* FvfAll = VISC ? reinterpret_cast<const T*>(v.Fvf) : nullptr;
   const double lam_g = (FX & 2) != 0 && v.surf == 8 ? v.adapt[3] : 0.0;  // global Lax-Friedrichs
-  for (int x = t; x < 6 * nf; x += NT) {
+  auto face_eval = [&](int x, const FaceIn<T>& I) {
     const int f = x / nf, q = x - f * nf;
     const int d = f >> 1, side = f & 1;
     const int p = q % n, r = q / n;
     const int io = face_node<n>(d, side ? N : 0, p, r);
-    const int ne = v.nbr[e * 6 + f];
-    const int inb = face_node<n>(d, side ? 0 : N, p, r);
-    double un[5], uL[5], uR[5], S[3];
+    double uL[5], uR[5];
 #pragma unroll
     for (int c = 0; c < 5; c++) {
-      un[c] = Uin[(long)ne * nn * 5 + c * nn + inb];
-      const double uo = Uin[base * 5 + c * nn + io];
-      uL[c] = side ? uo : un[c];
-      uR[c] = side ? un[c] : uo;
+      uL[c] = side ? I.uo[c] : I.un[c];
+      uR[c] = side ? I.un[c] : I.uo[c];
     }
-#pragma unroll
-    for (int c = 0; c < 3; c++) S[c] = v.Ja[base * 9 + (3 * d + c) * nn + io];
     T F[5];
     if (DEV) {
       double F0d;
-      face_flux_dev<T>(v.surf, uL, uR, S, v.gamma, Rf, F, F0d);
+      face_flux_dev<T>(v.surf, uL, uR, I.S, v.gamma, Rf, F, F0d);
       sF0d[f][q] = F0d;
     } else {
-      face_flux<T, (FX & 2) != 0>(v.surf, uL, uR, S, v.gamma, F, lam_g);
+      face_flux<T, (FX & 2) != 0>(v.surf, uL, uR, I.S, v.gamma, F, lam_g);
     }
     if (VISC) {
-      const T* fo = FvfAll + ((long)e * 6 + f) * 4 * nf;
-      const T* fn = FvfAll + ((long)ne * 6 + (f ^ 1)) * 4 * nf;
 #pragma unroll
-      for (int c = 0; c < 4; c++) F[1 + c] -= (T)0.5 * (fo[c * nf + q] + fn[c * nf + q]);
+      for (int c = 0; c < 4; c++) F[1 + c] -= (T)0.5 * I.fv[c];
       T gn[4];
-      gvars(un, v.gamma, Tref, gn);
+      gvars(I.un, v.gamma, Tref, gn);
       const T go[4] = {sP[1][io], sP[2][io], sP[3][io], sT[io]};
 #pragma unroll
       for (int c = 0; c < 4; c++) sJ[f][c][q] = (T)0.5 * (gn[c] - go[c]);
     }
 #pragma unroll
     for (int c = 0; c < 5; c++) sF[f][c][q] = F[c];
-  }
-  if constexpr ((FX & 2) != 0 || VISC) {
+  };
+  // the metric terms of the kernels that load them late: in FP64 with the standard surface fluxes
+  // issued before the remaining face points, so that their latency overlaps that work; the others
+  // issue them after the face points (issued early they would spill: FP32-bulk at 4 waves per
+  // SIMD, the extended surface fluxes, and FP64 Navier-Stokes at order 3)
+  auto load_metric = [&]() {
     if (act) {
 #pragma unroll
       for (int c = 0; c < 9; c++) ja[c] = v.Ja[base * 9 + c * nn + t];
       ij = v.invJ[base + t];
     }
+  };
+  constexpr bool late_metric = (FX & 2) != 0 || VISC;
+  constexpr bool early = late_metric && !DEV && (FX & 2) == 0 && N != 3;
+  if (t < 6 * nf) face_eval(t, face0);
+  if constexpr (early) load_metric();
+  for (int x = t + NT; x < 6 * nf; x += NT) {
+    FaceIn<T> I;
+    face_load(x, I);
+    face_eval(x, I);
   }
+  if constexpr (late_metric && !early) load_metric();
   __syncthreads();
 
   const T iwN = (T)(1.0 / sw[N]), iw0 = (T)(1.0 / sw[0]);
@@ -209,6 +258,17 @@ __device__ __forceinline__ void stage_body(const View& v, const int e, const int
           for (int c = 0; c < 4; c++) acc[1 + c] -= Dh * sFv[c][b0 + m * stride];
         }
       }
+    }
+  }
+
+  // The RK update's operands, loaded before the pair phase so that their latency hides behind it
+  const long o = base * 5 + t;
+  double u_in[5], du_in[5];
+  if (act && mode != kModeResidual) {
+#pragma unroll
+    for (int c = 0; c < 5; c++) {
+      u_in[c] = Uin[o + c * nn];
+      du_in[c] = rkA == 0.0 ? 0.0 : v.dU[o + c * nn];
     }
   }
 
@@ -286,7 +346,6 @@ __device__ __forceinline__ void stage_body(const View& v, const int e, const int
     R[0] = -acc0d * ij;
     R[4] -= Rf.H * acc0d * ij;
   }
-  const long o = base * 5 + t;
   if (mode == kModeResidual) {
 #pragma unroll
     for (int c = 0; c < 5; c++) v.R[o + c * nn] = R[c];
@@ -296,9 +355,9 @@ __device__ __forceinline__ void stage_body(const View& v, const int e, const int
   const double h = v.dtp ? *v.dtp : dt;
 #pragma unroll
   for (int c = 0; c < 5; c++) {
-    const double du = (rkA == 0.0 ? 0.0 : rkA * v.dU[o + c * nn]) + h * R[c];
+    const double du = (rkA == 0.0 ? 0.0 : rkA * du_in[c]) + h * R[c];
     v.dU[o + c * nn] = du;
-    Uout[o + c * nn] = Uin[o + c * nn] + rkB * du;
+    Uout[o + c * nn] = u_in[c] + rkB * du;
   }
 }
 
