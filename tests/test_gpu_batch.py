@@ -150,7 +150,8 @@ def test_batch_members_match_oracle(dg, orc):
     member's increment within the stated FP32-bulk tolerance of the FP64 oracle."""
     import torch
     from helpers import gate_ok
-    fp32_tol = np.array([2e-5, 5e-4, 5e-4, 5e-4, 1e-4])
+    from helpers import FP32_TOL
+    fp32_tol = FP32_TOL["small"]
     specs = [dict(ex=3, ey=2, ez=5, N=3, Ma=0.4, deform=True),
              dict(ex=3, N=4, Ma=0.1, Re=1600.0, deform=True),
              dict(ex=2, N=4, Ma=0.1, Re=800.0, precision="fp32_bulk"),

@@ -16,7 +16,7 @@ import sys
 import numpy as np
 import pytest
 
-from helpers import to_conservative, GATE, gate_ok, parity_log
+from helpers import to_conservative, GATE, gate_ok, parity_log, FP32_TOL as FP32_TOLS
 from paper_2206_09733_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -505,11 +505,10 @@ def test_set_state_rejects_bad_input(dg, orc):
 
 # ------------------------------------------------------------------ FP32-bulk
 # Stated tolerance of the FP32-bulk path (FP32 flux and derivative arithmetic in deviation form
-# about the state's mean density and pressure, mass flux, metric terms, RK state and reductions
-# in FP64), relative L-infinity per conserved variable against the FP64 oracle on the Ma 0.1
-# Taylor-Green state: density 2e-5, momentum 5e-4, energy 1e-4.  The momentum floor is FP32
-# rounding of the convective flux rho v v_n in a divergence-free field.
-FP32_TOL = np.array([2e-5, 5e-4, 5e-4, 5e-4, 1e-4])
+# about the state's mean density and pressure; mass flux, metric terms, RK state and reductions
+# in FP64): relative L-infinity per conserved variable against the FP64 oracle, FP32_TOL in
+# tests/helpers.py ("small" for these meshes, "c2" for the 32^3 benchmark mesh).
+FP32_TOL = FP32_TOLS["small"]
 
 
 @pytest.mark.parametrize("Re", [0.0, 1600.0])
@@ -591,7 +590,7 @@ def test_fp32_bulk_full_size(dg, orc):
     err = np.abs(Rg - Ro).reshape(E, 5, 125).max(axis=(0, 2)) / np.abs(Ro).reshape(E, 5, 125).max(axis=(0, 2))
     glob = np.abs(Rg - Ro).max() / np.abs(Ro).max()
     log(f"[FP32-bulk 32^3] rel err per var {err} global {glob:.2e}")
-    assert np.all(err < 4 * FP32_TOL), err
+    assert np.all(err < FP32_TOLS["c2"]), err
 
 
 # ------------------------------------------------------------------ full size

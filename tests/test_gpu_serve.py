@@ -61,8 +61,10 @@ def test_served_results_equal_alone(dg, mixed_precision):
 
 
 # FP32-bulk served results: the stated tolerance of the FP32-bulk path (relative L-inf per
-# conserved variable against the FP64 oracle), applied to the increment of the served state
-FP32_TOL = np.array([2e-5, 5e-4, 5e-4, 5e-4, 1e-4])
+# conserved variable against the FP64 oracle, tests/helpers.py), applied to the increment of the
+# served state
+from helpers import FP32_TOL as _FP32_TOLS  # noqa: E402
+FP32_TOL = _FP32_TOLS["small"]
 
 
 def test_served_results_match_oracle(dg, orc):
