@@ -27,7 +27,8 @@ _libs = {}
 def _lib(precision="fp64"):
     name = {"fp64": "liborc64.so", "fp80": "liborc80.so"}[precision]
     if name not in _libs:
-        path = os.path.join(HERE, name)
+        # ORACLE_LIB_DIR: another build of the same source (the sanitizer test's instrumented one)
+        path = os.path.join(os.environ.get("ORACLE_LIB_DIR", HERE), name)
         if not os.path.exists(path):
             from . import build as _b
             _b.build()
