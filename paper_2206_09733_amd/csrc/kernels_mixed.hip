@@ -154,6 +154,10 @@ __global__ void __launch_bounds__(512) ic_mixed_kernel(View v, int cur, int ic, 
 // orders agree), the numerical flux is evaluated at the mortar points, and it is L2-projected
 // onto the face grids of both elements: Fs[e][f][c][p + n_a r], f = 2 d + side of element e,
 // c = 0..4 the flux and c = 5 its FP64 mass component (FP32-bulk).  Each face is evaluated once.
+// In each tangential direction at most one side has fewer nodes than the mortar: only that side
+// is interpolated and projected along it (the other side's data already lies on the mortar
+// grid and is used in place), so every loop has a trip count and branches that are uniform over
+// the wave.
 __host__ __device__ constexpr int mix_lanes(int nnmax, int npl) { return ((nnmax + npl - 1) / npl + 63) / 64 * 64; }
 
 // q / n for 0 <= q < 4096 and 1 <= n <= 64, from inv_n = 1.0f / n: (q + 1/2)/n lies at least
@@ -185,95 +189,90 @@ __global__ void __launch_bounds__(64) mixed_face_kernel(View v, int cur) {
   const int naL = L.n[ta], nbL = L.n[tb], naR = R.n[ta], nbR = R.n[tb];
   const int ma = naL > naR ? naL : naR, mb = nbL > nbR ? nbL : nbR;
   const float ima = 1.0f / (float)ma;
+  // the side (0 = L, 1 = R, -1 = none) with fewer nodes than the mortar along a and along b
+  const int sa = naL < ma ? 0 : (naR < ma ? 1 : -1);
+  const int sb = nbL < mb ? 0 : (nbR < mb ? 1 : -1);
+  // na_s, nb_a: the a-side's node counts along a and b; nb_s: the b-side's node count along b
+  const int na_s = sa == 0 ? naL : naR, nb_a = sa == 0 ? nbL : nbR, nb_s = sb == 0 ? nbL : nbR;
+  // sA: rows 0-4 L's state, 5-7 L's Ja^d (L's grid), rows 8-12 R's state (R's grid); later
+  // rows 0-5 the flux on the mortar.  sB: the side interpolated along a (up to 8 rows), later
+  // the flux projected along a onto that side's grid (up to 6 rows).
+  __shared__ double sA[13][kMixNF], sB[8][kMixNF];
+  // interpolation to the mortar and projection back, along a and along b (only the sides
+  // that need them)
+  __shared__ double sIa[kMixNF], sPa[kMixNF], sIb[kMixNF], sPb[kMixNF];
   const double* mt = v.mtab;
-  // rows 0-4 L's state, 5-7 L's Ja^d, 8-12 R's state; then the flux rows
-  __shared__ double sA[13][kMixNF], sB[13][kMixNF];
-  // the face's mortar matrices: interpolation of L and R along a and b, projection onto L's
-  // and R's grids along a and b (unused ones stay unread)
-  __shared__ double sIaL[kMixNF], sIaR[kMixNF], sIbL[kMixNF], sIbR[kMixNF];
-  __shared__ double sPaL[kMixNF], sPaR[kMixNF], sPbL[kMixNF], sPbR[kMixNF];
-  {
-    auto stage = [&](double* dst, int n, int m, bool proj) __attribute__((always_inline)) {
-      if (n < m) {
-        const double* src = mt + v.mort_off[n - 1][m - 1] + (proj ? m * n : 0);
-        for (int x = t; x < m * n; x += 64) dst[x] = src[x];
-      }
-    };
-    stage(sIaL, naL, ma, false);
-    stage(sIaR, naR, ma, false);
-    stage(sIbL, nbL, mb, false);
-    stage(sIbR, nbR, mb, false);
-    stage(sPaL, naL, ma, true);
-    stage(sPaR, naR, ma, true);
-    stage(sPbL, nbL, mb, true);
-    stage(sPbR, nbR, mb, true);
+  if (sa >= 0) {
+    const double* src = mt + v.mort_off[na_s - 1][ma - 1];
+    for (int x = t; x < ma * na_s; x += 64) {
+      sIa[x] = src[x];
+      sPa[x] = src[ma * na_s + x];
+    }
   }
-
-  {  // stage the traces on their own grids (index p + n_a r)
-    const int nL = naL * nbL, nR = naR * nbR;
-    const float iLa = 1.0f / (float)naL, iRa = 1.0f / (float)naR;
+  if (sb >= 0) {
+    const double* src = mt + v.mort_off[nb_s - 1][mb - 1];
+    for (int x = t; x < mb * nb_s; x += 64) {
+      sIb[x] = src[x];
+      sPb[x] = src[mb * nb_s + x];
+    }
+  }
+  {  // the traces on their own grids (index p + n_a r)
     const int sLa = stride_of(L, ta), sLb = stride_of(L, tb), sRa = stride_of(R, ta), sRb = stride_of(R, tb);
     const int baseL = (L.n[d] - 1) * stride_of(L, d);
     const long offL = L.off, offR = R.off, nnL = L.nn, nnR = R.nn;
-    for (int x = t; x < nL + nR; x += 64) {
-      if (x < nL) {
-        const int r = sdiv(x, iLa), p = x - r * naL;
-        const int q = baseL + p * sLa + r * sLb;
+    const float iLa = 1.0f / (float)naL, iRa = 1.0f / (float)naR;
+    for (int x = t; x < naL * nbL; x += 64) {
+      const int r = sdiv(x, iLa), p = x - r * naL;
+      const int q = baseL + p * sLa + r * sLb;
 #pragma unroll
-        for (int c = 0; c < 5; c++) sA[c][x] = Uin[offL * 5 + c * nnL + q];
+      for (int c = 0; c < 5; c++) sA[c][x] = Uin[offL * 5 + c * nnL + q];
 #pragma unroll
-        for (int c = 0; c < 3; c++) sA[5 + c][x] = v.Ja[offL * 9 + (3 * d + c) * nnL + q];
-      } else {
-        const int y = x - nL;
-        const int r = sdiv(y, iRa), p = y - r * naR;
-        const int q = p * sRa + r * sRb;
+      for (int c = 0; c < 3; c++) sA[5 + c][x] = v.Ja[offL * 9 + (3 * d + c) * nnL + q];
+    }
+    for (int y = t; y < naR * nbR; y += 64) {
+      const int r = sdiv(y, iRa), p = y - r * naR;
+      const int q = p * sRa + r * sRb;
 #pragma unroll
-        for (int c = 0; c < 5; c++) sA[8 + c][y] = Uin[offR * 5 + c * nnR + q];
-      }
+      for (int c = 0; c < 5; c++) sA[8 + c][y] = Uin[offR * 5 + c * nnR + q];
     }
   }
   __syncthreads();
-  {  // along the first tangential direction (index pm + ma r)
-    const double* IaL = sIaL;
-    const double* IaR = sIaR;
-    const int nL1 = ma * nbL, nR1 = ma * nbR;
-    for (int x = t; x < nL1 + nR1; x += 64) {
-      const bool isL = x < nL1;
-      const int y = isL ? x : x - nL1;
+  // along a: the smaller side to the mortar (index pm + ma r); its fields are L's 8 or R's 5
+  if (sa >= 0) {
+    const int c0 = sa == 0 ? 0 : 8, nc = sa == 0 ? 8 : 5;
+    for (int y = t; y < ma * nb_a; y += 64) {
       const int r = sdiv(y, ima), pm = y - r * ma;
-      const int c0 = isL ? 0 : 8, nc = isL ? 8 : 5, nx = isL ? naL : naR;
-      const double* Ia = isL ? IaL : IaR;
-      for (int c = c0; c < c0 + nc; c++) {
-        double s;
-        if (nx == ma) {
-          s = sA[c][pm + nx * r];
-        } else {
-          s = 0.0;
-          for (int p = 0; p < nx; p++) s += Ia[pm * nx + p] * sA[c][p + nx * r];
-        }
+      for (int c = 0; c < nc; c++) {
+        double s = 0.0;
+        for (int p = 0; p < na_s; p++) s += sIa[pm * na_s + p] * sA[c0 + c][p + na_s * r];
         sB[c][y] = s;
       }
     }
   }
   __syncthreads();
-  {  // along the second, and the numerical flux at the mortar point (rows into sA)
-    const double* IbL = sIbL;
-    const double* IbR = sIbR;
-    for (int x = t; x < ma * mb; x += 64) {
-      const int rm = sdiv(x, ima), pm = x - rm * ma;
-      double a[13];
+  // along b, and the numerical flux at the mortar point (ma mb <= 49 points: one pass)
+  {
+    const int x = t;
+    const bool on = x < ma * mb;
+    const int rm = sdiv(x, ima), pm = x - rm * ma;
+    double a[13];
 #pragma unroll
-      for (int c = 0; c < 13; c++) {
-        const int nbX = c < 8 ? nbL : nbR;
-        const double* Ib = c < 8 ? IbL : IbR;
+    for (int c = 0; c < 13; c++) {
+      const bool isL = c < 8;
+      const double* row = (isL ? sa == 0 : sa == 1) ? sB[isL ? c : c - 8] : sA[c];  // on the mortar along a
+      const int nbX = isL ? nbL : nbR;
+      double s = 0.0;
+      if (on) {
         if (nbX == mb) {
-          a[c] = sB[c][pm + ma * rm];
+          s = row[pm + ma * rm];
         } else {
-          double s = 0.0;
-          for (int r = 0; r < nbX; r++) s += Ib[rm * nbX + r] * sB[c][pm + ma * r];
-          a[c] = s;
+          for (int r = 0; r < nbX; r++) s += sIb[rm * nbX + r] * row[pm + ma * r];
         }
       }
+      a[c] = s;
+    }
+    __syncthreads();  // every mortar point has read its data before the flux rows overwrite sA
+    if (on) {
       const double uL[5] = {a[0], a[1], a[2], a[3], a[4]};
       const double S[3] = {a[5], a[6], a[7]};
       const double uR[5] = {a[8], a[9], a[10], a[11], a[12]};
@@ -290,46 +289,40 @@ __global__ void __launch_bounds__(64) mixed_face_kernel(View v, int cur) {
     }
   }
   __syncthreads();
-  // L2 projection onto each side's grid, first along a (rows 0-5 of sB for L, 6-11 for R),
-  // then along b into Fs
-  const ElemInfo* Side[2] = {&L, &R};
-  const int eS[2] = {e, eR}, fS[2] = {2 * d + 1, 2 * d};
-  for (int x = t; x < 2 * kMixNF; x += 64) {
-    const int side = x >= kMixNF ? 1 : 0, y = x - side * kMixNF;
-    const int na = Side[side]->n[ta];
-    if (y >= na * mb) continue;
-    const int rm = sdiv(y, 1.0f / (float)na), po = y - rm * na;
-    const double* Pa = side ? sPaR : sPaL;
+  // L2 projection along a onto the smaller side's grid (index po + na rm), into sB
+  if (sa >= 0) {
+    for (int y = t; y < na_s * mb; y += 64) {
+      const int rm = sdiv(y, 1.0f / (float)na_s), po = y - rm * na_s;
 #pragma unroll
-    for (int c = 0; c < NC; c++) {
-      double s;
-      if (na == ma) {
-        s = sA[c][po + ma * rm];
-      } else {
-        s = 0.0;
-        for (int pm = 0; pm < ma; pm++) s += Pa[po * ma + pm] * sA[c][pm + ma * rm];
+      for (int c = 0; c < NC; c++) {
+        double s = 0.0;
+        for (int pm = 0; pm < ma; pm++) s += sPa[po * ma + pm] * sA[c][pm + ma * rm];
+        sB[c][y] = s;
       }
-      sB[6 * side + c][y] = s;
     }
   }
   __syncthreads();
-  for (int x = t; x < 2 * kMixNF; x += 64) {
-    const int side = x >= kMixNF ? 1 : 0, y = x - side * kMixNF;
-    const int na = Side[side]->n[ta], nb = Side[side]->n[tb];
-    if (y >= na * nb) continue;
-    const int ro = sdiv(y, 1.0f / (float)na), po = y - ro * na;
-    const double* Pb = side ? sPbR : sPbL;
-    double* out = v.Fs + ((long)eS[side] * 6 + fS[side]) * kFsFace;
+  // along b onto each side's face grid, into Fs
 #pragma unroll
-    for (int c = 0; c < NC; c++) {
-      double s;
-      if (nb == mb) {
-        s = sB[6 * side + c][po + na * ro];
-      } else {
-        s = 0.0;
-        for (int rm = 0; rm < mb; rm++) s += Pb[ro * mb + rm] * sB[6 * side + c][po + na * rm];
+  for (int side = 0; side < 2; side++) {
+    const ElemInfo& I = side ? R : L;
+    const int na = I.n[ta], nb = I.n[tb];
+    const double(*src)[kMixNF] = sa == side ? sB : sA;  // the flux along a on this side's grid
+    double* out = v.Fs + ((long)(side ? eR : e) * 6 + (side ? 2 * d : 2 * d + 1)) * kFsFace;
+    const float ina = 1.0f / (float)na;
+    for (int y = t; y < na * nb; y += 64) {
+      const int ro = sdiv(y, ina), po = y - ro * na;
+#pragma unroll
+      for (int c = 0; c < NC; c++) {
+        double s;
+        if (nb == mb) {
+          s = src[c][po + na * ro];
+        } else {
+          s = 0.0;
+          for (int rm = 0; rm < mb; rm++) s += sPb[ro * mb + rm] * src[c][po + na * rm];
+        }
+        out[c * kMixNF + y] = s;
       }
-      out[c * kMixNF + y] = s;
     }
   }
 }

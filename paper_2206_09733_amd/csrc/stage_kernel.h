@@ -94,9 +94,8 @@ __device__ __forceinline__ void stage_body(const View& v, const int e, const int
   // The six neighbours (uniform over the workgroup: scalar loads), and the global operands of
   // this lane's first face point, issued before the node's own state so that the two memory
   // round trips overlap.
-  int nb[6];
-#pragma unroll
-  for (int f = 0; f < 6; f++) nb[f] = v.nbr[e * 6 + f];
+  const int nb0 = v.nbr[e * 6], nb1 = v.nbr[e * 6 + 1], nb2 = v.nbr[e * 6 + 2], nb3 = v.nbr[e * 6 + 3],
+            nb4 = v.nbr[e * 6 + 4], nb5 = v.nbr[e * 6 + 5];
   const T* FvfAll = VISC ? reinterpret_cast<const T*>(v.Fvf) : nullptr;
   auto face_load = [&](int x, FaceIn<T>& I) {
     const int f = x / nf, q = x - f * nf;
@@ -104,9 +103,7 @@ __device__ __forceinline__ void stage_body(const View& v, const int e, const int
     const int p = q % n, r = q / n;
     const int io = face_node<n>(d, side ? N : 0, p, r);
     const int inb = face_node<n>(d, side ? 0 : N, p, r);
-    int ne = nb[0];
-#pragma unroll
-    for (int k = 1; k < 6; k++) ne = f == k ? nb[k] : ne;
+    const int ne = f < 3 ? (f == 0 ? nb0 : (f == 1 ? nb1 : nb2)) : (f == 3 ? nb3 : (f == 4 ? nb4 : nb5));
 #pragma unroll
     for (int c = 0; c < 5; c++) {
       I.un[c] = Uin[(long)ne * nn * 5 + c * nn + inb];
