@@ -3,7 +3,8 @@ and continues in a fresh solver from dg_set_state reproduces the uninterrupted r
 (FP64: uniform Navier-Stokes with RK3 and RK4, a mixed-order Euler mesh, graph replay on both
 sides).  In FP32-bulk the deviation form's reference state (mean density and pressure) is
 recomputed from the state handed to dg_set_state, so a resumed run matches to rounding only:
-it is checked against the uninterrupted run within the FP32-bulk tolerance of the increment."""
+both runs lie within the FP32-bulk tolerance of the FP64 result, so they are checked against each
+other within twice that tolerance, relative to the increment."""
 import numpy as np
 import pytest
 
@@ -70,4 +71,4 @@ def test_resume_fp32_bulk_within_tolerance(dg):
     d_ref = (U_ref - saved).reshape(E, 5, nn)
     err = np.abs(U.reshape(E, 5, nn) - U_ref.reshape(E, 5, nn)).max(axis=(0, 2)) / np.abs(d_ref).max(axis=(0, 2))
     print(f"[checkpoint fp32-bulk] resumed vs uninterrupted, relative to the increment {err}", flush=True)
-    assert np.all(err < FP32_TOL["small"]), err
+    assert np.all(err < 2 * FP32_TOL["small"]), err
