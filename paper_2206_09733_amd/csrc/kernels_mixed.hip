@@ -55,8 +55,17 @@ __device__ __forceinline__ int face_node_rt(const int n[3], int d, int id, int p
 }
 
 // Lobatto table pointers of order N (node count n = N + 1)
-__device__ __forceinline__ const double* tab_w(const View& v, int n) { return v.tab + v.tab_off[n - 1] + n; }
-__device__ __forceinline__ const double* tab_D(const View& v, int n) { return v.tab + v.tab_off[n - 1] + 2 * n; }
+// (the member arrays of the kernel argument are read with constant indices and a select: a
+// runtime index makes the compiler copy the whole argument to private memory)
+__device__ __forceinline__ int tab_offset(const View& v, int n) {
+  int o = v.tab_off[0];
+#pragma unroll
+  for (int k = 1; k < kMixN; k++) o = n - 1 == k ? v.tab_off[k] : o;
+  return o;
+}
+__device__ __forceinline__ const double* tab_w(const View& v, int n) { return v.tab + tab_offset(v, n) + n; }
+__device__ __forceinline__ const double* tab_D(const View& v, int n) { return v.tab + tab_offset(v, n) + 2 * n; }
+__device__ __forceinline__ double* state(const View& v, int k) { return k ? v.U[1] : v.U[0]; }
 
 // ------------------------------------------------------------------ geometry (FP64)
 __global__ void __launch_bounds__(512) geometry_mixed_kernel(View v) {
@@ -332,31 +341,94 @@ __global__ void __launch_bounds__(64) mixed_face_kernel(View v, int cur) {
 // a contiguous range of the work list (sorted by node count).  A lane holds NPL nodes (1 or 2,
 // the autotuner's choice per bucket), so the workgroup has mix_lanes(NNMAX, NPL) lanes.  KEP
 // selects the kinetic-energy-preserving volume fluxes (compiled apart, FP64 only).
+// Bound on the face points of an element of at most nnmax nodes (sum over its six faces of the
+// tangential node counts' products), for 1 <= n_d <= kMixN.
+__host__ __device__ constexpr int mix_face_points(int nnmax) {
+  int best = 0;
+  for (int a = 1; a <= kMixN; a++)
+    for (int b = 1; b <= kMixN; b++)
+      for (int c = 1; c <= kMixN; c++)
+        if (a * b * c <= nnmax) {
+          const int f = 2 * (a * b + b * c + a * c);
+          if (f > best) best = f;
+        }
+  return best;
+}
+
 template <int NNMAX, int NPL, typename T, bool KEP>
 __global__ void __launch_bounds__(mix_lanes(NNMAX, NPL))
     mixed_stage_kernel(View v, int wbeg, int cur, double dt, double rkA, double rkB, int mode) {
   constexpr int BS = mix_lanes(NNMAX, NPL);
   constexpr bool DEV = sizeof(T) == 4;  // FP32-bulk: deviation form, FP64 mass flux
+  constexpr int NC = DEV ? 6 : 5;       // face flux components read (FP32-bulk: + FP64 mass)
+  constexpr int NFS = NC * mix_face_points(NNMAX);
+  constexpr int KF = (NFS + BS - 1) / BS;  // face flux values per lane
   const int e = v.work[wbeg + blockIdx.x];
   const ElemInfo I = elem_info(v, e);
   const int t = threadIdx.x;
   const long off = I.off, nn = I.nn;
-  const double* __restrict__ Uin = v.U[cur];
+  const double* __restrict__ Uin = state(v, cur);
   const double* __restrict__ Fs = v.Fs + (long)e * 6 * kFsFace;
   const Ref Rf = make_ref(v.rho_r, v.p_r, v.gamma);
   const int str[3] = {1, I.n[0], I.n[0] * I.n[1]};
   const float inv0 = 1.0f / (float)I.n[0], inv01 = 1.0f / (float)str[2];
+  // face points of the faces normal to each direction, and where face f's fluxes start in sFs
+  // (the element's faces packed: f = 2 d + side, component-major within a face)
+  const int n0 = I.n[0], n1 = I.n[1], n2 = I.n[2];
+  const int pt0 = n1 * n2, pt1 = n0 * n2, pt2 = n0 * n1;
+  const float ip0 = 1.0f / (float)pt0, ip1 = 1.0f / (float)pt1, ip2 = 1.0f / (float)pt2;
+  const int fo1 = NC * pt0, fo2 = 2 * NC * pt0, fo3 = fo2 + NC * pt1, fo4 = fo2 + 2 * NC * pt1,
+            fo5 = fo4 + NC * pt2, fend = fo4 + 2 * NC * pt2;
 
   __shared__ double sD[3][kMixNF], sw[3][kMixN];
   __shared__ T sP[7][NNMAX];             // rho, v1, v2, v3, beta, ln rho, ln beta (FP32-bulk: deviations)
   constexpr int NV = DEV ? NNMAX : 1;
   __shared__ double sVd[3][NV];          // FP32-bulk: FP64 velocities for the mass flux
   __shared__ double sJ3[3][NNMAX];       // Ja^d of the direction in work
+  __shared__ double sFs[NFS];            // the element's face fluxes
+
+  // Every operand of the element is requested before any is used: state, the first direction's
+  // metric terms, the face fluxes and the tables (the tables with clamped indices, so that no
+  // load waits on a branch).
+  double u[NPL][5], jn[NPL][3];
+#pragma unroll
+  for (int s = 0; s < NPL; s++) {
+    const int q = t + s * BS;
+    const int qc = q < I.nn ? q : 0;
+#pragma unroll
+    for (int c = 0; c < 5; c++) u[s][c] = Uin[off * 5 + c * nn + qc];
+#pragma unroll
+    for (int c = 0; c < 3; c++) jn[s][c] = v.Ja[off * 9 + c * nn + qc];
+  }
+  double fv[KF];
+#pragma unroll
+  for (int k = 0; k < KF; k++) {
+    const int x = t + k * BS;
+    // face f of packed entry x, its component c and point q
+    const int f = x < fo1 ? 0 : (x < fo2 ? 1 : (x < fo3 ? 2 : (x < fo4 ? 3 : (x < fo5 ? 4 : 5))));
+    const int fb = f == 0 ? 0 : (f == 1 ? fo1 : (f == 2 ? fo2 : (f == 3 ? fo3 : (f == 4 ? fo4 : fo5))));
+    const int pf = f < 2 ? pt0 : (f < 4 ? pt1 : pt2);
+    const int c = sdiv(x - fb, f < 2 ? ip0 : (f < 4 ? ip1 : ip2)), q = x - fb - c * pf;
+    fv[k] = x < fend ? Fs[f * kFsFace + c * kMixNF + q] : 0.0;
+  }
+  double tD[3], tw[3];
+#pragma unroll
   for (int d = 0; d < 3; d++) {
     const int n = I.n[d];
-    for (int x = t; x < n * n; x += BS) sD[d][x] = tab_D(v, n)[x];
-    if (t < n) sw[d][t] = tab_w(v, n)[t];
+    tD[d] = tab_D(v, n)[t < n * n ? t : 0];
+    tw[d] = tab_w(v, n)[t < n ? t : 0];
   }
+  static_assert(BS >= kMixNF, "one table entry per lane");
+#pragma unroll
+  for (int d = 0; d < 3; d++) {
+    const int n = I.n[d];
+    if (t < n * n) sD[d][t] = tD[d];
+    if (t < n) sw[d][t] = tw[d];
+  }
+#pragma unroll
+  for (int k = 0; k < KF; k++)
+    if (t + k * BS < fend) sFs[t + k * BS] = fv[k];
+
   int ii[NPL][3];
 #pragma unroll
   for (int s = 0; s < NPL; s++) {
@@ -367,31 +439,37 @@ __global__ void __launch_bounds__(mix_lanes(NNMAX, NPL))
     ii[s][1] = j;
     ii[s][2] = k;
     if (q < I.nn) {
-      double u[5];
-#pragma unroll
-      for (int c = 0; c < 5; c++) u[c] = Uin[off * 5 + c * nn + q];
-      const Prim<T> P = DEV ? make_prim_dev<T>(u, v.gamma, Rf) : make_prim<T>(u, v.gamma);
+      const Prim<T> P = DEV ? make_prim_dev<T>(u[s], v.gamma, Rf) : make_prim<T>(u[s], v.gamma);
       sP[0][q] = P.rho; sP[1][q] = P.v1; sP[2][q] = P.v2; sP[3][q] = P.v3;
       sP[4][q] = P.beta; sP[5][q] = P.lrho; sP[6][q] = P.lbeta;
       if (DEV) {
-        const double ir = rcp(u[0]);
-        sVd[0][q] = u[1] * ir;
-        sVd[1][q] = u[2] * ir;
-        sVd[2][q] = u[3] * ir;
+        const double ir = rcp(u[s][0]);
+        sVd[0][q] = u[s][1] * ir;
+        sVd[1][q] = u[s][2] * ir;
+        sVd[2][q] = u[s][3] * ir;
       }
     }
   }
 
   // For each node and direction: sum over the line of D_im F#(U_i, U_m; Ja_i + Ja_m), then the
   // surface lift of the face fluxes.  Slot s of the lane holds node t + s BS.
-  T acc0[5] = {0, 0, 0, 0, 0}, acc1[5] = {0, 0, 0, 0, 0};
-  double m0 = 0.0, m1 = 0.0;  // FP32-bulk: FP64 mass accumulators
+  T acc[NPL][5];
+  double accm[NPL];  // FP32-bulk: FP64 mass accumulators
+#pragma unroll
+  for (int s = 0; s < NPL; s++) {
+#pragma unroll
+    for (int c = 0; c < 5; c++) acc[s][c] = 0;
+    accm[s] = 0.0;
+  }
   const T ce = (T)(0.5 / (v.gamma - 1.0)), gm1 = (T)(v.gamma - 1.0);
-  auto node_volume = [&](const int d, const int q, const int* iq, T* acc, double& accm) __attribute__((always_inline)) {
-    const int n = I.n[d], sd = str[d];
-    int ta, tb;
-    tangential(d, ta, tb);
-    const int id = iq[d];
+  // Direction d's parameters are passed in, and every per-direction choice is a select of
+  // values: an array indexed by the runtime d, or a select between captured variables, would keep
+  // the lambda's captures (the kernel argument among them) in private memory.
+  //   n, sd: node count and node stride along d; pf: points of a face normal to d; flo, fhi:
+  //   where the fluxes of the faces at index 0 and n - 1 along d start in sFs
+  auto node_volume = [&](const int d, const int n, const int sd, const int pf, const int flo, const int fhi,
+                         const int q, const int* iq, T* acc, double& accm) {
+    const int id = d == 0 ? iq[0] : (d == 1 ? iq[1] : iq[2]);
     const int b0 = q - id * sd;
     Prim<T> A;
     A.rho = sP[0][q]; A.v1 = sP[1][q]; A.v2 = sP[2][q]; A.v3 = sP[3][q];
@@ -425,36 +503,50 @@ __global__ void __launch_bounds__(mix_lanes(NNMAX, NPL))
       for (int c = 0; c < 5; c++) acc[c] += (T)Dm * F[c];
       if (DEV) accm += Dm * F0d;
     }
-    const int qf = iq[ta] + I.n[ta] * iq[tb];
+    // the node's point on the faces normal to d (tangential indices in increasing direction)
+    const int qf = d == 0 ? iq[1] + n1 * iq[2] : (d == 1 ? iq[0] + n0 * iq[2] : iq[0] + n0 * iq[1]);
     if (id == n - 1) {
       const double iw = 1.0 / sw[d][n - 1];
-      const double* F = Fs + (2 * d + 1) * kFsFace;
+      const double* F = sFs + fhi;
 #pragma unroll
-      for (int c = 0; c < 5; c++) acc[c] += (T)(iw * F[c * kMixNF + qf]);
-      if (DEV) accm += iw * F[5 * kMixNF + qf];
+      for (int c = 0; c < 5; c++) acc[c] += (T)(iw * F[c * pf + qf]);
+      if (DEV) accm += iw * F[5 * pf + qf];
     }
     if (id == 0) {
       const double iw = 1.0 / sw[d][0];
-      const double* F = Fs + 2 * d * kFsFace;
+      const double* F = sFs + flo;
 #pragma unroll
-      for (int c = 0; c < 5; c++) acc[c] -= (T)(iw * F[c * kMixNF + qf]);
-      if (DEV) accm -= iw * F[5 * kMixNF + qf];
+      for (int c = 0; c < 5; c++) acc[c] -= (T)(iw * F[c * pf + qf]);
+      if (DEV) accm -= iw * F[5 * pf + qf];
     }
   };
-  const int q0 = t, q1 = t + BS;
   for (int d = 0; d < 3; d++) {
     __syncthreads();  // the previous direction's metric is no longer read
-    if (q0 < I.nn)
 #pragma unroll
-      for (int c = 0; c < 3; c++) sJ3[c][q0] = v.Ja[off * 9 + (3 * d + c) * nn + q0];
-    if (NPL == 2 && q1 < I.nn)
+    for (int s = 0; s < NPL; s++)
+      if (t + s * BS < I.nn)
 #pragma unroll
-      for (int c = 0; c < 3; c++) sJ3[c][q1] = v.Ja[off * 9 + (3 * d + c) * nn + q1];
+        for (int c = 0; c < 3; c++) sJ3[c][t + s * BS] = jn[s][c];
     __syncthreads();
-    if (q0 < I.nn) node_volume(d, q0, ii[0], acc0, m0);
-    if (NPL == 2 && q1 < I.nn) node_volume(d, q1, ii[NPL - 1], acc1, m1);
+    if (d < 2) {  // the next direction's metric terms, in flight during this direction's sums
+#pragma unroll
+      for (int s = 0; s < NPL; s++) {
+        const int q = t + s * BS;
+        const int qc = q < I.nn ? q : 0;
+#pragma unroll
+        for (int c = 0; c < 3; c++) jn[s][c] = v.Ja[off * 9 + (3 * (d + 1) + c) * nn + qc];
+      }
+    }
+    const int n = d == 0 ? n0 : (d == 1 ? n1 : n2), sd = d == 0 ? 1 : (d == 1 ? n0 : n0 * n1);
+    const int pf = d == 0 ? pt0 : (d == 1 ? pt1 : pt2);
+    const int flo = d == 0 ? 0 : (d == 1 ? fo2 : fo4), fhi = d == 0 ? fo1 : (d == 1 ? fo3 : fo5);
+    // one call site (unrolled after inlining)
+#pragma unroll
+    for (int s = 0; s < NPL; s++)
+      if (t + s * BS < I.nn) node_volume(d, n, sd, pf, flo, fhi, t + s * BS, ii[s], acc[s], accm[s]);
   }
-  auto node_update = [&](const int q, const T* acc, const double accm) __attribute__((always_inline)) {
+  auto node_update = [&](const int q, const T* acc, const double accm) {
+    const long o = off * 5 + q;
     const double ij = v.invJ[off + q];
     double R[5];
 #pragma unroll
@@ -463,7 +555,6 @@ __global__ void __launch_bounds__(mix_lanes(NNMAX, NPL))
       R[0] = -accm * ij;
       R[4] -= Rf.H * accm * ij;
     }
-    const long o = off * 5 + q;
 #pragma unroll
     for (int c = 0; c < 5; c++) {
       if (mode == kModeResidual) {
@@ -471,12 +562,13 @@ __global__ void __launch_bounds__(mix_lanes(NNMAX, NPL))
       } else {
         const double du = (rkA == 0.0 ? 0.0 : rkA * v.dU[o + c * nn]) + (v.dtp ? *v.dtp : dt) * R[c];
         v.dU[o + c * nn] = du;
-        v.U[cur ^ 1][o + c * nn] = Uin[o + c * nn] + rkB * du;
+        state(v, cur ^ 1)[o + c * nn] = Uin[o + c * nn] + rkB * du;
       }
     }
   };
-  if (q0 < I.nn) node_update(q0, acc0, m0);
-  if (NPL == 2 && q1 < I.nn) node_update(q1, acc1, m1);
+#pragma unroll
+  for (int s = 0; s < NPL; s++)
+    if (t + s * BS < I.nn) node_update(t + s * BS, acc[s], accm[s]);
 }
 
 // ------------------------------------------------------------------ diagnostics (FP64)
