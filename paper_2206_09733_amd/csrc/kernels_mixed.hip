@@ -38,22 +38,6 @@ __device__ __forceinline__ ElemInfo elem_info(const View& v, int e) {
   return I;
 }
 
-// tangential directions of a face normal to d (ta < tb)
-__device__ __forceinline__ void tangential(int d, int& ta, int& tb) {
-  ta = d == 0 ? 1 : 0;
-  tb = d == 2 ? 1 : 2;
-}
-
-// node of an element with node counts n[] at reference indices ii[]
-__device__ __forceinline__ int node_index(const int n[3], int i0, int i1, int i2) {
-  return i0 + n[0] * (i1 + n[1] * i2);
-}
-
-// node on the face normal to d with index id along d and (p, r) along (ta, tb)
-__device__ __forceinline__ int face_node_rt(const int n[3], int d, int id, int p, int r) {
-  return d == 0 ? node_index(n, id, p, r) : (d == 1 ? node_index(n, p, id, r) : node_index(n, p, r, id));
-}
-
 // Lobatto table pointers of order N (node count n = N + 1)
 // (the member arrays of the kernel argument are read with constant indices and a select: a
 // runtime index makes the compiler copy the whole argument to private memory)
@@ -156,6 +140,14 @@ __global__ void __launch_bounds__(512) ic_mixed_kernel(View v, int cur, int ic, 
   }
 }
 
+// lanes of a workgroup for elements of up to nnmax nodes, npl nodes per lane (whole waves)
+__host__ __device__ constexpr int mix_lanes(int nnmax, int npl) { return ((nnmax + npl - 1) / npl + 63) / 64 * 64; }
+
+// q / n for 0 <= q < 4096 and 1 <= n <= 64, from inv_n = 1.0f / n: (q + 1/2)/n lies at least
+// 1/(2n) away from an integer, far more than the rounding error of the FP32 product (checked
+// for every q and n in that range).
+__device__ __forceinline__ int sdiv(int q, float inv_n) { return (int)(((float)q + 0.5f) * inv_n); }
+
 // ------------------------------------------------------------------ stage: faces
 // One 64-lane workgroup (a single wave) per face: the face normal to d between the owner L (its
 // +xi_d side) and R = nbr(L, +d), with L's metric Ja^d as the scaled normal.  Traces are staged
@@ -167,35 +159,28 @@ __global__ void __launch_bounds__(512) ic_mixed_kernel(View v, int cur, int ic, 
 // is interpolated and projected along it (the other side's data already lies on the mortar
 // grid and is used in place), so every loop has a trip count and branches that are uniform over
 // the wave.
-__host__ __device__ constexpr int mix_lanes(int nnmax, int npl) { return ((nnmax + npl - 1) / npl + 63) / 64 * 64; }
-
-// q / n for 0 <= q < 4096 and 1 <= n <= 64, from inv_n = 1.0f / n: (q + 1/2)/n lies at least
-// 1/(2n) away from an integer, far more than the rounding error of the FP32 product (checked
-// for every q and n in that range).
-__device__ __forceinline__ int sdiv(int q, float inv_n) { return (int)(((float)q + 0.5f) * inv_n); }
-
-__device__ __forceinline__ int stride_of(const ElemInfo& I, int d) {
-  return d == 0 ? 1 : (d == 1 ? I.n[0] : I.n[0] * I.n[1]);
-}
-
 constexpr int kFsFace = 6 * kMixNF;  // doubles per element face in Fs
 
 // XS: the extended surface fluxes (codes >= 4), compiled apart so that the others keep their
 // registers
 template <typename T, bool XS>
-__global__ void __launch_bounds__(64) mixed_face_kernel(View v, int cur) {
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(XS ? 3 : 4)))
+    mixed_face_kernel(View v, int cur) {
   constexpr bool DEV = sizeof(T) == 4;
   constexpr int NC = DEV ? 6 : 5;
+  static_assert(kMixNF <= 64, "a face grid, or a mortar matrix, fits one wave");
   const int fid = block_element(3 * v.E);
   const int e = fid / 3, d = fid - 3 * e;
   const int t = threadIdx.x;
   const double* __restrict__ Uin = v.U[cur];
   const Ref Rf = make_ref(v.rho_r, v.p_r, v.gamma);
-  int ta, tb;
-  tangential(d, ta, tb);
   const int eR = v.nbr[e * 6 + 2 * d + 1];
   const ElemInfo L = elem_info(v, e), R = elem_info(v, eR);
-  const int naL = L.n[ta], nbL = L.n[tb], naR = R.n[ta], nbR = R.n[tb];
+  // node counts along a and b, and node strides (selected by d: an array indexed by a runtime
+  // value would be kept in private memory)
+  const int nL0 = L.n[0], nL1 = L.n[1], nL2 = L.n[2], nR0 = R.n[0], nR1 = R.n[1], nR2 = R.n[2];
+  const int naL = d == 0 ? nL1 : nL0, nbL = d == 2 ? nL1 : nL2;
+  const int naR = d == 0 ? nR1 : nR0, nbR = d == 2 ? nR1 : nR2;
   const int ma = naL > naR ? naL : naR, mb = nbL > nbR ? nbL : nbR;
   const float ima = 1.0f / (float)ma;
   // the side (0 = L, 1 = R, -1 = none) with fewer nodes than the mortar along a and along b
@@ -210,52 +195,79 @@ __global__ void __launch_bounds__(64) mixed_face_kernel(View v, int cur) {
   // interpolation to the mortar and projection back, along a and along b (only the sides
   // that need them)
   __shared__ double sIa[kMixNF], sPa[kMixNF], sIb[kMixNF], sPb[kMixNF];
+  // Every operand is requested before any is stored (one lane per point or matrix entry, the
+  // indices clamped so that no load waits on a branch): the traces on their own grids (index
+  // p + n_a r) and the mortar matrices.
+  const int sLa = d == 0 ? nL0 : 1, sLb = d == 2 ? nL0 : nL0 * nL1;
+  const int sRa = d == 0 ? nR0 : 1, sRb = d == 2 ? nR0 : nR0 * nR1;
+  const int baseL = d == 0 ? nL0 - 1 : (d == 1 ? (nL1 - 1) * nL0 : (nL2 - 1) * nL0 * nL1);
+  const long offL = L.off, offR = R.off, nnL = L.nn, nnR = R.nn;
+  double tL[8], tR[5];
+  {
+    const int x = t < naL * nbL ? t : 0;
+    const int r = sdiv(x, 1.0f / (float)naL), p = x - r * naL;
+    const int q = baseL + p * sLa + r * sLb;
+#pragma unroll
+    for (int c = 0; c < 5; c++) tL[c] = Uin[offL * 5 + c * nnL + q];
+#pragma unroll
+    for (int c = 0; c < 3; c++) tL[5 + c] = v.Ja[offL * 9 + (3 * d + c) * nnL + q];
+  }
+  {
+    const int y = t < naR * nbR ? t : 0;
+    const int r = sdiv(y, 1.0f / (float)naR), p = y - r * naR;
+    const int q = p * sRa + r * sRb;
+#pragma unroll
+    for (int c = 0; c < 5; c++) tR[c] = Uin[offR * 5 + c * nnR + q];
+  }
   const double* mt = v.mtab;
+  double tIa = 0.0, tPa = 0.0, tIb = 0.0, tPb = 0.0;
   if (sa >= 0) {
     const double* src = mt + v.mort_off[na_s - 1][ma - 1];
-    for (int x = t; x < ma * na_s; x += 64) {
-      sIa[x] = src[x];
-      sPa[x] = src[ma * na_s + x];
-    }
+    const int x = t < ma * na_s ? t : 0;
+    tIa = src[x];
+    tPa = src[ma * na_s + x];
   }
   if (sb >= 0) {
     const double* src = mt + v.mort_off[nb_s - 1][mb - 1];
-    for (int x = t; x < mb * nb_s; x += 64) {
-      sIb[x] = src[x];
-      sPb[x] = src[mb * nb_s + x];
-    }
+    const int x = t < mb * nb_s ? t : 0;
+    tIb = src[x];
+    tPb = src[mb * nb_s + x];
   }
-  {  // the traces on their own grids (index p + n_a r)
-    const int sLa = stride_of(L, ta), sLb = stride_of(L, tb), sRa = stride_of(R, ta), sRb = stride_of(R, tb);
-    const int baseL = (L.n[d] - 1) * stride_of(L, d);
-    const long offL = L.off, offR = R.off, nnL = L.nn, nnR = R.nn;
-    const float iLa = 1.0f / (float)naL, iRa = 1.0f / (float)naR;
-    for (int x = t; x < naL * nbL; x += 64) {
-      const int r = sdiv(x, iLa), p = x - r * naL;
-      const int q = baseL + p * sLa + r * sLb;
+  if (t < naL * nbL) {
 #pragma unroll
-      for (int c = 0; c < 5; c++) sA[c][x] = Uin[offL * 5 + c * nnL + q];
+    for (int c = 0; c < 8; c++) sA[c][t] = tL[c];
+  }
+  if (t < naR * nbR) {
 #pragma unroll
-      for (int c = 0; c < 3; c++) sA[5 + c][x] = v.Ja[offL * 9 + (3 * d + c) * nnL + q];
-    }
-    for (int y = t; y < naR * nbR; y += 64) {
-      const int r = sdiv(y, iRa), p = y - r * naR;
-      const int q = p * sRa + r * sRb;
-#pragma unroll
-      for (int c = 0; c < 5; c++) sA[8 + c][y] = Uin[offR * 5 + c * nnR + q];
-    }
+    for (int c = 0; c < 5; c++) sA[8 + c][t] = tR[c];
+  }
+  if (sa >= 0 && t < ma * na_s) {
+    sIa[t] = tIa;
+    sPa[t] = tPa;
+  }
+  if (sb >= 0 && t < mb * nb_s) {
+    sIb[t] = tIb;
+    sPb[t] = tPb;
   }
   __syncthreads();
-  // along a: the smaller side to the mortar (index pm + ma r); its fields are L's 8 or R's 5
+  // along a: the smaller side to the mortar (index pm + ma r); its fields are L's 8 or R's 5.
+  // Each weight is read once and applied to every field (the sum over p of each field keeps its
+  // order).
   if (sa >= 0) {
     const int c0 = sa == 0 ? 0 : 8, nc = sa == 0 ? 8 : 5;
     for (int y = t; y < ma * nb_a; y += 64) {
       const int r = sdiv(y, ima), pm = y - r * ma;
-      for (int c = 0; c < nc; c++) {
-        double s = 0.0;
-        for (int p = 0; p < na_s; p++) s += sIa[pm * na_s + p] * sA[c0 + c][p + na_s * r];
-        sB[c][y] = s;
+      double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      for (int p = 0; p < na_s; p++) {
+        const double w = sIa[pm * na_s + p];
+        const int x = p + na_s * r;
+#pragma unroll
+        for (int c = 0; c < 8; c++)
+          if (c < nc) s[c] += w * sA[c0 + c][x];
       }
+#pragma unroll
+      for (int c = 0; c < 8; c++)
+        if (c < nc) sB[c][y] = s[c];
     }
   }
   __syncthreads();
@@ -265,20 +277,34 @@ __global__ void __launch_bounds__(64) mixed_face_kernel(View v, int cur) {
     const bool on = x < ma * mb;
     const int rm = sdiv(x, ima), pm = x - rm * ma;
     double a[13];
+    // L's 8 fields (rows of sB if L was interpolated along a), then R's 5
+    const double(*rowsL)[kMixNF] = sa == 0 ? sB : sA;
+    const double(*rowsR)[kMixNF] = sa == 1 ? sB : sA + 8;
+    if (nbL == mb) {
 #pragma unroll
-    for (int c = 0; c < 13; c++) {
-      const bool isL = c < 8;
-      const double* row = (isL ? sa == 0 : sa == 1) ? sB[isL ? c : c - 8] : sA[c];  // on the mortar along a
-      const int nbX = isL ? nbL : nbR;
-      double s = 0.0;
-      if (on) {
-        if (nbX == mb) {
-          s = row[pm + ma * rm];
-        } else {
-          for (int r = 0; r < nbX; r++) s += sIb[rm * nbX + r] * row[pm + ma * r];
+      for (int c = 0; c < 8; c++) a[c] = on ? rowsL[c][pm + ma * rm] : 0.0;
+    } else {
+#pragma unroll
+      for (int c = 0; c < 8; c++) a[c] = 0.0;
+      if (on)
+        for (int r = 0; r < nbL; r++) {
+          const double w = sIb[rm * nbL + r];
+#pragma unroll
+          for (int c = 0; c < 8; c++) a[c] += w * rowsL[c][pm + ma * r];
         }
-      }
-      a[c] = s;
+    }
+    if (nbR == mb) {
+#pragma unroll
+      for (int c = 0; c < 5; c++) a[8 + c] = on ? rowsR[c][pm + ma * rm] : 0.0;
+    } else {
+#pragma unroll
+      for (int c = 0; c < 5; c++) a[8 + c] = 0.0;
+      if (on)
+        for (int r = 0; r < nbR; r++) {
+          const double w = sIb[rm * nbR + r];
+#pragma unroll
+          for (int c = 0; c < 5; c++) a[8 + c] += w * rowsR[c][pm + ma * r];
+        }
     }
     __syncthreads();  // every mortar point has read its data before the flux rows overwrite sA
     if (on) {
@@ -300,38 +326,46 @@ __global__ void __launch_bounds__(64) mixed_face_kernel(View v, int cur) {
   __syncthreads();
   // L2 projection along a onto the smaller side's grid (index po + na rm), into sB
   if (sa >= 0) {
+    const float ina_s = 1.0f / (float)na_s;
     for (int y = t; y < na_s * mb; y += 64) {
-      const int rm = sdiv(y, 1.0f / (float)na_s), po = y - rm * na_s;
+      const int rm = sdiv(y, ina_s), po = y - rm * na_s;
+      double s[NC];
 #pragma unroll
-      for (int c = 0; c < NC; c++) {
-        double s = 0.0;
-        for (int pm = 0; pm < ma; pm++) s += sPa[po * ma + pm] * sA[c][pm + ma * rm];
-        sB[c][y] = s;
+      for (int c = 0; c < NC; c++) s[c] = 0.0;
+      for (int pm = 0; pm < ma; pm++) {
+        const double w = sPa[po * ma + pm];
+#pragma unroll
+        for (int c = 0; c < NC; c++) s[c] += w * sA[c][pm + ma * rm];
       }
+#pragma unroll
+      for (int c = 0; c < NC; c++) sB[c][y] = s[c];
     }
   }
   __syncthreads();
   // along b onto each side's face grid, into Fs
 #pragma unroll
   for (int side = 0; side < 2; side++) {
-    const ElemInfo& I = side ? R : L;
-    const int na = I.n[ta], nb = I.n[tb];
+    const int na = side ? naR : naL, nb = side ? nbR : nbL;
     const double(*src)[kMixNF] = sa == side ? sB : sA;  // the flux along a on this side's grid
     double* out = v.Fs + ((long)(side ? eR : e) * 6 + (side ? 2 * d : 2 * d + 1)) * kFsFace;
     const float ina = 1.0f / (float)na;
     for (int y = t; y < na * nb; y += 64) {
       const int ro = sdiv(y, ina), po = y - ro * na;
+      double s[NC];
+      if (nb == mb) {
 #pragma unroll
-      for (int c = 0; c < NC; c++) {
-        double s;
-        if (nb == mb) {
-          s = src[c][po + na * ro];
-        } else {
-          s = 0.0;
-          for (int rm = 0; rm < mb; rm++) s += sPb[ro * mb + rm] * src[c][po + na * rm];
+        for (int c = 0; c < NC; c++) s[c] = src[c][po + na * ro];
+      } else {
+#pragma unroll
+        for (int c = 0; c < NC; c++) s[c] = 0.0;
+        for (int rm = 0; rm < mb; rm++) {
+          const double w = sPb[ro * mb + rm];
+#pragma unroll
+          for (int c = 0; c < NC; c++) s[c] += w * src[c][po + na * rm];
         }
-        out[c * kMixNF + y] = s;
       }
+#pragma unroll
+      for (int c = 0; c < NC; c++) out[c * kMixNF + y] = s[c];
     }
   }
 }
