@@ -101,6 +101,8 @@ struct dg_solver {
   std::vector<hipEvent_t> ev_pool;   // events reused across regions
   size_t ev_used = 0;
   int mix_tiles = 0;                 // mixed-order stage: bit b = two nodes per lane in bucket b
+  bool mix_concurrent = false;       // mixed-order stage: buckets on the side streams of `mix`
+  dg::MixStreams mix{};
   // RK-step graphs: graph[p] advances one step starting from state buffer p with step graph_dt[p]
   bool use_graphs = true;
   hipStream_t cap_stream = nullptr;
@@ -229,7 +231,9 @@ hipError_t timed(dg_solver* s, int cls, F fn) {
 }
 
 hipError_t launch_stage_any(dg_solver* s, double dt, double a, double b, int mode) {
-  if (s->v.mixed) return dg::launch_stage_mixed(s->v, s->cur, dt, a, b, mode, s->mix_tiles, s->stream);
+  if (s->v.mixed)
+    return dg::launch_stage_mixed(s->v, s->cur, dt, a, b, mode, s->mix_tiles, s->stream,
+                                  s->mix_concurrent ? &s->mix : nullptr);
   if (s->v.gauss) return dg::launch_stage_gauss(s->v, s->cur, dt, a, b, mode, s->stream);
   return dg::launch_stage(s->v, s->cur, dt, a, b, mode, s->stream);
 }
@@ -765,6 +769,14 @@ int dg_solver_bind(dg_solver* s, void* dev_ptr, size_t bytes, void* hip_stream) 
   int rc = upload_view(s);
   if (rc) return rc;
   DG_HIP(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking), "capture stream");
+  if (s->v.mixed) {
+    for (int i = 0; i < dg::kMixSide; i++) {
+      DG_HIP(hipStreamCreateWithFlags(&s->mix.side[i], hipStreamNonBlocking), "side stream");
+      DG_HIP(hipEventCreateWithFlags(&s->mix.join[i], hipEventDisableTiming), "event");
+    }
+    DG_HIP(hipEventCreateWithFlags(&s->mix.fork, hipEventDisableTiming), "event");
+    s->mix_concurrent = true;
+  }
   hipPointerAttribute_t attr;
   if (hipPointerGetAttributes(&attr, dev_ptr) == hipSuccess && attr.device >= 0) {
     s->device = attr.device;
@@ -1229,7 +1241,8 @@ hipError_t batch_stage(dg_batch* b, const double* dts, int k, hipStream_t st) {
     const double A = kRk[b->scheme].A[k], Bk = kRk[b->scheme].B[k];
     hipError_t e;
     if (s->v.mixed) {
-      e = dg::launch_stage_mixed(s->v, s->cur, dts[i], A, Bk, dg::kModeRK, s->mix_tiles, st);
+      e = dg::launch_stage_mixed(s->v, s->cur, dts[i], A, Bk, dg::kModeRK, s->mix_tiles, st,
+                                 s->mix_concurrent ? &s->mix : nullptr);
     } else if (s->v.gauss) {
       e = dg::launch_stage_gauss(s->v, s->cur, dts[i], A, Bk, dg::kModeRK, st);
     } else {  // spectral vanishing viscosity: the solver's own stage sequence
@@ -1399,6 +1412,12 @@ void dg_solver_destroy(dg_solver* s) try {
   if (s->bound) (void)hipStreamSynchronize(s->stream);
   drop_graphs(s);
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+  for (int i = 0; i < dg::kMixSide; i++) {
+    if (s->mix.side[i]) (void)hipStreamSynchronize(s->mix.side[i]);
+    if (s->mix.side[i]) (void)hipStreamDestroy(s->mix.side[i]);
+    if (s->mix.join[i]) (void)hipEventDestroy(s->mix.join[i]);
+  }
+  if (s->mix.fork) (void)hipEventDestroy(s->mix.fork);
   for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
   delete s;
 } catch (...) {

@@ -130,8 +130,17 @@ constexpr int kMixMaxOrder = 6;
 constexpr int kMixBuckets = 6;
 hipError_t launch_geometry_mixed(const View& v, hipStream_t st);
 hipError_t launch_ic_mixed(const View& v, int cur, int ic, const double* params, hipStream_t st);
+// Side streams (default priority) and events over which the bucket launches of a stage run
+// concurrently: each bucket alone leaves the device partly idle at its end.  The fork and join
+// are events recorded on st, so the launches also form one graph under stream capture.
+constexpr int kMixSide = 3;
+struct MixStreams {
+  hipStream_t side[kMixSide];
+  hipEvent_t fork, join[kMixSide];
+};
+// ms == nullptr: the buckets one after the other on st
 hipError_t launch_stage_mixed(const View& v, int cur, double dt, double rkA, double rkB, int mode,
-                              int tiles, hipStream_t st);
+                              int tiles, hipStream_t st, const MixStreams* ms);
 hipError_t launch_stage_mixed_bucket(const View& v, int b, int npl, int cur, double dt, double rkA,
                                      double rkB, int mode, hipStream_t st);
 // the face pass alone (launch_stage_mixed runs it before the buckets)

@@ -754,14 +754,37 @@ hipError_t launch_stage_mixed_bucket(const View& v, int b, int npl, int cur, dou
 }
 
 hipError_t launch_stage_mixed(const View& v, int cur, double dt, double rkA, double rkB, int mode, int tiles,
-                              hipStream_t st) {
-  const hipError_t ef = launch_faces_mixed(v, cur, st);
-  if (ef != hipSuccess) return ef;
-  for (int b = kMixBuckets - 1; b >= 0; b--) {  // the work list starts with the largest elements
-    const hipError_t e = launch_stage_mixed_bucket(v, b, (tiles >> b) & 1 ? 2 : 1, cur, dt, rkA, rkB, mode, st);
+                              hipStream_t st, const MixStreams* ms) {
+  hipError_t e = launch_faces_mixed(v, cur, st);
+  if (e != hipSuccess) return e;
+  int bk[kMixBuckets], nb = 0;
+  for (int b = kMixBuckets - 1; b >= 0; b--)  // the work list starts with the largest elements
+    if (v.mix_cnt[b] > 0) bk[nb++] = b;
+  // the largest elements on st, up to kMixSide further buckets each on a side stream, the rest
+  // after the largest on st
+  const int ns = ms ? (nb - 1 < kMixSide ? nb - 1 : kMixSide) : 0;
+  if (ns > 0) {
+    e = hipEventRecord(ms->fork, st);
     if (e != hipSuccess) return e;
   }
-  return hipSuccess;
+  for (int i = 0; i < ns && e == hipSuccess; i++) {
+    const int b = bk[1 + i];
+    e = hipStreamWaitEvent(ms->side[i], ms->fork, 0);
+    if (e == hipSuccess)
+      e = launch_stage_mixed_bucket(v, b, (tiles >> b) & 1 ? 2 : 1, cur, dt, rkA, rkB, mode, ms->side[i]);
+    if (e == hipSuccess) e = hipEventRecord(ms->join[i], ms->side[i]);
+  }
+  for (int i = 0; i < nb && e == hipSuccess; i++) {
+    if (i >= 1 && i <= ns) continue;
+    const int b = bk[i];
+    e = launch_stage_mixed_bucket(v, b, (tiles >> b) & 1 ? 2 : 1, cur, dt, rkA, rkB, mode, st);
+  }
+  // the join, also after a failed launch: no side stream is left forked from st
+  for (int i = 0; i < ns; i++) {
+    const hipError_t ej = hipStreamWaitEvent(st, ms->join[i], 0);
+    if (e == hipSuccess) e = ej;
+  }
+  return e;
 }
 
 hipError_t launch_diagnostics_mixed(const View& v, int cur, hipStream_t st) {
