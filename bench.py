@@ -285,7 +285,8 @@ def run_mixed(steps, warmup):
         d = s.diagnostics()
         r = {"value": round(5 * s.nodes * 3 * steps / (ev_ms / 1e3) / 1e9, 3), "unit": "GDOF/s",
              "ms_per_step": round(ev_ms / steps, 4), "autotuned_tiles": f"{tiles:06b}",
-             "stage_avg_us": round(st["ms"] / st["launches"] * 1e3, 2), "state_finite": d["nonfinite"] == 0}
+             "stage_avg_us": round(st["ms"] / st["launches"] * 1e3, 2),
+             "stage_us_replay": round(ev_ms / steps / 3 * 1e3, 2), "state_finite": d["nonfinite"] == 0}
         if prec == "fp64":
             out.update({"elements": s.E, "nodes": s.nodes, "dof": 5 * s.nodes, "dtype": "f64", "steps": steps})
             out.update(r)

@@ -125,8 +125,8 @@ struct dg_solver {
 namespace {
 
 struct Plan {
-  size_t tab, nbr, X, Ja, J, invJ, U0, U1, dU, R, Fvf, part, diag, adapt, elem, work, mtab, Fs, Tr, svvtab, Fa,
-      self, total;
+  size_t tab, nbr, X, Ja, J, invJ, U0, U1, dU, R, Fvf, part, diag, adapt, elem, work, mtab, Fs, fdesc, Tr, svvtab,
+      Fa, self, total;
   size_t tab_n, mtab_n;
 };
 
@@ -174,6 +174,7 @@ Plan make_plan(const dg_solver* s) {
   p.work = mixed ? take(sizeof(int) * E) : 0;
   p.mtab = mixed ? take(sizeof(double) * p.mtab_n) : 0;
   p.Fs = mixed ? take(sizeof(double) * dg::kMixFaceDoubles * E) : 0;
+  p.fdesc = mixed ? take(sizeof(int4) * 3 * E) : 0;
   p.Tr = s->mesh.gauss ? take(sizeof(double) * E * 6 * 5 * nf) : 0;
   p.svvtab = s->phys.svv_mu > 0 ? take(sizeof(double) * n * n) : 0;
   p.Fa = s->phys.svv_mu > 0 ? take(sizeof(double) * 12 * nt) : 0;
@@ -649,6 +650,7 @@ int dg_solver_bind(dg_solver* s, void* dev_ptr, size_t bytes, void* hip_stream) 
   v.work = mixed ? reinterpret_cast<const int*>(b + p.work) : nullptr;
   v.mtab = mixed ? reinterpret_cast<const double*>(b + p.mtab) : nullptr;
   v.Fs = mixed ? reinterpret_cast<double*>(b + p.Fs) : nullptr;
+  v.fdesc = mixed ? reinterpret_cast<const int4*>(b + p.fdesc) : nullptr;
   v.gauss = s->mesh.gauss ? 1 : 0;
   v.Tr = s->mesh.gauss ? reinterpret_cast<double*>(b + p.Tr) : nullptr;
   s->svv_on = s->phys.svv_mu > 0;
@@ -722,6 +724,16 @@ int dg_solver_bind(dg_solver* s, void* dev_ptr, size_t bytes, void* hip_stream) 
       const int* n = &s->mesh.orders[3 * e];
       elem[e] = make_int4(n[0] + 1, n[1] + 1, n[2] + 1, (int)s->off[e]);
     }
+    // face table of the face pass: one entry per face 3 e + d (the face on e's +d side)
+    static_assert(dg::kMixMaxOrder + 1 < 8, "a node count takes 3 bits");
+    std::vector<int4> fdesc(3 * s->E);
+    for (long long e = 0; e < s->E; e++)
+      for (int d = 0; d < 3; d++) {
+        const int r = nbr[6 * e + 2 * d + 1];
+        const int4 L = elem[e], R = elem[r];
+        const int counts = L.x | L.y << 3 | L.z << 6 | R.x << 9 | R.y << 12 | R.z << 15;
+        fdesc[3 * e + d] = make_int4(r, counts, L.w, R.w);
+      }
     std::vector<int> work(s->E);
     std::iota(work.begin(), work.end(), 0);
     std::stable_sort(work.begin(), work.end(), [&](int x, int y) {
@@ -756,6 +768,8 @@ int dg_solver_bind(dg_solver* s, void* dev_ptr, size_t bytes, void* hip_stream) 
                           s->stream), "upload mortar matrices");
     DG_HIP(hipMemcpyAsync(b + p.elem, elem.data(), sizeof(int4) * elem.size(), hipMemcpyHostToDevice,
                           s->stream), "upload element table");
+    DG_HIP(hipMemcpyAsync(b + p.fdesc, fdesc.data(), sizeof(int4) * fdesc.size(), hipMemcpyHostToDevice,
+                          s->stream), "upload face table");
     DG_HIP(hipMemcpyAsync(b + p.work, work.data(), sizeof(int) * work.size(), hipMemcpyHostToDevice,
                           s->stream), "upload work list");
     DG_HIP(dg::launch_geometry_mixed(v, s->stream), "geometry kernel");

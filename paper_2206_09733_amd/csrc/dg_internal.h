@@ -69,6 +69,9 @@ struct View {
   int mixed;
   int nmax;
   const int4* elem;
+  // face 3 e + d of the face pass (the face on e's +d side): {R = nbr(e, +d), node counts of e
+  // then R along directions 0, 1, 2 (3 bits each, from bit 0), first node of e, first node of R}
+  const int4* fdesc;
   const int* work;
   const double* mtab;
   int tab_off[kMaxOrder + 1];

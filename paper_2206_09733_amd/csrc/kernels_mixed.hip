@@ -174,11 +174,14 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(XS ? 3 
   const int t = threadIdx.x;
   const double* __restrict__ Uin = v.U[cur];
   const Ref Rf = make_ref(v.rho_r, v.p_r, v.gamma);
-  const int eR = v.nbr[e * 6 + 2 * d + 1];
-  const ElemInfo L = elem_info(v, e), R = elem_info(v, eR);
+  // the face's table entry: R, both elements' node counts and first nodes (one load, where the
+  // neighbour and then its element entry would be two in sequence)
+  const int4 fd = v.fdesc[fid];
+  const int eR = fd.x;
+  const int nL0 = fd.y & 7, nL1 = (fd.y >> 3) & 7, nL2 = (fd.y >> 6) & 7;
+  const int nR0 = (fd.y >> 9) & 7, nR1 = (fd.y >> 12) & 7, nR2 = (fd.y >> 15) & 7;
   // node counts along a and b, and node strides (selected by d: an array indexed by a runtime
   // value would be kept in private memory)
-  const int nL0 = L.n[0], nL1 = L.n[1], nL2 = L.n[2], nR0 = R.n[0], nR1 = R.n[1], nR2 = R.n[2];
   const int naL = d == 0 ? nL1 : nL0, nbL = d == 2 ? nL1 : nL2;
   const int naR = d == 0 ? nR1 : nR0, nbR = d == 2 ? nR1 : nR2;
   const int ma = naL > naR ? naL : naR, mb = nbL > nbR ? nbL : nbR;
@@ -201,7 +204,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(XS ? 3 
   const int sLa = d == 0 ? nL0 : 1, sLb = d == 2 ? nL0 : nL0 * nL1;
   const int sRa = d == 0 ? nR0 : 1, sRb = d == 2 ? nR0 : nR0 * nR1;
   const int baseL = d == 0 ? nL0 - 1 : (d == 1 ? (nL1 - 1) * nL0 : (nL2 - 1) * nL0 * nL1);
-  const long offL = L.off, offR = R.off, nnL = L.nn, nnR = R.nn;
+  const long offL = fd.z, offR = fd.w, nnL = nL0 * nL1 * nL2, nnR = nR0 * nR1 * nR2;
   double tL[8], tR[5];
   {
     const int x = t < naL * nbL ? t : 0;
