@@ -171,7 +171,7 @@ Plan make_plan(const dg_solver* s) {
   p.diag = take(sizeof(double) * dg::kDiagSlots);
   p.adapt = take(sizeof(double) * 8);
   p.elem = mixed ? take(sizeof(int4) * E) : 0;
-  p.work = mixed ? take(sizeof(int) * E) : 0;
+  p.work = mixed ? take(sizeof(int4) * E) : 0;
   p.mtab = mixed ? take(sizeof(double) * p.mtab_n) : 0;
   p.Fs = mixed ? take(sizeof(double) * dg::kMixFaceDoubles * E) : 0;
   p.fdesc = mixed ? take(sizeof(int4) * 3 * E) : 0;
@@ -647,7 +647,7 @@ int dg_solver_bind(dg_solver* s, void* dev_ptr, size_t bytes, void* hip_stream) 
   v.adapt = reinterpret_cast<double*>(b + p.adapt);
   v.dtp = nullptr;
   v.elem = mixed ? reinterpret_cast<const int4*>(b + p.elem) : nullptr;
-  v.work = mixed ? reinterpret_cast<const int*>(b + p.work) : nullptr;
+  v.work = mixed ? reinterpret_cast<const int4*>(b + p.work) : nullptr;
   v.mtab = mixed ? reinterpret_cast<const double*>(b + p.mtab) : nullptr;
   v.Fs = mixed ? reinterpret_cast<double*>(b + p.Fs) : nullptr;
   v.fdesc = mixed ? reinterpret_cast<const int4*>(b + p.fdesc) : nullptr;
@@ -770,7 +770,13 @@ int dg_solver_bind(dg_solver* s, void* dev_ptr, size_t bytes, void* hip_stream) 
                           s->stream), "upload element table");
     DG_HIP(hipMemcpyAsync(b + p.fdesc, fdesc.data(), sizeof(int4) * fdesc.size(), hipMemcpyHostToDevice,
                           s->stream), "upload face table");
-    DG_HIP(hipMemcpyAsync(b + p.work, work.data(), sizeof(int) * work.size(), hipMemcpyHostToDevice,
+    // the work list's entries carry the element's table entry (one load in the stage kernel)
+    std::vector<int4> witem(s->E);
+    for (long long i = 0; i < s->E; i++) {
+      const int4 q = elem[work[i]];
+      witem[i] = make_int4(work[i], q.x | q.y << 3 | q.z << 6, q.w, q.x * q.y * q.z);
+    }
+    DG_HIP(hipMemcpyAsync(b + p.work, witem.data(), sizeof(int4) * witem.size(), hipMemcpyHostToDevice,
                           s->stream), "upload work list");
     DG_HIP(dg::launch_geometry_mixed(v, s->stream), "geometry kernel");
     // the host vectors must outlive the copies

@@ -72,7 +72,9 @@ struct View {
   // face 3 e + d of the face pass (the face on e's +d side): {R = nbr(e, +d), node counts of e
   // then R along directions 0, 1, 2 (3 bits each, from bit 0), first node of e, first node of R}
   const int4* fdesc;
-  const int* work;
+  // the launch order (largest elements first): {element, node counts along 0, 1, 2 (3 bits
+  // each, from bit 0), first node, node count}
+  const int4* work;
   const double* mtab;
   int tab_off[kMaxOrder + 1];
   int mort_off[kMaxOrder + 1][kMaxOrder + 1];

@@ -400,8 +400,14 @@ __global__ void __launch_bounds__(mix_lanes(NNMAX, NPL))
   constexpr int NC = DEV ? 6 : 5;       // face flux components read (FP32-bulk: + FP64 mass)
   constexpr int NFS = NC * mix_face_points(NNMAX);
   constexpr int KF = (NFS + BS - 1) / BS;  // face flux values per lane
-  const int e = v.work[wbeg + blockIdx.x];
-  const ElemInfo I = elem_info(v, e);
+  const int4 wi = v.work[wbeg + blockIdx.x];
+  const int e = wi.x;
+  ElemInfo I;
+  I.n[0] = wi.y & 7;
+  I.n[1] = (wi.y >> 3) & 7;
+  I.n[2] = (wi.y >> 6) & 7;
+  I.off = wi.z;
+  I.nn = wi.w;
   const int t = threadIdx.x;
   const long off = I.off, nn = I.nn;
   const double* __restrict__ Uin = state(v, cur);
