@@ -44,9 +44,9 @@ KERNEL_SOURCES = ["paper_2206_09733_amd/csrc/kernels.hip", "paper_2206_09733_amd
                   "paper_2206_09733_amd/csrc/dg_device.h", "paper_2206_09733_amd/csrc/dg_internal.h"]
 
 
-def profiled_traffic(kernel="dg::stage_kernel<4, double, true, 0>", shape="32768 x 128"):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary,
-    or None when the kernel sources changed since the counters were taken."""
+def _profile_rows(kernel, shape):
+    """Table rows of `kernel` (launch shape `shape`) in the committed rocprofv3 summary, or None when
+    the kernel sources changed since the counters were taken."""
     import hashlib
     import re
     try:
@@ -54,15 +54,40 @@ def profiled_traffic(kernel="dg::stage_kernel<4, double, true, 0>", shape="32768
         h = hashlib.sha256()
         for f in KERNEL_SOURCES:
             h.update(open(os.path.join(HERE, f), "rb").read())
-        m = re.search(r"Kernel sources \(sha256[^`]*`([0-9a-f]+)`", text)
-        if not m or m.group(1) != h.hexdigest()[:len(m.group(1))]:
-            return None
-        for line in text.splitlines():
-            cells = [c.strip() for c in line.strip().strip("|").split("|")]
-            if len(cells) == 8 and cells[0] == f"`{kernel}`" and cells[1] == shape:
-                return float(cells[7])
     except OSError:
         return None
+    m = re.search(r"Kernel sources \(sha256[^`]*`([0-9a-f]+)`", text)
+    if not m or m.group(1) != h.hexdigest()[:len(m.group(1))]:
+        return None
+    rows = []
+    for line in text.splitlines():
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) >= 2 and cells[0] == f"`{kernel}`" and cells[1] == shape:
+            rows.append(cells)
+    return rows
+
+
+def profiled_traffic(kernel="dg::stage_kernel<4, double, true, 0>", shape="32768 x 128"):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary,
+    or None when the kernel sources changed since the counters were taken."""
+    for cells in _profile_rows(kernel, shape) or []:
+        if len(cells) == 8:
+            return float(cells[7])
+    return None
+
+
+def profiled_limiter(kernel="dg::stage_kernel<4, double, true, 0>", shape="32768 x 128"):
+    """What binds `kernel`, from the committed rocprofv3 SQ counters (None when stale): VALU busy
+    share, mean resident waves per SIMD and the share of wave time spent waiting."""
+    for cells in _profile_rows(kernel, shape) or []:
+        if len(cells) == 12:
+            busy = float(cells[5].rstrip("%")) / 100
+            return {"valu_busy": busy, "waves_per_simd": float(cells[10]),
+                    "wait_share": float(cells[11].rstrip("%")) / 100, "vgprs": int(cells[2]),
+                    "lds_bytes": int(cells[3]),
+                    "reading": "issue/latency bound: neither the VALU nor HBM is saturated; residency "
+                               "is capped by registers and LDS, and each element's loads are only "
+                               "partly hidden behind other workgroups' compute"}
     return None
 
 
@@ -545,6 +570,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "stage_kernel<4,double,NS>",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(),
+                     "limiter": profiled_limiter(),
                      "avg_launch_us": round(avg_stage_s * 1e6, 2),
                      "avg_launch_from": f"library HIP events around each launch, a separate pass of "
                                         f"{st['launches'] // 3} steps",
