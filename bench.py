@@ -254,6 +254,20 @@ def run_svv(steps, warmup, plain_ms):
            "svv_kernel_pair_GB_s": round(algorithmic_bytes_svv(s.nodes) / pair_s / 1e9, 1),
            "state_finite": d["nonfinite"] == 0}
     s.close()
+    # the explicit LES closures on the same workload: Smagorinsky's eddy viscosity (C_s 0.17) in
+    # place of the constant one, filtered (SVV-Smagorinsky) and unfiltered (plain Smagorinsky)
+    for name, kernel, cut in (("svv_smagorinsky", "maday", 2), ("smagorinsky", "tadmor", -1)):
+        s = dgsem.Solver(**WORKLOAD, les_cs=0.17, svv_kernel=kernel, svv_cutoff=cut)
+        s.set_ic("tgv")
+        s.rk_step(dt, warmup)
+        ev_ms, _, _ = timed_steps(s, dt, steps, profile=False)
+        _, _, prof = timed_steps(s, dt, max(2, steps // 5))
+        ot = prof["other"]
+        out[name] = {"value": round(5 * s.nodes * 3 * steps / (ev_ms / 1e3) / 1e9, 3), "unit": "GDOF/s",
+                     "ms_per_step": round(ev_ms / steps, 4),
+                     "svv_kernel_pair_avg_us": round(ot["ms"] / ot["launches"] * 1e3, 2),
+                     "state_finite": s.diagnostics()["nonfinite"] == 0}
+        s.close()
     return out
 
 
@@ -315,6 +329,14 @@ def run_mixed(steps, warmup):
         if prec == "fp64":
             out.update({"elements": s.E, "nodes": s.nodes, "dof": 5 * s.nodes, "dtype": "f64", "steps": steps})
             out.update(r)
+            # the whole stage (face kernel and buckets) against its algorithmic bytes: those of the
+            # Euler stage, U in/out, dU out and (two stages in three) in, metric terms
+            b = algorithmic_bytes_stage(s.nodes, 0, False, False, 2.0 / 3.0)
+            st_s = ev_ms / steps / 3 / 1e3
+            out["roofline"] = {"bound": "hbm", "scope": "whole stage (face kernel + buckets), graph replay",
+                               "achieved": round(b / st_s / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": round(b / st_s / 1e9 / HBM_PEAK_GBS, 4),
+                               "algorithmic_bytes_per_stage": int(b)}
         else:
             r["speedup_vs_fp64"] = round(r["value"] / out["value"], 3)
             out["fp32_bulk"] = r

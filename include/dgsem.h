@@ -139,6 +139,16 @@ enum { DG_VISC_BR1 = 0, DG_VISC_BR2 = 1, DG_VISC_IP = 2 };
  * are this library's readings.  Uniform-order Gauss-Lobatto meshes, FP64. */
 enum { DG_SVV_TADMOR = 0, DG_SVV_MADAY = 1 };
 
+/* Explicit LES closure (section on turbulence models, which names Smagorinsky's model and the
+ * SVV-Smagorinsky model and leaves their definitions to its references): with les_cs > 0 the
+ * artificial viscosity of the term above becomes, node by node, svv_mu + rho (les_cs Delta)^2 |S|,
+ * Smagorinsky's eddy viscosity with |S| = sqrt(2 S:S), S = (grad v + grad v^T)/2 from the same
+ * BR1 gradient and Delta = 2 (J/(N+1)^3)^(1/3) (the cube root of the element volume per node),
+ * and the conductivity that viscosity times gamma/((gamma-1) Pr).  Filtered by the SVV kernel it
+ * is the SVV-Smagorinsky closure; with DG_SVV_TADMOR and svv_cutoff -1 (every mode kept) the
+ * plain Smagorinsky model.  The filter width and the turbulent Prandtl number (= Pr) are this
+ * library's readings.  The step-size estimates count svv_mu, not the eddy viscosity. */
+
 /* Physics of a solver.  Zero-initialise it (dg_physics p = {0}) before setting fields: every
  * option above is off or at its default when zero. */
 typedef struct {
@@ -150,6 +160,7 @@ typedef struct {
   int svv_kernel;   /* DG_SVV_TADMOR or DG_SVV_MADAY */
   int svv_cutoff;   /* cutoff mode, -1..N (-1 with DG_SVV_TADMOR: no filtering) */
   double svv_sensor; /* troubled-element threshold of the density sensor; < 0: none */
+  double les_cs;    /* Smagorinsky constant of the explicit LES closure; 0 = off */
 } dg_physics;
 
 /* Diagnostics, all FP64 with Gauss-Lobatto quadrature w_i w_j w_k J, reduced in a fixed order
@@ -184,9 +195,10 @@ int dg_mesh_info(const dg_mesh* m, long long* n_elements, long long* n_nodes, in
  * a compiled kernel (uniform orders 1..7 are compiled), for a mixed-order mesh with Re > 0
  * (mixed-order meshes are evaluated for the Euler equations, in FP64 or FP32-bulk), and for
  * DG_FP32_BULK with a volume flux other than DG_VOL_EC / DG_VOL_CENTRAL or a surface flux other
- * than DG_SURF_ROE / LLF / EC / CENTRAL.  Spectral vanishing viscosity (svv_mu > 0): DG_EINVAL
- * for an unknown kernel, a cutoff outside [-1, N], Pr <= 0 or a NaN threshold; DG_EUNSUPPORTED
- * on a mixed-order or Gauss-Legendre mesh or in FP32-bulk; svv_mu < 0 or non-finite: DG_EINVAL. */
+ * than DG_SURF_ROE / LLF / EC / CENTRAL.  Spectral vanishing viscosity (svv_mu > 0 or
+ * les_cs > 0): DG_EINVAL for an unknown kernel, a cutoff outside [-1, N], Pr <= 0 or a NaN
+ * threshold; DG_EUNSUPPORTED on a mixed-order or Gauss-Legendre mesh or in FP32-bulk; svv_mu or
+ * les_cs < 0 or non-finite: DG_EINVAL. */
 int dg_solver_create(const dg_mesh* m, const dg_physics* p, dg_solver** out);
 /* Bytes of device memory the solver needs (host-only; used for admission control). */
 int dg_solver_required_bytes(const dg_solver* s, size_t* bytes);

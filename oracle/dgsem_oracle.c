@@ -48,6 +48,7 @@
 #ifdef ORC_LONG_DOUBLE
 typedef long double real;
 #define RSQRT sqrtl
+#define RCBRT cbrtl
 #define RLOG logl
 #define RSIN sinl
 #define RCOS cosl
@@ -57,6 +58,7 @@ typedef long double real;
 #else
 typedef double real;
 #define RSQRT sqrt
+#define RCBRT cbrt
 #define RLOG log
 #define RSIN sin
 #define RCOS cos
@@ -334,6 +336,7 @@ struct orc_solver {
   int svv;         /* spectral vanishing viscosity on (section 8c) */
   int svv_kernel, svv_cut;
   real svv_mu, svv_kappa, svv_sensor;
+  real les_cs;     /* Smagorinsky constant of the explicit LES closure; 0 = off */
   real *Gw, *Fa;   /* entropy-variable gradients (15 per node), filtered fluxes (15 per node) */
   real *X, *Ja, *J; /* coordinates, metric terms, Jacobian */
   real *U, *dU, *G, *R;
@@ -1444,6 +1447,16 @@ static void element_residual_gauss(const orc_solver* s, const real* U, const rea
  *     Residual: as the viscous terms of section 8, J R_a = sum_d D_d F~^d
  *     + (1/w_N)(F~* - F~) at xi_d = +1 - (1/w_0)(F~* - F~) at -1, F~^d = Ja^d . F_a^F and F~* the
  *     average of the two sides' filtered fluxes along the owner's Ja^d.
+ *     Explicit LES closure (section on turbulence models: Smagorinsky, and SVV-Smagorinsky, whose
+ *     definitions the paper leaves to its references).  Reading: the artificial viscosity of the
+ *     term above becomes, node by node, mu_a + rho (C_s Delta)^2 |S| with Smagorinsky's
+ *     |S| = sqrt(2 S:S), S = (grad v + grad v^T)/2 from the same BR1 gradient
+ *     (grad v_k = theta (grad w_{k+1} + v_k grad w_5)), the filter width Delta = 2 (J/n)^(1/3)
+ *     (the cube root of the element volume per node, n the element's node count), and the
+ *     conductivity that viscosity times gamma/((gamma-1) Pr).  Filtered by the SVV kernel this is
+ *     the SVV-Smagorinsky closure; with Tadmor's kernel and cutoff -1 (every mode kept) it is the
+ *     plain Smagorinsky model.  Since D scales with the viscosity node by node, sqrt(J D) and
+ *     D^{1/2} carry the local value and the factorisation above is unchanged.
  * ---------------------------------------------------------------------------------------- */
 static real svv_sigma(int N, int kernel, int M, int k) {
   if (k <= M) return 0;
@@ -1531,6 +1544,34 @@ static void svv_filter_field(const int N[3], int kernel, int M, const real* f, r
   free(c);
 }
 
+/* Smagorinsky's eddy viscosity rho (cs Delta)^2 |S| at one node (explicit LES closure): state u,
+ * entropy-variable
+ * gradient G[3c + x], Jacobian J, n nodes in the element */
+static real les_viscosity(const real u[5], const real G[15], real gamma, real cs, real J, int n) {
+  prim_t q = prim(u, gamma);
+  real th = q.p / q.rho;
+  real dv[3][3];  /* d v_k / d x_j */
+  for (int k = 0; k < 3; k++)
+    for (int j = 0; j < 3; j++) dv[k][j] = th * (G[3 * (k + 1) + j] + q.v[k] * G[3 * 4 + j]);
+  real ss = 0;
+  for (int k = 0; k < 3; k++)
+    for (int j = 0; j < 3; j++) {
+      real sk = (dv[k][j] + dv[j][k]) / 2;
+      ss += sk * sk;
+    }
+  real delta = 2 * RCBRT(J / n);
+  return q.rho * (cs * delta) * (cs * delta) * RSQRT(2 * ss);
+}
+
+/* the factors of the artificial flux at one node: viscosity mu_a plus (cs > 0) Smagorinsky's eddy
+ * viscosity, conductivity that viscosity times gamma/((gamma-1) Pr) */
+static void svv_node_factors(const real u[5], const real G[15], real gamma, real Pr, real mu_a, real cs, real J,
+                             int n, real L[8][15], real D[8]) {
+  real mu = mu_a;
+  if (cs > 0) mu += les_viscosity(u, G, gamma, cs, J, n);
+  svv_factors(u, gamma, mu, mu * gamma / ((gamma - 1) * Pr), L, D);
+}
+
 /* the sensor s_rho of element e */
 static real svv_sensor(const orc_solver* s, const real* U, int e) {
   const int* N = s->N[e];
@@ -1569,8 +1610,8 @@ static real svv_element_flux(const orc_solver* s, const real* U, const real* Gw,
     real u[5], G[15];
     load5(s, U, e, q, u);
     for (int t = 0; t < 15; t++) G[t] = Gw[s->off[e] * 15 + (long)t * nn + q];
-    svv_factors(u, s->gamma, s->svv_mu, s->svv_kappa, Ln[q], &Dn[8 * q]);
     real Jq = s->J[s->off[e] + q];
+    svv_node_factors(u, G, s->gamma, s->Pr, s->svv_mu, s->les_cs, Jq, nn, Ln[q], &Dn[8 * q]);
     for (int m = 0; m < 8; m++) {
       real lg = 0;
       for (int t = 0; t < 15; t++) lg += Ln[q][m][t] * G[t];
@@ -2059,7 +2100,7 @@ int orc_viscous_flux(const double* U, const double* grad, double gamma, double P
  * ---------------------------------------------------------------------------------------- */
 int orc_set_svv(orc_solver* s, double mu_a, int kernel, int cutoff, double sensor_threshold) {
   if (!s || s->gauss || !(mu_a >= 0) || kernel < ORC_SVV_TADMOR || kernel > ORC_SVV_MADAY) return -1;
-  if (mu_a == 0) { s->svv = 0; return 0; }
+  if (mu_a == 0 && !(s->les_cs > 0)) { s->svv = 0; return 0; }
   for (int e = 0; e < s->E; e++)
     for (int d = 0; d < 3; d++) {
       if (cutoff < -1 || cutoff > s->N[e][d]) return -1;
@@ -2076,6 +2117,25 @@ int orc_set_svv(orc_solver* s, double mu_a, int kernel, int cutoff, double senso
   s->svv_kernel = kernel;
   s->svv_cut = cutoff;
   s->svv_sensor = sensor_threshold;
+  return 0;
+}
+
+/* the explicit LES closure with Smagorinsky constant cs (0 = off); call before orc_set_svv,
+ * which then sets the filter (and may take mu_a = 0) */
+int orc_set_les(orc_solver* s, double cs) {
+  if (!s || s->gauss || !(cs >= 0) || !isfinite(cs)) return -1;
+  s->les_cs = cs;
+  return 0;
+}
+
+/* Smagorinsky's eddy viscosity of the explicit LES closure at one state: U the conservative state, Gw[3c+x] the
+ * entropy-variable gradient, J the Jacobian and n the element's node count */
+int orc_les_viscosity(const double* U, const double* Gw, double gamma, double cs, double J, int n, double* mu) {
+  if (!U || !Gw || !mu || n < 1 || !(J > 0)) return -1;
+  real u[5], G[15];
+  to_real(U, u, 5);
+  to_real(Gw, G, 15);
+  *mu = (double)les_viscosity(u, G, gamma, cs, J, n);
   return 0;
 }
 
@@ -2111,13 +2171,15 @@ int orc_svv_filter(int N, int kernel, int cutoff, const double* f, double* out) 
   return 0;
 }
 
-/* the unfiltered flux L^T D L G at one state, G[3c+x] = d w_c / d x_x; F[5x+v] */
-int orc_svv_flux(const double* U, const double* Gw, double gamma, double Pr, double mu_a, double* F) {
+/* the unfiltered flux L^T D L G at one state, G[3c+x] = d w_c / d x_x; F[5x+v]; with cs > 0 the
+ * viscosity gains Smagorinsky's at Jacobian J in an element of n nodes */
+int orc_les_flux(const double* U, const double* Gw, double gamma, double Pr, double mu_a, double cs, double J, int n,
+                 double* F) {
+  if (n < 1 || !(J > 0)) return -1;
   real u[5], G[15], L[8][15], D[8];
   to_real(U, u, 5);
   to_real(Gw, G, 15);
-  real mu = mu_a, kappa = mu * (real)gamma / (((real)gamma - 1) * (real)Pr);
-  svv_factors(u, gamma, mu, kappa, L, D);
+  svv_node_factors(u, G, gamma, Pr, mu_a, cs, J, n, L, D);
   for (int x = 0; x < 3; x++)
     for (int c = 0; c < 5; c++) {
       real acc = 0;
@@ -2129,4 +2191,8 @@ int orc_svv_flux(const double* U, const double* Gw, double gamma, double Pr, dou
       F[5 * x + c] = (double)acc;
     }
   return 0;
+}
+
+int orc_svv_flux(const double* U, const double* Gw, double gamma, double Pr, double mu_a, double* F) {
+  return orc_les_flux(U, Gw, gamma, Pr, mu_a, 0.0, 1.0, 1, F);
 }

@@ -176,8 +176,9 @@ Plan make_plan(const dg_solver* s) {
   p.Fs = mixed ? take(sizeof(double) * dg::kMixFaceDoubles * E) : 0;
   p.fdesc = mixed ? take(sizeof(int4) * 3 * E) : 0;
   p.Tr = s->mesh.gauss ? take(sizeof(double) * E * 6 * 5 * nf) : 0;
-  p.svvtab = s->phys.svv_mu > 0 ? take(sizeof(double) * n * n) : 0;
-  p.Fa = s->phys.svv_mu > 0 ? take(sizeof(double) * 12 * nt) : 0;
+  const bool svv = s->phys.svv_mu > 0 || s->phys.les_cs > 0;
+  p.svvtab = svv ? take(sizeof(double) * n * n) : 0;
+  p.Fa = svv ? take(sizeof(double) * 12 * nt) : 0;
   p.self = take(sizeof(dg::View));  // device copy of the View, read by batched launches
   p.total = off;
   return p;
@@ -565,7 +566,8 @@ int dg_solver_create(const dg_mesh* m, const dg_physics* p, dg_solver** out) try
     return fail(DG_EUNSUPPORTED, "Gauss-Legendre nodes: FP64, volume flux DG_VOL_CENTRAL (the plain weak "
                                  "form), BR1 viscous terms");
   if (!(p->svv_mu >= 0) || !std::isfinite(p->svv_mu)) return fail(DG_EINVAL, "svv_mu must be >= 0");
-  if (p->svv_mu > 0) {
+  if (!(p->les_cs >= 0) || !std::isfinite(p->les_cs)) return fail(DG_EINVAL, "les_cs must be >= 0");
+  if (p->svv_mu > 0 || p->les_cs > 0) {
     if (p->svv_kernel != DG_SVV_TADMOR && p->svv_kernel != DG_SVV_MADAY) return fail(DG_EINVAL, "unknown SVV kernel");
     if (p->svv_cutoff < -1 || p->svv_cutoff > m->N) return fail(DG_EINVAL, "SVV cutoff outside [-1, N]");
     if (!(p->Pr > 0)) return fail(DG_EINVAL, "Pr must be positive");
@@ -653,10 +655,12 @@ int dg_solver_bind(dg_solver* s, void* dev_ptr, size_t bytes, void* hip_stream) 
   v.fdesc = mixed ? reinterpret_cast<const int4*>(b + p.fdesc) : nullptr;
   v.gauss = s->mesh.gauss ? 1 : 0;
   v.Tr = s->mesh.gauss ? reinterpret_cast<double*>(b + p.Tr) : nullptr;
-  s->svv_on = s->phys.svv_mu > 0;
+  s->svv_on = s->phys.svv_mu > 0 || s->phys.les_cs > 0;
   if (s->svv_on) {
     s->svv.mu = s->phys.svv_mu;
-    s->svv.kappa = s->phys.svv_mu * s->phys.gamma / ((s->phys.gamma - 1.0) * s->phys.Pr);
+    s->svv.kfac = s->phys.gamma / ((s->phys.gamma - 1.0) * s->phys.Pr);
+    s->svv.kappa = s->phys.svv_mu * s->svv.kfac;
+    s->svv.cs2 = s->phys.les_cs * s->phys.les_cs;
     s->svv.sensor = s->phys.svv_sensor;
     s->svv.filt = reinterpret_cast<const double*>(b + p.svvtab);
     s->svv.Fa = reinterpret_cast<double*>(b + p.Fa);

@@ -16,6 +16,10 @@
 // Elements whose density sensor s = sum w_i w_j w_k J |grad_xi rho|^2 exceeds the threshold
 // take the unfiltered flux.  The residual of the term is the divergence of the contravariant
 // flux with BR1 face terms (the average of the two sides' fluxes along the owner's Ja^d).
+// Explicit LES closure (turbulence models: Smagorinsky, SVV-Smagorinsky): the viscosity gains
+// Smagorinsky's rho (C_s Delta)^2 |S| node by node, |S| = sqrt(2 S:S) with S the symmetric part
+// of grad v = theta Z and Delta = 2 (J/(N+1)^3)^(1/3); mu and kappa enter only through sqrt(mu)
+// and sqrt(kappa) at the node itself, so the factorisation holds with the local values.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -51,7 +55,8 @@ __global__ void __launch_bounds__(nthreads_for(N)) svv_flux_kernel(View v, int c
   if (t < n) sw[t] = v.tab[n + t];
   const long base = (long)e * nn;
   const double g1 = v.gamma - 1.0;
-  double vel[3] = {0, 0, 0}, th = 1.0;
+  double vel[3] = {0, 0, 0}, th = 1.0, rho = 1.0;
+  double mu = a.mu, kappa = a.kappa;  // the node's viscosity and conductivity
   if (act) {
     double u[5];
 #pragma unroll
@@ -62,6 +67,7 @@ __global__ void __launch_bounds__(nthreads_for(N)) svv_flux_kernel(View v, int c
     const double p = g1 * (u[4] - 0.5 * u[0] * (vel[0] * vel[0] + vel[1] * vel[1] + vel[2] * vel[2]));
     const double b = u[0] / p;  // 1 / theta
     th = p * ir;
+    rho = u[0];
     sW[0][t] = u[0];
 #pragma unroll
     for (int c = 0; c < 3; c++) sW[1 + c][t] = b * vel[c];
@@ -149,7 +155,20 @@ __global__ void __launch_bounds__(nthreads_for(N)) svv_flux_kernel(View v, int c
 #pragma unroll
       for (int j = 0; j < 3; j++) Z[k][j] = G[k][j] + vel[k] * G[3][j];
     const double tr3 = (Z[0][0] + Z[1][1] + Z[2][2]) * (1.0 / 3.0);
-    const double sv = sqrt(J * a.mu * th), sq = th * sqrt(J * a.kappa);
+    if (a.cs2 > 0.0) {  // explicit LES: Smagorinsky's eddy viscosity at this node
+      double ss = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; k++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+          const double sk = 0.5 * th * (Z[k][j] + Z[j][k]);
+          ss += sk * sk;
+        }
+      const double delta = 2.0 * cbrt(J * (1.0 / nn));
+      mu = a.mu + rho * a.cs2 * delta * delta * sqrt(2.0 * ss);
+      kappa = mu * a.kfac;
+    }
+    const double sv = sqrt(J * mu * th), sq = th * sqrt(J * kappa);
     y[0] = sv * (Z[0][0] - tr3);
     y[1] = sv * (Z[1][1] - tr3);
     y[2] = sv * (Z[2][2] - tr3);
@@ -189,7 +208,7 @@ __global__ void __launch_bounds__(nthreads_for(N)) svv_flux_kernel(View v, int c
     for (int c = 0; c < 9; c++) y[c] -= r[c];
   }
   if (!act) return;
-  const double ks = 2.0 * sqrt(a.mu * th / J), kq = th * sqrt(a.kappa / J);
+  const double ks = 2.0 * sqrt(mu * th / J), kq = th * sqrt(kappa / J);
   const double tau[3][3] = {{ks * y[0], ks * y[3], ks * y[4]},
                             {ks * y[3], ks * y[1], ks * y[5]},
                             {ks * y[4], ks * y[5], ks * y[2]}};

@@ -11,6 +11,8 @@ namespace dg {
 
 struct SvvArgs {
   double mu, kappa;     // artificial viscosity and conductivity mu gamma / ((gamma-1) Pr)
+  double cs2;           // explicit LES: the Smagorinsky constant squared (0: constant viscosity)
+  double kfac;          // gamma / ((gamma-1) Pr): conductivity per unit viscosity
   double sensor;        // density-sensor threshold; < 0: every element filtered
   const double* filt;   // (I - Phi) of one direction, (N+1) x (N+1) row-major: Phi = V diag(s) V^-1
   double* Fa;           // filtered contravariant flux Ja^d . F [E][12][nn]: index 4 d + c, d the

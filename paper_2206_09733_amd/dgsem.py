@@ -39,7 +39,7 @@ class Physics(_c.Structure):
                 ("Re", _c.c_double), ("vol_flux", _c.c_int), ("surf_flux", _c.c_int),
                 ("precision", _c.c_int), ("visc_flux", _c.c_int), ("visc_eta", _c.c_double),
                 ("svv_mu", _c.c_double), ("svv_kernel", _c.c_int), ("svv_cutoff", _c.c_int),
-                ("svv_sensor", _c.c_double)]
+                ("svv_sensor", _c.c_double), ("les_cs", _c.c_double)]
 
 
 class Diag(_c.Structure):
@@ -156,13 +156,14 @@ def box_desc(ex, ey, ez, lo, hi, deform, amp, N, orders=None, nodes="lobatto"):
 
 
 def physics(gamma=1.4, Pr=0.71, Ma=0.1, Re=0.0, vol="ec", surf="roe", precision="fp64", visc="br1",
-            visc_eta=0.0, svv_mu=0.0, svv_kernel="maday", svv_cutoff=0, svv_sensor=-1.0):
+            visc_eta=0.0, svv_mu=0.0, svv_kernel="maday", svv_cutoff=0, svv_sensor=-1.0, les_cs=0.0):
     p = Physics()
     p.gamma, p.Pr, p.Ma, p.Re = gamma, Pr, Ma, Re
     p.vol_flux, p.surf_flux, p.precision = VOL[vol], SURF[surf], PRECISION[precision]
     p.visc_flux, p.visc_eta = VISC[visc], float(visc_eta)
     p.svv_mu, p.svv_kernel = float(svv_mu), SVV_KERNEL[svv_kernel]
     p.svv_cutoff, p.svv_sensor = int(svv_cutoff), float(svv_sensor)
+    p.les_cs = float(les_cs)
     return p
 
 
@@ -172,13 +173,16 @@ class Solver:
     `orders` (optional, shape (E, 3) or 3 E integers) gives every element its own order per
     direction; otherwise all elements take order N.  `svv_mu` > 0 adds spectral vanishing
     viscosity (kernel "maday" or "tadmor", cutoff mode `svv_cutoff`, default N // 2, and the
-    troubled-element threshold `svv_sensor` of the density sensor, < 0 for none).
+    troubled-element threshold `svv_sensor` of the density sensor, < 0 for none).  `les_cs` > 0
+    adds Smagorinsky's eddy viscosity with that constant to the artificial viscosity, node by node
+    (filtered by the SVV kernel: SVV-Smagorinsky; kernel "tadmor" with cutoff -1 keeps every mode:
+    plain Smagorinsky).
     """
 
     def __init__(self, ex, ey=None, ez=None, lo=(0.0, 0.0, 0.0), hi=None, deform=False, amp=0.05,
                  N=3, gamma=1.4, Pr=0.71, Ma=0.1, Re=0.0, vol="ec", surf="roe", precision="fp64",
                  device="cuda", bind=True, orders=None, visc="br1", visc_eta=0.0, nodes="lobatto",
-                 svv_mu=0.0, svv_kernel="maday", svv_cutoff=None, svv_sensor=-1.0):
+                 svv_mu=0.0, svv_kernel="maday", svv_cutoff=None, svv_sensor=-1.0, les_cs=0.0):
         L = lib()
         ey = ex if ey is None else ey
         ez = ex if ez is None else ez
@@ -198,7 +202,7 @@ class Solver:
             h = _c.c_void_p()
             cut = N // 2 if svv_cutoff is None else svv_cutoff
             ph = physics(gamma, Pr, Ma, Re, vol, surf, precision, visc, visc_eta, svv_mu, svv_kernel, cut,
-                         svv_sensor)
+                         svv_sensor, les_cs)
             check(L.dg_solver_create(mesh, _c.byref(ph), _c.byref(h)))
             self.h = h
         finally:

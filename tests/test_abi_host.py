@@ -213,10 +213,25 @@ def test_spectral_vanishing_viscosity_limits(dg):
         p = dg.physics(svv_mu=0.1, svv_kernel=kernel, svv_cutoff=cut, Re=100.0)
         assert L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)) == dg.DG_OK
         L.dg_solver_destroy(s)
+    # the explicit LES closure alone switches the term on (same buffers, same checks)
+    p = dg.physics(les_cs=0.17, svv_cutoff=1)
+    dg.check(L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)))
+    nb = ctypes.c_size_t()
+    dg.check(L.dg_solver_required_bytes(s, ctypes.byref(nb)))
+    assert nb.value == sizes[1]
+    L.dg_solver_destroy(s)
+    for bad in (dict(les_cs=-0.1), dict(les_cs=float("nan")), dict(les_cs=float("inf")),
+                dict(les_cs=0.1, svv_cutoff=4)):
+        p = dg.physics(**bad)
+        assert L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)) == dg.DG_EINVAL, bad
+    p = dg.physics(les_cs=0.1, precision="fp32_bulk")
+    assert L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)) == dg.DG_EUNSUPPORTED
     L.dg_mesh_destroy(m)
     for kw in (dict(orders=[2, 3, 3] * 8), dict(nodes="gauss")):
         d, _k = dg.box_desc(2, 2, 2, (0, 0, 0), (1, 1, 1), False, 0.0, 3, **kw)
         dg.check(L.dg_mesh_create_box(ctypes.byref(d), ctypes.byref(m)))
         p = dg.physics(svv_mu=0.1, vol="central", svv_cutoff=1)
+        assert L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)) == dg.DG_EUNSUPPORTED, kw
+        p = dg.physics(les_cs=0.1, vol="central", svv_cutoff=1)
         assert L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)) == dg.DG_EUNSUPPORTED, kw
         L.dg_mesh_destroy(m)
