@@ -57,8 +57,12 @@ enum { DG_DEFORM_NONE = 0, DG_DEFORM_SINSIN = 1 };
 /* quadrature / collocation points (section "Spatial discretisation" allows both): Gauss-Lobatto
  * (every split form, every viscous flux, mixed orders, FP32-bulk), or Gauss-Legendre (more
  * accurate; no boundary nodes, so the plain weak form with face traces interpolated to the
- * element boundaries: undeformed uniform-order boxes, FP64, volume flux DG_VOL_CENTRAL, any
- * surface flux, BR1 viscous terms) */
+ * element boundaries: uniform-order boxes, undeformed or deformed, FP64, volume flux
+ * DG_VOL_CENTRAL, any surface flux, BR1 viscous terms).  On Gauss-Legendre points the map and
+ * its metric terms are those of the Lobatto grid of the same order (isoparametric there, curl
+ * form there) evaluated at the Gauss points, and each face takes the metric of the element on
+ * its -xi side interpolated to the face: a uniform state stays steady on curvilinear meshes.
+ * The paper leaves these geometry rules to its references; this is the library's reading. */
 enum { DG_NODES_LOBATTO = 0, DG_NODES_GAUSS = 1 };
 /* volume two-point flux (the list of split forms of section "Energy/Entropy stable versions"):
  * Chandrashekar's entropy-conserving, kinetic-energy-preserving flux; the central average;

@@ -61,8 +61,8 @@ def _lib(precision="fp64"):
         L.orc_gl.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp]
         L.orc_create_gauss.restype = ctypes.c_void_p
         L.orc_create_gauss.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int,
-                                       ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                       ctypes.c_int]
+                                       ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_int]
         L.orc_mortar_matrices.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp]
         L.orc_euler_flux.argtypes = [_dp, _dp, ctypes.c_double, _dp]
         L.orc_two_point_ec.argtypes = [_dp, _dp, _dp, ctypes.c_double, _dp]
@@ -266,11 +266,11 @@ class OracleSolver:
             self._orders = np.ascontiguousarray(orders, dtype=np.int32).reshape(-1)
             assert self._orders.size == 3 * ex * ey * ez
             optr = self._orders.ctypes.data_as(_ip)
-        if nodes == "gauss":  # undeformed, uniform order, plain weak form
-            if deform or orders is not None or vol != "central":
-                raise ValueError("Gauss-Legendre nodes: undeformed uniform-order boxes, central volume form")
-            self.h = self.L.orc_create_gauss(ex, ey, ez, _ptr(lo), _ptr(hi), int(N), gamma, Pr, Ma, Re,
-                                             SURF[surf])
+        if nodes == "gauss":  # uniform order, plain weak form
+            if orders is not None or vol != "central":
+                raise ValueError("Gauss-Legendre nodes: uniform-order boxes, central volume form")
+            self.h = self.L.orc_create_gauss(ex, ey, ez, _ptr(lo), _ptr(hi), int(bool(deform)), amp, int(N), gamma,
+                                             Pr, Ma, Re, SURF[surf])
         else:
             self.h = self.L.orc_create(ex, ey, ez, _ptr(lo), _ptr(hi), int(bool(deform)), amp, int(N),
                                        optr, gamma, Pr, Ma, Re, VOL[vol], SURF[surf])

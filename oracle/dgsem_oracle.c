@@ -382,94 +382,162 @@ static void displacement(const orc_solver* s, const real xu[3], real dx[3]) {
   }
 }
 
-/* derivative of a nodal field f along reference direction d at node (i,j,k) of element e */
-static real dref(const orc_solver* s, int e, const real* f, int d, const int ii[3]) {
+/* derivative along reference direction d, at node ii of element e, of a nodal field f on the
+ * nodes of table set T (the element's orders) */
+static real dref_t(const orc_solver* s, const gll_t* T, int e, const real* f, int d, const int ii[3]) {
   int Nd = s->N[e][d];
   real acc = 0;
   int jj[3] = {ii[0], ii[1], ii[2]};
   for (int m = 0; m <= Nd; m++) {
     jj[d] = m;
-    acc += s->T[Nd].D[ii[d]][m] * f[node_of(s, e, jj)];
+    acc += T[Nd].D[ii[d]][m] * f[node_of(s, e, jj)];
   }
   return acc;
+}
+
+static real dref(const orc_solver* s, int e, const real* f, int d, const int ii[3]) {
+  return dref_t(s, s->T, e, f, d, ii);
+}
+
+/* Geometry of element e on the nodes of table set T: coordinates X[3][nn], metric terms
+ * Ja[9][nn] in the curl form and the map's derivatives dX[9][nn] (dX[3m+d] = d x_m / d xi_d). */
+static void element_geometry(const orc_solver* s, int e, const gll_t* T, real* X, real* Ja, real* dX) {
+  int a = e % s->ex, b = (e / s->ex) % s->ey, c = e / (s->ex * s->ey);
+  int cell[3] = {a, b, c};
+  const int* N = s->N[e];
+  int nn = nn_of(s, e);
+  /* The map is x = corner + Xl, Xl = (1+xi)/2 h + displacement.  The metric terms depend
+   * only on derivatives of x and on x up to a constant per element (a constant c added to
+   * X_l in the curl form adds c grad X_m, whose discrete curl vanishes because the
+   * tensor-product derivative matrices commute), so they are formed from Xl, whose size is
+   * the element's, not the box's. */
+  real* Xl = (real*)malloc(sizeof(real) * 3 * nn);
+  for (int k = 0; k <= N[2]; k++)
+    for (int j = 0; j <= N[1]; j++)
+      for (int i = 0; i <= N[0]; i++) {
+        int ii[3] = {i, j, k};
+        real xu[3], loc[3], dx[3];
+        for (int d = 0; d < 3; d++) {
+          loc[d] = (1 + T[N[d]].xi[ii[d]]) / 2 * s->h[d];
+          xu[d] = s->lo[d] + cell[d] * s->h[d] + loc[d];
+        }
+        displacement(s, xu, dx);
+        long q = node_of(s, e, ii);
+        for (int d = 0; d < 3; d++) {
+          X[(long)d * nn + q] = xu[d] + dx[d];
+          Xl[(long)d * nn + q] = loc[d] + dx[d];
+        }
+      }
+  real* A = (real*)malloc(sizeof(real) * 3 * nn);
+  for (int k = 0; k <= N[2]; k++)
+    for (int j = 0; j <= N[1]; j++)
+      for (int i = 0; i <= N[0]; i++) {
+        int ii[3] = {i, j, k};
+        long q = node_of(s, e, ii);
+        for (int m = 0; m < 3; m++)
+          for (int d = 0; d < 3; d++) dX[(3 * m + d) * nn + q] = dref_t(s, T, e, Xl + (long)m * nn, d, ii);
+      }
+  /* curl form: Ja^i_n = -[curl_xi (X_l grad_xi X_m)]_i with (n,m,l) cyclic */
+  for (int n = 0; n < 3; n++) {
+    int m = (n + 1) % 3, l = (n + 2) % 3;
+    for (int q = 0; q < nn; q++)
+      for (int d = 0; d < 3; d++) A[d * nn + q] = Xl[(long)l * nn + q] * dX[(3 * m + d) * nn + q];
+    for (int k = 0; k <= N[2]; k++)
+      for (int j = 0; j <= N[1]; j++)
+        for (int i = 0; i <= N[0]; i++) {
+          int ii[3] = {i, j, k};
+          long q = node_of(s, e, ii);
+          /* curl components: (d1 A2 - d2 A1, d2 A0 - d0 A2, d0 A1 - d1 A0) */
+          real c0 = dref_t(s, T, e, A + 2 * nn, 1, ii) - dref_t(s, T, e, A + 1 * nn, 2, ii);
+          real c1 = dref_t(s, T, e, A + 0 * nn, 2, ii) - dref_t(s, T, e, A + 2 * nn, 0, ii);
+          real c2 = dref_t(s, T, e, A + 1 * nn, 0, ii) - dref_t(s, T, e, A + 0 * nn, 1, ii);
+          Ja[(long)(3 * 0 + n) * nn + q] = -c0;
+          Ja[(long)(3 * 1 + n) * nn + q] = -c1;
+          Ja[(long)(3 * 2 + n) * nn + q] = -c2;
+        }
+  }
+  free(A);
+  free(Xl);
+}
+
+/* J = a_1 . (a_2 x a_3), a_d = dX/dxi_d, at each of the nn nodes */
+static void jacobian(const real* dX, int nn, real* J) {
+  for (int q = 0; q < nn; q++) {
+    real a1[3], a2[3], a3[3];
+    for (int m = 0; m < 3; m++) {
+      a1[m] = dX[(3 * m + 0) * nn + q];
+      a2[m] = dX[(3 * m + 1) * nn + q];
+      a3[m] = dX[(3 * m + 2) * nn + q];
+    }
+    J[q] = a1[0] * (a2[1] * a3[2] - a2[2] * a3[1]) + a1[1] * (a2[2] * a3[0] - a2[0] * a3[2]) +
+           a1[2] * (a2[0] * a3[1] - a2[1] * a3[0]);
+  }
+}
+
+/* Gauss-Legendre solvers: the map and its metric terms are those of the Lobatto grid of the
+ * same order (isoparametric there, curl form there), evaluated as the polynomials they are at
+ * the Gauss points.  The curl form makes sum_d d(Ja^d)/dxi_d vanish at the (N+1)^3 Lobatto
+ * nodes, hence identically for these polynomials, hence at any points; and the normal
+ * component on a face depends only on the Lobatto nodes of that face, which both elements
+ * share, so the face metric the two sides interpolate is the same (free stream). */
+static void element_geometry_gauss(const orc_solver* s, int e, real* X, real* Ja, real* J) {
+  const int N = s->N[e][0], n = N + 1, nn = n * n * n;
+  real* Xg = (real*)malloc(sizeof(real) * 21 * nn);  /* X, Ja, dX on the Lobatto nodes */
+  real* tmp = (real*)malloc(sizeof(real) * 2 * nn);
+  real* out = (real*)malloc(sizeof(real) * 21 * nn);
+  element_geometry(s, e, GLL, Xg, Xg + 3 * nn, Xg + 12 * nn);
+  /* I[g][l]: the Lobatto basis function l at Gauss point g */
+  real I[ORC_NMAX + 1][ORC_NMAX + 1];
+  for (int g = 0; g < n; g++)
+    for (int l = 0; l < n; l++) I[g][l] = (real)lagrange(N, l, GL[N].xl[g]);
+  for (int f = 0; f < 21; f++) {
+    const real* src = Xg + (long)f * nn;
+    real *t1 = tmp, *t2 = tmp + nn;
+    for (int k = 0; k < n; k++)  /* along xi_0, then xi_1, then xi_2 */
+      for (int j = 0; j < n; j++)
+        for (int g = 0; g < n; g++) {
+          real acc = 0;
+          for (int l = 0; l < n; l++) acc += I[g][l] * src[nidx(n, n, l, j, k)];
+          t1[nidx(n, n, g, j, k)] = acc;
+        }
+    for (int k = 0; k < n; k++)
+      for (int g = 0; g < n; g++)
+        for (int i = 0; i < n; i++) {
+          real acc = 0;
+          for (int l = 0; l < n; l++) acc += I[g][l] * t1[nidx(n, n, i, l, k)];
+          t2[nidx(n, n, i, g, k)] = acc;
+        }
+    for (int g = 0; g < n; g++)
+      for (int j = 0; j < n; j++)
+        for (int i = 0; i < n; i++) {
+          real acc = 0;
+          for (int l = 0; l < n; l++) acc += I[g][l] * t2[nidx(n, n, i, j, l)];
+          out[(long)f * nn + nidx(n, n, i, j, g)] = acc;
+        }
+  }
+  memcpy(X, out, sizeof(real) * 3 * nn);
+  memcpy(Ja, out + 3 * nn, sizeof(real) * 9 * nn);
+  jacobian(out + 12 * nn, nn, J);
+  free(Xg);
+  free(tmp);
+  free(out);
 }
 
 static void build_geometry(orc_solver* s) {
 #pragma omp parallel for schedule(static)
   for (int e = 0; e < s->E; e++) {
-    int a = e % s->ex, b = (e / s->ex) % s->ey, c = e / (s->ex * s->ey);
-    int cell[3] = {a, b, c};
-    const int* N = s->N[e];
     int nn = nn_of(s, e);
     real* X = s->X + s->off[e] * 3;
-    /* The map is x = corner + Xl, Xl = (1+xi)/2 h + displacement.  The metric terms depend
-     * only on derivatives of x and on x up to a constant per element (a constant c added to
-     * X_l in the curl form adds c grad X_m, whose discrete curl vanishes because the
-     * tensor-product derivative matrices commute), so they are formed from Xl, whose size is
-     * the element's, not the box's. */
-    real* Xl = (real*)malloc(sizeof(real) * 3 * nn);
-    for (int k = 0; k <= N[2]; k++)
-      for (int j = 0; j <= N[1]; j++)
-        for (int i = 0; i <= N[0]; i++) {
-          int ii[3] = {i, j, k};
-          real xu[3], loc[3], dx[3];
-          for (int d = 0; d < 3; d++) {
-            loc[d] = (1 + s->T[N[d]].xi[ii[d]]) / 2 * s->h[d];
-            xu[d] = s->lo[d] + cell[d] * s->h[d] + loc[d];
-          }
-          displacement(s, xu, dx);
-          long q = node_of(s, e, ii);
-          for (int d = 0; d < 3; d++) {
-            X[(long)d * nn + q] = xu[d] + dx[d];
-            Xl[(long)d * nn + q] = loc[d] + dx[d];
-          }
-        }
-    /* dX[m][d]: derivative of coordinate m along xi_d */
-    real* dX = (real*)malloc(sizeof(real) * 9 * nn);
-    real* A = (real*)malloc(sizeof(real) * 3 * nn);
-    for (int k = 0; k <= N[2]; k++)
-      for (int j = 0; j <= N[1]; j++)
-        for (int i = 0; i <= N[0]; i++) {
-          int ii[3] = {i, j, k};
-          long q = node_of(s, e, ii);
-          for (int m = 0; m < 3; m++)
-            for (int d = 0; d < 3; d++) dX[(3 * m + d) * nn + q] = dref(s, e, Xl + (long)m * nn, d, ii);
-        }
     real* Ja = s->Ja + s->off[e] * 9;
     real* J = s->J + s->off[e];
-    /* curl form: Ja^i_n = -[curl_xi (X_l grad_xi X_m)]_i with (n,m,l) cyclic */
-    for (int n = 0; n < 3; n++) {
-      int m = (n + 1) % 3, l = (n + 2) % 3;
-      for (int q = 0; q < nn; q++)
-        for (int d = 0; d < 3; d++) A[d * nn + q] = Xl[(long)l * nn + q] * dX[(3 * m + d) * nn + q];
-      for (int k = 0; k <= N[2]; k++)
-        for (int j = 0; j <= N[1]; j++)
-          for (int i = 0; i <= N[0]; i++) {
-            int ii[3] = {i, j, k};
-            long q = node_of(s, e, ii);
-            /* curl components: (d1 A2 - d2 A1, d2 A0 - d0 A2, d0 A1 - d1 A0) */
-            real c0 = dref(s, e, A + 2 * nn, 1, ii) - dref(s, e, A + 1 * nn, 2, ii);
-            real c1 = dref(s, e, A + 0 * nn, 2, ii) - dref(s, e, A + 2 * nn, 0, ii);
-            real c2 = dref(s, e, A + 1 * nn, 0, ii) - dref(s, e, A + 0 * nn, 1, ii);
-            Ja[(long)(3 * 0 + n) * nn + q] = -c0;
-            Ja[(long)(3 * 1 + n) * nn + q] = -c1;
-            Ja[(long)(3 * 2 + n) * nn + q] = -c2;
-          }
+    if (s->gauss) {
+      element_geometry_gauss(s, e, X, Ja, J);
+      continue;
     }
-    /* J = a_1 . (a_2 x a_3), a_d = dX/dxi_d */
-    for (int q = 0; q < nn; q++) {
-      real a1[3], a2[3], a3[3];
-      for (int m = 0; m < 3; m++) {
-        a1[m] = dX[(3 * m + 0) * nn + q];
-        a2[m] = dX[(3 * m + 1) * nn + q];
-        a3[m] = dX[(3 * m + 2) * nn + q];
-      }
-      J[q] = a1[0] * (a2[1] * a3[2] - a2[2] * a3[1]) + a1[1] * (a2[2] * a3[0] - a2[0] * a3[2]) +
-             a1[2] * (a2[0] * a3[1] - a2[1] * a3[0]);
-    }
+    real* dX = (real*)malloc(sizeof(real) * 9 * nn);
+    element_geometry(s, e, s->T, X, Ja, dX);
+    jacobian(dX, nn, J);
     free(dX);
-    free(A);
-    free(Xl);
   }
 }
 
@@ -545,9 +613,9 @@ orc_solver* orc_create(int ex, int ey, int ez, const double* lo, const double* h
   return create(ex, ey, ez, lo, hi, deform, amp, n_uniform, orders, gamma, Pr, Ma, Re, vol_flux, surf_flux, 0);
 }
 
-orc_solver* orc_create_gauss(int ex, int ey, int ez, const double* lo, const double* hi, int N, double gamma,
-                             double Pr, double Ma, double Re, int surf_flux) {
-  return create(ex, ey, ez, lo, hi, 0, 0.0, N, NULL, gamma, Pr, Ma, Re, ORC_VOL_CENTRAL, surf_flux, 1);
+orc_solver* orc_create_gauss(int ex, int ey, int ez, const double* lo, const double* hi, int deform, double amp,
+                             int N, double gamma, double Pr, double Ma, double Re, int surf_flux) {
+  return create(ex, ey, ez, lo, hi, deform, amp, N, NULL, gamma, Pr, Ma, Re, ORC_VOL_CENTRAL, surf_flux, 1);
 }
 
 void orc_destroy(orc_solver* s) {
@@ -1297,8 +1365,7 @@ static void gauss_trace(const orc_solver* s, const real* f, int nv, int e, int d
  *     g* = (g(U_L) + g(U_R)) / 2 of the interpolated traces:
  *       J grad g = sum_d Ja^d (delta_d g),
  *       (delta_d g)_i = -sum_m (w_m / w_i) D_mi g_m + (l_i(+1) g*(+d) - l_i(-1) g*(-d)) / w_i
- *     (the path takes affine elements, whose metric is constant and comes out of the
- *     derivative). */
+ *     (the node's metric outside the weak derivative, as in the Lobatto BR1 gradient of 7). */
 static void compute_gradients_gauss(orc_solver* s, const real* U, real* Gout) {
 #pragma omp parallel for schedule(static)
   for (int e = 0; e < s->E; e++) {

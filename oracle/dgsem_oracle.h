@@ -54,10 +54,11 @@ int orc_mortar_matrices(int N, int M, double* I, double* P);
 orc_solver* orc_create(int ex, int ey, int ez, const double* lo, const double* hi, int deform,
                        double amp, int n_uniform, const int* orders, double gamma, double Pr,
                        double Ma, double Re, int vol_flux, int surf_flux);
-/* The same box (undeformed, uniform order N) on Gauss-Legendre nodes: plain (non-split) weak
- * form, face traces interpolated to the element boundaries; Re > 0 adds BR1 viscous terms. */
-orc_solver* orc_create_gauss(int ex, int ey, int ez, const double* lo, const double* hi, int N, double gamma,
-                             double Pr, double Ma, double Re, int surf_flux);
+/* The same box (uniform order N, optionally deformed) on Gauss-Legendre nodes: plain (non-split)
+ * weak form, face traces interpolated to the element boundaries; Re > 0 adds BR1 viscous terms.
+ * The map and its metric terms are the Lobatto grid's, evaluated at the Gauss points. */
+orc_solver* orc_create_gauss(int ex, int ey, int ez, const double* lo, const double* hi, int deform, double amp,
+                             int N, double gamma, double Pr, double Ma, double Re, int surf_flux);
 void orc_destroy(orc_solver* s);
 /* Face viscous flux: BR1 (default), BR2 with lifting factor eta, or the symmetric interior
  * penalty with penalty factor eta (sigma = eta (N+1)^2 / h); eta = 0 takes 2 (BR2), 1 (IP). */

@@ -22,6 +22,7 @@
 namespace dg {
 void gll_tables(int N, double* xi, double* w, double* D, double* Dh);
 void gl_tables(int N, double* xi, double* w, double* D, double* lb);
+void lobatto_to_gauss(int N, double* xl, double* Dl, double* I);
 void mortar_tables(int N, int M, double* I, double* P);
 }
 
@@ -125,7 +126,7 @@ struct dg_solver {
 namespace {
 
 struct Plan {
-  size_t tab, nbr, X, Ja, J, invJ, U0, U1, dU, R, Fvf, part, diag, adapt, elem, work, mtab, Fs, fdesc, Tr, svvtab,
+  size_t tab, nbr, X, Ja, J, invJ, U0, U1, dU, R, Fvf, part, diag, adapt, elem, work, mtab, Fs, fdesc, Tr, Sf, svvtab,
       Fa, self, total;
   size_t tab_n, mtab_n;
 };
@@ -154,7 +155,7 @@ Plan make_plan(const dg_solver* s) {
     for (int N = 1; N <= dg::kMaxOrder; N++)
       for (int M = N + 1; M <= dg::kMaxOrder; M++) p.mtab_n += 2 * (N + 1) * (M + 1);
   } else {
-    p.tab_n = dg::tab_size((int)n);
+    p.tab_n = dg::tab_size((int)n) + (s->mesh.gauss ? dg::tab_gauss_geo_size((int)n) : 0);
   }
   p.tab = take(sizeof(double) * p.tab_n);
   p.nbr = take(sizeof(int) * 6 * E);
@@ -176,6 +177,7 @@ Plan make_plan(const dg_solver* s) {
   p.Fs = mixed ? take(sizeof(double) * dg::kMixFaceDoubles * E) : 0;
   p.fdesc = mixed ? take(sizeof(int4) * 3 * E) : 0;
   p.Tr = s->mesh.gauss ? take(sizeof(double) * E * 6 * 5 * nf) : 0;
+  p.Sf = s->mesh.gauss ? take(sizeof(double) * E * 9 * nf) : 0;
   const bool svv = s->phys.svv_mu > 0 || s->phys.les_cs > 0;
   p.svvtab = svv ? take(sizeof(double) * n * n) : 0;
   p.Fa = svv ? take(sizeof(double) * 12 * nt) : 0;
@@ -515,8 +517,7 @@ int dg_mesh_create_box(const dg_box_desc* d, dg_mesh** out) try {
   m->amp = d->deform_amp;
   m->mixed = mixed;
   m->gauss = d->nodes == DG_NODES_GAUSS;
-  if (m->gauss && (mixed || d->deform != DG_DEFORM_NONE))
-    return fail(DG_EUNSUPPORTED, "Gauss-Legendre nodes are built for undeformed uniform-order boxes");
+  if (m->gauss && mixed) return fail(DG_EUNSUPPORTED, "Gauss-Legendre nodes are built for uniform-order boxes");
   m->N = mixed ? nmax : N;
   if (mixed) m->orders.assign(d->orders, d->orders + 3 * E);
   *out = m.release();
@@ -655,6 +656,7 @@ int dg_solver_bind(dg_solver* s, void* dev_ptr, size_t bytes, void* hip_stream) 
   v.fdesc = mixed ? reinterpret_cast<const int4*>(b + p.fdesc) : nullptr;
   v.gauss = s->mesh.gauss ? 1 : 0;
   v.Tr = s->mesh.gauss ? reinterpret_cast<double*>(b + p.Tr) : nullptr;
+  v.Sf = s->mesh.gauss ? reinterpret_cast<double*>(b + p.Sf) : nullptr;
   s->svv_on = s->phys.svv_mu > 0 || s->phys.les_cs > 0;
   if (s->svv_on) {
     s->svv.mu = s->phys.svv_mu;
@@ -672,8 +674,11 @@ int dg_solver_bind(dg_solver* s, void* dev_ptr, size_t bytes, void* hip_stream) 
   std::vector<double> tab(p.tab_n);
   auto fill = [&](int N, double* t) {
     const int n = N + 1;
-    if (s->mesh.gauss)
+    if (s->mesh.gauss) {
       dg::gl_tables(N, t + dg::tab_xi(n), t + dg::tab_w(n), t + dg::tab_D(n), t + dg::tab_Dh(n));
+      double* g = t + dg::tab_size(n);
+      dg::lobatto_to_gauss(N, g, g + n, g + n + n * n);
+    }
     else
       dg::gll_tables(N, t + dg::tab_xi(n), t + dg::tab_w(n), t + dg::tab_D(n), t + dg::tab_Dh(n));
   };

@@ -29,6 +29,11 @@ inline int tab_w(int n) { return n; }
 inline int tab_D(int n) { return 2 * n; }
 inline int tab_Dh(int n) { return 2 * n + n * n; }
 inline int tab_size(int n) { return 2 * n + 2 * n * n; }
+// Gauss-Legendre meshes (whose geometry is the Lobatto grid's, evaluated at the Gauss points)
+// append the Lobatto nodes [g, g+n), the Lobatto derivative matrix [g+n, g+n+n^2) and the
+// interpolation matrix from the Lobatto to the Gauss points [g+n+n^2, g+n+2n^2), I[q*n+l] the
+// Lobatto basis function l at Gauss point q, g = tab_size(n)
+inline int tab_gauss_geo_size(int n) { return n + 2 * n * n; }
 
 // Everything a kernel needs to know about one bound uniform-order solver.
 struct View {
@@ -43,6 +48,8 @@ struct View {
   int visc_flux;    // 0 BR1, 1 BR2, 2 symmetric interior penalty (face viscous flux)
   int gauss;        // Gauss-Legendre nodes: tab's Dhat slot holds l_j(-1), l_j(+1) instead
   double* Tr;       // Gauss-Legendre: face traces [E][6][5][nf] of the state
+  double* Sf;       // Gauss-Legendre: each element's +xi_d face metric Ja^d interpolated to its
+                    // face points, [E][3 d][3 components][nf]
   double visc_eta;  // BR2 lifting factor or interior-penalty factor
   double rho_r, p_r;  // FP32-bulk reference state (mean density and pressure of the state set)
   const int* nbr; // [E][6] neighbour across face f = 2 d + side (side 1: xi_d = +1)

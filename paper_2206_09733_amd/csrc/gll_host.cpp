@@ -178,6 +178,18 @@ void gl_tables(int N, double* xi, double* w, double* D, double* lb) {
   }
 }
 
+// Geometry tables of Gauss-Legendre meshes of order N: the Lobatto nodes xl, the Lobatto
+// derivative matrix Dl and I[q*n+l], the Lobatto basis function l at Gauss point q (the points of
+// gl_tables).
+void lobatto_to_gauss(int N, double* xl, double* Dl, double* I) {
+  const int n = N + 1;
+  std::vector<double> wl(n), Dhl(n * n), xg(n), wg(n), Dg(n * n), lb(n * n);
+  gll_tables(N, xl, wl.data(), Dl, Dhl.data());
+  gl_tables(N, xg.data(), wg.data(), Dg.data(), lb.data());
+  for (int q = 0; q < n; q++)
+    for (int l = 0; l < n; l++) I[q * n + l] = lagrange_at(xl, n, l, xg[q]);
+}
+
 // Mortar operators between Lobatto grids of orders N < M:
 //   I[p][q] (M+1)x(N+1): value at M-node p of the order-N interpolant of the q-th basis function
 //   P[i][q] (N+1)x(M+1): L2 projection onto degree N of the q-th order-M basis function,

@@ -112,6 +112,133 @@ __global__ void __launch_bounds__(nthreads_for(N)) geometry_kernel(View v) {
   }
 }
 
+// Gauss-Legendre meshes: the map and its metric terms are those of the Lobatto grid of the same
+// order (isoparametric there, curl form there), evaluated at the Gauss points.  The curl form
+// makes sum_d d(Ja^d)/dxi_d vanish at the Lobatto nodes, hence identically for these
+// polynomials, and the normal component on a face depends only on that face's Lobatto nodes,
+// which both elements share: a uniform state stays steady.  One lane per node: coordinates,
+// map derivatives and metric terms on the Lobatto nodes (21 fields in LDS), then three passes of
+// the Lobatto-to-Gauss interpolation along the element's lines; J from the interpolated
+// derivatives; each +xi_d face's metric Ja^d interpolated to its face points (into Sf), which
+// both elements of the face take as its scaled normal.
+template <int N>
+__global__ void __launch_bounds__(nthreads_for(N)) geometry_gauss_kernel(View v) {
+  constexpr int n = N + 1, nn = n * n * n, nf = n * n, NT = nthreads_for(N);
+  constexpr int kGeo = 2 * n + 2 * n * n;  // the geometry tables after the Gauss tables
+  const int e = blockIdx.x;
+  const int t = threadIdx.x;
+  const bool act = t < nn;
+  const int ti = t % n, tj = (t / n) % n, tk = t / nf;
+  const int ii[3] = {ti, tj, tk};
+  __shared__ double sD[n * n], sI[n * n], sxi[n], slb[n];
+  __shared__ double sF[21][nn];  // X 0-2, Ja 3-11, dX 12-20 (dX[3m+d] = d x_m / d xi_d)
+  __shared__ double sXl[3][nn], sA[3][nn];
+  for (int x = t; x < n * n; x += NT) {
+    sD[x] = v.tab[kGeo + n + x];
+    sI[x] = v.tab[kGeo + n + n * n + x];
+  }
+  if (t < n) {
+    sxi[t] = v.tab[kGeo + t];
+    slb[t] = v.tab[2 * n + n * n + n + t];  // Gauss basis at xi = +1
+  }
+  __syncthreads();
+  const int cell[3] = {e % v.ex, (e / v.ex) % v.ey, e / (v.ex * v.ey)};
+  const long base = (long)e * nn;
+  if (act) {  // the map at the Lobatto nodes
+    double loc[3], xu[3], dx[3] = {0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+      loc[d] = (1.0 + sxi[ii[d]]) * 0.5 * v.h[d];
+      xu[d] = v.lo[d] + cell[d] * v.h[d] + loc[d];
+    }
+    if (v.deform) {
+      dx[0] = v.amp * sin(xu[1]) * sin(xu[2]);
+      dx[1] = v.amp * sin(xu[2]) * sin(xu[0]);
+      dx[2] = v.amp * sin(xu[0]) * sin(xu[1]);
+    }
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+      sF[d][t] = xu[d] + dx[d];
+      sXl[d][t] = loc[d] + dx[d];  // coordinates relative to the element's corner
+    }
+  }
+  __syncthreads();
+  auto dref = [&](const double* f, int d) {
+    const int id = d == 0 ? ti : (d == 1 ? tj : tk);
+    const int stride = d == 0 ? 1 : (d == 1 ? n : nf);
+    const int b0 = t - id * stride;
+    double s = 0.0;
+#pragma unroll
+    for (int m = 0; m < n; m++) s += sD[id * n + m] * f[b0 + m * stride];
+    return s;
+  };
+  if (act) {
+#pragma unroll
+    for (int m = 0; m < 3; m++)
+#pragma unroll
+      for (int d = 0; d < 3; d++) sF[12 + 3 * m + d][t] = dref(sXl[m], d);
+  }
+  __syncthreads();
+  for (int c = 0; c < 3; c++) {  // curl form, as in geometry_kernel
+    const int m = (c + 1) % 3, l = (c + 2) % 3;
+    if (act) {
+#pragma unroll
+      for (int d = 0; d < 3; d++) sA[d][t] = sXl[l][t] * sF[12 + 3 * m + d][t];
+    }
+    __syncthreads();
+    if (act) {
+      sF[3 + 3 * 0 + c][t] = -(dref(sA[2], 1) - dref(sA[1], 2));
+      sF[3 + 3 * 1 + c][t] = -(dref(sA[0], 2) - dref(sA[2], 0));
+      sF[3 + 3 * 2 + c][t] = -(dref(sA[1], 0) - dref(sA[0], 1));
+    }
+    __syncthreads();
+  }
+  // to the Gauss points: along xi_0, xi_1, xi_2 in turn
+  for (int d = 0; d < 3; d++) {
+    double r[21];
+    if (act) {
+      const int id = d == 0 ? ti : (d == 1 ? tj : tk);
+      const int stride = d == 0 ? 1 : (d == 1 ? n : nf);
+      const int b0 = t - id * stride;
+#pragma unroll
+      for (int f = 0; f < 21; f++) {
+        double s = 0.0;
+#pragma unroll
+        for (int l = 0; l < n; l++) s += sI[id * n + l] * sF[f][b0 + l * stride];
+        r[f] = s;
+      }
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int f = 0; f < 21; f++) sF[f][t] = r[f];
+    }
+    __syncthreads();
+  }
+  if (act) {
+#pragma unroll
+    for (int d = 0; d < 3; d++) v.X[base * 3 + d * nn + t] = sF[d][t];
+#pragma unroll
+    for (int c = 0; c < 9; c++) v.Ja[base * 9 + c * nn + t] = sF[3 + c][t];
+    auto X = [&](int m, int d) { return sF[12 + 3 * m + d][t]; };
+    const double J = X(0, 0) * (X(1, 1) * X(2, 2) - X(2, 1) * X(1, 2)) +
+                     X(1, 0) * (X(2, 1) * X(0, 2) - X(0, 1) * X(2, 2)) +
+                     X(2, 0) * (X(0, 1) * X(1, 2) - X(1, 1) * X(0, 2));
+    v.J[base + t] = J;
+    v.invJ[base + t] = 1.0 / J;
+  }
+  // the +xi_d faces' metric at their face points: sum_i l_i(+1) Ja^d(node i of the line)
+  for (int x = t; x < 9 * nf; x += NT) {
+    const int dc = x / nf, q = x - dc * nf;
+    const int d = dc / 3;
+    const int p = q % n, r = q / n;
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < n; i++) s += slb[i] * sF[3 + dc][face_node<n>(d, i, p, r)];
+    v.Sf[((long)e * 9 + dc) * nf + q] = s;
+  }
+}
+
 // The face normal Ja^d on the -d side of each element is replaced by the owner's (the
 // element across that face, whose +d side it is): both sides then evaluate bitwise the same
 // face flux.  The two values differ only by rounding.
@@ -499,10 +626,13 @@ __global__ void adapt_reset_kernel(View v) {
 template <int N>
 static hipError_t geometry_n(const View& v, hipStream_t st) {
   constexpr int n = N + 1, nf = n * n;
+  if (v.gauss) {  // no boundary nodes: each face takes its owner's interpolated metric
+    hipLaunchKernelGGL(geometry_gauss_kernel<N>, dim3(v.E), dim3(nthreads_for(N)), 0, st, v);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(geometry_kernel<N>, dim3(v.E), dim3(nthreads_for(N)), 0, st, v);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
-  if (v.gauss) return hipSuccess;  // no boundary nodes: nothing to make single-valued
   const long total = (long)v.E * 3 * nf;
   hipLaunchKernelGGL(facefix_kernel<N>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, v);
   return hipGetLastError();

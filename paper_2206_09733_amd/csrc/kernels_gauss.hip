@@ -1,6 +1,6 @@
 // kernels_gauss.hip -- DGSEM on Gauss-Legendre nodes, the other quadrature that section "Spatial
 // discretisation" allows: the plain weak form (no boundary nodes, so no split form), with BR1
-// viscous terms for Navier-Stokes, on undeformed uniform-order boxes, FP64.
+// viscous terms for Navier-Stokes, on uniform-order boxes (undeformed or deformed), FP64.
 //
 // Two launches per RK stage (three with viscosity: gauss_grad_kernel between them).
 // gauss_trace_kernel interpolates each element's state to its six
@@ -9,9 +9,9 @@
 //   J dU_i/dt = -[ sum_d sum_m Dw_im F~^d_m + sum_d (l_i(+1) F*(+d) - l_i(-1) F*(-d)) / w_i ],
 // Dw_im = -D_mi w_m / w_i (the quadrature of the weak derivative), F~^d = Ja^d . F(U) at the
 // nodes, and F* the numerical flux between the element's own trace and its neighbour's, both
-// read from Tr, oriented along +xi_d with the owner's metric (the element on the -xi_d side;
-// affine elements have constant metrics) as the scaled normal, so both elements evaluate the
-// same flux from the same values.  Every node of a line receives the lift of both of the
+// read from Tr, oriented along +xi_d with the owner's metric (the element on the -xi_d side)
+// interpolated to the face point as the scaled normal (Sf, formed with the geometry), so both
+// elements evaluate the same flux from the same values.  Every node of a line receives the lift of both of the
 // line's face fluxes (l_i(+-1) != 0 for all i), unlike the Lobatto form.
 #include <hip/hip_runtime.h>
 
@@ -54,9 +54,10 @@ __global__ void __launch_bounds__(nthreads_for(N)) gauss_trace_kernel(View v, in
 // BR1 on Gauss points (Navier-Stokes): the weak-form gradient of g = (v, T) with the face values
 // g* = (g(U_L) + g(U_R)) / 2 of both sides' traces,
 //   J grad g = sum_d Ja^d [ sum_m Dw_im g_m + (l_i(+1) g*(+d) - l_i(-1) g*(-d)) / w_i ]
-// (affine elements: constant metric), written to Q[E][12][nn], and on the six faces the
-// contravariant viscous flux of this side's traces, F_v(U trace, sum_i l_i grad g_i) . S with the
-// owner's metric S, into Fvf[E][6][4][nf]; the stage kernel averages the two sides.
+// (the node's metric outside the weak derivative, as in the Lobatto BR1 gradient), written to
+// Q[E][12][nn], and on the six faces the contravariant viscous flux of this side's traces,
+// F_v(U trace, sum_i l_i grad g_i) . S with the owner's face metric S (Sf), into
+// Fvf[E][6][4][nf]; the stage kernel averages the two sides.
 template <int N>
 __global__ void __launch_bounds__(nthreads_for(N)) gauss_grad_kernel(View v, int cur) {
   constexpr int n = N + 1, nn = n * n * n, nf = n * n, NT = nthreads_for(N);
@@ -152,8 +153,8 @@ __global__ void __launch_bounds__(nthreads_for(N)) gauss_grad_kernel(View v, int
     double Fv[3][4];
     viscous_flux_g(go[0], go[1], go[2], gr, v.mu, v.kappa, Fv);
     const long owner = side ? e : v.nbr[e * 6 + f];
-    const double s1 = v.Ja[owner * nn * 9 + (3 * d) * nn], s2 = v.Ja[owner * nn * 9 + (3 * d + 1) * nn],
-                 s3 = v.Ja[owner * nn * 9 + (3 * d + 2) * nn];
+    const double* So = v.Sf + (owner * 9 + 3 * d) * nf;
+    const double s1 = So[q], s2 = So[nf + q], s3 = So[2 * nf + q];
 #pragma unroll
     for (int c = 0; c < 4; c++) Fvf[(f * 4 + c) * nf + q] = s1 * Fv[0][c] + s2 * Fv[1][c] + s3 * Fv[2][c];
   }
@@ -216,7 +217,7 @@ __global__ void __launch_bounds__(nthreads_for(N))
     }
     const long owner = side ? e : ne;
 #pragma unroll
-    for (int c = 0; c < 3; c++) S[c] = v.Ja[owner * nn * 9 + (3 * d + c) * nn];
+    for (int c = 0; c < 3; c++) S[c] = v.Sf[(owner * 9 + 3 * d + c) * nf + q];
     if (VISC) {
       double go[4], gn[4];
       gvars(side ? uL : uR, v.gamma, 0.0, go);
