@@ -143,15 +143,23 @@ enum { DG_VISC_BR1 = 0, DG_VISC_BR2 = 1, DG_VISC_IP = 2 };
  * are this library's readings.  Uniform-order Gauss-Lobatto meshes, FP64. */
 enum { DG_SVV_TADMOR = 0, DG_SVV_MADAY = 1 };
 
-/* Explicit LES closure (section on turbulence models, which names Smagorinsky's model and the
- * SVV-Smagorinsky model and leaves their definitions to its references): with les_cs > 0 the
- * artificial viscosity of the term above becomes, node by node, svv_mu + rho (les_cs Delta)^2 |S|,
- * Smagorinsky's eddy viscosity with |S| = sqrt(2 S:S), S = (grad v + grad v^T)/2 from the same
- * BR1 gradient and Delta = 2 (J/(N+1)^3)^(1/3) (the cube root of the element volume per node),
- * and the conductivity that viscosity times gamma/((gamma-1) Pr).  Filtered by the SVV kernel it
- * is the SVV-Smagorinsky closure; with DG_SVV_TADMOR and svv_cutoff -1 (every mode kept) the
- * plain Smagorinsky model.  The filter width and the turbulent Prandtl number (= Pr) are this
- * library's readings.  The step-size estimates count svv_mu, not the eddy viscosity. */
+/* Explicit LES closure (section on turbulence models, which names the Smagorinsky, WALE, Vreman
+ * and SVV-Smagorinsky models and leaves their definitions to its references): with les_cs > 0
+ * the artificial viscosity of the term above becomes, node by node, svv_mu + rho nu_t, the eddy
+ * viscosity of model les_model with constant C = les_cs, from g = grad v of the same BR1 gradient
+ * and the filter width Delta = 2 (J/(N+1)^3)^(1/3) (the cube root of the element volume per
+ * node):
+ *   DG_LES_SMAGORINSKY  nu_t = (C Delta)^2 |S|, S = (g + g^T)/2, |S| = sqrt(2 S:S);
+ *   DG_LES_WALE         nu_t = (C Delta)^2 (Sd:Sd)^(3/2) / ((S:S)^(5/2) + (Sd:Sd)^(5/4)),
+ *                       Sd = (g^2 + (g^2)^T)/2 - tr(g^2) I/3 (Nicoud and Ducros);
+ *   DG_LES_VREMAN       nu_t = C sqrt(B / (g:g)), b = Delta^2 g g^T,
+ *                       B = b11 b22 - b12^2 + b11 b33 - b13^2 + b22 b33 - b23^2 (Vreman);
+ * each zero where its denominator vanishes, and the conductivity that viscosity times
+ * gamma/((gamma-1) Pr).  Filtered by the SVV kernel, Smagorinsky's is the SVV-Smagorinsky
+ * closure; with DG_SVV_TADMOR and svv_cutoff -1 (every mode kept) the plain model.  The filter
+ * width and the turbulent Prandtl number (= Pr) are this library's readings.  The step-size
+ * estimates count svv_mu, not the eddy viscosity. */
+enum { DG_LES_SMAGORINSKY = 0, DG_LES_WALE = 1, DG_LES_VREMAN = 2 };
 
 /* Physics of a solver.  Zero-initialise it (dg_physics p = {0}) before setting fields: every
  * option above is off or at its default when zero. */
@@ -164,7 +172,8 @@ typedef struct {
   int svv_kernel;   /* DG_SVV_TADMOR or DG_SVV_MADAY */
   int svv_cutoff;   /* cutoff mode, -1..N (-1 with DG_SVV_TADMOR: no filtering) */
   double svv_sensor; /* troubled-element threshold of the density sensor; < 0: none */
-  double les_cs;    /* Smagorinsky constant of the explicit LES closure; 0 = off */
+  double les_cs;    /* constant of the explicit LES closure; 0 = off */
+  int les_model;    /* DG_LES_SMAGORINSKY, DG_LES_WALE or DG_LES_VREMAN */
 } dg_physics;
 
 /* Diagnostics, all FP64 with Gauss-Lobatto quadrature w_i w_j w_k J, reduced in a fixed order
@@ -200,8 +209,8 @@ int dg_mesh_info(const dg_mesh* m, long long* n_elements, long long* n_nodes, in
  * (mixed-order meshes are evaluated for the Euler equations, in FP64 or FP32-bulk), and for
  * DG_FP32_BULK with a volume flux other than DG_VOL_EC / DG_VOL_CENTRAL or a surface flux other
  * than DG_SURF_ROE / LLF / EC / CENTRAL.  Spectral vanishing viscosity (svv_mu > 0 or
- * les_cs > 0): DG_EINVAL for an unknown kernel, a cutoff outside [-1, N], Pr <= 0 or a NaN
- * threshold; DG_EUNSUPPORTED on a mixed-order or Gauss-Legendre mesh or in FP32-bulk; svv_mu or
+ * les_cs > 0): DG_EINVAL for an unknown kernel or LES model, a cutoff outside [-1, N], Pr <= 0
+ * or a NaN threshold; DG_EUNSUPPORTED on a mixed-order or Gauss-Legendre mesh or in FP32-bulk; svv_mu or
  * les_cs < 0 or non-finite: DG_EINVAL. */
 int dg_solver_create(const dg_mesh* m, const dg_physics* p, dg_solver** out);
 /* Bytes of device memory the solver needs (host-only; used for admission control). */

@@ -84,11 +84,11 @@ def _lib(precision="fp64"):
         L.orc_svv_sensor.argtypes = [ctypes.c_void_p, _dp]
         L.orc_svv_filter.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp]
         L.orc_svv_flux.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]
-        L.orc_set_les.argtypes = [ctypes.c_void_p, ctypes.c_double]
-        L.orc_les_viscosity.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+        L.orc_set_les.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double]
+        L.orc_les_viscosity.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                         ctypes.c_int, _dp]
-        L.orc_les_flux.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                   ctypes.c_double, ctypes.c_int, _dp]
+        L.orc_les_flux.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                   ctypes.c_double, ctypes.c_double, ctypes.c_int, _dp]
         _libs[name] = L
     return _libs[name]
 
@@ -225,22 +225,26 @@ def svv_flux(U, Gw, mu_a, gamma=1.4, Pr=0.71, precision="fp64"):
     return res.reshape(3, 5)
 
 
-def les_viscosity(U, Gw, cs, J, n, gamma=1.4, precision="fp64"):
-    """Smagorinsky's eddy viscosity rho (cs Delta)^2 |S| at one state (explicit LES closure):
-    Gw[3c+x] = d w_c / d x_x, J the Jacobian, n the element's node count."""
+LES_MODEL = {"smagorinsky": 0, "wale": 1, "vreman": 2}
+
+
+def les_viscosity(U, Gw, cs, J, n, model="smagorinsky", gamma=1.4, precision="fp64"):
+    """The eddy viscosity rho nu_t of the explicit LES closure at one state (Smagorinsky, WALE or
+    Vreman with constant cs): Gw[3c+x] = d w_c / d x_x, J the Jacobian, n the element's node
+    count."""
     out = np.zeros(1)
-    if _lib(precision).orc_les_viscosity(_ptr(_f64(U, 5)), _ptr(_f64(Gw, 15)), gamma, float(cs), float(J), int(n),
-                                         _ptr(out)):
+    if _lib(precision).orc_les_viscosity(_ptr(_f64(U, 5)), _ptr(_f64(Gw, 15)), gamma, LES_MODEL[model], float(cs),
+                                         float(J), int(n), _ptr(out)):
         raise ValueError("orc_les_viscosity rejected the arguments")
     return float(out[0])
 
 
-def les_flux(U, Gw, cs, J, n, mu_a=0.0, gamma=1.4, Pr=0.71, precision="fp64"):
-    """Unfiltered artificial flux at one state with Smagorinsky's viscosity added (rows =
+def les_flux(U, Gw, cs, J, n, mu_a=0.0, model="smagorinsky", gamma=1.4, Pr=0.71, precision="fp64"):
+    """Unfiltered artificial flux at one state with the model's eddy viscosity added (rows =
     directions), the factors the solver's filtered flux uses."""
     res = np.zeros(15)
-    if _lib(precision).orc_les_flux(_ptr(_f64(U, 5)), _ptr(_f64(Gw, 15)), gamma, Pr, float(mu_a), float(cs),
-                                    float(J), int(n), _ptr(res)):
+    if _lib(precision).orc_les_flux(_ptr(_f64(U, 5)), _ptr(_f64(Gw, 15)), gamma, Pr, float(mu_a), LES_MODEL[model],
+                                    float(cs), float(J), int(n), _ptr(res)):
         raise ValueError("orc_les_flux rejected the arguments")
     return res.reshape(3, 5)
 
@@ -360,11 +364,12 @@ class OracleSolver:
         if self.L.orc_set_svv(self.h, float(mu_a), SVV_KERNEL[kernel], int(cutoff), float(sensor)):
             raise ValueError("orc_set_svv rejected the configuration")
 
-    def set_les(self, cs):
-        """Explicit LES closure: Smagorinsky's eddy viscosity with constant cs joins the artificial
-        viscosity of the SVV term (then filtered by its kernel: SVV-Smagorinsky; Tadmor's kernel
-        with cutoff -1 keeps every mode: plain Smagorinsky).  Call before set_svv."""
-        if self.L.orc_set_les(self.h, float(cs)):
+    def set_les(self, cs, model="smagorinsky"):
+        """Explicit LES closure: the model's eddy viscosity (Smagorinsky, WALE or Vreman, constant
+        cs) joins the artificial viscosity of the SVV term (then filtered by its kernel:
+        SVV-Smagorinsky; Tadmor's kernel with cutoff -1 keeps every mode: the plain model).
+        Call before set_svv."""
+        if self.L.orc_set_les(self.h, LES_MODEL[model], float(cs)):
             raise ValueError("orc_set_les rejected the configuration")
 
     def svv_residual(self):

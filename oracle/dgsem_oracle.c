@@ -336,7 +336,8 @@ struct orc_solver {
   int svv;         /* spectral vanishing viscosity on (section 8c) */
   int svv_kernel, svv_cut;
   real svv_mu, svv_kappa, svv_sensor;
-  real les_cs;     /* Smagorinsky constant of the explicit LES closure; 0 = off */
+  real les_cs;     /* constant of the explicit LES closure; 0 = off */
+  int les_model;   /* ORC_LES_SMAGORINSKY / WALE / VREMAN */
   real *Gw, *Fa;   /* entropy-variable gradients (15 per node), filtered fluxes (15 per node) */
   real *X, *Ja, *J; /* coordinates, metric terms, Jacobian */
   real *U, *dU, *G, *R;
@@ -1514,16 +1515,23 @@ static void element_residual_gauss(const orc_solver* s, const real* U, const rea
  *     Residual: as the viscous terms of section 8, J R_a = sum_d D_d F~^d
  *     + (1/w_N)(F~* - F~) at xi_d = +1 - (1/w_0)(F~* - F~) at -1, F~^d = Ja^d . F_a^F and F~* the
  *     average of the two sides' filtered fluxes along the owner's Ja^d.
- *     Explicit LES closure (section on turbulence models: Smagorinsky, and SVV-Smagorinsky, whose
- *     definitions the paper leaves to its references).  Reading: the artificial viscosity of the
- *     term above becomes, node by node, mu_a + rho (C_s Delta)^2 |S| with Smagorinsky's
- *     |S| = sqrt(2 S:S), S = (grad v + grad v^T)/2 from the same BR1 gradient
- *     (grad v_k = theta (grad w_{k+1} + v_k grad w_5)), the filter width Delta = 2 (J/n)^(1/3)
- *     (the cube root of the element volume per node, n the element's node count), and the
- *     conductivity that viscosity times gamma/((gamma-1) Pr).  Filtered by the SVV kernel this is
- *     the SVV-Smagorinsky closure; with Tadmor's kernel and cutoff -1 (every mode kept) it is the
- *     plain Smagorinsky model.  Since D scales with the viscosity node by node, sqrt(J D) and
- *     D^{1/2} carry the local value and the factorisation above is unchanged.
+ *     Explicit LES closure (section on turbulence models: Smagorinsky, WALE, Vreman and
+ *     SVV-Smagorinsky, whose definitions the paper leaves to its references).  Reading: the
+ *     artificial viscosity of the term above becomes, node by node, mu_a + rho nu_t with the
+ *     eddy viscosity nu_t of the model from g = grad v (g_kj = d v_k / d x_j) of the same BR1
+ *     gradient (grad v_k = theta (grad w_{k+1} + v_k grad w_5)) and the filter width
+ *     Delta = 2 (J/n)^(1/3) (the cube root of the element volume per node, n the element's node
+ *     count):
+ *       Smagorinsky  nu_t = (C Delta)^2 |S|,  S = (g + g^T)/2,  |S| = sqrt(2 S:S);
+ *       WALE         nu_t = (C Delta)^2 (Sd:Sd)^(3/2) / ((S:S)^(5/2) + (Sd:Sd)^(5/4)),
+ *                    Sd = (g^2 + (g^2)^T)/2 - tr(g^2) I/3  (Nicoud and Ducros);
+ *       Vreman       nu_t = C sqrt(B / (g:g)),  b = Delta^2 g g^T,
+ *                    B = b11 b22 - b12^2 + b11 b33 - b13^2 + b22 b33 - b23^2  (Vreman);
+ *     each zero where its denominator vanishes; the conductivity is that viscosity times
+ *     gamma/((gamma-1) Pr).  Filtered by the SVV kernel this is the SVV-Smagorinsky closure (with
+ *     Smagorinsky's nu_t); with Tadmor's kernel and cutoff -1 (every mode kept) the plain model.
+ *     Since D scales with the viscosity node by node, sqrt(J D) and D^{1/2} carry the local value
+ *     and the factorisation above is unchanged.
  * ---------------------------------------------------------------------------------------- */
 static real svv_sigma(int N, int kernel, int M, int k) {
   if (k <= M) return 0;
@@ -1611,31 +1619,61 @@ static void svv_filter_field(const int N[3], int kernel, int M, const real* f, r
   free(c);
 }
 
-/* Smagorinsky's eddy viscosity rho (cs Delta)^2 |S| at one node (explicit LES closure): state u,
- * entropy-variable
- * gradient G[3c + x], Jacobian J, n nodes in the element */
-static real les_viscosity(const real u[5], const real G[15], real gamma, real cs, real J, int n) {
+/* the eddy viscosity rho nu_t of the explicit LES closure at one node: state u, entropy-variable
+ * gradient G[3c + x], model and constant, Jacobian J, n nodes in the element */
+static real les_viscosity(const real u[5], const real G[15], real gamma, int model, real cs, real J, int n) {
   prim_t q = prim(u, gamma);
   real th = q.p / q.rho;
-  real dv[3][3];  /* d v_k / d x_j */
+  real g[3][3];  /* d v_k / d x_j */
   for (int k = 0; k < 3; k++)
-    for (int j = 0; j < 3; j++) dv[k][j] = th * (G[3 * (k + 1) + j] + q.v[k] * G[3 * 4 + j]);
-  real ss = 0;
+    for (int j = 0; j < 3; j++) g[k][j] = th * (G[3 * (k + 1) + j] + q.v[k] * G[3 * 4 + j]);
+  real delta = 2 * RCBRT(J / n);
+  real ss = 0;  /* S:S */
   for (int k = 0; k < 3; k++)
     for (int j = 0; j < 3; j++) {
-      real sk = (dv[k][j] + dv[j][k]) / 2;
+      real sk = (g[k][j] + g[j][k]) / 2;
       ss += sk * sk;
     }
-  real delta = 2 * RCBRT(J / n);
-  return q.rho * (cs * delta) * (cs * delta) * RSQRT(2 * ss);
+  real nu = 0;
+  if (model == ORC_LES_SMAGORINSKY) {
+    nu = (cs * delta) * (cs * delta) * RSQRT(2 * ss);
+  } else if (model == ORC_LES_WALE) {
+    real g2[3][3], tr = 0;
+    for (int i = 0; i < 3; i++)
+      for (int j = 0; j < 3; j++) {
+        g2[i][j] = 0;
+        for (int k = 0; k < 3; k++) g2[i][j] += g[i][k] * g[k][j];
+      }
+    for (int i = 0; i < 3; i++) tr += g2[i][i];
+    real sd = 0;  /* Sd:Sd */
+    for (int i = 0; i < 3; i++)
+      for (int j = 0; j < 3; j++) {
+        real x = (g2[i][j] + g2[j][i]) / 2 - (i == j ? tr / 3 : 0);
+        sd += x * x;
+      }
+    real den = RPOW(ss, (real)2.5) + RPOW(sd, (real)1.25);
+    nu = den > 0 ? (cs * delta) * (cs * delta) * RPOW(sd, (real)1.5) / den : 0;
+  } else {  /* Vreman */
+    real b[3][3], gg = 0;
+    for (int i = 0; i < 3; i++)
+      for (int j = 0; j < 3; j++) {
+        b[i][j] = 0;
+        for (int m = 0; m < 3; m++) b[i][j] += delta * delta * g[i][m] * g[j][m];
+        gg += g[i][j] * g[i][j];
+      }
+    real B = b[0][0] * b[1][1] - b[0][1] * b[0][1] + b[0][0] * b[2][2] - b[0][2] * b[0][2] +
+             b[1][1] * b[2][2] - b[1][2] * b[1][2];
+    nu = gg > 0 && B > 0 ? cs * RSQRT(B / gg) : 0;
+  }
+  return q.rho * nu;
 }
 
-/* the factors of the artificial flux at one node: viscosity mu_a plus (cs > 0) Smagorinsky's eddy
+/* the factors of the artificial flux at one node: viscosity mu_a plus (cs > 0) the LES model's eddy
  * viscosity, conductivity that viscosity times gamma/((gamma-1) Pr) */
-static void svv_node_factors(const real u[5], const real G[15], real gamma, real Pr, real mu_a, real cs, real J,
-                             int n, real L[8][15], real D[8]) {
+static void svv_node_factors(const real u[5], const real G[15], real gamma, real Pr, real mu_a, int model,
+                             real cs, real J, int n, real L[8][15], real D[8]) {
   real mu = mu_a;
-  if (cs > 0) mu += les_viscosity(u, G, gamma, cs, J, n);
+  if (cs > 0) mu += les_viscosity(u, G, gamma, model, cs, J, n);
   svv_factors(u, gamma, mu, mu * gamma / ((gamma - 1) * Pr), L, D);
 }
 
@@ -1678,7 +1716,7 @@ static real svv_element_flux(const orc_solver* s, const real* U, const real* Gw,
     load5(s, U, e, q, u);
     for (int t = 0; t < 15; t++) G[t] = Gw[s->off[e] * 15 + (long)t * nn + q];
     real Jq = s->J[s->off[e] + q];
-    svv_node_factors(u, G, s->gamma, s->Pr, s->svv_mu, s->les_cs, Jq, nn, Ln[q], &Dn[8 * q]);
+    svv_node_factors(u, G, s->gamma, s->Pr, s->svv_mu, s->les_model, s->les_cs, Jq, nn, Ln[q], &Dn[8 * q]);
     for (int m = 0; m < 8; m++) {
       real lg = 0;
       for (int t = 0; t < 15; t++) lg += Ln[q][m][t] * G[t];
@@ -2187,22 +2225,26 @@ int orc_set_svv(orc_solver* s, double mu_a, int kernel, int cutoff, double senso
   return 0;
 }
 
-/* the explicit LES closure with Smagorinsky constant cs (0 = off); call before orc_set_svv,
- * which then sets the filter (and may take mu_a = 0) */
-int orc_set_les(orc_solver* s, double cs) {
-  if (!s || s->gauss || !(cs >= 0) || !isfinite(cs)) return -1;
+/* the explicit LES closure: model (ORC_LES_*) and its constant cs (0 = off); call before
+ * orc_set_svv, which then sets the filter (and may take mu_a = 0) */
+int orc_set_les(orc_solver* s, int model, double cs) {
+  if (!s || s->gauss || !(cs >= 0) || !isfinite(cs) || model < ORC_LES_SMAGORINSKY || model > ORC_LES_VREMAN)
+    return -1;
   s->les_cs = cs;
+  s->les_model = model;
   return 0;
 }
 
-/* Smagorinsky's eddy viscosity of the explicit LES closure at one state: U the conservative state, Gw[3c+x] the
- * entropy-variable gradient, J the Jacobian and n the element's node count */
-int orc_les_viscosity(const double* U, const double* Gw, double gamma, double cs, double J, int n, double* mu) {
-  if (!U || !Gw || !mu || n < 1 || !(J > 0)) return -1;
+/* the eddy viscosity rho nu_t of the explicit LES closure at one state: U the conservative state,
+ * Gw[3c+x] the entropy-variable gradient, model and constant, J the Jacobian and n the element's
+ * node count */
+int orc_les_viscosity(const double* U, const double* Gw, double gamma, int model, double cs, double J, int n,
+                      double* mu) {
+  if (!U || !Gw || !mu || n < 1 || !(J > 0) || model < ORC_LES_SMAGORINSKY || model > ORC_LES_VREMAN) return -1;
   real u[5], G[15];
   to_real(U, u, 5);
   to_real(Gw, G, 15);
-  *mu = (double)les_viscosity(u, G, gamma, cs, J, n);
+  *mu = (double)les_viscosity(u, G, gamma, model, cs, J, n);
   return 0;
 }
 
@@ -2240,13 +2282,13 @@ int orc_svv_filter(int N, int kernel, int cutoff, const double* f, double* out) 
 
 /* the unfiltered flux L^T D L G at one state, G[3c+x] = d w_c / d x_x; F[5x+v]; with cs > 0 the
  * viscosity gains Smagorinsky's at Jacobian J in an element of n nodes */
-int orc_les_flux(const double* U, const double* Gw, double gamma, double Pr, double mu_a, double cs, double J, int n,
-                 double* F) {
-  if (n < 1 || !(J > 0)) return -1;
+int orc_les_flux(const double* U, const double* Gw, double gamma, double Pr, double mu_a, int model, double cs,
+                 double J, int n, double* F) {
+  if (n < 1 || !(J > 0) || model < ORC_LES_SMAGORINSKY || model > ORC_LES_VREMAN) return -1;
   real u[5], G[15], L[8][15], D[8];
   to_real(U, u, 5);
   to_real(Gw, G, 15);
-  svv_node_factors(u, G, gamma, Pr, mu_a, cs, J, n, L, D);
+  svv_node_factors(u, G, gamma, Pr, mu_a, model, cs, J, n, L, D);
   for (int x = 0; x < 3; x++)
     for (int c = 0; c < 5; c++) {
       real acc = 0;
@@ -2261,5 +2303,5 @@ int orc_les_flux(const double* U, const double* Gw, double gamma, double Pr, dou
 }
 
 int orc_svv_flux(const double* U, const double* Gw, double gamma, double Pr, double mu_a, double* F) {
-  return orc_les_flux(U, Gw, gamma, Pr, mu_a, 0.0, 1.0, 1, F);
+  return orc_les_flux(U, Gw, gamma, Pr, mu_a, ORC_LES_SMAGORINSKY, 0.0, 1.0, 1, F);
 }

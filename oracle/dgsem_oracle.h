@@ -104,12 +104,15 @@ int orc_viscous_flux(const double* U, const double* grad, double gamma, double P
  * density sensor exceeds sensor_threshold (< 0: no sensor).  Added to the residual of Lobatto
  * solvers with conforming faces; mu_a = 0 switches it off. */
 int orc_set_svv(orc_solver* s, double mu_a, int kernel, int cutoff, double sensor_threshold);
-/* explicit LES closure: the artificial viscosity of the SVV term gains Smagorinsky's eddy
- * viscosity rho (cs Delta)^2 |S| node by node; cs = 0: off.  Set before orc_set_svv. */
-int orc_set_les(orc_solver* s, double cs);
-int orc_les_viscosity(const double* U, const double* Gw, double gamma, double cs, double J, int n, double* mu);
-int orc_les_flux(const double* U, const double* Gw, double gamma, double Pr, double mu_a, double cs, double J, int n,
-                 double* F);
+/* explicit LES closure: the artificial viscosity of the SVV term gains the eddy viscosity
+ * rho nu_t of the model (Smagorinsky, WALE or Vreman; constant cs) node by node; cs = 0: off.
+ * Set before orc_set_svv. */
+enum { ORC_LES_SMAGORINSKY = 0, ORC_LES_WALE = 1, ORC_LES_VREMAN = 2 };
+int orc_set_les(orc_solver* s, int model, double cs);
+int orc_les_viscosity(const double* U, const double* Gw, double gamma, int model, double cs, double J, int n,
+                      double* mu);
+int orc_les_flux(const double* U, const double* Gw, double gamma, double Pr, double mu_a, int model, double cs,
+                 double J, int n, double* F);
 int orc_svv_residual(orc_solver* s, double* Ra, double* form); /* SVV part alone; entropy form */
 int orc_svv_sensor(orc_solver* s, double* sens);              /* s_rho of every element       */
 int orc_svv_filter(int N, int kernel, int cutoff, const double* f, double* out); /* one field */

@@ -568,6 +568,9 @@ int dg_solver_create(const dg_mesh* m, const dg_physics* p, dg_solver** out) try
                                  "form), BR1 viscous terms");
   if (!(p->svv_mu >= 0) || !std::isfinite(p->svv_mu)) return fail(DG_EINVAL, "svv_mu must be >= 0");
   if (!(p->les_cs >= 0) || !std::isfinite(p->les_cs)) return fail(DG_EINVAL, "les_cs must be >= 0");
+  if (p->les_cs > 0 && p->les_model != DG_LES_SMAGORINSKY && p->les_model != DG_LES_WALE &&
+      p->les_model != DG_LES_VREMAN)
+    return fail(DG_EINVAL, "unknown LES model");
   if (p->svv_mu > 0 || p->les_cs > 0) {
     if (p->svv_kernel != DG_SVV_TADMOR && p->svv_kernel != DG_SVV_MADAY) return fail(DG_EINVAL, "unknown SVV kernel");
     if (p->svv_cutoff < -1 || p->svv_cutoff > m->N) return fail(DG_EINVAL, "SVV cutoff outside [-1, N]");
@@ -662,7 +665,8 @@ int dg_solver_bind(dg_solver* s, void* dev_ptr, size_t bytes, void* hip_stream) 
     s->svv.mu = s->phys.svv_mu;
     s->svv.kfac = s->phys.gamma / ((s->phys.gamma - 1.0) * s->phys.Pr);
     s->svv.kappa = s->phys.svv_mu * s->svv.kfac;
-    s->svv.cs2 = s->phys.les_cs * s->phys.les_cs;
+    s->svv.les_c = s->phys.les_cs;
+    s->svv.les_model = s->phys.les_model;
     s->svv.sensor = s->phys.svv_sensor;
     s->svv.filt = reinterpret_cast<const double*>(b + p.svvtab);
     s->svv.Fa = reinterpret_cast<double*>(b + p.Fa);

@@ -16,10 +16,10 @@
 // Elements whose density sensor s = sum w_i w_j w_k J |grad_xi rho|^2 exceeds the threshold
 // take the unfiltered flux.  The residual of the term is the divergence of the contravariant
 // flux with BR1 face terms (the average of the two sides' fluxes along the owner's Ja^d).
-// Explicit LES closure (turbulence models: Smagorinsky, SVV-Smagorinsky): the viscosity gains
-// Smagorinsky's rho (C_s Delta)^2 |S| node by node, |S| = sqrt(2 S:S) with S the symmetric part
-// of grad v = theta Z and Delta = 2 (J/(N+1)^3)^(1/3); mu and kappa enter only through sqrt(mu)
-// and sqrt(kappa) at the node itself, so the factorisation holds with the local values.
+// Explicit LES closure (turbulence models: Smagorinsky, WALE, Vreman, SVV-Smagorinsky): the
+// viscosity gains the model's rho nu_t node by node, from g = grad v = theta Z and
+// Delta = 2 (J/(N+1)^3)^(1/3) (the formulas are in the C header); mu and kappa enter only through
+// sqrt(mu) and sqrt(kappa) at the node itself, so the factorisation holds with the local values.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -155,17 +155,53 @@ __global__ void __launch_bounds__(nthreads_for(N)) svv_flux_kernel(View v, int c
 #pragma unroll
       for (int j = 0; j < 3; j++) Z[k][j] = G[k][j] + vel[k] * G[3][j];
     const double tr3 = (Z[0][0] + Z[1][1] + Z[2][2]) * (1.0 / 3.0);
-    if (a.cs2 > 0.0) {  // explicit LES: Smagorinsky's eddy viscosity at this node
-      double ss = 0.0;
+    if (a.les_c > 0.0) {  // explicit LES: the model's eddy viscosity at this node
+      double g[3][3], ss = 0.0;  // g = grad v, ss = S:S
+#pragma unroll
+      for (int k = 0; k < 3; k++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) g[k][j] = th * Z[k][j];
 #pragma unroll
       for (int k = 0; k < 3; k++)
 #pragma unroll
         for (int j = 0; j < 3; j++) {
-          const double sk = 0.5 * th * (Z[k][j] + Z[j][k]);
+          const double sk = 0.5 * (g[k][j] + g[j][k]);
           ss += sk * sk;
         }
-      const double delta = 2.0 * cbrt(J * (1.0 / nn));
-      mu = a.mu + rho * a.cs2 * delta * delta * sqrt(2.0 * ss);
+      const double delta = 2.0 * cbrt(J * (1.0 / nn)), cd2 = a.les_c * a.les_c * delta * delta;
+      double nu;
+      if (a.les_model == DG_LES_SMAGORINSKY) {
+        nu = cd2 * sqrt(2.0 * ss);
+      } else if (a.les_model == DG_LES_WALE) {
+        double g2[3][3], sd = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+          for (int j = 0; j < 3; j++) g2[i][j] = g[i][0] * g[0][j] + g[i][1] * g[1][j] + g[i][2] * g[2][j];
+        const double tr3 = (g2[0][0] + g2[1][1] + g2[2][2]) * (1.0 / 3.0);
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+          for (int j = 0; j < 3; j++) {
+            const double x = 0.5 * (g2[i][j] + g2[j][i]) - (i == j ? tr3 : 0.0);
+            sd += x * x;
+          }
+        const double rs = sqrt(sd), den = ss * ss * sqrt(ss) + sd * sqrt(rs);  // (S:S)^5/2 + (Sd:Sd)^5/4
+        nu = den > 0.0 ? cd2 * sd * rs / den : 0.0;
+      } else {  // Vreman
+        double b[3][3], gg = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+          for (int j = 0; j < 3; j++) {
+            b[i][j] = delta * delta * (g[i][0] * g[j][0] + g[i][1] * g[j][1] + g[i][2] * g[j][2]);
+            gg += g[i][j] * g[i][j];
+          }
+        const double B = b[0][0] * b[1][1] - b[0][1] * b[0][1] + b[0][0] * b[2][2] - b[0][2] * b[0][2] +
+                         b[1][1] * b[2][2] - b[1][2] * b[1][2];
+        nu = gg > 0.0 && B > 0.0 ? a.les_c * sqrt(B / gg) : 0.0;
+      }
+      mu = a.mu + rho * nu;
       kappa = mu * a.kfac;
     }
     const double sv = sqrt(J * mu * th), sq = th * sqrt(J * kappa);

@@ -6,12 +6,14 @@
 #include <hip/hip_runtime.h>
 
 #include "dg_internal.h"
+#include "dgsem.h"  // DG_LES_* model codes
 
 namespace dg {
 
 struct SvvArgs {
   double mu, kappa;     // artificial viscosity and conductivity mu gamma / ((gamma-1) Pr)
-  double cs2;           // explicit LES: the Smagorinsky constant squared (0: constant viscosity)
+  double les_c;         // explicit LES: the model's constant (0: constant viscosity)
+  int les_model;        // DG_LES_SMAGORINSKY, DG_LES_WALE or DG_LES_VREMAN
   double kfac;          // gamma / ((gamma-1) Pr): conductivity per unit viscosity
   double sensor;        // density-sensor threshold; < 0: every element filtered
   const double* filt;   // (I - Phi) of one direction, (N+1) x (N+1) row-major: Phi = V diag(s) V^-1

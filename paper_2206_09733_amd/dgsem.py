@@ -19,6 +19,7 @@ SURF = {"roe": 0, "llf": 1, "ec": 2, "central": 3, "es": 4, "ir": 5, "es_matrix"
         "lf_global": 8}
 VISC = {"br1": 0, "br2": 1, "ip": 2}
 SVV_KERNEL = {"tadmor": 0, "maday": 1}
+LES_MODEL = {"smagorinsky": 0, "wale": 1, "vreman": 2}
 PRECISION = {"fp64": 0, "fp32_bulk": 1}
 IC = {"uniform": 0, "tgv": 1, "vortex": 2, "density_wave": 3}
 SCHEME = {"rk3": 0, "rk4": 1}
@@ -39,7 +40,7 @@ class Physics(_c.Structure):
                 ("Re", _c.c_double), ("vol_flux", _c.c_int), ("surf_flux", _c.c_int),
                 ("precision", _c.c_int), ("visc_flux", _c.c_int), ("visc_eta", _c.c_double),
                 ("svv_mu", _c.c_double), ("svv_kernel", _c.c_int), ("svv_cutoff", _c.c_int),
-                ("svv_sensor", _c.c_double), ("les_cs", _c.c_double)]
+                ("svv_sensor", _c.c_double), ("les_cs", _c.c_double), ("les_model", _c.c_int)]
 
 
 class Diag(_c.Structure):
@@ -156,14 +157,15 @@ def box_desc(ex, ey, ez, lo, hi, deform, amp, N, orders=None, nodes="lobatto"):
 
 
 def physics(gamma=1.4, Pr=0.71, Ma=0.1, Re=0.0, vol="ec", surf="roe", precision="fp64", visc="br1",
-            visc_eta=0.0, svv_mu=0.0, svv_kernel="maday", svv_cutoff=0, svv_sensor=-1.0, les_cs=0.0):
+            visc_eta=0.0, svv_mu=0.0, svv_kernel="maday", svv_cutoff=0, svv_sensor=-1.0, les_cs=0.0,
+            les_model="smagorinsky"):
     p = Physics()
     p.gamma, p.Pr, p.Ma, p.Re = gamma, Pr, Ma, Re
     p.vol_flux, p.surf_flux, p.precision = VOL[vol], SURF[surf], PRECISION[precision]
     p.visc_flux, p.visc_eta = VISC[visc], float(visc_eta)
     p.svv_mu, p.svv_kernel = float(svv_mu), SVV_KERNEL[svv_kernel]
     p.svv_cutoff, p.svv_sensor = int(svv_cutoff), float(svv_sensor)
-    p.les_cs = float(les_cs)
+    p.les_cs, p.les_model = float(les_cs), LES_MODEL[les_model]
     return p
 
 
@@ -174,15 +176,16 @@ class Solver:
     direction; otherwise all elements take order N.  `svv_mu` > 0 adds spectral vanishing
     viscosity (kernel "maday" or "tadmor", cutoff mode `svv_cutoff`, default N // 2, and the
     troubled-element threshold `svv_sensor` of the density sensor, < 0 for none).  `les_cs` > 0
-    adds Smagorinsky's eddy viscosity with that constant to the artificial viscosity, node by node
-    (filtered by the SVV kernel: SVV-Smagorinsky; kernel "tadmor" with cutoff -1 keeps every mode:
-    plain Smagorinsky).
+    adds the eddy viscosity of `les_model` ("smagorinsky", "wale" or "vreman") with that constant
+    to the artificial viscosity, node by node (filtered by the SVV kernel: SVV-Smagorinsky; kernel
+    "tadmor" with cutoff -1 keeps every mode: the plain model).
     """
 
     def __init__(self, ex, ey=None, ez=None, lo=(0.0, 0.0, 0.0), hi=None, deform=False, amp=0.05,
                  N=3, gamma=1.4, Pr=0.71, Ma=0.1, Re=0.0, vol="ec", surf="roe", precision="fp64",
                  device="cuda", bind=True, orders=None, visc="br1", visc_eta=0.0, nodes="lobatto",
-                 svv_mu=0.0, svv_kernel="maday", svv_cutoff=None, svv_sensor=-1.0, les_cs=0.0):
+                 svv_mu=0.0, svv_kernel="maday", svv_cutoff=None, svv_sensor=-1.0, les_cs=0.0,
+                 les_model="smagorinsky"):
         L = lib()
         ey = ex if ey is None else ey
         ez = ex if ez is None else ez
@@ -202,7 +205,7 @@ class Solver:
             h = _c.c_void_p()
             cut = N // 2 if svv_cutoff is None else svv_cutoff
             ph = physics(gamma, Pr, Ma, Re, vol, surf, precision, visc, visc_eta, svv_mu, svv_kernel, cut,
-                         svv_sensor, les_cs)
+                         svv_sensor, les_cs, les_model)
             check(L.dg_solver_create(mesh, _c.byref(ph), _c.byref(h)))
             self.h = h
         finally:

@@ -226,6 +226,16 @@ def test_spectral_vanishing_viscosity_limits(dg):
                 dict(les_cs=0.1, svv_cutoff=4)):
         p = dg.physics(**bad)
         assert L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)) == dg.DG_EINVAL, bad
+    for model in ("wale", "vreman"):
+        p = dg.physics(les_cs=0.3, les_model=model, svv_cutoff=1)
+        dg.check(L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)))
+        L.dg_solver_destroy(s)
+    p = dg.physics(les_cs=0.1, svv_cutoff=1)
+    p.les_model = 3
+    assert L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)) == dg.DG_EINVAL
+    p.les_cs = 0.0  # the model code is read only with the closure on
+    dg.check(L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)))
+    L.dg_solver_destroy(s)
     p = dg.physics(les_cs=0.1, precision="fp32_bulk")
     assert L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)) == dg.DG_EUNSUPPORTED
     L.dg_mesh_destroy(m)

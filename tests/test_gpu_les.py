@@ -1,9 +1,10 @@
-"""Explicit LES closure on the GPU (turbulence models: Smagorinsky and SVV-Smagorinsky) against the
-oracle: Smagorinsky's eddy viscosity joins the artificial viscosity of the SVV term node by node.
+"""Explicit LES closures on the GPU (turbulence models: Smagorinsky, WALE, Vreman and
+SVV-Smagorinsky) against the oracle: the model's eddy viscosity joins the artificial viscosity of
+the SVV term node by node.
 
 - Residuals of perturbed states on deformed meshes for orders 1..7: SVV-Smagorinsky (Maday kernel)
-  on Euler, the plain Smagorinsky model (every mode kept) on Navier-Stokes, and the closure added
-  to a constant artificial viscosity, to the parity bar (within GATE times the FP64 oracle's
+  on Euler, the plain Smagorinsky, WALE and Vreman models (every mode kept) on Navier-Stokes, and
+  the closure added to a constant artificial viscosity, to the parity bar (within GATE times the FP64 oracle's
   distance to the long-double oracle, or 1e-12 relative); with the density sensor marking some
   elements.
 - The closure's term alone (GPU residual with it minus without) against the oracle's term.
@@ -62,7 +63,7 @@ def oracles(orc, c, U, les):
     for prec in ("fp64", "fp80"):
         o = orc.OracleSolver(**c, precision=prec)
         o.set_state(U)
-        o.set_les(les["cs"])
+        o.set_les(les["cs"], les.get("model", "smagorinsky"))
         o.set_svv(les["mu"], les["kernel"], les["cutoff"], les.get("sensor", -1.0))
         out.append(o)
     return out
@@ -70,20 +71,30 @@ def oracles(orc, c, U, les):
 
 def gpu_solver(dg, c, les):
     return dg.Solver(**c, svv_mu=les["mu"], svv_kernel=les["kernel"], svv_cutoff=les["cutoff"],
-                     svv_sensor=les.get("sensor", -1.0), les_cs=les["cs"])
+                     svv_sensor=les.get("sensor", -1.0), les_cs=les["cs"],
+                     les_model=les.get("model", "smagorinsky"))
 
 
-# (kernel, cutoff, Re, constant artificial viscosity): SVV-Smagorinsky, plain Smagorinsky, both
-MODELS = {"svv_smagorinsky": ("maday", None, 0.0, 0.0), "smagorinsky": ("tadmor", -1, 200.0, 0.0),
-          "svv_plus_smagorinsky": ("maday", None, 0.0, 0.01)}
+# (kernel, cutoff, Re, constant artificial viscosity, LES model): SVV-Smagorinsky, the plain
+# Smagorinsky, WALE and Vreman models, SVV-Smagorinsky on top of a constant viscosity
+MODELS = {"svv_smagorinsky": ("maday", None, 0.0, 0.0, "smagorinsky"),
+          "smagorinsky": ("tadmor", -1, 200.0, 0.0, "smagorinsky"),
+          "wale": ("tadmor", -1, 200.0, 0.0, "wale"), "vreman": ("tadmor", -1, 200.0, 0.0, "vreman"),
+          "svv_plus_smagorinsky": ("maday", None, 0.0, 0.01, "smagorinsky")}
+# the models' usual constants: C_s, C_w (Nicoud and Ducros), c = 2.5 C_s^2 (Vreman)
+CONST = {"smagorinsky": 0.17, "wale": 0.5, "vreman": 0.07}
 CASES = [(N, m) for N in range(1, 8) for m in MODELS]
+
+
+def les_args(model, N):
+    kernel, cut, Re, mu, lm = MODELS[model]
+    return Re, dict(cs=CONST[lm], mu=mu, kernel=kernel, cutoff=N // 2 if cut is None else cut, model=lm)
 
 
 @pytest.mark.parametrize("N,model", CASES)
 def test_les_residual_parity(dg, orc, N, model):
-    kernel, cut, Re, mu = MODELS[model]
+    Re, les = les_args(model, N)
     c = dict(ex=3, ey=2, ez=3, N=N, deform=True, Ma=0.3, Re=Re)
-    les = dict(cs=0.17, mu=mu, kernel=kernel, cutoff=N // 2 if cut is None else cut)
     log(f"les residual N={N} {model}")
     U = perturbed(orc, c, seed=1500 + N)
     o64, o80 = oracles(orc, c, U, les)
@@ -99,9 +110,8 @@ def test_les_part_alone(dg, orc, N, model):
     term minus its residual without, against the oracle's term.  The difference carries the
     rounding of the two full residuals, so the bar is the parity gate or 1e-15 of the full
     residual, whichever is larger."""
-    kernel, cut, Re, mu = MODELS[model]
+    Re, les = les_args(model, N)
     c = dict(ex=3, ey=2, ez=3, N=N, deform=True, Ma=0.3, Re=Re)
-    les = dict(cs=0.17, mu=mu, kernel=kernel, cutoff=N // 2 if cut is None else cut)
     U = perturbed(orc, c, seed=1700 + N)
     o64, o80 = oracles(orc, c, U, les)
     a64, a80 = o64.svv_residual()[0], o80.svv_residual()[0]
@@ -143,11 +153,10 @@ def test_les_with_sensor_marking_some_elements(dg, orc, N):
     g.close()
 
 
-@pytest.mark.parametrize("model", ["svv_smagorinsky", "smagorinsky"])
+@pytest.mark.parametrize("model", ["svv_smagorinsky", "smagorinsky", "wale", "vreman"])
 def test_les_trajectory(dg, orc, model):
-    kernel, cut, Re, mu = MODELS[model]
+    Re, les = les_args(model, 4)
     c = dict(ex=3, N=4, deform=True, Ma=0.3, Re=Re)
-    les = dict(cs=0.17, mu=mu, kernel=kernel, cutoff=2 if cut is None else cut)
     U0 = perturbed(orc, c, seed=51, amp=(0.02, 0.03, 0.02))
     o, o80 = oracles(orc, c, U0, les)
     dt = o.suggest_dt(0.4)
@@ -164,9 +173,10 @@ def test_les_trajectory(dg, orc, model):
     g.close()
 
 
-def test_les_graph_replay_equals_eager(dg):
+@pytest.mark.parametrize("model", ["smagorinsky", "wale", "vreman"])
+def test_les_graph_replay_equals_eager(dg, model):
     c = dict(ex=3, ey=3, ez=2, N=4, deform=True, Ma=0.3, Re=400.0, svv_kernel="maday", svv_cutoff=2,
-             les_cs=0.17)
+             les_cs=CONST[model], les_model=model)
     eager, graph = dg.Solver(**c), dg.Solver(**c)
     for s in (eager, graph):
         s.set_ic("tgv")

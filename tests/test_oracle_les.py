@@ -1,7 +1,8 @@
-"""Pins of the oracle's explicit LES closure (turbulence models: Smagorinsky and SVV-Smagorinsky;
-the paper names them and leaves their definitions to its references, so the closure follows the
-reading stated in the oracle: the artificial viscosity of the SVV term gains rho (C_s Delta)^2 |S|
-node by node, |S| = sqrt(2 S:S), Delta = 2 (J/n)^(1/3)).
+"""Pins of the oracle's explicit LES closure (turbulence models: Smagorinsky, WALE, Vreman and
+SVV-Smagorinsky; the paper names them and leaves their definitions to its references, so the
+closure follows the reading stated in the oracle: the artificial viscosity of the SVV term gains
+the model's rho nu_t node by node, e.g. Smagorinsky's rho (C_s Delta)^2 |S|, |S| = sqrt(2 S:S),
+Delta = 2 (J/n)^(1/3)).
 
 - Smagorinsky's viscosity from entropy-variable gradients equals rho (C_s Delta)^2 |S| with S taken
   from the velocity gradient of the same smooth field (both gradients by central differences, so
@@ -9,6 +10,9 @@ node by node, |S| = sqrt(2 S:S), Delta = 2 (J/n)^(1/3)).
   forms for a pure shear (|S| = |a|), a uniform dilatation (|S| = sqrt(6) |c|) and a rigid rotation
   (|S| = 0), a temperature gradient alone gives none, and Delta scales as J^(1/3); the unfiltered
   flux with the closure is the Navier-Stokes viscous flux with that viscosity and its conductivity.
+- WALE and Vreman: closed forms (both vanish in a pure shear; rigid rotation, axisymmetric strain,
+  dilatation), each model's flux is the Navier-Stokes flux with its viscosity, and the residual
+  scales with the constant as the model does.
 - The residual: the entropy production still equals minus the filtered form (so it is never
   positive), momentum and energy totals are conserved, the term scales as C_s^2 exactly, troubled
   elements take the unfiltered flux (the plain Smagorinsky model), and a uniform flow with a
@@ -198,3 +202,87 @@ def test_uniform_flow_with_varying_temperature_gives_no_eddy_viscosity(orc):
     s = _perturbed(orc, c, seed=2)
     Rs, _ = _les(s, 0.17)
     assert np.abs(R0).max() < 1e-9 * np.abs(Rs).max(), (np.abs(R0).max(), np.abs(Rs).max())
+
+
+# ------------------------------------------------------------------ WALE and Vreman
+def _grad_state(orc, g, rho0=1.3, p0=2.1, v0=(0.4, -0.2, 0.1)):
+    du = np.zeros((3, 5))
+    du[:, 1:4] = np.asarray(g, float).T  # du[x, 1 + k] = d v_k / d x
+    state = _linear_field(rho0, np.asarray(v0, float), p0, du)
+    Gw, gv = _gradients(orc, state)
+    return state(np.zeros(3)), Gw, gv
+
+
+@pytest.mark.parametrize("model,kind", [("wale", "shear"), ("wale", "rotation"), ("wale", "axisymmetric"),
+                                        ("wale", "two_shears"), ("vreman", "shear"), ("vreman", "rotation"),
+                                        ("vreman", "dilatation"), ("vreman", "two_shears")])
+def test_wale_and_vreman_closed_forms(orc, model, kind):
+    """WALE (Nicoud and Ducros) and Vreman's model: both vanish in a pure shear; WALE gives
+    (C Delta)^2 |a| (2/3)^(1/4) for a rigid rotation of rate a and (C Delta)^2 |a| 6^(3/2) /
+    (6^(5/2) + 6^(5/4)) for the axisymmetric strain diag(a, a, -2a); Vreman gives C Delta^2 |a| /
+    sqrt(2) for the rotation and C Delta^2 |a| for a uniform dilatation; and both for two shears
+    in different planes, whose g^2 is not symmetric (worked out in the table below)."""
+    a, rho0 = 0.7, 1.3
+    g = np.zeros((3, 3))
+    if kind == "shear":
+        g[0, 1] = a
+    elif kind == "rotation":
+        g[0, 1], g[1, 0] = -a, a
+    elif kind == "axisymmetric":
+        g[0, 0], g[1, 1], g[2, 2] = a, a, -2 * a
+    elif kind == "two_shears":  # d v_x / d y = a, d v_y / d z = b: g^2 is not symmetric
+        g[0, 1], g[1, 2] = a, 0.4
+    else:
+        g[0, 0] = g[1, 1] = g[2, 2] = a
+    u0, Gw, _ = _grad_state(orc, g, rho0)
+    cs, J, n = 0.3, 0.3, 125
+    delta = 2 * (J / n) ** (1 / 3)
+    ref = {("wale", "shear"): 0.0, ("wale", "rotation"): (cs * delta) ** 2 * a * (2 / 3) ** 0.25,
+           ("wale", "axisymmetric"): (cs * delta) ** 2 * a * 6 ** 1.5 / (6 ** 2.5 + 6 ** 1.25),
+           ("vreman", "shear"): 0.0, ("vreman", "rotation"): cs * delta ** 2 * a / math.sqrt(2),
+           ("vreman", "dilatation"): cs * delta ** 2 * a,
+           # two shears a, b: Sd:Sd = a^2 b^2 / 2, S:S = (a^2 + b^2) / 2; b = Delta^2 diag(a^2, b^2, 0)
+           ("wale", "two_shears"): (cs * delta) ** 2 * (a * a * 0.16 / 2) ** 1.5
+           / (((a * a + 0.16) / 2) ** 2.5 + (a * a * 0.16 / 2) ** 1.25),
+           ("vreman", "two_shears"): cs * delta ** 2 * a * 0.4 / math.sqrt(a * a + 0.16)}[(model, kind)] * rho0
+    mu = orc.les_viscosity(u0, Gw, cs, J, n, model=model)
+    unit = rho0 * cs * delta ** 2 * a
+    assert abs(mu - ref) <= 1e-8 * unit, (model, kind, mu, ref)
+
+
+@pytest.mark.parametrize("model", ["smagorinsky", "wale", "vreman"])
+def test_les_models_flux_and_constant_scaling(orc, model):
+    """Each model's flux is the Navier-Stokes viscous flux with its eddy viscosity; the
+    residual scales with the constant as the model does (C^2 for Smagorinsky and WALE, C for
+    Vreman), and the entropy identity holds."""
+    rng = np.random.default_rng(7)
+    rho0, v0, p0 = 1.1, rng.standard_normal(3) * 0.4, 0.9
+    du = rng.standard_normal((3, 5)) * 0.1
+    state = _linear_field(rho0, v0, p0, du)
+    h = 1e-5
+    Gw, _ = _gradients(orc, state, h)
+    Gg = np.zeros(12)
+    for x in range(3):
+        e = np.zeros(3)
+        e[x] = h
+        rp, vp, pp = _prim(state(e))
+        rm, vm, pm = _prim(state(-e))
+        dg = np.concatenate([(vp - vm), [pp / rp - pm / rm]]) / (2 * h)
+        for c in range(4):
+            Gg[3 * c + x] = dg[c]
+    u0 = state(np.zeros(3))
+    mu = orc.les_viscosity(u0, Gw, 0.2, 0.4, 64, model=model)
+    assert mu > 0
+    Fa = orc.les_flux(u0, Gw, 0.2, 0.4, 64, model=model)
+    Fv = orc.viscous_flux(u0, Gg, GAMMA, 0.71, 1.0 / mu)
+    assert np.abs(Fa - Fv).max() < 1e-7 * np.abs(Fv).max()
+    o = _perturbed(orc, dict(ex=2, ey=3, ez=2, N=3, deform=True, Ma=0.3), seed=41)
+    o.set_les(0.1, model)
+    o.set_svv(0.0, "maday")
+    R1, f1 = o.svv_residual()
+    assert abs(o.entropy_production(R1) + f1) < 1e-11 * f1
+    o.set_les(0.2, model)
+    o.set_svv(0.0, "maday")
+    R2, _ = o.svv_residual()
+    k = 2.0 if model == "vreman" else 4.0
+    assert np.abs(R2 - k * R1).max() < 1e-12 * np.abs(R2).max()
