@@ -1802,11 +1802,16 @@ static void svv_element_residual(const orc_solver* s, const real* Fa, int e, rea
 /* the artificial-viscosity residual of U added to R; returns the entropy form sum <y, F* y> */
 static real svv_residual(orc_solver* s, const real* U, real* R) {
   br1_gradient(s, U, 5, entropy_vars, s->Gw);
-  real form = 0;
-#pragma omp parallel for schedule(dynamic, 4) reduction(+ : form)
-  for (int e = 0; e < s->E; e++) form += svv_element_flux(s, U, s->Gw, e, s->Fa);
+  /* per-element terms of the form, summed in element order: the result does not depend on the
+   * thread count */
+  real* fe = (real*)malloc(sizeof(real) * (size_t)(s->E > 0 ? s->E : 1));
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int e = 0; e < s->E; e++) fe[e] = svv_element_flux(s, U, s->Gw, e, s->Fa);
 #pragma omp parallel for schedule(dynamic, 4)
   for (int e = 0; e < s->E; e++) svv_element_residual(s, s->Fa, e, R + s->off[e] * 5);
+  real form = 0;
+  for (int e = 0; e < s->E; e++) form += fe[e];
+  free(fe);
   return form;
 }
 

@@ -13,6 +13,7 @@
   elements take the unfiltered flux, which equals a filter that passes every mode.
 """
 import math
+import os
 
 import numpy as np
 import numpy.polynomial.legendre as npleg
@@ -206,3 +207,28 @@ def test_svv_rejects_what_it_does_not_cover(orc):
     for bad in (dict(mu_a=-1.0), dict(mu_a=0.1, cutoff=4), dict(mu_a=0.1, cutoff=-2)):
         with pytest.raises(ValueError):
             o.set_svv(**bad)
+
+
+def test_entropy_form_does_not_depend_on_the_thread_count():
+    """The oracle's entropy form and SVV residual are the same, bit for bit, with 1 and 4 OpenMP
+    threads (its per-element terms are summed in element order)."""
+    import subprocess
+    import sys
+    code = ("import numpy as np, oracle\n"
+            "o = oracle.OracleSolver(ex=3, ey=2, ez=3, N=3, deform=True, Ma=0.3)\n"
+            "o.set_ic('tgv')\n"
+            "U = o.state().reshape(o.E, 5, -1)\n"
+            "U[:, 0] *= 1 + 0.05 * np.random.default_rng(3).standard_normal(U[:, 0].shape)\n"
+            "o.set_state(U.reshape(-1))\n"
+            "o.set_svv(0.02, 'maday')\n"
+            "R, f = o.svv_residual()\n"
+            "print(float(f).hex(), __import__('hashlib').sha1(R.tobytes()).hexdigest())\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = []
+    for t in ("1", "4"):
+        env = dict(os.environ, OMP_NUM_THREADS=t)
+        r = subprocess.run([sys.executable, "-c", code], cwd=root, env=env, capture_output=True, text=True,
+                           timeout=120)
+        assert r.returncode == 0, r.stderr
+        out.append(r.stdout.strip())
+    assert out[0] == out[1], out
