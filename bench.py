@@ -202,13 +202,20 @@ def run_small_latency(steps=24, warmup=24):
 def run_gauss(steps, warmup):
     """Euler TGV on the undeformed 32^3 box at N=4 on Gauss-Legendre points (the plain weak form:
     a face-trace kernel and the stage kernel per RK stage), against the same mesh on Lobatto
-    points with the central volume form."""
+    points with the central volume form; Navier-Stokes with BR1, BR2 and the interior penalty,
+    and BR1 on the deformed box."""
     from paper_2206_09733_amd import dgsem
     out = {"workload": "Euler Taylor-Green vortex Ma 0.1, 32^3 hex undeformed, N=4, Roe faces, RK3 CFL 0.5, "
                        "plain (central) volume form"}
-    for nodes, Re in (("gauss", 0.0), ("lobatto", 0.0), ("gauss", 1600.0), ("lobatto", 1600.0)):
+    for nodes, Re, visc, deform in (("gauss", 0.0, "br1", False), ("lobatto", 0.0, "br1", False),
+                                    ("gauss", 1600.0, "br1", False), ("lobatto", 1600.0, "br1", False),
+                                    ("gauss", 1600.0, "br2", False), ("gauss", 1600.0, "ip", False),
+                                    ("gauss", 1600.0, "br1", True)):
         key = nodes if Re == 0.0 else f"{nodes}_navier_stokes_re1600"
-        s = dgsem.Solver(ex=32, N=4, Ma=0.1, Re=Re, vol="central", surf="roe", nodes=nodes)
+        key += "" if visc == "br1" else f"_{visc}"
+        key += "_deformed" if deform else ""
+        s = dgsem.Solver(ex=32, N=4, Ma=0.1, Re=Re, vol="central", surf="roe", nodes=nodes, visc=visc,
+                         deform=deform)
         s.set_ic("tgv")
         dt = s.suggest_dt(0.5)
         s.rk_step(dt, warmup)
@@ -254,10 +261,13 @@ def run_svv(steps, warmup, plain_ms):
            "svv_kernel_pair_GB_s": round(algorithmic_bytes_svv(s.nodes) / pair_s / 1e9, 1),
            "state_finite": d["nonfinite"] == 0}
     s.close()
-    # the explicit LES closures on the same workload: Smagorinsky's eddy viscosity (C_s 0.17) in
-    # place of the constant one, filtered (SVV-Smagorinsky) and unfiltered (plain Smagorinsky)
-    for name, kernel, cut in (("svv_smagorinsky", "maday", 2), ("smagorinsky", "tadmor", -1)):
-        s = dgsem.Solver(**WORKLOAD, les_cs=0.17, svv_kernel=kernel, svv_cutoff=cut)
+    # the explicit LES closures on the same workload: the model's eddy viscosity in place of the
+    # constant one, filtered (SVV-Smagorinsky) and unfiltered (the plain models), with the models'
+    # usual constants (C_s 0.17, C_w 0.5, Vreman's c 0.07)
+    for name, kernel, cut, model, cs in (("svv_smagorinsky", "maday", 2, "smagorinsky", 0.17),
+                                         ("smagorinsky", "tadmor", -1, "smagorinsky", 0.17),
+                                         ("wale", "tadmor", -1, "wale", 0.5), ("vreman", "tadmor", -1, "vreman", 0.07)):
+        s = dgsem.Solver(**WORKLOAD, les_cs=cs, les_model=model, svv_kernel=kernel, svv_cutoff=cut)
         s.set_ic("tgv")
         s.rk_step(dt, warmup)
         ev_ms, _, _ = timed_steps(s, dt, steps, profile=False)

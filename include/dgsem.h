@@ -58,7 +58,7 @@ enum { DG_DEFORM_NONE = 0, DG_DEFORM_SINSIN = 1 };
  * (every split form, every viscous flux, mixed orders, FP32-bulk), or Gauss-Legendre (more
  * accurate; no boundary nodes, so the plain weak form with face traces interpolated to the
  * element boundaries: uniform-order boxes, undeformed or deformed, FP64, volume flux
- * DG_VOL_CENTRAL, any surface flux, BR1 viscous terms).  On Gauss-Legendre points the map and
+ * DG_VOL_CENTRAL, any surface flux, every viscous flux).  On Gauss-Legendre points the map and
  * its metric terms are those of the Lobatto grid of the same order (isoparametric there, curl
  * form there) evaluated at the Gauss points, and each face takes the metric of the element on
  * its -xi side interpolated to the face: a uniform state stays steady on curvilinear meshes.
@@ -121,6 +121,10 @@ typedef struct {
  *   IP   symmetric interior penalty: the same with the broken gradients, plus the penalty
  *        sigma F_v(v_mean, [g] n^) . S, sigma = visc_eta (N+1)^2 / h, h = 2 min(J_-, J_+)/|S|
  *        (visc_eta = 0: 1).
+ * On Gauss-Legendre points the values on a face are traces (sum_i l_i(+-1) along the line): the
+ * broken gradient's, the lift's (of g* - g(+-1), with g(+-1) the trace of the element's
+ * interpolant of g, the split of BR1's weak-form gradient that Gauss quadrature makes exact),
+ * U's and J's.
  * The choice is this library's reading: the paper names the three fluxes, not their constants. */
 enum { DG_VISC_BR1 = 0, DG_VISC_BR2 = 1, DG_VISC_IP = 2 };
 

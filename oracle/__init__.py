@@ -49,6 +49,8 @@ def _lib(precision="fp64"):
                    "orc_gradients", "orc_diagnostics"):
             getattr(L, fn).argtypes = [ctypes.c_void_p, _dp]
         L.orc_get_metrics.argtypes = [ctypes.c_void_p, _dp, _dp]
+        L.orc_gauss_gradient_parts.argtypes = [ctypes.c_void_p, _dp, _dp]
+        L.orc_gauss_face_viscous.argtypes = [ctypes.c_void_p, _dp]
         L.orc_set_ic.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp]
         L.orc_rk3.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_int]
         L.orc_rk.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_int]
@@ -258,6 +260,7 @@ class OracleSolver:
                  surf="roe", precision="fp64", visc="br1", visc_eta=0.0, nodes="lobatto"):
         ey = ex if ey is None else ey
         ez = ex if ez is None else ez
+        self.N = int(N)
         if hi is None:
             hi = (2 * np.pi,) * 3
         self.L = _lib(precision)
@@ -335,6 +338,23 @@ class OracleSolver:
         G = np.zeros(12 * self.nodes)
         self.L.orc_gradients(self.h, _ptr(G))
         return G
+
+    def gauss_gradient_parts(self):
+        """Gauss-Legendre meshes: (broken gradient, sum of the six face lifts) of g = (v, T) at
+        every node, in the layout of gradients(); their sum is the BR1 gradient."""
+        Gb, Gl = np.zeros(12 * self.nodes), np.zeros(12 * self.nodes)
+        if self.L.orc_gauss_gradient_parts(self.h, _ptr(Gb), _ptr(Gl)):
+            raise ValueError("not a Gauss-Legendre solver")
+        return Gb, Gl
+
+    def gauss_face_viscous(self):
+        """Gauss-Legendre Navier-Stokes meshes: the face viscous flux of the current state,
+        [E][6 faces][5][nf], f = 2 d + side, face point p + n r."""
+        n = self.N + 1
+        F = np.zeros(self.E * 6 * 5 * n * n)
+        if self.L.orc_gauss_face_viscous(self.h, _ptr(F)):
+            raise ValueError("not a Gauss-Legendre Navier-Stokes solver")
+        return F.reshape(self.E, 6, 5, n * n)
 
     def rk3(self, dt, nsteps):
         self.L.orc_rk3(self.h, float(dt), int(nsteps))

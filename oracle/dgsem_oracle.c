@@ -30,7 +30,8 @@
  *     p-adaptation"): interpolate both traces to the finer face grid, flux there, L2-project
  *     back with exactly integrated matrices;
  *   - on Gauss-Legendre nodes (the section's other quadrature), the plain weak form with
- *     interpolated face traces, for the Euler equations on uniform-order affine boxes;
+ *     interpolated face traces on uniform-order boxes (affine or deformed), with BR1, BR2 or
+ *     the interior penalty for the viscous terms;
  *   - Williamson's low-storage RK3 and Carpenter-Kennedy's low-storage RK4 (section "Time
  *     advancement");
  *   - entropy S=-rho*s, s=ln p - gamma ln rho and w=dS/du (section "Shock capturing",
@@ -1413,6 +1414,170 @@ static void compute_gradients_gauss(orc_solver* s, const real* U, real* Gout) {
   }
 }
 
+/* 7c. BR2 and the symmetric interior penalty on Gauss-Legendre points.  Gauss quadrature is
+ *     exact to degree 2N-1, so integrating by parts splits the weak derivative of 7b into the
+ *     element's own (broken) derivative and, per face, the lift of g* - g(+-1), where
+ *     g(+-1) = sum_j l_j(+-1) g_j is the trace of the element's interpolant of g:
+ *       (delta_d g)_i = sum_m D_im g_m + (l_i(+1) (g*(+d) - g(+1)) - l_i(-1) (g*(-d) - g(-1))) / w_i.
+ *     On face (d, side), BR2 takes the trace of the broken gradient plus eta times the trace of
+ *     that face's lift alone; the interior penalty takes the trace of the broken gradient and
+ *     adds its penalty (7, face_viscous_flux) with [g] and the mean velocity from g of the two
+ *     interpolated traces of U, and h = 2 min(J_L, J_R)/|S| from the two traces of J.  On the
+ *     box's smooth maps the two traces of J agree to interpolation error, so taking the smaller
+ *     one is parity unpinned; the rest of 7c is pinned. */
+static void gauss_broken_gradient(const orc_solver* s, const real* U, int e, const int ii[3], real gr[12]) {
+  const int N = s->N[e][0], n = N + 1;
+  const gll_t* T = &s->T[N];
+  long q = node_of(s, e, ii);
+  for (int t = 0; t < 12; t++) gr[t] = 0;
+  for (int d = 0; d < 3; d++) {
+    real a[4] = {0, 0, 0, 0};
+    int jj[3] = {ii[0], ii[1], ii[2]};
+    for (int m = 0; m < n; m++) {
+      jj[d] = m;
+      real um[5], gm[4];
+      load5(s, U, e, node_of(s, e, jj), um);
+      gvars(um, s->gamma, gm);
+      for (int c = 0; c < 4; c++) a[c] += T->D[ii[d]][m] * gm[c];
+    }
+    real nv[3];
+    load_ja(s, e, q, d, nv);
+    for (int c = 0; c < 4; c++)
+      for (int x = 0; x < 3; x++) gr[3 * c + x] += nv[x] * a[c];
+  }
+  real Jq = s->J[s->off[e] + q];
+  for (int t = 0; t < 12; t++) gr[t] /= Jq;
+}
+
+/* g* - g(side) on face (d, side) of element e at face point (p, r): the jump that face lifts */
+static void gauss_face_jump(const orc_solver* s, const real* U, int e, int d, int side, int p, int r, real jump[4]) {
+  const int N = s->N[e][0], n = N + 1;
+  const gll_t* T = &s->T[N];
+  int ta, tb;
+  face_dirs(d, &ta, &tb);
+  int ne = s->nbr[6 * e + 2 * d + side];
+  real uo[5], un[5], go[4], gn[4], gt[4] = {0, 0, 0, 0};
+  gauss_trace(s, U + s->off[e] * 5, 5, e, d, side, p, r, uo);
+  gauss_trace(s, U + s->off[ne] * 5, 5, ne, d, 1 - side, p, r, un);
+  gvars(uo, s->gamma, go);
+  gvars(un, s->gamma, gn);
+  for (int i = 0; i < n; i++) {
+    int ii[3];
+    ii[d] = i; ii[ta] = p; ii[tb] = r;
+    real ui[5], gi[4];
+    load5(s, U, e, node_of(s, e, ii), ui);
+    gvars(ui, s->gamma, gi);
+    for (int c = 0; c < 4; c++) gt[c] += T->lb[side][i] * gi[c];
+  }
+  for (int c = 0; c < 4; c++) jump[c] = (go[c] + gn[c]) / 2 - gt[c];
+}
+
+/* fac times the lift of the jump of face (d, side), at node ii of the line through the face
+ * point, added to the gradient gr */
+static void gauss_add_lift(const orc_solver* s, int e, const int ii[3], int d, int side, const real jump[4], real fac,
+                           real gr[12]) {
+  const gll_t* T = &s->T[s->N[e][0]];
+  long q = node_of(s, e, ii);
+  real l = fac * T->lb[side][ii[d]] / T->w[ii[d]];
+  if (!side) l = -l;
+  real nv[3];
+  load_ja(s, e, q, d, nv);
+  real Jq = s->J[s->off[e] + q];
+  for (int c = 0; c < 4; c++)
+    for (int x = 0; x < 3; x++) gr[3 * c + x] += l * nv[x] * jump[c] / Jq;
+}
+
+/* BR2 (br2 = 1) or interior-penalty (br2 = 0) gradient of element e on its face (d, side) at
+ * face point (p, r) */
+static void gauss_face_gradient(const orc_solver* s, const real* U, int e, int d, int side, int p, int r, int br2,
+                                real eta, real gr[12]) {
+  const int N = s->N[e][0], n = N + 1;
+  const gll_t* T = &s->T[N];
+  int ta, tb;
+  face_dirs(d, &ta, &tb);
+  real jump[4];
+  if (br2) gauss_face_jump(s, U, e, d, side, p, r, jump);
+  for (int t = 0; t < 12; t++) gr[t] = 0;
+  for (int i = 0; i < n; i++) {
+    int ii[3];
+    ii[d] = i; ii[ta] = p; ii[tb] = r;
+    real gb[12];
+    gauss_broken_gradient(s, U, e, ii, gb);
+    if (br2) gauss_add_lift(s, e, ii, d, side, jump, eta, gb);
+    for (int t = 0; t < 12; t++) gr[t] += T->lb[side][i] * gb[t];
+  }
+}
+
+/* the traces uL, uR at face point (p, r) of the face between L (its +d face) and its neighbour
+ * Rr, and the owner L's metric Ja^d interpolated there, the face's scaled normal S */
+static void gauss_face_state(const orc_solver* s, const real* U, int L, int Rr, int d, int p, int r, real uL[5],
+                             real uR[5], real S[3]) {
+  const int n = s->N[L][0] + 1;
+  const gll_t* T = &s->T[s->N[L][0]];
+  int ta, tb;
+  face_dirs(d, &ta, &tb);
+  for (int v = 0; v < 5; v++) uL[v] = uR[v] = 0;
+  S[0] = S[1] = S[2] = 0;
+  for (int i = 0; i < n; i++) {
+    int ii[3];
+    ii[d] = i; ii[ta] = p; ii[tb] = r;
+    real a[5], b[5], ja[3];
+    long qL = node_of(s, L, ii), qR = node_of(s, Rr, ii);
+    load5(s, U, L, qL, a);
+    load5(s, U, Rr, qR, b);
+    load_ja(s, L, qL, d, ja);
+    for (int v = 0; v < 5; v++) {
+      uL[v] += T->lb[1][i] * a[v];
+      uR[v] += T->lb[0][i] * b[v];
+    }
+    for (int c = 0; c < 3; c++) S[c] += T->lb[1][i] * ja[c];
+  }
+}
+
+/* the face viscous flux along S at face point (p, r) between L and Rr, from the traces uL, uR
+ * (BR1: the two sides' fluxes from their traces of the BR1 gradient Gall; BR2 and the interior
+ * penalty: from their face gradients of 7c, plus the penalty) */
+static void gauss_face_viscous(const orc_solver* s, const real* U, const real* Gall, int L, int Rr, int d, int p, int r,
+                               const real uL[5], const real uR[5], const real S[3], real Fst[5]) {
+  real qL[12], qR[12], Fa[15], Fb[15];
+  if (s->visc_flux == ORC_VISC_BR1) {
+    gauss_trace(s, Gall + s->off[L] * 12, 12, L, d, 1, p, r, qL);
+    gauss_trace(s, Gall + s->off[Rr] * 12, 12, Rr, d, 0, p, r, qR);
+  } else {
+    const int br2 = s->visc_flux == ORC_VISC_BR2;
+    gauss_face_gradient(s, U, L, d, 1, p, r, br2, s->visc_eta, qL);
+    gauss_face_gradient(s, U, Rr, d, 0, p, r, br2, s->visc_eta, qR);
+  }
+  viscous_flux(uL, qL, s->gamma, s->mu, s->kappa, Fa);
+  viscous_flux(uR, qR, s->gamma, s->mu, s->kappa, Fb);
+  for (int v = 0; v < 5; v++)
+    Fst[v] = (S[0] * (Fa[v] + Fb[v]) + S[1] * (Fa[5 + v] + Fb[5 + v]) + S[2] * (Fa[10 + v] + Fb[10 + v])) / 2;
+  if (s->visc_flux == ORC_VISC_IP) {
+    const int N = s->N[L][0], n = N + 1;
+    const gll_t* T = &s->T[N];
+    int ta, tb;
+    face_dirs(d, &ta, &tb);
+    real JL = 0, JR = 0;
+    for (int i = 0; i < n; i++) {
+      int ii[3];
+      ii[d] = i; ii[ta] = p; ii[tb] = r;
+      JL += T->lb[1][i] * s->J[s->off[L] + node_of(s, L, ii)];
+      JR += T->lb[0][i] * s->J[s->off[Rr] + node_of(s, Rr, ii)];
+    }
+    real gL[4], gR[4], vm[3], gr[12], Fv[15];
+    gvars(uL, s->gamma, gL);
+    gvars(uR, s->gamma, gR);
+    real area = RSQRT(S[0] * S[0] + S[1] * S[1] + S[2] * S[2]);
+    real h = 2 * (JL < JR ? JL : JR) / area;
+    real sigma = s->visc_eta * (real)(n * n) / h;
+    for (int c = 0; c < 3; c++) vm[c] = (gL[c] + gR[c]) / 2;
+    for (int c = 0; c < 4; c++)
+      for (int x = 0; x < 3; x++) gr[3 * c + x] = sigma * (gR[c] - gL[c]) * S[x] / area;
+    viscous_flux_v(vm, gr, s->mu, s->kappa, Fv);
+    for (int v = 0; v < 5; v++) Fst[v] += S[0] * Fv[v] + S[1] * Fv[5 + v] + S[2] * Fv[10 + v];
+  }
+}
+
 static void element_residual_gauss(const orc_solver* s, const real* U, const real* Gall, int e, real* R) {
   const int N = s->N[e][0], n = N + 1, nn = n * n * n;
   const gll_t* T = &s->T[N];
@@ -1426,32 +1591,14 @@ static void element_residual_gauss(const orc_solver* s, const real* U, const rea
       int Rr = s->nbr[6 * L + 2 * d + 1];
       for (int r = 0; r < n; r++)
         for (int p = 0; p < n; p++) {
-          real uL[5] = {0, 0, 0, 0, 0}, uR[5] = {0, 0, 0, 0, 0}, S[3] = {0, 0, 0};
-          for (int i = 0; i < n; i++) {
-            int ii[3];
-            ii[d] = i; ii[ta] = p; ii[tb] = r;
-            real a[5], b[5], ja[3];
-            long qL = node_of(s, L, ii), qR = node_of(s, Rr, ii);
-            load5(s, U, L, qL, a);
-            load5(s, U, Rr, qR, b);
-            load_ja(s, L, qL, d, ja);
-            for (int v = 0; v < 5; v++) {
-              uL[v] += T->lb[1][i] * a[v];
-              uR[v] += T->lb[0][i] * b[v];
-            }
-            for (int c = 0; c < 3; c++) S[c] += T->lb[1][i] * ja[c];
-          }
+          real uL[5], uR[5], S[3];
+          gauss_face_state(s, U, L, Rr, d, p, r, uL, uR, S);
           real F[5];
           surface_flux(s, uL, uR, S, F);
           if (s->viscous) {
-            /* BR1: average of the two sides' viscous fluxes from their traces of U and grad g */
-            real qL[12], qR[12], Fa[15], Fb[15];
-            gauss_trace(s, Gall + s->off[L] * 12, 12, L, d, 1, p, r, qL);
-            gauss_trace(s, Gall + s->off[Rr] * 12, 12, Rr, d, 0, p, r, qR);
-            viscous_flux(uL, qL, s->gamma, s->mu, s->kappa, Fa);
-            viscous_flux(uR, qR, s->gamma, s->mu, s->kappa, Fb);
-            for (int v = 0; v < 5; v++)
-              F[v] -= (S[0] * (Fa[v] + Fb[v]) + S[1] * (Fa[5 + v] + Fb[5 + v]) + S[2] * (Fa[10 + v] + Fb[10 + v])) / 2;
+            real Fst[5];
+            gauss_face_viscous(s, U, Gall, L, Rr, d, p, r, uL, uR, S, Fst);
+            for (int v = 0; v < 5; v++) F[v] -= Fst[v];
           }
           for (int v = 0; v < 5; v++) Ff[2 * d + side][v][p + n * r] = F[v];
         }
@@ -2141,6 +2288,61 @@ int orc_two_point_central(const double* UL, const double* UR, const double* n, d
   to_dbl(f, F, 5);
   return 0;
 }
+/* Gauss-Legendre meshes: the broken gradient Gb and the sum Gl of the six face lifts of 7c at
+ * every node (layout of orc_gradients); Gb + Gl is the BR1 gradient of 7b */
+int orc_gauss_gradient_parts(const orc_solver* s, double* Gb, double* Gl) {
+  if (!s || !s->gauss) return -1;
+  for (int e = 0; e < s->E; e++) {
+    const int N = s->N[e][0], n = N + 1, nn = n * n * n;
+    for (int k = 0; k < n; k++)
+      for (int j = 0; j < n; j++)
+        for (int i = 0; i < n; i++) {
+          int ii[3] = {i, j, k};
+          long q = node_of(s, e, ii);
+          real gb[12], gl[12] = {0};
+          gauss_broken_gradient(s, s->U, e, ii, gb);
+          for (int d = 0; d < 3; d++) {
+            int ta, tb;
+            face_dirs(d, &ta, &tb);
+            for (int side = 0; side < 2; side++) {
+              real jump[4];
+              gauss_face_jump(s, s->U, e, d, side, ii[ta], ii[tb], jump);
+              gauss_add_lift(s, e, ii, d, side, jump, 1, gl);
+            }
+          }
+          for (int t = 0; t < 12; t++) {
+            Gb[s->off[e] * 12 + (long)t * nn + q] = (double)gb[t];
+            Gl[s->off[e] * 12 + (long)t * nn + q] = (double)gl[t];
+          }
+        }
+  }
+  return 0;
+}
+
+/* Gauss-Legendre Navier-Stokes meshes: the face viscous flux of the current state on every face
+ * of every element, F[((e * 6 + f) * 5 + v) * nf + q] for face f = 2 d + side and face point
+ * q = p + n r (the flux along the owner's scaled normal; both elements of a face hold the same) */
+int orc_gauss_face_viscous(orc_solver* s, double* F) {
+  if (!s || !s->gauss || !s->viscous) return -1;
+  compute_gradients_gauss(s, s->U, s->G);
+  for (int e = 0; e < s->E; e++) {
+    const int n = s->N[e][0] + 1, nf = n * n;
+    for (int d = 0; d < 3; d++)
+      for (int side = 0; side < 2; side++) {
+        int L = side ? e : s->nbr[6 * e + 2 * d];
+        int Rr = s->nbr[6 * L + 2 * d + 1];
+        for (int r = 0; r < n; r++)
+          for (int p = 0; p < n; p++) {
+            real uL[5], uR[5], S[3], Fst[5];
+            gauss_face_state(s, s->U, L, Rr, d, p, r, uL, uR, S);
+            gauss_face_viscous(s, s->U, s->G, L, Rr, d, p, r, uL, uR, S, Fst);
+            for (int v = 0; v < 5; v++) F[(((long)e * 6 + 2 * d + side) * 5 + v) * nf + p + n * r] = (double)Fst[v];
+          }
+      }
+  }
+  return 0;
+}
+
 int orc_set_viscous_flux(orc_solver* s, int kind, double eta) {
   if (!s || kind < ORC_VISC_BR1 || kind > ORC_VISC_IP || !(eta >= 0)) return -1;
   s->visc_flux = kind;

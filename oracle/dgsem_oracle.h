@@ -55,14 +55,20 @@ orc_solver* orc_create(int ex, int ey, int ez, const double* lo, const double* h
                        double amp, int n_uniform, const int* orders, double gamma, double Pr,
                        double Ma, double Re, int vol_flux, int surf_flux);
 /* The same box (uniform order N, optionally deformed) on Gauss-Legendre nodes: plain (non-split)
- * weak form, face traces interpolated to the element boundaries; Re > 0 adds BR1 viscous terms.
- * The map and its metric terms are the Lobatto grid's, evaluated at the Gauss points. */
+ * weak form, face traces interpolated to the element boundaries; Re > 0 adds viscous terms (BR1,
+ * or BR2 / the interior penalty through orc_set_viscous_flux).  The map and its metric terms are
+ * the Lobatto grid's, evaluated at the Gauss points. */
 orc_solver* orc_create_gauss(int ex, int ey, int ez, const double* lo, const double* hi, int deform, double amp,
                              int N, double gamma, double Pr, double Ma, double Re, int surf_flux);
 void orc_destroy(orc_solver* s);
 /* Face viscous flux: BR1 (default), BR2 with lifting factor eta, or the symmetric interior
  * penalty with penalty factor eta (sigma = eta (N+1)^2 / h); eta = 0 takes 2 (BR2), 1 (IP). */
 int orc_set_viscous_flux(orc_solver* s, int kind, double eta);
+/* Gauss-Legendre meshes: the broken gradient of g = (v, T) and the sum of its six face lifts at
+ * every node (layout of orc_gradients), whose sum is the BR1 gradient; and (Navier-Stokes) the
+ * face viscous flux of the current state, F[((e*6 + f)*5 + v)*nf + q], f = 2 d + side. */
+int orc_gauss_gradient_parts(const orc_solver* s, double* Gb, double* Gl);
+int orc_gauss_face_viscous(orc_solver* s, double* F);
 long orc_num_nodes(const orc_solver* s);
 int orc_num_elements(const orc_solver* s);
 int orc_elem_info(const orc_solver* s, int e, int* n3, long* off);

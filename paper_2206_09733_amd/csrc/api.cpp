@@ -562,10 +562,9 @@ int dg_solver_create(const dg_mesh* m, const dg_physics* p, dg_solver** out) try
                                  "central surface fluxes; the others are evaluated in FP64");
   if (m->mixed && p->Re > 0)
     return fail(DG_EUNSUPPORTED, "mixed-order meshes are evaluated for the Euler equations (Re <= 0)");
-  if (m->gauss && (p->precision != DG_FP64 || p->vol_flux != DG_VOL_CENTRAL ||
-                   (p->Re > 0 && p->visc_flux != DG_VISC_BR1)))
+  if (m->gauss && (p->precision != DG_FP64 || p->vol_flux != DG_VOL_CENTRAL))
     return fail(DG_EUNSUPPORTED, "Gauss-Legendre nodes: FP64, volume flux DG_VOL_CENTRAL (the plain weak "
-                                 "form), BR1 viscous terms");
+                                 "form)");
   if (!(p->svv_mu >= 0) || !std::isfinite(p->svv_mu)) return fail(DG_EINVAL, "svv_mu must be >= 0");
   if (!(p->les_cs >= 0) || !std::isfinite(p->les_cs)) return fail(DG_EINVAL, "les_cs must be >= 0");
   if (p->les_cs > 0 && p->les_model != DG_LES_SMAGORINSKY && p->les_model != DG_LES_WALE &&

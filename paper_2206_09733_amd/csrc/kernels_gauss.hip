@@ -1,6 +1,7 @@
 // kernels_gauss.hip -- DGSEM on Gauss-Legendre nodes, the other quadrature that section "Spatial
-// discretisation" allows: the plain weak form (no boundary nodes, so no split form), with BR1
-// viscous terms for Navier-Stokes, on uniform-order boxes (undeformed or deformed), FP64.
+// discretisation" allows: the plain weak form (no boundary nodes, so no split form), with BR1,
+// BR2 or interior-penalty viscous terms for Navier-Stokes, on uniform-order boxes (undeformed or
+// deformed), FP64.
 //
 // Two launches per RK stage (three with viscosity: gauss_grad_kernel between them).
 // gauss_trace_kernel interpolates each element's state to its six
@@ -51,14 +52,22 @@ __global__ void __launch_bounds__(nthreads_for(N)) gauss_trace_kernel(View v, in
   }
 }
 
-// BR1 on Gauss points (Navier-Stokes): the weak-form gradient of g = (v, T) with the face values
-// g* = (g(U_L) + g(U_R)) / 2 of both sides' traces,
+// Viscous face fluxes on Gauss points (Navier-Stokes), XV = 0 BR1, 1 BR2, 2 interior penalty.
+// BR1's gradient of g = (v, T) is the weak form with the face values g* = (g(U_L) + g(U_R)) / 2
+// of both sides' traces,
 //   J grad g = sum_d Ja^d [ sum_m Dw_im g_m + (l_i(+1) g*(+d) - l_i(-1) g*(-d)) / w_i ]
-// (the node's metric outside the weak derivative, as in the Lobatto BR1 gradient), written to
-// Q[E][12][nn], and on the six faces the contravariant viscous flux of this side's traces,
-// F_v(U trace, sum_i l_i grad g_i) . S with the owner's face metric S (Sf), into
-// Fvf[E][6][4][nf]; the stage kernel averages the two sides.
-template <int N>
+// (the node's metric outside the weak derivative, as in the Lobatto BR1 gradient).  Gauss
+// quadrature integrates that weak derivative exactly, so it equals the broken (strong) derivative
+// sum_m D_im g_m plus, per face, the lift of g* - g(+-1), g(+-1) = sum_j l_j(+-1) g_j.  On each
+// of the six faces the kernel writes this side's contravariant viscous flux F_v(U trace, face
+// gradient) . S with the owner's face metric S (Sf) into Fvf[E][6][4][nf]; the stage kernel
+// averages the two sides and forms the BR1 gradient again for its volume term.  The face gradient
+// is the trace of the BR1 gradient (BR1), the trace of the broken gradient plus eta times the
+// trace of this face's lift (BR2), or the trace of the broken gradient (interior penalty, whose
+// penalty sigma F_v(v_mean, [g] n^) . S, sigma = eta (N+1)^2 |S| / (2 min(J_L, J_R)), with g of
+// both traces of U and J_L, J_R the two traces of J, each side adds to its flux, so the average
+// holds it once; both sides evaluate it from the same values in the same order).
+template <int N, int XV>
 __global__ void __launch_bounds__(nthreads_for(N)) gauss_grad_kernel(View v, int cur) {
   constexpr int n = N + 1, nn = n * n * n, nf = n * n, NT = nthreads_for(N);
   const int e = block_element(v.E);
@@ -68,10 +77,11 @@ __global__ void __launch_bounds__(nthreads_for(N)) gauss_grad_kernel(View v, int
   __shared__ double sDw[n * n], sw[n], sl[2][n];
   __shared__ double sG[4][nn];
   __shared__ double sGs[6][4][nf];  // face values g*
-  __shared__ double sQ[12][nn];
+  __shared__ double sQ[12][nn];     // BR1: the gradient; BR2, IP: the broken gradient
   for (int x = t; x < n * n; x += NT) {
     const int i = x / n, m = x - i * n;
-    sDw[x] = -v.tab[2 * n + m * n + i] * v.tab[n + m] / v.tab[n + i];
+    // BR1: the weak derivative matrix Dw; BR2, IP: the derivative matrix D itself
+    sDw[x] = XV == 0 ? -v.tab[2 * n + m * n + i] * v.tab[n + m] / v.tab[n + i] : v.tab[2 * n + x];
   }
   if (t < n) sw[t] = v.tab[n + t];
   if (t < 2 * n) sl[t / n][t % n] = v.tab[gauss_tab_ends(n) + t];
@@ -114,7 +124,7 @@ __global__ void __launch_bounds__(nthreads_for(N)) gauss_grad_kernel(View v, int
       const double lp = sl[1][id] / sw[id], lm = sl[0][id] / sw[id];
 #pragma unroll
       for (int c = 0; c < 4; c++) {
-        double acc = lp * sGs[2 * d + 1][c][qd] - lm * sGs[2 * d][c][qd];
+        double acc = XV == 0 ? lp * sGs[2 * d + 1][c][qd] - lm * sGs[2 * d][c][qd] : 0.0;
 #pragma unroll
         for (int m = 0; m < n; m++) acc += sDw[id * n + m] * sG[c][b0 + m * stride];
         a[d][c] = acc;
@@ -137,6 +147,58 @@ __global__ void __launch_bounds__(nthreads_for(N)) gauss_grad_kernel(View v, int
     const int f = x / nf, q = x - f * nf;
     const int d = f >> 1, side = f & 1;
     const int p = q % n, r = q / n;
+    const long ne = v.nbr[e * 6 + f];
+    const long owner = side ? e : ne;
+    const double* So = v.Sf + (owner * 9 + 3 * d) * nf;
+    const double s1 = So[q], s2 = So[nf + q], s3 = So[2 * nf + q];
+    // the scheme's own face terms first, so that their operands are retired before the twelve
+    // gradient traces are formed
+    double Fo[4] = {0.0, 0.0, 0.0, 0.0}, jump[4], M[3] = {0.0, 0.0, 0.0};
+    if (XV == 1) {  // BR2: the jump g* - g(side) and the trace of its lift's metric factor
+#pragma unroll
+      for (int c = 0; c < 4; c++) jump[c] = sGs[f][c][q];
+#pragma unroll 1
+      for (int i = 0; i < n; i++) {
+        const int node = face_node<n>(d, i, p, r);
+        const double l = sl[side][i];
+#pragma unroll
+        for (int c = 0; c < 4; c++) jump[c] -= l * sG[c][node];
+        // l_i(side) (+-l_i(side) / w_i) Ja^d_i / J_i
+        const double wl = (side ? l : -l) * l / sw[i] * v.invJ[base + node];
+#pragma unroll
+        for (int y = 0; y < 3; y++) M[y] += wl * v.Ja[base * 9 + (3 * d + y) * nn + node];
+      }
+    }
+    if (XV == 2) {  // interior penalty, from the face's minus (L) and plus (R) sides
+      const long eL = side ? e : ne, eR = side ? ne : e;
+      const double* TL = v.Tr + (eL * 6 + 2 * d + 1) * 5 * nf;
+      const double* TR = v.Tr + (eR * 6 + 2 * d) * 5 * nf;
+      double uL[5], uR[5], gL[4], gR[4], JL = 0.0, JR = 0.0;
+#pragma unroll
+      for (int c = 0; c < 5; c++) {
+        uL[c] = TL[c * nf + q];
+        uR[c] = TR[c * nf + q];
+      }
+#pragma unroll 1
+      for (int i = 0; i < n; i++) {
+        const int node = face_node<n>(d, i, p, r);
+        JL += sl[1][i] * v.J[eL * nn + node];
+        JR += sl[0][i] * v.J[eR * nn + node];
+      }
+      gvars(uL, v.gamma, 0.0, gL);
+      gvars(uR, v.gamma, 0.0, gR);
+      const double area = sqrt(s1 * s1 + s2 * s2 + s3 * s3);
+      const double sigma = v.visc_eta * (double)(n * n) * area / (2.0 * (JL < JR ? JL : JR));
+      const double nh[3] = {s1 / area, s2 / area, s3 / area};
+      double gp[4][3], Fp[3][4];
+#pragma unroll
+      for (int c = 0; c < 4; c++)
+#pragma unroll
+        for (int y = 0; y < 3; y++) gp[c][y] = sigma * (gR[c] - gL[c]) * nh[y];
+      viscous_flux_g(0.5 * (gL[0] + gR[0]), 0.5 * (gL[1] + gR[1]), 0.5 * (gL[2] + gR[2]), gp, v.mu, v.kappa, Fp);
+#pragma unroll
+      for (int c = 0; c < 4; c++) Fo[c] = s1 * Fp[0][c] + s2 * Fp[1][c] + s3 * Fp[2][c];
+    }
     double gr[4][3];
 #pragma unroll
     for (int k = 0; k < 12; k++) {
@@ -145,6 +207,12 @@ __global__ void __launch_bounds__(nthreads_for(N)) gauss_grad_kernel(View v, int
       for (int i = 0; i < n; i++) acc += sl[side][i] * sQ[k][face_node<n>(d, i, p, r)];
       gr[k / 3][k % 3] = acc;
     }
+    if (XV == 1) {  // + eta times the trace of this face's lift
+#pragma unroll
+      for (int c = 0; c < 4; c++)
+#pragma unroll
+        for (int y = 0; y < 3; y++) gr[c][y] += v.visc_eta * M[y] * jump[c];
+    }
     const double* To = v.Tr + ((long)e * 6 + f) * 5 * nf;
     double uo[5], go[4];
 #pragma unroll
@@ -152,11 +220,11 @@ __global__ void __launch_bounds__(nthreads_for(N)) gauss_grad_kernel(View v, int
     gvars(uo, v.gamma, 0.0, go);
     double Fv[3][4];
     viscous_flux_g(go[0], go[1], go[2], gr, v.mu, v.kappa, Fv);
-    const long owner = side ? e : v.nbr[e * 6 + f];
-    const double* So = v.Sf + (owner * 9 + 3 * d) * nf;
-    const double s1 = So[q], s2 = So[nf + q], s3 = So[2 * nf + q];
 #pragma unroll
-    for (int c = 0; c < 4; c++) Fvf[(f * 4 + c) * nf + q] = s1 * Fv[0][c] + s2 * Fv[1][c] + s3 * Fv[2][c];
+    for (int c = 0; c < 4; c++) {
+      const double own = s1 * Fv[0][c] + s2 * Fv[1][c] + s3 * Fv[2][c];
+      Fvf[(f * 4 + c) * nf + q] = XV == 2 ? own + Fo[c] : own;
+    }
   }
 }
 
@@ -340,7 +408,12 @@ static hipError_t gauss_stage_n(const View& v, int cur, double dt, double a, dou
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   if (v.viscous) {
-    hipLaunchKernelGGL(gauss_grad_kernel<N>, grid, block, 0, st, v, cur);
+    if (v.visc_flux == 1)
+      hipLaunchKernelGGL((gauss_grad_kernel<N, 1>), grid, block, 0, st, v, cur);
+    else if (v.visc_flux == 2)
+      hipLaunchKernelGGL((gauss_grad_kernel<N, 2>), grid, block, 0, st, v, cur);
+    else
+      hipLaunchKernelGGL((gauss_grad_kernel<N, 0>), grid, block, 0, st, v, cur);
     err = hipGetLastError();
     if (err != hipSuccess) return err;
     if (v.surf >= 4)

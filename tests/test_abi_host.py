@@ -84,9 +84,13 @@ def test_gauss_legendre_limits(dg):
     d, _ = dg.box_desc(2, 2, 2, (0, 0, 0), (1, 1, 1), False, 0.0, 3, nodes="gauss")
     dg.check(L.dg_mesh_create_box(ctypes.byref(d), ctypes.byref(m)))
     s = ctypes.c_void_p()
-    for bad in (dict(vol="ec"), dict(vol="central", Re=100.0, visc="br2"), dict(vol="central", precision="fp32_bulk")):
+    for bad in (dict(vol="ec"), dict(vol="central", precision="fp32_bulk")):
         p = dg.physics(**bad)
         assert L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)) == dg.DG_EUNSUPPORTED, bad
+    for visc in ("br1", "br2", "ip"):
+        p = dg.physics(vol="central", Re=100.0, visc=visc)
+        dg.check(L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)))
+        L.dg_solver_destroy(s)
     for surf in dg.SURF:
         p = dg.physics(vol="central", surf=surf, Re=100.0 if surf == "roe" else 0.0)
         assert L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)) == dg.DG_OK

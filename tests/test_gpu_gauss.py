@@ -10,6 +10,9 @@ against the oracle's Gauss path.
   Lobatto errors at every order, as the paper states for these points.
 - The deformed box: residual parity at orders 1-7 (Euler and NS), geometry against the
   long-double oracle, the free stream, trajectories with conservation, spectral accuracy.
+- BR2 and the interior penalty on Gauss points (deformed box): residual parity at orders 1-7 with
+  the default and other factors, the schemes' face terms alone (residual minus BR1's residual),
+  RK3 trajectories with conservation.
 """
 import math
 import sys
@@ -284,3 +287,80 @@ def test_gauss_deformed_density_wave_accuracy(dg, orc):
     log(f"[deformed density wave t=0.5] gauss {gs} lobatto {ls}")
     assert np.all(gs < ls)
     assert np.all(gs[:-1] / gs[1:] > 4)
+
+
+XV_CASES = [(N, visc, 0.0) for N in range(1, 8) for visc in ("br2", "ip")] + \
+    [(3, "br2", 1.3), (5, "ip", 3.0)]
+
+
+@pytest.mark.parametrize("N,visc,eta", XV_CASES)
+def test_gauss_br2_ip_residual_parity(dg, orc, N, visc, eta):
+    """BR2 (the broken gradient's trace plus eta times the trace of the face's own lift) and the
+    interior penalty (the broken gradient's trace plus the penalty) on Gauss points."""
+    c = cfg(N=N, Re=100.0, deform=True, visc=visc, visc_eta=eta)
+    log(f"gauss {visc} residual N={N} eta={eta}")
+    U = perturbed(orc, c, seed=2100 + N)
+    o64, o80 = orc.OracleSolver(**c), orc.OracleSolver(**c, precision="fp80")
+    o64.set_state(U)
+    o80.set_state(U)
+    g = dg.Solver(**c)
+    g.set_state(U)
+    parity(f"gauss {visc} N={N} eta={eta}", g.residual(), o64.residual(), o80.residual(), 18, (N + 1) ** 3)
+    g.close()
+
+
+@pytest.mark.parametrize("N,visc", [(N, v) for N in (2, 4, 6) for v in ("br2", "ip")])
+def test_gauss_br2_ip_face_terms_alone(dg, orc, N, visc):
+    """The scheme's face terms by themselves: its residual minus BR1's, GPU against the oracle.
+    The difference carries the rounding of both full residuals, so the bar is the gate or 1e-15
+    of the full residual, whichever is larger."""
+    c = cfg(N=N, Re=100.0, deform=True)
+    U = perturbed(orc, c, seed=2200 + N)
+    res = {}
+    for kind in ("br1", visc):
+        cc = dict(c, visc=kind)
+        o64, o80 = orc.OracleSolver(**cc), orc.OracleSolver(**cc, precision="fp80")
+        o64.set_state(U)
+        o80.set_state(U)
+        g = dg.Solver(**cc)
+        g.set_state(U)
+        res[kind] = (g.residual(), o64.residual(), o80.residual())
+        g.close()
+    nn, E = (N + 1) ** 3, 18
+    G, A, B = ((res[visc][i] - res["br1"][i]).reshape(E, 5, nn) for i in range(3))
+    full = np.abs(res[visc][2].reshape(E, 5, nn)).max(axis=(0, 2))
+    sc = np.abs(B).max(axis=(0, 2))
+    e64, eg = np.abs(A - B).max(axis=(0, 2)), np.abs(G - B).max(axis=(0, 2))
+    floor = 1e-15 * full
+    log(f"[gauss {visc} part N={N}] |part|/|R| {sc[1:] / full[1:]} gpu-vs-fp80 {eg[1:] / sc[1:]} "
+        f"fp64-vs-fp80 {e64[1:] / sc[1:]}")
+    assert np.all(sc[1:] > 1e-3 * full[1:])  # the schemes differ
+    assert np.all(np.abs(G[:, 0]) <= floor[0] + GATE * e64[0])
+    assert np.all(eg[1:] <= np.maximum(GATE * e64[1:], floor[1:])), (eg, e64, floor)
+
+
+@pytest.mark.parametrize("visc", ["br2", "ip"])
+def test_gauss_br2_ip_trajectory_and_conservation(dg, orc, visc):
+    c = cfg(ex=3, ey=3, ez=3, N=4, Ma=0.4, Re=400.0, deform=True, visc=visc)
+    U0 = perturbed(orc, c, seed=41, amp=(0.01, 0.02, 0.01))
+    o, o80 = orc.OracleSolver(**c), orc.OracleSolver(**c, precision="fp80")
+    for s in (o, o80):
+        s.set_state(U0)
+    dt = o.suggest_dt(0.4)
+    o.rk(dt, 5, "rk3")
+    o80.rk(dt, 5, "rk3")
+    g = dg.Solver(**c)
+    g.set_state(U0)
+    d0 = g.diagnostics()
+    g.rk_step(dt, 5)
+    nn = 125
+    Ug, Uo, U80 = g.state(), o.state(), o80.state()
+    dd = lambda a, b: np.abs(a - b).reshape(27, 5, nn).max(axis=(0, 2))
+    sc = np.abs(U80).reshape(27, 5, nn).max(axis=(0, 2))
+    log(f"[gauss {visc} rk3] gpu-vs-fp80 {dd(Ug, U80) / sc} fp64-vs-fp80 {dd(Uo, U80) / sc}")
+    assert gate_ok(f"test_gauss_br2_ip_trajectory {visc}", dd(Ug, U80), dd(Uo, U80), sc, 1e-14), "parity gate"
+    d1 = g.diagnostics()
+    V = d0["volume"]
+    for k in ("mass_rho", "mass_rhou", "mass_rhov", "mass_rhow", "mass_rhoE"):
+        assert abs(d1[k] - d0[k]) / V < 1e-12 * max(1.0, abs(d0[k]) / V), k
+    g.close()
