@@ -119,7 +119,7 @@ struct dg_solver {
   double agraph_cfl[2] = {0.0, 0.0};
   dg::View* dev_view = nullptr;      // device copy of v (inside the caller's buffer)
   int scheme = DG_RK3_WILLIAMSON;    // time scheme of dg_rk_step
-  bool svv_on = false;               // spectral vanishing viscosity after every stage kernel
+  bool svv_on = false;               // spectral vanishing viscosity in every stage
   dg::SvvArgs svv{};
 };
 
@@ -248,6 +248,13 @@ hipError_t pre_stage(const dg_solver* s, int cur, hipStream_t st) {
   return hipSuccess;
 }
 
+// spectral vanishing viscosity on Navier-Stokes with the standard fluxes: the filtered flux of the
+// stage's input is formed first and the stage kernel adds it to the viscous flux (no correction
+// pass after it); otherwise the two SVV kernels correct the stage kernel's output
+bool svv_folded(const dg_solver* s) {
+  return s->svv_on && s->v.viscous && dg::flux_family(s->v.vol, s->v.surf) == 0;
+}
+
 hipError_t run_stage(dg_solver* s, double dt, double a, double b, int mode) {
   if (s->v.surf == DG_SURF_LF_GLOBAL) {
     hipError_t e = timed(s, DG_K_OTHER, [&] { return pre_stage(s, s->cur, s->stream); });
@@ -256,6 +263,13 @@ hipError_t run_stage(dg_solver* s, double dt, double a, double b, int mode) {
   if (s->v.viscous && !s->v.gauss) {  // (Gauss-Legendre solvers take their gradients in their stage launch)
     hipError_t e = timed(s, DG_K_GRADIENT, [&] { return dg::launch_gradient(s->v, s->cur, s->stream); });
     if (e != hipSuccess) return e;
+  }
+  if (svv_folded(s)) {
+    hipError_t e = timed(s, DG_K_OTHER, [&] { return dg::launch_svv_flux(s->v, s->cur, s->svv, s->stream); });
+    if (e != hipSuccess) return e;
+    dg::View vf = s->v;
+    vf.Fa = s->svv.Fa;
+    return timed(s, DG_K_STAGE, [&] { return dg::launch_stage(vf, s->cur, dt, a, b, mode, s->stream); });
   }
   hipError_t e = timed(s, DG_K_STAGE, [&] { return launch_stage_any(s, dt, a, b, mode); });
   if (e != hipSuccess || !s->svv_on) return e;
@@ -1279,8 +1293,15 @@ hipError_t batch_stage(dg_batch* b, const double* dts, int k, hipStream_t st) {
       e = dg::launch_stage_gauss(s->v, s->cur, dts[i], A, Bk, dg::kModeRK, st);
     } else {  // spectral vanishing viscosity: the solver's own stage sequence
       e = s->v.viscous ? dg::launch_gradient(s->v, s->cur, st) : hipSuccess;
-      if (e == hipSuccess) e = dg::launch_stage(s->v, s->cur, dts[i], A, Bk, dg::kModeRK, st);
-      if (e == hipSuccess) e = dg::launch_svv(s->v, s->cur, s->svv, dts[i], Bk, dg::kModeRK, st);
+      if (svv_folded(s)) {
+        if (e == hipSuccess) e = dg::launch_svv_flux(s->v, s->cur, s->svv, st);
+        dg::View vf = s->v;
+        vf.Fa = s->svv.Fa;
+        if (e == hipSuccess) e = dg::launch_stage(vf, s->cur, dts[i], A, Bk, dg::kModeRK, st);
+      } else {
+        if (e == hipSuccess) e = dg::launch_stage(s->v, s->cur, dts[i], A, Bk, dg::kModeRK, st);
+        if (e == hipSuccess) e = dg::launch_svv(s->v, s->cur, s->svv, dts[i], Bk, dg::kModeRK, st);
+      }
     }
     if (e != hipSuccess) return e;
   }

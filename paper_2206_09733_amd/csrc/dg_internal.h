@@ -91,6 +91,10 @@ struct View {
   // face fluxes of mixed-order meshes: [E][6 faces][6][49], rows 0-4 the numerical flux on the
   // element's face grid, row 5 its FP64 mass component (FP32-bulk)
   double* Fs;
+  // spectral vanishing viscosity folded into the Navier-Stokes stage kernel (set only in the View
+  // of that launch): the filtered contravariant flux [E][12][nn] of the stage's input state,
+  // index 4 d + c (c = momentum 1..3, energy), added to the viscous flux
+  const double* Fa;
 };
 
 // Several solvers of one order and precision advanced by one launch: workgroup b of the grid

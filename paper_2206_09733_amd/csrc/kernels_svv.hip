@@ -346,6 +346,26 @@ static hipError_t launch_svv_n(const View& v, int cur, const SvvArgs& a, double 
   return hipGetLastError();
 }
 
+template <int N>
+static hipError_t launch_svv_flux_n(const View& v, int cur, const SvvArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(svv_flux_kernel<N>, dim3(v.E), dim3(nthreads_for(N)), 0, st, v, cur, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_svv_flux(const View& v, int cur, const SvvArgs& a, hipStream_t st) {
+  if (v.mixed || v.gauss || v.fp32 || v.E <= 0 || !a.filt || !a.Fa) return hipErrorInvalidValue;
+  switch (v.N) {
+    case 1: return launch_svv_flux_n<1>(v, cur, a, st);
+    case 2: return launch_svv_flux_n<2>(v, cur, a, st);
+    case 3: return launch_svv_flux_n<3>(v, cur, a, st);
+    case 4: return launch_svv_flux_n<4>(v, cur, a, st);
+    case 5: return launch_svv_flux_n<5>(v, cur, a, st);
+    case 6: return launch_svv_flux_n<6>(v, cur, a, st);
+    case 7: return launch_svv_flux_n<7>(v, cur, a, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t launch_svv(const View& v, int cur, const SvvArgs& a, double dt, double b, int mode, hipStream_t st) {
   if (v.mixed || v.gauss || v.fp32 || v.E <= 0 || !a.filt || !a.Fa) return hipErrorInvalidValue;
   switch (v.N) {

@@ -34,9 +34,14 @@ struct FaceIn {
   T fv[4];
 };
 
-template <int N, typename T, bool VISC, int FX>
+// SVA (FP64 Navier-Stokes only): the filtered spectral-vanishing-viscosity flux v.Fa of the
+// same state joins the viscous flux at the nodes, and on the faces the average of both sides'
+// stored values (as the viscous face fluxes; a face node's lane lifts it, the sum taken in the same
+// order from both sides), so the residual holds its term too
+template <int N, typename T, bool VISC, int FX, bool SVA = false>
 __device__ __forceinline__ void stage_body(const View& v, const int e, const int cur, const double dt,
                                            const double rkA, const double rkB, const int mode) {
+  static_assert(!SVA || (VISC && sizeof(T) == 8), "the folded SVV term needs the FP64 viscous kernel");
   constexpr int n = N + 1, nn = n * n * n, nf = n * n, NT = nthreads_for(N);
   constexpr int np = n * (n - 1) / 2;  // pairs (a < b) on one line of n nodes
   constexpr int P = nf * np;           // pairs per direction
@@ -238,10 +243,25 @@ __device__ __forceinline__ void stage_body(const View& v, const int e, const int
     }
 #pragma unroll
     for (int d = 0; d < 3; d++) {
+      T fa[4] = {0, 0, 0, 0}, fb[4] = {0, 0, 0, 0};  // SVA: this node's Fa^d, the neighbour's across a face
+      const int idd = ii[d];
+      const bool onf = SVA && act && (idd == 0 || idd == N);
+      if (SVA && act) {
+#pragma unroll
+        for (int c = 0; c < 4; c++) fa[c] = (T)v.Fa[(base * 12) + (4 * d + c) * nn + t];
+      }
+      if (onf) {
+        const int side = idd == N ? 1 : 0;
+        const int ne = side ? (d == 0 ? nb1 : (d == 1 ? nb3 : nb5)) : (d == 0 ? nb0 : (d == 1 ? nb2 : nb4));
+        const int stride = d == 0 ? 1 : (d == 1 ? n : nf);
+        const int inb = t + (side ? -N : N) * stride;  // the matching node across the face
+#pragma unroll
+        for (int c = 0; c < 4; c++) fb[c] = (T)v.Fa[((long)ne * 12 + 4 * d + c) * nn + inb];
+      }
       __syncthreads();  // previous users of the phase region are done
       if (act) {
 #pragma unroll
-        for (int c = 0; c < 4; c++) sFv[c][t] = Fvd[d][c];
+        for (int c = 0; c < 4; c++) sFv[c][t] = SVA ? Fvd[d][c] + fa[c] : Fvd[d][c];
       }
       __syncthreads();
       if (act) {
@@ -253,6 +273,11 @@ __device__ __forceinline__ void stage_body(const View& v, const int e, const int
           const T Dh = (T)sDh[id * n + m];
 #pragma unroll
           for (int c = 0; c < 4; c++) acc[1 + c] -= Dh * sFv[c][b0 + m * stride];
+        }
+        if (onf) {  // lift of the face average of Fa (the own value's lift is in Dhat)
+          const T wl = id == N ? -(T)0.5 * iwN : (T)0.5 * iw0;
+#pragma unroll
+          for (int c = 0; c < 4; c++) acc[1 + c] += wl * (fa[c] + fb[c]);  // (commutes: the same on both sides)
         }
       }
     }
@@ -359,11 +384,11 @@ __device__ __forceinline__ void stage_body(const View& v, const int e, const int
 }
 
 // FX: the flux family (see flux_family); each family is compiled as separate kernels
-template <int N, typename T, bool VISC, int FX>
+template <int N, typename T, bool VISC, int FX, bool SVA = false>
 __global__ void __launch_bounds__(nthreads_for(N))
     __attribute__((amdgpu_waves_per_eu(stage_waves_per_eu(N, sizeof(T) == 4))))
     stage_kernel(View v, int cur, double dt, double rkA, double rkB, int mode) {
-  stage_body<N, T, VISC, FX>(v, block_element(v.E), cur, dt, rkA, rkB, mode);
+  stage_body<N, T, VISC, FX, SVA>(v, block_element(v.E), cur, dt, rkA, rkB, mode);
 }
 
 template <int N, typename T, bool VISC, int FX>
@@ -380,6 +405,13 @@ template <int N, typename T, int FX>
 inline hipError_t stage_ntx(const View& v, int cur, double dt, double a, double b, int mode,
                             hipStream_t st) {
   const dim3 grid(v.E), block(nthreads_for(N));
+  if constexpr (sizeof(T) == 8 && FX == 0) {
+    if (v.viscous && v.Fa) {
+      hipLaunchKernelGGL((stage_kernel<N, double, true, 0, true>), grid, block, 0, st, v, cur, dt, a, b, mode);
+      return hipGetLastError();
+    }
+  }
+  if (v.Fa) return hipErrorInvalidValue;  // the folded SVV term needs the FP64 viscous kernel
   if (v.viscous)
     hipLaunchKernelGGL((stage_kernel<N, T, true, FX>), grid, block, 0, st, v, cur, dt, a, b, mode);
   else

@@ -149,8 +149,10 @@ def test_filter_passing_nothing_leaves_the_solver_unchanged(dg, shape, N):
 
 def test_full_size_svv_term_dissipates_entropy(dg):
     """32^3 elements of order 4 (the benchmark's mesh and state), Maday kernel: the SVV part of the
-    residual has non-positive entropy production sum w J w(U) . R_a and conserves momentum and
-    energy, computed on the host from the GPU's residuals and geometry."""
+    residual has non-positive entropy production sum w J w(U) . R_a, and the residual with it
+    conserves momentum and energy, computed on the host from the GPU's residuals and geometry.  On
+    Navier-Stokes the term is folded into the stage kernel, so R_a here is the difference of two
+    full residuals and its totals vanish to the full residual's rounding."""
     c = dict(ex=32, N=4, deform=True, Ma=0.1, Re=1600.0)
     g = dg.Solver(**c, svv_mu=0.01, svv_kernel="maday", svv_cutoff=2)
     p = dg.Solver(**c)
@@ -170,10 +172,15 @@ def test_full_size_svv_term_dissipates_entropy(dg):
     ep = np.einsum("evn,evn,en,n->", w[:, 1:], Ra[:, 1:], J, W)
     scale = np.einsum("evn,en,n->", np.abs(w[:, 1:] * Ra[:, 1:]), J, W)
     tot = np.einsum("evn,en,n->v", Ra, J, W)
-    log(f"full size: SVV entropy production {ep:.6e} (scale {scale:.3e}), totals {tot}")
+    Rf = g.residual().reshape(g.E, 5, 125)
+    tot_f = np.einsum("evn,en,n->v", Rf, J, W)
+    mag_f = np.einsum("evn,en,n->v", np.abs(Rf), J, W)
+    log(f"full size: SVV entropy production {ep:.6e} (scale {scale:.3e}), totals {tot}, "
+        f"full residual totals {tot_f} (scale {mag_f.max():.3e})")
     assert np.all(Ra[:, 0] == 0)
-    assert ep < 0
-    assert np.all(np.abs(tot[1:]) < 1e-12 * np.einsum("evn,en,n->v", np.abs(Ra), J, W)[1:].max())
+    assert ep < 0 and abs(ep) > 1e-6 * scale
+    assert np.all(np.abs(tot_f[1:]) < 1e-12 * mag_f.max())
+    assert np.all(np.abs(tot[1:]) < 1e-12 * mag_f.max())
     g.close()
     p.close()
 
