@@ -31,7 +31,8 @@
 namespace dg {
 
 template <int N>
-__global__ void __launch_bounds__(nthreads_for(N)) svv_flux_kernel(View v, int cur, SvvArgs a) {
+__global__ void __launch_bounds__(nthreads_for(N)) __attribute__((amdgpu_waves_per_eu(N <= 6 ? 4 : 3)))
+    svv_flux_kernel(View v, int cur, SvvArgs a) {
   constexpr int n = N + 1, nn = n * n * n, nf = n * n, NT = nthreads_for(N), NW = NT / 64;
   const int e = block_element(v.E);
   const int t = threadIdx.x;
@@ -57,6 +58,19 @@ __global__ void __launch_bounds__(nthreads_for(N)) svv_flux_kernel(View v, int c
   const double g1 = v.gamma - 1.0;
   double vel[3] = {0, 0, 0}, th = 1.0, rho = 1.0;
   double mu = a.mu, kappa = a.kappa;  // the node's viscosity and conductivity
+  // the neighbour's state at this lane's first face point, requested with the node's own state
+  // so that the two memory round trips overlap (face point clamped: every lane loads)
+  auto face_nb = [&](int x, double un[5]) {
+    const int f = x / nf, q = x - f * nf;
+    const int d = f >> 1, side = f & 1;
+    const int p = q % n, r = q / n;
+    const int ne = v.nbr[e * 6 + f];
+    const int inb = face_node<n>(d, side ? 0 : N, p, r);
+#pragma unroll
+    for (int c = 0; c < 5; c++) un[c] = Uin[(long)ne * nn * 5 + c * nn + inb];
+  };
+  double un0[5];
+  face_nb(t < 6 * nf ? t : 0, un0);
   if (act) {
     double u[5];
 #pragma unroll
@@ -74,16 +88,26 @@ __global__ void __launch_bounds__(nthreads_for(N)) svv_flux_kernel(View v, int c
     sW[4][t] = -b;
   }
   __syncthreads();
+  // the metric terms, requested before the face work so that their latency overlaps it
+  double ja[9], J = 1.0, ij = 1.0;
+  if (act) {
+#pragma unroll
+    for (int c = 0; c < 9; c++) ja[c] = v.Ja[base * 9 + c * nn + t];
+    J = v.J[base + t];
+    ij = v.invJ[base + t];
+  }
   for (int x = t; x < 6 * nf; x += NT) {
     const int f = x / nf, q = x - f * nf;
     const int d = f >> 1, side = f & 1;
     const int p = q % n, r = q / n;
     const int io = face_node<n>(d, side ? N : 0, p, r);
-    const int ne = v.nbr[e * 6 + f];
-    const int inb = face_node<n>(d, side ? 0 : N, p, r);
     double un[5];
+    if (x == t) {
 #pragma unroll
-    for (int c = 0; c < 5; c++) un[c] = Uin[(long)ne * nn * 5 + c * nn + inb];
+      for (int c = 0; c < 5; c++) un[c] = un0[c];
+    } else {
+      face_nb(x, un);
+    }
     const double ir = 1.0 / un[0];
     const double w1 = un[1] * ir, w2 = un[2] * ir, w3 = un[3] * ir;
     const double pn = g1 * (un[4] - 0.5 * un[0] * (w1 * w1 + w2 * w2 + w3 * w3));
@@ -96,7 +120,7 @@ __global__ void __launch_bounds__(nthreads_for(N)) svv_flux_kernel(View v, int c
   __syncthreads();
   // gradients of w2..w5 (lifted), the sensor's share of this node
   double G[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  double sens = 0.0, J = 1.0;
+  double sens = 0.0;
   if (act) {
     const double iwN = 1.0 / sw[N], iw0 = 1.0 / sw[0];
     double g2 = 0.0;
@@ -124,13 +148,10 @@ __global__ void __launch_bounds__(nthreads_for(N)) svv_flux_kernel(View v, int c
       }
 #pragma unroll
       for (int x = 0; x < 3; x++) {
-        const double ja = v.Ja[base * 9 + (3 * d + x) * nn + t];
 #pragma unroll
-        for (int c = 0; c < 4; c++) G[c][x] += ja * acc[1 + c];
+        for (int c = 0; c < 4; c++) G[c][x] += ja[3 * d + x] * acc[1 + c];
       }
     }
-    J = v.J[base + t];
-    const double ij = v.invJ[base + t];
 #pragma unroll
     for (int c = 0; c < 4; c++)
 #pragma unroll
@@ -147,7 +168,7 @@ __global__ void __launch_bounds__(nthreads_for(N)) svv_flux_kernel(View v, int c
   for (int k = 0; k < NW; k++) s_el += sRed[k];
   const bool filter = !(a.sensor >= 0.0 && s_el > a.sensor);
   // the nine fields: sqrt(J mu theta) sym-dev(Z), theta sqrt(J kappa) grad w5
-  double y[9];
+  double y[9], sv = 0.0, sq = 0.0;
   {
     double Z[3][3];
 #pragma unroll
@@ -204,7 +225,8 @@ __global__ void __launch_bounds__(nthreads_for(N)) svv_flux_kernel(View v, int c
       mu = a.mu + rho * nu;
       kappa = mu * a.kfac;
     }
-    const double sv = sqrt(J * mu * th), sq = th * sqrt(J * kappa);
+    sv = sqrt(J * mu * th);
+    sq = th * sqrt(J * kappa);
     y[0] = sv * (Z[0][0] - tr3);
     y[1] = sv * (Z[1][1] - tr3);
     y[2] = sv * (Z[2][2] - tr3);
@@ -244,7 +266,8 @@ __global__ void __launch_bounds__(nthreads_for(N)) svv_flux_kernel(View v, int c
     for (int c = 0; c < 9; c++) y[c] -= r[c];
   }
   if (!act) return;
-  const double ks = 2.0 * sqrt(mu * th / J), kq = th * sqrt(kappa / J);
+  // 2 sqrt(mu theta / J) and theta sqrt(kappa / J), from the factors of the filtered fields
+  const double ks = 2.0 * sv * ij, kq = sq * ij;
   const double tau[3][3] = {{ks * y[0], ks * y[3], ks * y[4]},
                             {ks * y[3], ks * y[1], ks * y[5]},
                             {ks * y[4], ks * y[5], ks * y[2]}};
