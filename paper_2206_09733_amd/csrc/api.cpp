@@ -260,16 +260,23 @@ hipError_t run_stage(dg_solver* s, double dt, double a, double b, int mode) {
     hipError_t e = timed(s, DG_K_OTHER, [&] { return pre_stage(s, s->cur, s->stream); });
     if (e != hipSuccess) return e;
   }
-  if (s->v.viscous && !s->v.gauss) {  // (Gauss-Legendre solvers take their gradients in their stage launch)
-    hipError_t e = timed(s, DG_K_GRADIENT, [&] { return dg::launch_gradient(s->v, s->cur, s->stream); });
-    if (e != hipSuccess) return e;
-  }
-  if (svv_folded(s)) {
-    hipError_t e = timed(s, DG_K_OTHER, [&] { return dg::launch_svv_flux(s->v, s->cur, s->svv, s->stream); });
+  if (svv_folded(s)) {  // (takes its own gradient pass)
+    hipError_t e;
+    if (s->v.visc_flux == DG_VISC_BR1) {  // the gradient pass and the SVV flux in one launch
+      e = timed(s, DG_K_GRADIENT, [&] { return dg::launch_grad_svv(s->v, s->cur, s->svv, s->stream); });
+    } else {
+      e = timed(s, DG_K_GRADIENT, [&] { return dg::launch_gradient(s->v, s->cur, s->stream); });
+      if (e == hipSuccess)
+        e = timed(s, DG_K_OTHER, [&] { return dg::launch_svv_flux(s->v, s->cur, s->svv, s->stream); });
+    }
     if (e != hipSuccess) return e;
     dg::View vf = s->v;
     vf.Fa = s->svv.Fa;
     return timed(s, DG_K_STAGE, [&] { return dg::launch_stage(vf, s->cur, dt, a, b, mode, s->stream); });
+  }
+  if (s->v.viscous && !s->v.gauss) {  // (Gauss-Legendre solvers take their gradients in their stage launch)
+    hipError_t e = timed(s, DG_K_GRADIENT, [&] { return dg::launch_gradient(s->v, s->cur, s->stream); });
+    if (e != hipSuccess) return e;
   }
   hipError_t e = timed(s, DG_K_STAGE, [&] { return launch_stage_any(s, dt, a, b, mode); });
   if (e != hipSuccess || !s->svv_on) return e;
@@ -1292,13 +1299,18 @@ hipError_t batch_stage(dg_batch* b, const double* dts, int k, hipStream_t st) {
     } else if (s->v.gauss) {
       e = dg::launch_stage_gauss(s->v, s->cur, dts[i], A, Bk, dg::kModeRK, st);
     } else {  // spectral vanishing viscosity: the solver's own stage sequence
-      e = s->v.viscous ? dg::launch_gradient(s->v, s->cur, st) : hipSuccess;
       if (svv_folded(s)) {
-        if (e == hipSuccess) e = dg::launch_svv_flux(s->v, s->cur, s->svv, st);
+        if (s->v.visc_flux == DG_VISC_BR1) {
+          e = dg::launch_grad_svv(s->v, s->cur, s->svv, st);
+        } else {
+          e = dg::launch_gradient(s->v, s->cur, st);
+          if (e == hipSuccess) e = dg::launch_svv_flux(s->v, s->cur, s->svv, st);
+        }
         dg::View vf = s->v;
         vf.Fa = s->svv.Fa;
         if (e == hipSuccess) e = dg::launch_stage(vf, s->cur, dts[i], A, Bk, dg::kModeRK, st);
       } else {
+        e = s->v.viscous ? dg::launch_gradient(s->v, s->cur, st) : hipSuccess;
         if (e == hipSuccess) e = dg::launch_stage(s->v, s->cur, dts[i], A, Bk, dg::kModeRK, st);
         if (e == hipSuccess) e = dg::launch_svv(s->v, s->cur, s->svv, dts[i], Bk, dg::kModeRK, st);
       }

@@ -26,15 +26,14 @@
 #include <vector>
 
 #include "dg_device.h"
+#include "grad_body.h"
 #include "svv.h"
 
 namespace dg {
 
 template <int N>
-__global__ void __launch_bounds__(nthreads_for(N)) __attribute__((amdgpu_waves_per_eu(N <= 6 ? 4 : 3)))
-    svv_flux_kernel(View v, int cur, SvvArgs a) {
+__device__ __forceinline__ void svv_flux_body(const View& v, const int e, const int cur, const SvvArgs& a) {
   constexpr int n = N + 1, nn = n * n * n, nf = n * n, NT = nthreads_for(N), NW = NT / 64;
-  const int e = block_element(v.E);
   const int t = threadIdx.x;
   const bool act = t < nn;
   const int ti = t % n, tj = (t / n) % n, tk = t / nf;
@@ -359,6 +358,24 @@ __global__ void __launch_bounds__(nthreads_for(N))
   }
 }
 
+// occupancy target: 4 waves per SIMD up to order 6 (no spills), 3 at order 7
+template <int N>
+__global__ void __launch_bounds__(nthreads_for(N)) __attribute__((amdgpu_waves_per_eu(N <= 6 ? 4 : 3)))
+    svv_flux_kernel(View v, int cur, SvvArgs a) {
+  svv_flux_body<N>(v, block_element(v.E), cur, a);
+}
+
+// Navier-Stokes pass A (BR1) and the SVV flux of the same element in one workgroup: the second
+// body reads the element's state, metric terms and neighbour traces that the first has just
+// read, from the L2 cache instead of HBM.  The two bodies share no LDS and no results.
+template <int N>
+__global__ void __launch_bounds__(nthreads_for(N)) __attribute__((amdgpu_waves_per_eu(N <= 6 ? 4 : 3)))
+    grad_svv_kernel(View v, int cur, SvvArgs a) {
+  const int e = block_element(v.E);
+  grad_body<N, double, false>(v, e, cur);
+  svv_flux_body<N>(v, e, cur, a);
+}
+
 template <int N>
 static hipError_t launch_svv_n(const View& v, int cur, const SvvArgs& a, double dt, double b, int mode,
                                hipStream_t st) {
@@ -373,6 +390,27 @@ template <int N>
 static hipError_t launch_svv_flux_n(const View& v, int cur, const SvvArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(svv_flux_kernel<N>, dim3(v.E), dim3(nthreads_for(N)), 0, st, v, cur, a);
   return hipGetLastError();
+}
+
+template <int N>
+static hipError_t launch_grad_svv_n(const View& v, int cur, const SvvArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(grad_svv_kernel<N>, dim3(v.E), dim3(nthreads_for(N)), 0, st, v, cur, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_svv(const View& v, int cur, const SvvArgs& a, hipStream_t st) {
+  if (v.mixed || v.gauss || v.fp32 || !v.viscous || v.visc_flux != 0 || v.E <= 0 || !a.filt || !a.Fa)
+    return hipErrorInvalidValue;
+  switch (v.N) {
+    case 1: return launch_grad_svv_n<1>(v, cur, a, st);
+    case 2: return launch_grad_svv_n<2>(v, cur, a, st);
+    case 3: return launch_grad_svv_n<3>(v, cur, a, st);
+    case 4: return launch_grad_svv_n<4>(v, cur, a, st);
+    case 5: return launch_grad_svv_n<5>(v, cur, a, st);
+    case 6: return launch_grad_svv_n<6>(v, cur, a, st);
+    case 7: return launch_grad_svv_n<7>(v, cur, a, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_svv_flux(const View& v, int cur, const SvvArgs& a, hipStream_t st) {

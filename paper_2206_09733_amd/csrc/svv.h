@@ -29,6 +29,8 @@ hipError_t launch_svv(const View& v, int cur, const SvvArgs& a, double dt, doubl
 // kernel 1 alone, for a stage kernel that takes the filtered flux itself (View::Fa = a.Fa): it
 // enters that kernel's viscous volume and face terms, which then hold R_a, and kernel 2 is not run
 hipError_t launch_svv_flux(const View& v, int cur, const SvvArgs& a, hipStream_t st);
+// Navier-Stokes with BR1: the gradient pass (launch_gradient) and kernel 1 in one launch
+hipError_t launch_grad_svv(const View& v, int cur, const SvvArgs& a, hipStream_t st);
 
 // Host: (I - Phi) for order N, kernel (0 Tadmor, 1 Maday) and cutoff M, from the Legendre
 // polynomials at the Lobatto nodes xi with weights w (long double, rounded once).
