@@ -41,7 +41,8 @@ def algorithmic_bytes_gradient(nodes, N, fp32):
 HERE = os.path.dirname(os.path.abspath(__file__))
 TRAFFIC_PROFILE = os.path.join(HERE, "profiles", "stage_kernel_c2_ns_fp64.md")
 KERNEL_SOURCES = ["paper_2206_09733_amd/csrc/kernels.hip", "paper_2206_09733_amd/csrc/stage_kernel.h",
-                  "paper_2206_09733_amd/csrc/dg_device.h", "paper_2206_09733_amd/csrc/dg_internal.h"]
+                  "paper_2206_09733_amd/csrc/dg_device.h", "paper_2206_09733_amd/csrc/dg_internal.h",
+                  "paper_2206_09733_amd/csrc/grad_body.h"]
 
 
 def _profile_rows(kernel, shape):
@@ -67,7 +68,7 @@ def _profile_rows(kernel, shape):
     return rows
 
 
-def profiled_traffic(kernel="dg::stage_kernel<4, double, true, 0>", shape="32768 x 128"):
+def profiled_traffic(kernel="dg::stage_kernel<4, double, true, 0, false>", shape="32768 x 128"):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary,
     or None when the kernel sources changed since the counters were taken."""
     for cells in _profile_rows(kernel, shape) or []:
@@ -76,7 +77,7 @@ def profiled_traffic(kernel="dg::stage_kernel<4, double, true, 0>", shape="32768
     return None
 
 
-def profiled_limiter(kernel="dg::stage_kernel<4, double, true, 0>", shape="32768 x 128"):
+def profiled_limiter(kernel="dg::stage_kernel<4, double, true, 0, false>", shape="32768 x 128"):
     """What binds `kernel`, from the committed rocprofv3 SQ counters (None when stale): VALU busy
     share, mean resident waves per SIMD and the share of wave time spent waiting."""
     for cells in _profile_rows(kernel, shape) or []:

@@ -78,6 +78,8 @@ __global__ void __launch_bounds__(nthreads_for(N)) gauss_grad_kernel(View v, int
   __shared__ double sG[4][nn];
   __shared__ double sGs[6][4][nf];  // face values g*
   __shared__ double sQ[12][nn];     // BR1: the gradient; BR2, IP: the broken gradient
+  // interior penalty: [g] = g(plus side) - g(minus side) of the two traces of U
+  __shared__ double sGd[XV == 2 ? 6 : 1][4][XV == 2 ? nf : 1];
   for (int x = t; x < n * n; x += NT) {
     const int i = x / n, m = x - i * n;
     // BR1: the weak derivative matrix Dw; BR2, IP: the derivative matrix D itself
@@ -110,6 +112,11 @@ __global__ void __launch_bounds__(nthreads_for(N)) gauss_grad_kernel(View v, int
     gvars(un, v.gamma, 0.0, gn);
 #pragma unroll
     for (int c = 0; c < 4; c++) sGs[f][c][q] = 0.5 * (go[c] + gn[c]);
+    if (XV == 2) {
+      const bool plus = f & 1;  // this element is the face's minus side: the neighbour is plus
+#pragma unroll
+      for (int c = 0; c < 4; c++) sGd[XV == 2 ? f : 0][c][XV == 2 ? q : 0] = plus ? gn[c] - go[c] : go[c] - gn[c];
+    }
   }
   __syncthreads();
   if (act) {
@@ -171,22 +178,13 @@ __global__ void __launch_bounds__(nthreads_for(N)) gauss_grad_kernel(View v, int
     }
     if (XV == 2) {  // interior penalty, from the face's minus (L) and plus (R) sides
       const long eL = side ? e : ne, eR = side ? ne : e;
-      const double* TL = v.Tr + (eL * 6 + 2 * d + 1) * 5 * nf;
-      const double* TR = v.Tr + (eR * 6 + 2 * d) * 5 * nf;
-      double uL[5], uR[5], gL[4], gR[4], JL = 0.0, JR = 0.0;
-#pragma unroll
-      for (int c = 0; c < 5; c++) {
-        uL[c] = TL[c * nf + q];
-        uR[c] = TR[c * nf + q];
-      }
+      double JL = 0.0, JR = 0.0;
 #pragma unroll 1
       for (int i = 0; i < n; i++) {
         const int node = face_node<n>(d, i, p, r);
         JL += sl[1][i] * v.J[eL * nn + node];
         JR += sl[0][i] * v.J[eR * nn + node];
       }
-      gvars(uL, v.gamma, 0.0, gL);
-      gvars(uR, v.gamma, 0.0, gR);
       const double area = sqrt(s1 * s1 + s2 * s2 + s3 * s3);
       const double sigma = v.visc_eta * (double)(n * n) * area / (2.0 * (JL < JR ? JL : JR));
       const double nh[3] = {s1 / area, s2 / area, s3 / area};
@@ -194,8 +192,9 @@ __global__ void __launch_bounds__(nthreads_for(N)) gauss_grad_kernel(View v, int
 #pragma unroll
       for (int c = 0; c < 4; c++)
 #pragma unroll
-        for (int y = 0; y < 3; y++) gp[c][y] = sigma * (gR[c] - gL[c]) * nh[y];
-      viscous_flux_g(0.5 * (gL[0] + gR[0]), 0.5 * (gL[1] + gR[1]), 0.5 * (gL[2] + gR[2]), gp, v.mu, v.kappa, Fp);
+        for (int y = 0; y < 3; y++) gp[c][y] = sigma * sGd[XV == 2 ? f : 0][c][XV == 2 ? q : 0] * nh[y];
+      // the mean velocity: g* (the same sum of the same two values on both sides)
+      viscous_flux_g(sGs[f][0][q], sGs[f][1][q], sGs[f][2][q], gp, v.mu, v.kappa, Fp);
 #pragma unroll
       for (int c = 0; c < 4; c++) Fo[c] = s1 * Fp[0][c] + s2 * Fp[1][c] + s3 * Fp[2][c];
     }
