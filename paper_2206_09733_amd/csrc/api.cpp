@@ -126,7 +126,7 @@ struct dg_solver {
 namespace {
 
 struct Plan {
-  size_t tab, nbr, X, Ja, J, invJ, U0, U1, dU, R, Fvf, part, diag, adapt, elem, work, mtab, Fs, fdesc, Tr, Sf, svvtab,
+  size_t tab, nbr, X, Ja, J, invJ, U0, U1, dU, R, Fvf, part, diag, adapt, elem, work, mtab, Fs, fdesc, Tr, Sf, Jt, Mt, svvtab,
       Fa, self, total;
   size_t tab_n, mtab_n;
 };
@@ -178,6 +178,10 @@ Plan make_plan(const dg_solver* s) {
   p.fdesc = mixed ? take(sizeof(int4) * 3 * E) : 0;
   p.Tr = s->mesh.gauss ? take(sizeof(double) * E * 6 * 5 * nf) : 0;
   p.Sf = s->mesh.gauss ? take(sizeof(double) * E * 9 * nf) : 0;
+  const bool jt = s->mesh.gauss && s->phys.Re > 0 && s->phys.visc_flux == DG_VISC_IP;
+  p.Jt = jt ? take(sizeof(double) * E * 6 * nf) : 0;
+  const bool mt = s->mesh.gauss && s->phys.Re > 0 && s->phys.visc_flux == DG_VISC_BR2;
+  p.Mt = mt ? take(sizeof(double) * E * 18 * nf) : 0;
   const bool svv = s->phys.svv_mu > 0 || s->phys.les_cs > 0;
   p.svvtab = svv ? take(sizeof(double) * n * n) : 0;
   p.Fa = svv ? take(sizeof(double) * 12 * nt) : 0;
@@ -680,6 +684,8 @@ int dg_solver_bind(dg_solver* s, void* dev_ptr, size_t bytes, void* hip_stream) 
   v.gauss = s->mesh.gauss ? 1 : 0;
   v.Tr = s->mesh.gauss ? reinterpret_cast<double*>(b + p.Tr) : nullptr;
   v.Sf = s->mesh.gauss ? reinterpret_cast<double*>(b + p.Sf) : nullptr;
+  v.Jt = p.Jt ? reinterpret_cast<double*>(b + p.Jt) : nullptr;
+  v.Mt = p.Mt ? reinterpret_cast<double*>(b + p.Mt) : nullptr;
   s->svv_on = s->phys.svv_mu > 0 || s->phys.les_cs > 0;
   if (s->svv_on) {
     s->svv.mu = s->phys.svv_mu;
@@ -816,6 +822,7 @@ int dg_solver_bind(dg_solver* s, void* dev_ptr, size_t bytes, void* hip_stream) 
     DG_HIP(hipStreamSynchronize(s->stream), "upload");
   } else {
     DG_HIP(dg::launch_geometry(v, s->stream), "geometry kernel");
+    if (v.Jt || v.Mt) DG_HIP(dg::launch_jtrace_gauss(v, s->stream), "face factor kernel");
   }
   DG_HIP(hipMemsetAsync(v.dU, 0, sizeof(double) * 5 * s->ntot, s->stream), "clear RK register");
   DG_HIP(hipStreamSynchronize(s->stream), "geometry");

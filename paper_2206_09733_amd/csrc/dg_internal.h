@@ -50,6 +50,10 @@ struct View {
   double* Tr;       // Gauss-Legendre: face traces [E][6][5][nf] of the state
   double* Sf;       // Gauss-Legendre: each element's +xi_d face metric Ja^d interpolated to its
                     // face points, [E][3 d][3 components][nf]
+  double* Jt;       // Gauss-Legendre with the interior penalty: each element's trace of J on its
+                    // six faces, [E][6][nf] (formed once after the geometry)
+  double* Mt;       // Gauss-Legendre with BR2: the metric factor of each face's lift, traced,
+                    // sum_i l_i(side) (+-l_i(side) / w_i) Ja^d_i / J_i, [E][6][3][nf]
   double visc_eta;  // BR2 lifting factor or interior-penalty factor
   double rho_r, p_r;  // FP32-bulk reference state (mean density and pressure of the state set)
   const int* nbr; // [E][6] neighbour across face f = 2 d + side (side 1: xi_d = +1)
@@ -126,6 +130,8 @@ hipError_t launch_stage_batch(const BatchArgs& B, int N, bool fp32, bool visc, i
                               int mode, hipStream_t st);  // fx: the members' flux family
 // Gauss-Legendre nodes: face traces of U[cur], then the weak-form residual / RK stage
 hipError_t launch_stage_gauss(const View& v, int cur, double dt, double rkA, double rkB, int mode, hipStream_t st);
+// Gauss-Legendre with the interior penalty or BR2: the face factors Jt or Mt (after launch_geometry)
+hipError_t launch_jtrace_gauss(const View& v, hipStream_t st);
 // adaptive step size (uniform and mixed orders): clear adapt[], then per step reduce the wave
 // speeds of U[cur] and write the step size to adapt[0]
 hipError_t launch_adapt_reset(const View& v, hipStream_t st);

@@ -23,6 +23,43 @@ namespace dg {
 // the Lobatto Dhat slot of the order's table holds l_j(-1) (n values), then l_j(+1)
 __host__ __device__ constexpr int gauss_tab_ends(int n) { return 2 * n + n * n; }
 
+// Static face factors of the element's six faces, formed once after the geometry: the trace of J,
+// Jt[E][6][nf] (the interior penalty's element sizes), or the traced metric factor of the face's
+// BR2 lift, Mt[E][6][3][nf] = sum_i l_i(side) (+-l_i(side) / w_i) Ja^d_i / J_i
+template <int N>
+__global__ void __launch_bounds__(nthreads_for(N)) gauss_jtrace_kernel(View v) {
+  constexpr int n = N + 1, nn = n * n * n, nf = n * n, NT = nthreads_for(N);
+  const int e = block_element(v.E);
+  const int t = threadIdx.x;
+  const long base = (long)e * nn;
+  __shared__ double sl[2][n], sw[n];
+  if (t < 2 * n) sl[t / n][t % n] = v.tab[gauss_tab_ends(n) + t];
+  if (t < n) sw[t] = v.tab[n + t];
+  __syncthreads();
+  for (int x = t; x < 6 * nf; x += NT) {
+    const int f = x / nf, q = x - f * nf;
+    const int d = f >> 1, side = f & 1;
+    const int p = q % n, r = q / n;
+    double acc = 0.0, M[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < n; i++) {
+      const int node = face_node<n>(d, i, p, r);
+      const double l = sl[side][i];
+      if (v.Jt) acc += l * v.J[base + node];
+      if (v.Mt) {
+        const double wl = (side ? l : -l) * l / sw[i] * v.invJ[base + node];
+#pragma unroll
+        for (int y = 0; y < 3; y++) M[y] += wl * v.Ja[base * 9 + (3 * d + y) * nn + node];
+      }
+    }
+    if (v.Jt) v.Jt[((long)e * 6 + f) * nf + q] = acc;
+    if (v.Mt) {
+#pragma unroll
+      for (int y = 0; y < 3; y++) v.Mt[(((long)e * 6 + f) * 3 + y) * nf + q] = M[y];
+    }
+  }
+}
+
 template <int N>
 __global__ void __launch_bounds__(nthreads_for(N)) gauss_trace_kernel(View v, int cur) {
   constexpr int n = N + 1, nn = n * n * n, nf = n * n, NT = nthreads_for(N);
@@ -161,7 +198,7 @@ __global__ void __launch_bounds__(nthreads_for(N)) gauss_grad_kernel(View v, int
     // the scheme's own face terms first, so that their operands are retired before the twelve
     // gradient traces are formed
     double Fo[4] = {0.0, 0.0, 0.0, 0.0}, jump[4], M[3] = {0.0, 0.0, 0.0};
-    if (XV == 1) {  // BR2: the jump g* - g(side) and the trace of its lift's metric factor
+    if (XV == 1) {  // BR2: the jump g* - g(side) and the traced metric factor of its lift (Mt)
 #pragma unroll
       for (int c = 0; c < 4; c++) jump[c] = sGs[f][c][q];
 #pragma unroll 1
@@ -170,21 +207,11 @@ __global__ void __launch_bounds__(nthreads_for(N)) gauss_grad_kernel(View v, int
         const double l = sl[side][i];
 #pragma unroll
         for (int c = 0; c < 4; c++) jump[c] -= l * sG[c][node];
-        // l_i(side) (+-l_i(side) / w_i) Ja^d_i / J_i
-        const double wl = (side ? l : -l) * l / sw[i] * v.invJ[base + node];
-#pragma unroll
-        for (int y = 0; y < 3; y++) M[y] += wl * v.Ja[base * 9 + (3 * d + y) * nn + node];
       }
     }
     if (XV == 2) {  // interior penalty, from the face's minus (L) and plus (R) sides
       const long eL = side ? e : ne, eR = side ? ne : e;
-      double JL = 0.0, JR = 0.0;
-#pragma unroll 1
-      for (int i = 0; i < n; i++) {
-        const int node = face_node<n>(d, i, p, r);
-        JL += sl[1][i] * v.J[eL * nn + node];
-        JR += sl[0][i] * v.J[eR * nn + node];
-      }
+      const double JL = v.Jt[(eL * 6 + 2 * d + 1) * nf + q], JR = v.Jt[(eR * 6 + 2 * d) * nf + q];
       const double area = sqrt(s1 * s1 + s2 * s2 + s3 * s3);
       const double sigma = v.visc_eta * (double)(n * n) * area / (2.0 * (JL < JR ? JL : JR));
       const double nh[3] = {s1 / area, s2 / area, s3 / area};
@@ -207,6 +234,8 @@ __global__ void __launch_bounds__(nthreads_for(N)) gauss_grad_kernel(View v, int
       gr[k / 3][k % 3] = acc;
     }
     if (XV == 1) {  // + eta times the trace of this face's lift
+#pragma unroll
+      for (int y = 0; y < 3; y++) M[y] = v.Mt[(((long)e * 6 + f) * 3 + y) * nf + q];
 #pragma unroll
       for (int c = 0; c < 4; c++)
 #pragma unroll
@@ -427,8 +456,30 @@ static hipError_t gauss_stage_n(const View& v, int cur, double dt, double a, dou
   return hipGetLastError();
 }
 
+template <int N>
+static hipError_t gauss_jtrace_n(const View& v, hipStream_t st) {
+  hipLaunchKernelGGL(gauss_jtrace_kernel<N>, dim3(v.E), dim3(nthreads_for(N)), 0, st, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_jtrace_gauss(const View& v, hipStream_t st) {
+  if (!v.gauss || (!v.Jt && !v.Mt) || v.E <= 0) return hipErrorInvalidValue;
+  switch (v.N) {
+    case 1: return gauss_jtrace_n<1>(v, st);
+    case 2: return gauss_jtrace_n<2>(v, st);
+    case 3: return gauss_jtrace_n<3>(v, st);
+    case 4: return gauss_jtrace_n<4>(v, st);
+    case 5: return gauss_jtrace_n<5>(v, st);
+    case 6: return gauss_jtrace_n<6>(v, st);
+    case 7: return gauss_jtrace_n<7>(v, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t launch_stage_gauss(const View& v, int cur, double dt, double rkA, double rkB, int mode, hipStream_t st) {
   if (!v.gauss || !v.Tr) return hipErrorInvalidValue;
+  if (v.viscous && v.visc_flux == 2 && !v.Jt) return hipErrorInvalidValue;  // the penalty's traces of J
+  if (v.viscous && v.visc_flux == 1 && !v.Mt) return hipErrorInvalidValue;  // BR2's lift factors
   switch (v.N) {
     case 1: return gauss_stage_n<1>(v, cur, dt, rkA, rkB, mode, st);
     case 2: return gauss_stage_n<2>(v, cur, dt, rkA, rkB, mode, st);
