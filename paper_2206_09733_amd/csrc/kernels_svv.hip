@@ -15,7 +15,10 @@
 // low-pass Q = I - Phi: three passes of an (N+1) x (N+1) matrix along the element's lines.
 // Elements whose density sensor s = sum w_i w_j w_k J |grad_xi rho|^2 exceeds the threshold
 // take the unfiltered flux.  The residual of the term is the divergence of the contravariant
-// flux with BR1 face terms (the average of the two sides' fluxes along the owner's Ja^d).
+// flux with BR1 face terms (the average of the two sides' fluxes along the owner's Ja^d): on
+// Navier-Stokes with the standard fluxes the stage kernel forms it with the viscous flux (the
+// flux kernel runs before it, with BR1 in one launch with the gradient pass); otherwise
+// svv_div_kernel adds it after the stage kernel.
 // Explicit LES closure (turbulence models: Smagorinsky, WALE, Vreman, SVV-Smagorinsky): the
 // viscosity gains the model's rho nu_t node by node, from g = grad v = theta Z and
 // Delta = 2 (J/(N+1)^3)^(1/3) (the formulas are in the C header); mu and kappa enter only through

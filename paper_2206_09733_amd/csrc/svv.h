@@ -1,6 +1,7 @@
-// svv.h -- spectral vanishing viscosity (section "Shock capturing"): launch interface of the two
-// kernels in kernels_svv.hip.  They run after the stage kernel of a Gauss-Lobatto, uniform-order,
-// FP64 solver and add the artificial-viscosity term to what it produced.
+// svv.h -- spectral vanishing viscosity (section "Shock capturing"): launch interface of the
+// kernels in kernels_svv.hip, for Gauss-Lobatto, uniform-order, FP64 solvers.  The filtered flux
+// either enters the Navier-Stokes stage kernel's viscous flux (launch_svv_flux or launch_grad_svv
+// before it), or its divergence is added to what the stage kernel produced (launch_svv after it).
 #pragma once
 
 #include <hip/hip_runtime.h>
