@@ -368,6 +368,35 @@ def run_mixed(steps, warmup):
     return out
 
 
+def run_halo(steps, warmup):
+    """One GPU's share of the 64^3 N=5 Navier-Stokes TGV split across eight GPUs: a 32^3 block run
+    with its periodic neighbours reached through ghost elements and a halo exchange before every
+    stage (state face values; after the gradient pass the face viscous fluxes), against the same
+    block with direct neighbours.  The exchange moves its buffers with a device copy where a split
+    run would send them between GPUs."""
+    from paper_2206_09733_amd import dgsem
+    out = {"workload": "compressible NS TGV Re1600 Ma0.1, 32^3 hex block of a deformed 64^3 N=5 mesh, "
+                       "EC + Roe + BR1, RK3 CFL 0.5, FP64"}
+    K, nf = 6 * 32 * 32, 36
+    for halo in (False, True):
+        s = dgsem.Solver(32, N=5, deform=True, Ma=0.1, Re=1600.0, halo=halo)
+        s.set_ic("tgv")
+        dt = s.suggest_dt(0.5)
+        s.rk_step(dt, warmup)
+        ev_ms, _, _ = timed_steps(s, dt, steps, profile=False)
+        _, _, prof = timed_steps(s, dt, max(2, steps // 5))
+        key = "halo" if halo else "direct"
+        out[key] = {"value": round(5 * s.nodes * 3 * steps / (ev_ms / 1e3) / 1e9, 3), "unit": "GDOF/s",
+                    "ms_per_step": round(ev_ms / steps, 4), "state_finite": s.diagnostics()["nonfinite"] == 0}
+        if halo:
+            ot = prof["other"]
+            out[key]["exchange_us_per_stage"] = round(ot["ms"] / ot["launches"] * 2 * 1e3, 2)
+            out[key]["exchanged_bytes_per_stage"] = K * nf * 8 * (5 + 4)
+        s.close()
+    out["halo"]["overhead_pct"] = round(100.0 * (out["halo"]["ms_per_step"] / out["direct"]["ms_per_step"] - 1), 2)
+    return out
+
+
 def run_large(steps, warmup):
     """The large comparison: 64^3 elements, N = 5 (56.6 M nodes), Navier-Stokes TGV Re 1600,
     Ma 0.1, deformed mesh; FP64 against FP32-bulk, time per RK3 step."""
@@ -523,7 +552,8 @@ def run_cpu_baseline(budget_s=12.0, max_steps=4):
                 sample_1_thread=f"one residual evaluation of the same mesh on 1 thread ({t1:.1f} s)")
 
 
-LEGS = ["fp32", "rk4", "adaptive", "small", "gauss", "variants", "svv", "mixed", "large", "batch", "serve", "cpu"]
+LEGS = ["fp32", "rk4", "adaptive", "small", "gauss", "variants", "svv", "mixed", "large", "halo", "batch", "serve",
+        "cpu"]
 
 
 def main():
@@ -652,6 +682,8 @@ def main():
         result["mixed_order"] = run_mixed(max(10, args.steps // 2), args.warmup)
     if "large" in legs:
         result["large_64_n5"] = run_large(max(5, args.steps // 10), 2)
+    if "halo" in legs:
+        result["halo_block_32_n5"] = run_halo(max(10, args.steps // 2), 2)
     if "batch" in legs:
         from paper_2206_09733_amd import synth
         result["batch_vs_solo"] = {

@@ -102,7 +102,15 @@ typedef struct dg_batch dg_batch;
 /* Periodic box of ex*ey*ez hexahedra on [lo, hi]; with DG_DEFORM_SINSIN each node is moved by
  * (a sin y sin z, a sin z sin x, a sin x sin y) evaluated at its undeformed position
  * (a = deform_amp).  Uniform order n_uniform in every direction, or per-element anisotropic
- * orders orders[3 e + d] (NULL for uniform). */
+ * orders orders[3 e + d] (NULL for uniform).
+ * halo = 1 (uniform-order Gauss-Lobatto boxes): the box is treated as one block of a domain split
+ * across GPUs whose neighbours across every box face are the block's own periodic images.  Each
+ * element face on the box boundary then reads a ghost element instead of its periodic partner,
+ * and every stage first exchanges the block's boundary face values: the state's face nodes (and,
+ * with viscosity, the face viscous fluxes after the gradient pass) are packed into a contiguous
+ * send buffer, moved to the receive buffer (a device copy here, the inter-GPU transfer of a split
+ * run) and unpacked into the ghosts.  Results equal those of the direct periodic box bit for bit.
+ * The face metrics of the -d faces take the owner's once, at set-up. */
 typedef struct {
   int ex, ey, ez;
   double lo[3], hi[3];
@@ -111,6 +119,7 @@ typedef struct {
   int n_uniform;
   const int* orders;
   int nodes;  /* DG_NODES_LOBATTO (default) or DG_NODES_GAUSS */
+  int halo;   /* 0 (default) or 1: periodic neighbours through ghost elements and a halo exchange */
 } dg_box_desc;
 
 /* face viscous flux (box of viscous fluxes in section "Spatial discretisation"), all with the

@@ -14,7 +14,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdgsem.so")
-SOURCES = ["kernels.hip", "kernels_ext.hip", "kernels_mixed.hip", "kernels_gauss.hip", "kernels_svv.hip", "api.cpp", "gll_host.cpp"]
+SOURCES = ["kernels.hip", "kernels_ext.hip", "kernels_mixed.hip", "kernels_gauss.hip", "kernels_svv.hip",
+           "kernels_halo.hip", "api.cpp", "gll_host.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall",

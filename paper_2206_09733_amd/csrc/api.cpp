@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "dg_internal.h"
+#include "halo.h"
 #include "svv.h"
 #include "dgsem.h"
 
@@ -79,8 +80,16 @@ struct dg_mesh {
   int N;                    // the order of a uniform mesh, the largest order of a mixed one
   bool mixed = false;
   bool gauss = false;       // Gauss-Legendre nodes
+  bool halo = false;        // periodic neighbours through ghost elements and a halo exchange
   std::vector<int> orders;  // mixed meshes: orders[3 e + d]
 };
+
+namespace {
+// faces on the box boundary (the ghost elements of a halo box): x, y and z faces of both sides
+long long halo_faces(const dg_mesh& m) {
+  return 2LL * ((long long)m.ey * m.ez + (long long)m.ex * m.ez + (long long)m.ex * m.ey);
+}
+}  // namespace
 
 struct ProfRecord {
   int cls;
@@ -121,12 +130,14 @@ struct dg_solver {
   int scheme = DG_RK3_WILLIAMSON;    // time scheme of dg_rk_step
   bool svv_on = false;               // spectral vanishing viscosity in every stage
   dg::SvvArgs svv{};
+  dg::HaloArgs halo{};               // halo boxes: the exchange's map and buffers (halo.K > 0)
 };
 
 namespace {
 
 struct Plan {
   size_t tab, nbr, X, Ja, J, invJ, U0, U1, dU, R, Fvf, part, diag, adapt, elem, work, mtab, Fs, fdesc, Tr, Sf, Jt, Mt, svvtab,
+      hmap, hsend, hrecv, hsendv, hrecvv,
       Fa, self, total;
   size_t tab_n, mtab_n;
 };
@@ -163,11 +174,18 @@ Plan make_plan(const dg_solver* s) {
   p.Ja = take(sizeof(double) * 9 * nt);
   p.J = take(sizeof(double) * nt);
   p.invJ = take(sizeof(double) * nt);
-  p.U0 = take(sizeof(double) * 5 * nt);
-  p.U1 = take(sizeof(double) * 5 * nt);
+  // halo boxes: K ghost elements after the E elements of the state and of the face viscous fluxes
+  const size_t K = s->mesh.halo ? (size_t)halo_faces(s->mesh) : 0;
+  p.U0 = take(sizeof(double) * 5 * (nt + K * n * nf));
+  p.U1 = take(sizeof(double) * 5 * (nt + K * n * nf));
   p.dU = take(sizeof(double) * 5 * nt);
   p.R = take(sizeof(double) * 5 * nt);
-  p.Fvf = s->phys.Re > 0 ? take(sizeof(double) * E * 6 * 4 * nf) : 0;
+  p.Fvf = s->phys.Re > 0 ? take(sizeof(double) * (E + K) * 6 * 4 * nf) : 0;
+  p.hmap = K ? take(sizeof(int4) * K) : 0;
+  p.hsend = K ? take(sizeof(double) * K * 5 * nf) : 0;
+  p.hrecv = K ? take(sizeof(double) * K * 5 * nf) : 0;
+  p.hsendv = K && s->phys.Re > 0 ? take(sizeof(double) * K * 4 * nf) : 0;
+  p.hrecvv = K && s->phys.Re > 0 ? take(sizeof(double) * K * 4 * nf) : 0;
   p.part = take(sizeof(double) * E * dg::kDiagSlots);
   p.diag = take(sizeof(double) * dg::kDiagSlots);
   p.adapt = take(sizeof(double) * 8);
@@ -278,9 +296,17 @@ hipError_t run_stage(dg_solver* s, double dt, double a, double b, int mode) {
     vf.Fa = s->svv.Fa;
     return timed(s, DG_K_STAGE, [&] { return dg::launch_stage(vf, s->cur, dt, a, b, mode, s->stream); });
   }
+  if (s->halo.K) {  // the ghosts' face state of this stage's input
+    hipError_t e = timed(s, DG_K_OTHER, [&] { return dg::halo_exchange_state(s->v, s->cur, s->halo, s->stream); });
+    if (e != hipSuccess) return e;
+  }
   if (s->v.viscous && !s->v.gauss) {  // (Gauss-Legendre solvers take their gradients in their stage launch)
     hipError_t e = timed(s, DG_K_GRADIENT, [&] { return dg::launch_gradient(s->v, s->cur, s->stream); });
     if (e != hipSuccess) return e;
+    if (s->halo.K) {  // and their face viscous fluxes
+      e = timed(s, DG_K_OTHER, [&] { return dg::halo_exchange_viscous(s->v, s->halo, s->stream); });
+      if (e != hipSuccess) return e;
+    }
   }
   hipError_t e = timed(s, DG_K_STAGE, [&] { return launch_stage_any(s, dt, a, b, mode); });
   if (e != hipSuccess || !s->svv_on) return e;
@@ -543,6 +569,12 @@ int dg_mesh_create_box(const dg_box_desc* d, dg_mesh** out) try {
   m->mixed = mixed;
   m->gauss = d->nodes == DG_NODES_GAUSS;
   if (m->gauss && mixed) return fail(DG_EUNSUPPORTED, "Gauss-Legendre nodes are built for uniform-order boxes");
+  if (d->halo != 0 && d->halo != 1) return fail(DG_EINVAL, "halo must be 0 or 1");
+  m->halo = d->halo == 1;
+  if (m->halo && (mixed || m->gauss))
+    return fail(DG_EUNSUPPORTED, "halo exchange: uniform-order Gauss-Lobatto boxes");
+  if (m->halo && E + halo_faces(*m) >= (1LL << 31))
+    return fail(DG_EUNSUPPORTED, "halo exchange: elements and ghost elements must number fewer than 2^31");
   m->N = mixed ? nmax : N;
   if (mixed) m->orders.assign(d->orders, d->orders + 3 * E);
   *out = m.release();
@@ -590,6 +622,9 @@ int dg_solver_create(const dg_mesh* m, const dg_physics* p, dg_solver** out) try
   if (m->gauss && (p->precision != DG_FP64 || p->vol_flux != DG_VOL_CENTRAL))
     return fail(DG_EUNSUPPORTED, "Gauss-Legendre nodes: FP64, volume flux DG_VOL_CENTRAL (the plain weak "
                                  "form)");
+  if (m->halo && (p->svv_mu > 0 || p->les_cs > 0 || (p->Re > 0 && p->visc_flux == DG_VISC_IP)))
+    return fail(DG_EUNSUPPORTED, "halo exchange: no spectral vanishing viscosity or interior penalty (their face "
+                                 "terms read more of the neighbour than its face state and viscous flux)");
   if (!(p->svv_mu >= 0) || !std::isfinite(p->svv_mu)) return fail(DG_EINVAL, "svv_mu must be >= 0");
   if (!(p->les_cs >= 0) || !std::isfinite(p->les_cs)) return fail(DG_EINVAL, "les_cs must be >= 0");
   if (p->les_cs > 0 && p->les_model != DG_LES_SMAGORINSKY && p->les_model != DG_LES_WALE &&
@@ -672,6 +707,14 @@ int dg_solver_bind(dg_solver* s, void* dev_ptr, size_t bytes, void* hip_stream) 
   v.dU = reinterpret_cast<double*>(b + p.dU);
   v.R = reinterpret_cast<double*>(b + p.R);
   v.Fvf = v.viscous ? reinterpret_cast<double*>(b + p.Fvf) : nullptr;
+  if (s->mesh.halo) {
+    s->halo.map = reinterpret_cast<const int4*>(b + p.hmap);
+    s->halo.K = (int)halo_faces(s->mesh);
+    s->halo.send = reinterpret_cast<double*>(b + p.hsend);
+    s->halo.recv = reinterpret_cast<double*>(b + p.hrecv);
+    s->halo.sendv = v.viscous ? reinterpret_cast<double*>(b + p.hsendv) : nullptr;
+    s->halo.recvv = v.viscous ? reinterpret_cast<double*>(b + p.hrecvv) : nullptr;
+  }
   v.part = reinterpret_cast<double*>(b + p.part);
   v.diag = reinterpret_cast<double*>(b + p.diag);
   v.adapt = reinterpret_cast<double*>(b + p.adapt);
@@ -823,6 +866,36 @@ int dg_solver_bind(dg_solver* s, void* dev_ptr, size_t bytes, void* hip_stream) 
   } else {
     DG_HIP(dg::launch_geometry(v, s->stream), "geometry kernel");
     if (v.Jt || v.Mt) DG_HIP(dg::launch_jtrace_gauss(v, s->stream), "face factor kernel");
+  }
+  std::vector<int> hnbr;
+  std::vector<int4> hmap;
+  if (s->mesh.halo) {
+    // The geometry above took the -d faces' metric from their owners through the direct periodic
+    // neighbours (in a split run, a one-time exchange at set-up).  From here on each face on the
+    // box boundary reads ghost element E + k, filled by the exchange before every stage from the
+    // block's periodic image of its neighbour (the same face number on both).
+    hnbr = nbr;
+    const long long E = s->E;
+    for (long long e = 0; e < E; e++) {
+      const int a = (int)(e % ex), bb = (int)((e / ex) % ey), c = (int)(e / ((long long)ex * ey));
+      const int idx[3] = {a, bb, c}, cnt[3] = {ex, ey, ez};
+      for (int f = 0; f < 6; f++) {
+        const int d = f >> 1, side = f & 1;
+        if (idx[d] != (side ? cnt[d] - 1 : 0)) continue;  // not on the box boundary
+        const long long g = E + (long long)hmap.size();
+        hmap.push_back(make_int4(nbr[6 * e + f], f ^ 1, (int)g, f ^ 1));
+        hnbr[6 * e + f] = (int)g;
+      }
+    }
+    if ((long long)hmap.size() != s->halo.K) return fail(DG_EINVAL, "internal error: halo face count");
+    for (const int4& m : hmap)
+      if (m.x < 0 || m.x >= E || m.z < E || m.z >= E + s->halo.K || m.y < 0 || m.y > 5)
+        return fail(DG_EINVAL, "internal error: halo map out of range");
+    DG_HIP(hipStreamSynchronize(s->stream), "geometry");
+    DG_HIP(hipMemcpyAsync(b + p.nbr, hnbr.data(), sizeof(int) * hnbr.size(), hipMemcpyHostToDevice, s->stream),
+           "upload halo connectivity");
+    DG_HIP(hipMemcpyAsync(b + p.hmap, hmap.data(), sizeof(int4) * hmap.size(), hipMemcpyHostToDevice, s->stream),
+           "upload halo map");
   }
   DG_HIP(hipMemsetAsync(v.dU, 0, sizeof(double) * 5 * s->ntot, s->stream), "clear RK register");
   DG_HIP(hipStreamSynchronize(s->stream), "geometry");
@@ -1370,6 +1443,7 @@ int dg_batch_create(dg_solver* const* solvers, int n, void* hip_stream, dg_batch
   for (int i = 0; i < n; i++) {
     int rc = check_bound(solvers[i]);
     if (rc) return rc;
+    if (solvers[i]->mesh.halo) return fail(DG_EUNSUPPORTED, "solvers of halo boxes are not batched");
     for (int j = 0; j < i; j++)
       if (solvers[j] == solvers[i]) return fail(DG_EINVAL, "a solver appears twice in the batch");
   }

@@ -32,7 +32,8 @@ _dp = _c.POINTER(_c.c_double)
 class BoxDesc(_c.Structure):
     _fields_ = [("ex", _c.c_int), ("ey", _c.c_int), ("ez", _c.c_int), ("lo", _c.c_double * 3),
                 ("hi", _c.c_double * 3), ("deform", _c.c_int), ("deform_amp", _c.c_double),
-                ("n_uniform", _c.c_int), ("orders", _c.POINTER(_c.c_int)), ("nodes", _c.c_int)]
+                ("n_uniform", _c.c_int), ("orders", _c.POINTER(_c.c_int)), ("nodes", _c.c_int),
+                ("halo", _c.c_int)]
 
 
 class Physics(_c.Structure):
@@ -140,9 +141,10 @@ def _ptr(a):
 NODES = {"lobatto": 0, "gauss": 1}
 
 
-def box_desc(ex, ey, ez, lo, hi, deform, amp, N, orders=None, nodes="lobatto"):
+def box_desc(ex, ey, ez, lo, hi, deform, amp, N, orders=None, nodes="lobatto", halo=False):
     d = BoxDesc()
     d.nodes = NODES[nodes]
+    d.halo = 1 if halo else 0
     d.ex, d.ey, d.ez = ex, ey, ez
     d.lo[:] = list(lo)
     d.hi[:] = list(hi)
@@ -178,14 +180,16 @@ class Solver:
     troubled-element threshold `svv_sensor` of the density sensor, < 0 for none).  `les_cs` > 0
     adds the eddy viscosity of `les_model` ("smagorinsky", "wale" or "vreman") with that constant
     to the artificial viscosity, node by node (filtered by the SVV kernel: SVV-Smagorinsky; kernel
-    "tadmor" with cutoff -1 keeps every mode: the plain model).
+    "tadmor" with cutoff -1 keeps every mode: the plain model).  `halo=True` runs the box as one
+    block of a split domain: faces on the box boundary read ghost elements that a halo exchange
+    (pack, transfer, unpack) fills before every stage; results equal the direct periodic box.
     """
 
     def __init__(self, ex, ey=None, ez=None, lo=(0.0, 0.0, 0.0), hi=None, deform=False, amp=0.05,
                  N=3, gamma=1.4, Pr=0.71, Ma=0.1, Re=0.0, vol="ec", surf="roe", precision="fp64",
                  device="cuda", bind=True, orders=None, visc="br1", visc_eta=0.0, nodes="lobatto",
                  svv_mu=0.0, svv_kernel="maday", svv_cutoff=None, svv_sensor=-1.0, les_cs=0.0,
-                 les_model="smagorinsky"):
+                 les_model="smagorinsky", halo=False):
         L = lib()
         ey = ex if ey is None else ey
         ez = ex if ez is None else ez
@@ -195,7 +199,7 @@ class Solver:
         self.gamma, self.Pr, self.Ma, self.Re = gamma, Pr, Ma, Re
         self.h = None
         self.buf = None
-        d, _keep = box_desc(ex, ey, ez, lo, hi, deform, amp, N, orders, nodes)
+        d, _keep = box_desc(ex, ey, ez, lo, hi, deform, amp, N, orders, nodes, halo)
         mesh = _c.c_void_p()
         check(L.dg_mesh_create_box(_c.byref(d), _c.byref(mesh)))
         try:

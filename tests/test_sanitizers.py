@@ -132,11 +132,14 @@ def test_library_host_code_under_asan_ubsan(tmp_path):
         assert rc == dgsem.DG_EUNSUPPORTED
         rc, m, _ = mesh(2, 2, 2, (0, 0, 0), (1, 1, 1), False, 0.0, 3, orders=[2, 3, 3] * 8, nodes="gauss")
         assert rc == dgsem.DG_EUNSUPPORTED
+        rc, m, _ = mesh(2, 2, 2, (0, 0, 0), (1, 1, 1), False, 0.0, 3, nodes="gauss", halo=True)
+        assert rc == dgsem.DG_EUNSUPPORTED
         # valid meshes and solvers of every option family, their memory plans, then destroy
         specs = [((3, 2, 4, (0, 0, 0), (1, 1, 1), True, 0.05, 4), {{}}),
                  ((3, 3, 3, (-1, -1, -1), (1, 1, 1), False, 0.0, 3), dict(orders=synth.mixed_orders(27, seed=3))),
                  ((2, 2, 2, (0, 0, 0), (1, 1, 1), False, 0.0, 5), dict(nodes="gauss")),
-                 ((2, 3, 2, (0, 0, 0), (1, 1, 1), True, 0.05, 4), dict(nodes="gauss"))]
+                 ((2, 3, 2, (0, 0, 0), (1, 1, 1), True, 0.05, 4), dict(nodes="gauss")),
+                 ((1, 3, 2, (0, 0, 0), (1, 1, 1), True, 0.05, 3), dict(halo=True))]
         phys = [dgsem.physics(Ma=0.1), dgsem.physics(Ma=0.1, Re=1600.0, precision="fp32_bulk"),
                 dgsem.physics(Ma=0.3, Re=400.0, visc="ip", vol="kg", surf="es_matrix"),
                 dgsem.physics(Ma=0.3, svv_mu=0.01, svv_kernel="tadmor", svv_cutoff=2),
