@@ -35,7 +35,17 @@
  *   - Williamson's low-storage RK3 and Carpenter-Kennedy's low-storage RK4 (section "Time
  *     advancement");
  *   - entropy S=-rho*s, s=ln p - gamma ln rho and w=dS/du (section "Shock capturing",
- *     eq. shock:entropy).
+ *     eq. shock:entropy);
+ *   - spectral vanishing viscosity (same section, eqs. shock:fluxmatrix and
+ *     shock:filteredflux): the Navier-Stokes viscous flux in entropy variables, B = L^T D L,
+ *     half-filtered in Legendre modal space with Tadmor's or Maday's kernel, the density sensor;
+ *     and the explicit LES closures of the turbulence-models section (Smagorinsky, WALE,
+ *     Vreman), as the eddy viscosity added to the artificial one node by node.
+ *
+ * Parity unpinned (no test fixes the choice; every other function fails a pin under a plausible
+ * mistake): the averaged state of the matrix-dissipation surface flux (8b), the L^T D L
+ * factorisation of the SVV flux matrix (8c), and the interior penalty's use of the smaller of
+ * the two traces of J on Gauss-Legendre points (7c; on these boxes the two agree).
  */
 #include "dgsem_oracle.h"
 
@@ -1700,7 +1710,11 @@ static void svv_basis(real E[5][3][3]) {
   E[4][0][0] = r6; E[4][1][1] = r6; E[4][2][2] = -2 * r6;
 }
 
-/* rows L[8][15] (over G[3c + x], c the entropy variable, x the direction) and D[8] at one state */
+/* rows L[8][15] (over G[3c + x], c the entropy variable, x the direction) and D[8] at one state.
+ * B is singular, so its L^T D L factorisation is not unique and the filtered flux depends on the
+ * one taken: this one (the symmetric traceless basis above and the temperature gradient) is
+ * parity unpinned; the pins fix B = L^T D L and the entropy identity, which every such
+ * factorisation satisfies. */
 static void svv_factors(const real u[5], real gamma, real mu, real kappa, real L[8][15], real D[8]) {
   prim_t q = prim(u, gamma);
   real th = q.p / q.rho;
