@@ -43,7 +43,7 @@
  *     Vreman), as the eddy viscosity added to the artificial one node by node.
  *
  * Parity unpinned (no test fixes the choice; every other function fails a pin under a plausible
- * mistake): the averaged state of the matrix-dissipation surface flux (8b), the L^T D L
+ * mistake): the averaged state of the matrix-dissipation surface flux (5), the L^T D L
  * factorisation of the SVV flux matrix (8c), and the interior penalty's use of the smaller of
  * the two traces of J on Gauss-Legendre points (7c; on these boxes the two agree).
  */
