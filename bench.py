@@ -578,9 +578,9 @@ def main():
                          "for hardware traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the library runs the DGSEM path on a single GPU (sharding "
-              "the elements over several GPUs is described in the design notes, not implemented)",
-              file=sys.stderr)
+        print("bench.py measures one GPU: the library runs the DGSEM path on a single GPU. A split "
+              "run's halo exchange is built and timed on one GPU (the 'halo' leg); the transfer "
+              "between GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
     legs = set() if args.legs == "none" else set(x for x in args.legs.split(",") if x)
     unknown = legs - set(LEGS)
