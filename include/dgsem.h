@@ -153,7 +153,9 @@ enum { DG_VISC_BR1 = 0, DG_VISC_BR2 = 1, DG_VISC_IP = 2 };
  *   residual: the divergence of the filtered flux with BR1 face terms (average of the two
  *        sides' fluxes).
  * The paper leaves the factorisation, the 3D kernel and the sensor's use to cited works: these
- * are this library's readings.  Uniform-order Gauss-Lobatto meshes, FP64. */
+ * are this library's readings.  Uniform-order Gauss-Lobatto meshes.  The term is formed in FP64
+ * in both precisions: an FP32-bulk solver adds its divergence, in FP64, to what its FP32 stage
+ * produced. */
 enum { DG_SVV_TADMOR = 0, DG_SVV_MADAY = 1 };
 
 /* Explicit LES closure (section on turbulence models, which names the Smagorinsky, WALE, Vreman
@@ -223,7 +225,7 @@ int dg_mesh_info(const dg_mesh* m, long long* n_elements, long long* n_nodes, in
  * DG_FP32_BULK with a volume flux other than DG_VOL_EC / DG_VOL_CENTRAL or a surface flux other
  * than DG_SURF_ROE / LLF / EC / CENTRAL.  Spectral vanishing viscosity (svv_mu > 0 or
  * les_cs > 0): DG_EINVAL for an unknown kernel or LES model, a cutoff outside [-1, N], Pr <= 0
- * or a NaN threshold; DG_EUNSUPPORTED on a mixed-order or Gauss-Legendre mesh or in FP32-bulk; svv_mu or
+ * or a NaN threshold; DG_EUNSUPPORTED on a mixed-order or Gauss-Legendre mesh; svv_mu or
  * les_cs < 0 or non-finite: DG_EINVAL. */
 int dg_solver_create(const dg_mesh* m, const dg_physics* p, dg_solver** out);
 /* Bytes of device memory the solver needs (host-only; used for admission control). */

@@ -273,8 +273,8 @@ hipError_t pre_stage(const dg_solver* s, int cur, hipStream_t st) {
 // spectral vanishing viscosity on Navier-Stokes with the standard fluxes: the filtered flux of the
 // stage's input is formed first and the stage kernel adds it to the viscous flux (no correction
 // pass after it); otherwise the two SVV kernels correct the stage kernel's output
-bool svv_folded(const dg_solver* s) {
-  return s->svv_on && s->v.viscous && dg::flux_family(s->v.vol, s->v.surf) == 0;
+bool svv_folded(const dg_solver* s) {  // (the stage kernel's SVV twin exists in FP64 only)
+  return s->svv_on && s->v.viscous && !s->v.fp32 && dg::flux_family(s->v.vol, s->v.surf) == 0;
 }
 
 hipError_t run_stage(dg_solver* s, double dt, double a, double b, int mode) {
@@ -635,8 +635,8 @@ int dg_solver_create(const dg_mesh* m, const dg_physics* p, dg_solver** out) try
     if (p->svv_cutoff < -1 || p->svv_cutoff > m->N) return fail(DG_EINVAL, "SVV cutoff outside [-1, N]");
     if (!(p->Pr > 0)) return fail(DG_EINVAL, "Pr must be positive");
     if (std::isnan(p->svv_sensor)) return fail(DG_EINVAL, "SVV sensor threshold is NaN");
-    if (m->mixed || m->gauss || p->precision != DG_FP64)
-      return fail(DG_EUNSUPPORTED, "spectral vanishing viscosity: uniform-order Gauss-Lobatto meshes in FP64");
+    if (m->mixed || m->gauss)
+      return fail(DG_EUNSUPPORTED, "spectral vanishing viscosity: uniform-order Gauss-Lobatto meshes");
   }
   std::unique_ptr<dg_solver> s(new dg_solver);
   s->mesh = *m;

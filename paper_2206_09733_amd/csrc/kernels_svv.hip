@@ -1,5 +1,6 @@
-// kernels_svv.hip -- spectral vanishing viscosity (section "Shock capturing"), FP64, uniform
-// order N on Gauss-Lobatto nodes, one workgroup per element, one lane per node.
+// kernels_svv.hip -- spectral vanishing viscosity (section "Shock capturing"), FP64 for solvers
+// of either precision, uniform order N on Gauss-Lobatto nodes, one workgroup per element, one
+// lane per node.
 //
 // The artificial flux is the Navier-Stokes viscous flux with viscosity mu_a and conductivity
 // kappa_a = mu_a gamma / ((gamma-1) Pr), written in the entropy variables w (eq.
@@ -17,8 +18,8 @@
 // take the unfiltered flux.  The residual of the term is the divergence of the contravariant
 // flux with BR1 face terms (the average of the two sides' fluxes along the owner's Ja^d): on
 // Navier-Stokes with the standard fluxes the stage kernel forms it with the viscous flux (the
-// flux kernel runs before it, with BR1 in one launch with the gradient pass); otherwise
-// svv_div_kernel adds it after the stage kernel.
+// flux kernel runs before it, with BR1 in one launch with the gradient pass); otherwise (Euler,
+// the extended flux families, FP32-bulk) svv_div_kernel adds it after the stage kernel.
 // Explicit LES closure (turbulence models: Smagorinsky, WALE, Vreman, SVV-Smagorinsky): the
 // viscosity gains the model's rho nu_t node by node, from g = grad v = theta Z and
 // Delta = 2 (J/(N+1)^3)^(1/3) (the formulas are in the C header); mu and kappa enter only through
@@ -431,7 +432,7 @@ hipError_t launch_svv_flux(const View& v, int cur, const SvvArgs& a, hipStream_t
 }
 
 hipError_t launch_svv(const View& v, int cur, const SvvArgs& a, double dt, double b, int mode, hipStream_t st) {
-  if (v.mixed || v.gauss || v.fp32 || v.E <= 0 || !a.filt || !a.Fa) return hipErrorInvalidValue;
+  if (v.mixed || v.gauss || v.E <= 0 || !a.filt || !a.Fa) return hipErrorInvalidValue;
   switch (v.N) {
     case 1: return launch_svv_n<1>(v, cur, a, dt, b, mode, st);
     case 2: return launch_svv_n<2>(v, cur, a, dt, b, mode, st);

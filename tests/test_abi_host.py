@@ -190,8 +190,9 @@ def test_mixed_order_mesh_info_and_solver_limits(dg):
 
 
 def test_spectral_vanishing_viscosity_limits(dg):
-    """SVV: uniform-order Lobatto meshes in FP64; kernel, cutoff and viscosity checked; the
-    workspace grows by the filtered-flux buffer (12 doubles per node) and the filter table."""
+    """SVV: uniform-order Lobatto meshes, either precision (not Gauss-Legendre); kernel, cutoff and
+    viscosity checked; the workspace grows by the filtered-flux buffer (12 doubles per node) and
+    the filter table."""
     L = dg.lib()
     m, s = ctypes.c_void_p(), ctypes.c_void_p()
     d, _ = dg.box_desc(2, 2, 2, (0, 0, 0), (1, 1, 1), True, 0.05, 3)
@@ -213,8 +214,23 @@ def test_spectral_vanishing_viscosity_limits(dg):
     p = dg.physics(svv_mu=0.1)
     p.svv_kernel = 2
     assert L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)) == dg.DG_EINVAL
-    p = dg.physics(svv_mu=0.1, precision="fp32_bulk")
-    assert L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)) == dg.DG_EUNSUPPORTED
+    # FP32-bulk solvers take the term too (formed in FP64 after their stage): same buffers
+    for prec in ("fp32_bulk",):
+        nb2 = []
+        for svv in (0.0, 0.05):
+            p = dg.physics(svv_mu=svv, svv_cutoff=1, precision=prec)
+            dg.check(L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)))
+            nb = ctypes.c_size_t()
+            dg.check(L.dg_solver_required_bytes(s, ctypes.byref(nb)))
+            nb2.append(nb.value)
+            L.dg_solver_destroy(s)
+        assert nb2[1] - nb2[0] == sizes[1] - sizes[0]
+    dg_gauss, _ = dg.box_desc(2, 2, 2, (0, 0, 0), (1, 1, 1), False, 0.0, 3, nodes="gauss")
+    mg = ctypes.c_void_p()
+    dg.check(L.dg_mesh_create_box(ctypes.byref(dg_gauss), ctypes.byref(mg)))
+    p = dg.physics(svv_mu=0.1, vol="central")
+    assert L.dg_solver_create(mg, ctypes.byref(p), ctypes.byref(s)) == dg.DG_EUNSUPPORTED
+    L.dg_mesh_destroy(mg)
     for kernel, cut in (("tadmor", -1), ("maday", 3), ("tadmor", 0)):
         p = dg.physics(svv_mu=0.1, svv_kernel=kernel, svv_cutoff=cut, Re=100.0)
         assert L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)) == dg.DG_OK
@@ -241,7 +257,8 @@ def test_spectral_vanishing_viscosity_limits(dg):
     dg.check(L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)))
     L.dg_solver_destroy(s)
     p = dg.physics(les_cs=0.1, precision="fp32_bulk")
-    assert L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)) == dg.DG_EUNSUPPORTED
+    dg.check(L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)))
+    L.dg_solver_destroy(s)
     L.dg_mesh_destroy(m)
     for kw in (dict(orders=[2, 3, 3] * 8), dict(nodes="gauss")):
         d, _k = dg.box_desc(2, 2, 2, (0, 0, 0), (1, 1, 1), False, 0.0, 3, **kw)

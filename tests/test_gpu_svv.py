@@ -9,12 +9,15 @@
   the full 32^3 order-4 size too, where the SVV part's entropy production is also <= 0.
 - RK3 / RK4 trajectories against the oracle; graph replay and the adaptive step agree bitwise
   with eager fixed steps; a batch with an SVV member advances it as alone.
+- FP32-bulk solvers (the term formed in FP64 after their FP32 stage): the residual against the
+  FP64 oracle at the FP32-bulk tolerance, the term alone against the oracle's term at the parity
+  bar, graph replay and batches bitwise as eager and alone.
 """
 import sys
 
 import numpy as np
 
-from helpers import GATE, gate_ok
+from helpers import GATE, gate_ok, FP32_TOL
 import pytest
 
 from paper_2206_09733_amd import synth
@@ -303,3 +306,107 @@ def test_filter_passing_every_mode_equals_the_unfiltered_flux(dg, orc):
     scale = np.abs(R[1]).max()
     log(f"identity filter vs all troubled: max|diff| / max|R| = {np.abs(R[0] - R[1]).max() / scale:.2e}")
     assert np.abs(R[0] - R[1]).max() < 1e-13 * scale
+
+
+FP32_CASES = {"svv_euler": dict(Re=0.0, svv=dict(mu=0.02, kernel="maday", cutoff=2)),
+              "svv_ns": dict(Re=1600.0, svv=dict(mu=0.02, kernel="tadmor", cutoff=2)),
+              "wale_ns": dict(Re=1600.0, svv=dict(mu=0.0, kernel="tadmor", cutoff=-1), les=("wale", 0.5))}
+
+
+def fp32_case_solvers(dg, orc, c, case, precision_gpu):
+    k = FP32_CASES[case]
+    svv, les = k["svv"], k.get("les")
+    o = orc.OracleSolver(**c, Re=k["Re"])
+    if les:
+        o.set_les(les[1], les[0])
+    o.set_svv(svv["mu"], svv["kernel"], svv["cutoff"], -1.0)
+    extra = dict(les_cs=les[1], les_model=les[0]) if les else {}
+    g = dg.Solver(**c, Re=k["Re"], svv_mu=svv["mu"], svv_kernel=svv["kernel"], svv_cutoff=svv["cutoff"],
+                  precision=precision_gpu, **extra)
+    return o, g
+
+
+@pytest.mark.parametrize("case", list(FP32_CASES))
+def test_svv_fp32_bulk_residual(dg, orc, case):
+    """The Taylor-Green state on the deformed 8^3 mesh of order 4 at Ma 0.1 (the meshes of the
+    stated FP32-bulk tolerance): relative L-infinity per variable against the FP64 oracle with the
+    same term."""
+    c = dict(ex=8, N=4, deform=True, Ma=0.1)
+    o, g = fp32_case_solvers(dg, orc, c, case, "fp32_bulk")
+    o.set_ic("tgv")
+    U = o.state()
+    Ro = o.residual()
+    g.set_state(U)
+    Rg = g.residual()
+    E = 512
+    err = np.abs(Rg - Ro).reshape(E, 5, 125).max(axis=(0, 2)) / np.abs(Ro).reshape(E, 5, 125).max(axis=(0, 2))
+    part = np.abs(o.svv_residual()[0]).reshape(E, 5, 125).max(axis=(0, 2))
+    log(f"[svv FP32-bulk {case}] rel err per var {err}; |term|/|R| {part / np.abs(Ro).reshape(E, 5, 125).max(axis=(0, 2))}")
+    assert np.all(err < FP32_TOL["small"]), err
+    g.close()
+
+
+@pytest.mark.parametrize("case", list(FP32_CASES))
+def test_svv_fp32_bulk_term_alone(dg, orc, case):
+    """The residual with the term minus the residual without it: the FP32 stage is the same
+    launch in both and cancels exactly, so what is left is the FP64 term, added after the stage
+    as on the Euler route (bar: the parity gate, or 1e-15 of the full residual)."""
+    N = 4
+    c = dict(ex=3, ey=2, ez=3, N=N, deform=True, Ma=0.3)
+    U = perturbed(orc, dict(c, Re=FP32_CASES[case]["Re"]), seed=1900)
+    o64, g = fp32_case_solvers(dg, orc, c, case, "fp32_bulk")
+    o80 = orc.OracleSolver(**c, Re=FP32_CASES[case]["Re"], precision="fp80")
+    k = FP32_CASES[case]
+    if k.get("les"):
+        o80.set_les(k["les"][1], k["les"][0])
+    o80.set_svv(k["svv"]["mu"], k["svv"]["kernel"], k["svv"]["cutoff"], -1.0)
+    for o in (o64, o80):
+        o.set_state(U)
+    a64, a80 = o64.svv_residual()[0], o80.svv_residual()[0]
+    p = dg.Solver(**c, Re=k["Re"], precision="fp32_bulk")
+    for s in (g, p):
+        s.set_state(U)
+    Rg = g.residual()
+    part = Rg - p.residual()
+    nn, E = (N + 1) ** 3, 18
+    B, A, G = (x.reshape(E, 5, nn) for x in (a80, a64, part))
+    sc = np.abs(B).max(axis=(0, 2))
+    e64, eg = np.abs(A - B).max(axis=(0, 2)), np.abs(G - B).max(axis=(0, 2))
+    floor = 1e-15 * np.abs(Rg.reshape(E, 5, nn)).max(axis=(0, 2))
+    log(f"[svv FP32-bulk term {case}] gpu-vs-fp80 {eg[1:] / sc[1:]} fp64-vs-fp80 {e64[1:] / sc[1:]}")
+    assert np.all(B[:, 0] == 0) and np.all(np.abs(G[:, 0]) <= floor[0])
+    assert np.all(eg[1:] <= np.maximum(GATE * e64[1:], floor[1:])), (eg, e64, floor)
+    g.close()
+    p.close()
+
+
+def test_svv_fp32_bulk_graphs_and_batch(dg):
+    """FP32-bulk with the term: graph replay equals eager steps, and a batch (the member launched
+    on its own within each stage) advances it as alone, bitwise; a few RK3 steps stay within the
+    FP32-bulk tolerance of the FP64 solver's trajectory."""
+    c = dict(ex=3, ey=3, ez=2, N=4, deform=True, Ma=0.1, Re=1600.0, svv_mu=0.02, svv_kernel="maday",
+             svv_cutoff=2, precision="fp32_bulk")
+    eager, graph, ref = dg.Solver(**c), dg.Solver(**c), dg.Solver(**dict(c, precision="fp64"))
+    for s in (eager, graph, ref):
+        s.set_ic("tgv")
+    eager.use_graphs(False)
+    dt = ref.suggest_dt(0.5)
+    for s in (eager, graph, ref):
+        s.rk_step(dt, 4)
+    assert np.array_equal(graph.state(), eager.state())
+    sc = np.abs(ref.state()).reshape(18, 5, 125).max(axis=(0, 2))
+    err = np.abs(graph.state() - ref.state()).reshape(18, 5, 125).max(axis=(0, 2)) / sc
+    log(f"[svv FP32-bulk 4 RK3 steps] state rel err per var vs FP64 {err}")
+    assert np.all(err < 2e-5), err  # residual error (FP32_TOL) times a few steps
+    mem = [dg.Solver(**c), dg.Solver(**dict(c, svv_mu=0.0))]
+    alone = dg.Solver(**dict(c, svv_mu=0.0))
+    for s in mem + [alone]:
+        s.set_ic("tgv")
+    b = dg.Batch(mem)
+    b.rk_step([dt, dt], 4)
+    alone.rk_step(dt, 4)
+    assert np.array_equal(mem[0].state(), eager.state())
+    assert np.array_equal(mem[1].state(), alone.state())
+    b.close()
+    for s in mem + [eager, graph, ref, alone]:
+        s.close()
