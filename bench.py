@@ -245,7 +245,8 @@ def algorithmic_bytes_grad_svv(nodes):
 def run_svv(steps, warmup, plain_ms):
     """The benchmark workload with spectral vanishing viscosity (Maday kernel, cutoff 2,
     artificial viscosity 1/1600): throughput, cost against the plain step, and the two SVV
-    kernels' time per stage from the library's HIP events."""
+    kernels' time per stage from the library's HIP events; the same in FP32-bulk, and the LES
+    closures."""
     from paper_2206_09733_amd import dgsem
     s = dgsem.Solver(**WORKLOAD, svv_mu=1.0 / 1600.0, svv_kernel="maday", svv_cutoff=2)
     s.set_ic("tgv")
@@ -264,6 +265,20 @@ def run_svv(steps, warmup, plain_ms):
            "gradient_and_svv_flux_kernel_GB_s": round(algorithmic_bytes_grad_svv(s.nodes) / flux_s / 1e9, 1),
            "stage_kernel_with_svv_avg_us": round(stg["ms"] / stg["launches"] * 1e3, 2),
            "state_finite": d["nonfinite"] == 0}
+    s.close()
+    # FP32-bulk with the same term: the FP32 stage kernel as without it, then the two SVV
+    # kernels add the term in FP64
+    s = dgsem.Solver(**WORKLOAD, svv_mu=1.0 / 1600.0, svv_kernel="maday", svv_cutoff=2, precision="fp32_bulk")
+    s.set_ic("tgv")
+    s.rk_step(dt, warmup)
+    ev_ms, _, _ = timed_steps(s, dt, steps, profile=False)
+    _, _, prof = timed_steps(s, dt, max(2, steps // 5))
+    oth = prof["other"]
+    out["fp32_bulk"] = {"value": round(5 * s.nodes * 3 * steps / (ev_ms / 1e3) / 1e9, 3), "unit": "GDOF/s",
+                        "ms_per_step": round(ev_ms / steps, 4),
+                        "svv_kernels_avg_us_per_stage": round(oth["ms"] / (3 * max(2, steps // 5)) * 1e3, 2),
+                        "stage_kernel_avg_us": round(prof["stage"]["ms"] / prof["stage"]["launches"] * 1e3, 2),
+                        "state_finite": s.diagnostics()["nonfinite"] == 0}
     s.close()
     # the explicit LES closures on the same workload: the model's eddy viscosity in place of the
     # constant one, filtered (SVV-Smagorinsky) and unfiltered (the plain models), with the models'
