@@ -266,18 +266,18 @@ def run_svv(steps, warmup, plain_ms):
            "stage_kernel_with_svv_avg_us": round(stg["ms"] / stg["launches"] * 1e3, 2),
            "state_finite": d["nonfinite"] == 0}
     s.close()
-    # FP32-bulk with the same term: the FP32 stage kernel as without it, then the two SVV
-    # kernels add the term in FP64
+    # FP32-bulk with the same term: the FP32 gradient pass and the FP64 filtered flux in one
+    # launch, then the FP32 stage kernel with that flux in its viscous flux
     s = dgsem.Solver(**WORKLOAD, svv_mu=1.0 / 1600.0, svv_kernel="maday", svv_cutoff=2, precision="fp32_bulk")
     s.set_ic("tgv")
     s.rk_step(dt, warmup)
     ev_ms, _, _ = timed_steps(s, dt, steps, profile=False)
     _, _, prof = timed_steps(s, dt, max(2, steps // 5))
-    oth = prof["other"]
+    gr, stg = prof["gradient"], prof["stage"]
     out["fp32_bulk"] = {"value": round(5 * s.nodes * 3 * steps / (ev_ms / 1e3) / 1e9, 3), "unit": "GDOF/s",
                         "ms_per_step": round(ev_ms / steps, 4),
-                        "svv_kernels_avg_us_per_stage": round(oth["ms"] / (3 * max(2, steps // 5)) * 1e3, 2),
-                        "stage_kernel_avg_us": round(prof["stage"]["ms"] / prof["stage"]["launches"] * 1e3, 2),
+                        "gradient_and_svv_flux_kernel_avg_us": round(gr["ms"] / gr["launches"] * 1e3, 2),
+                        "stage_kernel_with_svv_avg_us": round(stg["ms"] / stg["launches"] * 1e3, 2),
                         "state_finite": s.diagnostics()["nonfinite"] == 0}
     s.close()
     # the explicit LES closures on the same workload: the model's eddy viscosity in place of the

@@ -153,9 +153,9 @@ enum { DG_VISC_BR1 = 0, DG_VISC_BR2 = 1, DG_VISC_IP = 2 };
  *   residual: the divergence of the filtered flux with BR1 face terms (average of the two
  *        sides' fluxes).
  * The paper leaves the factorisation, the 3D kernel and the sensor's use to cited works: these
- * are this library's readings.  Uniform-order Gauss-Lobatto meshes.  The term is formed in FP64
- * in both precisions: an FP32-bulk solver adds its divergence, in FP64, to what its FP32 stage
- * produced. */
+ * are this library's readings.  Uniform-order Gauss-Lobatto meshes.  The filtered flux is formed
+ * in FP64 in both precisions; an FP32-bulk Navier-Stokes solver adds it to its FP32 viscous flux
+ * (rounded once), an FP32-bulk Euler solver adds its divergence in FP64 after the stage. */
 enum { DG_SVV_TADMOR = 0, DG_SVV_MADAY = 1 };
 
 /* Explicit LES closure (section on turbulence models, which names the Smagorinsky, WALE, Vreman

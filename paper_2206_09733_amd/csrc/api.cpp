@@ -273,8 +273,8 @@ hipError_t pre_stage(const dg_solver* s, int cur, hipStream_t st) {
 // spectral vanishing viscosity on Navier-Stokes with the standard fluxes: the filtered flux of the
 // stage's input is formed first and the stage kernel adds it to the viscous flux (no correction
 // pass after it); otherwise the two SVV kernels correct the stage kernel's output
-bool svv_folded(const dg_solver* s) {  // (the stage kernel's SVV twin exists in FP64 only)
-  return s->svv_on && s->v.viscous && !s->v.fp32 && dg::flux_family(s->v.vol, s->v.surf) == 0;
+bool svv_folded(const dg_solver* s) {
+  return s->svv_on && s->v.viscous && dg::flux_family(s->v.vol, s->v.surf) == 0;
 }
 
 hipError_t run_stage(dg_solver* s, double dt, double a, double b, int mode) {

@@ -18,8 +18,8 @@
 // take the unfiltered flux.  The residual of the term is the divergence of the contravariant
 // flux with BR1 face terms (the average of the two sides' fluxes along the owner's Ja^d): on
 // Navier-Stokes with the standard fluxes the stage kernel forms it with the viscous flux (the
-// flux kernel runs before it, with BR1 in one launch with the gradient pass); otherwise (Euler,
-// the extended flux families, FP32-bulk) svv_div_kernel adds it after the stage kernel.
+// flux kernel runs before it, with BR1 in one launch with the gradient pass, in FP64 or FP32-bulk);
+// otherwise (Euler, the extended flux families) svv_div_kernel adds it after the stage kernel.
 // Explicit LES closure (turbulence models: Smagorinsky, WALE, Vreman, SVV-Smagorinsky): the
 // viscosity gains the model's rho nu_t node by node, from g = grad v = theta Z and
 // Delta = 2 (J/(N+1)^3)^(1/3) (the formulas are in the C header); mu and kappa enter only through
@@ -369,14 +369,15 @@ __global__ void __launch_bounds__(nthreads_for(N)) __attribute__((amdgpu_waves_p
   svv_flux_body<N>(v, block_element(v.E), cur, a);
 }
 
-// Navier-Stokes pass A (BR1) and the SVV flux of the same element in one workgroup: the second
-// body reads the element's state, metric terms and neighbour traces that the first has just
-// read, from the L2 cache instead of HBM.  The two bodies share no LDS and no results.
-template <int N>
+// Navier-Stokes pass A (BR1, in the solver's precision T) and the SVV flux (FP64) of the same
+// element in one workgroup: the second body reads the element's state, metric terms and
+// neighbour traces that the first has just read, from the L2 cache instead of HBM.  The two
+// bodies share no LDS and no results.
+template <int N, typename T>
 __global__ void __launch_bounds__(nthreads_for(N)) __attribute__((amdgpu_waves_per_eu(N <= 6 ? 4 : 3)))
     grad_svv_kernel(View v, int cur, SvvArgs a) {
   const int e = block_element(v.E);
-  grad_body<N, double, false>(v, e, cur);
+  grad_body<N, T, false>(v, e, cur);
   svv_flux_body<N>(v, e, cur, a);
 }
 
@@ -398,12 +399,15 @@ static hipError_t launch_svv_flux_n(const View& v, int cur, const SvvArgs& a, hi
 
 template <int N>
 static hipError_t launch_grad_svv_n(const View& v, int cur, const SvvArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(grad_svv_kernel<N>, dim3(v.E), dim3(nthreads_for(N)), 0, st, v, cur, a);
+  if (v.fp32)
+    hipLaunchKernelGGL((grad_svv_kernel<N, float>), dim3(v.E), dim3(nthreads_for(N)), 0, st, v, cur, a);
+  else
+    hipLaunchKernelGGL((grad_svv_kernel<N, double>), dim3(v.E), dim3(nthreads_for(N)), 0, st, v, cur, a);
   return hipGetLastError();
 }
 
 hipError_t launch_grad_svv(const View& v, int cur, const SvvArgs& a, hipStream_t st) {
-  if (v.mixed || v.gauss || v.fp32 || !v.viscous || v.visc_flux != 0 || v.E <= 0 || !a.filt || !a.Fa)
+  if (v.mixed || v.gauss || !v.viscous || v.visc_flux != 0 || v.E <= 0 || !a.filt || !a.Fa)
     return hipErrorInvalidValue;
   switch (v.N) {
     case 1: return launch_grad_svv_n<1>(v, cur, a, st);
@@ -418,7 +422,7 @@ hipError_t launch_grad_svv(const View& v, int cur, const SvvArgs& a, hipStream_t
 }
 
 hipError_t launch_svv_flux(const View& v, int cur, const SvvArgs& a, hipStream_t st) {
-  if (v.mixed || v.gauss || v.fp32 || v.E <= 0 || !a.filt || !a.Fa) return hipErrorInvalidValue;
+  if (v.mixed || v.gauss || v.E <= 0 || !a.filt || !a.Fa) return hipErrorInvalidValue;
   switch (v.N) {
     case 1: return launch_svv_flux_n<1>(v, cur, a, st);
     case 2: return launch_svv_flux_n<2>(v, cur, a, st);

@@ -34,14 +34,14 @@ struct FaceIn {
   T fv[4];
 };
 
-// SVA (FP64 Navier-Stokes only): the filtered spectral-vanishing-viscosity flux v.Fa of the
-// same state joins the viscous flux at the nodes, and on the faces the average of both sides'
+// SVA (Navier-Stokes): the filtered spectral-vanishing-viscosity flux v.Fa (FP64; rounded to T
+// as it is read) of the same state joins the viscous flux at the nodes, and on the faces the average of both sides'
 // stored values (as the viscous face fluxes; a face node's lane lifts it, the sum taken in the same
 // order from both sides), so the residual holds its term too
 template <int N, typename T, bool VISC, int FX, bool SVA = false>
 __device__ __forceinline__ void stage_body(const View& v, const int e, const int cur, const double dt,
                                            const double rkA, const double rkB, const int mode) {
-  static_assert(!SVA || (VISC && sizeof(T) == 8), "the folded SVV term needs the FP64 viscous kernel");
+  static_assert(!SVA || VISC, "the folded SVV term needs the viscous kernel");
   constexpr int n = N + 1, nn = n * n * n, nf = n * n, NT = nthreads_for(N);
   constexpr int np = n * (n - 1) / 2;  // pairs (a < b) on one line of n nodes
   constexpr int P = nf * np;           // pairs per direction
@@ -405,13 +405,13 @@ template <int N, typename T, int FX>
 inline hipError_t stage_ntx(const View& v, int cur, double dt, double a, double b, int mode,
                             hipStream_t st) {
   const dim3 grid(v.E), block(nthreads_for(N));
-  if constexpr (sizeof(T) == 8 && FX == 0) {
+  if constexpr (FX == 0) {
     if (v.viscous && v.Fa) {
-      hipLaunchKernelGGL((stage_kernel<N, double, true, 0, true>), grid, block, 0, st, v, cur, dt, a, b, mode);
+      hipLaunchKernelGGL((stage_kernel<N, T, true, 0, true>), grid, block, 0, st, v, cur, dt, a, b, mode);
       return hipGetLastError();
     }
   }
-  if (v.Fa) return hipErrorInvalidValue;  // the folded SVV term needs the FP64 viscous kernel
+  if (v.Fa) return hipErrorInvalidValue;  // the folded SVV term: Navier-Stokes, standard fluxes
   if (v.viscous)
     hipLaunchKernelGGL((stage_kernel<N, T, true, FX>), grid, block, 0, st, v, cur, dt, a, b, mode);
   else

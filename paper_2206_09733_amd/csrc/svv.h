@@ -1,8 +1,8 @@
 // svv.h -- spectral vanishing viscosity (section "Shock capturing"): launch interface of the
-// kernels in kernels_svv.hip, for Gauss-Lobatto, uniform-order solvers (the term in FP64 in both
-// precisions).  The filtered flux either enters the FP64 Navier-Stokes stage kernel's viscous flux
-// (launch_svv_flux or launch_grad_svv before it), or its divergence is added to what the stage
-// kernel produced (launch_svv after it; FP32-bulk solvers take this route).
+// kernels in kernels_svv.hip, for Gauss-Lobatto, uniform-order solvers (the filtered flux in FP64
+// in both precisions).  The filtered flux either enters the Navier-Stokes stage kernel's viscous
+// flux (launch_svv_flux or launch_grad_svv before it), or its divergence is added to what the
+// stage kernel produced (launch_svv after it).
 #pragma once
 
 #include <hip/hip_runtime.h>

@@ -9,9 +9,10 @@
   the full 32^3 order-4 size too, where the SVV part's entropy production is also <= 0.
 - RK3 / RK4 trajectories against the oracle; graph replay and the adaptive step agree bitwise
   with eager fixed steps; a batch with an SVV member advances it as alone.
-- FP32-bulk solvers (the term formed in FP64 after their FP32 stage): the residual against the
-  FP64 oracle at the FP32-bulk tolerance, the term alone against the oracle's term at the parity
-  bar, graph replay and batches bitwise as eager and alone.
+- FP32-bulk solvers (the filtered flux formed in FP64; on Navier-Stokes it joins the FP32 stage
+  kernel's viscous flux, on Euler its divergence is added after the stage): the residual against
+  the FP64 oracle at the FP32-bulk tolerance, the term alone against the oracle's term, graph
+  replay and batches bitwise as eager and alone.
 """
 import sys
 
@@ -348,9 +349,12 @@ def test_svv_fp32_bulk_residual(dg, orc, case):
 
 @pytest.mark.parametrize("case", list(FP32_CASES))
 def test_svv_fp32_bulk_term_alone(dg, orc, case):
-    """The residual with the term minus the residual without it: the FP32 stage is the same
-    launch in both and cancels exactly, so what is left is the FP64 term, added after the stage
-    as on the Euler route (bar: the parity gate, or 1e-15 of the full residual)."""
+    """The residual with the term minus the residual without it.  Euler: the FP32 stage is the
+    same launch in both and cancels exactly, so what is left is the FP64 term added after it (bar:
+    the parity gate, or 1e-15 of the full residual).  Navier-Stokes: the FP64 filtered flux joins
+    the FP32 stage kernel's viscous flux, so the two residuals round apart at the FP32-bulk level
+    (bar: the FP32-bulk tolerance of the residual).  The density part is exactly zero on both
+    routes."""
     N = 4
     c = dict(ex=3, ey=2, ez=3, N=N, deform=True, Ma=0.3)
     U = perturbed(orc, dict(c, Re=FP32_CASES[case]["Re"]), seed=1900)
@@ -372,9 +376,13 @@ def test_svv_fp32_bulk_term_alone(dg, orc, case):
     B, A, G = (x.reshape(E, 5, nn) for x in (a80, a64, part))
     sc = np.abs(B).max(axis=(0, 2))
     e64, eg = np.abs(A - B).max(axis=(0, 2)), np.abs(G - B).max(axis=(0, 2))
-    floor = 1e-15 * np.abs(Rg.reshape(E, 5, nn)).max(axis=(0, 2))
-    log(f"[svv FP32-bulk term {case}] gpu-vs-fp80 {eg[1:] / sc[1:]} fp64-vs-fp80 {e64[1:] / sc[1:]}")
-    assert np.all(B[:, 0] == 0) and np.all(np.abs(G[:, 0]) <= floor[0])
+    rs = np.abs(Rg.reshape(E, 5, nn)).max(axis=(0, 2))
+    floor = 1e-15 * rs
+    if k["Re"] > 0:  # folded into the FP32 stage kernel
+        floor = np.maximum(floor, FP32_TOL["small"] * rs)
+    log(f"[svv FP32-bulk term {case}] gpu-vs-fp80 {eg[1:] / sc[1:]} fp64-vs-fp80 {e64[1:] / sc[1:]} "
+        f"|term|/|R| {sc[1:] / rs[1:]}")
+    assert np.all(B[:, 0] == 0) and np.all(G[:, 0] == 0)
     assert np.all(eg[1:] <= np.maximum(GATE * e64[1:], floor[1:])), (eg, e64, floor)
     g.close()
     p.close()
