@@ -107,10 +107,12 @@ typedef struct dg_batch dg_batch;
  * across GPUs whose neighbours across every box face are the block's own periodic images.  Each
  * element face on the box boundary then reads a ghost element instead of its periodic partner,
  * and every stage first exchanges the block's boundary face values: the state's face nodes (and,
- * with viscosity, the face viscous fluxes after the gradient pass) are packed into a contiguous
- * send buffer, moved to the receive buffer (a device copy here, the inter-GPU transfer of a split
- * run) and unpacked into the ghosts.  Results equal those of the direct periodic box bit for bit.
- * The face metrics of the -d faces take the owner's once, at set-up. */
+ * with viscosity, the face viscous fluxes after the gradient pass; with spectral vanishing
+ * viscosity, the filtered flux's components of the face's direction after its flux kernel) are
+ * packed into a contiguous send buffer, moved to the receive buffer (a device copy here, the
+ * inter-GPU transfer of a split run) and unpacked into the ghosts.  Results equal those of the
+ * direct periodic box bit for bit.  The face metrics of the -d faces take the owner's, and the
+ * ghosts' faces the Jacobian (read by the interior penalty), once, at set-up. */
 typedef struct {
   int ex, ey, ez;
   double lo[3], hi[3];

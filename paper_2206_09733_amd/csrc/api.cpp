@@ -171,11 +171,12 @@ Plan make_plan(const dg_solver* s) {
   p.tab = take(sizeof(double) * p.tab_n);
   p.nbr = take(sizeof(int) * 6 * E);
   p.X = take(sizeof(double) * 3 * nt);
-  p.Ja = take(sizeof(double) * 9 * nt);
-  p.J = take(sizeof(double) * nt);
-  p.invJ = take(sizeof(double) * nt);
-  // halo boxes: K ghost elements after the E elements of the state and of the face viscous fluxes
+  // halo boxes: K ghost elements after the E elements of the state, the face viscous fluxes, the
+  // filtered SVV flux and J (of the ghosts only the faces are used)
   const size_t K = s->mesh.halo ? (size_t)halo_faces(s->mesh) : 0;
+  p.Ja = take(sizeof(double) * 9 * nt);
+  p.J = take(sizeof(double) * (nt + K * n * nf));
+  p.invJ = take(sizeof(double) * nt);
   p.U0 = take(sizeof(double) * 5 * (nt + K * n * nf));
   p.U1 = take(sizeof(double) * 5 * (nt + K * n * nf));
   p.dU = take(sizeof(double) * 5 * nt);
@@ -202,7 +203,7 @@ Plan make_plan(const dg_solver* s) {
   p.Mt = mt ? take(sizeof(double) * E * 18 * nf) : 0;
   const bool svv = s->phys.svv_mu > 0 || s->phys.les_cs > 0;
   p.svvtab = svv ? take(sizeof(double) * n * n) : 0;
-  p.Fa = svv ? take(sizeof(double) * 12 * nt) : 0;
+  p.Fa = svv ? take(sizeof(double) * 12 * (nt + K * n * nf)) : 0;
   p.self = take(sizeof(dg::View));  // device copy of the View, read by batched launches
   p.total = off;
   return p;
@@ -282,6 +283,10 @@ hipError_t run_stage(dg_solver* s, double dt, double a, double b, int mode) {
     hipError_t e = timed(s, DG_K_OTHER, [&] { return pre_stage(s, s->cur, s->stream); });
     if (e != hipSuccess) return e;
   }
+  if (s->halo.K) {  // the ghosts' face state of this stage's input
+    hipError_t e = timed(s, DG_K_OTHER, [&] { return dg::halo_exchange_state(s->v, s->cur, s->halo, s->stream); });
+    if (e != hipSuccess) return e;
+  }
   if (svv_folded(s)) {  // (takes its own gradient pass)
     hipError_t e;
     if (s->v.visc_flux == DG_VISC_BR1) {  // the gradient pass and the SVV flux in one launch
@@ -291,14 +296,15 @@ hipError_t run_stage(dg_solver* s, double dt, double a, double b, int mode) {
       if (e == hipSuccess)
         e = timed(s, DG_K_OTHER, [&] { return dg::launch_svv_flux(s->v, s->cur, s->svv, s->stream); });
     }
+    if (e == hipSuccess && s->halo.K) {  // the ghosts' face viscous fluxes and filtered fluxes
+      e = timed(s, DG_K_OTHER, [&] { return dg::halo_exchange_viscous(s->v, s->halo, s->stream); });
+      if (e == hipSuccess)
+        e = timed(s, DG_K_OTHER, [&] { return dg::halo_exchange_svv(s->v, s->svv.Fa, s->halo, s->stream); });
+    }
     if (e != hipSuccess) return e;
     dg::View vf = s->v;
     vf.Fa = s->svv.Fa;
     return timed(s, DG_K_STAGE, [&] { return dg::launch_stage(vf, s->cur, dt, a, b, mode, s->stream); });
-  }
-  if (s->halo.K) {  // the ghosts' face state of this stage's input
-    hipError_t e = timed(s, DG_K_OTHER, [&] { return dg::halo_exchange_state(s->v, s->cur, s->halo, s->stream); });
-    if (e != hipSuccess) return e;
   }
   if (s->v.viscous && !s->v.gauss) {  // (Gauss-Legendre solvers take their gradients in their stage launch)
     hipError_t e = timed(s, DG_K_GRADIENT, [&] { return dg::launch_gradient(s->v, s->cur, s->stream); });
@@ -310,7 +316,14 @@ hipError_t run_stage(dg_solver* s, double dt, double a, double b, int mode) {
   }
   hipError_t e = timed(s, DG_K_STAGE, [&] { return launch_stage_any(s, dt, a, b, mode); });
   if (e != hipSuccess || !s->svv_on) return e;
-  return timed(s, DG_K_OTHER, [&] { return dg::launch_svv(s->v, s->cur, s->svv, dt, b, mode, s->stream); });
+  if (!s->halo.K)
+    return timed(s, DG_K_OTHER, [&] { return dg::launch_svv(s->v, s->cur, s->svv, dt, b, mode, s->stream); });
+  // halo box: the filtered flux, its exchange, then its divergence
+  e = timed(s, DG_K_OTHER, [&] { return dg::launch_svv_flux(s->v, s->cur, s->svv, s->stream); });
+  if (e == hipSuccess)
+    e = timed(s, DG_K_OTHER, [&] { return dg::halo_exchange_svv(s->v, s->svv.Fa, s->halo, s->stream); });
+  if (e != hipSuccess) return e;
+  return timed(s, DG_K_OTHER, [&] { return dg::launch_svv_div(s->v, s->cur, s->svv, dt, b, mode, s->stream); });
 }
 
 hipError_t launch_diag_any(dg_solver* s) {
@@ -622,9 +635,6 @@ int dg_solver_create(const dg_mesh* m, const dg_physics* p, dg_solver** out) try
   if (m->gauss && (p->precision != DG_FP64 || p->vol_flux != DG_VOL_CENTRAL))
     return fail(DG_EUNSUPPORTED, "Gauss-Legendre nodes: FP64, volume flux DG_VOL_CENTRAL (the plain weak "
                                  "form)");
-  if (m->halo && (p->svv_mu > 0 || p->les_cs > 0 || (p->Re > 0 && p->visc_flux == DG_VISC_IP)))
-    return fail(DG_EUNSUPPORTED, "halo exchange: no spectral vanishing viscosity or interior penalty (their face "
-                                 "terms read more of the neighbour than its face state and viscous flux)");
   if (!(p->svv_mu >= 0) || !std::isfinite(p->svv_mu)) return fail(DG_EINVAL, "svv_mu must be >= 0");
   if (!(p->les_cs >= 0) || !std::isfinite(p->les_cs)) return fail(DG_EINVAL, "les_cs must be >= 0");
   if (p->les_cs > 0 && p->les_model != DG_LES_SMAGORINSKY && p->les_model != DG_LES_WALE &&
@@ -896,6 +906,8 @@ int dg_solver_bind(dg_solver* s, void* dev_ptr, size_t bytes, void* hip_stream) 
            "upload halo connectivity");
     DG_HIP(hipMemcpyAsync(b + p.hmap, hmap.data(), sizeof(int4) * hmap.size(), hipMemcpyHostToDevice, s->stream),
            "upload halo map");
+    // the ghosts' Jacobian on their faces (read by the interior penalty), once
+    DG_HIP(dg::halo_exchange_jacobian(v, s->halo, s->stream), "halo exchange of J");
   }
   DG_HIP(hipMemsetAsync(v.dU, 0, sizeof(double) * 5 * s->ntot, s->stream), "clear RK register");
   DG_HIP(hipStreamSynchronize(s->stream), "geometry");

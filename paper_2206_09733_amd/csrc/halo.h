@@ -14,7 +14,7 @@ namespace dg {
 struct HaloArgs {
   const int4* map;  // [K] {src element, src face, ghost element, ghost face}
   int K;            // box-boundary faces (= ghost elements)
-  double* send;     // state face values [K][5][nf]
+  double* send;     // state face values [K][5][nf] (also the SVV flux's [K][4][nf] and J's [K][nf])
   double* recv;
   double* sendv;    // face viscous fluxes [K][4][nf] (FP32-bulk: floats), Navier-Stokes only
   double* recvv;
@@ -25,5 +25,10 @@ struct HaloArgs {
 hipError_t halo_exchange_state(const View& v, int cur, const HaloArgs& h, hipStream_t st);
 // the face viscous fluxes Fvf (after the gradient pass), the same way
 hipError_t halo_exchange_viscous(const View& v, const HaloArgs& h, hipStream_t st);
+// the filtered SVV flux Fa [E + K][12][nn] (after the flux kernel): each face's four components
+// of its direction; uses the state's send / receive buffers
+hipError_t halo_exchange_svv(const View& v, double* Fa, const HaloArgs& h, hipStream_t st);
+// the Jacobian J [E + K][nn] on the faces (once, after the geometry); the state's buffers
+hipError_t halo_exchange_jacobian(const View& v, const HaloArgs& h, hipStream_t st);
 
 }  // namespace dg

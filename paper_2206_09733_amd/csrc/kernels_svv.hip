@@ -392,6 +392,13 @@ static hipError_t launch_svv_n(const View& v, int cur, const SvvArgs& a, double 
 }
 
 template <int N>
+static hipError_t launch_svv_div_n(const View& v, int cur, const SvvArgs& a, double dt, double b, int mode,
+                                   hipStream_t st) {
+  hipLaunchKernelGGL(svv_div_kernel<N>, dim3(v.E), dim3(nthreads_for(N)), 0, st, v, cur, a, dt, b, mode);
+  return hipGetLastError();
+}
+
+template <int N>
 static hipError_t launch_svv_flux_n(const View& v, int cur, const SvvArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(svv_flux_kernel<N>, dim3(v.E), dim3(nthreads_for(N)), 0, st, v, cur, a);
   return hipGetLastError();
@@ -417,6 +424,20 @@ hipError_t launch_grad_svv(const View& v, int cur, const SvvArgs& a, hipStream_t
     case 5: return launch_grad_svv_n<5>(v, cur, a, st);
     case 6: return launch_grad_svv_n<6>(v, cur, a, st);
     case 7: return launch_grad_svv_n<7>(v, cur, a, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_svv_div(const View& v, int cur, const SvvArgs& a, double dt, double b, int mode, hipStream_t st) {
+  if (v.mixed || v.gauss || v.E <= 0 || !a.filt || !a.Fa) return hipErrorInvalidValue;
+  switch (v.N) {
+    case 1: return launch_svv_div_n<1>(v, cur, a, dt, b, mode, st);
+    case 2: return launch_svv_div_n<2>(v, cur, a, dt, b, mode, st);
+    case 3: return launch_svv_div_n<3>(v, cur, a, dt, b, mode, st);
+    case 4: return launch_svv_div_n<4>(v, cur, a, dt, b, mode, st);
+    case 5: return launch_svv_div_n<5>(v, cur, a, dt, b, mode, st);
+    case 6: return launch_svv_div_n<6>(v, cur, a, dt, b, mode, st);
+    case 7: return launch_svv_div_n<7>(v, cur, a, dt, b, mode, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -28,6 +28,9 @@ struct SvvArgs {
 // (after the stage kernel wrote dU and U[cur^1] for the same stage): dU += h R_a and
 // U[cur^1] += b h R_a, h = *v.dtp if set, else dt.
 hipError_t launch_svv(const View& v, int cur, const SvvArgs& a, double dt, double b, int mode, hipStream_t st);
+// kernel 2 alone (after kernel 1 and, on a halo box, the exchange of the filtered flux), modes
+// as launch_svv
+hipError_t launch_svv_div(const View& v, int cur, const SvvArgs& a, double dt, double b, int mode, hipStream_t st);
 // kernel 1 alone, for a stage kernel that takes the filtered flux itself (View::Fa = a.Fa): it
 // enters that kernel's viscous volume and face terms, which then hold R_a, and kernel 2 is not run
 hipError_t launch_svv_flux(const View& v, int cur, const SvvArgs& a, hipStream_t st);

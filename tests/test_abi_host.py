@@ -271,9 +271,9 @@ def test_spectral_vanishing_viscosity_limits(dg):
 
 
 def test_halo_box_limits_and_sizes(dg):
-    """Halo boxes (the box as one block of a split domain): uniform-order Gauss-Lobatto only; no
-    spectral vanishing viscosity or interior penalty; the buffer grows by the ghost elements'
-    state (two copies) and face viscous fluxes, the map and the send / receive buffers."""
+    """Halo boxes (the box as one block of a split domain): uniform-order Gauss-Lobatto only; the
+    buffer grows by the ghost elements' state (two copies), Jacobian, face viscous fluxes and (with
+    spectral vanishing viscosity) filtered flux, the map and the send / receive buffers."""
     L = dg.lib()
     m = ctypes.c_void_p()
     d, _ = dg.box_desc(3, 2, 4, (0, 0, 0), (1, 1, 1), False, 0.0, 3)
@@ -287,22 +287,22 @@ def test_halo_box_limits_and_sizes(dg):
         d, _ = dg.box_desc(3, 2, 4, (0, 0, 0), (1, 1, 1), False, 0.0, 3, halo=halo)
         dg.check(L.dg_mesh_create_box(ctypes.byref(d), ctypes.byref(m)))
         s = ctypes.c_void_p()
-        if halo:
-            for bad in (dict(Re=100.0, visc="ip"), dict(svv_mu=0.1, svv_cutoff=1), dict(les_cs=0.1, svv_cutoff=1)):
-                p = dg.physics(**bad)
-                assert L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)) == dg.DG_EUNSUPPORTED, bad
-        for Re, visc, prec in ((0.0, "br1", "fp64"), (100.0, "br1", "fp64"), (100.0, "br2", "fp32_bulk")):
-            p = dg.physics(Re=Re, visc=visc, precision=prec)
+        cases = ((0.0, "br1", "fp64", 0.0), (100.0, "br1", "fp64", 0.0), (100.0, "br2", "fp32_bulk", 0.0),
+                 (100.0, "ip", "fp64", 0.0), (100.0, "br1", "fp64", 0.1), (0.0, "br1", "fp64", 0.1))
+        for Re, visc, prec, svv in cases:
+            p = dg.physics(Re=Re, visc=visc, precision=prec, svv_mu=svv, svv_cutoff=1)
             dg.check(L.dg_solver_create(m, ctypes.byref(p), ctypes.byref(s)))
             nb = ctypes.c_size_t()
             dg.check(L.dg_solver_required_bytes(s, ctypes.byref(nb)))
-            sizes[(halo, Re, visc)] = nb.value
+            sizes[(halo, Re, visc, svv)] = nb.value
             L.dg_solver_destroy(s)
         L.dg_mesh_destroy(m)
     K, nn, nf = 2 * (2 * 4 + 3 * 4 + 3 * 2), 64, 16
-    for Re, visc in ((0.0, "br1"), (100.0, "br1"), (100.0, "br2")):
-        extra = sizes[(True, Re, visc)] - sizes[(False, Re, visc)]
-        least = 8 * (2 * 5 * K * nn + 2 * 5 * K * nf) + 16 * K
+    for Re, visc, _, svv in cases:
+        extra = sizes[(True, Re, visc, svv)] - sizes[(False, Re, visc, svv)]
+        least = 8 * (2 * 5 * K * nn + K * nn + 2 * 5 * K * nf) + 16 * K
         if Re > 0:
             least += 8 * (K * 6 * 4 * nf + 2 * 4 * K * nf)
-        assert least <= extra <= least + 256 * 8, (Re, visc, extra, least)
+        if svv > 0:
+            least += 8 * 12 * K * nn
+        assert least <= extra <= least + 256 * 8, (Re, visc, svv, extra, least)

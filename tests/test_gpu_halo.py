@@ -4,9 +4,10 @@ through ghost elements that a halo exchange (pack, transfer, unpack) fills befor
 Every comparison is bitwise against the same box with direct periodic neighbours: the ghosts hold
 exact copies of the neighbours' face values, so each kernel sees the same operands in the same
 order.  Residuals, RK3 steps (graph replay and eager), the adaptive step and the diagnostics;
-Euler and Navier-Stokes (BR1, BR2), FP64 and FP32-bulk, the extended flux family, the global
-Lax-Friedrichs flux, one element across a direction, and the real share of a split 64^3 N=5 run
-(a 32^3 block).  A batch refuses a halo box.
+Euler and Navier-Stokes (BR1, BR2, the interior penalty), FP64 and FP32-bulk, the extended flux
+family, the global Lax-Friedrichs flux, spectral vanishing viscosity on its folded and unfolded
+routes and an LES closure, one element across a direction, and the real share of a split 64^3
+N=5 run (a 32^3 block).  A batch refuses a halo box.
 """
 import sys
 
@@ -39,6 +40,19 @@ CASES = {
     "lf_global": dict(ex=3, ey=2, ez=2, N=3, Ma=0.3, surf="lf_global"),
     "one_element_ns": dict(ex=1, ey=1, ez=1, N=3, Ma=0.3, Re=100.0),
     "thin_box": dict(ex=5, ey=1, ez=2, N=2, Ma=0.3, Re=100.0, hi=(1.0, 0.5, 2.0)),
+    # the interior penalty reads the neighbour's J on the face: the ghosts' faces hold it
+    "ns_ip": dict(ex=3, ey=2, ez=2, N=3, deform=True, Ma=0.3, Re=200.0, visc="ip"),
+    # spectral vanishing viscosity: the filtered flux's face components are exchanged too
+    "svv_ns_br1": dict(ex=3, ey=3, ez=2, N=4, deform=True, Ma=0.3, Re=200.0, svv_mu=0.02, svv_kernel="maday",
+                       svv_cutoff=2),
+    "svv_ns_br2_fp32_bulk": dict(ex=2, ey=3, ez=2, N=4, Ma=0.2, Re=300.0, visc="br2", svv_mu=0.02,
+                                 svv_kernel="tadmor", svv_cutoff=2, precision="fp32_bulk"),
+    "svv_euler": dict(ex=3, ey=2, ez=3, N=3, Ma=0.3, svv_mu=0.02, svv_kernel="maday", svv_cutoff=1),
+    "svv_kg_es_matrix": dict(ex=2, ey=2, ez=3, N=3, Ma=0.3, Re=300.0, vol="kg", surf="es_matrix", svv_mu=0.02,
+                             svv_kernel="maday", svv_cutoff=1),
+    "les_wale": dict(ex=3, ey=2, ez=2, N=4, deform=True, Ma=0.3, Re=200.0, les_cs=0.5, les_model="wale",
+                     svv_kernel="tadmor", svv_cutoff=-1),
+    "svv_one_element_across": dict(ex=1, ey=3, ez=2, N=3, Ma=0.3, Re=100.0, svv_mu=0.02, svv_cutoff=1),
 }
 
 
