@@ -11,8 +11,8 @@
   with eager fixed steps; a batch with an SVV member advances it as alone.
 - FP32-bulk solvers (the filtered flux formed in FP64; on Navier-Stokes it joins the FP32 stage
   kernel's viscous flux, on Euler its divergence is added after the stage): the residual against
-  the FP64 oracle at the FP32-bulk tolerance, the term alone against the oracle's term, graph
-  replay and batches bitwise as eager and alone.
+  the FP64 oracle at the FP32-bulk tolerance (orders 1-7 with BR1 and BR2), the term alone against
+  the oracle's term, graph replay and batches bitwise as eager and alone.
 """
 import sys
 
@@ -418,3 +418,27 @@ def test_svv_fp32_bulk_graphs_and_batch(dg):
     b.close()
     for s in mem + [eager, graph, ref, alone]:
         s.close()
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 5, 6, 7])
+@pytest.mark.parametrize("visc", ["br1", "br2"])
+def test_svv_fp32_bulk_orders(dg, orc, N, visc):
+    """Every order of the FP32-bulk folded route (the FP32 gradient pass with the FP64 flux kernel
+    in one launch for BR1, the flux kernel alone for BR2, then the FP32 stage kernel's SVV twin):
+    the Taylor-Green state on a deformed 4^3 mesh at Ma 0.1 (the meshes of the stated FP32-bulk
+    tolerance), residual against the FP64 oracle with the same term."""
+    c = dict(ex=4, N=N, deform=True, Ma=0.1, Re=800.0)
+    cut = N // 2
+    o = orc.OracleSolver(**c, visc=visc)
+    o.set_svv(0.02, "maday", cut, -1.0)
+    o.set_ic("tgv")
+    U = o.state()
+    Ro = o.residual()
+    g = dg.Solver(**c, visc=visc, svv_mu=0.02, svv_kernel="maday", svv_cutoff=cut, precision="fp32_bulk")
+    g.set_state(U)
+    Rg = g.residual()
+    E, nn = 64, (N + 1) ** 3
+    err = np.abs(Rg - Ro).reshape(E, 5, nn).max(axis=(0, 2)) / np.abs(Ro).reshape(E, 5, nn).max(axis=(0, 2))
+    log(f"[svv FP32-bulk N={N} {visc}] rel err per var {err}")
+    assert np.all(err < FP32_TOL["small"]), err
+    g.close()
